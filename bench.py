@@ -1,0 +1,211 @@
+"""Benchmark: solve time to 1e-8 relative residual and V-cycles/s at N = 512,
+FP32 smoother against FP64, on one MI355X.
+
+Workload: 512 x 512 periodic grid, rho = 1, mu = 1e-2, dt = 5e-4; elastic
+annulus between radii 0.2 and 0.25 (4 rings x 2048 points, ring and radial
+springs, kappa = 1e4); 7-level V-cycle (512 -> 8), restricted additive Schwarz
+on 8 x 8 boxes with overlap 2, 2 + 2 FGMRES smoothing iterations, outer
+FGMRES(30) to 1e-8; seeded uniform[-1, 1] right-hand side.
+
+One step = one FP64 solve plus one FP32-smoother solve of the same
+right-hand side, both to 1e-8 (set-up excluded; inputs resident in HBM).
+``value`` = V-cycles applied in the timed steps / timed wall time.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-baseline sample|off]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve time to 1e-8 rel-res & V-cycles/s at N=512; FP32 smoother vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--N", type=int, default=512)
+    p.add_argument("--cpu-baseline", default="sample", choices=["sample", "off"])
+    p.add_argument("--cpu-boxes", type=int, default=1024)
+    p.add_argument("--roofline-reps", type=int, default=50)
+    return p.parse_args()
+
+
+def box_geometry(N, box=8, overlap=2):
+    b = min(box, N // 2)
+    o = max(0, min(overlap, (N - b - 1) // 2))
+    m = b + 2 * o
+    return b, o, m, 2 * m * (m + 1) + m * m, 3 * b * b
+
+
+def cpu_baseline(wl, nboxes):
+    """Time the plain FP64 oracle on a bounded sample of the same workload and
+    scale it to V-cycles/s: the box solves of the finest level (gather,
+    LU solve, owned-set scatter) on ``nboxes`` of its boxes, and one
+    L_IB apply per level; a V-cycle performs (nu1 + nu2) box solves per box of
+    every level >= 1 and six operator applies per level."""
+    import scipy.linalg as la
+    from oracle import hierarchy, schwarz
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    levels = hierarchy.build(wl)
+    fine = levels[-1]
+    parts = schwarz.patches(fine.N, wl.box, wl.overlap)
+    step = max(1, len(parts) // nboxes)
+    sample = parts[::step][:nboxes]
+    Lc = fine.L.tocsr()
+    facs = [la.lu_factor(Lc[p.idx][:, p.idx].toarray()) for p in sample]
+    rng = np.random.default_rng(0)
+    r = rng.uniform(-1, 1, fine.n)
+    z = np.zeros_like(r)
+    t0 = time.perf_counter()
+    for p, f in zip(sample, facs):
+        y = la.lu_solve(f, r[p.idx])
+        z[p.own_global] = y[p.own_local]
+    t_box = (time.perf_counter() - t0) / len(sample)
+    t_ops = 0.0
+    for lev in levels:
+        w = rng.uniform(-1, 1, lev.n)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            lev.L @ w
+        t_ops += 6 * (time.perf_counter() - t0) / 3
+    box_solves = (wl.nu1 + wl.nu2) * sum(len(schwarz.patches(l.N, wl.box, wl.overlap)) for l in levels[1:])
+    t_vc = box_solves * t_box + t_ops
+    return {"value": 1.0 / t_vc, "unit": "V-cycles/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle on the N={wl.N} annulus: {len(sample)} of {len(parts)} finest boxes "
+                       f"(LU solve + scatter, {t_box * 1e3:.3f} ms/box) scaled to the {box_solves} box "
+                       f"solves of one V-cycle, plus 6 sparse L_IB applies per level "
+                       f"({t_ops * 1e3:.1f} ms); factorisation and set-up excluded"),
+            "vcycle_s": t_vc}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_1612_02208_amd import StokesIB
+
+    wl = W.annulus_512(N=a.N)
+    wl.N = a.N
+    b_h = W.rhs(wl.N, 0)
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    b = torch.from_numpy(b_h).to(dev)
+    t0 = time.perf_counter()
+    g64 = StokesIB(wl, precision="fp64")
+    t_setup64 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g32 = StokesIB(wl, precision="fp32")
+    t_setup32 = time.perf_counter() - t0
+    print(f"[bench] set-up fp64 {t_setup64:.2f}s fp32 {t_setup32:.2f}s", file=sys.stderr, flush=True)
+
+    x64 = torch.empty_like(b)
+    x32 = torch.empty_like(b)
+
+    def step():
+        _, i64 = g64.solve(b, rtol=1e-8, out=x64)
+        _, i32 = g32.solve(b, rtol=1e-8, out=x32)
+        return i64, i32
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] {a.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+    vcycles = sum(r[0]["vcycles"] + r[1]["vcycles"] for r in recs)
+    s64 = [r[0]["solve_ms"] for r in recs]
+    s32 = [r[1]["solve_ms"] for r in recs]
+    i64, i32 = recs[-1]
+    diff = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+
+    # standalone V-cycle throughput (back-to-back, FP64 and FP32 smoother)
+    def vc_rate(g, reps=20):
+        r = torch.from_numpy(b_h).to(dev)
+        z = torch.empty_like(r)
+        g.vcycle(r, out=z)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            g.vcycle(r, out=z)
+        torch.cuda.synchronize()
+        return reps / (time.perf_counter() - t)
+
+    vc64, vc32 = vc_rate(g64), vc_rate(g32)
+
+    # roofline of the dominant kernel: the finest-level restricted additive
+    # Schwarz application (one launch per smoother_apply on the FP64 handle),
+    # timed with HIP events on the stream it is launched on.
+    st = g64.stats()["levels"][-1]
+    bb, oo, m, nloc, nown = box_geometry(wl.N, wl.box, wl.overlap)
+    n = 3 * wl.N * wl.N
+    alg_bytes = (st["unique_boxes"]) * nloc * nown * 8 + 2 * n * 8
+    r = torch.from_numpy(b_h).to(dev)
+    stream = torch.cuda.current_stream()
+    g64.smoother_apply(-1, r)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(a.roofline_reps):
+        g64.smoother_apply(-1, r)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ras_ms = ev0.elapsed_time(ev1) / a.roofline_reps
+    achieved = alg_bytes / (ras_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": vcycles / elapsed,
+        "unit": "V-cycles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 + f32-smoother",
+        "data": "synthetic",
+        "config": {"workload": f"annulus_{wl.N}: {wl.N}x{wl.N} periodic, rho=1 mu=1e-2 dt=5e-4, "
+                               f"4x2048-point annulus r=0.2..0.25, kappa=1e4, 7-level V-cycle, "
+                               f"RAS 8x8/2, nu=2+2, FGMRES(30) to 1e-8",
+                   "N": wl.N, "points": wl.M, "springs": int(len(wl.springs))},
+        "solve_ms_fp64": float(np.median(s64)),
+        "solve_ms_fp32": float(np.median(s32)),
+        "fp32_speedup": float(np.median(s64) / np.median(s32)),
+        "iters_fp64": i64["iters"], "iters_fp32": i32["iters"],
+        "rel_res_true_fp64": i64["rel_res_true"], "rel_res_true_fp32": i32["rel_res_true"],
+        "fp32_vs_fp64_rel_diff": diff,
+        "vcycles_per_s_fp64": vc64, "vcycles_per_s_fp32": vc32,
+        "setup_s_fp64": t_setup64, "setup_s_fp32": t_setup32,
+        "roofline": {"bound": "hbm", "kernel": "k_ras_apply<double> (finest level)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "launch_ms": ras_ms, "alg_bytes_per_launch": alg_bytes},
+    }
+    if a.cpu_baseline != "off":
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_boxes)
+        print(f"[bench] cpu baseline {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/* ibmg.h -- C ABI of the MI355X multigrid solver for the Stokes-IB system
+ *
+ *   L_IB [u; p] = [A_IB, G; -D, 0] [u; p] = b,
+ *   A_IB = rho/dt I - mu Lap_h - dt S_h K_h J_h            (Eq. matrix-impib)
+ *
+ * on a periodic N x N staggered grid (App. A.1), preconditioned by the
+ * geometric-multigrid V-cycle of Alg. 1 with a restricted additive Schwarz
+ * (Alg. 2) or Schur-complement (Eq. approx-fact-Stokes-IB) smoother wrapped in
+ * a fixed number of FGMRES iterations (Sec. 3.3), inside flexible GMRES.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Vector layout.  A level vector w of an n x n level has 3 n^2 entries
+ *   [u (j*n+i), v (j*n+i), p (j*n+i)],
+ * u[j][i] the x-velocity on the face at (i h, (j+1/2) h), v[j][i] the
+ * y-velocity on the face at ((i+1/2) h, j h), p[j][i] the pressure at the cell
+ * centre ((i+1/2) h, (j+1/2) h), h = 1/n, all indices periodic.
+ * Lagrangian arrays are [M][2] (x, y interleaved).
+ * Memory.  Pointers named in a ``desc`` (X, ends, kappa) are HOST pointers,
+ * copied during ibmg_create.  Every vector argument of the other calls is a
+ * DEVICE pointer (FP64 unless stated) owned by the caller; the library never
+ * frees caller memory.  The library allocates its own device workspace in
+ * ibmg_create and frees it in ibmg_destroy.
+ * Streams.  Calls enqueue work on the given HIP stream and return without
+ * synchronising, except ibmg_create, ibmg_set_kappa and the *_solve calls,
+ * which synchronise that stream.  A handle is not thread-safe; distinct
+ * handles are independent.
+ * Errors.  Every call returns an ibmg_status; nothing throws across the ABI.
+ * Argument errors are detected on the host before any work is enqueued.  A
+ * HIP error is returned by the call that observes it; ibmg_last_error gives
+ * the message of the last failure on a handle (or of a failed create when
+ * passed NULL).
+ */
+#ifndef IBMG_H
+#define IBMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibmg_handle ibmg_handle;
+typedef void* ibmg_stream; /* a hipStream_t; NULL means the null stream */
+
+typedef enum {
+  IBMG_OK = 0,
+  IBMG_NOT_CONVERGED = 1, /* result valid, tolerance not reached in max_it */
+  IBMG_ERR_ARG = -1,      /* invalid argument; nothing was enqueued */
+  IBMG_ERR_HIP = -2,      /* HIP runtime error (allocation, launch, fault) */
+  IBMG_ERR_NONFINITE = -5,/* NaN/Inf in an input vector or in the iteration */
+  IBMG_ERR_STATE = -6     /* call not valid for this handle */
+} ibmg_status;
+
+enum { IBMG_RAS = 0, IBMG_SC = 1 };              /* smoother */
+enum { IBMG_FP64 = 0, IBMG_FP32_SMOOTHER = 1 };  /* precision */
+
+typedef struct {
+  int32_t N;          /* finest grid size; N = coarse_N * 2^k, k >= 1        */
+  int32_t coarse_N;   /* coarsest grid (Sec. 5 uses 8); 4 <= coarse_N <= 32   */
+  double rho, mu, dt; /* A = rho/dt I - mu Lap_h (Eq. system-impib); rho >= 0,
+                         mu > 0, dt > 0                                      */
+  int32_t M;          /* Lagrangian points, >= 0                             */
+  const double* X;    /* host [M][2], positions in [0,1)^2 (lagged X^n)      */
+  int32_t n_springs;  /* >= 0                                                */
+  const int32_t* ends;/* host [n_springs][2] node ids, a != b, in [0, M)     */
+  const double* kappa;/* host [n_springs] spring stiffness >= 0 (zero rest
+                         length, Sec. 5 linear fibre force)                  */
+  int32_t smoother;   /* IBMG_RAS | IBMG_SC                                   */
+  int32_t box;        /* RAS box size b (cells); must divide every level's
+                         n >= 2b, levels below use min(b, n/2)               */
+  int32_t overlap;    /* RAS overlap o (cells) >= 0                          */
+  int32_t nu1, nu2;   /* pre/post smoothing: FGMRES iterations, 1..8         */
+  int32_t cheb_its;   /* SC: Chebyshev iterations per inner solve, 1..8      */
+  int32_t precision;  /* IBMG_FP64 | IBMG_FP32_SMOOTHER                       */
+} ibmg_desc;
+
+typedef struct {
+  double rtol;        /* stop at ||b - L x|| <= rtol ||b|| (Arnoldi estimate) */
+  int32_t restart;    /* FGMRES restart length, 1..64 (30)                    */
+  int32_t max_it;     /* total iteration cap (100, the paper's Sec. 5 cap)    */
+  int32_t use_x0;     /* 1: x holds the initial guess; 0: start from zero     */
+} ibmg_solve_opts;
+
+typedef struct {
+  int32_t iters, restarts;
+  double rel_res_est;   /* Arnoldi residual estimate / ||b||                 */
+  double rel_res_true;  /* ||P b - L x|| / ||P b|| recomputed at the end      */
+  double rhs_null_norm; /* ||b - P b||, the null-space part removed from b    */
+  double solve_ms;      /* wall time of the call                             */
+  double* history;      /* optional host array of residual estimates         */
+  int32_t history_cap;  /* its capacity (0 if history is NULL)               */
+  int32_t vcycles;      /* V-cycles applied                                  */
+} ibmg_solve_info;
+
+/* Create a solver for one system: copies the structure, builds every level's
+ * operators (rediscretised A, G, D; Galerkin IB operator, Sec. 3.1), the
+ * smoother data (RAS box inverses, Alg. 2; or SC colourings and Chebyshev
+ * bounds) and the coarsest direct solve.  Synchronises ``stream``.
+ * Errors: IBMG_ERR_ARG for an invalid desc (non-finite values, bad sizes,
+ * out-of-range ids), IBMG_ERR_HIP on allocation or kernel failure. */
+ibmg_status ibmg_create(const ibmg_desc* desc, ibmg_stream stream, ibmg_handle** out);
+ibmg_status ibmg_destroy(ibmg_handle* h);
+const char* ibmg_last_error(const ibmg_handle* h);
+
+/* Number of levels and the grid size of a level (0 = coarsest). */
+ibmg_status ibmg_levels(const ibmg_handle* h, int32_t* n_levels);
+ibmg_status ibmg_level_n(const ibmg_handle* h, int32_t level, int32_t* n);
+
+/* y = L_IB^l w on level l (Eq. matrix-h-impib; the finest level is
+ * Eq. matrix-impib), FP64, w and y of length 3 n_l^2, must not alias. */
+ibmg_status ibmg_apply_A_IB(ibmg_handle* h, int32_t level, const double* w, double* y,
+                            ibmg_stream stream);
+/* y = L_IB^T w on level l, computed by the transposed stencils and the
+ * interpolation reused as the adjoint of spreading (S = J^*, App. A.3). */
+ibmg_status ibmg_apply_A_IB_T(ibmg_handle* h, int32_t level, const double* w, double* y,
+                              ibmg_stream stream);
+
+/* f = S_h F on the finest grid (App. A.3 spreading, unit nodal weights):
+ * F [M][2] -> f [2][N][N] (u-faces then v-faces). */
+ibmg_status ibmg_spread(ibmg_handle* h, const double* F, double* f, ibmg_stream stream);
+/* U = J_h u on the finest grid (App. A.3 interpolation): u [2][N][N] -> U [M][2]. */
+ibmg_status ibmg_interp(ibmg_handle* h, const double* u, double* U, ibmg_stream stream);
+
+/* Inter-level transfers (Sec. 3.2) between level l (fine) and l-1 (coarse):
+ * coarse = [R_u; R_u; R_p] fine;  fine += [P_u; P_u; P_p] coarse. */
+ibmg_status ibmg_restrict(ibmg_handle* h, int32_t level, const double* fine, double* coarse,
+                          ibmg_stream stream);
+ibmg_status ibmg_prolong_add(ibmg_handle* h, int32_t level, const double* coarse, double* fine,
+                             ibmg_stream stream);
+
+/* One application of the basic smoother on level l >= 1 from a zero guess:
+ * z = RAS(r) (Alg. 2) or the SC approximate inverse (Eq. approx-fact-Stokes-IB). */
+ibmg_status ibmg_smoother_apply(ibmg_handle* h, int32_t level, const double* r, double* z,
+                                ibmg_stream stream);
+/* Sec. 3.3 smoothing on level l >= 1: w <- w + e, e from nu FGMRES iterations
+ * on L e = b - L w (e0 = 0) preconditioned by the basic smoother. */
+ibmg_status ibmg_smooth(ibmg_handle* h, int32_t level, double* w, const double* b, int32_t nu,
+                        ibmg_stream stream);
+/* Coarsest-level direct solve: x = L_IB^0+ r (bordered by the null vectors). */
+ibmg_status ibmg_coarse_solve(ibmg_handle* h, const double* r, double* x, ibmg_stream stream);
+
+/* z = MG(0, r): one V-cycle (Alg. 1) on the finest level from a zero guess. */
+ibmg_status ibmg_vcycle(ibmg_handle* h, const double* r, double* z, ibmg_stream stream);
+
+/* Solve L_IB x = b with FGMRES(restart) preconditioned by one V-cycle per
+ * iteration.  b is projected onto range(L_IB) (block means removed: pressure
+ * always, velocity components when rho = 0); the returned x has no null-space
+ * component.  FGMRES orthogonalisation, the outer residual and the coarsest
+ * solve are FP64 in both precisions.  Synchronises ``stream``.
+ * Returns IBMG_NOT_CONVERGED if max_it is reached, IBMG_ERR_NONFINITE if b
+ * holds NaN/Inf or the iteration produces it. */
+ibmg_status ibmg_fgmres_solve(ibmg_handle* h, const double* b, double* x,
+                              const ibmg_solve_opts* opts, ibmg_solve_info* info,
+                              ibmg_stream stream);
+
+/* dL/dkappa_e = -lambda^T (dL_IB/dkappa_e) w
+ *             = -(dt/h^2) sum_c (B_e J lambda_c)(B_e J w_c),
+ * B_e J x = (J x)_{b_e} - (J x)_{a_e}: the derivative of a loss through the
+ * adjoint solution lambda of L_IB^T lambda = dL/dw (finest level, FP64).
+ * w, lambda: 3 N^2; out: [n_springs]. */
+ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* lambda,
+                                 double* out, ibmg_stream stream);
+
+/* Replace the spring stiffnesses (host array [n_springs]) and rebuild every
+ * level's IB operator and smoother data.  Synchronises ``stream``. */
+ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream stream);
+
+/* Setup statistics: IB-touched boxes per level (RAS), colours (SC), etc.
+ * Writes up to cap int64 values: [levels, then per level: n, boxes,
+ * unique boxes, colours_u, colours_p] and returns the count in *written. */
+ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,85 @@
+"""ctypes declarations of libibmg (include/ibmg.h).  Argument marshalling only."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibmg.so")
+
+IBMG_OK = 0
+IBMG_NOT_CONVERGED = 1
+IBMG_ERR_ARG = -1
+IBMG_ERR_HIP = -2
+IBMG_ERR_NONFINITE = -5
+IBMG_ERR_STATE = -6
+
+RAS, SC = 0, 1
+FP64, FP32_SMOOTHER = 0, 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("coarse_N", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("M", ctypes.c_int32), ("X", _dp),
+        ("n_springs", ctypes.c_int32), ("ends", _ip), ("kappa", _dp),
+        ("smoother", ctypes.c_int32), ("box", ctypes.c_int32), ("overlap", ctypes.c_int32),
+        ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("cheb_its", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_it", ctypes.c_int32), ("use_x0", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("rhs_null_norm", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("history", _dp), ("history_cap", ctypes.c_int32), ("vcycles", ctypes.c_int32)]
+
+
+EXPORTS = [
+    "ibmg_create", "ibmg_destroy", "ibmg_last_error", "ibmg_levels", "ibmg_level_n",
+    "ibmg_apply_A_IB", "ibmg_apply_A_IB_T", "ibmg_spread", "ibmg_interp", "ibmg_restrict",
+    "ibmg_prolong_add", "ibmg_smoother_apply", "ibmg_smooth", "ibmg_coarse_solve", "ibmg_vcycle",
+    "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats",
+]
+
+_lib = None
+
+
+def load():
+    """Load libibmg.so from the package directory; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libibmg.so is not built ({LIB_PATH}); run paper_1612_02208_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.ibmg_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+    lib.ibmg_destroy.argtypes = [vp]
+    lib.ibmg_last_error.argtypes = [vp]
+    lib.ibmg_last_error.restype = ctypes.c_char_p
+    lib.ibmg_levels.argtypes = [vp, _ip]
+    lib.ibmg_level_n.argtypes = [vp, ctypes.c_int32, _ip]
+    for name in ("ibmg_apply_A_IB", "ibmg_apply_A_IB_T", "ibmg_restrict", "ibmg_prolong_add",
+                 "ibmg_smoother_apply"):
+        getattr(lib, name).argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    lib.ibmg_smooth.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
+    for name in ("ibmg_spread", "ibmg_interp", "ibmg_coarse_solve", "ibmg_vcycle"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+    lib.ibmg_fgmres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.ibmg_spring_gradient.argtypes = [vp, vp, vp, vp, vp]
+    lib.ibmg_set_kappa.argtypes = [vp, _dp, vp]
+    lib.ibmg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
+    for name in EXPORTS:
+        if name != "ibmg_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib

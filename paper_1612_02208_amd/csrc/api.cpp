@@ -1,0 +1,215 @@
+// extern "C" entry points of libibmg (declared in include/ibmg.h): argument
+// checks, error translation and dispatch to the solver object.
+#include <cmath>
+#include <mutex>
+
+#include "solver.hpp"
+
+struct ibmg_handle {
+  ibmg::SolverBase* s = nullptr;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <typename F>
+ibmg_status guarded(ibmg_handle* h, F&& f) {
+  if (!h || !h->s) return IBMG_ERR_STATE;
+  try {
+    return (ibmg_status)f(h->s);
+  } catch (const ibmg::Error& e) {
+    h->err = e.what();
+    return (ibmg_status)e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return IBMG_ERR_HIP;
+  }
+}
+
+hipStream_t S(ibmg_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_level(ibmg::SolverBase* s, int level, int lo) {
+  ibmg::require(level >= lo && level < s->levels(), "level out of range");
+}
+
+}  // namespace
+
+extern "C" {
+
+ibmg_status ibmg_create(const ibmg_desc* desc, ibmg_stream stream, ibmg_handle** out) {
+  if (!out) return IBMG_ERR_ARG;
+  *out = nullptr;
+  if (!desc) {
+    g_create_error = "desc is NULL";
+    return IBMG_ERR_ARG;
+  }
+  try {
+    auto* h = new ibmg_handle();
+    try {
+      h->s = ibmg::make_solver(*desc, S(stream));
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return IBMG_OK;
+  } catch (const ibmg::Error& e) {
+    g_create_error = e.what();
+    return (ibmg_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return IBMG_ERR_HIP;
+  }
+}
+
+ibmg_status ibmg_destroy(ibmg_handle* h) {
+  if (!h) return IBMG_ERR_STATE;
+  delete h->s;
+  delete h;
+  return IBMG_OK;
+}
+
+const char* ibmg_last_error(const ibmg_handle* h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+ibmg_status ibmg_levels(const ibmg_handle* h, int32_t* n_levels) {
+  if (!h || !h->s) return IBMG_ERR_STATE;
+  if (!n_levels) return IBMG_ERR_ARG;
+  *n_levels = h->s->levels();
+  return IBMG_OK;
+}
+
+ibmg_status ibmg_level_n(const ibmg_handle* h, int32_t level, int32_t* n) {
+  if (!h || !h->s) return IBMG_ERR_STATE;
+  if (!n || level < 0 || level >= h->s->levels()) return IBMG_ERR_ARG;
+  *n = h->s->level_n(level);
+  return IBMG_OK;
+}
+
+ibmg_status ibmg_apply_A_IB(ibmg_handle* h, int32_t level, const double* w, double* y, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    check_level(s, level, 0);
+    ibmg::require(w && y && w != y, "w and y must be distinct device pointers");
+    s->apply(level, w, y, false, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_apply_A_IB_T(ibmg_handle* h, int32_t level, const double* w, double* y, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    check_level(s, level, 0);
+    ibmg::require(w && y && w != y, "w and y must be distinct device pointers");
+    s->apply(level, w, y, true, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_spread(ibmg_handle* h, const double* F, double* f, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(f != nullptr, "f is NULL");
+    s->spread(F, f, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_interp(ibmg_handle* h, const double* u, double* U, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(u != nullptr, "u is NULL");
+    s->interp(u, U, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_restrict(ibmg_handle* h, int32_t level, const double* fine, double* coarse, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    check_level(s, level, 1);
+    ibmg::require(fine && coarse, "NULL vector");
+    s->restrict_(level, fine, coarse, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_prolong_add(ibmg_handle* h, int32_t level, const double* coarse, double* fine, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    check_level(s, level, 1);
+    ibmg::require(fine && coarse, "NULL vector");
+    s->prolong_add(level, coarse, fine, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_smoother_apply(ibmg_handle* h, int32_t level, const double* r, double* z, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    check_level(s, level, 1);
+    ibmg::require(r && z && r != z, "r and z must be distinct device pointers");
+    s->smoother_apply(level, r, z, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_smooth(ibmg_handle* h, int32_t level, double* w, const double* b, int32_t nu, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    check_level(s, level, 1);
+    ibmg::require(w && b && w != b, "w and b must be distinct device pointers");
+    s->smooth(level, w, b, nu, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_coarse_solve(ibmg_handle* h, const double* r, double* x, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(r && x && r != x, "r and x must be distinct device pointers");
+    s->coarse_solve(r, x, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_vcycle(ibmg_handle* h, const double* r, double* z, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(r && z && r != z, "r and z must be distinct device pointers");
+    s->vcycle(r, z, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_fgmres_solve(ibmg_handle* h, const double* b, double* x, const ibmg_solve_opts* opts,
+                              ibmg_solve_info* info, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(b && x && b != x, "b and x must be distinct device pointers");
+    ibmg_solve_opts o{1e-8, 30, 100, 0};
+    if (opts) o = *opts;
+    return s->fgmres(b, x, o, info, S(st));
+  });
+}
+
+ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* lambda, double* out,
+                                 ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(w && lambda, "NULL vector");
+    s->spring_gradient(w, lambda, out, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    s->set_kappa(kappa, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written) {
+  if (!h || !h->s) return IBMG_ERR_STATE;
+  if (!written || (cap > 0 && !out)) return IBMG_ERR_ARG;
+  std::vector<int64_t> v = h->s->stats();
+  int n = 0;
+  for (; n < (int)v.size() && n < cap; ++n) out[n] = v[n];
+  *written = (int32_t)v.size();
+  return IBMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,527 @@
+// Grid kernels: the MAC Stokes-IB operator (Eq. matrix-impib, App. A.1), its
+// transpose, the inter-level transfers (Sec. 3.2) and the BLAS-1 / small
+// dense pieces of the Krylov iterations (Sec. 3.3 smoothing, outer FGMRES).
+#include "internal.hpp"
+
+namespace ibmg {
+
+static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// L_IB w (or its transpose, or the residual b - L_IB w).  One thread per
+// (i, j) computes the x-face, y-face and cell rows of that index:
+//   y_u = alpha u - mu Lap u + (p_ij - p_{i-1,j}) / h + dt/h^2 (J^T K' J u)
+//   y_v = alpha v - mu Lap v + (p_ij - p_{i,j-1}) / h + dt/h^2 (J^T K' J v)
+//   y_p = -(u_{i+1,j} - u_ij + v_{i,j+1} - v_ij) / h
+// The IB term arrives as the nodal forces F = K' J u (k_ib_force) and is
+// gathered through the face -> (point, slot) lists, so no atomics are used.
+// The transposed form evaluates -D^T p and G^T u directly; the IB block is
+// the same J^T K' J chain with J standing in for S^T (S = J^* / h^2).
+// ---------------------------------------------------------------------------
+template <typename T, bool TRANS, bool RESID>
+__global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __restrict__ y,
+                                               const T* __restrict__ b, const T* __restrict__ F,
+                                               FootView<T> fx, FootView<T> fy, int N, int M,
+                                               StokesCoef<T> c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  const size_t n = (size_t)N * N;
+  const T* u = w;
+  const T* v = w + n;
+  const T* p = w + 2 * n;
+  const int im = i == 0 ? N - 1 : i - 1;
+  const int ip = i == N - 1 ? 0 : i + 1;
+  const int jm = j == 0 ? N - 1 : j - 1;
+  const int jp = j == N - 1 ? 0 : j + 1;
+  const size_t c0 = (size_t)j * N + i;
+  const size_t cl = (size_t)j * N + im, cr = (size_t)j * N + ip;
+  const size_t cd = (size_t)jm * N + i, ct = (size_t)jp * N + i;
+  const T uc = u[c0], ul = u[cl], ur = u[cr], ud = u[cd], ut = u[ct];
+  const T vc = v[c0], vl = v[cl], vr = v[cr], vd = v[cd], vt = v[ct];
+  const T pc = p[c0], pl = p[cl], pd = p[cd];
+  T ibu = 0, ibv = 0;
+  if (F != nullptr) {
+    const int a0 = fx.sp_ptr[c0], a1 = fx.sp_ptr[c0 + 1];
+    for (int e = a0; e < a1; ++e) {
+      const int ent = fx.sp_ent[e];
+      ibu += fx.w[ent] * F[ent >> 4];
+    }
+    const int b0 = fy.sp_ptr[c0], b1 = fy.sp_ptr[c0 + 1];
+    for (int e = b0; e < b1; ++e) {
+      const int ent = fy.sp_ent[e];
+      ibv += fy.w[ent] * F[M + (ent >> 4)];
+    }
+  }
+  const T lapu = ul + ur + ud + ut - T(4) * uc;
+  const T lapv = vl + vr + vd + vt - T(4) * vc;
+  T yu, yv, yp;
+  if (!TRANS) {
+    yu = c.alpha * uc - c.beta * lapu + c.gi * (pc - pl) + c.ibs * ibu;
+    yv = c.alpha * vc - c.beta * lapv + c.gi * (pc - pd) + c.ibs * ibv;
+    yp = -c.gi * (ur - uc + vt - vc);
+  } else {
+    // (-D^T p) on the x-face (i, j): D maps the face to cells (i, j) with -1/h
+    // and (i-1, j) with +1/h.  G^T u on cell (i, j): G maps the cell to faces
+    // (i, j) with +1/h and (i+1, j) with -1/h (likewise in y).
+    yu = c.alpha * uc - c.beta * lapu - c.gi * (pl - pc) + c.ibs * ibu;
+    yv = c.alpha * vc - c.beta * lapv - c.gi * (pd - pc) + c.ibs * ibv;
+    yp = c.gi * (uc - ur + vc - vt);
+  }
+  if (RESID) {
+    yu = b[c0] - yu;
+    yv = b[n + c0] - yv;
+    yp = b[2 * n + c0] - yp;
+  }
+  y[c0] = yu;
+  y[n + c0] = yv;
+  y[2 * n + c0] = yp;
+}
+
+template <typename T>
+void launch_apply(const T* w, T* y, const T* b, const T* F, FootView<T> fx, FootView<T> fy,
+                  int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s) {
+  dim3 blk(64, 4);
+  dim3 grd((N + 63) / 64, (N + 3) / 4);
+  if (b) {
+    if (transpose)
+      hipLaunchKernelGGL((k_apply<T, true, true>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+    else
+      hipLaunchKernelGGL((k_apply<T, false, true>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+  } else {
+    if (transpose)
+      hipLaunchKernelGGL((k_apply<T, true, false>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+    else
+      hipLaunchKernelGGL((k_apply<T, false, false>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+  }
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Restriction (Sec. 3.2): R_u = P_u^T / 4 (adjoint of the Raviart-Thomas
+// prolongation), R_p = mean of the four fine cells.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_restrict(const T* __restrict__ f, T* __restrict__ cz, int Nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= Nc || j >= Nc) return;
+  const int Nf = 2 * Nc;
+  const size_t nf = (size_t)Nf * Nf, nc = (size_t)Nc * Nc;
+  auto at = [&](int comp, int I, int J) -> T {
+    I = I < 0 ? I + Nf : (I >= Nf ? I - Nf : I);
+    J = J < 0 ? J + Nf : (J >= Nf ? J - Nf : J);
+    return f[comp * nf + (size_t)J * Nf + I];
+  };
+  const int I = 2 * i, J = 2 * j;
+  const T ru = T(0.25) * (at(0, I, J) + at(0, I, J + 1)) +
+               T(0.125) * (at(0, I - 1, J) + at(0, I - 1, J + 1) + at(0, I + 1, J) + at(0, I + 1, J + 1));
+  const T rv = T(0.25) * (at(1, I, J) + at(1, I + 1, J)) +
+               T(0.125) * (at(1, I, J - 1) + at(1, I + 1, J - 1) + at(1, I, J + 1) + at(1, I + 1, J + 1));
+  const T rp = T(0.25) * (at(2, I, J) + at(2, I + 1, J) + at(2, I, J + 1) + at(2, I + 1, J + 1));
+  const size_t o = (size_t)j * Nc + i;
+  cz[o] = ru;
+  cz[nc + o] = rv;
+  cz[2 * nc + o] = rp;
+}
+
+template <typename T>
+void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s) {
+  dim3 blk(64, 4);
+  dim3 grd((Nc + 63) / 64, (Nc + 3) / 4);
+  hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc);
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation and correction, fine += P e (Sec. 3.2): lowest-order
+// Raviart-Thomas for velocity (linear across the face normal, constant along
+// it), bilinear cell-centred interpolation for pressure.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_prolong_add(const T* __restrict__ cz, T* __restrict__ f, int Nc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  const int Nf = 2 * Nc;
+  if (I >= Nf || J >= Nf) return;
+  const size_t nf = (size_t)Nf * Nf, nc = (size_t)Nc * Nc;
+  auto at = [&](int comp, int i, int j) -> T {
+    i = i < 0 ? i + Nc : (i >= Nc ? i - Nc : i);
+    j = j < 0 ? j + Nc : (j >= Nc ? j - Nc : j);
+    return cz[comp * nc + (size_t)j * Nc + i];
+  };
+  const int i = I >> 1, j = J >> 1;
+  const T eu = (I & 1) ? T(0.5) * (at(0, i, j) + at(0, i + 1, j)) : at(0, i, j);
+  const T ev = (J & 1) ? T(0.5) * (at(1, i, j) + at(1, i, j + 1)) : at(1, i, j);
+  const int di = (I & 1) ? 1 : -1, dj = (J & 1) ? 1 : -1;
+  const T ep = T(9.0 / 16.0) * at(2, i, j) + T(3.0 / 16.0) * (at(2, i + di, j) + at(2, i, j + dj)) +
+               T(1.0 / 16.0) * at(2, i + di, j + dj);
+  const size_t o = (size_t)J * Nf + I;
+  f[o] += eu;
+  f[nf + o] += ev;
+  f[2 * nf + o] += ep;
+}
+
+template <typename T>
+void launch_prolong_add(const T* coarse, T* fine, int Nc, hipStream_t s) {
+  const int Nf = 2 * Nc;
+  dim3 blk(64, 4);
+  dim3 grd((Nf + 63) / 64, (Nf + 3) / 4);
+  hipLaunchKernelGGL((k_prolong_add<T>), grd, blk, 0, s, coarse, fine, Nc);
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers.
+// ---------------------------------------------------------------------------
+template <typename Ts, typename Td>
+__global__ void k_cast(const Ts* __restrict__ a, Td* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (Td)a[i];
+}
+
+template <typename Ts, typename Td>
+void launch_cast(const Ts* a, Td* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  int g = cdiv(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL((k_cast<Ts, Td>), dim3(g), dim3(256), 0, s, a, b, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void k_fill(T* a, T v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+template <typename T>
+void launch_fill(T* a, T v, size_t n, hipStream_t s) {
+  if (!n) return;
+  int g = cdiv(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL((k_fill<T>), dim3(g), dim3(256), 0, s, a, v, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic multi-dot: partial[blk * nvec + q] = sum over the block's
+// grid-stride slice of V_q . t, accumulated in double; the finishing kernel
+// adds the partials in a fixed tree order.  The grid size depends only on n.
+// ---------------------------------------------------------------------------
+int dots_blocks(size_t n) {
+  int g = cdiv(n, 256 * 8);
+  if (g < 1) g = 1;
+  if (g > 512) g = 512;
+  return g;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dots(const T* __restrict__ V, int nvec, size_t stride,
+                                              const T* __restrict__ t, size_t n,
+                                              double* __restrict__ partial) {
+  __shared__ double red[8][256];
+  const int tid = threadIdx.x;
+  for (int v0 = 0; v0 < nvec; v0 += 8) {
+    const int nv = nvec - v0 < 8 ? nvec - v0 : 8;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (size_t i = blockIdx.x * (size_t)256 + tid; i < n; i += (size_t)gridDim.x * 256) {
+      const double ti = (double)t[i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nv) acc[q] += (double)V[(size_t)(v0 + q) * stride + i] * ti;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][tid] = acc[q];
+    __syncthreads();
+    for (int sft = 128; sft > 0; sft >>= 1) {
+      if (tid < sft) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][tid] += red[q][tid + sft];
+      }
+      __syncthreads();
+    }
+    if (tid < nv) partial[(size_t)blockIdx.x * nvec + v0 + tid] = red[tid][0];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void launch_dots(const T* V, int nvec, size_t stride, const T* t, size_t n, double* partial,
+                 int nblk, hipStream_t s) {
+  hipLaunchKernelGGL((k_dots<T>), dim3(nblk), dim3(256), 0, s, V, nvec, stride, t, n, partial);
+  IBMG_LAUNCH_CHECK();
+}
+
+// mode 0: out1 = s; mode 1: out1 = s, out2 += s; mode 2: out1 = sqrt(s) (and out2 = sqrt(s))
+__global__ void __launch_bounds__(256) k_dots_finish(const double* __restrict__ partial, int nvec,
+                                                     int nblk, double* out1, double* out2, int mode) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  for (int q = 0; q < nvec; ++q) {
+    double a = 0.0;
+    for (int b = tid; b < nblk; b += 256) a += partial[(size_t)b * nvec + q];
+    red[tid] = a;
+    __syncthreads();
+    for (int sft = 128; sft > 0; sft >>= 1) {
+      if (tid < sft) red[tid] += red[tid + sft];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double sres = red[0];
+      if (mode == 0) {
+        out1[q] = sres;
+      } else if (mode == 1) {
+        out1[q] = sres;
+        out2[q] += sres;
+      } else {
+        const double r = sqrt(sres);
+        out1[q] = r;
+        if (out2) out2[q] = r;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_dots_finish(const double* partial, int nvec, int nblk, double* out1, double* out2,
+                        int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(256), 0, s, partial, nvec, nblk, out1, out2, mode);
+  IBMG_LAUNCH_CHECK();
+}
+
+// t += sign * sum_q coef[q] V_q
+template <typename T>
+__global__ void k_update(T* __restrict__ t, const T* __restrict__ V, int nvec, size_t stride,
+                         const double* __restrict__ coef, double sign, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double a = (double)t[i];
+    for (int q = 0; q < nvec; ++q) a += sign * coef[q] * (double)V[(size_t)q * stride + i];
+    t[i] = (T)a;
+  }
+}
+
+template <typename T>
+void launch_update(T* t, const T* V, int nvec, size_t stride, const double* coef, double sign,
+                   size_t n, hipStream_t s) {
+  int g = cdiv(n, 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL((k_update<T>), dim3(g), dim3(256), 0, s, t, V, nvec, stride, coef, sign, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+// v = t / denom (v = 0 when denom == 0: an exact Krylov breakdown)
+template <typename T>
+__global__ void k_scale(const T* t, T* v, const double* __restrict__ denom,
+                        size_t n) {
+  const double d = denom[0];
+  const double inv = d != 0.0 ? 1.0 / d : 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = (T)((double)t[i] * inv);
+}
+
+template <typename T>
+void launch_scale(const T* t, T* v, const double* denom, size_t n, hipStream_t s) {
+  int g = cdiv(n, 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL((k_scale<T>), dim3(g), dim3(256), 0, s, t, v, denom, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+// x += sum_q y[q] Z_q
+template <typename T>
+__global__ void k_combine(T* __restrict__ x, const T* __restrict__ Z, int k, size_t stride,
+                          const double* __restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double a = (double)x[i];
+    for (int q = 0; q < k; ++q) a += y[q] * (double)Z[(size_t)q * stride + i];
+    x[i] = (T)a;
+  }
+}
+
+template <typename T>
+void launch_combine(T* x, const T* Z, int k, size_t stride, const double* y, size_t n, hipStream_t s) {
+  int g = cdiv(n, 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL((k_combine<T>), dim3(g), dim3(256), 0, s, x, Z, k, stride, y, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Least squares min || beta e1 - H y || for a (k+1) x k Hessenberg matrix
+// (column-major, leading dimension ldh) by Givens rotations; k <= 16.
+// Zero pivots (exact breakdown) give zero components.
+// ---------------------------------------------------------------------------
+__global__ void k_small_ls(const double* __restrict__ H, int ldh, int k, const double* __restrict__ beta,
+                           double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double R[17][16];
+  double g[17];
+  double cs[16], sn[16];
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= k; ++i) R[i][j] = H[i + (size_t)j * ldh];
+  for (int i = 0; i <= k; ++i) g[i] = 0.0;
+  g[0] = beta[0];
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i < j; ++i) {
+      const double a = R[i][j], b = R[i + 1][j];
+      R[i][j] = cs[i] * a + sn[i] * b;
+      R[i + 1][j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = R[j][j], b = R[j + 1][j];
+    const double d = sqrt(a * a + b * b);
+    double c = 1.0, s = 0.0;
+    if (d != 0.0) { c = a / d; s = b / d; }
+    cs[j] = c;
+    sn[j] = s;
+    R[j][j] = d;
+    R[j + 1][j] = 0.0;
+    const double gj = g[j];
+    g[j] = c * gj;
+    g[j + 1] = -s * gj;
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    double a = g[j];
+    for (int m = j + 1; m < k; ++m) a -= R[j][m] * y[m];
+    y[j] = R[j][j] != 0.0 ? a / R[j][j] : 0.0;
+  }
+}
+
+void launch_small_ls(double* H, int ldh, int k, const double* beta, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_ls, dim3(1), dim3(64), 0, s, H, ldh, k, beta, y);
+  IBMG_LAUNCH_CHECK();
+}
+
+// Outer FGMRES: rotate column k of H (rows 0..k+1) by the stored rotations,
+// form rotation k, update g and write |g[k+1]| to res.
+__global__ void k_givens(double* __restrict__ H, int ldh, int k, double* __restrict__ cs,
+                         double* __restrict__ sn, double* __restrict__ g, double* __restrict__ res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* col = H + (size_t)k * ldh;
+  for (int i = 0; i < k; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[k], b = col[k + 1];
+  const double d = sqrt(a * a + b * b);
+  double c = 1.0, s = 0.0;
+  if (d != 0.0) { c = a / d; s = b / d; }
+  cs[k] = c;
+  sn[k] = s;
+  col[k] = d;
+  col[k + 1] = 0.0;
+  const double gk = g[k];
+  g[k] = c * gk;
+  g[k + 1] = -s * gk;
+  res[0] = fabs(g[k + 1]);
+}
+
+void launch_givens(double* H, int ldh, int k, double* cs, double* sn, double* g, double* res,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, H, ldh, k, cs, sn, g, res);
+  IBMG_LAUNCH_CHECK();
+}
+
+__global__ void k_backsolve(const double* __restrict__ H, int ldh, int k, const double* __restrict__ g,
+                            double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int j = k - 1; j >= 0; --j) {
+    double a = g[j];
+    for (int m = j + 1; m < k; ++m) a -= H[j + (size_t)m * ldh] * y[m];
+    const double d = H[j + (size_t)j * ldh];
+    y[j] = d != 0.0 ? a / d : 0.0;
+  }
+}
+
+void launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, k, g, y);
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Block sums of a level vector (u, v, p) for the null-space projection.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_block_sums(const T* __restrict__ a, size_t nn,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x;
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (size_t i = blockIdx.x * (size_t)256 + tid; i < nn; i += (size_t)gridDim.x * 256) {
+    s0 += (double)a[i];
+    s1 += (double)a[nn + i];
+    s2 += (double)a[2 * nn + i];
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  red[2][tid] = s2;
+  __syncthreads();
+  for (int sft = 128; sft > 0; sft >>= 1) {
+    if (tid < sft) {
+      red[0][tid] += red[0][tid + sft];
+      red[1][tid] += red[1][tid + sft];
+      red[2][tid] += red[2][tid + sft];
+    }
+    __syncthreads();
+  }
+  if (tid < 3) partial[(size_t)blockIdx.x * 3 + tid] = red[tid][0];
+}
+
+template <typename T>
+void launch_block_sums(const T* a, int N, double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL((k_block_sums<T>), dim3(nblk), dim3(256), 0, s, a, (size_t)N * N, partial);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void k_subtract_means(T* __restrict__ a, size_t nn, const double* __restrict__ sums,
+                                 int nvel) {
+  const double inv = 1.0 / (double)nn;
+  const double m0 = nvel ? sums[0] * inv : 0.0;
+  const double m1 = nvel ? sums[1] * inv : 0.0;
+  const double m2 = sums[2] * inv;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
+    if (nvel) {
+      a[i] = (T)((double)a[i] - m0);
+      a[nn + i] = (T)((double)a[nn + i] - m1);
+    }
+    a[2 * nn + i] = (T)((double)a[2 * nn + i] - m2);
+  }
+}
+
+template <typename T>
+void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_t s) {
+  size_t nn = (size_t)N * N;
+  int g = cdiv(nn, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL((k_subtract_means<T>), dim3(g), dim3(256), 0, s, a, nn, sums, nvel);
+  IBMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Explicit instantiations.
+// ---------------------------------------------------------------------------
+#define IBMG_INST_GRID(T)                                                                         \
+  template void launch_apply<T>(const T*, T*, const T*, const T*, FootView<T>, FootView<T>, int,  \
+                                int, StokesCoef<T>, bool, hipStream_t);                           \
+  template void launch_restrict<T>(const T*, T*, int, hipStream_t);                               \
+  template void launch_prolong_add<T>(const T*, T*, int, hipStream_t);                            \
+  template void launch_fill<T>(T*, T, size_t, hipStream_t);                                       \
+  template void launch_dots<T>(const T*, int, size_t, const T*, size_t, double*, int, hipStream_t); \
+  template void launch_update<T>(T*, const T*, int, size_t, const double*, double, size_t,        \
+                                 hipStream_t);                                                    \
+  template void launch_scale<T>(const T*, T*, const double*, size_t, hipStream_t);                \
+  template void launch_combine<T>(T*, const T*, int, size_t, const double*, size_t, hipStream_t); \
+  template void launch_block_sums<T>(const T*, int, double*, int, hipStream_t);                   \
+  template void launch_subtract_means<T>(T*, int, const double*, int, hipStream_t);
+
+IBMG_INST_GRID(double)
+IBMG_INST_GRID(float)
+template void launch_cast<double, float>(const double*, float*, size_t, hipStream_t);
+template void launch_cast<float, double>(const float*, double*, size_t, hipStream_t);
+template void launch_cast<double, double>(const double*, double*, size_t, hipStream_t);
+
+}  // namespace ibmg

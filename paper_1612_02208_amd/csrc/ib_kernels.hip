@@ -1,0 +1,299 @@
+// Immersed-boundary kernels: Peskin four-point weights (App. A.3), their
+// Galerkin coarsening through the velocity prolongation (Sec. 3.1-3.2),
+// interpolation J_h, spreading S_h = J_h^T / h^2 with unit nodal weights,
+// the spring operator K' = sum_e kappa_e B_e^T B_e of zero-rest-length fibres
+// (Sec. 5, App. A.2), the explicit Galerkin IB operator rows used to assemble
+// dense box and coarsest-level matrices, and the stiffness gradient.
+//
+// Spreading is a gather: every face walks the (point, slot) entries sorted
+// by face at set-up, so results are deterministic and use no atomics.
+#include "internal.hpp"
+
+namespace ibmg {
+
+static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ double phi4(double r) {
+  const double a = fabs(r);
+  if (a < 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+  if (a < 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+  return 0.0;
+}
+
+__device__ __forceinline__ int wrapi(int a, int N) { return a >= N ? a - N : a; }
+
+// periodic difference t - k folded into (-N/2, N/2]
+__device__ __forceinline__ double pdiff(double t, int k, int N) {
+  double d = t - (double)k;
+  if (d > 0.5 * N) d -= N;
+  if (d <= -0.5 * N) d += N;
+  return d;
+}
+
+// Finest-level weights phi(rx) phi(ry) on the 4 x 4 window (masked slots 0).
+__global__ void k_fp_fine(const double* __restrict__ X, int M, int N, int comp,
+                          const int* __restrict__ base, const int* __restrict__ mask,
+                          double* __restrict__ w) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= M) return;
+  const double sx = comp == 0 ? 0.0 : 0.5;
+  const double sy = comp == 0 ? 0.5 : 0.0;
+  const double tx = X[2 * l] * N - sx;
+  const double ty = X[2 * l + 1] * N - sy;
+  const int i0 = base[2 * l], j0 = base[2 * l + 1];
+  const int mk = mask[l];
+  double wx[4], wy[4];
+  for (int a = 0; a < 4; ++a) {
+    wx[a] = phi4(pdiff(tx, i0 + a, N));
+    wy[a] = phi4(pdiff(ty, j0 + a, N));
+  }
+  for (int s = 0; s < 16; ++s)
+    w[(size_t)l * 16 + s] = ((mk >> s) & 1) ? wx[s & 3] * wy[s >> 2] : 0.0;
+}
+
+void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
+                    double* w, hipStream_t s) {
+  if (!M) return;
+  hipLaunchKernelGGL(k_fp_fine, dim3(cdiv(M, 128)), dim3(128), 0, s, X, M, N, comp, base, mask, w);
+  IBMG_LAUNCH_CHECK();
+}
+
+// Coarse weights J_l = J_{l+1} P_u: every fine slot (I, J) is pushed to the
+// coarse faces that P_u interpolates it from -- along the face normal an
+// even fine index copies coarse I/2 and an odd one averages (I-1)/2 and
+// (I+1)/2; tangentially the coarse index is floor(I/2).
+__global__ void k_fp_coarsen(const int* __restrict__ fbase, const double* __restrict__ fw,
+                             const int* __restrict__ cbase, int M, int comp,
+                             double* __restrict__ cw) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= M) return;
+  const int I0 = fbase[2 * l], J0 = fbase[2 * l + 1];
+  const int ci0 = I0 >> 1, cj0 = J0 >> 1;
+  double acc[16];
+  for (int s = 0; s < 16; ++s) acc[s] = 0.0;
+  for (int s = 0; s < 16; ++s) {
+    const double wf = fw[(size_t)l * 16 + s];
+    if (wf == 0.0) continue;
+    const int I = I0 + (s & 3), J = J0 + (s >> 2);
+    if (comp == 0) {
+      const int cj = (J >> 1) - cj0;
+      if ((I & 1) == 0) {
+        acc[cj * 4 + ((I >> 1) - ci0)] += wf;
+      } else {
+        acc[cj * 4 + ((I - 1) / 2 - ci0)] += 0.5 * wf;
+        acc[cj * 4 + ((I + 1) / 2 - ci0)] += 0.5 * wf;
+      }
+    } else {
+      const int ci = (I >> 1) - ci0;
+      if ((J & 1) == 0) {
+        acc[((J >> 1) - cj0) * 4 + ci] += wf;
+      } else {
+        acc[((J - 1) / 2 - cj0) * 4 + ci] += 0.5 * wf;
+        acc[((J + 1) / 2 - cj0) * 4 + ci] += 0.5 * wf;
+      }
+    }
+  }
+  (void)cbase;
+  for (int s = 0; s < 16; ++s) cw[(size_t)l * 16 + s] = acc[s];
+}
+
+void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int M, int comp,
+                       int Nf, int Nc, double* cw, hipStream_t s) {
+  (void)Nf;
+  (void)Nc;
+  if (!M) return;
+  hipLaunchKernelGGL(k_fp_coarsen, dim3(cdiv(M, 128)), dim3(128), 0, s, fbase, fw, cbase, M, comp, cw);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+__device__ __forceinline__ T interp_one(const T* __restrict__ f, const int* __restrict__ base,
+                                        const T* __restrict__ w, int l, int N) {
+  const int i0 = base[2 * l], j0 = base[2 * l + 1];
+  T acc = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = wrapi(j0 + b, N);
+    const T* row = f + (size_t)j * N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc += w[(size_t)l * 16 + b * 4 + a] * row[wrapi(i0 + a, N)];
+  }
+  return acc;
+}
+
+// F_l = sum over springs e at l of kappa_e ((J u)_l - (J u)_{other end}), both
+// components; F is planar [2][M].
+template <typename T>
+__global__ void k_ib_force(const T* __restrict__ u, const T* __restrict__ v, FootView<T> fx,
+                           FootView<T> fy, SpringView<T> sv, int N, T* __restrict__ F) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= sv.M) return;
+  const int e0 = sv.adj_ptr[l], e1 = sv.adj_ptr[l + 1];
+  T f0 = 0, f1 = 0;
+  if (e1 > e0) {
+    const T U0 = interp_one(u, fx.base, fx.w, l, N);
+    const T U1 = interp_one(v, fy.base, fy.w, l, N);
+    for (int e = e0; e < e1; ++e) {
+      const int q = sv.adj_nbr[e];
+      const T k = sv.adj_k[e];
+      f0 += k * (U0 - interp_one(u, fx.base, fx.w, q, N));
+      f1 += k * (U1 - interp_one(v, fy.base, fy.w, q, N));
+    }
+  }
+  F[l] = f0;
+  F[sv.M + l] = f1;
+}
+
+template <typename T>
+void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
+                     int N, T* F, hipStream_t s) {
+  if (!sv.M) return;
+  hipLaunchKernelGGL((k_ib_force<T>), dim3(cdiv(sv.M, 128)), dim3(128), 0, s, u, v, fx, fy, sv, N, F);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void k_interp(const T* __restrict__ u, const T* __restrict__ v, FootView<T> fx,
+                         FootView<T> fy, int M, int N, T* __restrict__ U) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= M) return;
+  U[2 * l] = interp_one(u, fx.base, fx.w, l, N);
+  U[2 * l + 1] = interp_one(v, fy.base, fy.w, l, N);
+}
+
+template <typename T>
+void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
+                   hipStream_t s) {
+  if (!M) return;
+  hipLaunchKernelGGL((k_interp<T>), dim3(cdiv(M, 128)), dim3(128), 0, s, u, v, fx, fy, M, N, U);
+  IBMG_LAUNCH_CHECK();
+}
+
+// f_face = scale * sum_(l, slot) w F_l, F interleaved [M][2]; f = [2][N][N].
+__global__ void k_spread(const double* __restrict__ F, FootView<double> fx, FootView<double> fy,
+                         int N, double scale, double* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  const size_t c0 = (size_t)j * N + i;
+  double a = 0, b = 0;
+  for (int e = fx.sp_ptr[c0]; e < fx.sp_ptr[c0 + 1]; ++e) {
+    const int ent = fx.sp_ent[e];
+    a += fx.w[ent] * F[2 * (ent >> 4)];
+  }
+  for (int e = fy.sp_ptr[c0]; e < fy.sp_ptr[c0 + 1]; ++e) {
+    const int ent = fy.sp_ent[e];
+    b += fy.w[ent] * F[2 * (ent >> 4) + 1];
+  }
+  f[c0] = scale * a;
+  f[(size_t)N * N + c0] = scale * b;
+}
+
+void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, int M, int N,
+                   double scale, double* f, hipStream_t s) {
+  (void)M;
+  dim3 blk(64, 4);
+  dim3 grd((N + 63) / 64, (N + 3) / 4);
+  hipLaunchKernelGGL(k_spread, grd, blk, 0, s, F, fx, fy, N, scale, f);
+  IBMG_LAUNCH_CHECK();
+}
+
+// Slot of face (i, j) in point q's window, or -1.
+__device__ __forceinline__ int slot_of(const int* __restrict__ base, const int* __restrict__ mask,
+                                       int q, int i, int j, int N) {
+  int a = i - base[2 * q];
+  if (a < 0) a += N;
+  int b = j - base[2 * q + 1];
+  if (b < 0) b += N;
+  if (a > 3 || b > 3) return -1;
+  const int s = b * 4 + a;
+  return ((mask[q] >> s) & 1) ? s : -1;
+}
+
+__device__ __forceinline__ void csr_add(const int* __restrict__ cols, double* __restrict__ vals,
+                                        int lo, int hi, int col, double v) {
+  int a = lo, b = hi - 1;
+  while (a <= b) {
+    const int m = (a + b) >> 1;
+    const int c = cols[m];
+    if (c == col) { vals[m] += v; return; }
+    if (c < col) a = m + 1; else b = m - 1;
+  }
+}
+
+// Row r of the level IB operator dt/h^2 J^T K' J (one component):
+//   T(r, :) = ibs * sum_e kappa_e g_e(r) g_e,   g_e = J_{b_e} - J_{a_e},
+// summing over the springs with an end whose window holds r (a spring with
+// both ends there is counted once, from its lower-numbered end).
+__global__ void k_t_values(FootView<double> f, const int* __restrict__ mask, SpringView<double> sv,
+                           int N, double ibs, const int* __restrict__ t_ptr,
+                           const int* __restrict__ t_col, double* __restrict__ t_val) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N * N) return;
+  const int lo = t_ptr[r], hi = t_ptr[r + 1];
+  if (hi == lo) return;
+  for (int k = lo; k < hi; ++k) t_val[k] = 0.0;
+  const int ri = r % N, rj = r / N;
+  for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
+    const int ent = f.sp_ent[e];
+    const int l = ent >> 4;
+    const double wl_r = f.w[ent];
+    for (int a = sv.adj_ptr[l]; a < sv.adj_ptr[l + 1]; ++a) {
+      const int q = sv.adj_nbr[a];
+      const int sq = slot_of(f.base, mask, q, ri, rj, N);
+      if (sq >= 0 && q < l) continue;  // counted from q's side
+      const double wq_r = sq >= 0 ? f.w[(size_t)q * 16 + sq] : 0.0;
+      const double coef = ibs * sv.adj_k[a] * (wq_r - wl_r);
+      if (coef == 0.0) continue;
+      for (int s = 0; s < 16; ++s) {
+        if (((mask[l] >> s) & 1) == 0) continue;
+        const int ci = wrapi(f.base[2 * l] + (s & 3), N), cj = wrapi(f.base[2 * l + 1] + (s >> 2), N);
+        csr_add(t_col, t_val, lo, hi, cj * N + ci, -coef * f.w[(size_t)l * 16 + s]);
+      }
+      for (int s = 0; s < 16; ++s) {
+        if (((mask[q] >> s) & 1) == 0) continue;
+        const int ci = wrapi(f.base[2 * q] + (s & 3), N), cj = wrapi(f.base[2 * q + 1] + (s >> 2), N);
+        csr_add(t_col, t_val, lo, hi, cj * N + ci, coef * f.w[(size_t)q * 16 + s]);
+      }
+    }
+  }
+}
+
+void launch_t_values(FootView<double> f, const int* mask, SpringView<double> sv, int N, double ibs,
+                     const int* t_ptr, const int* t_col, double* t_val, hipStream_t s) {
+  const int n = N * N;
+  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n, 128)), dim3(128), 0, s, f, mask, sv, N, ibs, t_ptr,
+                     t_col, t_val);
+  IBMG_LAUNCH_CHECK();
+}
+
+// g_e = scale * sum_c (Ul_b - Ul_a)(Uw_b - Uw_a), U interleaved [M][2].
+__global__ void k_spring_grad(const double* __restrict__ Uw, const double* __restrict__ Ul,
+                              const int* __restrict__ ends, int n_springs, double scale,
+                              double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_springs) return;
+  const int a = ends[2 * e], b = ends[2 * e + 1];
+  double g = 0.0;
+  for (int c = 0; c < 2; ++c) g += (Ul[2 * b + c] - Ul[2 * a + c]) * (Uw[2 * b + c] - Uw[2 * a + c]);
+  out[e] = scale * g;
+}
+
+void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* unused,
+                        int n_springs, int M, double scale, double* out, hipStream_t s) {
+  (void)unused;
+  (void)M;
+  if (!n_springs) return;
+  hipLaunchKernelGGL(k_spring_grad, dim3(cdiv(n_springs, 128)), dim3(128), 0, s, Uw, Ul, ends,
+                     n_springs, scale, out);
+  IBMG_LAUNCH_CHECK();
+}
+
+template void launch_ib_force<double>(const double*, const double*, FootView<double>,
+                                      FootView<double>, SpringView<double>, int, double*, hipStream_t);
+template void launch_ib_force<float>(const float*, const float*, FootView<float>, FootView<float>,
+                                     SpringView<float>, int, float*, hipStream_t);
+template void launch_interp<double>(const double*, const double*, FootView<double>, FootView<double>,
+                                    int, int, double*, hipStream_t);
+
+}  // namespace ibmg

@@ -1,0 +1,188 @@
+// Internal declarations shared by the host orchestration and the HIP kernels.
+//
+// Conventions (see include/ibmg.h): a level vector is [u | v | p], each block
+// n*n in (j, i) row-major order; u[j][i] sits on the x-face (i h, (j+1/2) h),
+// v[j][i] on the y-face ((i+1/2) h, j h), p[j][i] at the cell centre.
+//
+// Immersed-boundary footprints.  Each Lagrangian point owns, per velocity
+// component and per level, a 4 x 4 window of faces starting at a wrapped base
+// (i0, j0); slot s = 4*b + a addresses face (i0 + a, j0 + b).  A 16-bit mask
+// marks the structurally coupled faces; the weights of the other slots are 0.
+// On the finest level the weight is phi(rx) phi(ry) (App. A.3); on a coarser
+// level it is the finer window pushed through the velocity prolongation,
+// J_l = J_{l+1} P_u, so that dt/h_l^2 J_l^T K' J_l is the Galerkin product
+// R_u [S K J]^{l+1} P_u of Sec. 3.1 (R_u = P_u^T / 4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ibmg.h"
+
+namespace ibmg {
+
+struct Error : public std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define IBMG_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::ibmg::Error(IBMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define IBMG_LAUNCH_CHECK() IBMG_HIP(hipGetLastError())
+
+inline void require(bool ok, const std::string& msg) {
+  if (!ok) throw Error(IBMG_ERR_ARG, msg);
+}
+
+// Owning device buffer.
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  explicit DBuf(size_t count) { alloc(count); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) IBMG_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const T* h, size_t count, hipStream_t s) {
+    if (count > n) alloc(count);
+    if (count) IBMG_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) { upload(h.data(), h.size(), s); }
+};
+
+// ---------------------------------------------------------------------------
+// Device-side views passed to kernels by value.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FootView {       // one component of one level
+  const int* base;      // [M][2] wrapped (i0, j0)
+  const T* w;           // [M][16] weights
+  const int* sp_ptr;    // [n*n + 1] faces -> entries
+  const int* sp_ent;    // entries l*16 + slot
+};
+
+template <typename T>
+struct SpringView {
+  int M;
+  const int* adj_ptr;   // [M + 1]
+  const int* adj_nbr;   // neighbour node per incidence
+  const T* adj_k;       // stiffness per incidence
+};
+
+template <typename T>
+struct StokesCoef {     // A = alpha I - mu Lap: alpha, beta = mu/h^2, gi = 1/h, ibs = dt/h^2
+  T alpha, beta, gi, ibs;
+};
+
+struct BoxGeom {        // RAS boxes on one level
+  int N, b, o, m, npd, nloc, nown;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+// grid ops
+template <typename T>
+void launch_apply(const T* w, T* y, const T* b, const T* F, FootView<T> fx, FootView<T> fy,
+                  int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s);
+template <typename T>
+void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const T* coarse, T* fine, int Nc, hipStream_t s);
+template <typename Ts, typename Td>
+void launch_cast(const Ts* a, Td* b, size_t n, hipStream_t s);
+template <typename T>
+void launch_fill(T* a, T v, size_t n, hipStream_t s);
+
+// Krylov helpers (T = vector type, reductions in double)
+template <typename T>
+void launch_dots(const T* V, int nvec, size_t stride, const T* t, size_t n, double* partial,
+                 int nblk, hipStream_t s);
+void launch_dots_finish(const double* partial, int nvec, int nblk, double* out1, double* out2,
+                        int mode, hipStream_t s);
+template <typename T>
+void launch_update(T* t, const T* V, int nvec, size_t stride, const double* coef, double sign,
+                   size_t n, hipStream_t s);
+template <typename T>
+void launch_scale(const T* t, T* v, const double* denom, size_t n, hipStream_t s);
+template <typename T>
+void launch_combine(T* x, const T* Z, int k, size_t stride, const double* y, size_t n,
+                    hipStream_t s);
+void launch_small_ls(double* H, int ldh, int k, const double* beta, double* y, hipStream_t s);
+void launch_givens(double* H, int ldh, int k, double* cs, double* sn, double* g, double* res,
+                   hipStream_t s);
+void launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s);
+template <typename T>
+void launch_block_sums(const T* a, int N, double* partial, int nblk, hipStream_t s);
+template <typename T>
+void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_t s);
+
+int dots_blocks(size_t n);
+
+// immersed boundary
+void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
+                    double* w, hipStream_t s);
+void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int M, int comp,
+                       int Nf, int Nc, double* cw, hipStream_t s);
+template <typename T>
+void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
+                     int N, T* F, hipStream_t s);
+template <typename T>
+void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N,
+                   T* U, hipStream_t s);
+void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, int M, int N,
+                   double scale, double* f, hipStream_t s);
+void launch_t_values(FootView<double> f, const int* mask, SpringView<double> sv, int N,
+                     double ibs, const int* t_ptr, const int* t_col, double* t_val,
+                     hipStream_t s);
+void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* unused,
+                        int n_springs, int M, double scale, double* out, hipStream_t s);
+
+// dense boxes and coarsest solve
+void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoef<double> c,
+                           const int* tptr_u, const int* tcol_u, const double* tval_u,
+                           const int* tptr_v, const int* tcol_v, const double* tval_v,
+                           double* mats, hipStream_t s);
+void launch_gj_invert(double* mats, int n, int count, double* colk, hipStream_t s);
+constexpr int kGjNb = 16;  // block width of the batched Gauss-Jordan inversion
+template <typename T>
+void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
+template <typename T>
+void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* blk_of_patch,
+                      hipStream_t s);
+void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,
+                            const double* tval_u, const int* tptr_v, const int* tcol_v,
+                            const double* tval_v, int nb, double* aug, hipStream_t s);
+void launch_coarse_invert(double* aug, int n, hipStream_t s);
+void launch_coarse_extract(const double* aug, int n, int n0, double* inv, hipStream_t s);
+template <typename T>
+void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_t s);
+
+}  // namespace ibmg

@@ -1,0 +1,774 @@
+// Host orchestration: hierarchy set-up, the V-cycle of Alg. 1 with
+// FGMRES-wrapped smoothing (Sec. 3.3), and the outer flexible GMRES solve.
+// Every arithmetic step runs in the kernels; the host builds index structures
+// (footprint windows, face -> point lists, IB row patterns, box classes) and
+// sequences launches on one stream.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <type_traits>
+
+#include "solver.hpp"
+
+namespace ibmg {
+
+namespace {
+
+constexpr int kMaxNu = 8;
+constexpr int kMaxRestart = 64;
+constexpr int kScalY = 1;     // scal[1..16]: least-squares solution
+constexpr int kScalTmp = 20;  // scal[20..]: second Gram-Schmidt pass
+
+int wrapn(int a, int N) {
+  a %= N;
+  return a < 0 ? a + N : a;
+}
+
+std::vector<int> level_sizes(int N, int coarse) {
+  std::vector<int> s;
+  for (int n = N; n >= coarse; n /= 2) {
+    s.push_back(n);
+    if (n == coarse) break;
+  }
+  std::reverse(s.begin(), s.end());
+  return s;
+}
+
+void box_params(int N, int box, int overlap, int* b, int* o) {
+  *b = std::min(box, N / 2);
+  *o = std::min(overlap, (N - *b - 1) / 2);
+  if (*o < 0) *o = 0;
+}
+
+}  // namespace
+
+void validate_desc(const ibmg_desc& d) {
+  require(d.coarse_N >= 4 && d.coarse_N <= 16, "coarse_N must lie in [4, 16]");
+  require(d.N > d.coarse_N && d.N <= 8192, "N must exceed coarse_N and be at most 8192");
+  {
+    int n = d.N;
+    while (n > d.coarse_N && n % 2 == 0) n /= 2;
+    require(n == d.coarse_N, "N must be coarse_N * 2^k");
+  }
+  require(std::isfinite(d.rho) && d.rho >= 0.0, "rho must be finite and >= 0");
+  require(std::isfinite(d.mu) && d.mu > 0.0, "mu must be finite and > 0");
+  require(std::isfinite(d.dt) && d.dt > 0.0, "dt must be finite and > 0");
+  require(d.M >= 0 && d.M <= (1 << 26), "M out of range");
+  require(d.M == 0 || d.X != nullptr, "X is NULL");
+  for (int l = 0; l < d.M; ++l)
+    for (int c = 0; c < 2; ++c) {
+      const double x = d.X[2 * l + c];
+      require(std::isfinite(x) && x >= 0.0 && x < 1.0, "X must be finite and lie in [0, 1)");
+    }
+  require(d.n_springs >= 0, "n_springs < 0");
+  require(d.n_springs == 0 || (d.ends != nullptr && d.kappa != nullptr), "ends/kappa is NULL");
+  for (int e = 0; e < d.n_springs; ++e) {
+    const int a = d.ends[2 * e], b = d.ends[2 * e + 1];
+    require(a >= 0 && a < d.M && b >= 0 && b < d.M && a != b, "spring end out of range");
+    require(std::isfinite(d.kappa[e]) && d.kappa[e] >= 0.0, "kappa must be finite and >= 0");
+  }
+  require(d.smoother == IBMG_RAS || d.smoother == IBMG_SC, "unknown smoother");
+  require(d.nu1 >= 1 && d.nu1 <= kMaxNu && d.nu2 >= 1 && d.nu2 <= kMaxNu, "nu1/nu2 must lie in [1, 8]");
+  require(d.precision == IBMG_FP64 || d.precision == IBMG_FP32_SMOOTHER, "unknown precision");
+  if (d.smoother == IBMG_SC) require(d.cheb_its >= 1 && d.cheb_its <= 8, "cheb_its must lie in [1, 8]");
+  if (d.smoother == IBMG_RAS) {
+    require(d.box >= 1 && d.overlap >= 0, "box must be >= 1 and overlap >= 0");
+    require(d.box + 2 * d.overlap <= 32, "box + 2 overlap must be <= 32");
+    for (int n : level_sizes(d.N, d.coarse_N)) {
+      if (n == d.coarse_N) continue;
+      int b, o;
+      box_params(n, d.box, d.overlap, &b, &o);
+      require(b >= 1 && n % b == 0, "box size does not tile level " + std::to_string(n));
+    }
+  }
+}
+
+template <typename T>
+struct Level {
+  int N = 0;
+  CompFoot f[2];
+  StokesCoef<double> cd{};
+  StokesCoef<T> ct{};
+  // restricted additive Schwarz
+  BoxGeom g{};
+  int n_unique = 0, n_ib = 0;
+  std::vector<int> uniq;  // unique box ids (IB boxes, then one interior representative)
+  std::vector<int> blk_h;
+  DBuf<int> blk;
+  DBuf<T> inv;
+  // work vectors
+  DBuf<T> w, b, r, t, V, Z, F;
+  DBuf<double> H, scal, part;
+};
+
+template <typename T>
+class Solver final : public SolverBase {
+ public:
+  Solver(const ibmg_desc& d, hipStream_t s) : d_(d) {
+    M_ = d.M;
+    E_ = d.n_springs;
+    X_.assign(d.X, d.X + 2 * (size_t)M_);
+    ends_.assign(d.ends, d.ends + 2 * (size_t)E_);
+    kappa_.assign(d.kappa, d.kappa + E_);
+    nu_ = std::max(d.nu1, d.nu2);
+    sizes_ = level_sizes(d.N, d.coarse_N);
+    L_ = (int)sizes_.size() - 1;
+    build_structure(s);
+    build_numeric(s);
+    alloc_work(s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  ~Solver() override {
+    if (pinned_) (void)hipHostFree(pinned_);
+  }
+
+  int levels() const override { return L_ + 1; }
+  int level_n(int l) const override { return sizes_.at(l); }
+
+  // ---------------------------------------------------------------- set-up
+  void build_structure(hipStream_t s) {
+    // spring adjacency (node -> incident springs in spring order)
+    adj_ptr_.assign(M_ + 1, 0);
+    for (int e = 0; e < E_; ++e) {
+      adj_ptr_[ends_[2 * e] + 1]++;
+      adj_ptr_[ends_[2 * e + 1] + 1]++;
+    }
+    for (int l = 0; l < M_; ++l) adj_ptr_[l + 1] += adj_ptr_[l];
+    adj_nbr_.assign(adj_ptr_[M_], 0);
+    adj_sid_.assign(adj_ptr_[M_], 0);
+    {
+      std::vector<int> fill(adj_ptr_.begin(), adj_ptr_.end() - 1);
+      for (int e = 0; e < E_; ++e) {
+        const int a = ends_[2 * e], b = ends_[2 * e + 1];
+        adj_nbr_[fill[a]] = b;
+        adj_sid_[fill[a]++] = e;
+        adj_nbr_[fill[b]] = a;
+        adj_sid_[fill[b]++] = e;
+      }
+    }
+    d_adj_ptr_.upload(adj_ptr_, s);
+    d_adj_nbr_.upload(adj_nbr_, s);
+    d_ends_.upload(ends_, s);
+    d_X_.upload(X_, s);
+    levels_.resize(L_ + 1);
+    for (int l = L_; l >= 0; --l) {
+      Level<T>& lev = levels_[l];
+      lev.N = sizes_[l];
+      const double h = 1.0 / lev.N;
+      lev.cd = StokesCoef<double>{d_.rho / d_.dt, d_.mu / (h * h), 1.0 / h, d_.dt / (h * h)};
+      lev.ct = StokesCoef<T>{(T)lev.cd.alpha, (T)lev.cd.beta, (T)lev.cd.gi, (T)lev.cd.ibs};
+      for (int c = 0; c < 2; ++c) {
+        CompFoot& f = lev.f[c];
+        if (l == L_) fine_windows(lev.N, c, f);
+        else coarse_windows(levels_[l + 1].f[c], c, levels_[l + 1].N, lev.N, f);
+        f.d_base.upload(f.base, s);
+        f.d_mask.upload(f.mask, s);
+        f.w.alloc((size_t)M_ * 16);
+        if (l == L_)
+          launch_fp_fine(d_X_.p, M_, lev.N, c, f.d_base.p, f.d_mask.p, f.w.p, s);
+        else
+          launch_fp_coarsen(levels_[l + 1].f[c].d_base.p, levels_[l + 1].f[c].w.p, f.d_base.p, M_, c,
+                            levels_[l + 1].N, lev.N, f.w.p, s);
+        if (std::is_same<T, float>::value) {
+          f.wf.alloc((size_t)M_ * 16);
+          launch_cast<double, float>(f.w.p, f.wf.p, (size_t)M_ * 16, s);
+        }
+        spread_lists(lev.N, f);
+        f.d_sp_ptr.upload(f.sp_ptr, s);
+        f.d_sp_ent.upload(f.sp_ent, s);
+        ib_pattern(lev.N, f);
+        f.d_tptr.upload(f.tptr, s);
+        f.d_tcol.upload(f.tcol, s);
+        f.tval.alloc(f.tcol.size());
+      }
+      if (l >= 1 && d_.smoother == IBMG_RAS) classify_boxes(lev);
+    }
+  }
+
+  // Finest windows: t = X N - shift, i0 = floor(t) - 1, slots with |t - k| < 2.
+  void fine_windows(int N, int comp, CompFoot& f) {
+    f.base.assign(2 * (size_t)M_, 0);
+    f.mask.assign(M_, 0);
+    const double sx = comp == 0 ? 0.0 : 0.5, sy = comp == 0 ? 0.5 : 0.0;
+    for (int l = 0; l < M_; ++l) {
+      const double tx = X_[2 * l] * N - sx, ty = X_[2 * l + 1] * N - sy;
+      const int i0 = (int)std::floor(tx) - 1, j0 = (int)std::floor(ty) - 1;
+      int mk = 0;
+      for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a)
+          if (std::fabs(tx - (i0 + a)) < 2.0 && std::fabs(ty - (j0 + b)) < 2.0) mk |= 1 << (b * 4 + a);
+      f.base[2 * l] = wrapn(i0, N);
+      f.base[2 * l + 1] = wrapn(j0, N);
+      f.mask[l] = mk;
+    }
+  }
+
+  // Coarse windows: base = fine base / 2; a coarse slot is structural when a
+  // structural fine slot is interpolated from it by P_u.
+  void coarse_windows(const CompFoot& ff, int comp, int Nf, int Nc, CompFoot& f) {
+    (void)Nf;
+    f.base.assign(2 * (size_t)M_, 0);
+    f.mask.assign(M_, 0);
+    for (int l = 0; l < M_; ++l) {
+      const int I0 = ff.base[2 * l], J0 = ff.base[2 * l + 1];
+      const int ci0 = I0 >> 1, cj0 = J0 >> 1;
+      int mk = 0;
+      for (int s = 0; s < 16; ++s) {
+        if (!((ff.mask[l] >> s) & 1)) continue;
+        const int I = I0 + (s & 3), J = J0 + (s >> 2);
+        if (comp == 0) {
+          const int cj = (J >> 1) - cj0;
+          if ((I & 1) == 0) mk |= 1 << (cj * 4 + (I >> 1) - ci0);
+          else mk |= (1 << (cj * 4 + ((I - 1) >> 1) - ci0)) | (1 << (cj * 4 + ((I + 1) >> 1) - ci0));
+        } else {
+          const int ci = (I >> 1) - ci0;
+          if ((J & 1) == 0) mk |= 1 << (((J >> 1) - cj0) * 4 + ci);
+          else mk |= (1 << ((((J - 1) >> 1) - cj0) * 4 + ci)) | (1 << ((((J + 1) >> 1) - cj0) * 4 + ci));
+        }
+      }
+      f.base[2 * l] = wrapn(ci0, Nc);
+      f.base[2 * l + 1] = wrapn(cj0, Nc);
+      f.mask[l] = mk;
+    }
+  }
+
+  static int face_of(const CompFoot& f, int l, int s, int N) {
+    int i = f.base[2 * l] + (s & 3), j = f.base[2 * l + 1] + (s >> 2);
+    if (i >= N) i -= N;
+    if (j >= N) j -= N;
+    return j * N + i;
+  }
+
+  // faces -> (point, slot) entries, entries of a face in increasing (l, s)
+  void spread_lists(int N, CompFoot& f) {
+    const size_t nf = (size_t)N * N;
+    f.sp_ptr.assign(nf + 1, 0);
+    for (int l = 0; l < M_; ++l)
+      for (int s = 0; s < 16; ++s)
+        if ((f.mask[l] >> s) & 1) f.sp_ptr[face_of(f, l, s, N) + 1]++;
+    for (size_t r = 0; r < nf; ++r) f.sp_ptr[r + 1] += f.sp_ptr[r];
+    f.sp_ent.assign(f.sp_ptr[nf], 0);
+    std::vector<int> fill(f.sp_ptr.begin(), f.sp_ptr.end() - 1);
+    for (int l = 0; l < M_; ++l)
+      for (int s = 0; s < 16; ++s)
+        if ((f.mask[l] >> s) & 1) f.sp_ent[fill[face_of(f, l, s, N)]++] = l * 16 + s;
+  }
+
+  // Pattern of dt/h^2 J^T K' J: row r couples to every face of every point
+  // that shares a spring (or is itself) with a point whose window holds r.
+  void ib_pattern(int N, CompFoot& f) {
+    const size_t nf = (size_t)N * N;
+    f.tptr.assign(nf + 1, 0);
+    f.tcol.clear();
+    std::vector<int> stamp(nf, -1);
+    std::vector<int> cols;
+    auto add_point = [&](int q, int r) {
+      for (int s = 0; s < 16; ++s) {
+        if (!((f.mask[q] >> s) & 1)) continue;
+        const int c = face_of(f, q, s, N);
+        if (stamp[c] != r) {
+          stamp[c] = r;
+          cols.push_back(c);
+        }
+      }
+    };
+    for (size_t r = 0; r < nf; ++r) {
+      cols.clear();
+      for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
+        const int l = f.sp_ent[e] >> 4;
+        if (adj_ptr_[l + 1] == adj_ptr_[l]) continue;
+        add_point(l, (int)r);
+        for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a], (int)r);
+      }
+      std::sort(cols.begin(), cols.end());
+      f.tcol.insert(f.tcol.end(), cols.begin(), cols.end());
+      f.tptr[r + 1] = (int)f.tcol.size();
+    }
+  }
+
+  // A box needs its own inverse when one of its faces carries an IB row;
+  // every other box has the same (translation-invariant) matrix.
+  void classify_boxes(Level<T>& lev) {
+    int b, o;
+    box_params(lev.N, d_.box, d_.overlap, &b, &o);
+    const int m = b + 2 * o, N = lev.N;
+    lev.g = BoxGeom{N, b, o, m, N / b, 2 * m * (m + 1) + m * m, 3 * b * b};
+    const int nbox = lev.g.npd * lev.g.npd;
+    lev.uniq.clear();
+    lev.blk_h.assign(nbox, -1);
+    int interior = -1;
+    for (int p = 0; p < nbox; ++p) {
+      const int x0 = (p % lev.g.npd) * b - o, y0 = (p / lev.g.npd) * b - o;
+      bool ib = false;
+      for (int jj = 0; jj <= m && !ib; ++jj)
+        for (int ii = 0; ii <= m && !ib; ++ii) {
+          const int r = wrapn(y0 + jj, N) * N + wrapn(x0 + ii, N);
+          if (jj < m && lev.f[0].tptr[r + 1] > lev.f[0].tptr[r]) ib = true;   // x-face (ii, jj)
+          if (ii < m && lev.f[1].tptr[r + 1] > lev.f[1].tptr[r]) ib = true;   // y-face (ii, jj)
+        }
+      if (ib) {
+        lev.blk_h[p] = (int)lev.uniq.size();
+        lev.uniq.push_back(p);
+      } else if (interior < 0) {
+        interior = p;
+      }
+    }
+    lev.n_ib = (int)lev.uniq.size();
+    if (interior >= 0) {
+      for (int p = 0; p < nbox; ++p)
+        if (lev.blk_h[p] < 0) lev.blk_h[p] = lev.n_ib;
+      lev.uniq.push_back(interior);
+    }
+    lev.n_unique = (int)lev.uniq.size();
+  }
+
+  void build_numeric(hipStream_t s) {
+    // spring stiffness per incidence
+    std::vector<double> ak(adj_nbr_.size());
+    for (size_t a = 0; a < ak.size(); ++a) ak[a] = kappa_[adj_sid_[a]];
+    d_adj_k_.upload(ak, s);
+    if (std::is_same<T, float>::value) {
+      std::vector<float> akf(ak.begin(), ak.end());
+      d_adj_kf_.upload(akf, s);
+    }
+    for (int l = L_; l >= 0; --l) {
+      Level<T>& lev = levels_[l];
+      for (int c = 0; c < 2; ++c) {
+        CompFoot& f = lev.f[c];
+        if (!f.tcol.empty())
+          launch_t_values(fview<double>(f), f.d_mask.p, sview<double>(), lev.N, lev.cd.ibs, f.d_tptr.p,
+                          f.d_tcol.p, f.tval.p, s);
+      }
+    }
+    build_coarse(s);
+    if (d_.smoother == IBMG_RAS)
+      for (int l = 1; l <= L_; ++l) build_boxes(levels_[l], s);
+  }
+
+  void build_coarse(hipStream_t s) {
+    Level<T>& lev = levels_[0];
+    const int N = lev.N;
+    const int nb = d_.rho == 0.0 ? 3 : 1;
+    n0_ = 3 * N * N;
+    const int nn = n0_ + nb;
+    DBuf<double> aug((size_t)nn * 2 * nn);
+    launch_fill<double>(aug.p, 0.0, aug.n, s);
+    launch_coarse_assemble(N, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p, lev.f[0].tval.p,
+                           lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p, nb, aug.p, s);
+    launch_coarse_invert(aug.p, nn, s);
+    inv0_.alloc((size_t)n0_ * n0_);
+    launch_coarse_extract(aug.p, nn, n0_, inv0_.p, s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void build_boxes(Level<T>& lev, hipStream_t s) {
+    const BoxGeom& g = lev.g;
+    const size_t per = (size_t)g.nloc * g.nloc;
+    lev.blk.upload(lev.blk_h, s);
+    lev.inv.alloc((size_t)lev.n_unique * g.nloc * g.nown);
+    const size_t budget = (size_t)1 << 30;
+    int batch = (int)std::max<size_t>(1, budget / ((per + (size_t)g.nloc * kGjNb) * sizeof(double)));
+    batch = std::min(batch, lev.n_unique);
+    DBuf<double> mats((size_t)batch * per);
+    DBuf<double> colk((size_t)batch * g.nloc * kGjNb);
+    DBuf<int> ids;
+    ids.upload(lev.uniq, s);
+    for (int b0 = 0; b0 < lev.n_unique; b0 += batch) {
+      const int cnt = std::min(batch, lev.n_unique - b0);
+      launch_patch_assemble(ids.p + b0, cnt, g, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p,
+                            lev.f[0].tval.p, lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p,
+                            mats.p, s);
+      launch_gj_invert(mats.p, g.nloc, cnt, colk.p, s);
+      launch_extract_owned<T>(mats.p, cnt, g, lev.inv.p + (size_t)b0 * g.nloc * g.nown, s);
+    }
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void alloc_work(hipStream_t s) {
+    (void)s;
+    for (int l = 0; l <= L_; ++l) {
+      Level<T>& lev = levels_[l];
+      const size_t n = 3 * (size_t)lev.N * lev.N;
+      lev.w.alloc(n);
+      lev.b.alloc(n);
+      lev.r.alloc(n);
+      lev.t.alloc(n);
+      if (l >= 1) {
+        lev.V.alloc((size_t)(nu_ + 1) * n);
+        lev.Z.alloc((size_t)nu_ * n);
+      }
+      lev.F.alloc(2 * (size_t)std::max(M_, 1));
+      lev.H.alloc((size_t)(kMaxNu + 1) * kMaxNu);
+      lev.scal.alloc(64);
+      lev.part.alloc((size_t)512 * 32);
+    }
+    Fd_.alloc(2 * (size_t)std::max(M_, 1));
+    Uw_.alloc(2 * (size_t)std::max(M_, 1));
+    Ul_.alloc(2 * (size_t)std::max(M_, 1));
+    IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
+  }
+
+  // --------------------------------------------------------------- views
+  template <typename U>
+  FootView<U> fview(CompFoot& f) {
+    if constexpr (std::is_same<U, double>::value)
+      return FootView<double>{f.d_base.p, f.w.p, f.d_sp_ptr.p, f.d_sp_ent.p};
+    else
+      return FootView<float>{f.d_base.p, f.wf.p, f.d_sp_ptr.p, f.d_sp_ent.p};
+  }
+  template <typename U>
+  SpringView<U> sview() {
+    if constexpr (std::is_same<U, double>::value)
+      return SpringView<double>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_k_.p};
+    else
+      return SpringView<float>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_kf_.p};
+  }
+  template <typename U>
+  StokesCoef<U> coef(Level<T>& lev) {
+    if constexpr (std::is_same<U, double>::value) return lev.cd;
+    else return StokesCoef<float>{(float)lev.cd.alpha, (float)lev.cd.beta, (float)lev.cd.gi, (float)lev.cd.ibs};
+  }
+
+  // y = L_IB^l x (b != null: y = b - L_IB^l x)
+  template <typename U>
+  void op(int l, const U* x, U* y, const U* b, bool trans, U* F, hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    const size_t nn = (size_t)lev.N * lev.N;
+    const U* Fp = nullptr;
+    if (M_ > 0 && E_ > 0) {
+      launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N, F, s);
+      Fp = F;
+    }
+    launch_apply<U>(x, y, b, Fp, fview<U>(lev.f[0]), fview<U>(lev.f[1]), lev.N, M_, coef<U>(lev),
+                    trans, s);
+  }
+
+  // ------------------------------------------------------- V-cycle pieces
+  void basic_smoother(int l, const T* v, T* z, hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.blk.p, s);
+  }
+
+  // w <- w + e, e = nu FGMRES iterations (CGS2) on L e = b - L w from e = 0.
+  void smooth_t(int l, T* w, const T* b, int nu, bool w_zero, hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    const int nblk = dots_blocks(n);
+    const int ldh = kMaxNu + 1;
+    const T* r0;
+    if (w_zero) {
+      launch_fill<T>(w, T(0), n, s);
+      r0 = b;
+    } else {
+      op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
+      r0 = lev.r.p;
+    }
+    double* beta = lev.scal.p;
+    launch_dots<T>(r0, 1, n, r0, n, lev.part.p, nblk, s);
+    launch_dots_finish(lev.part.p, 1, nblk, beta, nullptr, 2, s);
+    T* V = lev.V.p;
+    T* Z = lev.Z.p;
+    launch_scale<T>(r0, V, beta, n, s);
+    for (int k = 0; k < nu; ++k) {
+      T* vk = V + (size_t)k * n;
+      T* zk = Z + (size_t)k * n;
+      T* t = V + (size_t)(k + 1) * n;
+      basic_smoother(l, vk, zk, s);
+      op<T>(l, zk, t, nullptr, false, lev.F.p, s);
+      double* hcol = lev.H.p + (size_t)k * ldh;
+      orthogonalise<T>(V, k + 1, n, t, hcol, lev.scal.p + kScalTmp, lev.part.p, nblk, s);
+      launch_scale<T>(t, t, hcol + k + 1, n, s);
+    }
+    launch_small_ls(lev.H.p, ldh, nu, beta, lev.scal.p + kScalY, s);
+    launch_combine<T>(w, Z, nu, n, lev.scal.p + kScalY, n, s);
+  }
+
+  // Classical Gram-Schmidt twice against V[0..k): h (first pass + second
+  // pass) into hcol[0..k), ||t|| into hcol[k].
+  template <typename U>
+  void orthogonalise(const U* V, int k, size_t n, U* t, double* hcol, double* tmp, double* part,
+                     int nblk, hipStream_t s) {
+    launch_dots<U>(V, k, n, t, n, part, nblk, s);
+    launch_dots_finish(part, k, nblk, hcol, nullptr, 0, s);
+    launch_update<U>(t, V, k, n, hcol, -1.0, n, s);
+    launch_dots<U>(V, k, n, t, n, part, nblk, s);
+    launch_dots_finish(part, k, nblk, tmp, hcol, 1, s);
+    launch_update<U>(t, V, k, n, tmp, -1.0, n, s);
+    launch_dots<U>(t, 1, n, t, n, part, nblk, s);
+    launch_dots_finish(part, 1, nblk, hcol + k, nullptr, 2, s);
+  }
+
+  // w = MG(0, b) on level l (Alg. 1)
+  void mg(int l, const T* b, T* w, hipStream_t s) {
+    if (l == 0) {
+      launch_coarse_apply<T>(inv0_.p, n0_, b, w, s);
+      return;
+    }
+    Level<T>& lev = levels_[l];
+    Level<T>& crs = levels_[l - 1];
+    smooth_t(l, w, b, d_.nu1, true, s);
+    op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
+    launch_restrict<T>(lev.r.p, crs.b.p, crs.N, s);
+    mg(l - 1, crs.b.p, crs.w.p, s);
+    launch_prolong_add<T>(crs.w.p, w, crs.N, s);
+    smooth_t(l, w, b, d_.nu2, false, s);
+  }
+
+  // ------------------------------------------------------------ ABI calls
+  void apply(int level, const double* w, double* y, bool trans, hipStream_t s) override {
+    op<double>(level, w, y, nullptr, trans, Fd_.p, s);
+  }
+
+  void spread(const double* F, double* f, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    const double h = 1.0 / lev.N;
+    launch_spread(F, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, 1.0 / (h * h), f, s);
+  }
+
+  void interp(const double* u, double* U, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    launch_interp<double>(u, u + (size_t)lev.N * lev.N, fview<double>(lev.f[0]), fview<double>(lev.f[1]),
+                          M_, lev.N, U, s);
+  }
+
+  void restrict_(int level, const double* fine, double* coarse, hipStream_t s) override {
+    launch_restrict<double>(fine, coarse, levels_[level - 1].N, s);
+  }
+
+  void prolong_add(int level, const double* coarse, double* fine, hipStream_t s) override {
+    launch_prolong_add<double>(coarse, fine, levels_[level - 1].N, s);
+  }
+
+  void smoother_apply(int level, const double* r, double* z, hipStream_t s) override {
+    Level<T>& lev = levels_[level];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    if constexpr (std::is_same<T, double>::value) {
+      basic_smoother(level, r, z, s);
+    } else {
+      launch_cast<double, T>(r, lev.r.p, n, s);
+      basic_smoother(level, lev.r.p, lev.t.p, s);
+      launch_cast<T, double>(lev.t.p, z, n, s);
+    }
+  }
+
+  void smooth(int level, double* w, const double* b, int nu, hipStream_t s) override {
+    require(nu >= 1 && nu <= nu_, "nu must lie in [1, max(nu1, nu2)]");
+    Level<T>& lev = levels_[level];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    if constexpr (std::is_same<T, double>::value) {
+      smooth_t(level, w, b, nu, false, s);
+    } else {
+      launch_cast<double, T>(w, lev.w.p, n, s);
+      launch_cast<double, T>(b, lev.b.p, n, s);
+      smooth_t(level, lev.w.p, lev.b.p, nu, false, s);
+      launch_cast<T, double>(lev.w.p, w, n, s);
+    }
+  }
+
+  void coarse_solve(const double* r, double* x, hipStream_t s) override {
+    launch_coarse_apply<double>(inv0_.p, n0_, r, x, s);
+  }
+
+  void vcycle(const double* r, double* z, hipStream_t s) override {
+    Level<T>& top = levels_[L_];
+    const size_t n = 3 * (size_t)top.N * top.N;
+    if constexpr (std::is_same<T, double>::value) {
+      mg(L_, r, z, s);
+    } else {
+      launch_cast<double, T>(r, top.b.p, n, s);
+      mg(L_, top.b.p, top.w.p, s);
+      launch_cast<T, double>(top.w.p, z, n, s);
+    }
+  }
+
+  double read_scalar(const double* dptr, hipStream_t s) {
+    IBMG_HIP(hipMemcpyAsync(pinned_, dptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    return pinned_[0];
+  }
+
+  void ensure_outer(int restart) {
+    const size_t n = 3 * (size_t)d_.N * d_.N;
+    if (restart <= outer_cap_) return;
+    Vo_.alloc((size_t)(restart + 1) * n);
+    Zo_.alloc((size_t)restart * n);
+    Ho_.alloc((size_t)(restart + 1) * restart);
+    cs_.alloc(restart + 1);
+    sn_.alloc(restart + 1);
+    g_.alloc(restart + 2);
+    y_.alloc(restart + 1);
+    osc_.alloc(256);
+    opart_.alloc((size_t)512 * (restart + 1));
+    bp_.alloc(n);
+    rr_.alloc(n);
+    outer_cap_ = restart;
+  }
+
+  void project(double* a, hipStream_t s) {
+    Level<T>& top = levels_[L_];
+    launch_block_sums<double>(a, top.N, opart_.p, 64, s);
+    launch_dots_finish(opart_.p, 3, 64, osc_.p + 8, nullptr, 0, s);
+    launch_subtract_means<double>(a, top.N, osc_.p + 8, d_.rho == 0.0 ? 1 : 0, s);
+  }
+
+  double norm(const double* a, size_t n, hipStream_t s) {
+    const int nblk = dots_blocks(n);
+    launch_dots<double>(a, 1, n, a, n, opart_.p, nblk, s);
+    launch_dots_finish(opart_.p, 1, nblk, osc_.p + 0, nullptr, 2, s);
+    return read_scalar(osc_.p + 0, s);
+  }
+
+  int fgmres(const double* b, double* x, const ibmg_solve_opts& o, ibmg_solve_info* info,
+             hipStream_t s) override {
+    const auto t0 = std::chrono::steady_clock::now();
+    require(o.restart >= 1 && o.restart <= kMaxRestart, "restart must lie in [1, 64]");
+    require(o.max_it >= 1, "max_it must be >= 1");
+    require(std::isfinite(o.rtol) && o.rtol > 0.0, "rtol must be finite and > 0");
+    ensure_outer(o.restart);
+    const int N = d_.N;
+    const size_t n = 3 * (size_t)N * N;
+    const int nblk = dots_blocks(n);
+    const int ldh = o.restart + 1;
+    int hist_n = 0;
+    auto push_hist = [&](double v) {
+      if (info && info->history && hist_n < info->history_cap) info->history[hist_n] = v;
+      ++hist_n;
+    };
+    // projected right-hand side and the removed null-space part
+    IBMG_HIP(hipMemcpyAsync(bp_.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    project(bp_.p, s);
+    IBMG_HIP(hipMemcpyAsync(pinned_, osc_.p + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    const double nn = (double)N * N;
+    double null2 = pinned_[2] * pinned_[2] / nn;
+    if (d_.rho == 0.0) null2 += (pinned_[0] * pinned_[0] + pinned_[1] * pinned_[1]) / nn;
+    const double bnorm = norm(bp_.p, n, s);
+    if (info) {
+      info->iters = 0;
+      info->restarts = 0;
+      info->rhs_null_norm = std::sqrt(null2);
+      info->vcycles = 0;
+    }
+    if (!std::isfinite(bnorm) || !std::isfinite(null2)) throw Error(IBMG_ERR_NONFINITE, "right-hand side holds NaN/Inf");
+    if (!o.use_x0) launch_fill<double>(x, 0.0, n, s);
+    if (bnorm == 0.0) {
+      launch_fill<double>(x, 0.0, n, s);
+      IBMG_HIP(hipStreamSynchronize(s));
+      if (info) {
+        info->rel_res_est = info->rel_res_true = 0.0;
+        info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      return IBMG_OK;
+    }
+    const double target = o.rtol * bnorm;
+    int its = 0, restarts = 0, vcycles = 0;
+    bool converged = false;
+    double est = bnorm;
+    while (its < o.max_it) {
+      double* V0 = Vo_.p;
+      op<double>(L_, x, V0, bp_.p, false, Fd_.p, s);
+      const double beta = norm(V0, n, s);
+      if (!std::isfinite(beta)) throw Error(IBMG_ERR_NONFINITE, "residual is not finite");
+      est = beta;
+      if (beta <= target) { converged = true; break; }
+      launch_scale<double>(V0, V0, osc_.p + 0, n, s);
+      launch_fill<double>(g_.p, 0.0, (size_t)o.restart + 2, s);
+      IBMG_HIP(hipMemcpyAsync(g_.p, osc_.p + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
+      int k = 0;
+      for (; k < o.restart && its < o.max_it;) {
+        double* vk = Vo_.p + (size_t)k * n;
+        double* zk = Zo_.p + (size_t)k * n;
+        double* t = Vo_.p + (size_t)(k + 1) * n;
+        vcycle(vk, zk, s);
+        ++vcycles;
+        op<double>(L_, zk, t, nullptr, false, Fd_.p, s);
+        double* hcol = Ho_.p + (size_t)k * ldh;
+        orthogonalise<double>(Vo_.p, k + 1, n, t, hcol, osc_.p + 128, opart_.p, nblk, s);
+        launch_scale<double>(t, t, hcol + k + 1, n, s);
+        launch_givens(Ho_.p, ldh, k, cs_.p, sn_.p, g_.p, osc_.p + 1, s);
+        est = read_scalar(osc_.p + 1, s);
+        ++k;
+        ++its;
+        push_hist(est / bnorm);
+        if (!std::isfinite(est)) throw Error(IBMG_ERR_NONFINITE, "iteration produced NaN/Inf");
+        if (est <= target) { converged = true; break; }
+      }
+      launch_backsolve(Ho_.p, ldh, k, g_.p, y_.p, s);
+      launch_combine<double>(x, Zo_.p, k, n, y_.p, n, s);
+      ++restarts;
+      if (converged) break;
+    }
+    project(x, s);
+    op<double>(L_, x, rr_.p, bp_.p, false, Fd_.p, s);
+    const double tr = norm(rr_.p, n, s);
+    if (info) {
+      info->iters = its;
+      info->restarts = restarts;
+      info->rel_res_est = est / bnorm;
+      info->rel_res_true = tr / bnorm;
+      info->vcycles = vcycles;
+      info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!std::isfinite(tr)) throw Error(IBMG_ERR_NONFINITE, "solution is not finite");
+    return converged ? IBMG_OK : IBMG_NOT_CONVERGED;
+  }
+
+  void spring_gradient(const double* w, const double* lam, double* out, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    const size_t nn = (size_t)lev.N * lev.N;
+    const double h = 1.0 / lev.N;
+    launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw_.p, s);
+    launch_interp<double>(lam, lam + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Ul_.p, s);
+    launch_spring_grad(Uw_.p, Ul_.p, d_ends_.p, nullptr, E_, M_, -d_.dt / (h * h), out, s);
+  }
+
+  void set_kappa(const double* kappa, hipStream_t s) override {
+    require(E_ == 0 || kappa != nullptr, "kappa is NULL");
+    for (int e = 0; e < E_; ++e)
+      require(std::isfinite(kappa[e]) && kappa[e] >= 0.0, "kappa must be finite and >= 0");
+    kappa_.assign(kappa, kappa + E_);
+    build_numeric(s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  std::vector<int64_t> stats() const override {
+    std::vector<int64_t> v;
+    v.push_back(L_ + 1);
+    for (int l = 0; l <= L_; ++l) {
+      const Level<T>& lev = levels_[l];
+      v.push_back(lev.N);
+      v.push_back((int64_t)lev.g.npd * lev.g.npd);
+      v.push_back(lev.n_unique);
+      v.push_back(lev.n_ib);
+      v.push_back((int64_t)lev.f[0].tcol.size() + (int64_t)lev.f[1].tcol.size());
+    }
+    return v;
+  }
+
+ private:
+  ibmg_desc d_;
+  int M_ = 0, E_ = 0, nu_ = 2, L_ = 0, n0_ = 0;
+  std::vector<double> X_, kappa_;
+  std::vector<int> ends_, sizes_;
+  std::vector<int> adj_ptr_, adj_nbr_, adj_sid_;
+  DBuf<int> d_adj_ptr_, d_adj_nbr_, d_ends_;
+  DBuf<double> d_adj_k_, d_X_;
+  DBuf<float> d_adj_kf_;
+  std::vector<Level<T>> levels_;
+  DBuf<double> inv0_;
+  DBuf<double> Fd_, Uw_, Ul_;
+  // outer FGMRES
+  int outer_cap_ = 0;
+  DBuf<double> Vo_, Zo_, Ho_, cs_, sn_, g_, y_, osc_, opart_, bp_, rr_;
+  double* pinned_ = nullptr;
+};
+
+SolverBase* make_solver(const ibmg_desc& d, hipStream_t s) {
+  validate_desc(d);
+  require(d.smoother == IBMG_RAS, "the Schur-complement smoother is not built into this library");
+  if (d.precision == IBMG_FP32_SMOOTHER) return new Solver<float>(d, s);
+  return new Solver<double>(d, s);
+}
+
+}  // namespace ibmg

@@ -1,0 +1,43 @@
+// Host orchestration of the Stokes-IB multigrid solver.
+#pragma once
+
+#include "internal.hpp"
+
+namespace ibmg {
+
+struct CompFoot {             // one velocity component on one level
+  std::vector<int> base;      // [M][2] wrapped window base (i0, j0)
+  std::vector<int> mask;      // [M] structural slots
+  std::vector<int> sp_ptr, sp_ent;   // faces -> (point, slot) entries
+  std::vector<int> tptr, tcol;       // Galerkin IB rows (pattern)
+  DBuf<int> d_base, d_mask, d_sp_ptr, d_sp_ent, d_tptr, d_tcol;
+  DBuf<double> w;             // [M][16]
+  DBuf<float> wf;             // FP32 copy for the FP32 smoother
+  DBuf<double> tval;
+};
+
+struct SolverBase {
+  virtual ~SolverBase() = default;
+  std::string last_error;
+  virtual int levels() const = 0;
+  virtual int level_n(int l) const = 0;
+  virtual void apply(int level, const double* w, double* y, bool trans, hipStream_t s) = 0;
+  virtual void spread(const double* F, double* f, hipStream_t s) = 0;
+  virtual void interp(const double* u, double* U, hipStream_t s) = 0;
+  virtual void restrict_(int level, const double* fine, double* coarse, hipStream_t s) = 0;
+  virtual void prolong_add(int level, const double* coarse, double* fine, hipStream_t s) = 0;
+  virtual void smoother_apply(int level, const double* r, double* z, hipStream_t s) = 0;
+  virtual void smooth(int level, double* w, const double* b, int nu, hipStream_t s) = 0;
+  virtual void coarse_solve(const double* r, double* x, hipStream_t s) = 0;
+  virtual void vcycle(const double* r, double* z, hipStream_t s) = 0;
+  virtual int fgmres(const double* b, double* x, const ibmg_solve_opts& o, ibmg_solve_info* info,
+                     hipStream_t s) = 0;
+  virtual void spring_gradient(const double* w, const double* lam, double* out, hipStream_t s) = 0;
+  virtual void set_kappa(const double* kappa, hipStream_t s) = 0;
+  virtual std::vector<int64_t> stats() const = 0;
+};
+
+SolverBase* make_solver(const ibmg_desc& d, hipStream_t s);
+void validate_desc(const ibmg_desc& d);
+
+}  // namespace ibmg

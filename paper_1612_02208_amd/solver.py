@@ -1,0 +1,218 @@
+"""Python binding of libibmg: one ``StokesIB`` object per Stokes-IB system.
+
+Only argument marshalling happens here: torch supplies device memory and the
+current HIP stream, every computation runs in the library's kernels.  Vectors
+are float64 CUDA tensors laid out [u | v | p] (see include/ibmg.h).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_HIP", -5: "ERR_NONFINITE",
+           -6: "ERR_STATE"}
+
+
+class IbmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_vec(t, n, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with {n} elements")
+    return t
+
+
+class StokesIB:
+    """Multigrid-preconditioned solver for one periodic Stokes-IB system.
+
+    ``system`` is any object with the attributes N, coarse_N, rho, mu, dt,
+    X [M,2], springs [E,2], kappa [E], smoother ("ras"|"sc"), box, overlap,
+    nu1, nu2, cheb_its (e.g. ``workloads.Workload``)."""
+
+    def __init__(self, system, precision="fp64"):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("StokesIB needs a HIP device")
+        self.N = int(system.N)
+        self.X = np.ascontiguousarray(system.X, dtype=np.float64)
+        self.springs = np.ascontiguousarray(system.springs, dtype=np.int32)
+        self.kappa = np.ascontiguousarray(system.kappa, dtype=np.float64)
+        self.M = int(self.X.shape[0])
+        self.E = int(self.springs.shape[0])
+        self.rho = float(system.rho)
+        d = _lib.Desc()
+        d.N = self.N
+        d.coarse_N = int(system.coarse_N)
+        d.rho, d.mu, d.dt = float(system.rho), float(system.mu), float(system.dt)
+        d.M = self.M
+        d.X = self.X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.n_springs = self.E
+        d.ends = self.springs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.kappa = self.kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.smoother = {"ras": _lib.RAS, "sc": _lib.SC}[getattr(system, "smoother", "ras")]
+        d.box = int(getattr(system, "box", 8))
+        d.overlap = int(getattr(system, "overlap", 2))
+        d.nu1 = int(getattr(system, "nu1", 2))
+        d.nu2 = int(getattr(system, "nu2", 2))
+        d.cheb_its = int(getattr(system, "cheb_its", 2))
+        d.precision = {"fp64": _lib.FP64, "fp32": _lib.FP32_SMOOTHER}[precision]
+        self.precision = precision
+        self.desc = d
+        h = ctypes.c_void_p()
+        st = self.lib.ibmg_create(ctypes.byref(d), _stream(), ctypes.byref(h))
+        if st != 0:
+            raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
+        self.h = h
+        nl = ctypes.c_int32()
+        self._check(self.lib.ibmg_levels(self.h, ctypes.byref(nl)))
+        self.n_levels = nl.value
+        self.level_sizes = []
+        for l in range(self.n_levels):
+            n = ctypes.c_int32()
+            self._check(self.lib.ibmg_level_n(self.h, l, ctypes.byref(n)))
+            self.level_sizes.append(n.value)
+
+    def _check(self, st, ok=(0,)):
+        if st not in ok:
+            raise IbmgError(st, self.lib.ibmg_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ibmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n(self, level=-1):
+        N = self.level_sizes[level]
+        return 3 * N * N
+
+    def _new(self, n):
+        return torch.empty(n, dtype=torch.float64, device="cuda")
+
+    # ---- operators ---------------------------------------------------------
+    def apply(self, w, level=-1, transpose=False, out=None):
+        level = level % self.n_levels
+        n = self.n(level)
+        _dev_vec(w, n, "w")
+        y = self._new(n) if out is None else _dev_vec(out, n, "out")
+        fn = self.lib.ibmg_apply_A_IB_T if transpose else self.lib.ibmg_apply_A_IB
+        self._check(fn(self.h, level, _ptr(w), _ptr(y), _stream()))
+        return y
+
+    def spread(self, F):
+        F = _dev_vec(F, 2 * self.M, "F") if self.M else F
+        f = self._new(2 * self.N * self.N)
+        self._check(self.lib.ibmg_spread(self.h, _ptr(F) if self.M else None, _ptr(f), _stream()))
+        return f
+
+    def interp(self, u):
+        _dev_vec(u, 2 * self.N * self.N, "u")
+        U = self._new(max(2 * self.M, 1))
+        self._check(self.lib.ibmg_interp(self.h, _ptr(u), _ptr(U), _stream()))
+        return U[:2 * self.M]
+
+    def restrict(self, level, fine):
+        level = level % self.n_levels
+        _dev_vec(fine, self.n(level), "fine")
+        c = self._new(self.n(level - 1))
+        self._check(self.lib.ibmg_restrict(self.h, level, _ptr(fine), _ptr(c), _stream()))
+        return c
+
+    def prolong_add(self, level, coarse, fine):
+        level = level % self.n_levels
+        _dev_vec(coarse, self.n(level - 1), "coarse")
+        _dev_vec(fine, self.n(level), "fine")
+        self._check(self.lib.ibmg_prolong_add(self.h, level, _ptr(coarse), _ptr(fine), _stream()))
+        return fine
+
+    def smoother_apply(self, level, r):
+        level = level % self.n_levels
+        _dev_vec(r, self.n(level), "r")
+        z = self._new(self.n(level))
+        self._check(self.lib.ibmg_smoother_apply(self.h, level, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def smooth(self, level, w, b, nu):
+        level = level % self.n_levels
+        _dev_vec(w, self.n(level), "w")
+        _dev_vec(b, self.n(level), "b")
+        self._check(self.lib.ibmg_smooth(self.h, level, _ptr(w), _ptr(b), int(nu), _stream()))
+        return w
+
+    def coarse_solve(self, r):
+        _dev_vec(r, self.n(0), "r")
+        x = self._new(self.n(0))
+        self._check(self.lib.ibmg_coarse_solve(self.h, _ptr(r), _ptr(x), _stream()))
+        return x
+
+    def vcycle(self, r, out=None):
+        _dev_vec(r, self.n(), "r")
+        z = self._new(self.n()) if out is None else _dev_vec(out, self.n(), "out")
+        self._check(self.lib.ibmg_vcycle(self.h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def solve(self, b, rtol=1e-8, restart=30, max_it=100, x0=None, out=None, history=128):
+        _dev_vec(b, self.n(), "b")
+        if x0 is not None:
+            x = x0.clone() if out is None else out.copy_(x0)
+        else:
+            x = self._new(self.n()) if out is None else out
+        o = _lib.SolveOpts(float(rtol), int(restart), int(max_it), 1 if x0 is not None else 0)
+        hist = (ctypes.c_double * history)()
+        info = _lib.SolveInfo()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = history
+        st = self._check(self.lib.ibmg_fgmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o),
+                                                    ctypes.byref(info), _stream()), ok=(0, 1))
+        k = min(info.iters, history)
+        return x, dict(status=_STATUS[st], converged=st == 0, iters=info.iters,
+                       restarts=info.restarts, rel_res_est=info.rel_res_est,
+                       rel_res_true=info.rel_res_true, rhs_null_norm=info.rhs_null_norm,
+                       solve_ms=info.solve_ms, vcycles=info.vcycles, history=list(hist[:k]))
+
+    def spring_gradient(self, w, lam):
+        _dev_vec(w, self.n(), "w")
+        _dev_vec(lam, self.n(), "lam")
+        g = self._new(max(self.E, 1))
+        self._check(self.lib.ibmg_spring_gradient(self.h, _ptr(w), _ptr(lam), _ptr(g), _stream()))
+        return g[:self.E]
+
+    def set_kappa(self, kappa):
+        k = np.ascontiguousarray(kappa, dtype=np.float64)
+        if k.shape != (self.E,):
+            raise ValueError("kappa has the wrong length")
+        self.kappa = k
+        self._check(self.lib.ibmg_set_kappa(self.h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            _stream()))
+
+    def stats(self):
+        buf = (ctypes.c_int64 * 256)()
+        wr = ctypes.c_int32()
+        self._check(self.lib.ibmg_stats(self.h, buf, 256, ctypes.byref(wr)))
+        v = list(buf[:wr.value])
+        out = {"levels": []}
+        for l in range(v[0]):
+            N, boxes, uniq, ib, tnnz = v[1 + 5 * l:6 + 5 * l]
+            out["levels"].append(dict(N=N, boxes=boxes, unique_boxes=uniq, ib_boxes=ib, ib_nnz=tnnz))
+        return out

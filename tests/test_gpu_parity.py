@@ -1,0 +1,188 @@
+"""GPU parity: every C-ABI call of libibmg against the plain FP64 oracle on the
+same seeded inputs (FP64 library path).
+
+Tolerances (relative, 2-norm) follow from the arithmetic:
+* operators, transfers, spreading/interpolation: sums of <= ~60 terms of
+  rounded products, so <= 1e-12 (a few hundred ulps) is a safe bound;
+* solves (box inverses, the coarsest inverse, V-cycle, FGMRES): the library
+  multiplies by explicit inverses while the oracle uses LU solves, so the
+  difference scales with the conditioning of the local matrices; the bound is
+  1e-10 relative, the figure the method is specified to.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import hierarchy, krylov, transfer
+from oracle import ib as oib
+from oracle.solver import Problem, spring_gradient
+
+pytestmark = pytest.mark.gpu
+
+OPS_TOL = 1e-12
+SOLVE_TOL = 1e-10
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _cases():
+    # plain 32x32 Stokes membrane (3 levels)
+    c1 = W.plain_32()
+    # annulus at nonzero Reynolds number, ragged point count (4 rings x 150)
+    X, S = W.annulus(4, 150, 0.2, 0.25)
+    c2 = W.Workload("annulus_64", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4))
+    # random points with random springs, odd sizes everywhere (coarse 6, N = 48)
+    Xr = W.random_points(37, 21)
+    rng = np.random.default_rng(5)
+    Sr = np.stack([np.arange(37), (np.arange(37) + 1 + rng.integers(0, 5, 37)) % 37], 1).astype(np.int32)
+    Sr = Sr[Sr[:, 0] != Sr[:, 1]]
+    c3 = W.Workload("random_48", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, rng.uniform(10, 1e3, len(Sr)), box=6,
+                    overlap=1)
+    return [c1, c2, c3]
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)), ids=[c.name for c in CASES])
+def pair(request):
+    from paper_1612_02208_amd import StokesIB
+    wl = CASES[request.param]
+    print(f"[case] {wl.name} N={wl.N} M={wl.M}", flush=True)
+    P = Problem(wl)
+    G = StokesIB(wl)
+    yield wl, P, G
+    G.close()
+
+
+def test_apply_every_level(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(1)
+    for l, lev in enumerate(P.levels):
+        w = rng.uniform(-1, 1, lev.n)
+        y = host(G.apply(dev(w), level=l))
+        assert rel(y, lev.L @ w) < OPS_TOL, (l, rel(y, lev.L @ w))
+        yt = host(G.apply(dev(w), level=l, transpose=True))
+        assert rel(yt, lev.L.T @ w) < OPS_TOL
+        assert rel(yt, y) < OPS_TOL   # L_IB is symmetric (G = -D^T, S = J^*)
+
+
+def test_spread_interp(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(2)
+    N = wl.N
+    F = rng.uniform(-1, 1, (wl.M, 2))
+    f = host(G.spread(dev(F.ravel())))
+    ref = np.concatenate([oib.spread_matrix(wl.X, N, c) @ F[:, c] for c in (0, 1)])
+    assert rel(f, ref) < OPS_TOL
+    u = rng.uniform(-1, 1, 2 * N * N)
+    U = host(G.interp(dev(u))).reshape(-1, 2)
+    for c in (0, 1):
+        assert rel(U[:, c], oib.interp_matrix(wl.X, N, c) @ u[c * N * N:(c + 1) * N * N]) < OPS_TOL
+
+
+def test_transfers(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(3)
+    for l in range(1, len(P.levels)):
+        Nc = P.levels[l - 1].N
+        f = rng.uniform(-1, 1, P.levels[l].n)
+        c = host(G.restrict(l, dev(f)))
+        assert rel(c, transfer.restriction(Nc) @ f) < OPS_TOL
+        e = rng.uniform(-1, 1, P.levels[l - 1].n)
+        base = rng.uniform(-1, 1, P.levels[l].n)
+        out = host(G.prolong_add(l, dev(e), dev(base)))
+        assert rel(out, base + transfer.prolongation(Nc) @ e) < OPS_TOL
+
+
+def test_coarse_solve(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(4)
+    r = rng.uniform(-1, 1, P.levels[0].n)
+    x = host(G.coarse_solve(dev(r)))
+    assert rel(x, P.mg.coarse(r)) < SOLVE_TOL
+
+
+def test_smoother_apply(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(6)
+    for l in range(1, len(P.levels)):
+        r = rng.uniform(-1, 1, P.levels[l].n)
+        z = host(G.smoother_apply(l, dev(r)))
+        assert rel(z, P.mg.smoothers[l](r)) < SOLVE_TOL, (l, rel(z, P.mg.smoothers[l](r)))
+
+
+def test_smooth(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(7)
+    for l in range(1, len(P.levels)):
+        lev = P.levels[l]
+        w = rng.uniform(-1, 1, lev.n)
+        b = rng.uniform(-1, 1, lev.n)
+        out = host(G.smooth(l, dev(w), dev(b), 2))
+        ref = krylov.fgmres_smooth(lambda x: lev.L @ x, P.mg.smoothers[l], w, b, 2)
+        assert rel(out, ref) < SOLVE_TOL
+
+
+def test_vcycle(pair):
+    wl, P, G = pair
+    r = P.project(W.rhs(wl.N, 11))
+    z = host(G.vcycle(dev(r)))
+    assert rel(z, P.mg.vcycle(r)) < SOLVE_TOL
+
+
+def test_fgmres_fixed_iterations(pair):
+    wl, P, G = pair
+    b = W.rhs(wl.N, 0)
+    bp = P.project(b)
+    k = 4
+    x, info = G.solve(dev(b), rtol=1e-300, restart=30, max_it=k)
+    assert info["iters"] == k and info["status"] == "NOT_CONVERGED"
+    xo, io = krylov.fgmres(P.apply, P.mg, bp, restart=30, rtol=1e-300, max_it=k)
+    xo = P.project(xo)
+    assert rel(host(x), xo) < SOLVE_TOL
+    np.testing.assert_allclose(info["history"], np.array(io["history"][:k]) / np.linalg.norm(bp),
+                               rtol=1e-8)
+
+
+def test_solve_to_tolerance(pair):
+    wl, P, G = pair
+    b = W.rhs(wl.N, 0)
+    x, info = G.solve(dev(b), rtol=1e-8)
+    assert info["converged"]
+    xh = host(x)
+    bp = P.project(b)
+    true = np.linalg.norm(bp - P.L @ xh) / np.linalg.norm(bp)
+    assert true <= 1.2e-8, true
+    assert abs(info["rel_res_true"] - true) < 1e-10
+    assert abs(info["rhs_null_norm"] - np.linalg.norm(b - bp)) < 1e-9 * np.linalg.norm(b)
+    xo, io = P.solve(b, rtol=1e-8)
+    assert abs(info["iters"] - io["iters"]) <= 1
+    # both to 1e-12: the solutions agree to the conditioning of the system
+    x12, i12 = G.solve(dev(b), rtol=1e-12, max_it=200)
+    xo12, _ = P.solve(b, rtol=1e-12, max_it=200)
+    assert rel(host(x12), xo12) < SOLVE_TOL
+
+
+def test_spring_gradient(pair):
+    wl, P, G = pair
+    rng = np.random.default_rng(8)
+    n = P.fine.n
+    w = rng.uniform(-1, 1, n)
+    lam = rng.uniform(-1, 1, n)
+    g = host(G.spring_gradient(dev(w), dev(lam)))
+    assert rel(g, spring_gradient(wl, w, lam)) < OPS_TOL
