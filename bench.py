@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--cpu-baseline", default="sample", choices=["sample", "off"])
     p.add_argument("--cpu-boxes", type=int, default=1024)
     p.add_argument("--roofline-reps", type=int, default=50)
+    p.add_argument("--box", type=int, default=8)
+    p.add_argument("--overlap", type=int, default=2)
     return p.parse_args()
 
 
@@ -100,6 +102,7 @@ def main():
 
     wl = W.annulus_512(N=a.N)
     wl.N = a.N
+    wl.box, wl.overlap = a.box, a.overlap
     b_h = W.rhs(wl.N, 0)
     torch.cuda.init()
     dev = torch.device("cuda:0")
@@ -185,8 +188,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"annulus_{wl.N}: {wl.N}x{wl.N} periodic, rho=1 mu=1e-2 dt=5e-4, "
                                f"4x2048-point annulus r=0.2..0.25, kappa=1e4, 7-level V-cycle, "
-                               f"RAS 8x8/2, nu=2+2, FGMRES(30) to 1e-8",
-                   "N": wl.N, "points": wl.M, "springs": int(len(wl.springs))},
+                               f"RAS {wl.box}x{wl.box}/{wl.overlap}, nu=2+2, FGMRES(30) to 1e-8",
+                   "N": wl.N, "points": wl.M, "springs": int(len(wl.springs)),
+                   "box": wl.box, "overlap": wl.overlap},
         "solve_ms_fp64": float(np.median(s64)),
         "solve_ms_fp32": float(np.median(s32)),
         "fp32_speedup": float(np.median(s64) / np.median(s32)),

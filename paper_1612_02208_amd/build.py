@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libibmg.so")
 ARCH = os.environ.get("IBMG_ARCH", "gfx950")
 
-SOURCES = ["grid_kernels.hip", "ib_kernels.hip", "dense_kernels.hip", "sc_kernels.hip",
-           "solver.cpp", "api.cpp"]
+SOURCES = ["grid_kernels.hip", "ib_kernels.hip", "dense_kernels.hip", "krylov_kernels.hip",
+           "sc_kernels.hip", "solver.cpp", "api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -93,95 +93,140 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
 }
 
 // ---------------------------------------------------------------------------
-// Batched in-place Gauss-Jordan inversion without pivoting, blocked by NB
+// Batched in-place Gauss-Jordan inversion without pivoting, blocked by 64
 // columns.  The box matrices are ordered velocities first: the velocity block
 // R_k A_IB R_k^T is symmetric positive definite (a principal submatrix of
 // rho/dt - mu Lap + IB with the periodic constants cut off), and the pressure
 // pivots come from the negative definite Schur complement -G^T A^{-1} G, so
-// no pivot vanishes.  One work-group per matrix.
-// Step K: D = A_KK -> D^{-1};  A_Kj <- D^{-1} A_Kj;  A_ij <- A_ij - A_iK A_Kj;
-//         A_iK <- -A_iK D^{-1};  A_KK <- D^{-1}.
+// no pivot vanishes.
+// Step K (columns kb .. kb+w):
+//   panel  (one work-group per matrix): D = A_KK -> D^{-1} in LDS, C = A_:K
+//          saved, A_Kj <- D^{-1} A_Kj (j outside K), A_KK <- D^{-1};
+//   update (64 x 64 tiles of every matrix): A_ij <- [j outside K] A_ij
+//          - sum_k C_ik A_Kj  for i outside K (with A_KK = D^{-1} this also
+//          gives A_iK <- -A_iK D^{-1}).
 // ---------------------------------------------------------------------------
-constexpr int GJ_NB = 16;
+constexpr int GJ_NB = 64;
 
-__global__ void __launch_bounds__(512) k_gj_invert(double* __restrict__ mats, int n,
-                                                   double* __restrict__ colk_all) {
+__global__ void __launch_bounds__(256) k_gj_panel(double* __restrict__ mats, int n, int kb,
+                                                  double* __restrict__ colk_all) {
   __shared__ double Dm[GJ_NB][GJ_NB + 1];
   double* A = mats + (size_t)blockIdx.x * n * n;
   double* colK = colk_all + (size_t)blockIdx.x * n * GJ_NB;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int kb = 0; kb < n; kb += GJ_NB) {
-    const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
-    // diagonal block into LDS and unblocked in-place inversion
-    for (int t = tid; t < w * w; t += nt) Dm[t / w][t % w] = A[(size_t)(kb + t / w) * n + kb + t % w];
-    __syncthreads();
-    for (int k = 0; k < w; ++k) {
-      const double piv = Dm[k][k];
-      const double ip = 1.0 / piv;
-      // other rows / columns use the old row k and column k
-      double rk = 0.0, ck = 0.0;
-      const int t = tid;
-      const bool act = t < w * w;
-      const int ti = act ? t / w : 0, tj = act ? t % w : 0;
-      if (act) {
-        rk = Dm[k][tj];
-        ck = Dm[ti][k];
-      }
-      __syncthreads();
-      if (act) {
-        double val = Dm[ti][tj];
-        if (ti == k && tj == k) val = ip;
-        else if (ti == k) val = rk * ip;
-        else if (tj == k) val = -ck * ip;
-        else val = val - ck * rk * ip;
-        Dm[ti][tj] = val;
-      }
-      __syncthreads();
-    }
-    // save the old block column A_iK
-    for (size_t t = tid; t < (size_t)n * w; t += nt) {
-      const int i = (int)(t / w), k = (int)(t % w);
-      colK[(size_t)i * GJ_NB + k] = A[(size_t)i * n + kb + k];
+  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
+  for (int t = tid; t < GJ_NB * GJ_NB; t += nt) {
+    const int a = t / GJ_NB, b = t % GJ_NB;
+    Dm[a][b] = (a < w && b < w) ? A[(size_t)(kb + a) * n + kb + b] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < w; ++k) {
+    const double ip = 1.0 / Dm[k][k];
+    double rk[16], ck[16];
+    int q = 0;
+    for (int t = tid; t < w * w; t += nt, ++q) {
+      rk[q] = Dm[k][t % w];
+      ck[q] = Dm[t / w][k];
     }
     __syncthreads();
-    // row panel A_Kj <- D^{-1} A_Kj (j outside K), A_KK <- D^{-1}
-    for (int j = tid; j < n; j += nt) {
-      if (j >= kb && j < kb + w) {
-        for (int k = 0; k < w; ++k) A[(size_t)(kb + k) * n + j] = Dm[k][j - kb];
-      } else {
-        double col[GJ_NB];
-        for (int k = 0; k < w; ++k) col[k] = A[(size_t)(kb + k) * n + j];
-        for (int k = 0; k < w; ++k) {
-          double a = 0.0;
-          for (int q = 0; q < w; ++q) a += Dm[k][q] * col[q];
-          A[(size_t)(kb + k) * n + j] = a;
-        }
-      }
+    q = 0;
+    for (int t = tid; t < w * w; t += nt, ++q) {
+      const int ti = t / w, tj = t % w;
+      double val = Dm[ti][tj];
+      if (ti == k && tj == k) val = ip;
+      else if (ti == k) val = rk[q] * ip;
+      else if (tj == k) val = -ck[q] * ip;
+      else val = val - ck[q] * rk[q] * ip;
+      Dm[ti][tj] = val;
     }
     __syncthreads();
-    // trailing update of every row outside K
-    for (size_t t = tid; t < (size_t)n * n; t += nt) {
-      const int i = (int)(t / n), j = (int)(t % n);
-      if (i >= kb && i < kb + w) continue;
-      const double* ck = colK + (size_t)i * GJ_NB;
-      double a;
-      if (j >= kb && j < kb + w) {
-        a = 0.0;
-        for (int k = 0; k < w; ++k) a -= ck[k] * Dm[k][j - kb];
-      } else {
-        a = A[t];
-        for (int k = 0; k < w; ++k) a -= ck[k] * A[(size_t)(kb + k) * n + j];
+  }
+  for (size_t t = tid; t < (size_t)n * GJ_NB; t += nt) {
+    const int i = (int)(t / GJ_NB), k = (int)(t % GJ_NB);
+    colK[t] = k < w ? A[(size_t)i * n + kb + k] : 0.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += nt) {
+    if (j >= kb && j < kb + w) {
+      for (int k = 0; k < w; ++k) A[(size_t)(kb + k) * n + j] = Dm[k][j - kb];
+    } else {
+      double col[GJ_NB];
+#pragma unroll
+      for (int k = 0; k < GJ_NB; ++k) col[k] = k < w ? A[(size_t)(kb + k) * n + j] : 0.0;
+      for (int k = 0; k < w; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < GJ_NB; ++q) a += Dm[k][q] * col[q];
+        A[(size_t)(kb + k) * n + j] = a;
       }
-      A[t] = a;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, int n, int kb,
+                                                   const double* __restrict__ colk_all) {
+  __shared__ double Cs[64][33];
+  __shared__ double Ps[32][65];
+  double* A = mats + (size_t)blockIdx.z * n * n;
+  const double* colK = colk_all + (size_t)blockIdx.z * n * GJ_NB;
+  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
+  const int I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k0 = 0; k0 < w; k0 += 32) {
+    for (int t = tid; t < 64 * 32; t += 256) {
+      const int a = t / 32, k = t % 32;
+      const int i = I0 + a;
+      Cs[a][k] = (i < n && k0 + k < w) ? colK[(size_t)i * GJ_NB + k0 + k] : 0.0;
+    }
+    for (int t = tid; t < 32 * 64; t += 256) {
+      const int k = t / 64, b = t % 64;
+      const int j = J0 + b;
+      Ps[k][b] = (j < n && k0 + k < w) ? A[(size_t)(kb + k0 + k) * n + j] : 0.0;
     }
     __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < 32; ++k) {
+      double c[4], p[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) c[a] = Cs[ty + 16 * a][k];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) p[b] = Ps[k][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += c[a] * p[b];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = I0 + ty + 16 * a;
+    if (i >= n || (i >= kb && i < kb + w)) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = J0 + tx + 16 * b;
+      if (j >= n) continue;
+      const size_t o = (size_t)i * n + j;
+      const double old = (j >= kb && j < kb + w) ? 0.0 : A[o];
+      A[o] = old - acc[a][b];
+    }
   }
 }
 
 void launch_gj_invert(double* mats, int n, int count, double* colk, hipStream_t s) {
   if (!count) return;
-  hipLaunchKernelGGL(k_gj_invert, dim3(count), dim3(512), 0, s, mats, n, colk);
-  IBMG_LAUNCH_CHECK();
+  const int tiles = (n + 63) / 64;
+  for (int kb = 0; kb < n; kb += GJ_NB) {
+    hipLaunchKernelGGL(k_gj_panel, dim3(count), dim3(256), 0, s, mats, n, kb, colk);
+    IBMG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, count), dim3(256), 0, s, mats, n, kb, colk);
+    IBMG_LAUNCH_CHECK();
+  }
 }
 
 __device__ __forceinline__ int own_local(int r, const BoxGeom& g) {
@@ -194,25 +239,64 @@ __device__ __forceinline__ int own_local(int r, const BoxGeom& g) {
   return 2 * m * (m + 1) + oj * m + oi;
 }
 
-// out[(blk * nloc + j) * nown + r] = A^{-1}[own(r)][j]  (owned rows, column-major)
+// global index of local unknown k of box pid (periodic wrap)
+__device__ __forceinline__ size_t box_glob(const BoxGeom& g, int pid, int k) {
+  const int N = g.N, m = g.m, nu = m * (m + 1);
+  const int x0 = (pid % g.npd) * g.b - g.o, y0 = (pid / g.npd) * g.b - g.o;
+  const size_t nn = (size_t)N * N;
+  int ii, jj;
+  size_t off;
+  if (k < nu) {
+    ii = k % (m + 1);
+    jj = k / (m + 1);
+    off = 0;
+  } else if (k < 2 * nu) {
+    const int q = k - nu;
+    ii = q % m;
+    jj = q / m;
+    off = nn;
+  } else {
+    const int q = k - 2 * nu;
+    ii = q % m;
+    jj = q / m;
+    off = 2 * nn;
+  }
+  return off + (size_t)pmod(y0 + jj, N) * N + pmod(x0 + ii, N);
+}
+
+// global index of owned row r of box pid
+__device__ __forceinline__ size_t own_glob(const BoxGeom& g, int pid, int r) {
+  const int bb = g.b * g.b;
+  const int comp = r / bb, q = r % bb;
+  const int gi = (pid % g.npd) * g.b + q % g.b, gj = (pid / g.npd) * g.b + q / g.b;
+  return (size_t)comp * g.N * g.N + (size_t)gj * g.N + gi;
+}
+
+// Owned rows of A^{-1}, stored per box as row chunks of 64: element (row, j)
+// at (row / 64) * nloc * 64 + j * 64 + row % 64 (rows beyond nown are 0), so
+// a chunk's 64 rows of one column are contiguous and a chunk is one
+// contiguous stream of nloc * 64 values.
 template <typename T>
 __global__ void k_extract_owned(const double* __restrict__ mats, int count, BoxGeom g,
                                 T* __restrict__ out) {
-  const size_t per = (size_t)g.nloc * g.nown;
+  const size_t per = (size_t)g.nch * g.nloc * 64;
   const size_t tot = per * count;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
     const size_t blk = t / per;
-    const size_t rem = t % per;
-    const int j = (int)(rem / g.nown), r = (int)(rem % g.nown);
+    size_t rem = t % per;
+    const int c = (int)(rem / ((size_t)g.nloc * 64));
+    rem %= (size_t)g.nloc * 64;
+    const int j = (int)(rem / 64), rr = (int)(rem % 64);
+    const int row = c * 64 + rr;
     const double* A = mats + blk * g.nloc * g.nloc;
-    out[t] = (T)A[(size_t)own_local(r, g) * g.nloc + j];
+    out[t] = row < g.nown ? (T)A[(size_t)own_local(row, g) * g.nloc + j] : (T)0;
   }
 }
 
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s) {
   if (!count) return;
-  size_t tot = (size_t)g.nloc * g.nown * count;
+  size_t tot = (size_t)g.nch * g.nloc * 64 * count;
   int grid = cdiv(tot, 256);
   if (grid > 16384) grid = 16384;
   hipLaunchKernelGGL((k_extract_owned<T>), dim3(grid), dim3(256), 0, s, mats, count, g, out);
@@ -222,64 +306,254 @@ void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipS
 // ---------------------------------------------------------------------------
 // Restricted additive Schwarz (Alg. 2 from a zero guess):
 //   z[G~_k] = (L_k^{-1} R_k r)[G~_k]  for every box k.
-// One work-group per box gathers R_k r into LDS and multiplies by the stored
-// owned rows of L_k^{-1}; the owned sets partition the unknowns, so every z
-// entry is written by exactly one work-group.
+// The owned sets partition the unknowns, so every z entry is written by
+// exactly one work-group and no atomics are needed.
+//
+// Boxes with their own inverse (IB boxes): work-group = (box, 64-row chunk).
+// R_k r is gathered into LDS; each wave streams a quarter of the chunk's
+// columns with 16-byte loads (a wave reads 1 KB of contiguous inverse per
+// load: VEC rows per lane, VEC columns side by side), lane groups are summed
+// by shuffles and the four quarters in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_ras_apply(const T* __restrict__ r, T* __restrict__ z,
-                                                   BoxGeom g, const T* __restrict__ inv,
-                                                   const int* __restrict__ blk_of_patch) {
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
+                                                const T* __restrict__ inv, const int* __restrict__ boxes) {
+  using V = typename Vec16<T>::type;
+  constexpr int VEC = Vec16<T>::n;
+  constexpr int LPC = 64 / VEC;  // lanes per column
   extern __shared__ char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
-  const int pid = blockIdx.x;
-  const int N = g.N, m = g.m;
-  const int pi = pid % g.npd, pj = pid / g.npd;
-  const int x0 = pi * g.b - g.o, y0 = pj * g.b - g.o;
-  const size_t nn = (size_t)N * N;
-  const int nu = m * (m + 1);
-  for (int k = threadIdx.x; k < g.nloc; k += blockDim.x) {
-    size_t gi;
-    if (k < nu) {
-      const int ii = k % (m + 1), jj = k / (m + 1);
-      gi = (size_t)pmod(y0 + jj, N) * N + pmod(x0 + ii, N);
-    } else if (k < 2 * nu) {
-      const int q = k - nu, ii = q % m, jj = q / m;
-      gi = nn + (size_t)pmod(y0 + jj, N) * N + pmod(x0 + ii, N);
-    } else {
-      const int q = k - 2 * nu, ii = q % m, jj = q / m;
-      gi = 2 * nn + (size_t)pmod(y0 + jj, N) * N + pmod(x0 + ii, N);
-    }
-    x[k] = r[gi];
-  }
+  T* part = x + ((g.nloc + 3) & ~3);
+  const int slot = blockIdx.x;
+  const int pid = boxes[slot];
+  for (int k = threadIdx.x; k < g.nloc; k += blockDim.x) x[k] = r[box_glob(g, pid, k)];
   __syncthreads();
-  const T* Mt = inv + (size_t)blk_of_patch[pid] * g.nloc * g.nown;
-  const int bb = g.b * g.b;
-  for (int row = threadIdx.x; row < g.nown; row += blockDim.x) {
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    int j = 0;
-    for (; j + 3 < g.nloc; j += 4) {
-      a0 += Mt[(size_t)j * g.nown + row] * x[j];
-      a1 += Mt[(size_t)(j + 1) * g.nown + row] * x[j + 1];
-      a2 += Mt[(size_t)(j + 2) * g.nown + row] * x[j + 2];
-      a3 += Mt[(size_t)(j + 3) * g.nown + row] * x[j + 3];
-    }
-    for (; j < g.nloc; ++j) a0 += Mt[(size_t)j * g.nown + row] * x[j];
-    const int comp = row / bb, q = row % bb;
-    const int gi = pi * g.b + q % g.b, gj = pj * g.b + q / g.b;
-    z[comp * nn + (size_t)gj * N + gi] = (a0 + a1) + (a2 + a3);
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int cph = lane / LPC;           // column phase 0..VEC-1
+  const int rl = (lane % LPC) * VEC;    // first of this lane's VEC rows
+  const int per = ((g.nloc + 4 * VEC - 1) / (4 * VEC)) * VEC;
+  const int j0 = q * per, j1 = j0 + per < g.nloc ? j0 + per : g.nloc;
+  const T* Mc = inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64 + rl;
+  T acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0;
+  int j = j0 + cph;
+  for (; j + 3 * VEC < j1; j += 4 * VEC) {
+    const V m0 = *reinterpret_cast<const V*>(Mc + (size_t)j * 64);
+    const V m1 = *reinterpret_cast<const V*>(Mc + (size_t)(j + VEC) * 64);
+    const V m2 = *reinterpret_cast<const V*>(Mc + (size_t)(j + 2 * VEC) * 64);
+    const V m3 = *reinterpret_cast<const V*>(Mc + (size_t)(j + 3 * VEC) * 64);
+    const T x0 = x[j], x1 = x[j + VEC], x2 = x[j + 2 * VEC], x3 = x[j + 3 * VEC];
+    const T* a0 = reinterpret_cast<const T*>(&m0);
+    const T* a1 = reinterpret_cast<const T*>(&m1);
+    const T* a2 = reinterpret_cast<const T*>(&m2);
+    const T* a3 = reinterpret_cast<const T*>(&m3);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += (a0[v] * x0 + a1[v] * x1) + (a2[v] * x2 + a3[v] * x3);
+  }
+  for (; j < j1; j += VEC) {
+    const V m0 = *reinterpret_cast<const V*>(Mc + (size_t)j * 64);
+    const T* a0 = reinterpret_cast<const T*>(&m0);
+    const T x0 = x[j];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += a0[v] * x0;
+  }
+  // sum the VEC column phases (lanes l, l + LPC, ...)
+#pragma unroll
+  for (int off = 32; off >= LPC; off >>= 1)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += __shfl_down(acc[v], off, 64);
+  if (lane < LPC)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) part[q * 64 + rl + v] = acc[v];
+  __syncthreads();
+  if (q == 0) {
+    const int row = blockIdx.y * 64 + lane;
+    if (row < g.nown) z[own_glob(g, pid, row)] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
   }
 }
 
+// ---------------------------------------------------------------------------
+// Interior boxes share one inverse (translation invariance of the periodic
+// stencil away from the structure), so they form one dense contraction
+//   Z[64-row chunk, 32 boxes] = M[chunk, :] X[:, boxes]
+// on the matrix cores: wave w owns rows 16w..16w+15 of the chunk and two
+// 16 x 16 output tiles (boxes 0-15, 16-31), accumulated with 16x16x4 MFMA
+// steps.  A fragments stream straight from the chunk layout (16 contiguous
+// rows per reduction index), B fragments come from the boxes' residuals,
+// gathered 64 reduction indices at a time into LDS.
+// Operand layout of the 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its result register v holds D[row][l % 16] with
+// row = 4 (l / 16) + v for FP32 and row = l / 16 + 4 v for FP64 (checked on
+// gfx950 with a one-wave probe).
 template <typename T>
-void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* blk_of_patch,
-                      hipStream_t s) {
-  const int nbox = g.npd * g.npd;
-  int threads = ((g.nown + 63) / 64) * 64;
-  if (threads > 256) threads = 256;
-  hipLaunchKernelGGL((k_ras_apply<T>), dim3(nbox), dim3(threads), g.nloc * sizeof(T), s, r, z, g, inv,
-                     blk_of_patch);
-  IBMG_LAUNCH_CHECK();
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T* __restrict__ z,
+                                                      BoxGeom g, const T* __restrict__ M,
+                                                      const int* __restrict__ boxes, int nlist,
+                                                      const int* __restrict__ loc_tab,
+                                                      T* __restrict__ part, int ksplit) {
+  constexpr int KC = 64, TB = 32, GPT = KC * TB / 256, AS = KC / 4;
+  using acc_t = typename Mfma<T>::acc_t;
+  __shared__ T Xs[KC][TB + 1];
+  __shared__ int bx0[TB], by0[TB], bid[TB];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int bt = blockIdx.x * TB;
+  const int N = g.N;
+  const size_t nn = (size_t)N * N;
+  if (tid < TB) {
+    const int b = bt + tid;
+    const int pid = b < nlist ? boxes[b] : -1;
+    bid[tid] = pid;
+    bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
+    by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
+  }
+  __syncthreads();
+  // this block's slice of the reduction index: chunks [c0, c1) of KC columns
+  const int nchunk = (g.nloc + KC - 1) / KC;
+  const int per = (nchunk + ksplit - 1) / ksplit;
+  const int c0 = blockIdx.z * per;
+  const int c1 = c0 + per < nchunk ? c0 + per : nchunk;
+  const T* Mrow = M + (size_t)blockIdx.y * g.nloc * 64 + 16 * wave + (lane & 15);
+  const int kq = lane >> 4, bl = lane & 15;
+  acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  T gx[GPT], ga[AS];
+  auto load_chunk = [&](int c, T* gxo, T* gao) {
+    const int j0 = c * KC;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      const int t = tid + u * 256;
+      const int k = t / TB, b = t % TB;
+      const int jk = j0 + k;
+      T val = 0;
+      if (jk < g.nloc && bid[b] >= 0) {
+        const int code = loc_tab[jk];
+        int ii = (code & 0xfff) + bx0[b], jj = ((code >> 12) & 0xfff) + by0[b];
+        ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
+        jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
+        val = r[(size_t)(code >> 24) * nn + (size_t)jj * N + ii];
+      }
+      gxo[u] = val;
+    }
+#pragma unroll
+    for (int s = 0; s < AS; ++s) {
+      const int jk = j0 + 4 * s + kq;
+      gao[s] = jk < g.nloc ? Mrow[(size_t)jk * 64] : (T)0;
+    }
+  };
+  if (c0 < c1) load_chunk(c0, gx, ga);
+  for (int c = c0; c < c1; ++c) {
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      const int t = tid + u * 256;
+      Xs[t / TB][t % TB] = gx[u];
+    }
+    __syncthreads();
+    T a[AS];
+#pragma unroll
+    for (int s = 0; s < AS; ++s) a[s] = ga[s];
+    if (c + 1 < c1) load_chunk(c + 1, gx, ga);   // in flight during the MFMAs below
+#pragma unroll
+    for (int s = 0; s < AS; ++s) {
+      acc0 = Mfma<T>::mma(a[s], Xs[4 * s + kq][bl], acc0);
+      acc1 = Mfma<T>::mma(a[s], Xs[4 * s + kq][16 + bl], acc1);
+    }
+    __syncthreads();
+  }
+  const int nown_pad = g.nch * 64;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = blockIdx.y * 64 + 16 * wave + Mfma<T>::row(kq, v);
+    if (row >= g.nown) continue;
+    if (ksplit == 1) {
+      if (bid[bl] >= 0) z[own_glob(g, bid[bl], row)] = acc0[v];
+      if (bid[16 + bl] >= 0) z[own_glob(g, bid[16 + bl], row)] = acc1[v];
+    } else {
+      T* pp = part + (size_t)blockIdx.z * nlist * nown_pad;
+      if (bt + bl < nlist) pp[(size_t)(bt + bl) * nown_pad + row] = acc0[v];
+      if (bt + 16 + bl < nlist) pp[(size_t)(bt + 16 + bl) * nown_pad + row] = acc1[v];
+    }
+  }
+}
+
+// z[owned rows of interior box b] = sum over the reduction slices, in order.
+template <typename T>
+__global__ void k_ras_interior_sum(const T* __restrict__ part, T* __restrict__ z, BoxGeom g,
+                                   const int* __restrict__ boxes, int nlist, int ksplit) {
+  const int nown_pad = g.nch * 64;
+  const size_t tot = (size_t)nlist * g.nown;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t / g.nown), row = (int)(t % g.nown);
+    T a = 0;
+    for (int s = 0; s < ksplit; ++s) a += part[((size_t)s * nlist + b) * nown_pad + row];
+    z[own_glob(g, boxes[b], row)] = a;
+  }
+}
+
+// Reduction slices for the interior product: enough blocks to cover the
+// device (>= 768) while every slice keeps at least two column chunks.
+int ras_interior_ksplit(const BoxGeom& g, int n_int) {
+  if (n_int <= 0) return 1;
+  const int tiles = (n_int + 31) / 32;
+  const int nchunk = (g.nloc + 63) / 64;
+  int ks = 1;
+  while (ks < 8 && tiles * g.nch * ks < 768 && nchunk / (2 * ks) >= 2) ks *= 2;
+  return ks;
+}
+
+template <typename T>
+void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
+                      const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
+                      T* part, hipStream_t s) {
+  if (n_ib > 0) {
+    const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
+    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, z, g, inv, ib_boxes);
+    IBMG_LAUNCH_CHECK();
+  }
+  if (n_int > 0) {
+    const int ks = ras_interior_ksplit(g, n_int);
+    hipLaunchKernelGGL((k_ras_interior<T>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
+                       shared_inv, int_boxes, n_int, loc_tab, part, ks);
+    IBMG_LAUNCH_CHECK();
+    if (ks > 1) {
+      const size_t tot = (size_t)n_int * g.nown;
+      int grid = cdiv(tot, 256);
+      if (grid > 4096) grid = 4096;
+      hipLaunchKernelGGL((k_ras_interior_sum<T>), dim3(grid), dim3(256), 0, s, part, z, g, int_boxes, n_int, ks);
+      IBMG_LAUNCH_CHECK();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -433,9 +707,11 @@ void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_
 
 template void launch_extract_owned<double>(const double*, int, BoxGeom, double*, hipStream_t);
 template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t);
-template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*,
+template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*, int,
+                                       const double*, const int*, int, const int*, double*,
                                        hipStream_t);
-template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float*, const int*,
+template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float*, const int*, int,
+                                      const float*, const int*, int, const int*, float*,
                                       hipStream_t);
 template void launch_coarse_apply<double>(const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_apply<float>(const double*, int, const float*, float*, hipStream_t);

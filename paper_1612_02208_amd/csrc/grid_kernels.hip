@@ -18,11 +18,11 @@ static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 // The transposed form evaluates -D^T p and G^T u directly; the IB block is
 // the same J^T K' J chain with J standing in for S^T (S = J^* / h^2).
 // ---------------------------------------------------------------------------
-template <typename T, bool TRANS, bool RESID>
+template <typename T, bool TRANS, bool RESID, int IBM>
 __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __restrict__ y,
                                                const T* __restrict__ b, const T* __restrict__ F,
-                                               FootView<T> fx, FootView<T> fy, int N, int M,
-                                               StokesCoef<T> c) {
+                                               const T* __restrict__ Gib, FootView<T> fx,
+                                               FootView<T> fy, int N, int M, StokesCoef<T> c) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= N || j >= N) return;
@@ -41,7 +41,10 @@ __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __res
   const T vc = v[c0], vl = v[cl], vr = v[cr], vd = v[cd], vt = v[ct];
   const T pc = p[c0], pl = p[cl], pd = p[cd];
   T ibu = 0, ibv = 0;
-  if (F != nullptr) {
+  if (IBM == 2) {
+    ibu = Gib[c0];
+    ibv = Gib[n + c0];
+  } else if (IBM == 1) {
     const int a0 = fx.sp_ptr[c0], a1 = fx.sp_ptr[c0 + 1];
     for (int e = a0; e < a1; ++e) {
       const int ent = fx.sp_ent[e];
@@ -53,19 +56,21 @@ __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __res
       ibv += fy.w[ent] * F[M + (ent >> 4)];
     }
   }
+  // the precomputed Galerkin rows already carry the factor dt/h^2
+  const T ibs = IBM == 2 ? T(1) : c.ibs;
   const T lapu = ul + ur + ud + ut - T(4) * uc;
   const T lapv = vl + vr + vd + vt - T(4) * vc;
   T yu, yv, yp;
   if (!TRANS) {
-    yu = c.alpha * uc - c.beta * lapu + c.gi * (pc - pl) + c.ibs * ibu;
-    yv = c.alpha * vc - c.beta * lapv + c.gi * (pc - pd) + c.ibs * ibv;
+    yu = c.alpha * uc - c.beta * lapu + c.gi * (pc - pl) + ibs * ibu;
+    yv = c.alpha * vc - c.beta * lapv + c.gi * (pc - pd) + ibs * ibv;
     yp = -c.gi * (ur - uc + vt - vc);
   } else {
     // (-D^T p) on the x-face (i, j): D maps the face to cells (i, j) with -1/h
     // and (i-1, j) with +1/h.  G^T u on cell (i, j): G maps the cell to faces
     // (i, j) with +1/h and (i+1, j) with -1/h (likewise in y).
-    yu = c.alpha * uc - c.beta * lapu - c.gi * (pl - pc) + c.ibs * ibu;
-    yv = c.alpha * vc - c.beta * lapv - c.gi * (pd - pc) + c.ibs * ibv;
+    yu = c.alpha * uc - c.beta * lapu - c.gi * (pl - pc) + ibs * ibu;
+    yv = c.alpha * vc - c.beta * lapv - c.gi * (pd - pc) + ibs * ibv;
     yp = c.gi * (uc - ur + vc - vt);
   }
   if (RESID) {
@@ -78,23 +83,37 @@ __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __res
   y[2 * n + c0] = yp;
 }
 
-template <typename T>
-void launch_apply(const T* w, T* y, const T* b, const T* F, FootView<T> fx, FootView<T> fy,
-                  int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s) {
+template <typename T, int IBM>
+static void launch_apply_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+                           FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose,
+                           hipStream_t s) {
   dim3 blk(64, 4);
   dim3 grd((N + 63) / 64, (N + 3) / 4);
   if (b) {
     if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, true>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, true, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
     else
-      hipLaunchKernelGGL((k_apply<T, false, true>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, false, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
   } else {
     if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, false>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, true, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
     else
-      hipLaunchKernelGGL((k_apply<T, false, false>), grd, blk, 0, s, w, y, b, F, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, false, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
   }
   IBMG_LAUNCH_CHECK();
+}
+
+// IB source: G (precomputed dt/h^2 J^T K' J u rows) if non-null, else the
+// forces F gathered through the spreading lists if non-null, else none.
+template <typename T>
+void launch_apply(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+                  FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s) {
+  if (G)
+    launch_apply_m<T, 2>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
+  else if (F)
+    launch_apply_m<T, 1>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
+  else
+    launch_apply_m<T, 0>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -209,10 +228,10 @@ void launch_fill(T* a, T v, size_t n, hipStream_t s) {
 // grid-stride slice of V_q . t, accumulated in double; the finishing kernel
 // adds the partials in a fixed tree order.  The grid size depends only on n.
 // ---------------------------------------------------------------------------
-int dots_blocks(size_t n) {
-  int g = cdiv(n, 256 * 8);
+int dots_blocks(size_t n, int cap) {
+  int g = cdiv(n, 256 * 4);
   if (g < 1) g = 1;
-  if (g > 512) g = 512;
+  if (g > cap) g = cap;
   return g;
 }
 
@@ -227,6 +246,7 @@ __global__ void __launch_bounds__(256) k_dots(const T* __restrict__ V, int nvec,
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+#pragma unroll 4
     for (size_t i = blockIdx.x * (size_t)256 + tid; i < n; i += (size_t)gridDim.x * 256) {
       const double ti = (double)t[i];
 #pragma unroll
@@ -505,8 +525,8 @@ void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_
 // Explicit instantiations.
 // ---------------------------------------------------------------------------
 #define IBMG_INST_GRID(T)                                                                         \
-  template void launch_apply<T>(const T*, T*, const T*, const T*, FootView<T>, FootView<T>, int,  \
-                                int, StokesCoef<T>, bool, hipStream_t);                           \
+  template void launch_apply<T>(const T*, T*, const T*, const T*, const T*, FootView<T>,          \
+                                FootView<T>, int, int, StokesCoef<T>, bool, hipStream_t);         \
   template void launch_restrict<T>(const T*, T*, int, hipStream_t);                               \
   template void launch_prolong_add<T>(const T*, T*, int, hipStream_t);                            \
   template void launch_fill<T>(T*, T, size_t, hipStream_t);                                       \

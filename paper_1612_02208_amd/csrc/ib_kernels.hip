@@ -296,4 +296,39 @@ template void launch_ib_force<float>(const float*, const float*, FootView<float>
 template void launch_interp<double>(const double*, const double*, FootView<double>, FootView<double>,
                                     int, int, double*, hipStream_t);
 
+
+// G = dt/h^2 J^T K' J x for both components from the explicit Galerkin rows:
+// one wave per row, lanes stride the row, butterfly sum in a fixed order.
+// Used on levels where many points share each face, so that a per-face
+// gather would serialise on long lists.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_spmv(const T* __restrict__ x, T* __restrict__ G,
+                                                 CsrT<T> tu, CsrT<T> tv, int N) {
+  const int NN = N * N;
+  const int wave = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= 2 * NN) return;
+  const int comp = wave >= NN ? 1 : 0;
+  const int r = wave - comp * NN;
+  const int* ptr = comp ? tv.ptr : tu.ptr;
+  const int* col = comp ? tv.col : tu.col;
+  const T* val = comp ? tv.val : tu.val;
+  const T* xin = x + (size_t)comp * NN;
+  const int lo = ptr[r], hi = ptr[r + 1];
+  T acc = 0;
+  for (int k = lo + lane; k < hi; k += 64) acc += val[k] * xin[col[k]];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) G[wave] = acc;
+}
+
+template <typename T>
+void launch_ib_spmv(const T* x, T* G, CsrT<T> tu, CsrT<T> tv, int N, hipStream_t s) {
+  const size_t waves = 2 * (size_t)N * N;
+  hipLaunchKernelGGL((k_ib_spmv<T>), dim3(cdiv(waves * 64, 256)), dim3(256), 0, s, x, G, tu, tv, N);
+  IBMG_LAUNCH_CHECK();
+}
+
+template void launch_ib_spmv<double>(const double*, double*, CsrT<double>, CsrT<double>, int, hipStream_t);
+template void launch_ib_spmv<float>(const float*, float*, CsrT<float>, CsrT<float>, int, hipStream_t);
+
 }  // namespace ibmg

@@ -102,7 +102,7 @@ struct StokesCoef {     // A = alpha I - mu Lap: alpha, beta = mu/h^2, gi = 1/h,
 };
 
 struct BoxGeom {        // RAS boxes on one level
-  int N, b, o, m, npd, nloc, nown;
+  int N, b, o, m, npd, nloc, nown, nch;  // nch = ceil(nown / 64) row chunks
 };
 
 // ---------------------------------------------------------------------------
@@ -110,8 +110,16 @@ struct BoxGeom {        // RAS boxes on one level
 // ---------------------------------------------------------------------------
 // grid ops
 template <typename T>
-void launch_apply(const T* w, T* y, const T* b, const T* F, FootView<T> fx, FootView<T> fy,
-                  int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s);
+void launch_apply(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+                  FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s);
+template <typename T>
+struct CsrT {
+  const int* ptr;
+  const int* col;
+  const T* val;
+};
+template <typename T>
+void launch_ib_spmv(const T* x, T* G, CsrT<T> tu, CsrT<T> tv, int N, hipStream_t s);
 template <typename T>
 void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s);
 template <typename T>
@@ -144,7 +152,23 @@ void launch_block_sums(const T* a, int N, double* partial, int nblk, hipStream_t
 template <typename T>
 void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_t s);
 
-int dots_blocks(size_t n);
+// blocks of the deterministic reductions (depends only on n and cap);
+// consumers re-reduce blocks x vectors partials, so long bases use a lower cap
+int dots_blocks(size_t n, int cap = 256);
+
+// fused Gram-Schmidt passes (krylov_kernels.hip); nblk = producer blocks
+template <typename T>
+void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
+                     double* hcol, double* pout, hipStream_t s);
+template <typename T>
+void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
+                     double* hcol, double* pout, hipStream_t s);
+template <typename T>
+void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, double* hout,
+                      hipStream_t s);
+template <typename T>
+void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
+                       const double* beta, double* yout, hipStream_t s);
 
 // immersed boundary
 void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
@@ -171,12 +195,15 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
                            const int* tptr_v, const int* tcol_v, const double* tval_v,
                            double* mats, hipStream_t s);
 void launch_gj_invert(double* mats, int n, int count, double* colk, hipStream_t s);
-constexpr int kGjNb = 16;  // block width of the batched Gauss-Jordan inversion
+constexpr int kGjNb = 64;  // block width of the batched Gauss-Jordan inversion
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
 template <typename T>
-void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* blk_of_patch,
-                      hipStream_t s);
+void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
+                      const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
+                      T* part, hipStream_t s);
+// reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
+int ras_interior_ksplit(const BoxGeom& g, int n_int);
 void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,
                             const double* tval_u, const int* tptr_v, const int* tcol_v,
                             const double* tval_v, int nb, double* aug, hipStream_t s);

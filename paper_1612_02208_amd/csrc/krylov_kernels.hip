@@ -1,0 +1,237 @@
+// Fused Gram-Schmidt and small least-squares kernels of the FGMRES iterations
+// (outer solve and Sec. 3.3 smoothing).
+//
+// Classical Gram-Schmidt applied twice to t against V[0..k):
+//   launch_dots        partial dots V_q . t                      (pass 1)
+//   launch_upd_dots    h = sum partials; t -= V h; partial V_q . t (pass 2)
+//   launch_upd_norm    h2 = sum partials; t -= V h2; partial |t|^2
+//   launch_scale_red   |t| = sqrt(sum partials); v = t / |t|
+// A consumer kernel reduces its producer's per-block partials itself, every
+// block in the same fixed order, so the result is deterministic and no
+// cross-block synchronisation or atomics are needed; block 0 also records the
+// Hessenberg entries.
+#include "internal.hpp"
+
+namespace ibmg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// out[q] = sum_b partial[b * k + q], q < k, in a fixed tree order.
+__device__ void reduce_partials(const double* __restrict__ partial, int nblk, int k, double* out,
+                                double* red) {
+  const int tid = threadIdx.x;
+  for (int q = 0; q < k; ++q) {
+    double a = 0.0;
+    for (int b = tid; b < nblk; b += kThreads) a += partial[(size_t)b * k + q];
+    red[tid] = a;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) out[q] = red[0];
+    __syncthreads();
+  }
+}
+
+// per-block partial sums of up to 8 products at a time, written as
+// partial[blockIdx.x * k + q]
+template <typename T>
+__device__ void block_dots(const T* __restrict__ V, int k, size_t stride, const T* t, size_t n,
+                           double* __restrict__ partial, double (*red)[kThreads]) {
+  const int tid = threadIdx.x;
+  for (int v0 = 0; v0 < k; v0 += 8) {
+    const int nv = k - v0 < 8 ? k - v0 : 8;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+#pragma unroll 4
+    for (size_t i = blockIdx.x * (size_t)kThreads + tid; i < n; i += (size_t)gridDim.x * kThreads) {
+      const double ti = (double)t[i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nv) acc[q] += (double)V[(size_t)(v0 + q) * stride + i] * ti;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][tid] = acc[q];
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][tid] += red[q][tid + s];
+      }
+      __syncthreads();
+    }
+    if (tid < nv) partial[(size_t)blockIdx.x * k + v0 + tid] = red[tid][0];
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// t -= V h (h from pass-1 partials, stored into hcol by block 0), then the
+// pass-2 partial dots of the updated t.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict__ V, int k, size_t stride,
+                                                       size_t n, const double* __restrict__ pin, int nblk_in,
+                                                       double* __restrict__ hcol, double* __restrict__ pout) {
+  __shared__ double red[8][kThreads];
+  __shared__ double h[64];
+  reduce_partials(pin, nblk_in, k, h, red[0]);
+  if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] = h[threadIdx.x];
+#pragma unroll 4
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    double a = (double)t[i];
+    for (int q = 0; q < k; ++q) a -= h[q] * (double)V[(size_t)q * stride + i];
+    t[i] = (T)a;
+  }
+  __syncthreads();
+  block_dots<T>(V, k, stride, t, n, pout, red);
+}
+
+// t -= V h2 (h2 from pass-2 partials, added into hcol by block 0), then the
+// partial sums of |t|^2.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict__ V, int k, size_t stride,
+                                                       size_t n, const double* __restrict__ pin, int nblk_in,
+                                                       double* __restrict__ hcol, double* __restrict__ pout) {
+  __shared__ double red[8][kThreads];
+  __shared__ double h[64];
+  reduce_partials(pin, nblk_in, k, h, red[0]);
+  if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] += h[threadIdx.x];
+  double acc = 0.0;
+#pragma unroll 4
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    double a = (double)t[i];
+    for (int q = 0; q < k; ++q) a -= h[q] * (double)V[(size_t)q * stride + i];
+    const T tn = (T)a;
+    t[i] = tn;
+    acc += (double)tn * (double)tn;
+  }
+  red[0][threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[0][threadIdx.x] += red[0][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pout[blockIdx.x] = red[0][0];
+}
+
+// v = t / sqrt(sum partials) (v = 0 on an exact breakdown); block 0 stores the
+// norm into *hout.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, size_t n,
+                                                        const double* __restrict__ pin, int nblk_in,
+                                                        double* __restrict__ hout) {
+  __shared__ double red[kThreads];
+  __shared__ double nrm;
+  reduce_partials(pin, nblk_in, 1, &nrm, red);
+  const double d = sqrt(nrm);
+  if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = d;
+  const double inv = d != 0.0 ? 1.0 / d : 0.0;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
+    v[i] = (T)((double)t[i] * inv);
+}
+
+// Least squares min || beta e1 - H y || ((k+1) x k Hessenberg, column-major,
+// leading dimension ldh) by Givens rotations in every block, then
+// x += sum_q y_q Z_q; block 0 stores y.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, const T* __restrict__ Z, int k,
+                                                         size_t stride, size_t n, const double* __restrict__ H,
+                                                         int ldh, const double* __restrict__ beta,
+                                                         double* __restrict__ yout) {
+  __shared__ double y[16];
+  if (threadIdx.x == 0) {
+    double R[17][16];
+    double g[17], cs[16], sn[16];
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i <= k; ++i) R[i][j] = H[i + (size_t)j * ldh];
+    for (int i = 0; i <= k; ++i) g[i] = 0.0;
+    g[0] = beta[0];
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i < j; ++i) {
+        const double a = R[i][j], b = R[i + 1][j];
+        R[i][j] = cs[i] * a + sn[i] * b;
+        R[i + 1][j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = R[j][j], b = R[j + 1][j];
+      const double d = sqrt(a * a + b * b);
+      double c = 1.0, s = 0.0;
+      if (d != 0.0) {
+        c = a / d;
+        s = b / d;
+      }
+      cs[j] = c;
+      sn[j] = s;
+      R[j][j] = d;
+      R[j + 1][j] = 0.0;
+      const double gj = g[j];
+      g[j] = c * gj;
+      g[j + 1] = -s * gj;
+    }
+    for (int j = k - 1; j >= 0; --j) {
+      double a = g[j];
+      for (int m = j + 1; m < k; ++m) a -= R[j][m] * y[m];
+      y[j] = R[j][j] != 0.0 ? a / R[j][j] : 0.0;
+    }
+    if (blockIdx.x == 0)
+      for (int j = 0; j < k; ++j) yout[j] = y[j];
+  }
+  __syncthreads();
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    double a = (double)x[i];
+    for (int q = 0; q < k; ++q) a += y[q] * (double)Z[(size_t)q * stride + i];
+    x[i] = (T)a;
+  }
+}
+
+static int stream_blocks(size_t n) {
+  size_t g = (n + kThreads - 1) / kThreads;
+  if (g > 1024) g = 1024;
+  return (int)(g < 1 ? 1 : g);
+}
+
+template <typename T>
+void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
+                     double* hcol, double* pout, hipStream_t s) {
+  hipLaunchKernelGGL((k_upd_dots<T>), dim3(nblk), dim3(kThreads), 0, s, t, V, k, stride, n, pin, nblk, hcol, pout);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
+                     double* hcol, double* pout, hipStream_t s) {
+  hipLaunchKernelGGL((k_upd_norm<T>), dim3(nblk), dim3(kThreads), 0, s, t, V, k, stride, n, pin, nblk, hcol, pout);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, double* hout, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_red<T>), dim3(stream_blocks(n)), dim3(kThreads), 0, s, t, v, n, pin, nblk, hout);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
+                       const double* beta, double* yout, hipStream_t s) {
+  hipLaunchKernelGGL((k_combine_ls<T>), dim3(stream_blocks(n)), dim3(kThreads), 0, s, x, Z, k, stride, n, H,
+                     ldh, beta, yout);
+  IBMG_LAUNCH_CHECK();
+}
+
+#define IBMG_INST_KRY(T)                                                                               \
+  template void launch_upd_dots<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,     \
+                                   double*, hipStream_t);                                              \
+  template void launch_upd_norm<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,     \
+                                   double*, hipStream_t);                                              \
+  template void launch_scale_red<T>(const T*, T*, size_t, const double*, int, double*, hipStream_t);   \
+  template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, const double*, int,            \
+                                     const double*, double*, hipStream_t);
+
+IBMG_INST_KRY(double)
+IBMG_INST_KRY(float)
+
+}  // namespace ibmg

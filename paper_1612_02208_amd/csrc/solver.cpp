@@ -5,6 +5,7 @@
 // sequences launches on one stream.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <type_traits>
 
@@ -18,6 +19,11 @@ constexpr int kMaxNu = 8;
 constexpr int kMaxRestart = 64;
 constexpr int kScalY = 1;     // scal[1..16]: least-squares solution
 constexpr int kScalTmp = 20;  // scal[20..]: second Gram-Schmidt pass
+// Levels whose longest face -> point list exceeds this use the explicit
+// Galerkin IB rows (one wave per row) for the IB term.
+constexpr int kSpmvListThreshold = 24;
+// partial-sum buffers: two of kPartStride doubles (blocks x vectors)
+constexpr size_t kPartStride = (size_t)256 * 65;
 
 int wrapn(int a, int N) {
   a %= N;
@@ -87,15 +93,22 @@ template <typename T>
 struct Level {
   int N = 0;
   CompFoot f[2];
+  // IB term from the explicit Galerkin rows (wave per row) instead of the
+  // interpolate / spring / spread chain: chosen where points crowd the faces
+  bool use_spmv = false;
+  DBuf<double> Gd;
+  DBuf<T> Gt;
   StokesCoef<double> cd{};
   StokesCoef<T> ct{};
   // restricted additive Schwarz
   BoxGeom g{};
   int n_unique = 0, n_ib = 0;
   std::vector<int> uniq;  // unique box ids (IB boxes, then one interior representative)
-  std::vector<int> blk_h;
-  DBuf<int> blk;
-  DBuf<T> inv;
+  std::vector<int> ib_list, int_list;
+  std::vector<int> loc_tab;  // local unknown -> (comp << 24) | (jj << 12) | ii
+  DBuf<int> d_ib, d_int, d_loc;
+  DBuf<T> inv;            // [n_unique][nch][nloc][64]
+  DBuf<T> int_part;       // reduction slices of the interior-box product
   // work vectors
   DBuf<T> w, b, r, t, V, Z, F;
   DBuf<double> H, scal, part;
@@ -120,6 +133,8 @@ class Solver final : public SolverBase {
   }
 
   ~Solver() override {
+    drop_graph();
+    if (gstream_) (void)hipStreamDestroy(gstream_);
     if (pinned_) (void)hipHostFree(pinned_);
   }
 
@@ -181,7 +196,12 @@ class Solver final : public SolverBase {
         f.d_tptr.upload(f.tptr, s);
         f.d_tcol.upload(f.tcol, s);
         f.tval.alloc(f.tcol.size());
+        if (std::is_same<T, float>::value) f.tvalf.alloc(f.tcol.size());
+        f.max_list = 0;
+        for (size_t r = 0; r + 1 < f.sp_ptr.size(); ++r)
+          f.max_list = std::max(f.max_list, f.sp_ptr[r + 1] - f.sp_ptr[r]);
       }
+      lev.use_spmv = std::max(lev.f[0].max_list, lev.f[1].max_list) > kSpmvListThreshold;
       if (l >= 1 && d_.smoother == IBMG_RAS) classify_boxes(lev);
     }
   }
@@ -293,11 +313,11 @@ class Solver final : public SolverBase {
     int b, o;
     box_params(lev.N, d_.box, d_.overlap, &b, &o);
     const int m = b + 2 * o, N = lev.N;
-    lev.g = BoxGeom{N, b, o, m, N / b, 2 * m * (m + 1) + m * m, 3 * b * b};
+    lev.g = BoxGeom{N, b, o, m, N / b, 2 * m * (m + 1) + m * m, 3 * b * b, (3 * b * b + 63) / 64};
     const int nbox = lev.g.npd * lev.g.npd;
     lev.uniq.clear();
-    lev.blk_h.assign(nbox, -1);
-    int interior = -1;
+    lev.ib_list.clear();
+    lev.int_list.clear();
     for (int p = 0; p < nbox; ++p) {
       const int x0 = (p % lev.g.npd) * b - o, y0 = (p / lev.g.npd) * b - o;
       bool ib = false;
@@ -307,21 +327,25 @@ class Solver final : public SolverBase {
           if (jj < m && lev.f[0].tptr[r + 1] > lev.f[0].tptr[r]) ib = true;   // x-face (ii, jj)
           if (ii < m && lev.f[1].tptr[r + 1] > lev.f[1].tptr[r]) ib = true;   // y-face (ii, jj)
         }
-      if (ib) {
-        lev.blk_h[p] = (int)lev.uniq.size();
-        lev.uniq.push_back(p);
-      } else if (interior < 0) {
-        interior = p;
-      }
+      if (ib) lev.ib_list.push_back(p);
+      else lev.int_list.push_back(p);
     }
-    lev.n_ib = (int)lev.uniq.size();
-    if (interior >= 0) {
-      for (int p = 0; p < nbox; ++p)
-        if (lev.blk_h[p] < 0) lev.blk_h[p] = lev.n_ib;
-      lev.uniq.push_back(interior);
+    lev.loc_tab.assign(lev.g.nloc, 0);
+    for (int k = 0; k < lev.g.nloc; ++k) {
+      const int nu = m * (m + 1);
+      int comp, ii, jj;
+      if (k < nu) { comp = 0; ii = k % (m + 1); jj = k / (m + 1); }
+      else if (k < 2 * nu) { comp = 1; ii = (k - nu) % m; jj = (k - nu) / m; }
+      else { comp = 2; ii = (k - 2 * nu) % m; jj = (k - 2 * nu) / m; }
+      lev.loc_tab[k] = (comp << 24) | (jj << 12) | ii;
     }
+    lev.n_ib = (int)lev.ib_list.size();
+    lev.uniq = lev.ib_list;
+    if (!lev.int_list.empty()) lev.uniq.push_back(lev.int_list.front());
     lev.n_unique = (int)lev.uniq.size();
   }
+
+  size_t box_stride(const Level<T>& lev) const { return (size_t)lev.g.nch * lev.g.nloc * 64; }
 
   void build_numeric(hipStream_t s) {
     // spring stiffness per incidence
@@ -336,9 +360,12 @@ class Solver final : public SolverBase {
       Level<T>& lev = levels_[l];
       for (int c = 0; c < 2; ++c) {
         CompFoot& f = lev.f[c];
-        if (!f.tcol.empty())
+        if (!f.tcol.empty()) {
           launch_t_values(fview<double>(f), f.d_mask.p, sview<double>(), lev.N, lev.cd.ibs, f.d_tptr.p,
                           f.d_tcol.p, f.tval.p, s);
+          if (std::is_same<T, float>::value)
+            launch_cast<double, float>(f.tval.p, f.tvalf.p, f.tcol.size(), s);
+        }
       }
     }
     build_coarse(s);
@@ -365,8 +392,16 @@ class Solver final : public SolverBase {
   void build_boxes(Level<T>& lev, hipStream_t s) {
     const BoxGeom& g = lev.g;
     const size_t per = (size_t)g.nloc * g.nloc;
-    lev.blk.upload(lev.blk_h, s);
-    lev.inv.alloc((size_t)lev.n_unique * g.nloc * g.nown);
+    lev.d_ib.upload(lev.ib_list, s);
+    lev.d_int.upload(lev.int_list, s);
+    lev.d_loc.upload(lev.loc_tab, s);
+    {
+      const int n_int = (int)lev.int_list.size();
+      const int ks = ras_interior_ksplit(g, n_int);
+      if (ks > 1 && lev.int_part.n < (size_t)ks * n_int * g.nch * 64)
+        lev.int_part.alloc((size_t)ks * n_int * g.nch * 64);
+    }
+    lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
     const size_t budget = (size_t)1 << 30;
     int batch = (int)std::max<size_t>(1, budget / ((per + (size_t)g.nloc * kGjNb) * sizeof(double)));
     batch = std::min(batch, lev.n_unique);
@@ -380,7 +415,7 @@ class Solver final : public SolverBase {
                             lev.f[0].tval.p, lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p,
                             mats.p, s);
       launch_gj_invert(mats.p, g.nloc, cnt, colk.p, s);
-      launch_extract_owned<T>(mats.p, cnt, g, lev.inv.p + (size_t)b0 * g.nloc * g.nown, s);
+      launch_extract_owned<T>(mats.p, cnt, g, lev.inv.p + (size_t)b0 * box_stride(lev), s);
     }
     IBMG_HIP(hipStreamSynchronize(s));
   }
@@ -399,9 +434,13 @@ class Solver final : public SolverBase {
         lev.Z.alloc((size_t)nu_ * n);
       }
       lev.F.alloc(2 * (size_t)std::max(M_, 1));
+      if (lev.use_spmv) {
+        lev.Gd.alloc(2 * (size_t)lev.N * lev.N);
+        if (std::is_same<T, float>::value) lev.Gt.alloc(2 * (size_t)lev.N * lev.N);
+      }
       lev.H.alloc((size_t)(kMaxNu + 1) * kMaxNu);
       lev.scal.alloc(64);
-      lev.part.alloc((size_t)512 * 32);
+      lev.part.alloc(2 * kPartStride);
     }
     Fd_.alloc(2 * (size_t)std::max(M_, 1));
     Uw_.alloc(2 * (size_t)std::max(M_, 1));
@@ -436,25 +475,47 @@ class Solver final : public SolverBase {
     Level<T>& lev = levels_[l];
     const size_t nn = (size_t)lev.N * lev.N;
     const U* Fp = nullptr;
+    const U* Gp = nullptr;
     if (M_ > 0 && E_ > 0) {
-      launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N, F, s);
-      Fp = F;
+      if (lev.use_spmv) {
+        U* G = gbuf<U>(lev);
+        launch_ib_spmv<U>(x, G, csr<U>(lev.f[0]), csr<U>(lev.f[1]), lev.N, s);
+        Gp = G;
+      } else {
+        launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N, F, s);
+        Fp = F;
+      }
     }
-    launch_apply<U>(x, y, b, Fp, fview<U>(lev.f[0]), fview<U>(lev.f[1]), lev.N, M_, coef<U>(lev),
+    launch_apply<U>(x, y, b, Fp, Gp, fview<U>(lev.f[0]), fview<U>(lev.f[1]), lev.N, M_, coef<U>(lev),
                     trans, s);
+  }
+
+  template <typename U>
+  CsrT<U> csr(CompFoot& f) {
+    if constexpr (std::is_same<U, double>::value)
+      return CsrT<double>{f.d_tptr.p, f.d_tcol.p, f.tval.p};
+    else
+      return CsrT<float>{f.d_tptr.p, f.d_tcol.p, f.tvalf.p};
+  }
+  template <typename U>
+  U* gbuf(Level<T>& lev) {
+    if constexpr (std::is_same<U, double>::value) return lev.Gd.p;
+    else return lev.Gt.p;
   }
 
   // ------------------------------------------------------- V-cycle pieces
   void basic_smoother(int l, const T* v, T* z, hipStream_t s) {
     Level<T>& lev = levels_[l];
-    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.blk.p, s);
+    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.d_ib.p, lev.n_ib,
+                        lev.inv.p + (size_t)lev.n_ib * box_stride(lev), lev.d_int.p,
+                        (int)lev.int_list.size(), lev.d_loc.p, lev.int_part.p, s);
   }
 
   // w <- w + e, e = nu FGMRES iterations (CGS2) on L e = b - L w from e = 0.
   void smooth_t(int l, T* w, const T* b, int nu, bool w_zero, hipStream_t s) {
     Level<T>& lev = levels_[l];
     const size_t n = 3 * (size_t)lev.N * lev.N;
-    const int nblk = dots_blocks(n);
+    const int nblk = dots_blocks(n, 1024);  // at most nu + 1 vectors
     const int ldh = kMaxNu + 1;
     const T* r0;
     if (w_zero) {
@@ -465,11 +526,12 @@ class Solver final : public SolverBase {
       r0 = lev.r.p;
     }
     double* beta = lev.scal.p;
-    launch_dots<T>(r0, 1, n, r0, n, lev.part.p, nblk, s);
-    launch_dots_finish(lev.part.p, 1, nblk, beta, nullptr, 2, s);
+    double* pa = lev.part.p;
+    double* pb = lev.part.p + kPartStride;
+    launch_dots<T>(r0, 1, n, r0, n, pa, nblk, s);
     T* V = lev.V.p;
     T* Z = lev.Z.p;
-    launch_scale<T>(r0, V, beta, n, s);
+    launch_scale_red<T>(r0, V, n, pa, nblk, beta, s);
     for (int k = 0; k < nu; ++k) {
       T* vk = V + (size_t)k * n;
       T* zk = Z + (size_t)k * n;
@@ -477,26 +539,21 @@ class Solver final : public SolverBase {
       basic_smoother(l, vk, zk, s);
       op<T>(l, zk, t, nullptr, false, lev.F.p, s);
       double* hcol = lev.H.p + (size_t)k * ldh;
-      orthogonalise<T>(V, k + 1, n, t, hcol, lev.scal.p + kScalTmp, lev.part.p, nblk, s);
-      launch_scale<T>(t, t, hcol + k + 1, n, s);
+      orthogonalise<T>(V, k + 1, n, t, hcol, pa, pb, nblk, s);
+      launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
     }
-    launch_small_ls(lev.H.p, ldh, nu, beta, lev.scal.p + kScalY, s);
-    launch_combine<T>(w, Z, nu, n, lev.scal.p + kScalY, n, s);
+    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s);
   }
 
   // Classical Gram-Schmidt twice against V[0..k): h (first pass + second
-  // pass) into hcol[0..k), ||t|| into hcol[k].
+  // pass) into hcol[0..k); the partial sums of ||t||^2 are left in pa for
+  // launch_scale_red, which stores ||t|| and normalises t.
   template <typename U>
-  void orthogonalise(const U* V, int k, size_t n, U* t, double* hcol, double* tmp, double* part,
+  void orthogonalise(const U* V, int k, size_t n, U* t, double* hcol, double* pa, double* pb,
                      int nblk, hipStream_t s) {
-    launch_dots<U>(V, k, n, t, n, part, nblk, s);
-    launch_dots_finish(part, k, nblk, hcol, nullptr, 0, s);
-    launch_update<U>(t, V, k, n, hcol, -1.0, n, s);
-    launch_dots<U>(V, k, n, t, n, part, nblk, s);
-    launch_dots_finish(part, k, nblk, tmp, hcol, 1, s);
-    launch_update<U>(t, V, k, n, tmp, -1.0, n, s);
-    launch_dots<U>(t, 1, n, t, n, part, nblk, s);
-    launch_dots_finish(part, 1, nblk, hcol + k, nullptr, 2, s);
+    launch_dots<U>(V, k, n, t, n, pa, nblk, s);
+    launch_upd_dots<U>(t, V, k, n, n, pa, nblk, hcol, pb, s);
+    launch_upd_norm<U>(t, V, k, n, n, pb, nblk, hcol, pa, s);
   }
 
   // w = MG(0, b) on level l (Alg. 1)
@@ -570,7 +627,7 @@ class Solver final : public SolverBase {
     launch_coarse_apply<double>(inv0_.p, n0_, r, x, s);
   }
 
-  void vcycle(const double* r, double* z, hipStream_t s) override {
+  void vcycle_body(const double* r, double* z, hipStream_t s) {
     Level<T>& top = levels_[L_];
     const size_t n = 3 * (size_t)top.N * top.N;
     if constexpr (std::is_same<T, double>::value) {
@@ -580,6 +637,46 @@ class Solver final : public SolverBase {
       mg(L_, top.b.p, top.w.p, s);
       launch_cast<T, double>(top.w.p, z, n, s);
     }
+  }
+
+  // The whole V-cycle (several hundred launches, no host synchronisation)
+  // is captured once into a HIP graph reading vin_ and writing vout_, then
+  // replayed; the graph holds kernel nodes only.
+  void build_graph() {
+    const size_t n = 3 * (size_t)d_.N * d_.N;
+    vin_.alloc(n);
+    vout_.alloc(n);
+    if (!gstream_) IBMG_HIP(hipStreamCreateWithFlags(&gstream_, hipStreamNonBlocking));
+    IBMG_HIP(hipStreamBeginCapture(gstream_, hipStreamCaptureModeThreadLocal));
+    try {
+      vcycle_body(vin_.p, vout_.p, gstream_);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(gstream_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    IBMG_HIP(hipStreamEndCapture(gstream_, &graph_));
+    IBMG_HIP(hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0));
+  }
+
+  void drop_graph() {
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    gexec_ = nullptr;
+    graph_ = nullptr;
+  }
+
+  void vcycle(const double* r, double* z, hipStream_t s) override {
+    if (!use_graph_) {
+      vcycle_body(r, z, s);
+      return;
+    }
+    const size_t n = 3 * (size_t)d_.N * d_.N;
+    if (!gexec_) build_graph();
+    IBMG_HIP(hipMemcpyAsync(vin_.p, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipGraphLaunch(gexec_, s));
+    IBMG_HIP(hipMemcpyAsync(z, vout_.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
 
   double read_scalar(const double* dptr, hipStream_t s) {
@@ -599,7 +696,7 @@ class Solver final : public SolverBase {
     g_.alloc(restart + 2);
     y_.alloc(restart + 1);
     osc_.alloc(256);
-    opart_.alloc((size_t)512 * (restart + 1));
+    opart_.alloc(2 * kPartStride);
     bp_.alloc(n);
     rr_.alloc(n);
     outer_cap_ = restart;
@@ -684,8 +781,8 @@ class Solver final : public SolverBase {
         ++vcycles;
         op<double>(L_, zk, t, nullptr, false, Fd_.p, s);
         double* hcol = Ho_.p + (size_t)k * ldh;
-        orthogonalise<double>(Vo_.p, k + 1, n, t, hcol, osc_.p + 128, opart_.p, nblk, s);
-        launch_scale<double>(t, t, hcol + k + 1, n, s);
+        orthogonalise<double>(Vo_.p, k + 1, n, t, hcol, opart_.p, opart_.p + kPartStride, nblk, s);
+        launch_scale_red<double>(t, t, n, opart_.p, nblk, hcol + k + 1, s);
         launch_givens(Ho_.p, ldh, k, cs_.p, sn_.p, g_.p, osc_.p + 1, s);
         est = read_scalar(osc_.p + 1, s);
         ++k;
@@ -728,6 +825,7 @@ class Solver final : public SolverBase {
     for (int e = 0; e < E_; ++e)
       require(std::isfinite(kappa[e]) && kappa[e] >= 0.0, "kappa must be finite and >= 0");
     kappa_.assign(kappa, kappa + E_);
+    drop_graph();  // the box inverses are reallocated
     build_numeric(s);
     IBMG_HIP(hipStreamSynchronize(s));
   }
@@ -762,6 +860,17 @@ class Solver final : public SolverBase {
   int outer_cap_ = 0;
   DBuf<double> Vo_, Zo_, Ho_, cs_, sn_, g_, y_, osc_, opart_, bp_, rr_;
   double* pinned_ = nullptr;
+  // V-cycle graph
+  bool use_graph_ = graphs_enabled();
+  hipStream_t gstream_ = nullptr;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t gexec_ = nullptr;
+  DBuf<double> vin_, vout_;
+
+  static bool graphs_enabled() {
+    const char* e = std::getenv("IBMG_GRAPH");
+    return !(e && e[0] == '0');
+  }
 };
 
 SolverBase* make_solver(const ibmg_desc& d, hipStream_t s) {

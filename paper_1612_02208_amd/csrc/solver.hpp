@@ -14,6 +14,8 @@ struct CompFoot {             // one velocity component on one level
   DBuf<double> w;             // [M][16]
   DBuf<float> wf;             // FP32 copy for the FP32 smoother
   DBuf<double> tval;
+  DBuf<float> tvalf;          // FP32 copy for the FP32 smoother
+  int max_list = 0;           // longest face -> point list
 };
 
 struct SolverBase {

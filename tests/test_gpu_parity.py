@@ -52,7 +52,14 @@ def _cases():
     Sr = Sr[Sr[:, 0] != Sr[:, 1]]
     c3 = W.Workload("random_48", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, rng.uniform(10, 1e3, len(Sr)), box=6,
                     overlap=1)
-    return [c1, c2, c3]
+    # large boxes (16 x 16 cells, overlap 4: 1776 unknowns per box)
+    c4 = W.Workload("annulus_64_box16", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4), box=16,
+                    overlap=4)
+    # a small membrane: most boxes are interior and share one inverse (the
+    # matrix-core path), 2 tiles of 32 boxes with a ragged second tile
+    Xs, Ss = W.membrane(40, 0.05, centre=(0.31, 0.62))
+    c5 = W.Workload("small_64", 64, 8, 1.0, 0.1, 1e-3, Xs, Ss, np.full(len(Ss), 3e2), box=8, overlap=2)
+    return [c1, c2, c3, c4, c5]
 
 
 CASES = _cases()
