@@ -81,6 +81,8 @@ typedef struct {
   int32_t restart;    /* FGMRES restart length, 1..64 (30)                    */
   int32_t max_it;     /* total iteration cap (100, the paper's Sec. 5 cap)    */
   int32_t use_x0;     /* 1: x holds the initial guess; 0: start from zero     */
+  int32_t transpose;  /* 1: solve L_IB^T x = b (adjoint system; the Krylov
+                         operator is ibmg_apply_A_IB_T's transposed path)    */
 } ibmg_solve_opts;
 
 typedef struct {

@@ -33,7 +33,8 @@ class Desc(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int32),
-                ("max_it", ctypes.c_int32), ("use_x0", ctypes.c_int32)]
+                ("max_it", ctypes.c_int32), ("use_x0", ctypes.c_int32),
+                ("transpose", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

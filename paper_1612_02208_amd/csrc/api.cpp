@@ -180,7 +180,7 @@ ibmg_status ibmg_fgmres_solve(ibmg_handle* h, const double* b, double* x, const 
                               ibmg_solve_info* info, ibmg_stream st) {
   return guarded(h, [&](ibmg::SolverBase* s) {
     ibmg::require(b && x && b != x, "b and x must be distinct device pointers");
-    ibmg_solve_opts o{1e-8, 30, 100, 0};
+    ibmg_solve_opts o{1e-8, 30, 100, 0, 0};
     if (opts) o = *opts;
     return s->fgmres(b, x, o, info, S(st));
   });

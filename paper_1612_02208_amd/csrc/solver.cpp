@@ -723,6 +723,9 @@ class Solver final : public SolverBase {
     require(o.max_it >= 1, "max_it must be >= 1");
     require(std::isfinite(o.rtol) && o.rtol > 0.0, "rtol must be finite and > 0");
     ensure_outer(o.restart);
+    // the adjoint system uses the transposed operator path; L_IB is
+    // symmetric, so the same V-cycle preconditions it
+    const bool trans = o.transpose != 0;
     const int N = d_.N;
     const size_t n = 3 * (size_t)N * N;
     const int nblk = dots_blocks(n);
@@ -764,7 +767,7 @@ class Solver final : public SolverBase {
     double est = bnorm;
     while (its < o.max_it) {
       double* V0 = Vo_.p;
-      op<double>(L_, x, V0, bp_.p, false, Fd_.p, s);
+      op<double>(L_, x, V0, bp_.p, trans, Fd_.p, s);
       const double beta = norm(V0, n, s);
       if (!std::isfinite(beta)) throw Error(IBMG_ERR_NONFINITE, "residual is not finite");
       est = beta;
@@ -779,7 +782,7 @@ class Solver final : public SolverBase {
         double* t = Vo_.p + (size_t)(k + 1) * n;
         vcycle(vk, zk, s);
         ++vcycles;
-        op<double>(L_, zk, t, nullptr, false, Fd_.p, s);
+        op<double>(L_, zk, t, nullptr, trans, Fd_.p, s);
         double* hcol = Ho_.p + (size_t)k * ldh;
         orthogonalise<double>(Vo_.p, k + 1, n, t, hcol, opart_.p, opart_.p + kPartStride, nblk, s);
         launch_scale_red<double>(t, t, n, opart_.p, nblk, hcol + k + 1, s);
@@ -797,7 +800,7 @@ class Solver final : public SolverBase {
       if (converged) break;
     }
     project(x, s);
-    op<double>(L_, x, rr_.p, bp_.p, false, Fd_.p, s);
+    op<double>(L_, x, rr_.p, bp_.p, trans, Fd_.p, s);
     const double tr = norm(rr_.p, n, s);
     if (info) {
       info->iters = its;

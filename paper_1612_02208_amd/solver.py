@@ -172,13 +172,15 @@ class StokesIB:
         self._check(self.lib.ibmg_vcycle(self.h, _ptr(r), _ptr(z), _stream()))
         return z
 
-    def solve(self, b, rtol=1e-8, restart=30, max_it=100, x0=None, out=None, history=128):
+    def solve(self, b, rtol=1e-8, restart=30, max_it=100, x0=None, out=None, history=128,
+              transpose=False):
         _dev_vec(b, self.n(), "b")
         if x0 is not None:
             x = x0.clone() if out is None else out.copy_(x0)
         else:
             x = self._new(self.n()) if out is None else out
-        o = _lib.SolveOpts(float(rtol), int(restart), int(max_it), 1 if x0 is not None else 0)
+        o = _lib.SolveOpts(float(rtol), int(restart), int(max_it), 1 if x0 is not None else 0,
+                           1 if transpose else 0)
         hist = (ctypes.c_double * history)()
         info = _lib.SolveInfo()
         info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
