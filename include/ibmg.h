@@ -174,6 +174,13 @@ ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream stre
  * unique boxes, colours_u, colours_p] and returns the count in *written. */
 ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written);
 
+/* Schur-complement smoother data of level l >= 1 (Sec. 3.3.2): lam[0], lam[1]
+ * = the Chebyshev bounds' Ritz values for SGS(A_IB)^{-1} A_IB and for
+ * SGS(-M^)^{-1}(-D A~^{-1} G); colours[0], colours[1] = Gauss-Seidel colours
+ * of the velocity rows and of the cells.  IBMG_ERR_ARG if the handle uses the
+ * Schwarz smoother. */
+ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32_t* colours);
+
 #ifdef __cplusplus
 }
 #endif

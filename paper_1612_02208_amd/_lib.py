@@ -48,7 +48,7 @@ EXPORTS = [
     "ibmg_create", "ibmg_destroy", "ibmg_last_error", "ibmg_levels", "ibmg_level_n",
     "ibmg_apply_A_IB", "ibmg_apply_A_IB_T", "ibmg_spread", "ibmg_interp", "ibmg_restrict",
     "ibmg_prolong_add", "ibmg_smoother_apply", "ibmg_smooth", "ibmg_coarse_solve", "ibmg_vcycle",
-    "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats",
+    "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats", "ibmg_sc_info",
 ]
 
 _lib = None
@@ -79,6 +79,7 @@ def load():
     lib.ibmg_spring_gradient.argtypes = [vp, vp, vp, vp, vp]
     lib.ibmg_set_kappa.argtypes = [vp, _dp, vp]
     lib.ibmg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
+    lib.ibmg_sc_info.argtypes = [vp, ctypes.c_int32, _dp, _ip]
     for name in EXPORTS:
         if name != "ibmg_last_error":
             getattr(lib, name).restype = ctypes.c_int

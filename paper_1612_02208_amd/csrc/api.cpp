@@ -212,4 +212,15 @@ ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t*
   return IBMG_OK;
 }
 
+ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32_t* colours) {
+  if (!h || !h->s) return IBMG_ERR_STATE;
+  if (!lam || !colours) return IBMG_ERR_ARG;
+  try {
+    h->s->sc_info(level, lam, colours);
+    return IBMG_OK;
+  } catch (const ibmg::Error& e) {
+    return (ibmg_status)e.code;
+  }
+}
+
 }  // extern "C"

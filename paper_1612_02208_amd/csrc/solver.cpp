@@ -9,6 +9,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "sc_smoother.hpp"
 #include "solver.hpp"
 
 namespace ibmg {
@@ -112,6 +113,8 @@ struct Level {
   // work vectors
   DBuf<T> w, b, r, t, V, Z, F;
   DBuf<double> H, scal, part;
+  // Schur-complement smoother
+  std::unique_ptr<ScLevel<T>> sc;
 };
 
 template <typename T>
@@ -203,6 +206,7 @@ class Solver final : public SolverBase {
       }
       lev.use_spmv = std::max(lev.f[0].max_list, lev.f[1].max_list) > kSpmvListThreshold;
       if (l >= 1 && d_.smoother == IBMG_RAS) classify_boxes(lev);
+      if (l >= 1 && d_.smoother == IBMG_SC) sc_structure(lev, s);
     }
   }
 
@@ -371,6 +375,132 @@ class Solver final : public SolverBase {
     build_coarse(s);
     if (d_.smoother == IBMG_RAS)
       for (int l = 1; l <= L_; ++l) build_boxes(levels_[l], s);
+    if (d_.smoother == IBMG_SC)
+      for (int l = 1; l <= L_; ++l) sc_numeric(levels_[l], s);
+  }
+
+  // ------------------------------------------------ Schur-complement set-up
+  void sc_structure(Level<T>& lev, hipStream_t s) {
+    const int N = lev.N, NN = N * N;
+    lev.sc.reset(new ScLevel<T>());
+    ScLevel<T>& sc = *lev.sc;
+    sc.N = N;
+    sc.its = d_.cheb_its;
+    sc.rho_zero = d_.rho == 0.0;
+    // velocity colours: five-point stencil plus IB rows, per component
+    std::vector<int> colv(2 * (size_t)NN);
+    for (int c = 0; c < 2; ++c) {
+      const CompFoot& f = lev.f[c];
+      std::vector<int> cc = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
+        const int i = r % N, j = r / N;
+        nb.push_back(j * N + (i + 1) % N);
+        nb.push_back(j * N + (i + N - 1) % N);
+        nb.push_back(((j + 1) % N) * N + i);
+        nb.push_back(((j + N - 1) % N) * N + i);
+        for (int k = f.tptr[r]; k < f.tptr[r + 1]; ++k) nb.push_back(f.tcol[k]);
+      });
+      std::copy(cc.begin(), cc.end(), colv.begin() + (size_t)c * NN);
+    }
+    sc.colu.build(colv, s);
+    std::vector<int> colp = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
+      const int i = r % N, j = r / N;
+      nb.push_back(j * N + (i + 1) % N);
+      nb.push_back(j * N + (i + N - 1) % N);
+      nb.push_back(((j + 1) % N) * N + i);
+      nb.push_back(((j + N - 1) % N) * N + i);
+    });
+    sc.colp.build(colp, s);
+    const size_t n2 = 2 * (size_t)NN, n1 = NN;
+    sc.diag.alloc(n2);
+    sc.dinv.alloc(n2);
+    sc.mdiag.alloc(n1);
+    for (DBuf<T>* b : {&sc.yu, &sc.ga, &sc.gx, &sc.ad, &sc.ar, &sc.at, &sc.as}) b->alloc(n2);
+    for (DBuf<T>* b : {&sc.s, &sc.md, &sc.mr, &sc.mt, &sc.ms, &sc.ones}) b->alloc(n1);
+    sc.part.alloc(1024);
+    launch_fill<T>(sc.ones.p, T(1), n1, s);
+  }
+
+  // Largest Ritz value of ten Arnoldi steps (classical Gram-Schmidt twice)
+  // of op from v0 (overwritten).
+  template <typename OP>
+  double arnoldi_lambda(size_t n, T* v0, OP op, hipStream_t s) {
+    constexpr int steps = 10;
+    DBuf<T> V((size_t)(steps + 1) * n);
+    DBuf<double> part(2 * kPartStride), hd(64);
+    const int nblk = dots_blocks(n, 256);
+    std::vector<double> H((steps + 1) * steps, 0.0), h(steps + 1), h2(steps + 1);
+    auto norm_of = [&](const T* x) {
+      launch_dots<T>(x, 1, n, x, n, part.p, nblk, s);
+      launch_dots_finish(part.p, 1, nblk, hd.p, nullptr, 2, s);
+      double v;
+      IBMG_HIP(hipMemcpyAsync(&v, hd.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      IBMG_HIP(hipStreamSynchronize(s));
+      return v;
+    };
+    const double b0 = norm_of(v0);
+    launch_scale<T>(v0, V.p, hd.p, n, s);
+    int k = steps;
+    for (int j = 0; j < steps; ++j) {
+      T* w = V.p + (size_t)(j + 1) * n;
+      op(V.p + (size_t)j * n, w);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots<T>(V.p, j + 1, n, w, n, part.p, nblk, s);
+        launch_dots_finish(part.p, j + 1, nblk, hd.p, nullptr, 0, s);
+        launch_update<T>(w, V.p, j + 1, n, hd.p, -1.0, n, s);
+        IBMG_HIP(hipMemcpyAsync(h2.data(), hd.p, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        IBMG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) H[i * steps + j] += h2[i];
+      }
+      const double hn = norm_of(w);
+      H[(j + 1) * steps + j] = hn;
+      if (hn == 0.0) {
+        k = j + 1;
+        break;
+      }
+      launch_scale<T>(w, w, hd.p, n, s);
+    }
+    (void)b0;
+    std::vector<double> Hk((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Hk[(size_t)i * k + j] = H[i * steps + j];
+    return hessenberg_max_real_eig(Hk, k);
+  }
+
+  void sc_numeric(Level<T>& lev, hipStream_t s) {
+    ScLevel<T>& sc = *lev.sc;
+    const int N = lev.N, NN = N * N;
+    const size_t n2 = 2 * (size_t)NN, n1 = NN;
+    sc.c = coef<T>(lev);
+    sc.tu = csr<T>(lev.f[0]);
+    sc.tv = csr<T>(lev.f[1]);
+    sc.ih2 = (T)((double)N * N);
+    launch_sc_diag<T>(N, sc.c, sc.tu, sc.tv, sc.ih2, sc.diag.p, sc.dinv.p, sc.mdiag.p, s);
+    const int nb1 = dots_blocks(n1, 256);
+    // lam for SGS(A_IB)^{-1} A_IB, start vector with the velocity means
+    // removed when rho = 0
+    DBuf<T> v0(n2);
+    launch_weyl<T>(v0.p, n2, s);
+    if (sc.rho_zero)
+      for (int c = 0; c < 2; ++c) {
+        launch_dots<T>(sc.ones.p, 1, n1, v0.p + (size_t)c * n1, n1, sc.part.p, nb1, s);
+        launch_sub_mean<T>(v0.p + (size_t)c * n1, n1, sc.part.p, nb1, s);
+      }
+    sc.lamA = arnoldi_lambda(n2, v0.p, [&](const T* x, T* y) {
+      launch_aib_apply<T>(x, sc.at.p, N, sc.c, sc.tu, sc.tv, s);
+      sc.sgs_a(sc.at.p, y, s);
+    }, s);
+    ScLevel<T>::cheb_coefs(sc.lamA, sc.its, &sc.a_theta_inv, sc.a_c1, sc.a_c2);
+    // lam for SGS(-M^)^{-1} (-D A~^{-1} G), mean-free start vector
+    DBuf<T> q0(n1);
+    launch_weyl<T>(q0.p, n1, s);
+    launch_dots<T>(sc.ones.p, 1, n1, q0.p, n1, sc.part.p, nb1, s);
+    launch_sub_mean<T>(q0.p, n1, sc.part.p, nb1, s);
+    sc.lamM = arnoldi_lambda(n1, q0.p, [&](const T* x, T* y) {
+      sc.schur_op(x, sc.mt.p, s);
+      sc.sgs_m(sc.mt.p, y, s);
+    }, s);
+    ScLevel<T>::cheb_coefs(sc.lamM, sc.its, &sc.m_theta_inv, sc.m_c1, sc.m_c2);
+    IBMG_HIP(hipStreamSynchronize(s));
   }
 
   void build_coarse(hipStream_t s) {
@@ -506,6 +636,10 @@ class Solver final : public SolverBase {
   // ------------------------------------------------------- V-cycle pieces
   void basic_smoother(int l, const T* v, T* z, hipStream_t s) {
     Level<T>& lev = levels_[l];
+    if (lev.sc) {
+      lev.sc->apply(v, z, s);
+      return;
+    }
     launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.d_ib.p, lev.n_ib,
                         lev.inv.p + (size_t)lev.n_ib * box_stride(lev), lev.d_int.p,
                         (int)lev.int_list.size(), lev.d_loc.p, lev.int_part.p, s);
@@ -833,6 +967,16 @@ class Solver final : public SolverBase {
     IBMG_HIP(hipStreamSynchronize(s));
   }
 
+  void sc_info(int level, double* lam, int32_t* colours) const override {
+    require(level >= 1 && level <= L_, "level out of range");
+    const Level<T>& lev = levels_[level];
+    require(lev.sc != nullptr, "the handle does not use the Schur-complement smoother");
+    lam[0] = lev.sc->lamA;
+    lam[1] = lev.sc->lamM;
+    colours[0] = lev.sc->colu.ncol;
+    colours[1] = lev.sc->colp.ncol;
+  }
+
   std::vector<int64_t> stats() const override {
     std::vector<int64_t> v;
     v.push_back(L_ + 1);
@@ -878,7 +1022,6 @@ class Solver final : public SolverBase {
 
 SolverBase* make_solver(const ibmg_desc& d, hipStream_t s) {
   validate_desc(d);
-  require(d.smoother == IBMG_RAS, "the Schur-complement smoother is not built into this library");
   if (d.precision == IBMG_FP32_SMOOTHER) return new Solver<float>(d, s);
   return new Solver<double>(d, s);
 }

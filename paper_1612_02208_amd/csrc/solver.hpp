@@ -37,6 +37,7 @@ struct SolverBase {
   virtual void spring_gradient(const double* w, const double* lam, double* out, hipStream_t s) = 0;
   virtual void set_kappa(const double* kappa, hipStream_t s) = 0;
   virtual std::vector<int64_t> stats() const = 0;
+  virtual void sc_info(int level, double* lam, int32_t* colours) const = 0;
 };
 
 SolverBase* make_solver(const ibmg_desc& d, hipStream_t s);

@@ -208,6 +208,14 @@ class StokesIB:
         self._check(self.lib.ibmg_set_kappa(self.h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             _stream()))
 
+    def sc_info(self, level):
+        """Schur-complement smoother data of a level: Ritz-value bounds and
+        Gauss-Seidel colour counts."""
+        lam = (ctypes.c_double * 2)()
+        col = (ctypes.c_int32 * 2)()
+        self._check(self.lib.ibmg_sc_info(self.h, level % self.n_levels, lam, col))
+        return dict(lam_A=lam[0], lam_M=lam[1], colours_u=col[0], colours_p=col[1])
+
     def stats(self):
         buf = (ctypes.c_int64 * 256)()
         wr = ctypes.c_int32()

@@ -59,7 +59,11 @@ def _cases():
     # matrix-core path), 2 tiles of 32 boxes with a ragged second tile
     Xs, Ss = W.membrane(40, 0.05, centre=(0.31, 0.62))
     c5 = W.Workload("small_64", 64, 8, 1.0, 0.1, 1e-3, Xs, Ss, np.full(len(Ss), 3e2), box=8, overlap=2)
-    return [c1, c2, c3, c4, c5]
+    # Schur-complement smoother (Stokes membrane; annulus at nonzero Reynolds)
+    c6 = W.plain_32(smoother="sc")
+    c6.name = "plain_32_sc"
+    c7 = W.Workload("annulus_64_sc", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4), smoother="sc")
+    return [c1, c2, c3, c4, c5, c6, c7]
 
 
 CASES = _cases()
@@ -193,3 +197,17 @@ def test_spring_gradient(pair):
     lam = rng.uniform(-1, 1, n)
     g = host(G.spring_gradient(dev(w), dev(lam)))
     assert rel(g, spring_gradient(wl, w, lam)) < OPS_TOL
+
+
+def test_schur_setup_matches_oracle(pair):
+    """Colour counts are equal and the Chebyshev bounds' Ritz values agree."""
+    wl, P, G = pair
+    if wl.smoother != "sc":
+        pytest.skip("Schwarz smoother")
+    for l in range(1, len(P.levels)):
+        sm = P.mg.smoothers[l]
+        info = G.sc_info(l)
+        assert info["colours_u"] == int(sm.col_u.max()) + 1
+        assert info["colours_p"] == int(sm.col_p.max()) + 1
+        assert abs(info["lam_A"] - sm.lam_A) <= 1e-10 * abs(sm.lam_A)
+        assert abs(info["lam_M"] - sm.lam_M) <= 1e-10 * abs(sm.lam_M)
