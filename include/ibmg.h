@@ -169,9 +169,10 @@ ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* 
  * level's IB operator and smoother data.  Synchronises ``stream``. */
 ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream stream);
 
-/* Setup statistics: IB-touched boxes per level (RAS), colours (SC), etc.
- * Writes up to cap int64 values: [levels, then per level: n, boxes,
- * unique boxes, colours_u, colours_p] and returns the count in *written. */
+/* Setup statistics.  Writes up to cap int64 values: [levels, then per
+ * level: n, boxes, boxes with their own inverse (+1 for the shared interior
+ * one), IB-touched boxes, entries of the explicit IB rows] and returns the
+ * full count in *written. */
 ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written);
 
 /* Schur-complement smoother data of level l >= 1 (Sec. 3.3.2): lam[0], lam[1]
@@ -180,6 +181,45 @@ ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t*
  * of the velocity rows and of the cells.  IBMG_ERR_ARG if the handle uses the
  * Schwarz smoother. */
 ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32_t* colours);
+
+/* ------------------------------------------------------------------------
+ * Batched form: nsys independent systems, each described by its own
+ * ibmg_desc (grid size N, structure, stiffness), solved together.  All
+ * systems must share coarse_N, rho, mu, dt, box, overlap, nu1, nu2 and
+ * precision, and use the Schwarz smoother (IBMG_ERR_ARG otherwise).  The
+ * V-cycle (Alg. 1) runs on every system in lockstep by level: each smoother
+ * sweep is one persistent launch over all (system, box) items, tuned at
+ * creation by timing the candidate tile widths and grid sizes; the V-cycle
+ * is replayed from a HIP graph.  Vectors are passed as host arrays of nsys
+ * device pointers in the order of descs, system i's vector holding 3 N_i^2
+ * doubles in the single-system layout.  Single-system calls on a batch
+ * handle (and batch calls on a single handle) return IBMG_ERR_STATE.
+ * ---------------------------------------------------------------------- */
+ibmg_status ibmg_batch_create(int32_t nsys, const ibmg_desc* descs, ibmg_stream stream,
+                              ibmg_handle** out);
+
+/* Number of systems of a batch handle. */
+ibmg_status ibmg_batch_size(const ibmg_handle* h, int32_t* nsys);
+
+/* z_i = MG(0, r_i) for every system (Alg. 1, zero initial guess). */
+ibmg_status ibmg_batch_vcycle(ibmg_handle* h, const double* const* r, double* const* z,
+                              ibmg_stream stream);
+
+/* FGMRES(restart) on every system, right-preconditioned by the batched
+ * V-cycle, each system stopping at its own tolerance (as ibmg_fgmres_solve;
+ * opts->transpose must be 0).  The Krylov iterations run in lockstep with
+ * one host read of all residual estimates per iteration; converged systems
+ * stop doing work.  infos (nullable) receives one record per system, in the
+ * order of descs.  Synchronises ``stream``.  Returns IBMG_NOT_CONVERGED if
+ * any system reaches max_it. */
+ibmg_status ibmg_batch_fgmres_solve(ibmg_handle* h, const double* const* b, double* const* x,
+                                    const ibmg_solve_opts* opts, ibmg_solve_info* infos,
+                                    ibmg_stream stream);
+
+/* Batch statistics: [nsys, levels, then per level: n, systems on the level,
+ * interior boxes, IB boxes, explicit IB rows, chosen tile width, chosen
+ * persistent grid, tuned sweep time in ns]; count in *written. */
+ibmg_status ibmg_batch_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written);
 
 #ifdef __cplusplus
 }

@@ -8,11 +8,11 @@ package does not load the library; constructing ``StokesIB`` does, and fails
 loudly when it is missing.
 """
 
-__all__ = ["StokesIB", "IbmgError"]
+__all__ = ["StokesIB", "StokesIBBatch", "IbmgError"]
 
 
 def __getattr__(name):
-    if name in ("StokesIB", "IbmgError"):
+    if name in ("StokesIB", "StokesIBBatch", "IbmgError"):
         from . import solver
         return getattr(solver, name)
     raise AttributeError(name)

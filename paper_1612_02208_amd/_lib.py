@@ -49,6 +49,8 @@ EXPORTS = [
     "ibmg_apply_A_IB", "ibmg_apply_A_IB_T", "ibmg_spread", "ibmg_interp", "ibmg_restrict",
     "ibmg_prolong_add", "ibmg_smoother_apply", "ibmg_smooth", "ibmg_coarse_solve", "ibmg_vcycle",
     "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats", "ibmg_sc_info",
+    "ibmg_batch_create", "ibmg_batch_size", "ibmg_batch_vcycle", "ibmg_batch_fgmres_solve",
+    "ibmg_batch_stats",
 ]
 
 _lib = None
@@ -80,6 +82,12 @@ def load():
     lib.ibmg_set_kappa.argtypes = [vp, _dp, vp]
     lib.ibmg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
     lib.ibmg_sc_info.argtypes = [vp, ctypes.c_int32, _dp, _ip]
+    lib.ibmg_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+    lib.ibmg_batch_size.argtypes = [vp, _ip]
+    vpp = ctypes.POINTER(vp)
+    lib.ibmg_batch_vcycle.argtypes = [vp, vpp, vpp, vp]
+    lib.ibmg_batch_fgmres_solve.argtypes = [vp, vpp, vpp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.ibmg_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
     for name in EXPORTS:
         if name != "ibmg_last_error":
             getattr(lib, name).restype = ctypes.c_int

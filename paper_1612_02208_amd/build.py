@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libibmg.so")
 ARCH = os.environ.get("IBMG_ARCH", "gfx950")
 
 SOURCES = ["grid_kernels.hip", "ib_kernels.hip", "dense_kernels.hip", "krylov_kernels.hip",
-           "sc_kernels.hip", "sc_setup.cpp", "solver.cpp", "api.cpp"]
+           "sc_kernels.hip", "sc_setup.cpp", "solver.cpp", "batch.cpp", "api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

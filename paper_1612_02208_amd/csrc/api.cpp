@@ -6,7 +6,8 @@
 #include "solver.hpp"
 
 struct ibmg_handle {
-  ibmg::SolverBase* s = nullptr;
+  ibmg::SolverBase* s = nullptr;  // single system
+  ibmg::BatchBase* b = nullptr;   // batched systems
   std::string err;
 };
 
@@ -19,6 +20,20 @@ ibmg_status guarded(ibmg_handle* h, F&& f) {
   if (!h || !h->s) return IBMG_ERR_STATE;
   try {
     return (ibmg_status)f(h->s);
+  } catch (const ibmg::Error& e) {
+    h->err = e.what();
+    return (ibmg_status)e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return IBMG_ERR_HIP;
+  }
+}
+
+template <typename F>
+ibmg_status guarded_b(ibmg_handle* h, F&& f) {
+  if (!h || !h->b) return IBMG_ERR_STATE;
+  try {
+    return (ibmg_status)f(h->b);
   } catch (const ibmg::Error& e) {
     h->err = e.what();
     return (ibmg_status)e.code;
@@ -67,7 +82,67 @@ ibmg_status ibmg_create(const ibmg_desc* desc, ibmg_stream stream, ibmg_handle**
 ibmg_status ibmg_destroy(ibmg_handle* h) {
   if (!h) return IBMG_ERR_STATE;
   delete h->s;
+  delete h->b;
   delete h;
+  return IBMG_OK;
+}
+
+ibmg_status ibmg_batch_create(int32_t nsys, const ibmg_desc* descs, ibmg_stream stream, ibmg_handle** out) {
+  if (!out) return IBMG_ERR_ARG;
+  *out = nullptr;
+  if (!descs || nsys < 1) {
+    g_create_error = "descs is NULL or nsys < 1";
+    return IBMG_ERR_ARG;
+  }
+  try {
+    auto* h = new ibmg_handle();
+    try {
+      h->b = ibmg::make_batch(nsys, descs, S(stream));
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return IBMG_OK;
+  } catch (const ibmg::Error& e) {
+    g_create_error = e.what();
+    return (ibmg_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return IBMG_ERR_HIP;
+  }
+}
+
+ibmg_status ibmg_batch_size(const ibmg_handle* h, int32_t* nsys) {
+  if (!h || !h->b) return IBMG_ERR_STATE;
+  if (!nsys) return IBMG_ERR_ARG;
+  *nsys = h->b->nsys();
+  return IBMG_OK;
+}
+
+ibmg_status ibmg_batch_vcycle(ibmg_handle* h, const double* const* r, double* const* z, ibmg_stream st) {
+  return guarded_b(h, [&](ibmg::BatchBase* b) {
+    b->vcycle(r, z, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_batch_fgmres_solve(ibmg_handle* h, const double* const* b, double* const* x,
+                                    const ibmg_solve_opts* opts, ibmg_solve_info* infos, ibmg_stream st) {
+  return guarded_b(h, [&](ibmg::BatchBase* bs) {
+    ibmg_solve_opts o{1e-8, 30, 100, 0, 0};
+    if (opts) o = *opts;
+    return bs->fgmres(b, x, o, infos, S(st));
+  });
+}
+
+ibmg_status ibmg_batch_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written) {
+  if (!h || !h->b) return IBMG_ERR_STATE;
+  if (!written || (cap > 0 && !out)) return IBMG_ERR_ARG;
+  std::vector<int64_t> v = h->b->stats();
+  int n = 0;
+  for (; n < (int)v.size() && n < cap; ++n) out[n] = v[n];
+  *written = (int32_t)v.size();
   return IBMG_OK;
 }
 

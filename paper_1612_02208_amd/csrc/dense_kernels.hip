@@ -328,17 +328,14 @@ struct Vec16<float> {
   static constexpr int n = 4;
 };
 
+// One (box, 64-row chunk) item: Mc is the chunk of the box's owned-row
+// inverse, r and z the box's system vectors; x holds nloc values, part 256.
 template <typename T>
-__global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
-                                                const T* __restrict__ inv, const int* __restrict__ boxes) {
+__device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
+                                             const T* __restrict__ Mc, int pid, int chunk, T* x, T* part) {
   using V = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   constexpr int LPC = 64 / VEC;  // lanes per column
-  extern __shared__ char smem_raw[];
-  T* x = reinterpret_cast<T*>(smem_raw);
-  T* part = x + ((g.nloc + 3) & ~3);
-  const int slot = blockIdx.x;
-  const int pid = boxes[slot];
   for (int k = threadIdx.x; k < g.nloc; k += blockDim.x) x[k] = r[box_glob(g, pid, k)];
   __syncthreads();
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -346,7 +343,7 @@ __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __re
   const int rl = (lane % LPC) * VEC;    // first of this lane's VEC rows
   const int per = ((g.nloc + 4 * VEC - 1) / (4 * VEC)) * VEC;
   const int j0 = q * per, j1 = j0 + per < g.nloc ? j0 + per : g.nloc;
-  const T* Mc = inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64 + rl;
+  Mc += rl;
   T acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0;
@@ -381,9 +378,20 @@ __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __re
     for (int v = 0; v < VEC; ++v) part[q * 64 + rl + v] = acc[v];
   __syncthreads();
   if (q == 0) {
-    const int row = blockIdx.y * 64 + lane;
+    const int row = chunk * 64 + lane;
     if (row < g.nown) z[own_glob(g, pid, row)] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
+                                                const T* __restrict__ inv, const int* __restrict__ boxes) {
+  extern __shared__ char smem_raw[];
+  T* x = reinterpret_cast<T*>(smem_raw);
+  T* part = x + ((g.nloc + 3) & ~3);
+  const int slot = blockIdx.x;
+  ras_ib_chunk<T>(r, z, g, inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64, boxes[slot], blockIdx.y, x,
+                  part);
 }
 
 // ---------------------------------------------------------------------------
@@ -418,34 +426,52 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
 };
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T* __restrict__ z,
-                                                      BoxGeom g, const T* __restrict__ M,
-                                                      const int* __restrict__ boxes, int nlist,
-                                                      const int* __restrict__ loc_tab,
-                                                      T* __restrict__ part, int ksplit) {
-  constexpr int KC = 64, TB = 32, GPT = KC * TB / 256, AS = KC / 4;
+// Shared memory of one interior tile: the gathered residual columns and the
+// tile's box table.
+template <typename T, int TB>
+struct IntTileSmem {
+  T Xs[64][TB + 1];
+  size_t base[TB];   // system offset of each box's vectors
+  int bid[TB], bx0[TB], by0[TB];
+};
+
+// One interior tile (boxes ents[tile * TB ..], 64-row chunk, reduction slice
+// kslice of ksplit): box entry e = s * nbox + box id, system s at r + s
+// sys_n; boxes of inactive systems are left out.
+template <typename T, int TB>
+__device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
+                                             size_t sys_n, int nbox, const T* __restrict__ M,
+                                             const int* __restrict__ ents, int nlist, int tile, int chunk,
+                                             int kslice, int ksplit, const int* __restrict__ loc_tab,
+                                             const int* __restrict__ active, T* __restrict__ part,
+                                             IntTileSmem<T, TB>& sm) {
+  constexpr int KC = 64, GPT = KC * TB / 256, AS = KC / 4;
   using acc_t = typename Mfma<T>::acc_t;
-  __shared__ T Xs[KC][TB + 1];
-  __shared__ int bx0[TB], by0[TB], bid[TB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int bt = blockIdx.x * TB;
+  const int bt = tile * TB;
   const int N = g.N;
   const size_t nn = (size_t)N * N;
   if (tid < TB) {
     const int b = bt + tid;
-    const int pid = b < nlist ? boxes[b] : -1;
-    bid[tid] = pid;
-    bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
-    by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
+    int pid = -1, sy = 0;
+    if (b < nlist) {
+      const int e = ents[b];
+      sy = e / nbox;
+      pid = e - sy * nbox;
+      if (active && !active[sy]) pid = -1;
+    }
+    sm.bid[tid] = pid;
+    sm.base[tid] = (size_t)sy * sys_n;
+    sm.bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
+    sm.by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
   }
   __syncthreads();
-  // this block's slice of the reduction index: chunks [c0, c1) of KC columns
+  // this item's slice of the reduction index: chunks [c0, c1) of KC columns
   const int nchunk = (g.nloc + KC - 1) / KC;
   const int per = (nchunk + ksplit - 1) / ksplit;
-  const int c0 = blockIdx.z * per;
+  const int c0 = kslice * per;
   const int c1 = c0 + per < nchunk ? c0 + per : nchunk;
-  const T* Mrow = M + (size_t)blockIdx.y * g.nloc * 64 + 16 * wave + (lane & 15);
+  const T* Mrow = M + (size_t)chunk * g.nloc * 64 + 16 * wave + (lane & 15);
   const int kq = lane >> 4, bl = lane & 15;
   acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   T gx[GPT], ga[AS];
@@ -457,12 +483,12 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
       const int k = t / TB, b = t % TB;
       const int jk = j0 + k;
       T val = 0;
-      if (jk < g.nloc && bid[b] >= 0) {
+      if (jk < g.nloc && sm.bid[b] >= 0) {
         const int code = loc_tab[jk];
-        int ii = (code & 0xfff) + bx0[b], jj = ((code >> 12) & 0xfff) + by0[b];
+        int ii = (code & 0xfff) + sm.bx0[b], jj = ((code >> 12) & 0xfff) + sm.by0[b];
         ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
         jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
-        val = r[(size_t)(code >> 24) * nn + (size_t)jj * N + ii];
+        val = r[sm.base[b] + (size_t)(code >> 24) * nn + (size_t)jj * N + ii];
       }
       gxo[u] = val;
     }
@@ -477,7 +503,7 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int t = tid + u * 256;
-      Xs[t / TB][t % TB] = gx[u];
+      sm.Xs[t / TB][t % TB] = gx[u];
     }
     __syncthreads();
     T a[AS];
@@ -486,25 +512,36 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
     if (c + 1 < c1) load_chunk(c + 1, gx, ga);   // in flight during the MFMAs below
 #pragma unroll
     for (int s = 0; s < AS; ++s) {
-      acc0 = Mfma<T>::mma(a[s], Xs[4 * s + kq][bl], acc0);
-      acc1 = Mfma<T>::mma(a[s], Xs[4 * s + kq][16 + bl], acc1);
+      acc0 = Mfma<T>::mma(a[s], sm.Xs[4 * s + kq][bl], acc0);
+      if (TB == 32) acc1 = Mfma<T>::mma(a[s], sm.Xs[4 * s + kq][16 + bl], acc1);
     }
     __syncthreads();
   }
   const int nown_pad = g.nch * 64;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int row = blockIdx.y * 64 + 16 * wave + Mfma<T>::row(kq, v);
+    const int row = chunk * 64 + 16 * wave + Mfma<T>::row(kq, v);
     if (row >= g.nown) continue;
     if (ksplit == 1) {
-      if (bid[bl] >= 0) z[own_glob(g, bid[bl], row)] = acc0[v];
-      if (bid[16 + bl] >= 0) z[own_glob(g, bid[16 + bl], row)] = acc1[v];
+      if (sm.bid[bl] >= 0) z[sm.base[bl] + own_glob(g, sm.bid[bl], row)] = acc0[v];
+      if (TB == 32 && sm.bid[16 + bl] >= 0) z[sm.base[16 + bl] + own_glob(g, sm.bid[16 + bl], row)] = acc1[v];
     } else {
-      T* pp = part + (size_t)blockIdx.z * nlist * nown_pad;
+      T* pp = part + (size_t)kslice * nlist * nown_pad;
       if (bt + bl < nlist) pp[(size_t)(bt + bl) * nown_pad + row] = acc0[v];
-      if (bt + 16 + bl < nlist) pp[(size_t)(bt + 16 + bl) * nown_pad + row] = acc1[v];
+      if (TB == 32 && bt + 16 + bl < nlist) pp[(size_t)(bt + 16 + bl) * nown_pad + row] = acc1[v];
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T* __restrict__ z,
+                                                      BoxGeom g, const T* __restrict__ M,
+                                                      const int* __restrict__ boxes, int nlist,
+                                                      const int* __restrict__ loc_tab,
+                                                      T* __restrict__ part, int ksplit) {
+  __shared__ IntTileSmem<T, 32> sm;
+  ras_int_tile<T, 32>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit,
+                      loc_tab, nullptr, part, sm);
 }
 
 // z[owned rows of interior box b] = sum over the reduction slices, in order.
@@ -554,6 +591,66 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
       IBMG_LAUNCH_CHECK();
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Batched RAS sweep: one persistent launch per sweep.  Items are interior
+// tiles x row chunks first (matrix cores, shared inverse), then (IB box, row
+// chunk) pairs (streamed own inverses); work-group w takes items w, w + grid,
+// ... so the grid size, not the item count, sets the launch.  Every item
+// writes disjoint owned rows, so the result does not depend on the order.
+// ---------------------------------------------------------------------------
+template <typename T, int TB>
+__global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
+                                                   size_t sys_n, int nbox, const T* __restrict__ M,
+                                                   const int* __restrict__ int_ents, int n_int,
+                                                   const int* __restrict__ ib_ents, const T* const* __restrict__ ib_inv,
+                                                   int n_ib, const int* __restrict__ loc_tab,
+                                                   const int* __restrict__ active) {
+  extern __shared__ char smem_raw[];
+  const int n_tiles = (n_int + TB - 1) / TB;
+  const int int_items = n_tiles * g.nch;
+  const int total = int_items + n_ib * g.nch;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    if (it < int_items) {
+      ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, it / g.nch, it % g.nch, 0, 1, loc_tab, active,
+                          nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw));
+    } else {
+      const int q = it - int_items, e = q / g.nch, c = q % g.nch;
+      const int ent = ib_ents[e], sy = ent / nbox;
+      if (active && !active[sy]) continue;
+      T* x = reinterpret_cast<T*>(smem_raw);
+      ras_ib_chunk<T>(r + (size_t)sy * sys_n, z + (size_t)sy * sys_n, g, ib_inv[e] + (size_t)c * g.nloc * 64,
+                      ent - sy * nbox, c, x, x + ((g.nloc + 3) & ~3));
+    }
+    __syncthreads();
+  }
+}
+
+int ras_batch_items(const BoxGeom& g, int n_int, int n_ib, int tb) {
+  return ((n_int + tb - 1) / tb) * g.nch + n_ib * g.nch;
+}
+
+template <typename T>
+void launch_ras_batch(const T* r, T* z, BoxGeom g, size_t sys_n, int nbox, const T* shared_inv,
+                      const int* int_ents, int n_int, const int* ib_ents, const T* const* ib_inv, int n_ib,
+                      const int* loc_tab, const int* active, RasBatchPlan plan, hipStream_t s) {
+  const int tb = plan.tb == 16 ? 16 : 32;
+  const int items = ras_batch_items(g, n_int, n_ib, tb);
+  if (items <= 0) return;
+  if (n_int > 0 && !shared_inv) throw Error(IBMG_ERR_ARG, "interior boxes without a shared inverse");
+  int grid = plan.grid > 0 ? plan.grid : items;
+  if (grid > items) grid = items;
+  size_t lds = ((((size_t)g.nloc + 3) & ~(size_t)3) + 256) * sizeof(T);
+  const size_t tile = tb == 16 ? sizeof(IntTileSmem<T, 16>) : sizeof(IntTileSmem<T, 32>);
+  if (tile > lds) lds = tile;
+  if (tb == 16)
+    hipLaunchKernelGGL((k_ras_batch<T, 16>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
+                       int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
+  else
+    hipLaunchKernelGGL((k_ras_batch<T, 32>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
+                       int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
+  IBMG_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -693,6 +790,10 @@ __global__ void k_coarse_apply(const double* __restrict__ inv, int n0, const T* 
                                T* __restrict__ z) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n0) return;
+  // batched: system blockIdx.y, inverses n0^2 and vectors n0 apart
+  inv += (size_t)blockIdx.y * n0 * n0;
+  r += (size_t)blockIdx.y * n0;
+  z += (size_t)blockIdx.y * n0;
   const double* row = inv + (size_t)i * n0;
   double a = 0.0;
   for (int j = 0; j < n0; ++j) a += row[j] * (double)r[j];
@@ -700,9 +801,15 @@ __global__ void k_coarse_apply(const double* __restrict__ inv, int n0, const T* 
 }
 
 template <typename T>
-void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cdiv(n0, 64)), dim3(64), 0, s, inv, n0, r, z);
+void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cdiv(n0, 64), nsys), dim3(64), 0, s, inv, n0, r, z);
   IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_t s) {
+  launch_coarse_apply_batch<T>(inv, n0, r, z, 1, s);
 }
 
 template void launch_extract_owned<double>(const double*, int, BoxGeom, double*, hipStream_t);
@@ -715,5 +822,13 @@ template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float
                                       hipStream_t);
 template void launch_coarse_apply<double>(const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_apply<float>(const double*, int, const float*, float*, hipStream_t);
+template void launch_coarse_apply_batch<double>(const double*, int, const double*, double*, int, hipStream_t);
+template void launch_coarse_apply_batch<float>(const double*, int, const float*, float*, int, hipStream_t);
+template void launch_ras_batch<double>(const double*, double*, BoxGeom, size_t, int, const double*, const int*,
+                                       int, const int*, const double* const*, int, const int*, const int*,
+                                       RasBatchPlan, hipStream_t);
+template void launch_ras_batch<float>(const float*, float*, BoxGeom, size_t, int, const float*, const int*, int,
+                                      const int*, const float* const*, int, const int*, const int*, RasBatchPlan,
+                                      hipStream_t);
 
 }  // namespace ibmg

@@ -22,11 +22,16 @@ template <typename T, bool TRANS, bool RESID, int IBM>
 __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __restrict__ y,
                                                const T* __restrict__ b, const T* __restrict__ F,
                                                const T* __restrict__ Gib, FootView<T> fx,
-                                               FootView<T> fy, int N, int M, StokesCoef<T> c) {
+                                               FootView<T> fy, int N, int M, StokesCoef<T> c,
+                                               size_t bs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= N || j >= N) return;
   const size_t n = (size_t)N * N;
+  // batched launches: system blockIdx.z, systems bs apart
+  w += blockIdx.z * bs;
+  y += blockIdx.z * bs;
+  if (RESID) b += blockIdx.z * bs;
   const T* u = w;
   const T* v = w + n;
   const T* p = w + 2 * n;
@@ -86,19 +91,19 @@ __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __res
 template <typename T, int IBM>
 static void launch_apply_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
                            FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose,
-                           hipStream_t s) {
+                           hipStream_t s, int nsys = 1, size_t bs = 0) {
   dim3 blk(64, 4);
-  dim3 grd((N + 63) / 64, (N + 3) / 4);
+  dim3 grd((N + 63) / 64, (N + 3) / 4, nsys);
   if (b) {
     if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, true, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
     else
-      hipLaunchKernelGGL((k_apply<T, false, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, false, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
   } else {
     if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, true, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
     else
-      hipLaunchKernelGGL((k_apply<T, false, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c);
+      hipLaunchKernelGGL((k_apply<T, false, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
   }
   IBMG_LAUNCH_CHECK();
 }
@@ -116,6 +121,40 @@ void launch_apply(const T* w, T* y, const T* b, const T* F, const T* G, FootView
     launch_apply_m<T, 0>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
 }
 
+// Stencil part of L_IB (or the residual) for nsys systems of one grid size,
+// bs apart; the IB rows are added by launch_ib_rows.
+template <typename T>
+void launch_apply_batch(const T* w, T* y, const T* b, int N, StokesCoef<T> c, int nsys, size_t bs,
+                        hipStream_t s) {
+  if (nsys <= 0) return;
+  FootView<T> none{nullptr, nullptr, nullptr, nullptr};
+  launch_apply_m<T, 0>(w, y, b, nullptr, nullptr, none, none, N, 0, c, false, s, nsys, bs);
+}
+
+// Explicit IB rows: one wave per listed row, lanes over its entries, the
+// wave's sum formed by shuffles in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_rows(const T* __restrict__ x, T* __restrict__ y,
+                                                 const int* __restrict__ rows, const int* __restrict__ ptr,
+                                                 const int* __restrict__ col, const T* __restrict__ val,
+                                                 int nrows, T sign) {
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (q >= nrows) return;
+  T a = 0;
+  for (int k = ptr[q] + lane; k < ptr[q + 1]; k += 64) a += val[k] * x[col[k]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if (lane == 0) y[rows[q]] += sign * a;
+}
+
+template <typename T>
+void launch_ib_rows(const T* x, T* y, const int* rows, const int* ptr, const int* col, const T* val,
+                    int nrows, T sign, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL((k_ib_rows<T>), dim3(cdiv(nrows, 4)), dim3(256), 0, s, x, y, rows, ptr, col, val, nrows, sign);
+  IBMG_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------
 // Restriction (Sec. 3.2): R_u = P_u^T / 4 (adjoint of the Raviart-Thomas
 // prolongation), R_p = mean of the four fine cells.
@@ -127,6 +166,8 @@ __global__ void k_restrict(const T* __restrict__ f, T* __restrict__ cz, int Nc) 
   if (i >= Nc || j >= Nc) return;
   const int Nf = 2 * Nc;
   const size_t nf = (size_t)Nf * Nf, nc = (size_t)Nc * Nc;
+  f += blockIdx.z * 3 * nf;
+  cz += blockIdx.z * 3 * nc;
   auto at = [&](int comp, int I, int J) -> T {
     I = I < 0 ? I + Nf : (I >= Nf ? I - Nf : I);
     J = J < 0 ? J + Nf : (J >= Nf ? J - Nf : J);
@@ -145,11 +186,17 @@ __global__ void k_restrict(const T* __restrict__ f, T* __restrict__ cz, int Nc) 
 }
 
 template <typename T>
-void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s) {
+void launch_restrict_batch(const T* fine, T* coarse, int Nc, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
   dim3 blk(64, 4);
-  dim3 grd((Nc + 63) / 64, (Nc + 3) / 4);
+  dim3 grd((Nc + 63) / 64, (Nc + 3) / 4, nsys);
   hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc);
   IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s) {
+  launch_restrict_batch<T>(fine, coarse, Nc, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,6 +211,8 @@ __global__ void k_prolong_add(const T* __restrict__ cz, T* __restrict__ f, int N
   const int Nf = 2 * Nc;
   if (I >= Nf || J >= Nf) return;
   const size_t nf = (size_t)Nf * Nf, nc = (size_t)Nc * Nc;
+  f += blockIdx.z * 3 * nf;
+  cz += blockIdx.z * 3 * nc;
   auto at = [&](int comp, int i, int j) -> T {
     i = i < 0 ? i + Nc : (i >= Nc ? i - Nc : i);
     j = j < 0 ? j + Nc : (j >= Nc ? j - Nc : j);
@@ -182,12 +231,18 @@ __global__ void k_prolong_add(const T* __restrict__ cz, T* __restrict__ f, int N
 }
 
 template <typename T>
-void launch_prolong_add(const T* coarse, T* fine, int Nc, hipStream_t s) {
+void launch_prolong_add_batch(const T* coarse, T* fine, int Nc, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
   const int Nf = 2 * Nc;
   dim3 blk(64, 4);
-  dim3 grd((Nf + 63) / 64, (Nf + 3) / 4);
+  dim3 grd((Nf + 63) / 64, (Nf + 3) / 4, nsys);
   hipLaunchKernelGGL((k_prolong_add<T>), grd, blk, 0, s, coarse, fine, Nc);
   IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_prolong_add(const T* coarse, T* fine, int Nc, hipStream_t s) {
+  launch_prolong_add_batch<T>(coarse, fine, Nc, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,9 +292,15 @@ int dots_blocks(size_t n, int cap) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_dots(const T* __restrict__ V, int nvec, size_t stride,
-                                              const T* __restrict__ t, size_t n,
-                                              double* __restrict__ partial) {
+                                              const T* __restrict__ t, BSeg sg,
+                                              double* __restrict__ partial, size_t pstride) {
   __shared__ double red[8][256];
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  V += o;
+  t += o;
+  partial += sy * pstride;
   const int tid = threadIdx.x;
   for (int v0 = 0; v0 < nvec; v0 += 8) {
     const int nv = nvec - v0 < 8 ? nvec - v0 : 8;
@@ -269,17 +330,29 @@ __global__ void __launch_bounds__(256) k_dots(const T* __restrict__ V, int nvec,
 }
 
 template <typename T>
-void launch_dots(const T* V, int nvec, size_t stride, const T* t, size_t n, double* partial,
-                 int nblk, hipStream_t s) {
-  hipLaunchKernelGGL((k_dots<T>), dim3(nblk), dim3(256), 0, s, V, nvec, stride, t, n, partial);
+void launch_dots_b(const T* V, int nvec, size_t stride, const T* t, BSeg sg, int nsys, double* partial,
+                   size_t pstride, int nblk, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_dots<T>), dim3(nblk, nsys), dim3(256), 0, s, V, nvec, stride, t, sg, partial, pstride);
   IBMG_LAUNCH_CHECK();
 }
 
-// mode 0: out1 = s; mode 1: out1 = s, out2 += s; mode 2: out1 = sqrt(s) (and out2 = sqrt(s))
+template <typename T>
+void launch_dots(const T* V, int nvec, size_t stride, const T* t, size_t n, double* partial,
+                 int nblk, hipStream_t s) {
+  launch_dots_b<T>(V, nvec, stride, t, seg1(n), 1, partial, 0, nblk, s);
+}
+
+// mode 0: out1 = s; mode 1: out1 = s, out2 += s; mode 2: out1 = sqrt(s) (and out2 = sqrt(s)).
+// Batched: system blockIdx.x, partials pstride and outputs ostride apart.
 __global__ void __launch_bounds__(256) k_dots_finish(const double* __restrict__ partial, int nvec,
-                                                     int nblk, double* out1, double* out2, int mode) {
+                                                     int nblk, size_t pstride, double* out1, double* out2,
+                                                     size_t ostride, int mode) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
+  partial += blockIdx.x * pstride;
+  out1 += blockIdx.x * ostride;
+  if (out2) out2 += blockIdx.x * ostride;
   for (int q = 0; q < nvec; ++q) {
     double a = 0.0;
     for (int b = tid; b < nblk; b += 256) a += partial[(size_t)b * nvec + q];
@@ -306,10 +379,17 @@ __global__ void __launch_bounds__(256) k_dots_finish(const double* __restrict__ 
   }
 }
 
+void launch_dots_finish_b(const double* partial, int nvec, int nblk, size_t pstride, double* out1,
+                          double* out2, size_t ostride, int mode, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL(k_dots_finish, dim3(nsys), dim3(256), 0, s, partial, nvec, nblk, pstride, out1, out2,
+                     ostride, mode);
+  IBMG_LAUNCH_CHECK();
+}
+
 void launch_dots_finish(const double* partial, int nvec, int nblk, double* out1, double* out2,
                         int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(256), 0, s, partial, nvec, nblk, out1, out2, mode);
-  IBMG_LAUNCH_CHECK();
+  launch_dots_finish_b(partial, nvec, nblk, 0, out1, out2, 0, mode, 1, s);
 }
 
 // t += sign * sum_q coef[q] V_q
@@ -332,28 +412,47 @@ void launch_update(T* t, const T* V, int nvec, size_t stride, const double* coef
   IBMG_LAUNCH_CHECK();
 }
 
-// v = t / denom (v = 0 when denom == 0: an exact Krylov breakdown)
+// v = t / denom (v = 0 when denom == 0: an exact Krylov breakdown).
+// Batched: system blockIdx.y, denominators dstride apart.
 template <typename T>
-__global__ void k_scale(const T* t, T* v, const double* __restrict__ denom,
-                        size_t n) {
-  const double d = denom[0];
+__global__ void k_scale(const T* t, T* v, const double* __restrict__ denom, size_t dstride, BSeg sg) {
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  const double d = denom[sy * dstride];
   const double inv = d != 0.0 ? 1.0 / d : 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    v[i] = (T)((double)t[i] * inv);
+    v[o + i] = (T)((double)t[o + i] * inv);
+}
+
+template <typename T>
+void launch_scale_b(const T* t, T* v, const double* denom, size_t dstride, BSeg sg, int nsys, size_t nmax,
+                    hipStream_t s) {
+  if (nsys <= 0) return;
+  int g = cdiv(nmax, 256);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL((k_scale<T>), dim3(g, nsys), dim3(256), 0, s, t, v, denom, dstride, sg);
+  IBMG_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_scale(const T* t, T* v, const double* denom, size_t n, hipStream_t s) {
-  int g = cdiv(n, 256);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL((k_scale<T>), dim3(g), dim3(256), 0, s, t, v, denom, n);
-  IBMG_LAUNCH_CHECK();
+  launch_scale_b<T>(t, v, denom, 0, seg1(n), 1, n, s);
 }
 
-// x += sum_q y[q] Z_q
+// x += sum_q y[q] Z_q, q < k (batched: k = kcnt[s] per system when kcnt is
+// given, y ystride apart)
 template <typename T>
 __global__ void k_combine(T* __restrict__ x, const T* __restrict__ Z, int k, size_t stride,
-                          const double* __restrict__ y, size_t n) {
+                          const double* __restrict__ y, size_t ystride, const int* __restrict__ kcnt, BSeg sg) {
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  if (kcnt) k = kcnt[sy];
+  y += sy * ystride;
+  x += o;
+  Z += o;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     double a = (double)x[i];
     for (int q = 0; q < k; ++q) a += y[q] * (double)Z[(size_t)q * stride + i];
@@ -362,10 +461,22 @@ __global__ void k_combine(T* __restrict__ x, const T* __restrict__ Z, int k, siz
 }
 
 template <typename T>
+void launch_combine_b(T* x, const T* Z, size_t stride, const double* y, size_t ystride, const int* kcnt,
+                      BSeg sg, int nsys, size_t nmax, hipStream_t s) {
+  if (nsys <= 0) return;
+  int g = cdiv(nmax, 256);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL((k_combine<T>), dim3(g, nsys), dim3(256), 0, s, x, Z, 0, stride, y, ystride, kcnt, sg);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
 void launch_combine(T* x, const T* Z, int k, size_t stride, const double* y, size_t n, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL((k_combine<T>), dim3(g), dim3(256), 0, s, x, Z, k, stride, y, n);
+  hipLaunchKernelGGL((k_combine<T>), dim3(g, 1), dim3(256), 0, s, x, Z, k, stride, y, (size_t)0,
+                     (const int*)nullptr, seg1(n));
   IBMG_LAUNCH_CHECK();
 }
 
@@ -415,10 +526,18 @@ void launch_small_ls(double* H, int ldh, int k, const double* beta, double* y, h
 }
 
 // Outer FGMRES: rotate column k of H (rows 0..k+1) by the stored rotations,
-// form rotation k, update g and write |g[k+1]| to res.
-__global__ void k_givens(double* __restrict__ H, int ldh, int k, double* __restrict__ cs,
-                         double* __restrict__ sn, double* __restrict__ g, double* __restrict__ res) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// form rotation k, update g and write |g[k+1]| to res.  Batched: system
+// blockIdx.x (H hstride apart; cs, sn, g rstride apart; res[s]), inactive
+// systems untouched.
+__global__ void k_givens(double* __restrict__ H, int ldh, size_t hstride, int k, double* __restrict__ cs,
+                         double* __restrict__ sn, double* __restrict__ g, size_t rstride,
+                         double* __restrict__ res, const int* __restrict__ active) {
+  const int sy = blockIdx.x;
+  if (threadIdx.x != 0 || (active && !active[sy])) return;
+  H += sy * hstride;
+  cs += sy * rstride;
+  sn += sy * rstride;
+  g += sy * rstride;
   double* col = H + (size_t)k * ldh;
   for (int i = 0; i < k; ++i) {
     const double a = col[i], b = col[i + 1];
@@ -436,18 +555,31 @@ __global__ void k_givens(double* __restrict__ H, int ldh, int k, double* __restr
   const double gk = g[k];
   g[k] = c * gk;
   g[k + 1] = -s * gk;
-  res[0] = fabs(g[k + 1]);
+  res[sy] = fabs(g[k + 1]);
+}
+
+void launch_givens_b(double* H, int ldh, size_t hstride, int k, double* cs, double* sn, double* g,
+                     size_t rstride, double* res, const int* active, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL(k_givens, dim3(nsys), dim3(64), 0, s, H, ldh, hstride, k, cs, sn, g, rstride, res, active);
+  IBMG_LAUNCH_CHECK();
 }
 
 void launch_givens(double* H, int ldh, int k, double* cs, double* sn, double* g, double* res,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, H, ldh, k, cs, sn, g, res);
-  IBMG_LAUNCH_CHECK();
+  launch_givens_b(H, ldh, 0, k, cs, sn, g, 0, res, nullptr, 1, s);
 }
 
-__global__ void k_backsolve(const double* __restrict__ H, int ldh, int k, const double* __restrict__ g,
-                            double* __restrict__ y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// y = R^{-1} g (R: the rotated k x k upper triangle); batched: k = kcnt[s].
+__global__ void k_backsolve(const double* __restrict__ H, int ldh, size_t hstride, int k,
+                            const int* __restrict__ kcnt, const double* __restrict__ g,
+                            double* __restrict__ y, size_t rstride) {
+  const int sy = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  if (kcnt) k = kcnt[sy];
+  H += sy * hstride;
+  g += sy * rstride;
+  y += sy * rstride;
   for (int j = k - 1; j >= 0; --j) {
     double a = g[j];
     for (int m = j + 1; m < k; ++m) a -= H[j + (size_t)m * ldh] * y[m];
@@ -456,8 +588,16 @@ __global__ void k_backsolve(const double* __restrict__ H, int ldh, int k, const 
   }
 }
 
+void launch_backsolve_b(const double* H, int ldh, size_t hstride, const int* kcnt, const double* g,
+                        double* y, size_t rstride, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL(k_backsolve, dim3(nsys), dim3(64), 0, s, H, ldh, hstride, 0, kcnt, g, y, rstride);
+  IBMG_LAUNCH_CHECK();
+}
+
 void launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, k, g, y);
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, (size_t)0, k, (const int*)nullptr, g, y,
+                     (size_t)0);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -466,8 +606,10 @@ void launch_backsolve(const double* H, int ldh, int k, const double* g, double* 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_block_sums(const T* __restrict__ a, size_t nn,
-                                                    double* __restrict__ partial) {
+                                                    double* __restrict__ partial, size_t bs, size_t pstride) {
   __shared__ double red[3][256];
+  a += blockIdx.y * bs;
+  partial += blockIdx.y * pstride;
   const int tid = threadIdx.x;
   double s0 = 0, s1 = 0, s2 = 0;
   for (size_t i = blockIdx.x * (size_t)256 + tid; i < nn; i += (size_t)gridDim.x * 256) {
@@ -491,14 +633,24 @@ __global__ void __launch_bounds__(256) k_block_sums(const T* __restrict__ a, siz
 }
 
 template <typename T>
-void launch_block_sums(const T* a, int N, double* partial, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL((k_block_sums<T>), dim3(nblk), dim3(256), 0, s, a, (size_t)N * N, partial);
+void launch_block_sums_b(const T* a, int N, size_t bs, double* partial, int nblk, size_t pstride, int nsys,
+                         hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_block_sums<T>), dim3(nblk, nsys), dim3(256), 0, s, a, (size_t)N * N, partial, bs,
+                     pstride);
   IBMG_LAUNCH_CHECK();
 }
 
 template <typename T>
+void launch_block_sums(const T* a, int N, double* partial, int nblk, hipStream_t s) {
+  launch_block_sums_b<T>(a, N, 0, partial, nblk, 0, 1, s);
+}
+
+template <typename T>
 __global__ void k_subtract_means(T* __restrict__ a, size_t nn, const double* __restrict__ sums,
-                                 int nvel) {
+                                 int nvel, size_t bs, size_t sstride) {
+  a += blockIdx.y * bs;
+  sums += blockIdx.y * sstride;
   const double inv = 1.0 / (double)nn;
   const double m0 = nvel ? sums[0] * inv : 0.0;
   const double m1 = nvel ? sums[1] * inv : 0.0;
@@ -513,12 +665,19 @@ __global__ void k_subtract_means(T* __restrict__ a, size_t nn, const double* __r
 }
 
 template <typename T>
-void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_t s) {
+void launch_subtract_means_b(T* a, int N, size_t bs, const double* sums, size_t sstride, int nvel, int nsys,
+                             hipStream_t s) {
+  if (nsys <= 0) return;
   size_t nn = (size_t)N * N;
   int g = cdiv(nn, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_subtract_means<T>), dim3(g), dim3(256), 0, s, a, nn, sums, nvel);
+  hipLaunchKernelGGL((k_subtract_means<T>), dim3(g, nsys), dim3(256), 0, s, a, nn, sums, nvel, bs, sstride);
   IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_t s) {
+  launch_subtract_means_b<T>(a, N, 0, sums, 0, nvel, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,7 +695,23 @@ void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_
   template void launch_scale<T>(const T*, T*, const double*, size_t, hipStream_t);                \
   template void launch_combine<T>(T*, const T*, int, size_t, const double*, size_t, hipStream_t); \
   template void launch_block_sums<T>(const T*, int, double*, int, hipStream_t);                   \
-  template void launch_subtract_means<T>(T*, int, const double*, int, hipStream_t);
+  template void launch_subtract_means<T>(T*, int, const double*, int, hipStream_t);               \
+  template void launch_apply_batch<T>(const T*, T*, const T*, int, StokesCoef<T>, int, size_t,    \
+                                      hipStream_t);                                               \
+  template void launch_ib_rows<T>(const T*, T*, const int*, const int*, const int*, const T*, int, \
+                                  T, hipStream_t);                                                \
+  template void launch_restrict_batch<T>(const T*, T*, int, int, hipStream_t);                    \
+  template void launch_prolong_add_batch<T>(const T*, T*, int, int, hipStream_t);                 \
+  template void launch_dots_b<T>(const T*, int, size_t, const T*, BSeg, int, double*, size_t, int, \
+                                 hipStream_t);                                                    \
+  template void launch_scale_b<T>(const T*, T*, const double*, size_t, BSeg, int, size_t,         \
+                                  hipStream_t);                                                   \
+  template void launch_combine_b<T>(T*, const T*, size_t, const double*, size_t, const int*, BSeg, \
+                                    int, size_t, hipStream_t);                                    \
+  template void launch_block_sums_b<T>(const T*, int, size_t, double*, int, size_t, int,          \
+                                       hipStream_t);                                              \
+  template void launch_subtract_means_b<T>(T*, int, size_t, const double*, size_t, int, int,      \
+                                           hipStream_t);
 
 IBMG_INST_GRID(double)
 IBMG_INST_GRID(float)

@@ -105,6 +105,29 @@ struct BoxGeom {        // RAS boxes on one level
   int N, b, o, m, npd, nloc, nown, nch;  // nch = ceil(nown / 64) row chunks
 };
 
+// Segments of a batch vector: system s owns entries [begin(s), begin(s) +
+// len(s)).  A single system is one segment at 0; a batch of equal systems
+// has off = null and segment s = [s n, (s + 1) n); ragged batches (systems of
+// different grid sizes) list their offsets.  Kernels take the system from a
+// grid index and skip systems whose active flag is 0.
+struct BSeg {
+  const long long* off;  // [nsys + 1] device offsets, or null
+  size_t n;              // segment length when off is null
+  const int* active;     // [nsys] device flags, or null: every system active
+};
+inline BSeg seg1(size_t n) { return BSeg{nullptr, n, nullptr}; }
+__device__ __forceinline__ size_t seg_begin(const BSeg& g, int s) {
+  return g.off ? (size_t)g.off[s] : (size_t)s * g.n;
+}
+__device__ __forceinline__ size_t seg_len(const BSeg& g, int s) {
+  return g.off ? (size_t)(g.off[s + 1] - g.off[s]) : g.n;
+}
+__device__ __forceinline__ bool seg_on(const BSeg& g, int s) { return !g.active || g.active[s] != 0; }
+
+// Largest RAS box: b + 2 o <= 32 cells per side
+constexpr int kMaxBoxSide = 32;
+constexpr int kMaxNloc = 2 * kMaxBoxSide * (kMaxBoxSide + 1) + kMaxBoxSide * kMaxBoxSide;
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
@@ -211,5 +234,72 @@ void launch_coarse_invert(double* aug, int n, hipStream_t s);
 void launch_coarse_extract(const double* aug, int n, int n0, double* inv, hipStream_t s);
 template <typename T>
 void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched forms: nsys systems of one grid size stored back to back (system
+// stride bs), or ragged batches described by a BSeg.  Per-system scalars
+// (partial sums, Hessenberg columns, norms) sit at fixed strides.
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_apply_batch(const T* w, T* y, const T* b, int N, StokesCoef<T> c, int nsys, size_t bs,
+                        hipStream_t s);
+// y[rows[q]] += sign * sum_k val[k] x[col[k]], k in [ptr[q], ptr[q+1])
+template <typename T>
+void launch_ib_rows(const T* x, T* y, const int* rows, const int* ptr, const int* col, const T* val,
+                    int nrows, T sign, hipStream_t s);
+template <typename T>
+void launch_restrict_batch(const T* fine, T* coarse, int Nc, int nsys, hipStream_t s);
+template <typename T>
+void launch_prolong_add_batch(const T* coarse, T* fine, int Nc, int nsys, hipStream_t s);
+template <typename T>
+void launch_dots_b(const T* V, int nvec, size_t stride, const T* t, BSeg sg, int nsys, double* partial,
+                   size_t pstride, int nblk, hipStream_t s);
+void launch_dots_finish_b(const double* partial, int nvec, int nblk, size_t pstride, double* out1,
+                          double* out2, size_t ostride, int mode, int nsys, hipStream_t s);
+template <typename T>
+void launch_scale_b(const T* t, T* v, const double* denom, size_t dstride, BSeg sg, int nsys,
+                    size_t nmax, hipStream_t s);
+template <typename T>
+void launch_combine_b(T* x, const T* Z, size_t stride, const double* y, size_t ystride, const int* kcnt,
+                      BSeg sg, int nsys, size_t nmax, hipStream_t s);
+void launch_givens_b(double* H, int ldh, size_t hstride, int k, double* cs, double* sn, double* g,
+                     size_t rstride, double* res, const int* active, int nsys, hipStream_t s);
+void launch_backsolve_b(const double* H, int ldh, size_t hstride, const int* kcnt, const double* g,
+                        double* y, size_t rstride, int nsys, hipStream_t s);
+template <typename T>
+void launch_block_sums_b(const T* a, int N, size_t bs, double* partial, int nblk, size_t pstride, int nsys,
+                         hipStream_t s);
+template <typename T>
+void launch_subtract_means_b(T* a, int N, size_t bs, const double* sums, size_t sstride, int nvel, int nsys,
+                             hipStream_t s);
+template <typename T>
+void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s);
+template <typename T>
+void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s);
+template <typename T>
+void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const double* pin, int nblk,
+                        size_t pstride, double* hout, size_t hstride, hipStream_t s);
+template <typename T>
+void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
+                         const double* H, int ldh, size_t hstride, const double* beta, double* yout,
+                         size_t sstride, hipStream_t s);
+template <typename T>
+void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s);
+
+// One persistent launch per smoother sweep over every (system, box) of a
+// batch level: interior tiles of TB boxes on the matrix cores against the
+// shared interior inverse, then (IB box, row chunk) items against each box's
+// own inverse.  Box entries are s * nbox + box id; systems are sys_n apart.
+struct RasBatchPlan {
+  int tb = 32;      // interior tile width (16 or 32 boxes)
+  int grid = 0;     // work-groups of the persistent launch
+};
+template <typename T>
+void launch_ras_batch(const T* r, T* z, BoxGeom g, size_t sys_n, int nbox, const T* shared_inv,
+                      const int* int_ents, int n_int, const int* ib_ents, const T* const* ib_inv, int n_ib,
+                      const int* loc_tab, const int* active, RasBatchPlan plan, hipStream_t s);
+int ras_batch_items(const BoxGeom& g, int n_int, int n_ib, int tb);
 
 }  // namespace ibmg

@@ -10,6 +10,10 @@
 // block in the same fixed order, so the result is deterministic and no
 // cross-block synchronisation or atomics are needed; block 0 also records the
 // Hessenberg entries.
+//
+// Batched launches take the system from blockIdx.y: vectors are segments of
+// a batch vector (BSeg), and partial sums, Hessenberg columns and norms sit
+// at fixed per-system strides; systems whose active flag is 0 are skipped.
 #include "internal.hpp"
 
 namespace ibmg {
@@ -75,10 +79,19 @@ __device__ void block_dots(const T* __restrict__ V, int k, size_t stride, const 
 // pass-2 partial dots of the updated t.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict__ V, int k, size_t stride,
-                                                       size_t n, const double* __restrict__ pin, int nblk_in,
-                                                       double* __restrict__ hcol, double* __restrict__ pout) {
+                                                       BSeg sg, const double* __restrict__ pin, int nblk_in,
+                                                       size_t pstride, double* __restrict__ hcol,
+                                                       size_t hstride, double* __restrict__ pout) {
   __shared__ double red[8][kThreads];
   __shared__ double h[64];
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  t += o;
+  V += o;
+  pin += sy * pstride;
+  pout += sy * pstride;
+  hcol += sy * hstride;
   reduce_partials(pin, nblk_in, k, h, red[0]);
   if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] = h[threadIdx.x];
 #pragma unroll 4
@@ -95,10 +108,19 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
 // partial sums of |t|^2.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict__ V, int k, size_t stride,
-                                                       size_t n, const double* __restrict__ pin, int nblk_in,
-                                                       double* __restrict__ hcol, double* __restrict__ pout) {
+                                                       BSeg sg, const double* __restrict__ pin, int nblk_in,
+                                                       size_t pstride, double* __restrict__ hcol,
+                                                       size_t hstride, double* __restrict__ pout) {
   __shared__ double red[8][kThreads];
   __shared__ double h[64];
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  t += o;
+  V += o;
+  pin += sy * pstride;
+  pout += sy * pstride;
+  hcol += sy * hstride;
   reduce_partials(pin, nblk_in, k, h, red[0]);
   if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] += h[threadIdx.x];
   double acc = 0.0;
@@ -122,11 +144,19 @@ __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict
 // v = t / sqrt(sum partials) (v = 0 on an exact breakdown); block 0 stores the
 // norm into *hout.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, size_t n,
+__global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, BSeg sg,
                                                         const double* __restrict__ pin, int nblk_in,
-                                                        double* __restrict__ hout) {
+                                                        size_t pstride, double* __restrict__ hout,
+                                                        size_t hstride) {
   __shared__ double red[kThreads];
   __shared__ double nrm;
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  t += o;
+  v += o;
+  pin += sy * pstride;
+  hout += sy * hstride;
   reduce_partials(pin, nblk_in, 1, &nrm, red);
   const double d = sqrt(nrm);
   if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = d;
@@ -140,10 +170,18 @@ __global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, size_t
 // x += sum_q y_q Z_q; block 0 stores y.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, const T* __restrict__ Z, int k,
-                                                         size_t stride, size_t n, const double* __restrict__ H,
-                                                         int ldh, const double* __restrict__ beta,
-                                                         double* __restrict__ yout) {
+                                                         size_t stride, BSeg sg, const double* __restrict__ H,
+                                                         int ldh, size_t hstride, const double* __restrict__ beta,
+                                                         double* __restrict__ yout, size_t sstride) {
   __shared__ double y[16];
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  x += o;
+  Z += o;
+  H += sy * hstride;
+  beta += sy * sstride;
+  yout += sy * sstride;
   if (threadIdx.x == 0) {
     double R[17][16];
     double g[17], cs[16], sn[16];
@@ -195,31 +233,63 @@ static int stream_blocks(size_t n) {
 }
 
 template <typename T>
+void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_upd_dots<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin, nblk,
+                     pstride, hcol, hstride, pout);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_upd_norm<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin, nblk,
+                     pstride, hcol, hstride, pout);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const double* pin, int nblk,
+                        size_t pstride, double* hout, size_t hstride, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_scale_red<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, t, v, sg, pin,
+                     nblk, pstride, hout, hstride);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
+                         const double* H, int ldh, size_t hstride, const double* beta, double* yout,
+                         size_t sstride, hipStream_t s) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
+                     sg, H, ldh, hstride, beta, yout, sstride);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
 void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
                      double* hcol, double* pout, hipStream_t s) {
-  hipLaunchKernelGGL((k_upd_dots<T>), dim3(nblk), dim3(kThreads), 0, s, t, V, k, stride, n, pin, nblk, hcol, pout);
-  IBMG_LAUNCH_CHECK();
+  launch_upd_dots_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s);
 }
 
 template <typename T>
 void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
                      double* hcol, double* pout, hipStream_t s) {
-  hipLaunchKernelGGL((k_upd_norm<T>), dim3(nblk), dim3(kThreads), 0, s, t, V, k, stride, n, pin, nblk, hcol, pout);
-  IBMG_LAUNCH_CHECK();
+  launch_upd_norm_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s);
 }
 
 template <typename T>
 void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, double* hout, hipStream_t s) {
-  hipLaunchKernelGGL((k_scale_red<T>), dim3(stream_blocks(n)), dim3(kThreads), 0, s, t, v, n, pin, nblk, hout);
-  IBMG_LAUNCH_CHECK();
+  launch_scale_red_b<T>(t, v, seg1(n), 1, n, pin, nblk, 0, hout, 0, s);
 }
 
 template <typename T>
 void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
                        const double* beta, double* yout, hipStream_t s) {
-  hipLaunchKernelGGL((k_combine_ls<T>), dim3(stream_blocks(n)), dim3(kThreads), 0, s, x, Z, k, stride, n, H,
-                     ldh, beta, yout);
-  IBMG_LAUNCH_CHECK();
+  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s);
 }
 
 #define IBMG_INST_KRY(T)                                                                               \
@@ -229,7 +299,15 @@ void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const d
                                    double*, hipStream_t);                                              \
   template void launch_scale_red<T>(const T*, T*, size_t, const double*, int, double*, hipStream_t);   \
   template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, const double*, int,            \
-                                     const double*, double*, hipStream_t);
+                                     const double*, double*, hipStream_t);                             \
+  template void launch_upd_dots_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
+                                     double*, size_t, double*, hipStream_t);                           \
+  template void launch_upd_norm_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
+                                     double*, size_t, double*, hipStream_t);                           \
+  template void launch_scale_red_b<T>(const T*, T*, BSeg, int, size_t, const double*, int, size_t,     \
+                                      double*, size_t, hipStream_t);                                   \
+  template void launch_combine_ls_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, const double*,   \
+                                       int, size_t, const double*, double*, size_t, hipStream_t);
 
 IBMG_INST_KRY(double)
 IBMG_INST_KRY(float)

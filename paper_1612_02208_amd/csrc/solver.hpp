@@ -40,7 +40,19 @@ struct SolverBase {
   virtual void sc_info(int level, double* lam, int32_t* colours) const = 0;
 };
 
+// Many independent systems solved together (batched form): one launch per
+// smoother sweep covers every system.
+struct BatchBase {
+  virtual ~BatchBase() = default;
+  virtual int nsys() const = 0;
+  virtual void vcycle(const double* const* r, double* const* z, hipStream_t s) = 0;
+  virtual int fgmres(const double* const* b, double* const* x, const ibmg_solve_opts& o,
+                     ibmg_solve_info* infos, hipStream_t s) = 0;
+  virtual std::vector<int64_t> stats() const = 0;
+};
+
 SolverBase* make_solver(const ibmg_desc& d, hipStream_t s);
+BatchBase* make_batch(int nsys, const ibmg_desc* d, hipStream_t s);
 void validate_desc(const ibmg_desc& d);
 
 }  // namespace ibmg

@@ -1,0 +1,991 @@
+// Host orchestration: hierarchy set-up, the V-cycle of Alg. 1 with
+// FGMRES-wrapped smoothing (Sec. 3.3), and the outer flexible GMRES solve.
+// Every arithmetic step runs in the kernels; the host builds index structures
+// (footprint windows, face -> point lists, IB row patterns, box classes) and
+// sequences launches on one stream.
+#pragma once
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cmath>
+#include <type_traits>
+
+#include "sc_smoother.hpp"
+#include "solver.hpp"
+
+namespace ibmg {
+
+namespace detail {
+
+constexpr int kMaxNu = 8;
+constexpr int kMaxRestart = 64;
+constexpr int kScalY = 1;     // scal[1..16]: least-squares solution
+constexpr int kScalTmp = 20;  // scal[20..]: second Gram-Schmidt pass
+// Levels whose longest face -> point list exceeds this use the explicit
+// Galerkin IB rows (one wave per row) for the IB term.
+constexpr int kSpmvListThreshold = 24;
+// partial-sum buffers: two of kPartStride doubles (blocks x vectors)
+constexpr size_t kPartStride = (size_t)256 * 65;
+
+inline int wrapn(int a, int N) {
+  a %= N;
+  return a < 0 ? a + N : a;
+}
+
+inline std::vector<int> level_sizes(int N, int coarse) {
+  std::vector<int> s;
+  for (int n = N; n >= coarse; n /= 2) {
+    s.push_back(n);
+    if (n == coarse) break;
+  }
+  std::reverse(s.begin(), s.end());
+  return s;
+}
+
+inline void box_params(int N, int box, int overlap, int* b, int* o) {
+  *b = std::min(box, N / 2);
+  *o = std::min(overlap, (N - *b - 1) / 2);
+  if (*o < 0) *o = 0;
+}
+
+}  // namespace detail
+
+using namespace detail;
+
+template <typename T>
+struct Level {
+  int N = 0;
+  CompFoot f[2];
+  // IB term from the explicit Galerkin rows (wave per row) instead of the
+  // interpolate / spring / spread chain: chosen where points crowd the faces
+  bool use_spmv = false;
+  DBuf<double> Gd;
+  DBuf<T> Gt;
+  StokesCoef<double> cd{};
+  StokesCoef<T> ct{};
+  // restricted additive Schwarz
+  BoxGeom g{};
+  int n_unique = 0, n_ib = 0;
+  std::vector<int> uniq;  // unique box ids (IB boxes, then one interior representative)
+  std::vector<int> ib_list, int_list;
+  std::vector<int> loc_tab;  // local unknown -> (comp << 24) | (jj << 12) | ii
+  DBuf<int> d_ib, d_int, d_loc;
+  DBuf<T> inv;            // [n_unique][nch][nloc][64]
+  DBuf<T> int_part;       // reduction slices of the interior-box product
+  // work vectors
+  DBuf<T> w, b, r, t, V, Z, F;
+  DBuf<double> H, scal, part;
+  // Schur-complement smoother
+  std::unique_ptr<ScLevel<T>> sc;
+};
+
+template <typename T>
+class BatchSolver;
+
+template <typename T>
+class Solver final : public SolverBase {
+  friend class BatchSolver<T>;
+
+ public:
+  Solver(const ibmg_desc& d, hipStream_t s) : d_(d) {
+    M_ = d.M;
+    E_ = d.n_springs;
+    X_.assign(d.X, d.X + 2 * (size_t)M_);
+    ends_.assign(d.ends, d.ends + 2 * (size_t)E_);
+    kappa_.assign(d.kappa, d.kappa + E_);
+    nu_ = std::max(d.nu1, d.nu2);
+    sizes_ = level_sizes(d.N, d.coarse_N);
+    L_ = (int)sizes_.size() - 1;
+    build_structure(s);
+    build_numeric(s);
+    alloc_work(s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  ~Solver() override {
+    drop_graph();
+    if (gstream_) (void)hipStreamDestroy(gstream_);
+    if (pinned_) (void)hipHostFree(pinned_);
+  }
+
+  int levels() const override { return L_ + 1; }
+  int level_n(int l) const override { return sizes_.at(l); }
+
+  // ---------------------------------------------------------------- set-up
+  void build_structure(hipStream_t s) {
+    // spring adjacency (node -> incident springs in spring order)
+    adj_ptr_.assign(M_ + 1, 0);
+    for (int e = 0; e < E_; ++e) {
+      adj_ptr_[ends_[2 * e] + 1]++;
+      adj_ptr_[ends_[2 * e + 1] + 1]++;
+    }
+    for (int l = 0; l < M_; ++l) adj_ptr_[l + 1] += adj_ptr_[l];
+    adj_nbr_.assign(adj_ptr_[M_], 0);
+    adj_sid_.assign(adj_ptr_[M_], 0);
+    {
+      std::vector<int> fill(adj_ptr_.begin(), adj_ptr_.end() - 1);
+      for (int e = 0; e < E_; ++e) {
+        const int a = ends_[2 * e], b = ends_[2 * e + 1];
+        adj_nbr_[fill[a]] = b;
+        adj_sid_[fill[a]++] = e;
+        adj_nbr_[fill[b]] = a;
+        adj_sid_[fill[b]++] = e;
+      }
+    }
+    d_adj_ptr_.upload(adj_ptr_, s);
+    d_adj_nbr_.upload(adj_nbr_, s);
+    d_ends_.upload(ends_, s);
+    d_X_.upload(X_, s);
+    levels_.resize(L_ + 1);
+    for (int l = L_; l >= 0; --l) {
+      Level<T>& lev = levels_[l];
+      lev.N = sizes_[l];
+      const double h = 1.0 / lev.N;
+      lev.cd = StokesCoef<double>{d_.rho / d_.dt, d_.mu / (h * h), 1.0 / h, d_.dt / (h * h)};
+      lev.ct = StokesCoef<T>{(T)lev.cd.alpha, (T)lev.cd.beta, (T)lev.cd.gi, (T)lev.cd.ibs};
+      for (int c = 0; c < 2; ++c) {
+        CompFoot& f = lev.f[c];
+        if (l == L_) fine_windows(lev.N, c, f);
+        else coarse_windows(levels_[l + 1].f[c], c, levels_[l + 1].N, lev.N, f);
+        f.d_base.upload(f.base, s);
+        f.d_mask.upload(f.mask, s);
+        f.w.alloc((size_t)M_ * 16);
+        if (l == L_)
+          launch_fp_fine(d_X_.p, M_, lev.N, c, f.d_base.p, f.d_mask.p, f.w.p, s);
+        else
+          launch_fp_coarsen(levels_[l + 1].f[c].d_base.p, levels_[l + 1].f[c].w.p, f.d_base.p, M_, c,
+                            levels_[l + 1].N, lev.N, f.w.p, s);
+        if (std::is_same<T, float>::value) {
+          f.wf.alloc((size_t)M_ * 16);
+          launch_cast<double, float>(f.w.p, f.wf.p, (size_t)M_ * 16, s);
+        }
+        spread_lists(lev.N, f);
+        f.d_sp_ptr.upload(f.sp_ptr, s);
+        f.d_sp_ent.upload(f.sp_ent, s);
+        ib_pattern(lev.N, f);
+        f.d_tptr.upload(f.tptr, s);
+        f.d_tcol.upload(f.tcol, s);
+        f.tval.alloc(f.tcol.size());
+        if (std::is_same<T, float>::value) f.tvalf.alloc(f.tcol.size());
+        f.max_list = 0;
+        for (size_t r = 0; r + 1 < f.sp_ptr.size(); ++r)
+          f.max_list = std::max(f.max_list, f.sp_ptr[r + 1] - f.sp_ptr[r]);
+      }
+      lev.use_spmv = std::max(lev.f[0].max_list, lev.f[1].max_list) > kSpmvListThreshold;
+      if (l >= 1 && d_.smoother == IBMG_RAS) classify_boxes(lev);
+      if (l >= 1 && d_.smoother == IBMG_SC) sc_structure(lev, s);
+    }
+  }
+
+  // Finest windows: t = X N - shift, i0 = floor(t) - 1, slots with |t - k| < 2.
+  void fine_windows(int N, int comp, CompFoot& f) {
+    f.base.assign(2 * (size_t)M_, 0);
+    f.mask.assign(M_, 0);
+    const double sx = comp == 0 ? 0.0 : 0.5, sy = comp == 0 ? 0.5 : 0.0;
+    for (int l = 0; l < M_; ++l) {
+      const double tx = X_[2 * l] * N - sx, ty = X_[2 * l + 1] * N - sy;
+      const int i0 = (int)std::floor(tx) - 1, j0 = (int)std::floor(ty) - 1;
+      int mk = 0;
+      for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a)
+          if (std::fabs(tx - (i0 + a)) < 2.0 && std::fabs(ty - (j0 + b)) < 2.0) mk |= 1 << (b * 4 + a);
+      f.base[2 * l] = wrapn(i0, N);
+      f.base[2 * l + 1] = wrapn(j0, N);
+      f.mask[l] = mk;
+    }
+  }
+
+  // Coarse windows: base = fine base / 2; a coarse slot is structural when a
+  // structural fine slot is interpolated from it by P_u.
+  void coarse_windows(const CompFoot& ff, int comp, int Nf, int Nc, CompFoot& f) {
+    (void)Nf;
+    f.base.assign(2 * (size_t)M_, 0);
+    f.mask.assign(M_, 0);
+    for (int l = 0; l < M_; ++l) {
+      const int I0 = ff.base[2 * l], J0 = ff.base[2 * l + 1];
+      const int ci0 = I0 >> 1, cj0 = J0 >> 1;
+      int mk = 0;
+      for (int s = 0; s < 16; ++s) {
+        if (!((ff.mask[l] >> s) & 1)) continue;
+        const int I = I0 + (s & 3), J = J0 + (s >> 2);
+        if (comp == 0) {
+          const int cj = (J >> 1) - cj0;
+          if ((I & 1) == 0) mk |= 1 << (cj * 4 + (I >> 1) - ci0);
+          else mk |= (1 << (cj * 4 + ((I - 1) >> 1) - ci0)) | (1 << (cj * 4 + ((I + 1) >> 1) - ci0));
+        } else {
+          const int ci = (I >> 1) - ci0;
+          if ((J & 1) == 0) mk |= 1 << (((J >> 1) - cj0) * 4 + ci);
+          else mk |= (1 << ((((J - 1) >> 1) - cj0) * 4 + ci)) | (1 << ((((J + 1) >> 1) - cj0) * 4 + ci));
+        }
+      }
+      f.base[2 * l] = wrapn(ci0, Nc);
+      f.base[2 * l + 1] = wrapn(cj0, Nc);
+      f.mask[l] = mk;
+    }
+  }
+
+  static int face_of(const CompFoot& f, int l, int s, int N) {
+    int i = f.base[2 * l] + (s & 3), j = f.base[2 * l + 1] + (s >> 2);
+    if (i >= N) i -= N;
+    if (j >= N) j -= N;
+    return j * N + i;
+  }
+
+  // faces -> (point, slot) entries, entries of a face in increasing (l, s)
+  void spread_lists(int N, CompFoot& f) {
+    const size_t nf = (size_t)N * N;
+    f.sp_ptr.assign(nf + 1, 0);
+    for (int l = 0; l < M_; ++l)
+      for (int s = 0; s < 16; ++s)
+        if ((f.mask[l] >> s) & 1) f.sp_ptr[face_of(f, l, s, N) + 1]++;
+    for (size_t r = 0; r < nf; ++r) f.sp_ptr[r + 1] += f.sp_ptr[r];
+    f.sp_ent.assign(f.sp_ptr[nf], 0);
+    std::vector<int> fill(f.sp_ptr.begin(), f.sp_ptr.end() - 1);
+    for (int l = 0; l < M_; ++l)
+      for (int s = 0; s < 16; ++s)
+        if ((f.mask[l] >> s) & 1) f.sp_ent[fill[face_of(f, l, s, N)]++] = l * 16 + s;
+  }
+
+  // Pattern of dt/h^2 J^T K' J: row r couples to every face of every point
+  // that shares a spring (or is itself) with a point whose window holds r.
+  void ib_pattern(int N, CompFoot& f) {
+    const size_t nf = (size_t)N * N;
+    f.tptr.assign(nf + 1, 0);
+    f.tcol.clear();
+    std::vector<int> stamp(nf, -1);
+    std::vector<int> cols;
+    auto add_point = [&](int q, int r) {
+      for (int s = 0; s < 16; ++s) {
+        if (!((f.mask[q] >> s) & 1)) continue;
+        const int c = face_of(f, q, s, N);
+        if (stamp[c] != r) {
+          stamp[c] = r;
+          cols.push_back(c);
+        }
+      }
+    };
+    for (size_t r = 0; r < nf; ++r) {
+      cols.clear();
+      for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
+        const int l = f.sp_ent[e] >> 4;
+        if (adj_ptr_[l + 1] == adj_ptr_[l]) continue;
+        add_point(l, (int)r);
+        for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a], (int)r);
+      }
+      std::sort(cols.begin(), cols.end());
+      f.tcol.insert(f.tcol.end(), cols.begin(), cols.end());
+      f.tptr[r + 1] = (int)f.tcol.size();
+    }
+  }
+
+  // A box needs its own inverse when one of its faces carries an IB row;
+  // every other box has the same (translation-invariant) matrix.
+  void classify_boxes(Level<T>& lev) {
+    int b, o;
+    box_params(lev.N, d_.box, d_.overlap, &b, &o);
+    const int m = b + 2 * o, N = lev.N;
+    lev.g = BoxGeom{N, b, o, m, N / b, 2 * m * (m + 1) + m * m, 3 * b * b, (3 * b * b + 63) / 64};
+    const int nbox = lev.g.npd * lev.g.npd;
+    lev.uniq.clear();
+    lev.ib_list.clear();
+    lev.int_list.clear();
+    for (int p = 0; p < nbox; ++p) {
+      const int x0 = (p % lev.g.npd) * b - o, y0 = (p / lev.g.npd) * b - o;
+      bool ib = false;
+      for (int jj = 0; jj <= m && !ib; ++jj)
+        for (int ii = 0; ii <= m && !ib; ++ii) {
+          const int r = wrapn(y0 + jj, N) * N + wrapn(x0 + ii, N);
+          if (jj < m && lev.f[0].tptr[r + 1] > lev.f[0].tptr[r]) ib = true;   // x-face (ii, jj)
+          if (ii < m && lev.f[1].tptr[r + 1] > lev.f[1].tptr[r]) ib = true;   // y-face (ii, jj)
+        }
+      if (ib) lev.ib_list.push_back(p);
+      else lev.int_list.push_back(p);
+    }
+    lev.loc_tab.assign(lev.g.nloc, 0);
+    for (int k = 0; k < lev.g.nloc; ++k) {
+      const int nu = m * (m + 1);
+      int comp, ii, jj;
+      if (k < nu) { comp = 0; ii = k % (m + 1); jj = k / (m + 1); }
+      else if (k < 2 * nu) { comp = 1; ii = (k - nu) % m; jj = (k - nu) / m; }
+      else { comp = 2; ii = (k - 2 * nu) % m; jj = (k - 2 * nu) / m; }
+      lev.loc_tab[k] = (comp << 24) | (jj << 12) | ii;
+    }
+    lev.n_ib = (int)lev.ib_list.size();
+    lev.uniq = lev.ib_list;
+    if (!lev.int_list.empty()) lev.uniq.push_back(lev.int_list.front());
+    lev.n_unique = (int)lev.uniq.size();
+  }
+
+  size_t box_stride(const Level<T>& lev) const { return (size_t)lev.g.nch * lev.g.nloc * 64; }
+
+  void build_numeric(hipStream_t s) {
+    // spring stiffness per incidence
+    std::vector<double> ak(adj_nbr_.size());
+    for (size_t a = 0; a < ak.size(); ++a) ak[a] = kappa_[adj_sid_[a]];
+    d_adj_k_.upload(ak, s);
+    if (std::is_same<T, float>::value) {
+      std::vector<float> akf(ak.begin(), ak.end());
+      d_adj_kf_.upload(akf, s);
+    }
+    for (int l = L_; l >= 0; --l) {
+      Level<T>& lev = levels_[l];
+      for (int c = 0; c < 2; ++c) {
+        CompFoot& f = lev.f[c];
+        if (!f.tcol.empty()) {
+          launch_t_values(fview<double>(f), f.d_mask.p, sview<double>(), lev.N, lev.cd.ibs, f.d_tptr.p,
+                          f.d_tcol.p, f.tval.p, s);
+          if (std::is_same<T, float>::value)
+            launch_cast<double, float>(f.tval.p, f.tvalf.p, f.tcol.size(), s);
+        }
+      }
+    }
+    build_coarse(s);
+    if (d_.smoother == IBMG_RAS)
+      for (int l = 1; l <= L_; ++l) build_boxes(levels_[l], s);
+    if (d_.smoother == IBMG_SC)
+      for (int l = 1; l <= L_; ++l) sc_numeric(levels_[l], s);
+  }
+
+  // ------------------------------------------------ Schur-complement set-up
+  void sc_structure(Level<T>& lev, hipStream_t s) {
+    const int N = lev.N, NN = N * N;
+    lev.sc.reset(new ScLevel<T>());
+    ScLevel<T>& sc = *lev.sc;
+    sc.N = N;
+    sc.its = d_.cheb_its;
+    sc.rho_zero = d_.rho == 0.0;
+    // velocity colours: five-point stencil plus IB rows, per component
+    std::vector<int> colv(2 * (size_t)NN);
+    for (int c = 0; c < 2; ++c) {
+      const CompFoot& f = lev.f[c];
+      std::vector<int> cc = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
+        const int i = r % N, j = r / N;
+        nb.push_back(j * N + (i + 1) % N);
+        nb.push_back(j * N + (i + N - 1) % N);
+        nb.push_back(((j + 1) % N) * N + i);
+        nb.push_back(((j + N - 1) % N) * N + i);
+        for (int k = f.tptr[r]; k < f.tptr[r + 1]; ++k) nb.push_back(f.tcol[k]);
+      });
+      std::copy(cc.begin(), cc.end(), colv.begin() + (size_t)c * NN);
+    }
+    sc.colu.build(colv, s);
+    std::vector<int> colp = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
+      const int i = r % N, j = r / N;
+      nb.push_back(j * N + (i + 1) % N);
+      nb.push_back(j * N + (i + N - 1) % N);
+      nb.push_back(((j + 1) % N) * N + i);
+      nb.push_back(((j + N - 1) % N) * N + i);
+    });
+    sc.colp.build(colp, s);
+    const size_t n2 = 2 * (size_t)NN, n1 = NN;
+    sc.diag.alloc(n2);
+    sc.dinv.alloc(n2);
+    sc.mdiag.alloc(n1);
+    for (DBuf<T>* b : {&sc.yu, &sc.ga, &sc.gx, &sc.ad, &sc.ar, &sc.at, &sc.as}) b->alloc(n2);
+    for (DBuf<T>* b : {&sc.s, &sc.md, &sc.mr, &sc.mt, &sc.ms, &sc.ones}) b->alloc(n1);
+    sc.part.alloc(1024);
+    launch_fill<T>(sc.ones.p, T(1), n1, s);
+  }
+
+  // Largest Ritz value of ten Arnoldi steps (classical Gram-Schmidt twice)
+  // of op from v0 (overwritten).
+  template <typename OP>
+  double arnoldi_lambda(size_t n, T* v0, OP op, hipStream_t s) {
+    constexpr int steps = 10;
+    DBuf<T> V((size_t)(steps + 1) * n);
+    DBuf<double> part(2 * kPartStride), hd(64);
+    const int nblk = dots_blocks(n, 256);
+    std::vector<double> H((steps + 1) * steps, 0.0), h(steps + 1), h2(steps + 1);
+    auto norm_of = [&](const T* x) {
+      launch_dots<T>(x, 1, n, x, n, part.p, nblk, s);
+      launch_dots_finish(part.p, 1, nblk, hd.p, nullptr, 2, s);
+      double v;
+      IBMG_HIP(hipMemcpyAsync(&v, hd.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      IBMG_HIP(hipStreamSynchronize(s));
+      return v;
+    };
+    const double b0 = norm_of(v0);
+    launch_scale<T>(v0, V.p, hd.p, n, s);
+    int k = steps;
+    for (int j = 0; j < steps; ++j) {
+      T* w = V.p + (size_t)(j + 1) * n;
+      op(V.p + (size_t)j * n, w);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots<T>(V.p, j + 1, n, w, n, part.p, nblk, s);
+        launch_dots_finish(part.p, j + 1, nblk, hd.p, nullptr, 0, s);
+        launch_update<T>(w, V.p, j + 1, n, hd.p, -1.0, n, s);
+        IBMG_HIP(hipMemcpyAsync(h2.data(), hd.p, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        IBMG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) H[i * steps + j] += h2[i];
+      }
+      const double hn = norm_of(w);
+      H[(j + 1) * steps + j] = hn;
+      if (hn == 0.0) {
+        k = j + 1;
+        break;
+      }
+      launch_scale<T>(w, w, hd.p, n, s);
+    }
+    (void)b0;
+    std::vector<double> Hk((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Hk[(size_t)i * k + j] = H[i * steps + j];
+    return hessenberg_max_real_eig(Hk, k);
+  }
+
+  void sc_numeric(Level<T>& lev, hipStream_t s) {
+    ScLevel<T>& sc = *lev.sc;
+    const int N = lev.N, NN = N * N;
+    const size_t n2 = 2 * (size_t)NN, n1 = NN;
+    sc.c = coef<T>(lev);
+    sc.tu = csr<T>(lev.f[0]);
+    sc.tv = csr<T>(lev.f[1]);
+    sc.ih2 = (T)((double)N * N);
+    launch_sc_diag<T>(N, sc.c, sc.tu, sc.tv, sc.ih2, sc.diag.p, sc.dinv.p, sc.mdiag.p, s);
+    const int nb1 = dots_blocks(n1, 256);
+    // lam for SGS(A_IB)^{-1} A_IB, start vector with the velocity means
+    // removed when rho = 0
+    DBuf<T> v0(n2);
+    launch_weyl<T>(v0.p, n2, s);
+    if (sc.rho_zero)
+      for (int c = 0; c < 2; ++c) {
+        launch_dots<T>(sc.ones.p, 1, n1, v0.p + (size_t)c * n1, n1, sc.part.p, nb1, s);
+        launch_sub_mean<T>(v0.p + (size_t)c * n1, n1, sc.part.p, nb1, s);
+      }
+    sc.lamA = arnoldi_lambda(n2, v0.p, [&](const T* x, T* y) {
+      launch_aib_apply<T>(x, sc.at.p, N, sc.c, sc.tu, sc.tv, s);
+      sc.sgs_a(sc.at.p, y, s);
+    }, s);
+    ScLevel<T>::cheb_coefs(sc.lamA, sc.its, &sc.a_theta_inv, sc.a_c1, sc.a_c2);
+    // lam for SGS(-M^)^{-1} (-D A~^{-1} G), mean-free start vector
+    DBuf<T> q0(n1);
+    launch_weyl<T>(q0.p, n1, s);
+    launch_dots<T>(sc.ones.p, 1, n1, q0.p, n1, sc.part.p, nb1, s);
+    launch_sub_mean<T>(q0.p, n1, sc.part.p, nb1, s);
+    sc.lamM = arnoldi_lambda(n1, q0.p, [&](const T* x, T* y) {
+      sc.schur_op(x, sc.mt.p, s);
+      sc.sgs_m(sc.mt.p, y, s);
+    }, s);
+    ScLevel<T>::cheb_coefs(sc.lamM, sc.its, &sc.m_theta_inv, sc.m_c1, sc.m_c2);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void build_coarse(hipStream_t s) {
+    Level<T>& lev = levels_[0];
+    const int N = lev.N;
+    const int nb = d_.rho == 0.0 ? 3 : 1;
+    n0_ = 3 * N * N;
+    const int nn = n0_ + nb;
+    DBuf<double> aug((size_t)nn * 2 * nn);
+    launch_fill<double>(aug.p, 0.0, aug.n, s);
+    launch_coarse_assemble(N, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p, lev.f[0].tval.p,
+                           lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p, nb, aug.p, s);
+    launch_coarse_invert(aug.p, nn, s);
+    inv0_.alloc((size_t)n0_ * n0_);
+    launch_coarse_extract(aug.p, nn, n0_, inv0_.p, s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void build_boxes(Level<T>& lev, hipStream_t s) {
+    const BoxGeom& g = lev.g;
+    const size_t per = (size_t)g.nloc * g.nloc;
+    lev.d_ib.upload(lev.ib_list, s);
+    lev.d_int.upload(lev.int_list, s);
+    lev.d_loc.upload(lev.loc_tab, s);
+    {
+      const int n_int = (int)lev.int_list.size();
+      const int ks = ras_interior_ksplit(g, n_int);
+      if (ks > 1 && lev.int_part.n < (size_t)ks * n_int * g.nch * 64)
+        lev.int_part.alloc((size_t)ks * n_int * g.nch * 64);
+    }
+    lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
+    const size_t budget = (size_t)1 << 30;
+    int batch = (int)std::max<size_t>(1, budget / ((per + (size_t)g.nloc * kGjNb) * sizeof(double)));
+    batch = std::min(batch, lev.n_unique);
+    DBuf<double> mats((size_t)batch * per);
+    DBuf<double> colk((size_t)batch * g.nloc * kGjNb);
+    DBuf<int> ids;
+    ids.upload(lev.uniq, s);
+    for (int b0 = 0; b0 < lev.n_unique; b0 += batch) {
+      const int cnt = std::min(batch, lev.n_unique - b0);
+      launch_patch_assemble(ids.p + b0, cnt, g, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p,
+                            lev.f[0].tval.p, lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p,
+                            mats.p, s);
+      launch_gj_invert(mats.p, g.nloc, cnt, colk.p, s);
+      launch_extract_owned<T>(mats.p, cnt, g, lev.inv.p + (size_t)b0 * box_stride(lev), s);
+    }
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void alloc_work(hipStream_t s) {
+    (void)s;
+    for (int l = 0; l <= L_; ++l) {
+      Level<T>& lev = levels_[l];
+      const size_t n = 3 * (size_t)lev.N * lev.N;
+      lev.w.alloc(n);
+      lev.b.alloc(n);
+      lev.r.alloc(n);
+      lev.t.alloc(n);
+      if (l >= 1) {
+        lev.V.alloc((size_t)(nu_ + 1) * n);
+        lev.Z.alloc((size_t)nu_ * n);
+      }
+      lev.F.alloc(2 * (size_t)std::max(M_, 1));
+      if (lev.use_spmv) {
+        lev.Gd.alloc(2 * (size_t)lev.N * lev.N);
+        if (std::is_same<T, float>::value) lev.Gt.alloc(2 * (size_t)lev.N * lev.N);
+      }
+      lev.H.alloc((size_t)(kMaxNu + 1) * kMaxNu);
+      lev.scal.alloc(64);
+      lev.part.alloc(2 * kPartStride);
+    }
+    Fd_.alloc(2 * (size_t)std::max(M_, 1));
+    Uw_.alloc(2 * (size_t)std::max(M_, 1));
+    Ul_.alloc(2 * (size_t)std::max(M_, 1));
+    IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
+  }
+
+  // --------------------------------------------------------------- views
+  template <typename U>
+  FootView<U> fview(CompFoot& f) {
+    if constexpr (std::is_same<U, double>::value)
+      return FootView<double>{f.d_base.p, f.w.p, f.d_sp_ptr.p, f.d_sp_ent.p};
+    else
+      return FootView<float>{f.d_base.p, f.wf.p, f.d_sp_ptr.p, f.d_sp_ent.p};
+  }
+  template <typename U>
+  SpringView<U> sview() {
+    if constexpr (std::is_same<U, double>::value)
+      return SpringView<double>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_k_.p};
+    else
+      return SpringView<float>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_kf_.p};
+  }
+  template <typename U>
+  StokesCoef<U> coef(Level<T>& lev) {
+    if constexpr (std::is_same<U, double>::value) return lev.cd;
+    else return StokesCoef<float>{(float)lev.cd.alpha, (float)lev.cd.beta, (float)lev.cd.gi, (float)lev.cd.ibs};
+  }
+
+  // y = L_IB^l x (b != null: y = b - L_IB^l x)
+  template <typename U>
+  void op(int l, const U* x, U* y, const U* b, bool trans, U* F, hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    const size_t nn = (size_t)lev.N * lev.N;
+    const U* Fp = nullptr;
+    const U* Gp = nullptr;
+    if (M_ > 0 && E_ > 0) {
+      if (lev.use_spmv) {
+        U* G = gbuf<U>(lev);
+        launch_ib_spmv<U>(x, G, csr<U>(lev.f[0]), csr<U>(lev.f[1]), lev.N, s);
+        Gp = G;
+      } else {
+        launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N, F, s);
+        Fp = F;
+      }
+    }
+    launch_apply<U>(x, y, b, Fp, Gp, fview<U>(lev.f[0]), fview<U>(lev.f[1]), lev.N, M_, coef<U>(lev),
+                    trans, s);
+  }
+
+  template <typename U>
+  CsrT<U> csr(CompFoot& f) {
+    if constexpr (std::is_same<U, double>::value)
+      return CsrT<double>{f.d_tptr.p, f.d_tcol.p, f.tval.p};
+    else
+      return CsrT<float>{f.d_tptr.p, f.d_tcol.p, f.tvalf.p};
+  }
+  template <typename U>
+  U* gbuf(Level<T>& lev) {
+    if constexpr (std::is_same<U, double>::value) return lev.Gd.p;
+    else return lev.Gt.p;
+  }
+
+  // ------------------------------------------------------- V-cycle pieces
+  void basic_smoother(int l, const T* v, T* z, hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    if (lev.sc) {
+      lev.sc->apply(v, z, s);
+      return;
+    }
+    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.d_ib.p, lev.n_ib,
+                        lev.inv.p + (size_t)lev.n_ib * box_stride(lev), lev.d_int.p,
+                        (int)lev.int_list.size(), lev.d_loc.p, lev.int_part.p, s);
+  }
+
+  // w <- w + e, e = nu FGMRES iterations (CGS2) on L e = b - L w from e = 0.
+  void smooth_t(int l, T* w, const T* b, int nu, bool w_zero, hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    const int nblk = dots_blocks(n, 1024);  // at most nu + 1 vectors
+    const int ldh = kMaxNu + 1;
+    const T* r0;
+    if (w_zero) {
+      launch_fill<T>(w, T(0), n, s);
+      r0 = b;
+    } else {
+      op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
+      r0 = lev.r.p;
+    }
+    double* beta = lev.scal.p;
+    double* pa = lev.part.p;
+    double* pb = lev.part.p + kPartStride;
+    launch_dots<T>(r0, 1, n, r0, n, pa, nblk, s);
+    T* V = lev.V.p;
+    T* Z = lev.Z.p;
+    launch_scale_red<T>(r0, V, n, pa, nblk, beta, s);
+    for (int k = 0; k < nu; ++k) {
+      T* vk = V + (size_t)k * n;
+      T* zk = Z + (size_t)k * n;
+      T* t = V + (size_t)(k + 1) * n;
+      basic_smoother(l, vk, zk, s);
+      op<T>(l, zk, t, nullptr, false, lev.F.p, s);
+      double* hcol = lev.H.p + (size_t)k * ldh;
+      orthogonalise<T>(V, k + 1, n, t, hcol, pa, pb, nblk, s);
+      launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
+    }
+    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s);
+  }
+
+  // Classical Gram-Schmidt twice against V[0..k): h (first pass + second
+  // pass) into hcol[0..k); the partial sums of ||t||^2 are left in pa for
+  // launch_scale_red, which stores ||t|| and normalises t.
+  template <typename U>
+  void orthogonalise(const U* V, int k, size_t n, U* t, double* hcol, double* pa, double* pb,
+                     int nblk, hipStream_t s) {
+    launch_dots<U>(V, k, n, t, n, pa, nblk, s);
+    launch_upd_dots<U>(t, V, k, n, n, pa, nblk, hcol, pb, s);
+    launch_upd_norm<U>(t, V, k, n, n, pb, nblk, hcol, pa, s);
+  }
+
+  // w = MG(0, b) on level l (Alg. 1)
+  void mg(int l, const T* b, T* w, hipStream_t s) {
+    if (l == 0) {
+      launch_coarse_apply<T>(inv0_.p, n0_, b, w, s);
+      return;
+    }
+    Level<T>& lev = levels_[l];
+    Level<T>& crs = levels_[l - 1];
+    smooth_t(l, w, b, d_.nu1, true, s);
+    op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
+    launch_restrict<T>(lev.r.p, crs.b.p, crs.N, s);
+    mg(l - 1, crs.b.p, crs.w.p, s);
+    launch_prolong_add<T>(crs.w.p, w, crs.N, s);
+    smooth_t(l, w, b, d_.nu2, false, s);
+  }
+
+  // ------------------------------------------------------------ ABI calls
+  void apply(int level, const double* w, double* y, bool trans, hipStream_t s) override {
+    op<double>(level, w, y, nullptr, trans, Fd_.p, s);
+  }
+
+  void spread(const double* F, double* f, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    const double h = 1.0 / lev.N;
+    launch_spread(F, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, 1.0 / (h * h), f, s);
+  }
+
+  void interp(const double* u, double* U, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    launch_interp<double>(u, u + (size_t)lev.N * lev.N, fview<double>(lev.f[0]), fview<double>(lev.f[1]),
+                          M_, lev.N, U, s);
+  }
+
+  void restrict_(int level, const double* fine, double* coarse, hipStream_t s) override {
+    launch_restrict<double>(fine, coarse, levels_[level - 1].N, s);
+  }
+
+  void prolong_add(int level, const double* coarse, double* fine, hipStream_t s) override {
+    launch_prolong_add<double>(coarse, fine, levels_[level - 1].N, s);
+  }
+
+  void smoother_apply(int level, const double* r, double* z, hipStream_t s) override {
+    Level<T>& lev = levels_[level];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    if constexpr (std::is_same<T, double>::value) {
+      basic_smoother(level, r, z, s);
+    } else {
+      launch_cast<double, T>(r, lev.r.p, n, s);
+      basic_smoother(level, lev.r.p, lev.t.p, s);
+      launch_cast<T, double>(lev.t.p, z, n, s);
+    }
+  }
+
+  void smooth(int level, double* w, const double* b, int nu, hipStream_t s) override {
+    require(nu >= 1 && nu <= nu_, "nu must lie in [1, max(nu1, nu2)]");
+    Level<T>& lev = levels_[level];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    if constexpr (std::is_same<T, double>::value) {
+      smooth_t(level, w, b, nu, false, s);
+    } else {
+      launch_cast<double, T>(w, lev.w.p, n, s);
+      launch_cast<double, T>(b, lev.b.p, n, s);
+      smooth_t(level, lev.w.p, lev.b.p, nu, false, s);
+      launch_cast<T, double>(lev.w.p, w, n, s);
+    }
+  }
+
+  void coarse_solve(const double* r, double* x, hipStream_t s) override {
+    launch_coarse_apply<double>(inv0_.p, n0_, r, x, s);
+  }
+
+  void vcycle_body(const double* r, double* z, hipStream_t s) {
+    Level<T>& top = levels_[L_];
+    const size_t n = 3 * (size_t)top.N * top.N;
+    if constexpr (std::is_same<T, double>::value) {
+      mg(L_, r, z, s);
+    } else {
+      launch_cast<double, T>(r, top.b.p, n, s);
+      mg(L_, top.b.p, top.w.p, s);
+      launch_cast<T, double>(top.w.p, z, n, s);
+    }
+  }
+
+  // The whole V-cycle (several hundred launches, no host synchronisation)
+  // is captured once into a HIP graph reading vin_ and writing vout_, then
+  // replayed; the graph holds kernel nodes only.
+  void build_graph() {
+    const size_t n = 3 * (size_t)d_.N * d_.N;
+    vin_.alloc(n);
+    vout_.alloc(n);
+    if (!gstream_) IBMG_HIP(hipStreamCreateWithFlags(&gstream_, hipStreamNonBlocking));
+    IBMG_HIP(hipStreamBeginCapture(gstream_, hipStreamCaptureModeThreadLocal));
+    try {
+      vcycle_body(vin_.p, vout_.p, gstream_);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(gstream_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    IBMG_HIP(hipStreamEndCapture(gstream_, &graph_));
+    IBMG_HIP(hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0));
+  }
+
+  void drop_graph() {
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    gexec_ = nullptr;
+    graph_ = nullptr;
+  }
+
+  void vcycle(const double* r, double* z, hipStream_t s) override {
+    if (!use_graph_) {
+      vcycle_body(r, z, s);
+      return;
+    }
+    const size_t n = 3 * (size_t)d_.N * d_.N;
+    if (!gexec_) build_graph();
+    IBMG_HIP(hipMemcpyAsync(vin_.p, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IBMG_HIP(hipGraphLaunch(gexec_, s));
+    IBMG_HIP(hipMemcpyAsync(z, vout_.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+
+  double read_scalar(const double* dptr, hipStream_t s) {
+    IBMG_HIP(hipMemcpyAsync(pinned_, dptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    return pinned_[0];
+  }
+
+  void ensure_outer(int restart) {
+    const size_t n = 3 * (size_t)d_.N * d_.N;
+    if (restart <= outer_cap_) return;
+    Vo_.alloc((size_t)(restart + 1) * n);
+    Zo_.alloc((size_t)restart * n);
+    Ho_.alloc((size_t)(restart + 1) * restart);
+    cs_.alloc(restart + 1);
+    sn_.alloc(restart + 1);
+    g_.alloc(restart + 2);
+    y_.alloc(restart + 1);
+    osc_.alloc(256);
+    opart_.alloc(2 * kPartStride);
+    bp_.alloc(n);
+    rr_.alloc(n);
+    outer_cap_ = restart;
+  }
+
+  void project(double* a, hipStream_t s) {
+    Level<T>& top = levels_[L_];
+    launch_block_sums<double>(a, top.N, opart_.p, 64, s);
+    launch_dots_finish(opart_.p, 3, 64, osc_.p + 8, nullptr, 0, s);
+    launch_subtract_means<double>(a, top.N, osc_.p + 8, d_.rho == 0.0 ? 1 : 0, s);
+  }
+
+  double norm(const double* a, size_t n, hipStream_t s) {
+    const int nblk = dots_blocks(n);
+    launch_dots<double>(a, 1, n, a, n, opart_.p, nblk, s);
+    launch_dots_finish(opart_.p, 1, nblk, osc_.p + 0, nullptr, 2, s);
+    return read_scalar(osc_.p + 0, s);
+  }
+
+  int fgmres(const double* b, double* x, const ibmg_solve_opts& o, ibmg_solve_info* info,
+             hipStream_t s) override {
+    const auto t0 = std::chrono::steady_clock::now();
+    require(o.restart >= 1 && o.restart <= kMaxRestart, "restart must lie in [1, 64]");
+    require(o.max_it >= 1, "max_it must be >= 1");
+    require(std::isfinite(o.rtol) && o.rtol > 0.0, "rtol must be finite and > 0");
+    ensure_outer(o.restart);
+    // the adjoint system uses the transposed operator path; L_IB is
+    // symmetric, so the same V-cycle preconditions it
+    const bool trans = o.transpose != 0;
+    const int N = d_.N;
+    const size_t n = 3 * (size_t)N * N;
+    const int nblk = dots_blocks(n);
+    const int ldh = o.restart + 1;
+    int hist_n = 0;
+    auto push_hist = [&](double v) {
+      if (info && info->history && hist_n < info->history_cap) info->history[hist_n] = v;
+      ++hist_n;
+    };
+    // projected right-hand side and the removed null-space part
+    IBMG_HIP(hipMemcpyAsync(bp_.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    project(bp_.p, s);
+    IBMG_HIP(hipMemcpyAsync(pinned_, osc_.p + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    const double nn = (double)N * N;
+    double null2 = pinned_[2] * pinned_[2] / nn;
+    if (d_.rho == 0.0) null2 += (pinned_[0] * pinned_[0] + pinned_[1] * pinned_[1]) / nn;
+    const double bnorm = norm(bp_.p, n, s);
+    if (info) {
+      info->iters = 0;
+      info->restarts = 0;
+      info->rhs_null_norm = std::sqrt(null2);
+      info->vcycles = 0;
+    }
+    if (!std::isfinite(bnorm) || !std::isfinite(null2)) throw Error(IBMG_ERR_NONFINITE, "right-hand side holds NaN/Inf");
+    if (!o.use_x0) launch_fill<double>(x, 0.0, n, s);
+    if (bnorm == 0.0) {
+      launch_fill<double>(x, 0.0, n, s);
+      IBMG_HIP(hipStreamSynchronize(s));
+      if (info) {
+        info->rel_res_est = info->rel_res_true = 0.0;
+        info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      return IBMG_OK;
+    }
+    const double target = o.rtol * bnorm;
+    int its = 0, restarts = 0, vcycles = 0;
+    bool converged = false;
+    double est = bnorm;
+    while (its < o.max_it) {
+      double* V0 = Vo_.p;
+      op<double>(L_, x, V0, bp_.p, trans, Fd_.p, s);
+      const double beta = norm(V0, n, s);
+      if (!std::isfinite(beta)) throw Error(IBMG_ERR_NONFINITE, "residual is not finite");
+      est = beta;
+      if (beta <= target) { converged = true; break; }
+      launch_scale<double>(V0, V0, osc_.p + 0, n, s);
+      launch_fill<double>(g_.p, 0.0, (size_t)o.restart + 2, s);
+      IBMG_HIP(hipMemcpyAsync(g_.p, osc_.p + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
+      int k = 0;
+      for (; k < o.restart && its < o.max_it;) {
+        double* vk = Vo_.p + (size_t)k * n;
+        double* zk = Zo_.p + (size_t)k * n;
+        double* t = Vo_.p + (size_t)(k + 1) * n;
+        vcycle(vk, zk, s);
+        ++vcycles;
+        op<double>(L_, zk, t, nullptr, trans, Fd_.p, s);
+        double* hcol = Ho_.p + (size_t)k * ldh;
+        orthogonalise<double>(Vo_.p, k + 1, n, t, hcol, opart_.p, opart_.p + kPartStride, nblk, s);
+        launch_scale_red<double>(t, t, n, opart_.p, nblk, hcol + k + 1, s);
+        launch_givens(Ho_.p, ldh, k, cs_.p, sn_.p, g_.p, osc_.p + 1, s);
+        est = read_scalar(osc_.p + 1, s);
+        ++k;
+        ++its;
+        push_hist(est / bnorm);
+        if (!std::isfinite(est)) throw Error(IBMG_ERR_NONFINITE, "iteration produced NaN/Inf");
+        if (est <= target) { converged = true; break; }
+      }
+      launch_backsolve(Ho_.p, ldh, k, g_.p, y_.p, s);
+      launch_combine<double>(x, Zo_.p, k, n, y_.p, n, s);
+      ++restarts;
+      if (converged) break;
+    }
+    project(x, s);
+    op<double>(L_, x, rr_.p, bp_.p, trans, Fd_.p, s);
+    const double tr = norm(rr_.p, n, s);
+    if (info) {
+      info->iters = its;
+      info->restarts = restarts;
+      info->rel_res_est = est / bnorm;
+      info->rel_res_true = tr / bnorm;
+      info->vcycles = vcycles;
+      info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!std::isfinite(tr)) throw Error(IBMG_ERR_NONFINITE, "solution is not finite");
+    return converged ? IBMG_OK : IBMG_NOT_CONVERGED;
+  }
+
+  void spring_gradient(const double* w, const double* lam, double* out, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    const size_t nn = (size_t)lev.N * lev.N;
+    const double h = 1.0 / lev.N;
+    launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw_.p, s);
+    launch_interp<double>(lam, lam + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Ul_.p, s);
+    launch_spring_grad(Uw_.p, Ul_.p, d_ends_.p, nullptr, E_, M_, -d_.dt / (h * h), out, s);
+  }
+
+  void set_kappa(const double* kappa, hipStream_t s) override {
+    require(E_ == 0 || kappa != nullptr, "kappa is NULL");
+    for (int e = 0; e < E_; ++e)
+      require(std::isfinite(kappa[e]) && kappa[e] >= 0.0, "kappa must be finite and >= 0");
+    kappa_.assign(kappa, kappa + E_);
+    drop_graph();  // the box inverses are reallocated
+    build_numeric(s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void sc_info(int level, double* lam, int32_t* colours) const override {
+    require(level >= 1 && level <= L_, "level out of range");
+    const Level<T>& lev = levels_[level];
+    require(lev.sc != nullptr, "the handle does not use the Schur-complement smoother");
+    lam[0] = lev.sc->lamA;
+    lam[1] = lev.sc->lamM;
+    colours[0] = lev.sc->colu.ncol;
+    colours[1] = lev.sc->colp.ncol;
+  }
+
+  std::vector<int64_t> stats() const override {
+    std::vector<int64_t> v;
+    v.push_back(L_ + 1);
+    for (int l = 0; l <= L_; ++l) {
+      const Level<T>& lev = levels_[l];
+      v.push_back(lev.N);
+      v.push_back((int64_t)lev.g.npd * lev.g.npd);
+      v.push_back(lev.n_unique);
+      v.push_back(lev.n_ib);
+      v.push_back((int64_t)lev.f[0].tcol.size() + (int64_t)lev.f[1].tcol.size());
+    }
+    return v;
+  }
+
+ private:
+  ibmg_desc d_;
+  int M_ = 0, E_ = 0, nu_ = 2, L_ = 0, n0_ = 0;
+  std::vector<double> X_, kappa_;
+  std::vector<int> ends_, sizes_;
+  std::vector<int> adj_ptr_, adj_nbr_, adj_sid_;
+  DBuf<int> d_adj_ptr_, d_adj_nbr_, d_ends_;
+  DBuf<double> d_adj_k_, d_X_;
+  DBuf<float> d_adj_kf_;
+  std::vector<Level<T>> levels_;
+  DBuf<double> inv0_;
+  DBuf<double> Fd_, Uw_, Ul_;
+  // outer FGMRES
+  int outer_cap_ = 0;
+  DBuf<double> Vo_, Zo_, Ho_, cs_, sn_, g_, y_, osc_, opart_, bp_, rr_;
+  double* pinned_ = nullptr;
+  // V-cycle graph
+  bool use_graph_ = graphs_enabled();
+  hipStream_t gstream_ = nullptr;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t gexec_ = nullptr;
+  DBuf<double> vin_, vout_;
+
+  static bool graphs_enabled() {
+    const char* e = std::getenv("IBMG_GRAPH");
+    return !(e && e[0] == '0');
+  }
+};
+
+}  // namespace ibmg

@@ -1,4 +1,5 @@
-"""Python binding of libibmg: one ``StokesIB`` object per Stokes-IB system.
+"""Python binding of libibmg: one ``StokesIB`` object per Stokes-IB system,
+or one ``StokesIBBatch`` for many independent systems solved together.
 
 Only argument marshalling happens here: torch supplies device memory and the
 current HIP stream, every computation runs in the library's kernels.  Vectors
@@ -37,6 +38,35 @@ def _dev_vec(t, n, name):
     return t
 
 
+def _make_desc(system, precision):
+    """ibmg_desc of a system description; returns it with the host arrays it
+    points into (keep them alive while the descriptor is in use)."""
+    X = np.ascontiguousarray(system.X, dtype=np.float64)
+    springs = np.ascontiguousarray(system.springs, dtype=np.int32)
+    kappa = np.ascontiguousarray(system.kappa, dtype=np.float64)
+    d = _lib.Desc()
+    d.N = int(system.N)
+    d.coarse_N = int(system.coarse_N)
+    d.rho, d.mu, d.dt = float(system.rho), float(system.mu), float(system.dt)
+    d.M = int(X.shape[0])
+    d.X = X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.n_springs = int(springs.shape[0])
+    d.ends = springs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.kappa = kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.smoother = {"ras": _lib.RAS, "sc": _lib.SC}[getattr(system, "smoother", "ras")]
+    d.box = int(getattr(system, "box", 8))
+    d.overlap = int(getattr(system, "overlap", 2))
+    d.nu1 = int(getattr(system, "nu1", 2))
+    d.nu2 = int(getattr(system, "nu2", 2))
+    d.cheb_its = int(getattr(system, "cheb_its", 2))
+    d.precision = {"fp64": _lib.FP64, "fp32": _lib.FP32_SMOOTHER}[precision]
+    return d, (X, springs, kappa)
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
 class StokesIB:
     """Multigrid-preconditioned solver for one periodic Stokes-IB system.
 
@@ -48,29 +78,12 @@ class StokesIB:
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("StokesIB needs a HIP device")
-        self.N = int(system.N)
-        self.X = np.ascontiguousarray(system.X, dtype=np.float64)
-        self.springs = np.ascontiguousarray(system.springs, dtype=np.int32)
-        self.kappa = np.ascontiguousarray(system.kappa, dtype=np.float64)
-        self.M = int(self.X.shape[0])
-        self.E = int(self.springs.shape[0])
-        self.rho = float(system.rho)
-        d = _lib.Desc()
-        d.N = self.N
-        d.coarse_N = int(system.coarse_N)
-        d.rho, d.mu, d.dt = float(system.rho), float(system.mu), float(system.dt)
-        d.M = self.M
-        d.X = self.X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        d.n_springs = self.E
-        d.ends = self.springs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        d.kappa = self.kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        d.smoother = {"ras": _lib.RAS, "sc": _lib.SC}[getattr(system, "smoother", "ras")]
-        d.box = int(getattr(system, "box", 8))
-        d.overlap = int(getattr(system, "overlap", 2))
-        d.nu1 = int(getattr(system, "nu1", 2))
-        d.nu2 = int(getattr(system, "nu2", 2))
-        d.cheb_its = int(getattr(system, "cheb_its", 2))
-        d.precision = {"fp64": _lib.FP64, "fp32": _lib.FP32_SMOOTHER}[precision]
+        d, keep = _make_desc(system, precision)
+        self.N = d.N
+        self.X, self.springs, self.kappa = keep
+        self.M = d.M
+        self.E = d.n_springs
+        self.rho = d.rho
         self.precision = precision
         self.desc = d
         h = ctypes.c_void_p()
@@ -225,4 +238,97 @@ class StokesIB:
         for l in range(v[0]):
             N, boxes, uniq, ib, tnnz = v[1 + 5 * l:6 + 5 * l]
             out["levels"].append(dict(N=N, boxes=boxes, unique_boxes=uniq, ib_boxes=ib, ib_nnz=tnnz))
+        return out
+
+
+class StokesIBBatch:
+    """Many independent periodic Stokes-IB systems solved together (one
+    persistent launch per smoother sweep across all of them).  ``systems`` is
+    a list of system descriptions as for ``StokesIB``; they may differ in N,
+    structure and stiffness but must share the fluid and box parameters."""
+
+    def __init__(self, systems, precision="fp32"):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("StokesIBBatch needs a HIP device")
+        descs = (_lib.Desc * len(systems))()
+        keep = []
+        for i, sy in enumerate(systems):
+            d, k = _make_desc(sy, precision)
+            descs[i] = d
+            keep.append(k)
+        self.nsys = len(systems)
+        self.sizes = [int(sy.N) for sy in systems]
+        self.precision = precision
+        h = ctypes.c_void_p()
+        st = self.lib.ibmg_batch_create(self.nsys, descs, _stream(), ctypes.byref(h))
+        if st != 0:
+            raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st, ok=(0,)):
+        if st not in ok:
+            raise IbmgError(st, self.lib.ibmg_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ibmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vecs(self, ts, name):
+        if len(ts) != self.nsys:
+            raise ValueError(f"{name} must hold {self.nsys} vectors")
+        for i, t in enumerate(ts):
+            _dev_vec(t, 3 * self.sizes[i] ** 2, f"{name}[{i}]")
+        return ts
+
+    def vcycle(self, rs):
+        self._vecs(rs, "r")
+        zs = [torch.empty(3 * N * N, dtype=torch.float64, device="cuda") for N in self.sizes]
+        self._check(self.lib.ibmg_batch_vcycle(self.h, _ptr_array(rs), _ptr_array(zs), _stream()))
+        return zs
+
+    def solve(self, bs, rtol=1e-8, restart=30, max_it=100, x0=None, history=128):
+        self._vecs(bs, "b")
+        if x0 is not None:
+            xs = [x.clone() for x in self._vecs(x0, "x0")]
+        else:
+            xs = [torch.empty(3 * N * N, dtype=torch.float64, device="cuda") for N in self.sizes]
+        o = _lib.SolveOpts(float(rtol), int(restart), int(max_it), 1 if x0 is not None else 0, 0)
+        infos = (_lib.SolveInfo * self.nsys)()
+        hists = []
+        for i in range(self.nsys):
+            hb = (ctypes.c_double * history)()
+            hists.append(hb)
+            infos[i].history = ctypes.cast(hb, ctypes.POINTER(ctypes.c_double))
+            infos[i].history_cap = history
+        st = self._check(self.lib.ibmg_batch_fgmres_solve(self.h, _ptr_array(bs), _ptr_array(xs),
+                                                          ctypes.byref(o), infos, _stream()), ok=(0, 1))
+        out = []
+        for i in range(self.nsys):
+            inf = infos[i]
+            k = min(inf.iters, history)
+            out.append(dict(converged=inf.rel_res_est <= rtol, iters=inf.iters, restarts=inf.restarts,
+                            rel_res_est=inf.rel_res_est, rel_res_true=inf.rel_res_true,
+                            rhs_null_norm=inf.rhs_null_norm, solve_ms=inf.solve_ms, vcycles=inf.vcycles,
+                            history=list(hists[i][:k])))
+        return xs, dict(status=_STATUS[st], converged=st == 0, systems=out)
+
+    def stats(self):
+        buf = (ctypes.c_int64 * 1024)()
+        wr = ctypes.c_int32()
+        self._check(self.lib.ibmg_batch_stats(self.h, buf, 1024, ctypes.byref(wr)))
+        v = list(buf[:wr.value])
+        out = dict(nsys=v[0], levels=[])
+        for l in range(v[1]):
+            N, nact, n_int, n_ib, rows, tb, grid, ns = v[2 + 8 * l:10 + 8 * l]
+            out["levels"].append(dict(N=N, systems=nact, interior_boxes=n_int, ib_boxes=n_ib, ib_rows=rows,
+                                      tile=tb, grid=grid, sweep_us=ns / 1e3))
         return out

@@ -74,3 +74,40 @@ def test_create_rejects_bad_descriptors_without_a_device():
     d.ends = e2.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     assert lib.ibmg_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.IBMG_ERR_ARG
     assert lib.ibmg_destroy(None) == _lib.IBMG_ERR_STATE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libibmg.so not built")
+def test_batch_create_rejects_mismatched_systems_without_a_device():
+    """The batched form checks every descriptor and the shared parameters on
+    the host; single-system calls on no handle report a state error."""
+    import numpy as np
+    from paper_1612_02208_amd import _lib
+    lib = _lib.load()
+    X = np.array([[0.5, 0.5], [0.6, 0.5]])
+    ends = np.array([[0, 1]], dtype=np.int32)
+    kap = np.array([1.0])
+
+    def descs(n, changes=None):
+        arr = (_lib.Desc * n)()
+        for i in range(n):
+            d = arr[i]
+            d.N, d.coarse_N, d.rho, d.mu, d.dt = 32 if i % 2 == 0 else 64, 8, 0.0, 1.0, 1e-3
+            d.M, d.n_springs = 2, 1
+            d.X = X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.ends = ends.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.kappa = kap.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.smoother, d.box, d.overlap, d.nu1, d.nu2, d.cheb_its, d.precision = 0, 8, 2, 2, 2, 2, 1
+        for (i, k), v in (changes or {}).items():
+            setattr(arr[i], k, v)
+        return arr
+
+    h = ctypes.c_void_p()
+    for bad in ({(1, "mu"): 0.5}, {(1, "box"): 4}, {(0, "smoother"): 1}, {(1, "precision"): 0},
+                {(1, "rho"): 1.0}, {(1, "N"): 40}, {(0, "dt"): 2e-3}):
+        st = lib.ibmg_batch_create(3, descs(3, bad), None, ctypes.byref(h))
+        assert st == _lib.IBMG_ERR_ARG, (bad, st)
+        assert lib.ibmg_last_error(None)
+    assert lib.ibmg_batch_create(0, descs(1), None, ctypes.byref(h)) == _lib.IBMG_ERR_ARG
+    n = ctypes.c_int32()
+    assert lib.ibmg_batch_size(None, ctypes.byref(n)) == _lib.IBMG_ERR_STATE
+    assert lib.ibmg_batch_vcycle(None, None, None, None) == _lib.IBMG_ERR_STATE
