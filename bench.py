@@ -11,9 +11,17 @@ One step = one FP64 solve plus one FP32-smoother solve of the same
 right-hand side, both to 1e-8 (set-up excluded; inputs resident in HBM).
 ``value`` = V-cycles applied in the timed steps / timed wall time.
 
+Also reported: the roofline of the dominant kernel (k_ras_ib<double>, the
+finest level's Schwarz boxes with their own inverse), timed alone with HIP
+events on the stream it runs on; the other hot kernels; the batched form on
+64 independent systems (N in {64, 128, 256}, FP32 smoother); and the FP64 CPU
+oracle on a bounded sample of the same workload.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-baseline sample|off]
+                    [--batch on|off]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +34,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solve time to 1e-8 rel-res & V-cycles/s at N=512; FP32 smoother vs FP64"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_ras_ib_annulus512.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1612_02208_amd", "csrc", "dense_kernels.hip")
 
 
 def parse():
@@ -42,14 +54,65 @@ def parse():
     # here they need 30 iterations against 76 for 8 x 8 / 2 and solve faster
     p.add_argument("--box", type=int, default=16)
     p.add_argument("--overlap", type=int, default=4)
+    p.add_argument("--batch", default="on", choices=["on", "off"])
     return p.parse_args()
 
 
-def box_geometry(N, box=8, overlap=2):
-    b = min(box, N // 2)
-    o = max(0, min(overlap, (N - b - 1) // 2))
-    m = b + 2 * o
-    return b, o, m, 2 * m * (m + 1) + m * m, 3 * b * b
+def measured_traffic(alg_bytes):
+    """HBM bytes per launch of k_ras_ib<double> from the committed
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes, each scaled by what the
+    same counter reads for a plain copy of known size; None when no
+    counters are recorded or the kernel source changed since they were."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    f_fetch = rec["copy_bytes_read"] / (rec["copy_fetch_kib"] * 1024.0)
+    f_write = rec["copy_bytes_written"] / (rec["copy_write_kib"] * 1024.0)
+    return rec["fetch_kib"] * 1024.0 * f_fetch + rec["write_kib"] * 1024.0 * f_write
+
+
+def batch_bench(dev, reps=3):
+    """The batched form: 64 independent systems (N in {64, 128, 256}, kappa
+    log-uniform in [1e1, 1e5], membranes of 4N points), FP32 smoother, each
+    solved to 1e-8; set-up (with the tile autotuner) timed separately."""
+    import torch
+    import workloads as W
+    from paper_1612_02208_amd import StokesIBBatch
+    systems = W.batch_systems(64)
+    t0 = time.perf_counter()
+    B = StokesIBBatch(systems, precision="fp32")
+    setup = time.perf_counter() - t0
+    bs = [torch.from_numpy(W.rhs(s.N, s.rhs_seed)).to(dev) for s in systems]
+    B.solve(bs, rtol=1e-8)
+    torch.cuda.synchronize()
+    times, info = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, info = B.solve(bs, rtol=1e-8)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    its = [si["iters"] for si in info["systems"]]
+    st = B.stats()
+    top = st["levels"][-1]
+    kt = B.kernel_time("ras_batch", -1, 20)
+    out = {"workload": "64 systems, N in {64,128,256} (counts %s), Stokes mu=1 dt=1e-3, membranes r~U[0.15,0.3] "
+                       "with 4N points, kappa log-uniform [1e1,1e5], RAS 8x8/2, FP32 smoother, FGMRES to 1e-8"
+                       % {n: sum(1 for s in systems if s.N == n) for n in (64, 128, 256)},
+           "converged": info["converged"], "solve_ms": 1e3 * t, "systems_per_s": 64 / t,
+           "vcycles_per_s": sum(its) / t, "iters_min": min(its), "iters_max": max(its),
+           "max_rel_res_true": max(si["rel_res_true"] for si in info["systems"]), "setup_s": setup,
+           "tuned_plans": [dict(N=lv["N"], systems=lv["systems"], tile=lv["tile"], grid=lv["grid"],
+                                sweep_us=lv["sweep_us"]) for lv in st["levels"][1:]],
+           "ras_batch_finest": {"kernel": "k_ras_batch<float>", "N": top["N"], "systems": top["systems"],
+                                "avg_ms": kt["ms"], "alg_bytes": kt["bytes"],
+                                "achieved_gbs": kt["bytes"] / kt["ms"] / 1e6,
+                                "frac_hbm": kt["bytes"] / kt["ms"] / 1e6 / HBM_PEAK_GBS}}
+    B.close()
+    return out
 
 
 def cpu_baseline(wl, nboxes):
@@ -156,25 +219,28 @@ def main():
 
     vc64, vc32 = vc_rate(g64), vc_rate(g32)
 
-    # roofline of the dominant kernel: the finest-level restricted additive
-    # Schwarz application (one launch per smoother_apply on the FP64 handle),
-    # timed with HIP events on the stream it is launched on.
-    st = g64.stats()["levels"][-1]
-    bb, oo, m, nloc, nown = box_geometry(wl.N, wl.box, wl.overlap)
-    n = 3 * wl.N * wl.N
-    alg_bytes = (st["unique_boxes"]) * nloc * nown * 8 + 2 * n * 8
-    r = torch.from_numpy(b_h).to(dev)
-    stream = torch.cuda.current_stream()
-    g64.smoother_apply(-1, r)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(a.roofline_reps):
-        g64.smoother_apply(-1, r)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ras_ms = ev0.elapsed_time(ev1) / a.roofline_reps
+    # roofline of the dominant kernel: k_ras_ib<double>, the finest level's
+    # Schwarz boxes with their own inverse (HBM streaming of the owned
+    # inverse rows), launched alone by the library with HIP events on this
+    # stream; the other hot kernels for reference
+    kt = g64.kernel_time("ras_ib", -1, a.roofline_reps)
+    ras_ms, alg_bytes = kt["ms"], kt["bytes"]
     achieved = alg_bytes / (ras_ms * 1e-3) / 1e9
+    traffic = measured_traffic(alg_bytes)
+    kernels = {}
+    for g, tag, peak in ((g64, "double", FP64_MFMA_PEAK_TFS), (g32, "float", FP32_MFMA_PEAK_TFS)):
+        ib = g.kernel_time("ras_ib", -1, a.roofline_reps)
+        it = g.kernel_time("ras_interior", -1, a.roofline_reps)
+        sc = g.kernel_time("stencil", -1, a.roofline_reps)
+        kernels[f"k_ras_ib<{tag}>"] = {"bound": "hbm", "avg_ms": ib["ms"], "alg_bytes": ib["bytes"],
+                                       "gbs": ib["bytes"] / ib["ms"] / 1e6,
+                                       "frac": ib["bytes"] / ib["ms"] / 1e6 / HBM_PEAK_GBS}
+        kernels[f"k_ras_interior<{tag}>"] = {"bound": "mfma", "avg_ms": it["ms"], "alg_flops": it["flops"],
+                                             "tflops": it["flops"] / it["ms"] / 1e9,
+                                             "frac": it["flops"] / it["ms"] / 1e9 / peak}
+        kernels[f"k_apply<{tag}>"] = {"bound": "hbm", "avg_ms": sc["ms"], "alg_bytes": sc["bytes"],
+                                      "gbs": sc["bytes"] / sc["ms"] / 1e6,
+                                      "frac": sc["bytes"] / sc["ms"] / 1e6 / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC,
@@ -202,11 +268,16 @@ def main():
         "fp32_vs_fp64_rel_diff": diff,
         "vcycles_per_s_fp64": vc64, "vcycles_per_s_fp32": vc32,
         "setup_s_fp64": t_setup64, "setup_s_fp32": t_setup32,
-        "roofline": {"bound": "hbm", "kernel": "k_ras_apply<double> (finest level)",
+        "roofline": {"bound": "hbm", "kernel": "k_ras_ib<double> (finest level)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launch_ms": ras_ms, "alg_bytes_per_launch": alg_bytes},
+        "kernels": kernels,
     }
+    if a.batch == "on":
+        t0 = time.perf_counter()
+        out["batch"] = batch_bench(dev)
+        print(f"[bench] batch form {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if a.cpu_baseline != "off":
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_boxes)

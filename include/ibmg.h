@@ -182,6 +182,35 @@ ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t*
  * Schwarz smoother. */
 ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32_t* colours);
 
+/* Single-kernel timing, for benchmarks and profilers that price a kernel
+ * against the hardware's roofline.  Launches one kernel of `level` alone,
+ * once untimed and then `reps` times between two HIP events recorded on
+ * ``stream`` (the stream the kernel runs on), on the handle's own work
+ * vectors filled with ones, and returns the average duration of one launch in
+ * *avg_ms with the kernel's algorithmic bytes and flops per launch (nullable
+ * outputs).  Kernels:
+ *   IBMG_KERNEL_RAS_IB        Schwarz boxes with their own inverse (k_ras_ib):
+ *                             n_ib (nown nloc + nloc + nown) values, 2 n_ib nown
+ *                             nloc flops
+ *   IBMG_KERNEL_RAS_INTERIOR  interior boxes on the matrix cores
+ *                             (k_ras_interior, one launch): the shared inverse
+ *                             once plus n_int (nloc + nown) values, 2 n_int nown
+ *                             nloc flops
+ *   IBMG_KERNEL_STENCIL       the Stokes stencil k_apply (no IB term): 6 N^2
+ *                             values
+ *   IBMG_KERNEL_RAS_BATCH     (batch handles) the persistent batched Schwarz
+ *                             launch of a level with its tuned plan
+ * Synchronises ``stream``; IBMG_ERR_ARG if the level has no such work. */
+typedef enum {
+  IBMG_KERNEL_RAS_IB = 0,
+  IBMG_KERNEL_RAS_INTERIOR = 1,
+  IBMG_KERNEL_STENCIL = 2,
+  IBMG_KERNEL_RAS_BATCH = 3
+} ibmg_kernel;
+ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int32_t reps,
+                             ibmg_stream stream, double* avg_ms, double* alg_bytes,
+                             double* alg_flops);
+
 /* ------------------------------------------------------------------------
  * Batched form: nsys independent systems, each described by its own
  * ibmg_desc (grid size N, structure, stiffness), solved together.  All

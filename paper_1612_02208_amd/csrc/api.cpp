@@ -136,6 +136,23 @@ ibmg_status ibmg_batch_fgmres_solve(ibmg_handle* h, const double* const* b, doub
   });
 }
 
+ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int32_t reps, ibmg_stream st,
+                             double* avg_ms, double* alg_bytes, double* alg_flops) {
+  if (!h || (!h->s && !h->b)) return IBMG_ERR_STATE;
+  if (!avg_ms) return IBMG_ERR_ARG;
+  try {
+    *avg_ms = h->s ? h->s->kernel_time(kernel, level, reps, S(st), alg_bytes, alg_flops)
+                   : h->b->kernel_time(kernel, level, reps, S(st), alg_bytes, alg_flops);
+    return IBMG_OK;
+  } catch (const ibmg::Error& e) {
+    h->err = e.what();
+    return (ibmg_status)e.code;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return IBMG_ERR_HIP;
+  }
+}
+
 ibmg_status ibmg_batch_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written) {
   if (!h || !h->b) return IBMG_ERR_STATE;
   if (!written || (cap > 0 && !out)) return IBMG_ERR_ARG;

@@ -631,6 +631,28 @@ class BatchSolver final : public BatchBase {
     return all ? IBMG_OK : IBMG_NOT_CONVERGED;
   }
 
+  // The persistent Schwarz launch of a batch level alone, on the level's
+  // work vectors (filled with ones), with the tuned plan.  Algorithmic work:
+  // each IB box streams its owned inverse rows, the interior product reads
+  // the shared inverse once; every box gathers nloc values and writes nown.
+  double kernel_time(int kernel, int level, int reps, hipStream_t s, double* bytes, double* flops) override {
+    require(kernel == IBMG_KERNEL_RAS_BATCH, "batch handles time the batched Schwarz launch only");
+    require(level >= 1 && level <= Lmax_, "level out of range");
+    require(reps >= 1 && reps <= 100000, "reps must lie in [1, 100000]");
+    BLevel& L = lv_[level];
+    set_all_active(s);
+    launch_fill<T>(L.r.p, T(1), (size_t)L.nact * L.n, s);
+    const double ts = sizeof(T);
+    const BoxGeom& g = L.g;
+    double by = (double)L.n_ib * ((double)g.nown * g.nloc + g.nloc + g.nown) * ts +
+                (double)L.n_int * (g.nloc + g.nown) * ts;
+    if (L.n_int > 0) by += (double)g.nown * g.nloc * ts;
+    const double ms = time_launches([&] { ras(level, L.r.p, L.w.p, L.plan, s); }, reps, s);
+    if (bytes) *bytes = by;
+    if (flops) *flops = 2.0 * (double)(L.n_ib + L.n_int) * g.nown * g.nloc;
+    return ms;
+  }
+
   // [nsys, levels, then per level: N, systems, interior boxes, IB boxes,
   //  IB rows, tile width, persistent grid, tuned sweep time (ns)]
   std::vector<int64_t> stats() const override {

@@ -572,13 +572,13 @@ int ras_interior_ksplit(const BoxGeom& g, int n_int) {
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s) {
-  if (n_ib > 0) {
+                      T* part, hipStream_t s, int parts) {
+  if ((parts & 1) && n_ib > 0) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
     hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, z, g, inv, ib_boxes);
     IBMG_LAUNCH_CHECK();
   }
-  if (n_int > 0) {
+  if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
     hipLaunchKernelGGL((k_ras_interior<T>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
                        shared_inv, int_boxes, n_int, loc_tab, part, ks);
@@ -816,10 +816,10 @@ template void launch_extract_owned<double>(const double*, int, BoxGeom, double*,
 template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t);
 template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*, int,
                                        const double*, const int*, int, const int*, double*,
-                                       hipStream_t);
+                                       hipStream_t, int);
 template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float*, const int*, int,
                                       const float*, const int*, int, const int*, float*,
-                                      hipStream_t);
+                                      hipStream_t, int);
 template void launch_coarse_apply<double>(const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_apply<float>(const double*, int, const float*, float*, hipStream_t);
 template void launch_coarse_apply_batch<double>(const double*, int, const double*, double*, int, hipStream_t);

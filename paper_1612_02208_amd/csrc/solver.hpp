@@ -38,6 +38,10 @@ struct SolverBase {
   virtual void set_kappa(const double* kappa, hipStream_t s) = 0;
   virtual std::vector<int64_t> stats() const = 0;
   virtual void sc_info(int level, double* lam, int32_t* colours) const = 0;
+  // average duration (ms) of one launch of a single kernel, with its
+  // algorithmic bytes and flops per launch
+  virtual double kernel_time(int kernel, int level, int reps, hipStream_t s, double* bytes,
+                             double* flops) = 0;
 };
 
 // Many independent systems solved together (batched form): one launch per
@@ -49,7 +53,34 @@ struct BatchBase {
   virtual int fgmres(const double* const* b, double* const* x, const ibmg_solve_opts& o,
                      ibmg_solve_info* infos, hipStream_t s) = 0;
   virtual std::vector<int64_t> stats() const = 0;
+  virtual double kernel_time(int kernel, int level, int reps, hipStream_t s, double* bytes,
+                             double* flops) = 0;
 };
+
+// Time reps launches of fn on s with HIP events (after one untimed launch);
+// returns the average in ms.
+template <typename F>
+double time_launches(F&& fn, int reps, hipStream_t s) {
+  hipEvent_t e0, e1;
+  IBMG_HIP(hipEventCreate(&e0));
+  IBMG_HIP(hipEventCreate(&e1));
+  float ms = 0;
+  try {
+    fn();
+    IBMG_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) fn();
+    IBMG_HIP(hipEventRecord(e1, s));
+    IBMG_HIP(hipEventSynchronize(e1));
+    IBMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  IBMG_HIP(hipEventDestroy(e0));
+  IBMG_HIP(hipEventDestroy(e1));
+  return (double)ms / reps;
+}
 
 SolverBase* make_solver(const ibmg_desc& d, hipStream_t s);
 BatchBase* make_batch(int nsys, const ibmg_desc* d, hipStream_t s);

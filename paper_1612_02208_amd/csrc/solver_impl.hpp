@@ -945,6 +945,57 @@ class Solver final : public SolverBase {
     colours[1] = lev.sc->colp.ncol;
   }
 
+  // One kernel of level `level`, launched alone on the level's work vectors
+  // (filled with ones): IB-box Schwarz (k_ras_ib), interior-box Schwarz
+  // (k_ras_interior, one reduction slice when the product is split) or the
+  // stencil k_apply.  Algorithmic work per launch: every IB box streams its
+  // owned rows of the inverse (nown x nloc), gathers nloc values and writes
+  // nown; the interior product reads the shared inverse once and each box's
+  // nloc values and writes nown, 2 nown nloc flops per box; the stencil reads
+  // and writes the three fields once.
+  double kernel_time(int kernel, int level, int reps, hipStream_t s, double* bytes, double* flops) override {
+    require(level >= 0 && level <= L_, "level out of range");
+    require(reps >= 1 && reps <= 100000, "reps must lie in [1, 100000]");
+    Level<T>& lev = levels_[level];
+    const size_t n = 3 * (size_t)lev.N * lev.N;
+    const double ts = sizeof(T);
+    launch_fill<T>(lev.r.p, T(1), n, s);
+    launch_fill<T>(lev.t.p, T(0), n, s);
+    double by = 0, fl = 0, ms = 0;
+    const BoxGeom& g = lev.g;
+    if (kernel == IBMG_KERNEL_RAS_IB || kernel == IBMG_KERNEL_RAS_INTERIOR) {
+      require(level >= 1 && !lev.sc, "Schwarz kernels need a Schwarz smoother level >= 1");
+      const int n_int = (int)lev.int_list.size();
+      if (kernel == IBMG_KERNEL_RAS_IB) {
+        require(lev.n_ib > 0, "the level has no IB boxes");
+        by = (double)lev.n_ib * ((double)g.nown * g.nloc + g.nloc + g.nown) * ts;
+        fl = 2.0 * lev.n_ib * g.nown * g.nloc;
+      } else {
+        require(n_int > 0, "the level has no interior boxes");
+        by = ((double)g.nown * g.nloc + (double)n_int * (g.nloc + g.nown)) * ts;
+        fl = 2.0 * n_int * g.nown * g.nloc;
+      }
+      const int part = kernel == IBMG_KERNEL_RAS_IB ? 1 : 2;
+      ms = time_launches([&] {
+        launch_ras_apply<T>(lev.r.p, lev.t.p, g, lev.inv.p, lev.d_ib.p, lev.n_ib,
+                            lev.inv.p + (size_t)lev.n_ib * box_stride(lev), lev.d_int.p, n_int, lev.d_loc.p,
+                            lev.int_part.p, s, part);
+      }, reps, s);
+    } else if (kernel == IBMG_KERNEL_STENCIL) {
+      by = 2.0 * (double)n * ts;
+      fl = 0;
+      ms = time_launches([&] {
+        launch_apply<T>(lev.r.p, lev.t.p, nullptr, nullptr, nullptr, fview<T>(lev.f[0]), fview<T>(lev.f[1]), lev.N,
+                        M_, coef<T>(lev), false, s);
+      }, reps, s);
+    } else {
+      require(false, "unknown kernel");
+    }
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
+    return ms;
+  }
+
   std::vector<int64_t> stats() const override {
     std::vector<int64_t> v;
     v.push_back(L_ + 1);

@@ -1,0 +1,64 @@
+"""Single-kernel timings of the N = 512 annulus workload, and one plain copy
+of known size, for profilers (HIP-event averages, algorithmic bytes and the
+resulting rates; run it under ``rocprofv3 --pmc`` to read hardware counters
+per dispatch, the copy calibrating the counters' units):
+
+    python -m paper_1612_02208_amd.profile_kernels [--N 512] [--box 16]
+        [--overlap 4] [--precision fp64] [--reps 5] [--copy-mib 1024]
+
+Prints one JSON line per kernel.
+"""
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--N", type=int, default=512)
+    p.add_argument("--box", type=int, default=16)
+    p.add_argument("--overlap", type=int, default=4)
+    p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    p.add_argument("--reps", type=int, default=5)
+    p.add_argument("--copy-mib", type=int, default=1024)
+    a = p.parse_args()
+    import torch
+    import workloads as W
+    from paper_1612_02208_amd import StokesIB
+
+    wl = W.annulus_512(N=a.N)
+    wl.box, wl.overlap = a.box, a.overlap
+    g = StokesIB(wl, precision=a.precision)
+    suffix = "<double>" if a.precision == "fp64" else "<float>"
+    for kern, name in (("ras_ib", "k_ras_ib"), ("ras_interior", "k_ras_interior"), ("stencil", "k_apply")):
+        t = g.kernel_time(kern, -1, a.reps)
+        rec = dict(kernel=name + suffix, level=g.n_levels - 1, N=a.N, reps=a.reps, avg_ms=t["ms"],
+                   alg_bytes=t["bytes"], alg_flops=t["flops"], gbs=t["bytes"] / t["ms"] / 1e6,
+                   tflops=t["flops"] / t["ms"] / 1e9)
+        print(json.dumps(rec), flush=True)
+    g.close()
+    # plain device copy of known size (reads and writes copy_mib MiB once)
+    n = a.copy_mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(a.reps):
+        dst.copy_(src)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.reps
+    print(json.dumps(dict(kernel="copy", bytes_read=n * 8, bytes_written=n * 8, avg_ms=ms,
+                          gbs=2 * n * 8 / ms / 1e6)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

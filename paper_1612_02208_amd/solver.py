@@ -229,6 +229,18 @@ class StokesIB:
         self._check(self.lib.ibmg_sc_info(self.h, level % self.n_levels, lam, col))
         return dict(lam_A=lam[0], lam_M=lam[1], colours_u=col[0], colours_p=col[1])
 
+    def kernel_time(self, kernel, level=-1, reps=50):
+        """Average duration (ms) of one launch of a single library kernel on
+        this handle's stream, with its algorithmic bytes and flops per launch.
+        kernel: "ras_ib", "ras_interior", "stencil" (single handles) or
+        "ras_batch" (batch handles)."""
+        k = {"ras_ib": _lib.KERNEL_RAS_IB, "ras_interior": _lib.KERNEL_RAS_INTERIOR,
+             "stencil": _lib.KERNEL_STENCIL, "ras_batch": _lib.KERNEL_RAS_BATCH}[kernel]
+        ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.ibmg_kernel_time(self.h, k, level % self.n_levels, int(reps), _stream(),
+                                              ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)))
+        return dict(ms=ms.value, bytes=by.value, flops=fl.value)
+
     def stats(self):
         buf = (ctypes.c_int64 * 256)()
         wr = ctypes.c_int32()
@@ -265,6 +277,7 @@ class StokesIBBatch:
         if st != 0:
             raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
         self.h = h
+        self.n_levels = len(self.stats()["levels"])
 
     def _check(self, st, ok=(0,)):
         if st not in ok:
@@ -281,6 +294,8 @@ class StokesIBBatch:
             self.close()
         except Exception:
             pass
+
+    kernel_time = StokesIB.kernel_time
 
     def _vecs(self, ts, name):
         if len(ts) != self.nsys:
