@@ -61,17 +61,57 @@ __global__ void k_gs_colour(T* x, const T* __restrict__ b, const int* __restrict
 }
 
 // colours [c_first, c_last] in order (step +1 or -1) inside one work-group
-template <typename T, bool MHAT>
-__global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b, const int* __restrict__ cptr,
-                                                  const int* __restrict__ rows, int c_first, int c_last,
-                                                  int step, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
-                                                  const T* __restrict__ diag, const T* __restrict__ dinv,
-                                                  T ih2) {
+// (pressure rows: one thread per row)
+template <typename T>
+__global__ void __launch_bounds__(1024) k_gs_band_p(T* x, const T* __restrict__ b, const int* __restrict__ cptr,
+                                                    const int* __restrict__ rows, int c_first, int c_last, int step,
+                                                    int N, const T* __restrict__ diag, const T* __restrict__ dinv,
+                                                    T ih2) {
   for (int col = c_first;; col += step) {
     for (int t = cptr[col] + threadIdx.x; t < cptr[col + 1]; t += blockDim.x) {
       const int r = rows[t];
-      const T ax = MHAT ? mhat_row<T>(x, r, N, ih2, dinv) : aib_row<T>(x, r, N, c, tu, tv);
-      x[r] += (b[r] - ax) / diag[r];
+      x[r] += (b[r] - mhat_row<T>(x, r, N, ih2, dinv)) / diag[r];
+    }
+    __syncthreads();
+    if (col == c_last) break;
+  }
+}
+
+// The same for velocity rows, whose IB part is long near the structure:
+// groups of G lanes share a row, each lane summing every G-th IB entry, the
+// group's partial sums combined by shuffles in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b, const int* __restrict__ cptr,
+                                                  const int* __restrict__ rows, int c_first, int c_last,
+                                                  int step, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
+                                                  const T* __restrict__ diag) {
+  constexpr int G = 16;
+  const int sub = threadIdx.x % G;
+  const int NN = N * N;
+  for (int col = c_first;; col += step) {
+    const int r0 = cptr[col], r1 = cptr[col + 1];
+    // every lane of a wave takes part in each pass (shuffles below)
+    for (int t0 = r0 + (int)(threadIdx.x / G); t0 - (int)(threadIdx.x / G) < r1; t0 += blockDim.x / G) {
+      const bool live = t0 < r1;
+      const int r = live ? rows[t0] : 0;
+      const int comp = r >= NN ? 1 : 0;
+      const int q = r - comp * NN;
+      const T* f = x + (size_t)comp * NN;
+      const CsrT<T>& tm = comp ? tv : tu;
+      T a = 0;
+      if (live)
+        for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * f[tm.col[k]];
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
+      if (live && sub == 0) {
+        const int i = q % N, j = q / N;
+        const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
+        const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+        const T xc = f[q];
+        const T ax = c.alpha * xc - c.beta * (f[j * N + im] + f[j * N + ip] + f[jm * N + i] + f[jp * N + i] -
+                                              T(4) * xc) + a;
+        x[r] += (b[r] - ax) / diag[r];
+      }
     }
     __syncthreads();
     if (col == c_last) break;
@@ -96,11 +136,11 @@ void launch_gs_sweep(T* x, const T* b, const int* cptr_dev, const std::vector<in
   };
   auto band = [&](int first, int last, int step) {
     if (mhat)
-      hipLaunchKernelGGL((k_gs_band<T, true>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step,
-                         N, c, tu, tv, diag, dinv, ih2);
+      hipLaunchKernelGGL((k_gs_band_p<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N,
+                         diag, dinv, ih2);
     else
-      hipLaunchKernelGGL((k_gs_band<T, false>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step,
-                         N, c, tu, tv, diag, dinv, ih2);
+      hipLaunchKernelGGL((k_gs_band<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N, c,
+                         tu, tv, diag);
     IBMG_LAUNCH_CHECK();
   };
   // a colour with at least nbig rows gets its own full-grid launch; runs of
@@ -150,10 +190,9 @@ __global__ void k_grad(const T* __restrict__ p, T* __restrict__ f, int N, T gi) 
   f[N * N + q] = gi * (p[q] - p[jm * N + i]);
 }
 
-// cells = a (D u) + b y   (D u = (u_{i+1} - u_i + v_{j+1} - v_j) / h)
+// cells = a (D u) + b y   (D u = (u_{i+1} - u_i + v_{j+1} - v_j) / h); out may be y
 template <typename T>
-__global__ void k_div_comb(const T* __restrict__ u, const T* __restrict__ y, T* __restrict__ out, int N, T gi,
-                           T a, T b) {
+__global__ void k_div_comb(const T* __restrict__ u, const T* y, T* out, int N, T gi, T a, T b) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N * N) return;
   const int i = q % N, j = q / N;
@@ -168,6 +207,37 @@ template <typename T>
 __global__ void k_axpby(size_t n, T a, const T* x, T b, const T* y, T* out) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     out[i] = a * x[i] + (y ? b * y[i] : T(0));
+}
+
+// Chebyshev start: d = theta_inv s, x = d, and (rc != null) rc = r
+template <typename T>
+__global__ void k_cheb_init(size_t n, T theta_inv, const T* __restrict__ sv, T* __restrict__ d, T* __restrict__ x,
+                            const T* __restrict__ r, T* __restrict__ rc) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const T di = theta_inv * sv[i];
+    d[i] = di;
+    x[i] = di;
+    if (rc) rc[i] = r[i];
+  }
+}
+
+// Chebyshev step: d = c1 d + c2 s, x += d
+template <typename T>
+__global__ void k_cheb_step(size_t n, T c1, T c2, const T* __restrict__ sv, T* __restrict__ d, T* __restrict__ x) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const T di = c1 * d[i] + c2 * sv[i];
+    d[i] = di;
+    x[i] = x[i] + di;
+  }
+}
+
+// y -= A_IB x (velocity only)
+template <typename T>
+__global__ void k_aib_sub(const T* __restrict__ x, T* __restrict__ y, int N, StokesCoef<T> c, CsrT<T> tu,
+                          CsrT<T> tv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 2 * N * N) return;
+  y[r] = y[r] - aib_row<T>(x, r, N, c, tu, tv);
 }
 
 // x = frac(k g) - 1/2, g = (sqrt 5 - 1) / 2 (deterministic Arnoldi start vector)
@@ -203,6 +273,25 @@ void launch_axpby(size_t n, T a, const T* x, T b, const T* y, T* out, hipStream_
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
+void launch_cheb_init(size_t n, T theta_inv, const T* sv, T* d, T* x, const T* r, T* rc, hipStream_t s) {
+  int g = cdiv(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL((k_cheb_init<T>), dim3(g), dim3(256), 0, s, n, theta_inv, sv, d, x, r, rc);
+  IBMG_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_cheb_step(size_t n, T c1, T c2, const T* sv, T* d, T* x, hipStream_t s) {
+  int g = cdiv(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL((k_cheb_step<T>), dim3(g), dim3(256), 0, s, n, c1, c2, sv, d, x);
+  IBMG_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_aib_sub(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s) {
+  hipLaunchKernelGGL((k_aib_sub<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, x, y, N, c, tu, tv);
+  IBMG_LAUNCH_CHECK();
+}
+template <typename T>
 void launch_weyl(T* x, size_t n, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
@@ -218,7 +307,10 @@ void launch_weyl(T* x, size_t n, hipStream_t s) {
   template void launch_grad<T>(const T*, T*, int, T, hipStream_t);                                           \
   template void launch_div_comb<T>(const T*, const T*, T*, int, T, T, T, hipStream_t);                       \
   template void launch_axpby<T>(size_t, T, const T*, T, const T*, T*, hipStream_t);                          \
-  template void launch_weyl<T>(T*, size_t, hipStream_t);
+  template void launch_weyl<T>(T*, size_t, hipStream_t);                                                     \
+  template void launch_cheb_init<T>(size_t, T, const T*, T*, T*, const T*, T*, hipStream_t);                  \
+  template void launch_cheb_step<T>(size_t, T, T, const T*, T*, T*, hipStream_t);                             \
+  template void launch_aib_sub<T>(const T*, T*, int, StokesCoef<T>, CsrT<T>, CsrT<T>, hipStream_t);
 
 IBMG_INST_SC(double)
 IBMG_INST_SC(float)

@@ -44,6 +44,12 @@ void launch_axpby(size_t n, T a, const T* x, T b, const T* y, T* out, hipStream_
 template <typename T>
 void launch_weyl(T* x, size_t n, hipStream_t s);
 template <typename T>
+void launch_cheb_init(size_t n, T theta_inv, const T* sv, T* d, T* x, const T* r, T* rc, hipStream_t s);
+template <typename T>
+void launch_cheb_step(size_t n, T c1, T c2, const T* sv, T* d, T* x, hipStream_t s);
+template <typename T>
+void launch_aib_sub(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s);
+template <typename T>
 void launch_sc_diag(int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, T ih2, T* diag, T* dinv, T* mdiag,
                     hipStream_t s);
 template <typename T>
@@ -137,19 +143,15 @@ struct ScLevel {
                        dinv.p, ih2, kGsBigColour, st);
   }
 
-  // x = A~^{-1} r (velocity vectors)
+  // x = A~^{-1} r (velocity vectors); residual r_k = r - A x kept in ar
   void a_tilde(const T* r, T* x, hipStream_t st) {
     const size_t n2 = 2 * (size_t)N * N;
     sgs_a(r, as.p, st);
-    launch_axpby<T>(n2, a_theta_inv, as.p, T(0), nullptr, ad.p, st);
-    launch_axpby<T>(n2, T(1), ad.p, T(0), nullptr, x, st);
-    if (its > 1) launch_axpby<T>(n2, T(1), r, T(0), nullptr, ar.p, st);
+    launch_cheb_init<T>(n2, a_theta_inv, as.p, ad.p, x, r, its > 1 ? ar.p : nullptr, st);
     for (int k = 0; k + 1 < its; ++k) {
-      launch_aib_apply<T>(ad.p, at.p, N, c, tu, tv, st);
-      launch_axpby<T>(n2, T(1), ar.p, T(-1), at.p, ar.p, st);
+      launch_aib_sub<T>(ad.p, ar.p, N, c, tu, tv, st);
       sgs_a(ar.p, as.p, st);
-      launch_axpby<T>(n2, a_c1[k], ad.p, a_c2[k], as.p, ad.p, st);
-      launch_axpby<T>(n2, T(1), x, T(1), ad.p, x, st);
+      launch_cheb_step<T>(n2, a_c1[k], a_c2[k], as.p, ad.p, x, st);
     }
   }
 
@@ -160,19 +162,19 @@ struct ScLevel {
     launch_div_comb<T>(gx.p, nullptr, out, N, c.gi, T(-1), T(0), st);
   }
 
-  // y = M~^{-1} s: Chebyshev on -D A~^{-1} G with right-hand side -s
+  // y = M~^{-1} s: Chebyshev on -D A~^{-1} G with right-hand side -s;
+  // residual kept in mr (mr - (-D A~^{-1} G d) = mr + D A~^{-1} G d)
   void m_tilde(const T* s_in, T* y, hipStream_t st) {
     const size_t n1 = (size_t)N * N;
     launch_axpby<T>(n1, T(-1), s_in, T(0), nullptr, mr.p, st);
     sgs_m(mr.p, ms.p, st);
-    launch_axpby<T>(n1, m_theta_inv, ms.p, T(0), nullptr, md.p, st);
-    launch_axpby<T>(n1, T(1), md.p, T(0), nullptr, y, st);
+    launch_cheb_init<T>(n1, m_theta_inv, ms.p, md.p, y, nullptr, nullptr, st);
     for (int k = 0; k + 1 < its; ++k) {
-      schur_op(md.p, mt.p, st);
-      launch_axpby<T>(n1, T(1), mr.p, T(-1), mt.p, mr.p, st);
+      launch_grad<T>(md.p, ga.p, N, c.gi, st);
+      a_tilde(ga.p, gx.p, st);
+      launch_div_comb<T>(gx.p, mr.p, mr.p, N, c.gi, T(1), T(1), st);
       sgs_m(mr.p, ms.p, st);
-      launch_axpby<T>(n1, m_c1[k], md.p, m_c2[k], ms.p, md.p, st);
-      launch_axpby<T>(n1, T(1), y, T(1), md.p, y, st);
+      launch_cheb_step<T>(n1, m_c1[k], m_c2[k], ms.p, md.p, y, st);
     }
     const int nblk = dots_blocks(n1, 256);
     launch_dots<T>(ones.p, 1, n1, y, n1, part.p, nblk, st);
