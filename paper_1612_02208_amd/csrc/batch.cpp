@@ -230,7 +230,7 @@ class BatchSolver final : public BatchBase {
         BLevel& L = lv_[l];
         launch_fill<T>(L.r.p, T(1), (size_t)L.nact * L.n, s);
         double best = 1e300;
-        for (int tb : {16, 32}) {
+        for (int tb : {16, 32, 64}) {
           const int items = ras_batch_items(L.g, L.n_int, L.n_ib, tb);
           if (items <= 0) continue;
           std::vector<int> grids;

@@ -426,6 +426,10 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
 };
 
+// Boxes per interior tile of the single-system product (two 16 x 16 output
+// tiles per wave; wider tiles measured slower: fewer work-groups in flight)
+constexpr int kIntTile = 32;
+
 // Shared memory of one interior tile: the gathered residual columns and the
 // tile's box table.
 template <typename T, int TB>
@@ -473,14 +477,20 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
   const int c1 = c0 + per < nchunk ? c0 + per : nchunk;
   const T* Mrow = M + (size_t)chunk * g.nloc * 64 + 16 * wave + (lane & 15);
   const int kq = lane >> 4, bl = lane & 15;
-  acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  constexpr int NT = TB / 16;  // 16 x 16 output tiles per wave
+  acc_t acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = acc_t{0, 0, 0, 0};
   T gx[GPT], ga[AS];
+  // the gather runs along the reduction index (a wave reads 64 consecutive
+  // local unknowns of one box, mostly contiguous rows of the grid) and is
+  // transposed into Xs[k][box]
   auto load_chunk = [&](int c, T* gxo, T* gao) {
     const int j0 = c * KC;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int t = tid + u * 256;
-      const int k = t / TB, b = t % TB;
+      const int k = t % KC, b = t / KC;
       const int jk = j0 + k;
       T val = 0;
       if (jk < g.nloc && sm.bid[b] >= 0) {
@@ -503,7 +513,7 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int t = tid + u * 256;
-      sm.Xs[t / TB][t % TB] = gx[u];
+      sm.Xs[t % KC][t / KC] = gx[u];
     }
     __syncthreads();
     T a[AS];
@@ -512,8 +522,8 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
     if (c + 1 < c1) load_chunk(c + 1, gx, ga);   // in flight during the MFMAs below
 #pragma unroll
     for (int s = 0; s < AS; ++s) {
-      acc0 = Mfma<T>::mma(a[s], sm.Xs[4 * s + kq][bl], acc0);
-      if (TB == 32) acc1 = Mfma<T>::mma(a[s], sm.Xs[4 * s + kq][16 + bl], acc1);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[q] = Mfma<T>::mma(a[s], sm.Xs[4 * s + kq][16 * q + bl], acc[q]);
     }
     __syncthreads();
   }
@@ -523,12 +533,16 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
     const int row = chunk * 64 + 16 * wave + Mfma<T>::row(kq, v);
     if (row >= g.nown) continue;
     if (ksplit == 1) {
-      if (sm.bid[bl] >= 0) z[sm.base[bl] + own_glob(g, sm.bid[bl], row)] = acc0[v];
-      if (TB == 32 && sm.bid[16 + bl] >= 0) z[sm.base[16 + bl] + own_glob(g, sm.bid[16 + bl], row)] = acc1[v];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int bb = 16 * q + bl;
+        if (sm.bid[bb] >= 0) z[sm.base[bb] + own_glob(g, sm.bid[bb], row)] = acc[q][v];
+      }
     } else {
       T* pp = part + (size_t)kslice * nlist * nown_pad;
-      if (bt + bl < nlist) pp[(size_t)(bt + bl) * nown_pad + row] = acc0[v];
-      if (TB == 32 && bt + 16 + bl < nlist) pp[(size_t)(bt + 16 + bl) * nown_pad + row] = acc1[v];
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+        if (bt + 16 * q + bl < nlist) pp[(size_t)(bt + 16 * q + bl) * nown_pad + row] = acc[q][v];
     }
   }
 }
@@ -539,8 +553,8 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
                                                       const int* __restrict__ boxes, int nlist,
                                                       const int* __restrict__ loc_tab,
                                                       T* __restrict__ part, int ksplit) {
-  __shared__ IntTileSmem<T, 32> sm;
-  ras_int_tile<T, 32>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit,
+  __shared__ IntTileSmem<T, kIntTile> sm;
+  ras_int_tile<T, kIntTile>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit,
                       loc_tab, nullptr, part, sm);
 }
 
@@ -562,7 +576,7 @@ __global__ void k_ras_interior_sum(const T* __restrict__ part, T* __restrict__ z
 // device (>= 768) while every slice keeps at least two column chunks.
 int ras_interior_ksplit(const BoxGeom& g, int n_int) {
   if (n_int <= 0) return 1;
-  const int tiles = (n_int + 31) / 32;
+  const int tiles = (n_int + kIntTile - 1) / kIntTile;
   const int nchunk = (g.nloc + 63) / 64;
   int ks = 1;
   while (ks < 8 && tiles * g.nch * ks < 768 && nchunk / (2 * ks) >= 2) ks *= 2;
@@ -580,7 +594,7 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   }
   if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
-    hipLaunchKernelGGL((k_ras_interior<T>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
+    hipLaunchKernelGGL((k_ras_interior<T>), dim3((n_int + kIntTile - 1) / kIntTile, g.nch, ks), dim3(256), 0, s, r, z, g,
                        shared_inv, int_boxes, n_int, loc_tab, part, ks);
     IBMG_LAUNCH_CHECK();
     if (ks > 1) {
@@ -595,10 +609,12 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
 
 // ---------------------------------------------------------------------------
 // Batched RAS sweep: one persistent launch per sweep.  Items are interior
-// tiles x row chunks first (matrix cores, shared inverse), then (IB box, row
-// chunk) pairs (streamed own inverses); work-group w takes items w, w + grid,
-// ... so the grid size, not the item count, sets the launch.  Every item
-// writes disjoint owned rows, so the result does not depend on the order.
+// tiles x row chunks (matrix cores, shared inverse) and (IB box, row chunk)
+// pairs (streamed own inverses), interleaved evenly: item t is an IB item
+// when floor((t + 1) B / total) > floor(t B / total), B = IB items, so every
+// CU holds both kinds and the inverse streaming overlaps the products.
+// Work-group w takes items w, w + grid, ...  Every item writes disjoint
+// owned rows, so the result does not depend on the order.
 // ---------------------------------------------------------------------------
 template <typename T, int TB>
 __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
@@ -609,14 +625,18 @@ __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* _
                                                    const int* __restrict__ active) {
   extern __shared__ char smem_raw[];
   const int n_tiles = (n_int + TB - 1) / TB;
-  const int int_items = n_tiles * g.nch;
-  const int total = int_items + n_ib * g.nch;
-  for (int it = blockIdx.x; it < total; it += gridDim.x) {
-    if (it < int_items) {
-      ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, it / g.nch, it % g.nch, 0, 1, loc_tab, active,
+  const long long int_items = (long long)n_tiles * g.nch;
+  const long long ib_items = (long long)n_ib * g.nch;
+  const long long total = int_items + ib_items;
+  for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+    const long long before = it * ib_items / total;           // IB items among [0, it)
+    const bool is_ib = (it + 1) * ib_items / total > before;
+    if (!is_ib) {
+      const int ti = (int)(it - before);
+      ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab, active,
                           nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw));
     } else {
-      const int q = it - int_items, e = q / g.nch, c = q % g.nch;
+      const int q = (int)before, e = q / g.nch, c = q % g.nch;
       const int ent = ib_ents[e], sy = ent / nbox;
       if (active && !active[sy]) continue;
       T* x = reinterpret_cast<T*>(smem_raw);
@@ -635,17 +655,21 @@ template <typename T>
 void launch_ras_batch(const T* r, T* z, BoxGeom g, size_t sys_n, int nbox, const T* shared_inv,
                       const int* int_ents, int n_int, const int* ib_ents, const T* const* ib_inv, int n_ib,
                       const int* loc_tab, const int* active, RasBatchPlan plan, hipStream_t s) {
-  const int tb = plan.tb == 16 ? 16 : 32;
+  const int tb = plan.tb == 16 ? 16 : (plan.tb == 64 ? 64 : 32);
   const int items = ras_batch_items(g, n_int, n_ib, tb);
   if (items <= 0) return;
   if (n_int > 0 && !shared_inv) throw Error(IBMG_ERR_ARG, "interior boxes without a shared inverse");
   int grid = plan.grid > 0 ? plan.grid : items;
   if (grid > items) grid = items;
   size_t lds = ((((size_t)g.nloc + 3) & ~(size_t)3) + 256) * sizeof(T);
-  const size_t tile = tb == 16 ? sizeof(IntTileSmem<T, 16>) : sizeof(IntTileSmem<T, 32>);
+  const size_t tile = tb == 16 ? sizeof(IntTileSmem<T, 16>)
+                                : (tb == 64 ? sizeof(IntTileSmem<T, 64>) : sizeof(IntTileSmem<T, 32>));
   if (tile > lds) lds = tile;
   if (tb == 16)
     hipLaunchKernelGGL((k_ras_batch<T, 16>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
+                       int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
+  else if (tb == 64)
+    hipLaunchKernelGGL((k_ras_batch<T, 64>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
                        int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
   else
     hipLaunchKernelGGL((k_ras_batch<T, 32>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,

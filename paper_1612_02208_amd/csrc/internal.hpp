@@ -295,7 +295,7 @@ void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int 
 // shared interior inverse, then (IB box, row chunk) items against each box's
 // own inverse.  Box entries are s * nbox + box id; systems are sys_n apart.
 struct RasBatchPlan {
-  int tb = 32;      // interior tile width (16 or 32 boxes)
+  int tb = 32;      // interior tile width (16, 32 or 64 boxes)
   int grid = 0;     // work-groups of the persistent launch
 };
 template <typename T>

@@ -77,41 +77,62 @@ __global__ void __launch_bounds__(1024) k_gs_band_p(T* x, const T* __restrict__ 
   }
 }
 
-// The same for velocity rows, whose IB part is long near the structure:
-// groups of G lanes share a row, each lane summing every G-th IB entry, the
-// group's partial sums combined by shuffles in a fixed order.
+// Velocity rows whose IB part is long (near the structure): groups of G
+// lanes share a row, each lane summing every G-th IB entry, the group's
+// partial sums combined by shuffles in a fixed order.  Every lane of the
+// wave calls this (live = false for lanes without a row).
+constexpr int kGsGroup = 16;
+
+template <typename T>
+__device__ __forceinline__ void gs_row_group(T* x, const T* __restrict__ b, int r, bool live, int sub, int N,
+                                             const StokesCoef<T>& c, const CsrT<T>& tu, const CsrT<T>& tv,
+                                             const T* __restrict__ diag) {
+  constexpr int G = kGsGroup;
+  const int NN = N * N;
+  const int comp = r >= NN ? 1 : 0;
+  const int q = r - comp * NN;
+  const T* f = x + (size_t)comp * NN;
+  const CsrT<T>& tm = comp ? tv : tu;
+  T a = 0;
+  if (live)
+    for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * f[tm.col[k]];
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
+  if (live && sub == 0) {
+    const int i = q % N, j = q / N;
+    const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
+    const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+    const T xc = f[q];
+    const T ax = c.alpha * xc - c.beta * (f[j * N + im] + f[j * N + ip] + f[jm * N + i] + f[jp * N + i] -
+                                          T(4) * xc) + a;
+    x[r] += (b[r] - ax) / diag[r];
+  }
+}
+
+// one colour over the grid, a lane group per row
+template <typename T>
+__global__ void k_gs_colour_g(T* x, const T* __restrict__ b, const int* __restrict__ rows, int count, int N,
+                              StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, const T* __restrict__ diag) {
+  const int g = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kGsGroup);
+  const bool live = g < count;
+  gs_row_group<T>(x, b, live ? rows[g] : 0, live, threadIdx.x % kGsGroup, N, c, tu, tv, diag);
+}
+
+// colours [c_first, c_last] in order inside one work-group, lane groups per row
 template <typename T>
 __global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b, const int* __restrict__ cptr,
                                                   const int* __restrict__ rows, int c_first, int c_last,
                                                   int step, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
                                                   const T* __restrict__ diag) {
-  constexpr int G = 16;
-  const int sub = threadIdx.x % G;
-  const int NN = N * N;
+  constexpr int G = kGsGroup;
+  const int grp = threadIdx.x / G, sub = threadIdx.x % G;
   for (int col = c_first;; col += step) {
     const int r0 = cptr[col], r1 = cptr[col + 1];
-    // every lane of a wave takes part in each pass (shuffles below)
-    for (int t0 = r0 + (int)(threadIdx.x / G); t0 - (int)(threadIdx.x / G) < r1; t0 += blockDim.x / G) {
-      const bool live = t0 < r1;
-      const int r = live ? rows[t0] : 0;
-      const int comp = r >= NN ? 1 : 0;
-      const int q = r - comp * NN;
-      const T* f = x + (size_t)comp * NN;
-      const CsrT<T>& tm = comp ? tv : tu;
-      T a = 0;
-      if (live)
-        for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * f[tm.col[k]];
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
-      if (live && sub == 0) {
-        const int i = q % N, j = q / N;
-        const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
-        const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-        const T xc = f[q];
-        const T ax = c.alpha * xc - c.beta * (f[j * N + im] + f[j * N + ip] + f[jm * N + i] + f[jp * N + i] -
-                                              T(4) * xc) + a;
-        x[r] += (b[r] - ax) / diag[r];
-      }
+    // uniform trip count across the work-group (shuffles inside)
+    for (int base = r0; base < r1; base += blockDim.x / G) {
+      const int t = base + grp;
+      const bool live = t < r1;
+      gs_row_group<T>(x, b, live ? rows[t] : 0, live, sub, N, c, tu, tv, diag);
     }
     __syncthreads();
     if (col == c_last) break;
@@ -121,12 +142,16 @@ __global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b,
 template <typename T>
 void launch_gs_sweep(T* x, const T* b, const int* cptr_dev, const std::vector<int>& cptr, const int* rows,
                      int ncol, bool mhat, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, const T* diag,
-                     const T* dinv, T ih2, int nbig, hipStream_t s) {
-  // forward over colours then backward; colours < nbig are full-grid launches
+                     const T* dinv, T ih2, int nbig, const std::vector<char>& long_rows, hipStream_t s) {
+  // forward over colours then backward; colours >= nbig rows are full-grid
+  // launches, with lane groups per row when they hold long IB rows
   auto big = [&](int col) {
     const int cnt = cptr[col + 1] - cptr[col];
     if (!cnt) return;
-    if (mhat)
+    if (!mhat && col < (int)long_rows.size() && long_rows[col]) {
+      hipLaunchKernelGGL((k_gs_colour_g<T>), dim3(cdiv((size_t)cnt * kGsGroup, 256)), dim3(256), 0, s, x, b,
+                         rows + cptr[col], cnt, N, c, tu, tv, diag);
+    } else if (mhat)
       hipLaunchKernelGGL((k_gs_colour<T, true>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
                          cnt, N, c, tu, tv, diag, dinv, ih2);
     else
@@ -302,7 +327,7 @@ void launch_weyl(T* x, size_t n, hipStream_t s) {
 #define IBMG_INST_SC(T)                                                                                      \
   template void launch_gs_sweep<T>(T*, const T*, const int*, const std::vector<int>&, const int*, int, bool,  \
                                    int, StokesCoef<T>, CsrT<T>, CsrT<T>, const T*, const T*, T, int,          \
-                                   hipStream_t);                                                             \
+                                   const std::vector<char>&, hipStream_t);                                   \
   template void launch_aib_apply<T>(const T*, T*, int, StokesCoef<T>, CsrT<T>, CsrT<T>, hipStream_t);        \
   template void launch_grad<T>(const T*, T*, int, T, hipStream_t);                                           \
   template void launch_div_comb<T>(const T*, const T*, T*, int, T, T, T, hipStream_t);                       \

@@ -32,7 +32,11 @@ constexpr int kGsBigColour = 256;
 template <typename T>
 void launch_gs_sweep(T* x, const T* b, const int* cptr_dev, const std::vector<int>& cptr, const int* rows,
                      int ncol, bool mhat, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, const T* diag,
-                     const T* dinv, T ih2, int nbig, hipStream_t s);
+                     const T* dinv, T ih2, int nbig, const std::vector<char>& long_rows, hipStream_t s);
+
+// a colour whose longest IB row exceeds this many entries is swept with
+// lane groups per row
+constexpr int kGsLongRow = 8;
 template <typename T>
 void launch_aib_apply(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s);
 template <typename T>
@@ -82,6 +86,7 @@ std::vector<int> greedy_colours(int n, F nbrs) {
 
 struct ColourLists {
   std::vector<int> ptr, rows;  // rows grouped by colour, ascending within a colour
+  std::vector<char> long_rows;  // per colour: holds an IB row longer than kGsLongRow
   DBuf<int> d_ptr, d_rows;
   int ncol = 0;
   void build(const std::vector<int>& col, hipStream_t s) {
@@ -134,13 +139,13 @@ struct ScLevel {
     const size_t n2 = 2 * (size_t)N * N;
     launch_axpby<T>(n2, T(0), b, T(0), nullptr, x, st);
     launch_gs_sweep<T>(x, b, colu.d_ptr.p, colu.ptr, colu.d_rows.p, colu.ncol, false, N, c, tu, tv, diag.p,
-                       dinv.p, ih2, kGsBigColour, st);
+                       dinv.p, ih2, kGsBigColour, colu.long_rows, st);
   }
   void sgs_m(const T* b, T* x, hipStream_t st) {
     const size_t n1 = (size_t)N * N;
     launch_axpby<T>(n1, T(0), b, T(0), nullptr, x, st);
     launch_gs_sweep<T>(x, b, colp.d_ptr.p, colp.ptr, colp.d_rows.p, colp.ncol, true, N, c, tu, tv, mdiag.p,
-                       dinv.p, ih2, kGsBigColour, st);
+                       dinv.p, ih2, kGsBigColour, colp.long_rows, st);
   }
 
   // x = A~^{-1} r (velocity vectors); residual r_k = r - A x kept in ar

@@ -370,6 +370,13 @@ class Solver final : public SolverBase {
       std::copy(cc.begin(), cc.end(), colv.begin() + (size_t)c * NN);
     }
     sc.colu.build(colv, s);
+    sc.colu.long_rows.assign(sc.colu.ncol, 0);
+    for (int cc = 0; cc < sc.colu.ncol; ++cc)
+      for (int t = sc.colu.ptr[cc]; t < sc.colu.ptr[cc + 1]; ++t) {
+        const int r = sc.colu.rows[t], comp = r >= NN ? 1 : 0, q = r - comp * NN;
+        const CompFoot& f = lev.f[comp];
+        if (f.tptr[q + 1] - f.tptr[q] > kGsLongRow) sc.colu.long_rows[cc] = 1;
+      }
     std::vector<int> colp = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
       const int i = r % N, j = r / N;
       nb.push_back(j * N + (i + 1) % N);
