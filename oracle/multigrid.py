@@ -15,7 +15,7 @@ from . import transfer
 from .hierarchy import null_space
 from .krylov import fgmres_smooth
 from .schur import SchurSmoother
-from .schwarz import RAS
+from .schwarz import RAS, RMS, structural_pattern
 
 
 class CoarseSolver:
@@ -45,6 +45,8 @@ class Multigrid:
             lev = levels[l]
             if wl.smoother == "ras":
                 self.smoothers.append(RAS(lev.L, lev.N, wl.box, wl.overlap))
+            elif wl.smoother == "rms":
+                self.smoothers.append(RMS(lev.L, structural_pattern(lev), lev.N, wl.box, wl.overlap))
             elif wl.smoother == "sc":
                 self.smoothers.append(SchurSmoother(lev, wl.rho, wl.cheb_its))
             else:

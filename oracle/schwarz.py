@@ -1,4 +1,5 @@
-"""Restricted additive Schwarz smoother (Sec. 3.3.1, Alg. 2).
+"""Restricted additive and multiplicative Schwarz smoothers (Sec. 3.3.1,
+Alg. 2 and Alg. 3).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -14,6 +15,7 @@ from typing import List
 
 import numpy as np
 import scipy.linalg as la
+import scipy.sparse as sp
 
 
 def level_box(N, box, overlap):
@@ -76,5 +78,85 @@ class RAS:
             y = la.lu_solve(f, r[p.idx])
             z[p.own_global] = y[p.own_local]
         return z
+
+    __call__ = apply
+
+
+def structural_pattern(level):
+    """0/1 pattern of L_IB on a level: the five-point stencil on each velocity
+    component, the IB term's structural pattern, G and -D (whose entries are
+    +-1/h and never cancel); the pressure block is empty."""
+    St = level.A.copy()
+    St.data[:] = 1.0   # A = rho/dt I - mu Lap: diagonal + four neighbours, all nonzero
+    Pv = (St + level.T_pattern).tocsr()
+    Pv.data[:] = 1.0
+    G = level.G.copy()
+    G.data[:] = 1.0
+    D = level.D.copy()
+    D.data[:] = 1.0
+    n = D.shape[0]
+    P = sp.bmat([[Pv, G], [D, sp.csr_matrix((n, n))]], format="csr")
+    P.data[:] = 1.0
+    return P
+
+
+def box_colours(pattern, parts):
+    """Greedy colouring of the boxes for the multiplicative sweep.  Boxes i
+    and j conflict when the operator couples a row of G_j to an unknown of
+    G~_i, or a row of G_i to an unknown of G~_j: then the order of their two
+    updates matters.  Boxes are coloured in index order with the smallest
+    colour not taken by an already coloured conflicting box, so boxes of one
+    colour can be updated from the same residual."""
+    P = pattern.tocsr()
+    owner = np.empty(P.shape[0], dtype=np.int64)
+    for k, p in enumerate(parts):
+        owner[p.own_global] = k
+    nb = len(parts)
+    reach = []
+    for p in parts:
+        cols = np.unique(P[p.idx].indices)
+        reach.append(set(np.unique(owner[cols]).tolist()))
+    adj = [set() for _ in range(nb)]
+    for j in range(nb):
+        for i in reach[j]:
+            if i != j:
+                adj[j].add(i)
+                adj[i].add(j)
+    colour = np.full(nb, -1, dtype=np.int64)
+    for k in range(nb):
+        used = {colour[q] for q in adj[k] if colour[q] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        colour[k] = c
+    return colour
+
+
+class RMS:
+    """w <- RMS(w, b) (Alg. 3): for each box in turn, the residual of the
+    current w, a local solve with L_k = R_k L R_k^T, and the update of w on
+    G~_k.  The boxes are visited in colour-major order (colour 0's boxes in
+    index order, then colour 1's, ...), colours from ``box_colours``."""
+
+    def __init__(self, L, pattern, N, box, overlap):
+        self.parts = patches(N, box, overlap)
+        self.L = L.tocsr()
+        self.rows = [self.L[p.idx] for p in self.parts]
+        self.factors = [la.lu_factor(self.L[p.idx][:, p.idx].toarray()) for p in self.parts]
+        self.colour = box_colours(pattern, self.parts)
+        self.order = sorted(range(len(self.parts)), key=lambda k: (self.colour[k], k))
+
+    def sweep(self, w, b, order=None):
+        w = np.array(w, dtype=np.float64, copy=True)
+        for k in (self.order if order is None else order):
+            p = self.parts[k]
+            rk = b[p.idx] - self.rows[k] @ w          # R_k (b - L w)
+            y = la.lu_solve(self.factors[k], rk)
+            w[p.own_global] += y[p.own_local]
+        return w
+
+    def apply(self, r):
+        """Smoother application from a zero initial guess."""
+        return self.sweep(np.zeros_like(r), r)
 
     __call__ = apply
