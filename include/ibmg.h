@@ -5,8 +5,9 @@
  *
  * on a periodic N x N staggered grid (App. A.1), preconditioned by the
  * geometric-multigrid V-cycle of Alg. 1 with a restricted additive Schwarz
- * (Alg. 2) or Schur-complement (Eq. approx-fact-Stokes-IB) smoother wrapped in
- * a fixed number of FGMRES iterations (Sec. 3.3), inside flexible GMRES.
+ * (Alg. 2), restricted multiplicative Schwarz (Alg. 3) or Schur-complement
+ * (Eq. approx-fact-Stokes-IB) smoother wrapped in a fixed number of FGMRES
+ * iterations (Sec. 3.3), inside flexible GMRES.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -53,7 +54,14 @@ typedef enum {
   IBMG_ERR_STATE = -6     /* call not valid for this handle */
 } ibmg_status;
 
-enum { IBMG_RAS = 0, IBMG_SC = 1 };              /* smoother */
+/* smoother: restricted additive Schwarz (Alg. 2), Schur complement
+ * (Sec. 3.3.2), restricted multiplicative Schwarz (Alg. 3).  The
+ * multiplicative sweep visits the boxes colour by colour: boxes are greedily
+ * coloured in index order so that no box of a colour has a row coupled (by
+ * the stencil, the IB term, G or D) to an owned unknown of another box of
+ * that colour; each colour takes the residual of the current iterate, so the
+ * sweep equals Alg. 3 with the boxes in colour-major order. */
+enum { IBMG_RAS = 0, IBMG_SC = 1, IBMG_RMS = 2 };
 enum { IBMG_FP64 = 0, IBMG_FP32_SMOOTHER = 1 };  /* precision */
 
 typedef struct {
@@ -67,7 +75,7 @@ typedef struct {
   const int32_t* ends;/* host [n_springs][2] node ids, a != b, in [0, M)     */
   const double* kappa;/* host [n_springs] spring stiffness >= 0 (zero rest
                          length, Sec. 5 linear fibre force)                  */
-  int32_t smoother;   /* IBMG_RAS | IBMG_SC                                   */
+  int32_t smoother;   /* IBMG_RAS | IBMG_SC | IBMG_RMS                        */
   int32_t box;        /* RAS box size b (cells); must divide every level's
                          n >= 2b, levels below use min(b, n/2)               */
   int32_t overlap;    /* RAS overlap o (cells) >= 0                          */
@@ -133,7 +141,8 @@ ibmg_status ibmg_prolong_add(ibmg_handle* h, int32_t level, const double* coarse
                              ibmg_stream stream);
 
 /* One application of the basic smoother on level l >= 1 from a zero guess:
- * z = RAS(r) (Alg. 2) or the SC approximate inverse (Eq. approx-fact-Stokes-IB). */
+ * z = RAS(0, r) (Alg. 2), RMS(0, r) (Alg. 3) or the SC approximate inverse
+ * (Eq. approx-fact-Stokes-IB). */
 ibmg_status ibmg_smoother_apply(ibmg_handle* h, int32_t level, const double* r, double* z,
                                 ibmg_stream stream);
 /* Sec. 3.3 smoothing on level l >= 1: w <- w + e, e from nu FGMRES iterations
@@ -171,8 +180,9 @@ ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream stre
 
 /* Setup statistics.  Writes up to cap int64 values: [levels, then per
  * level: n, boxes, boxes with their own inverse (+1 for the shared interior
- * one), IB-touched boxes, entries of the explicit IB rows] and returns the
- * full count in *written. */
+ * one), IB-touched boxes, entries of the explicit IB rows, box colours of the
+ * multiplicative sweep (0 for the other smoothers)] and returns the full
+ * count in *written. */
 ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written);
 
 /* Schur-complement smoother data of level l >= 1 (Sec. 3.3.2): lam[0], lam[1]

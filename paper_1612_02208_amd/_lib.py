@@ -12,7 +12,7 @@ IBMG_ERR_HIP = -2
 IBMG_ERR_NONFINITE = -5
 IBMG_ERR_STATE = -6
 
-RAS, SC = 0, 1
+RAS, SC, RMS = 0, 1, 2
 FP64, FP32_SMOOTHER = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)

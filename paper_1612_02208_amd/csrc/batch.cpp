@@ -33,7 +33,7 @@ class BatchSolver final : public BatchBase {
     const ibmg_desc& d0 = d[0];
     for (int i = 0; i < nsys; ++i) {
       validate_desc(d[i]);
-      require(d[i].smoother == IBMG_RAS, "the batched form uses the Schwarz smoother");
+      require(d[i].smoother == IBMG_RAS, "the batched form uses the additive Schwarz smoother");
       require(d[i].coarse_N == d0.coarse_N && d[i].rho == d0.rho && d[i].mu == d0.mu && d[i].dt == d0.dt &&
                   d[i].box == d0.box && d[i].overlap == d0.overlap && d[i].nu1 == d0.nu1 &&
                   d[i].nu2 == d0.nu2 && d[i].precision == d0.precision,

@@ -332,7 +332,8 @@ struct Vec16<float> {
 // inverse, r and z the box's system vectors; x holds nloc values, part 256.
 template <typename T>
 __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
-                                             const T* __restrict__ Mc, int pid, int chunk, T* x, T* part) {
+                                             const T* __restrict__ Mc, int pid, int chunk, T* x, T* part,
+                                             bool acc_mode) {
   using V = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   constexpr int LPC = 64 / VEC;  // lanes per column
@@ -379,19 +380,23 @@ __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restr
   __syncthreads();
   if (q == 0) {
     const int row = chunk * 64 + lane;
-    if (row < g.nown) z[own_glob(g, pid, row)] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+    if (row < g.nown) {
+      const T v = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+      const size_t o = own_glob(g, pid, row);
+      z[o] = acc_mode ? z[o] + v : v;
+    }
   }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
-                                                const T* __restrict__ inv, const int* __restrict__ boxes) {
+                                                const T* __restrict__ inv, const int* __restrict__ boxes, bool acc) {
   extern __shared__ char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
   T* part = x + ((g.nloc + 3) & ~3);
   const int slot = blockIdx.x;
   ras_ib_chunk<T>(r, z, g, inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64, boxes[slot], blockIdx.y, x,
-                  part);
+                  part, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,7 +453,7 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
                                              const int* __restrict__ ents, int nlist, int tile, int chunk,
                                              int kslice, int ksplit, const int* __restrict__ loc_tab,
                                              const int* __restrict__ active, T* __restrict__ part,
-                                             IntTileSmem<T, TB>& sm) {
+                                             IntTileSmem<T, TB>& sm, bool acc_mode) {
   constexpr int KC = 64, GPT = KC * TB / 256, AS = KC / 4;
   using acc_t = typename Mfma<T>::acc_t;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -536,7 +541,10 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
         const int bb = 16 * q + bl;
-        if (sm.bid[bb] >= 0) z[sm.base[bb] + own_glob(g, sm.bid[bb], row)] = acc[q][v];
+        if (sm.bid[bb] >= 0) {
+          const size_t o = sm.base[bb] + own_glob(g, sm.bid[bb], row);
+          z[o] = acc_mode ? z[o] + acc[q][v] : acc[q][v];
+        }
       }
     } else {
       T* pp = part + (size_t)kslice * nlist * nown_pad;
@@ -552,23 +560,24 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
                                                       BoxGeom g, const T* __restrict__ M,
                                                       const int* __restrict__ boxes, int nlist,
                                                       const int* __restrict__ loc_tab,
-                                                      T* __restrict__ part, int ksplit) {
+                                                      T* __restrict__ part, int ksplit, bool acc) {
   __shared__ IntTileSmem<T, kIntTile> sm;
   ras_int_tile<T, kIntTile>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit,
-                      loc_tab, nullptr, part, sm);
+                      loc_tab, nullptr, part, sm, acc);
 }
 
 // z[owned rows of interior box b] = sum over the reduction slices, in order.
 template <typename T>
 __global__ void k_ras_interior_sum(const T* __restrict__ part, T* __restrict__ z, BoxGeom g,
-                                   const int* __restrict__ boxes, int nlist, int ksplit) {
+                                   const int* __restrict__ boxes, int nlist, int ksplit, bool acc) {
   const int nown_pad = g.nch * 64;
   const size_t tot = (size_t)nlist * g.nown;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
     const int b = (int)(t / g.nown), row = (int)(t % g.nown);
     T a = 0;
     for (int s = 0; s < ksplit; ++s) a += part[((size_t)s * nlist + b) * nown_pad + row];
-    z[own_glob(g, boxes[b], row)] = a;
+    const size_t o = own_glob(g, boxes[b], row);
+    z[o] = acc ? z[o] + a : a;
   }
 }
 
@@ -586,22 +595,23 @@ int ras_interior_ksplit(const BoxGeom& g, int n_int) {
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s, int parts) {
+                      T* part, hipStream_t s, int parts, bool acc) {
   if ((parts & 1) && n_ib > 0) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
-    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, z, g, inv, ib_boxes);
+    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc);
     IBMG_LAUNCH_CHECK();
   }
   if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
     hipLaunchKernelGGL((k_ras_interior<T>), dim3((n_int + kIntTile - 1) / kIntTile, g.nch, ks), dim3(256), 0, s, r, z, g,
-                       shared_inv, int_boxes, n_int, loc_tab, part, ks);
+                       shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
     IBMG_LAUNCH_CHECK();
     if (ks > 1) {
       const size_t tot = (size_t)n_int * g.nown;
       int grid = cdiv(tot, 256);
       if (grid > 4096) grid = 4096;
-      hipLaunchKernelGGL((k_ras_interior_sum<T>), dim3(grid), dim3(256), 0, s, part, z, g, int_boxes, n_int, ks);
+      hipLaunchKernelGGL((k_ras_interior_sum<T>), dim3(grid), dim3(256), 0, s, part, z, g, int_boxes, n_int, ks,
+                         acc);
       IBMG_LAUNCH_CHECK();
     }
   }
@@ -634,14 +644,14 @@ __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* _
     if (!is_ib) {
       const int ti = (int)(it - before);
       ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab, active,
-                          nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw));
+                          nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw), false);
     } else {
       const int q = (int)before, e = q / g.nch, c = q % g.nch;
       const int ent = ib_ents[e], sy = ent / nbox;
       if (active && !active[sy]) continue;
       T* x = reinterpret_cast<T*>(smem_raw);
       ras_ib_chunk<T>(r + (size_t)sy * sys_n, z + (size_t)sy * sys_n, g, ib_inv[e] + (size_t)c * g.nloc * 64,
-                      ent - sy * nbox, c, x, x + ((g.nloc + 3) & ~3));
+                      ent - sy * nbox, c, x, x + ((g.nloc + 3) & ~3), false);
     }
     __syncthreads();
   }
@@ -840,10 +850,10 @@ template void launch_extract_owned<double>(const double*, int, BoxGeom, double*,
 template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t);
 template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*, int,
                                        const double*, const int*, int, const int*, double*,
-                                       hipStream_t, int);
+                                       hipStream_t, int, bool);
 template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float*, const int*, int,
                                       const float*, const int*, int, const int*, float*,
-                                      hipStream_t, int);
+                                      hipStream_t, int, bool);
 template void launch_coarse_apply<double>(const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_apply<float>(const double*, int, const float*, float*, hipStream_t);
 template void launch_coarse_apply_batch<double>(const double*, int, const double*, double*, int, hipStream_t);

@@ -222,11 +222,12 @@ constexpr int kGjNb = 64;  // block width of the batched Gauss-Jordan inversion
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
 // parts: bit 0 = IB boxes (k_ras_ib), bit 1 = interior boxes
-// (k_ras_interior and its slice sum); the smoother launches both
+// (k_ras_interior and its slice sum); the smoother launches both.
+// acc: add the local solutions to z on the owned sets instead of storing them
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s, int parts = 3);
+                      T* part, hipStream_t s, int parts = 3, bool acc = false);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);
 void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,

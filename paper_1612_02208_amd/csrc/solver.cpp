@@ -28,11 +28,11 @@ void validate_desc(const ibmg_desc& d) {
     require(a >= 0 && a < d.M && b >= 0 && b < d.M && a != b, "spring end out of range");
     require(std::isfinite(d.kappa[e]) && d.kappa[e] >= 0.0, "kappa must be finite and >= 0");
   }
-  require(d.smoother == IBMG_RAS || d.smoother == IBMG_SC, "unknown smoother");
+  require(d.smoother == IBMG_RAS || d.smoother == IBMG_SC || d.smoother == IBMG_RMS, "unknown smoother");
   require(d.nu1 >= 1 && d.nu1 <= kMaxNu && d.nu2 >= 1 && d.nu2 <= kMaxNu, "nu1/nu2 must lie in [1, 8]");
   require(d.precision == IBMG_FP64 || d.precision == IBMG_FP32_SMOOTHER, "unknown precision");
   if (d.smoother == IBMG_SC) require(d.cheb_its >= 1 && d.cheb_its <= 8, "cheb_its must lie in [1, 8]");
-  if (d.smoother == IBMG_RAS) {
+  if (d.smoother == IBMG_RAS || d.smoother == IBMG_RMS) {
     require(d.box >= 1 && d.overlap >= 0, "box must be >= 1 and overlap >= 0");
     require(d.box + 2 * d.overlap <= 32, "box + 2 overlap must be <= 32");
     for (int n : level_sizes(d.N, d.coarse_N)) {

@@ -73,6 +73,12 @@ struct Level {
   DBuf<int> d_ib, d_int, d_loc;
   DBuf<T> inv;            // [n_unique][nch][nloc][64]
   DBuf<T> int_part;       // reduction slices of the interior-box product
+  // restricted multiplicative Schwarz: box colours; ib_list and int_list
+  // sorted by colour, colour c spanning [ib_off[c], ib_off[c+1]) and
+  // [int_off[c], int_off[c+1])
+  int ncolour = 0;
+  std::vector<int> box_colour, ib_off, int_off;
+  DBuf<T> rr;             // residual between colours
   // work vectors
   DBuf<T> w, b, r, t, V, Z, F;
   DBuf<double> H, scal, part;
@@ -173,7 +179,8 @@ class Solver final : public SolverBase {
           f.max_list = std::max(f.max_list, f.sp_ptr[r + 1] - f.sp_ptr[r]);
       }
       lev.use_spmv = std::max(lev.f[0].max_list, lev.f[1].max_list) > kSpmvListThreshold;
-      if (l >= 1 && d_.smoother == IBMG_RAS) classify_boxes(lev);
+      if (l >= 1 && (d_.smoother == IBMG_RAS || d_.smoother == IBMG_RMS)) classify_boxes(lev);
+      if (l >= 1 && d_.smoother == IBMG_RMS) colour_boxes(lev);
       if (l >= 1 && d_.smoother == IBMG_SC) sc_structure(lev, s);
     }
   }
@@ -319,6 +326,86 @@ class Solver final : public SolverBase {
 
   size_t box_stride(const Level<T>& lev) const { return (size_t)lev.g.nch * lev.g.nloc * 64; }
 
+  // Colours of the multiplicative sweep (Alg. 3 in colour-major order).
+  // Box p reaches box q when a row of p's enlarged box couples, through the
+  // five-point stencil, the IB rows, G or D, to an unknown owned by q
+  // (unknowns are owned by the box of their cell: left x-face, bottom
+  // y-face, pressure); reaching in either direction is a conflict.  Boxes
+  // take, in index order, the smallest colour unused by coloured conflicting
+  // boxes; the box lists are then sorted by colour.
+  void colour_boxes(Level<T>& lev) {
+    const BoxGeom& g = lev.g;
+    const int N = g.N, b = g.b, o = g.o, m = g.m, npd = g.npd, nb = npd * npd;
+    std::vector<std::vector<int>> adj(nb);
+    std::vector<int> stamp(nb, -1);
+    auto owner = [&](int i, int j) { return (wrapn(j, N) / b) * npd + wrapn(i, N) / b; };
+    for (int p = 0; p < nb; ++p) {
+      const int x0 = (p % npd) * b - o, y0 = (p / npd) * b - o;
+      auto touch = [&](int q) {
+        if (q != p && stamp[q] != p) {
+          stamp[q] = p;
+          adj[p].push_back(q);
+          adj[q].push_back(p);
+        }
+      };
+      auto ib_cols = [&](int comp, int i, int j) {
+        const CompFoot& f = lev.f[comp];
+        const int r = wrapn(j, N) * N + wrapn(i, N);
+        for (int k = f.tptr[r]; k < f.tptr[r + 1]; ++k) touch(owner(f.tcol[k] % N, f.tcol[k] / N));
+      };
+      for (int jj = 0; jj <= m; ++jj)
+        for (int ii = 0; ii <= m; ++ii) {
+          const int i = x0 + ii, j = y0 + jj;
+          if (jj < m) {  // x-face (i, j): u stencil, G (cells (i, j), (i-1, j)), IB row
+            touch(owner(i, j));
+            touch(owner(i - 1, j));
+            touch(owner(i + 1, j));
+            touch(owner(i, j - 1));
+            touch(owner(i, j + 1));
+            ib_cols(0, i, j);
+          }
+          if (ii < m) {  // y-face (i, j): v stencil, G (cells (i, j), (i, j-1)), IB row
+            touch(owner(i, j));
+            touch(owner(i - 1, j));
+            touch(owner(i + 1, j));
+            touch(owner(i, j - 1));
+            touch(owner(i, j + 1));
+            ib_cols(1, i, j);
+          }
+          if (ii < m && jj < m) {  // cell (i, j): D (faces (i, j), (i+1, j), (i, j+1))
+            touch(owner(i, j));
+            touch(owner(i + 1, j));
+            touch(owner(i, j + 1));
+          }
+        }
+    }
+    lev.box_colour.assign(nb, -1);
+    std::vector<int> mark;
+    lev.ncolour = 0;
+    for (int p = 0; p < nb; ++p) {
+      for (int q : adj[p])
+        if (lev.box_colour[q] >= 0) {
+          if ((int)mark.size() <= lev.box_colour[q]) mark.resize(lev.box_colour[q] + 1, -1);
+          mark[lev.box_colour[q]] = p;
+        }
+      int c = 0;
+      while (c < (int)mark.size() && mark[c] == p) ++c;
+      lev.box_colour[p] = c;
+      lev.ncolour = std::max(lev.ncolour, c + 1);
+    }
+    auto by_colour = [&](std::vector<int>& list, std::vector<int>& off) {
+      std::stable_sort(list.begin(), list.end(),
+                       [&](int a, int bb) { return lev.box_colour[a] < lev.box_colour[bb]; });
+      off.assign(lev.ncolour + 1, 0);
+      for (int q : list) off[lev.box_colour[q] + 1]++;
+      for (int c = 0; c < lev.ncolour; ++c) off[c + 1] += off[c];
+    };
+    by_colour(lev.ib_list, lev.ib_off);
+    by_colour(lev.int_list, lev.int_off);
+    lev.uniq = lev.ib_list;
+    if (!lev.int_list.empty()) lev.uniq.push_back(lev.int_list.front());
+  }
+
   void build_numeric(hipStream_t s) {
     // spring stiffness per incidence
     std::vector<double> ak(adj_nbr_.size());
@@ -341,7 +428,7 @@ class Solver final : public SolverBase {
       }
     }
     build_coarse(s);
-    if (d_.smoother == IBMG_RAS)
+    if (d_.smoother == IBMG_RAS || d_.smoother == IBMG_RMS)
       for (int l = 1; l <= L_; ++l) build_boxes(levels_[l], s);
     if (d_.smoother == IBMG_SC)
       for (int l = 1; l <= L_; ++l) sc_numeric(levels_[l], s);
@@ -501,10 +588,18 @@ class Solver final : public SolverBase {
     lev.d_int.upload(lev.int_list, s);
     lev.d_loc.upload(lev.loc_tab, s);
     {
-      const int n_int = (int)lev.int_list.size();
-      const int ks = ras_interior_ksplit(g, n_int);
-      if (ks > 1 && lev.int_part.n < (size_t)ks * n_int * g.nch * 64)
-        lev.int_part.alloc((size_t)ks * n_int * g.nch * 64);
+      // reduction slices of the interior product: the whole list (additive
+      // sweep) or each colour's range (multiplicative sweep)
+      size_t need = 0;
+      auto slices = [&](int cnt) {
+        const int ks = ras_interior_ksplit(g, cnt);
+        if (ks > 1) need = std::max(need, (size_t)ks * cnt * g.nch * 64);
+      };
+      if (d_.smoother == IBMG_RMS)
+        for (int c = 0; c < lev.ncolour; ++c) slices(lev.int_off[c + 1] - lev.int_off[c]);
+      else
+        slices((int)lev.int_list.size());
+      if (lev.int_part.n < need) lev.int_part.alloc(need);
     }
     lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
     const size_t budget = (size_t)1 << 30;
@@ -539,6 +634,7 @@ class Solver final : public SolverBase {
         lev.Z.alloc((size_t)nu_ * n);
       }
       lev.F.alloc(2 * (size_t)std::max(M_, 1));
+      if (l >= 1 && d_.smoother == IBMG_RMS) lev.rr.alloc(n);
       if (lev.use_spmv) {
         lev.Gd.alloc(2 * (size_t)lev.N * lev.N);
         if (std::is_same<T, float>::value) lev.Gt.alloc(2 * (size_t)lev.N * lev.N);
@@ -615,8 +711,25 @@ class Solver final : public SolverBase {
       lev.sc->apply(v, z, s);
       return;
     }
-    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.d_ib.p, lev.n_ib,
-                        lev.inv.p + (size_t)lev.n_ib * box_stride(lev), lev.d_int.p,
+    const T* shared = lev.inv.p + (size_t)lev.n_ib * box_stride(lev);
+    if (d_.smoother == IBMG_RMS) {
+      // Alg. 3 colour by colour from z = 0: each colour's boxes add their
+      // restricted local solutions of the residual of the current z
+      launch_fill<T>(z, T(0), 3 * (size_t)lev.N * lev.N, s);
+      for (int c = 0; c < lev.ncolour; ++c) {
+        const T* rc = v;
+        if (c > 0) {
+          op<T>(l, z, lev.rr.p, v, false, lev.F.p, s);
+          rc = lev.rr.p;
+        }
+        const int i0 = lev.ib_off[c], k0 = lev.int_off[c];
+        launch_ras_apply<T>(rc, z, lev.g, lev.inv.p + (size_t)i0 * box_stride(lev), lev.d_ib.p + i0,
+                            lev.ib_off[c + 1] - i0, shared, lev.d_int.p + k0, lev.int_off[c + 1] - k0, lev.d_loc.p,
+                            lev.int_part.p, s, 3, true);
+      }
+      return;
+    }
+    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.d_ib.p, lev.n_ib, shared, lev.d_int.p,
                         (int)lev.int_list.size(), lev.d_loc.p, lev.int_part.p, s);
   }
 
@@ -1013,6 +1126,7 @@ class Solver final : public SolverBase {
       v.push_back(lev.n_unique);
       v.push_back(lev.n_ib);
       v.push_back((int64_t)lev.f[0].tcol.size() + (int64_t)lev.f[1].tcol.size());
+      v.push_back(lev.ncolour);
     }
     return v;
   }

@@ -53,7 +53,7 @@ def _make_desc(system, precision):
     d.n_springs = int(springs.shape[0])
     d.ends = springs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     d.kappa = kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    d.smoother = {"ras": _lib.RAS, "sc": _lib.SC}[getattr(system, "smoother", "ras")]
+    d.smoother = {"ras": _lib.RAS, "sc": _lib.SC, "rms": _lib.RMS}[getattr(system, "smoother", "ras")]
     d.box = int(getattr(system, "box", 8))
     d.overlap = int(getattr(system, "overlap", 2))
     d.nu1 = int(getattr(system, "nu1", 2))
@@ -248,8 +248,9 @@ class StokesIB:
         v = list(buf[:wr.value])
         out = {"levels": []}
         for l in range(v[0]):
-            N, boxes, uniq, ib, tnnz = v[1 + 5 * l:6 + 5 * l]
-            out["levels"].append(dict(N=N, boxes=boxes, unique_boxes=uniq, ib_boxes=ib, ib_nnz=tnnz))
+            N, boxes, uniq, ib, tnnz, ncol = v[1 + 6 * l:7 + 6 * l]
+            out["levels"].append(dict(N=N, boxes=boxes, unique_boxes=uniq, ib_boxes=ib, ib_nnz=tnnz,
+                                      box_colours=ncol))
         return out
 
 

@@ -63,7 +63,14 @@ def _cases():
     c6 = W.plain_32(smoother="sc")
     c6.name = "plain_32_sc"
     c7 = W.Workload("annulus_64_sc", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4), smoother="sc")
-    return [c1, c2, c3, c4, c5, c6, c7]
+    # restricted multiplicative Schwarz (Alg. 3, colour-major box order): the
+    # membrane, the annulus at nonzero Reynolds number, and random springs
+    # whose long-range coupling needs up to 14 box colours
+    c8 = W.plain_32(smoother="rms")
+    c8.name = "plain_32_rms"
+    c9 = W.Workload("annulus_64_rms", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4), smoother="rms")
+    c10 = W.Workload("random_48_rms", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, c3.kappa, box=6, overlap=1, smoother="rms")
+    return [c1, c2, c3, c4, c5, c6, c7, c8, c9, c10]
 
 
 CASES = _cases()
@@ -211,3 +218,15 @@ def test_schur_setup_matches_oracle(pair):
         assert info["colours_p"] == int(sm.col_p.max()) + 1
         assert abs(info["lam_A"] - sm.lam_A) <= 1e-10 * abs(sm.lam_A)
         assert abs(info["lam_M"] - sm.lam_M) <= 1e-10 * abs(sm.lam_M)
+
+
+def test_rms_colours_match_oracle(pair):
+    """The multiplicative sweep's box colouring has the oracle's colour count
+    on every level (the sweep results, compared above, need the same
+    colours box by box)."""
+    wl, P, G = pair
+    if wl.smoother != "rms":
+        pytest.skip("not the multiplicative smoother")
+    st = G.stats()["levels"]
+    for l in range(1, len(P.levels)):
+        assert st[l]["box_colours"] == int(P.mg.smoothers[l].colour.max()) + 1, l
