@@ -55,6 +55,7 @@ def parse():
     p.add_argument("--box", type=int, default=16)
     p.add_argument("--overlap", type=int, default=4)
     p.add_argument("--batch", default="on", choices=["on", "off"])
+    p.add_argument("--rms", default="on", choices=["on", "off"])
     return p.parse_args()
 
 
@@ -72,6 +73,31 @@ def measured_traffic(alg_bytes):
     f_fetch = rec["copy_bytes_read"] / (rec["copy_fetch_kib"] * 1024.0)
     f_write = rec["copy_bytes_written"] / (rec["copy_write_kib"] * 1024.0)
     return rec["fetch_kib"] * 1024.0 * f_fetch + rec["write_kib"] * 1024.0 * f_write
+
+
+def smoother_bench(wl, b, smoother, box, overlap, reps=3):
+    """FP64 solve of the same workload and right-hand side with another
+    smoother: iterations, solve time and V-cycle rate."""
+    import copy
+    import torch
+    from paper_1612_02208_amd import StokesIB
+    w2 = copy.copy(wl)
+    w2.smoother, w2.box, w2.overlap = smoother, box, overlap
+    t0 = time.perf_counter()
+    g = StokesIB(w2, precision="fp64")
+    setup = time.perf_counter() - t0
+    x = torch.empty_like(b)
+    g.solve(b, rtol=1e-8, out=x)
+    ms, info = [], None
+    for _ in range(reps):
+        _, info = g.solve(b, rtol=1e-8, out=x)
+        ms.append(info["solve_ms"])
+    st = g.stats()["levels"]
+    g.close()
+    return {"smoother": smoother, "box": box, "overlap": overlap, "iters": info["iters"],
+            "solve_ms": float(np.median(ms)), "vcycles_per_s": info["vcycles"] / (float(np.median(ms)) / 1e3),
+            "rel_res_true": info["rel_res_true"], "setup_s": setup,
+            "box_colours": [lv["box_colours"] for lv in st[1:]]}
 
 
 def batch_bench(dev, reps=3):
@@ -274,6 +300,11 @@ def main():
                      "launch_ms": ras_ms, "alg_bytes_per_launch": alg_bytes},
         "kernels": kernels,
     }
+    if a.rms == "on":
+        t0 = time.perf_counter()
+        out["smoothers_fp64"] = [smoother_bench(wl, b, "rms", a.box, a.overlap),
+                                 smoother_bench(wl, b, "ras", 8, 2), smoother_bench(wl, b, "rms", 8, 2)]
+        print(f"[bench] smoother comparison {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if a.batch == "on":
         t0 = time.perf_counter()
         out["batch"] = batch_bench(dev)

@@ -349,18 +349,22 @@ __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restr
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0;
   int j = j0 + cph;
-  for (; j + 3 * VEC < j1; j += 4 * VEC) {
-    const V m0 = *reinterpret_cast<const V*>(Mc + (size_t)j * 64);
-    const V m1 = *reinterpret_cast<const V*>(Mc + (size_t)(j + VEC) * 64);
-    const V m2 = *reinterpret_cast<const V*>(Mc + (size_t)(j + 2 * VEC) * 64);
-    const V m3 = *reinterpret_cast<const V*>(Mc + (size_t)(j + 3 * VEC) * 64);
-    const T x0 = x[j], x1 = x[j + VEC], x2 = x[j + 2 * VEC], x3 = x[j + 3 * VEC];
-    const T* a0 = reinterpret_cast<const T*>(&m0);
-    const T* a1 = reinterpret_cast<const T*>(&m1);
-    const T* a2 = reinterpret_cast<const T*>(&m2);
-    const T* a3 = reinterpret_cast<const T*>(&m3);
+  // eight 16-byte loads in flight per lane, summed in a fixed tree
+  constexpr int UNR = 8;
+  for (; j + (UNR - 1) * VEC < j1; j += UNR * VEC) {
+    V m[UNR];
+    T xv[UNR];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] += (a0[v] * x0 + a1[v] * x1) + (a2[v] * x2 + a3[v] * x3);
+    for (int u = 0; u < UNR; ++u) m[u] = *reinterpret_cast<const V*>(Mc + (size_t)(j + u * VEC) * 64);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) xv[u] = x[j + u * VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      T t[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) t[u] = reinterpret_cast<const T*>(&m[u])[v] * xv[u];
+      acc[v] += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    }
   }
   for (; j < j1; j += VEC) {
     const V m0 = *reinterpret_cast<const V*>(Mc + (size_t)j * 64);

@@ -106,67 +106,72 @@ void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int
   IBMG_LAUNCH_CHECK();
 }
 
+// (J u)_l for every point and component: 16 lanes per (point, component),
+// lane s taking window slot s (masked slots carry weight 0), the lanes' terms
+// summed by shuffles in a fixed order.  Output planar U[comp * M + l] or
+// interleaved U[2 l + comp].
 template <typename T>
-__device__ __forceinline__ T interp_one(const T* __restrict__ f, const int* __restrict__ base,
-                                        const T* __restrict__ w, int l, int N) {
-  const int i0 = base[2 * l], j0 = base[2 * l + 1];
-  T acc = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int j = wrapi(j0 + b, N);
-    const T* row = f + (size_t)j * N;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc += w[(size_t)l * 16 + b * 4 + a] * row[wrapi(i0 + a, N)];
+__global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, const T* __restrict__ v,
+                                                      FootView<T> fx, FootView<T> fy, int M, int N,
+                                                      T* __restrict__ U, int interleaved) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int g = (int)(t / 16), s = (int)(t % 16);
+  const bool live = g < 2 * M;
+  const int comp = live && g >= M ? 1 : 0;
+  const int l = live ? g - comp * M : 0;
+  T a = 0;
+  if (live) {
+    const FootView<T>& f = comp ? fy : fx;
+    const T* src = comp ? v : u;
+    const int i = wrapi(f.base[2 * l] + (s & 3), N), j = wrapi(f.base[2 * l + 1] + (s >> 2), N);
+    a = f.w[(size_t)l * 16 + s] * src[(size_t)j * N + i];
   }
-  return acc;
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) a += __shfl_xor(a, off, 16);
+  if (live && s == 0) U[interleaved ? 2 * l + comp : comp * M + l] = a;
 }
 
-// F_l = sum over springs e at l of kappa_e ((J u)_l - (J u)_{other end}), both
-// components; F is planar [2][M].
+// F_l = sum over springs e at l of kappa_e (U_l - U_{other end}), both
+// components, from U = J u (planar [2][M]); F is planar [2][M].
 template <typename T>
-__global__ void k_ib_force(const T* __restrict__ u, const T* __restrict__ v, FootView<T> fx,
-                           FootView<T> fy, SpringView<T> sv, int N, T* __restrict__ F) {
+__global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __restrict__ F) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= sv.M) return;
-  const int e0 = sv.adj_ptr[l], e1 = sv.adj_ptr[l + 1];
+  const int M = sv.M;
+  const T U0 = U[l], U1 = U[M + l];
   T f0 = 0, f1 = 0;
-  if (e1 > e0) {
-    const T U0 = interp_one(u, fx.base, fx.w, l, N);
-    const T U1 = interp_one(v, fy.base, fy.w, l, N);
-    for (int e = e0; e < e1; ++e) {
-      const int q = sv.adj_nbr[e];
-      const T k = sv.adj_k[e];
-      f0 += k * (U0 - interp_one(u, fx.base, fx.w, q, N));
-      f1 += k * (U1 - interp_one(v, fy.base, fy.w, q, N));
-    }
+  for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
+    const int q = sv.adj_nbr[e];
+    const T k = sv.adj_k[e];
+    f0 += k * (U0 - U[q]);
+    f1 += k * (U1 - U[M + q]);
   }
   F[l] = f0;
-  F[sv.M + l] = f1;
+  F[M + l] = f1;
 }
 
 template <typename T>
-void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
-                     int N, T* F, hipStream_t s) {
-  if (!sv.M) return;
-  hipLaunchKernelGGL((k_ib_force<T>), dim3(cdiv(sv.M, 128)), dim3(128), 0, s, u, v, fx, fy, sv, N, F);
+static void launch_interp_lanes(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
+                                int interleaved, hipStream_t s) {
+  hipLaunchKernelGGL((k_interp_lanes<T>), dim3(cdiv((size_t)2 * M * 16, 256)), dim3(256), 0, s, u, v, fx, fy, M, N,
+                     U, interleaved);
   IBMG_LAUNCH_CHECK();
 }
 
 template <typename T>
-__global__ void k_interp(const T* __restrict__ u, const T* __restrict__ v, FootView<T> fx,
-                         FootView<T> fy, int M, int N, T* __restrict__ U) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= M) return;
-  U[2 * l] = interp_one(u, fx.base, fx.w, l, N);
-  U[2 * l + 1] = interp_one(v, fy.base, fy.w, l, N);
+void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
+                     int N, T* U, T* F, hipStream_t s) {
+  if (!sv.M) return;
+  launch_interp_lanes<T>(u, v, fx, fy, sv.M, N, U, 0, s);
+  hipLaunchKernelGGL((k_spring_force<T>), dim3(cdiv(sv.M, 256)), dim3(256), 0, s, U, sv, F);
+  IBMG_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
                    hipStream_t s) {
   if (!M) return;
-  hipLaunchKernelGGL((k_interp<T>), dim3(cdiv(M, 128)), dim3(128), 0, s, u, v, fx, fy, M, N, U);
-  IBMG_LAUNCH_CHECK();
+  launch_interp_lanes<T>(u, v, fx, fy, M, N, U, 1, s);
 }
 
 // f_face = scale * sum_(l, slot) w F_l, F interleaved [M][2]; f = [2][N][N].
@@ -290,9 +295,9 @@ void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, con
 }
 
 template void launch_ib_force<double>(const double*, const double*, FootView<double>,
-                                      FootView<double>, SpringView<double>, int, double*, hipStream_t);
+                                      FootView<double>, SpringView<double>, int, double*, double*, hipStream_t);
 template void launch_ib_force<float>(const float*, const float*, FootView<float>, FootView<float>,
-                                     SpringView<float>, int, float*, hipStream_t);
+                                     SpringView<float>, int, float*, float*, hipStream_t);
 template void launch_interp<double>(const double*, const double*, FootView<double>, FootView<double>,
                                     int, int, double*, hipStream_t);
 

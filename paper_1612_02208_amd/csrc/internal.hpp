@@ -200,7 +200,7 @@ void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int
                        int Nf, int Nc, double* cw, hipStream_t s);
 template <typename T>
 void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
-                     int N, T* F, hipStream_t s);
+                     int N, T* U, T* F, hipStream_t s);   // U: [2][M] scratch (J u)
 template <typename T>
 void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N,
                    T* U, hipStream_t s);

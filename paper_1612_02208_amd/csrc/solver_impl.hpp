@@ -633,7 +633,7 @@ class Solver final : public SolverBase {
         lev.V.alloc((size_t)(nu_ + 1) * n);
         lev.Z.alloc((size_t)nu_ * n);
       }
-      lev.F.alloc(2 * (size_t)std::max(M_, 1));
+      lev.F.alloc(4 * (size_t)std::max(M_, 1));   // forces [2][M] then J u [2][M]
       if (l >= 1 && d_.smoother == IBMG_RMS) lev.rr.alloc(n);
       if (lev.use_spmv) {
         lev.Gd.alloc(2 * (size_t)lev.N * lev.N);
@@ -643,7 +643,7 @@ class Solver final : public SolverBase {
       lev.scal.alloc(64);
       lev.part.alloc(2 * kPartStride);
     }
-    Fd_.alloc(2 * (size_t)std::max(M_, 1));
+    Fd_.alloc(4 * (size_t)std::max(M_, 1));   // forces [2][M] then J u [2][M]
     Uw_.alloc(2 * (size_t)std::max(M_, 1));
     Ul_.alloc(2 * (size_t)std::max(M_, 1));
     IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
@@ -683,7 +683,8 @@ class Solver final : public SolverBase {
         launch_ib_spmv<U>(x, G, csr<U>(lev.f[0]), csr<U>(lev.f[1]), lev.N, s);
         Gp = G;
       } else {
-        launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N, F, s);
+        launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N,
+                           F + 2 * (size_t)std::max(M_, 1), F, s);
         Fp = F;
       }
     }
