@@ -435,8 +435,9 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
 };
 
-// Boxes per interior tile of the single-system product (two 16 x 16 output
-// tiles per wave; wider tiles measured slower: fewer work-groups in flight)
+// Reference tile width of the single-system interior product: the number of
+// reduction slices is derived from it, so the sums (and the results) do not
+// depend on the tile width a level runs with (16 or 32, picked by timing).
 constexpr int kIntTile = 32;
 
 // Shared memory of one interior tile: the gathered residual columns and the
@@ -559,14 +560,14 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
   }
 }
 
-template <typename T>
+template <typename T, int TB>
 __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T* __restrict__ z,
                                                       BoxGeom g, const T* __restrict__ M,
                                                       const int* __restrict__ boxes, int nlist,
                                                       const int* __restrict__ loc_tab,
                                                       T* __restrict__ part, int ksplit, bool acc) {
-  __shared__ IntTileSmem<T, kIntTile> sm;
-  ras_int_tile<T, kIntTile>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit,
+  __shared__ IntTileSmem<T, TB> sm;
+  ras_int_tile<T, TB>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit,
                       loc_tab, nullptr, part, sm, acc);
 }
 
@@ -599,7 +600,7 @@ int ras_interior_ksplit(const BoxGeom& g, int n_int) {
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s, int parts, bool acc) {
+                      T* part, hipStream_t s, int parts, bool acc, int tb) {
   if ((parts & 1) && n_ib > 0) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
     hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc);
@@ -607,8 +608,12 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   }
   if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
-    hipLaunchKernelGGL((k_ras_interior<T>), dim3((n_int + kIntTile - 1) / kIntTile, g.nch, ks), dim3(256), 0, s, r, z, g,
-                       shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
+    if (tb == 16)
+      hipLaunchKernelGGL((k_ras_interior<T, 16>), dim3((n_int + 15) / 16, g.nch, ks), dim3(256), 0, s, r, z, g,
+                         shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
+    else
+      hipLaunchKernelGGL((k_ras_interior<T, 32>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
+                         shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
     IBMG_LAUNCH_CHECK();
     if (ks > 1) {
       const size_t tot = (size_t)n_int * g.nown;
@@ -854,10 +859,10 @@ template void launch_extract_owned<double>(const double*, int, BoxGeom, double*,
 template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t);
 template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*, int,
                                        const double*, const int*, int, const int*, double*,
-                                       hipStream_t, int, bool);
+                                       hipStream_t, int, bool, int);
 template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float*, const int*, int,
                                       const float*, const int*, int, const int*, float*,
-                                      hipStream_t, int, bool);
+                                      hipStream_t, int, bool, int);
 template void launch_coarse_apply<double>(const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_apply<float>(const double*, int, const float*, float*, hipStream_t);
 template void launch_coarse_apply_batch<double>(const double*, int, const double*, double*, int, hipStream_t);

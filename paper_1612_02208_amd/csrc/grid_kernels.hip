@@ -19,19 +19,11 @@ static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 // the same J^T K' J chain with J standing in for S^T (S = J^* / h^2).
 // ---------------------------------------------------------------------------
 template <typename T, bool TRANS, bool RESID, int IBM>
-__global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __restrict__ y,
-                                               const T* __restrict__ b, const T* __restrict__ F,
-                                               const T* __restrict__ Gib, FootView<T> fx,
-                                               FootView<T> fy, int N, int M, StokesCoef<T> c,
-                                               size_t bs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
+__device__ __forceinline__ void apply_point(const T* __restrict__ w, T* __restrict__ y, const T* __restrict__ b,
+                                            const T* __restrict__ F, const T* __restrict__ Gib,
+                                            const FootView<T>& fx, const FootView<T>& fy, int N, int M,
+                                            const StokesCoef<T>& c, int i, int j, T out[3]) {
   const size_t n = (size_t)N * N;
-  // batched launches: system blockIdx.z, systems bs apart
-  w += blockIdx.z * bs;
-  y += blockIdx.z * bs;
-  if (RESID) b += blockIdx.z * bs;
   const T* u = w;
   const T* v = w + n;
   const T* p = w + 2 * n;
@@ -86,7 +78,69 @@ __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __res
   y[c0] = yu;
   y[n + c0] = yv;
   y[2 * n + c0] = yp;
+  out[0] = yu;
+  out[1] = yv;
+  out[2] = yp;
 }
+
+template <typename T, bool TRANS, bool RESID, int IBM>
+__global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __restrict__ y,
+                                               const T* __restrict__ b, const T* __restrict__ F,
+                                               const T* __restrict__ Gib, FootView<T> fx,
+                                               FootView<T> fy, int N, int M, StokesCoef<T> c,
+                                               size_t bs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  // batched launches: system blockIdx.z, systems bs apart
+  w += blockIdx.z * bs;
+  y += blockIdx.z * bs;
+  if (RESID) b += blockIdx.z * bs;
+  T out[3];
+  apply_point<T, TRANS, RESID, IBM>(w, y, b, F, Gib, fx, fy, N, M, c, i, j, out);
+}
+
+// The same (non-transposed) with the first Gram-Schmidt dot products fused:
+// partial[blk * nvec + q] = this block's sum of V_q . y over its rows
+// (V = null: nvec = 1 and the sum of y . y), reduced over the block's four
+// waves by shuffles and shared memory in a fixed order; blk = the block's
+// linear index.
+template <typename T, bool RESID, int IBM>
+__global__ void __launch_bounds__(256) k_apply_dots(const T* __restrict__ w, T* __restrict__ y,
+                                                    const T* __restrict__ b, const T* __restrict__ F,
+                                                    const T* __restrict__ Gib, FootView<T> fx, FootView<T> fy,
+                                                    int N, int M, StokesCoef<T> c, const T* __restrict__ V,
+                                                    int nvec, size_t vstride, double* __restrict__ partial) {
+  __shared__ double red[9][4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const bool live = i < N && j < N;
+  const size_t n = (size_t)N * N;
+  T out[3] = {0, 0, 0};
+  if (live) apply_point<T, false, RESID, IBM>(w, y, b, F, Gib, fx, fy, N, M, c, i, j, out);
+  const size_t c0 = (size_t)j * N + i;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int q = 0; q < nvec; ++q) {
+    double d = 0.0;
+    if (live) {
+      if (V) {
+        const T* vq = V + (size_t)q * vstride;
+        d = (double)vq[c0] * (double)out[0] + (double)vq[n + c0] * (double)out[1] +
+            (double)vq[2 * n + c0] * (double)out[2];
+      } else {
+        d = (double)out[0] * (double)out[0] + (double)out[1] * (double)out[1] + (double)out[2] * (double)out[2];
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    if (lane == 0) red[q][wave] = d;
+  }
+  __syncthreads();
+  if (tid < nvec)
+    partial[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * nvec + tid] =
+        (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+}
+
 
 template <typename T, int IBM>
 static void launch_apply_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
@@ -119,6 +173,36 @@ void launch_apply(const T* w, T* y, const T* b, const T* F, const T* G, FootView
     launch_apply_m<T, 1>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
   else
     launch_apply_m<T, 0>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
+}
+
+template <typename T, int IBM>
+static void launch_apply_dots_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+                                FootView<T> fy, int N, int M, StokesCoef<T> c, const T* V, int nvec,
+                                size_t vstride, double* partial, hipStream_t s) {
+  dim3 blk(64, 4);
+  dim3 grd((N + 63) / 64, (N + 3) / 4);
+  if (b)
+    hipLaunchKernelGGL((k_apply_dots<T, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
+                       vstride, partial);
+  else
+    hipLaunchKernelGGL((k_apply_dots<T, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
+                       vstride, partial);
+  IBMG_LAUNCH_CHECK();
+}
+
+int apply_blocks(int N) { return ((N + 63) / 64) * ((N + 3) / 4); }
+
+template <typename T>
+void launch_apply_dots(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx, FootView<T> fy,
+                       int N, int M, StokesCoef<T> c, const T* V, int nvec, size_t vstride, double* partial,
+                       hipStream_t s) {
+  if (nvec < 1 || nvec > 9) throw Error(IBMG_ERR_ARG, "fused dots take 1..9 vectors");
+  if (G)
+    launch_apply_dots_m<T, 2>(w, y, b, F, G, fx, fy, N, M, c, V, nvec, vstride, partial, s);
+  else if (F)
+    launch_apply_dots_m<T, 1>(w, y, b, F, G, fx, fy, N, M, c, V, nvec, vstride, partial, s);
+  else
+    launch_apply_dots_m<T, 0>(w, y, b, F, G, fx, fy, N, M, c, V, nvec, vstride, partial, s);
 }
 
 // Stencil part of L_IB (or the residual) for nsys systems of one grid size,
@@ -696,6 +780,9 @@ void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_
   template void launch_combine<T>(T*, const T*, int, size_t, const double*, size_t, hipStream_t); \
   template void launch_block_sums<T>(const T*, int, double*, int, hipStream_t);                   \
   template void launch_subtract_means<T>(T*, int, const double*, int, hipStream_t);               \
+  template void launch_apply_dots<T>(const T*, T*, const T*, const T*, const T*, FootView<T>,     \
+                                     FootView<T>, int, int, StokesCoef<T>, const T*, int, size_t,  \
+                                     double*, hipStream_t);                                        \
   template void launch_apply_batch<T>(const T*, T*, const T*, int, StokesCoef<T>, int, size_t,    \
                                       hipStream_t);                                               \
   template void launch_ib_rows<T>(const T*, T*, const int*, const int*, const int*, const T*, int, \

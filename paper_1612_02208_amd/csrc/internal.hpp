@@ -135,6 +135,14 @@ constexpr int kMaxNloc = 2 * kMaxBoxSide * (kMaxBoxSide + 1) + kMaxBoxSide * kMa
 template <typename T>
 void launch_apply(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
                   FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose, hipStream_t s);
+// L_IB w (b != null: b - L_IB w) with the first Gram-Schmidt pass fused:
+// partial[blk * nvec + q] = block sums of V_q . y (V = null: nvec = 1, y . y)
+// over apply_blocks(N) blocks; nvec <= 9
+template <typename T>
+void launch_apply_dots(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx, FootView<T> fy,
+                       int N, int M, StokesCoef<T> c, const T* V, int nvec, size_t vstride, double* partial,
+                       hipStream_t s);
+int apply_blocks(int N);
 template <typename T>
 struct CsrT {
   const int* ptr;
@@ -180,9 +188,10 @@ void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_
 int dots_blocks(size_t n, int cap = 256);
 
 // fused Gram-Schmidt passes (krylov_kernels.hip); nblk = producer blocks
+// nblk_in: blocks of the producer of pin (<= 0: nblk)
 template <typename T>
 void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
-                     double* hcol, double* pout, hipStream_t s);
+                     double* hcol, double* pout, hipStream_t s, int nblk_in = 0);
 template <typename T>
 void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
                      double* hcol, double* pout, hipStream_t s);
@@ -223,11 +232,12 @@ template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
 // parts: bit 0 = IB boxes (k_ras_ib), bit 1 = interior boxes
 // (k_ras_interior and its slice sum); the smoother launches both.
-// acc: add the local solutions to z on the owned sets instead of storing them
+// acc: add the local solutions to z on the owned sets instead of storing them;
+// tb: interior tile width (16 or 32 boxes; results do not depend on it)
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s, int parts = 3, bool acc = false);
+                      T* part, hipStream_t s, int parts = 3, bool acc = false, int tb = 32);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);
 void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,
@@ -277,7 +287,8 @@ void launch_subtract_means_b(T* a, int N, size_t bs, const double* sums, size_t 
                              hipStream_t s);
 template <typename T>
 void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
-                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s);
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
+                       int nblk_in = 0);
 template <typename T>
 void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s);

@@ -78,6 +78,7 @@ struct Level {
   // [int_off[c], int_off[c+1])
   int ncolour = 0;
   std::vector<int> box_colour, ib_off, int_off;
+  int int_tb = 32;        // interior tile width, picked by timing at set-up
   DBuf<T> rr;             // residual between colours
   // work vectors
   DBuf<T> w, b, r, t, V, Z, F;
@@ -106,6 +107,7 @@ class Solver final : public SolverBase {
     build_structure(s);
     build_numeric(s);
     alloc_work(s);
+    tune_interior(s);
     IBMG_HIP(hipStreamSynchronize(s));
   }
 
@@ -325,6 +327,51 @@ class Solver final : public SolverBase {
   }
 
   size_t box_stride(const Level<T>& lev) const { return (size_t)lev.g.nch * lev.g.nloc * 64; }
+
+  // elements of the interior product's slice buffer for cnt boxes
+  static size_t interior_part_need(const BoxGeom& g, int cnt) {
+    if (cnt <= 0) return 0;
+    const int ks = ras_interior_ksplit(g, cnt);
+    return ks > 1 ? (size_t)ks * cnt * g.nch * 64 : 0;
+  }
+
+  // Every Schwarz launch goes through here: the interior product's slice
+  // buffer must hold the launch's reduction slices.
+  void ras_launch(Level<T>& lev, const T* r, T* z, const T* inv, const int* ib, int n_ib, const int* in, int n_int,
+                  hipStream_t s, int parts, bool acc, int tb) {
+    require(lev.int_part.n >= interior_part_need(lev.g, n_int), "interior slice buffer too small");
+    launch_ras_apply<T>(r, z, lev.g, inv, ib, n_ib, lev.inv.p + (size_t)lev.n_ib * box_stride(lev), in, n_int,
+                        lev.d_loc.p, lev.int_part.p, s, parts, acc, tb);
+  }
+
+  // partial-sum buffers of a level: the reductions' blocks x vectors, and the
+  // fused operator kernel's blocks x (nu + 1) vectors
+  static size_t part_stride(const Level<T>& lev) {
+    return std::max(kPartStride, (size_t)apply_blocks(lev.N) * (kMaxNu + 1));
+  }
+
+  // Interior tile width per Schwarz level: time the interior product with
+  // 16- and 32-box tiles (HIP events, on the level's work vectors) and keep
+  // the faster.  Both compute the same sums in the same order.
+  void tune_interior(hipStream_t s) {
+    if (d_.smoother != IBMG_RAS && d_.smoother != IBMG_RMS) return;
+    for (int l = 1; l <= L_; ++l) {
+      Level<T>& lev = levels_[l];
+      const int n_int = (int)lev.int_list.size();
+      if (n_int == 0) continue;
+      launch_fill<T>(lev.r.p, T(1), 3 * (size_t)lev.N * lev.N, s);
+      double best = 1e300;
+      for (int tb : {32, 16}) {
+        const double ms = time_launches([&] {
+          ras_launch(lev, lev.r.p, lev.t.p, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, n_int, s, 2, false, tb);
+        }, 5, s);
+        if (ms < best) {
+          best = ms;
+          lev.int_tb = tb;
+        }
+      }
+    }
+  }
 
   // Colours of the multiplicative sweep (Alg. 3 in colour-major order).
   // Box p reaches box q when a row of p's enlarged box couples, through the
@@ -589,16 +636,12 @@ class Solver final : public SolverBase {
     lev.d_loc.upload(lev.loc_tab, s);
     {
       // reduction slices of the interior product: the whole list (additive
-      // sweep) or each colour's range (multiplicative sweep)
-      size_t need = 0;
-      auto slices = [&](int cnt) {
-        const int ks = ras_interior_ksplit(g, cnt);
-        if (ks > 1) need = std::max(need, (size_t)ks * cnt * g.nch * 64);
-      };
+      // sweep, tuning, single-kernel timing) and each colour's range
+      // (multiplicative sweep)
+      size_t need = interior_part_need(g, (int)lev.int_list.size());
       if (d_.smoother == IBMG_RMS)
-        for (int c = 0; c < lev.ncolour; ++c) slices(lev.int_off[c + 1] - lev.int_off[c]);
-      else
-        slices((int)lev.int_list.size());
+        for (int c = 0; c < lev.ncolour; ++c)
+          need = std::max(need, interior_part_need(g, lev.int_off[c + 1] - lev.int_off[c]));
       if (lev.int_part.n < need) lev.int_part.alloc(need);
     }
     lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
@@ -641,7 +684,7 @@ class Solver final : public SolverBase {
       }
       lev.H.alloc((size_t)(kMaxNu + 1) * kMaxNu);
       lev.scal.alloc(64);
-      lev.part.alloc(2 * kPartStride);
+      lev.part.alloc(2 * part_stride(lev));
     }
     Fd_.alloc(4 * (size_t)std::max(M_, 1));   // forces [2][M] then J u [2][M]
     Uw_.alloc(2 * (size_t)std::max(M_, 1));
@@ -692,6 +735,31 @@ class Solver final : public SolverBase {
                     trans, s);
   }
 
+  // y = L_IB^l x (b != null: y = b - L_IB^l x) with the first Gram-Schmidt
+  // pass fused into the operator kernel: partial holds apply_blocks(N)
+  // blocks of the dots V_q . y, q < nvec (V = null: y . y)
+  template <typename U>
+  void op_dots(int l, const U* x, U* y, const U* b, const U* V, int nvec, size_t vstride, double* partial, U* F,
+               hipStream_t s) {
+    Level<T>& lev = levels_[l];
+    const size_t nn = (size_t)lev.N * lev.N;
+    const U* Fp = nullptr;
+    const U* Gp = nullptr;
+    if (M_ > 0 && E_ > 0) {
+      if (lev.use_spmv) {
+        U* G = gbuf<U>(lev);
+        launch_ib_spmv<U>(x, G, csr<U>(lev.f[0]), csr<U>(lev.f[1]), lev.N, s);
+        Gp = G;
+      } else {
+        launch_ib_force<U>(x, x + nn, fview<U>(lev.f[0]), fview<U>(lev.f[1]), sview<U>(), lev.N,
+                           F + 2 * (size_t)std::max(M_, 1), F, s);
+        Fp = F;
+      }
+    }
+    launch_apply_dots<U>(x, y, b, Fp, Gp, fview<U>(lev.f[0]), fview<U>(lev.f[1]), lev.N, M_, coef<U>(lev), V, nvec,
+                         vstride, partial, s);
+  }
+
   template <typename U>
   CsrT<U> csr(CompFoot& f) {
     if constexpr (std::is_same<U, double>::value)
@@ -712,7 +780,6 @@ class Solver final : public SolverBase {
       lev.sc->apply(v, z, s);
       return;
     }
-    const T* shared = lev.inv.p + (size_t)lev.n_ib * box_stride(lev);
     if (d_.smoother == IBMG_RMS) {
       // Alg. 3 colour by colour from z = 0: each colour's boxes add their
       // restricted local solutions of the residual of the current z
@@ -724,14 +791,13 @@ class Solver final : public SolverBase {
           rc = lev.rr.p;
         }
         const int i0 = lev.ib_off[c], k0 = lev.int_off[c];
-        launch_ras_apply<T>(rc, z, lev.g, lev.inv.p + (size_t)i0 * box_stride(lev), lev.d_ib.p + i0,
-                            lev.ib_off[c + 1] - i0, shared, lev.d_int.p + k0, lev.int_off[c + 1] - k0, lev.d_loc.p,
-                            lev.int_part.p, s, 3, true);
+        ras_launch(lev, rc, z, lev.inv.p + (size_t)i0 * box_stride(lev), lev.d_ib.p + i0, lev.ib_off[c + 1] - i0,
+                   lev.d_int.p + k0, lev.int_off[c + 1] - k0, s, 3, true, lev.int_tb);
       }
       return;
     }
-    launch_ras_apply<T>(v, z, lev.g, lev.inv.p, lev.d_ib.p, lev.n_ib, shared, lev.d_int.p,
-                        (int)lev.int_list.size(), lev.d_loc.p, lev.int_part.p, s);
+    ras_launch(lev, v, z, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, (int)lev.int_list.size(), s, 3, false,
+               lev.int_tb);
   }
 
   // w <- w + e, e = nu FGMRES iterations (CGS2) on L e = b - L w from e = 0.
@@ -745,24 +811,32 @@ class Solver final : public SolverBase {
       launch_fill<T>(w, T(0), n, s);
       r0 = b;
     } else {
-      op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
+      // r = b - L w with its squared norm's block sums
+      op_dots<T>(l, w, lev.r.p, b, nullptr, 1, 0, lev.part.p, lev.F.p, s);
       r0 = lev.r.p;
     }
     double* beta = lev.scal.p;
     double* pa = lev.part.p;
-    double* pb = lev.part.p + kPartStride;
-    launch_dots<T>(r0, 1, n, r0, n, pa, nblk, s);
+    double* pb = lev.part.p + part_stride(lev);
+    const int nab = apply_blocks(lev.N);  // blocks of the fused operator + dots kernel
     T* V = lev.V.p;
     T* Z = lev.Z.p;
-    launch_scale_red<T>(r0, V, n, pa, nblk, beta, s);
+    if (w_zero) {
+      launch_dots<T>(r0, 1, n, r0, n, pa, nblk, s);
+      launch_scale_red<T>(r0, V, n, pa, nblk, beta, s);
+    } else {
+      launch_scale_red<T>(r0, V, n, pa, nab, beta, s);
+    }
     for (int k = 0; k < nu; ++k) {
       T* vk = V + (size_t)k * n;
       T* zk = Z + (size_t)k * n;
       T* t = V + (size_t)(k + 1) * n;
       basic_smoother(l, vk, zk, s);
-      op<T>(l, zk, t, nullptr, false, lev.F.p, s);
+      // t = L z with the pass-1 dots V_q . t; pass 2 and the norm follow
+      op_dots<T>(l, zk, t, nullptr, V, k + 1, n, pa, lev.F.p, s);
       double* hcol = lev.H.p + (size_t)k * ldh;
-      orthogonalise<T>(V, k + 1, n, t, hcol, pa, pb, nblk, s);
+      launch_upd_dots<T>(t, V, k + 1, n, n, pa, nblk, hcol, pb, s, nab);
+      launch_upd_norm<T>(t, V, k + 1, n, n, pb, nblk, hcol, pa, s);
       launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
     }
     launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s);
@@ -1098,9 +1172,8 @@ class Solver final : public SolverBase {
       }
       const int part = kernel == IBMG_KERNEL_RAS_IB ? 1 : 2;
       ms = time_launches([&] {
-        launch_ras_apply<T>(lev.r.p, lev.t.p, g, lev.inv.p, lev.d_ib.p, lev.n_ib,
-                            lev.inv.p + (size_t)lev.n_ib * box_stride(lev), lev.d_int.p, n_int, lev.d_loc.p,
-                            lev.int_part.p, s, part);
+        ras_launch(lev, lev.r.p, lev.t.p, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, n_int, s, part, false,
+                   lev.int_tb);
       }, reps, s);
     } else if (kernel == IBMG_KERNEL_STENCIL) {
       by = 2.0 * (double)n * ts;

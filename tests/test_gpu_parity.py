@@ -230,3 +230,28 @@ def test_rms_colours_match_oracle(pair):
     st = G.stats()["levels"]
     for l in range(1, len(P.levels)):
         assert st[l]["box_colours"] == int(P.mg.smoothers[l].colour.max()) + 1, l
+
+
+def test_single_kernel_timing_every_level(pair):
+    """ibmg_kernel_time launches the Schwarz kernels over a level's whole box
+    lists; on multiplicative-sweep levels that is more than one colour's
+    range, so the interior product's slice buffer must hold it (the library
+    checks this before every launch).  Algorithmic bytes and flops follow
+    the box counts."""
+    wl, P, G = pair
+    if wl.smoother == "sc":
+        pytest.skip("Schur-complement smoother")
+    st = G.stats()["levels"]
+    for l in range(1, len(P.levels)):
+        lv = st[l]
+        n_int = lv["boxes"] - lv["ib_boxes"]
+        if lv["ib_boxes"]:
+            t = G.kernel_time("ras_ib", l, 2)
+            assert t["ms"] > 0 and t["bytes"] > 0
+        if n_int:
+            t = G.kernel_time("ras_interior", l, 2)
+            assert t["ms"] > 0 and t["flops"] > 0
+    # the handle still computes the oracle's smoother after the timing runs
+    r = np.random.default_rng(12).uniform(-1, 1, P.levels[-1].n)
+    z = host(G.smoother_apply(-1, dev(r)))
+    assert rel(z, P.mg.smoothers[-1](r)) < SOLVE_TOL
