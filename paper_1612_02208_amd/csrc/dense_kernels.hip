@@ -328,22 +328,24 @@ struct Vec16<float> {
   static constexpr int n = 4;
 };
 
-// One (box, 64-row chunk) item: Mc is the chunk of the box's owned-row
-// inverse, r and z the box's system vectors; x holds nloc values, part 256.
+// One (box, 64-row chunk) item over columns [cb, ce) of the chunk: Mc is the
+// chunk of the box's owned-row inverse, r and z the box's system vectors; x
+// holds nloc values (LDS, indexed by column), part 256.  With pout the 64
+// row sums of this column slice go to pout instead of z.
 template <typename T>
 __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
                                              const T* __restrict__ Mc, int pid, int chunk, T* x, T* part,
-                                             bool acc_mode) {
+                                             bool acc_mode, int cb, int ce, T* __restrict__ pout) {
   using V = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   constexpr int LPC = 64 / VEC;  // lanes per column
-  for (int k = threadIdx.x; k < g.nloc; k += blockDim.x) x[k] = r[box_glob(g, pid, k)];
+  for (int k = cb + threadIdx.x; k < ce; k += blockDim.x) x[k] = r[box_glob(g, pid, k)];
   __syncthreads();
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int cph = lane / LPC;           // column phase 0..VEC-1
   const int rl = (lane % LPC) * VEC;    // first of this lane's VEC rows
-  const int per = ((g.nloc + 4 * VEC - 1) / (4 * VEC)) * VEC;
-  const int j0 = q * per, j1 = j0 + per < g.nloc ? j0 + per : g.nloc;
+  const int per = ((ce - cb + 4 * VEC - 1) / (4 * VEC)) * VEC;
+  const int j0 = cb + q * per, j1 = j0 + per < ce ? j0 + per : ce;
   Mc += rl;
   T acc[VEC];
 #pragma unroll
@@ -384,23 +386,55 @@ __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restr
   __syncthreads();
   if (q == 0) {
     const int row = chunk * 64 + lane;
-    if (row < g.nown) {
-      const T v = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+    const T v = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+    if (pout) {
+      pout[lane] = v;
+    } else if (row < g.nown) {
       const size_t o = own_glob(g, pid, row);
       z[o] = acc_mode ? z[o] + v : v;
     }
   }
 }
 
+// grid (boxes, row chunks, column slices); with more than one slice the
+// slices' row sums go to spart[((slice * n_ib + box) * nch + chunk) * 64 + row]
 template <typename T>
 __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
-                                                const T* __restrict__ inv, const int* __restrict__ boxes, bool acc) {
+                                                const T* __restrict__ inv, const int* __restrict__ boxes, bool acc,
+                                                T* __restrict__ spart) {
   extern __shared__ char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
   T* part = x + ((g.nloc + 3) & ~3);
-  const int slot = blockIdx.x;
+  const int slot = blockIdx.x, ks = gridDim.z;
+  const int cs = ((g.nloc + ks - 1) / ks + 63) / 64 * 64;
+  const int cb = blockIdx.z * cs, ce = cb + cs < g.nloc ? cb + cs : g.nloc;
+  T* pout = ks > 1 ? spart + (((size_t)blockIdx.z * gridDim.x + slot) * g.nch + blockIdx.y) * 64 : nullptr;
   ras_ib_chunk<T>(r, z, g, inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64, boxes[slot], blockIdx.y, x,
-                  part, acc);
+                  part, acc, cb < ce ? cb : ce, ce, pout);
+}
+
+// z[owned rows of IB box b] (=, or += with acc) the sum of the column
+// slices' row sums, in slice order.
+template <typename T>
+__global__ void k_ras_ib_sum(const T* __restrict__ spart, T* __restrict__ z, BoxGeom g,
+                             const int* __restrict__ boxes, int n_ib, int ks, bool acc) {
+  const size_t tot = (size_t)n_ib * g.nown;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t / g.nown), row = (int)(t % g.nown);
+    T a = 0;
+    for (int sl = 0; sl < ks; ++sl) a += spart[(((size_t)sl * n_ib + b) * g.nch + row / 64) * 64 + row % 64];
+    const size_t o = own_glob(g, boxes[b], row);
+    z[o] = acc ? z[o] + a : a;
+  }
+}
+
+// Column slices of the IB-box kernel: enough work-groups to cover the
+// device (>= 1024) while every slice keeps at least 128 columns.
+int ras_ib_ksplit(const BoxGeom& g, int n_ib) {
+  if (n_ib <= 0) return 1;
+  int ks = 1;
+  while (ks < 16 && n_ib * g.nch * ks < 1024 && g.nloc / (2 * ks) >= 128) ks *= 2;
+  return ks;
 }
 
 // ---------------------------------------------------------------------------
@@ -603,8 +637,16 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
                       T* part, hipStream_t s, int parts, bool acc, int tb) {
   if ((parts & 1) && n_ib > 0) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
-    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc);
+    const int ks = ras_ib_ksplit(g, n_ib);
+    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch, ks), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc, part);
     IBMG_LAUNCH_CHECK();
+    if (ks > 1) {
+      const size_t tot = (size_t)n_ib * g.nown;
+      int grid = cdiv(tot, 256);
+      if (grid > 4096) grid = 4096;
+      hipLaunchKernelGGL((k_ras_ib_sum<T>), dim3(grid), dim3(256), 0, s, part, z, g, ib_boxes, n_ib, ks, acc);
+      IBMG_LAUNCH_CHECK();
+    }
   }
   if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
@@ -660,7 +702,7 @@ __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* _
       if (active && !active[sy]) continue;
       T* x = reinterpret_cast<T*>(smem_raw);
       ras_ib_chunk<T>(r + (size_t)sy * sys_n, z + (size_t)sy * sys_n, g, ib_inv[e] + (size_t)c * g.nloc * 64,
-                      ent - sy * nbox, c, x, x + ((g.nloc + 3) & ~3), false);
+                      ent - sy * nbox, c, x, x + ((g.nloc + 3) & ~3), false, 0, g.nloc, nullptr);
     }
     __syncthreads();
   }

@@ -240,6 +240,9 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
                       T* part, hipStream_t s, int parts = 3, bool acc = false, int tb = 32);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);
+// column slices of the IB-box kernel (part holds ksplit * n_ib * nch * 64);
+// the IB and interior launches of one sweep use the slice buffer in turn
+int ras_ib_ksplit(const BoxGeom& g, int n_ib);
 void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,
                             const double* tval_u, const int* tptr_v, const int* tcol_v,
                             const double* tval_v, int nb, double* aug, hipStream_t s);
