@@ -594,6 +594,135 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
   }
 }
 
+// Register-blocked form of the interior product: a work-group owns a
+// 64-row chunk and 64 boxes, its four waves 2 x 2 blocks of 32 rows x 32
+// boxes (four 16 x 16 MFMA tiles each).  Each 32-wide reduction step stages
+// the chunk's A block (32 x 64, contiguous rows) and the boxes' gathered
+// residuals (32 x 64) in LDS, the next step's values loading into registers
+// during the MFMAs.  The reduction runs over the same 64-column chunks and
+// slices, in the same order, as the narrow tiles, so the sums agree.
+template <typename T>
+struct GemmSmem {
+  T As[32][64];        // [reduction index][row of the chunk]
+  T Bs[32][65];        // [reduction index][box]
+  size_t base[64];
+  int bid[64], bx0[64], by0[64];
+};
+
+template <typename T>
+__device__ __forceinline__ void ras_int_gemm(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
+                                             size_t sys_n, int nbox, const T* __restrict__ M,
+                                             const int* __restrict__ ents, int nlist, int tile, int chunk,
+                                             int kslice, int ksplit, const int* __restrict__ loc_tab,
+                                             const int* __restrict__ active, T* __restrict__ part,
+                                             GemmSmem<T>& sm, bool acc_mode) {
+  constexpr int TBX = 64, KC = 32, GP = KC * TBX / 256;
+  using acc_t = typename Mfma<T>::acc_t;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wb = wave >> 1;
+  const int bt = tile * TBX;
+  const int N = g.N;
+  const size_t nn = (size_t)N * N;
+  if (tid < TBX) {
+    const int b = bt + tid;
+    int pid = -1, sy = 0;
+    if (b < nlist) {
+      const int e = ents[b];
+      sy = e / nbox;
+      pid = e - sy * nbox;
+      if (active && !active[sy]) pid = -1;
+    }
+    sm.bid[tid] = pid;
+    sm.base[tid] = (size_t)sy * sys_n;
+    sm.bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
+    sm.by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
+  }
+  __syncthreads();
+  const int nchunk = (g.nloc + 63) / 64;
+  const int per = (nchunk + ksplit - 1) / ksplit;
+  const int c0 = kslice * per, c1 = c0 + per < nchunk ? c0 + per : nchunk;
+  const int kb = c0 * 64, ke = c1 * 64;     // reduction indices beyond nloc read as zero
+  const T* Mc = M + (size_t)chunk * g.nloc * 64;
+  const int kq = lane >> 4, ln = lane & 15;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  T ga[GP], gb[GP];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < GP; ++u) {
+      const int t = tid + u * 256;
+      const int ka = t / 64, row = t % 64;   // A: 64 consecutive rows per index
+      const int ja = k0 + ka;
+      ga[u] = ja < g.nloc ? Mc[(size_t)ja * 64 + row] : (T)0;
+      const int kx = t % KC, b = t / KC;     // X: consecutive indices of one box
+      const int jx = k0 + kx;
+      T val = 0;
+      if (jx < g.nloc && sm.bid[b] >= 0) {
+        const int code = loc_tab[jx];
+        int ii = (code & 0xfff) + sm.bx0[b], jj = ((code >> 12) & 0xfff) + sm.by0[b];
+        ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
+        jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
+        val = r[sm.base[b] + (size_t)(code >> 24) * nn + (size_t)jj * N + ii];
+      }
+      gb[u] = val;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < GP; ++u) {
+      const int t = tid + u * 256;
+      sm.As[t / 64][t % 64] = ga[u];
+      sm.Bs[t % KC][t / KC] = gb[u];
+    }
+    __syncthreads();
+    if (k0 + KC < ke) load(k0 + KC);   // in flight during the MFMAs below
+#pragma unroll
+    for (int st = 0; st < KC / 4; ++st) {
+      const int kk = 4 * st + kq;
+      const T a0 = sm.As[kk][32 * wr + ln], a1 = sm.As[kk][32 * wr + 16 + ln];
+      const T b0 = sm.Bs[kk][32 * wb + ln], b1 = sm.Bs[kk][32 * wb + 16 + ln];
+      acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  const int nown_pad = g.nch * 64;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = chunk * 64 + 32 * wr + 16 * a + Mfma<T>::row(kq, v);
+        const int bb = 32 * wb + 16 * b + ln;
+        if (row >= g.nown) continue;
+        if (ksplit == 1) {
+          if (sm.bid[bb] >= 0) {
+            const size_t o = sm.base[bb] + own_glob(g, sm.bid[bb], row);
+            z[o] = acc_mode ? z[o] + acc[a][b][v] : acc[a][b][v];
+          }
+        } else if (bt + bb < nlist) {
+          part[((size_t)kslice * nlist + bt + bb) * nown_pad + row] = acc[a][b][v];
+        }
+      }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ras_interior_g(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
+                                                        const T* __restrict__ M, const int* __restrict__ boxes,
+                                                        int nlist, const int* __restrict__ loc_tab,
+                                                        T* __restrict__ part, int ksplit, bool acc) {
+  __shared__ GemmSmem<T> sm;
+  ras_int_gemm<T>(r, z, g, 0, g.npd * g.npd, M, boxes, nlist, blockIdx.x, blockIdx.y, blockIdx.z, ksplit, loc_tab,
+                  nullptr, part, sm, acc);
+}
+
 template <typename T, int TB>
 __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T* __restrict__ z,
                                                       BoxGeom g, const T* __restrict__ M,
@@ -650,7 +779,10 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   }
   if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
-    if (tb == 16)
+    if (tb == 64)
+      hipLaunchKernelGGL((k_ras_interior_g<T>), dim3((n_int + 63) / 64, g.nch, ks), dim3(256), 0, s, r, z, g,
+                         shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
+    else if (tb == 16)
       hipLaunchKernelGGL((k_ras_interior<T, 16>), dim3((n_int + 15) / 16, g.nch, ks), dim3(256), 0, s, r, z, g,
                          shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
     else
@@ -694,8 +826,12 @@ __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* _
     const bool is_ib = (it + 1) * ib_items / total > before;
     if (!is_ib) {
       const int ti = (int)(it - before);
-      ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab, active,
-                          nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw), false);
+      if constexpr (TB == 64)
+        ras_int_gemm<T>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab, active,
+                        nullptr, *reinterpret_cast<GemmSmem<T>*>(smem_raw), false);
+      else
+        ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab,
+                            active, nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw), false);
     } else {
       const int q = (int)before, e = q / g.nch, c = q % g.nch;
       const int ent = ib_ents[e], sy = ent / nbox;
@@ -724,7 +860,7 @@ void launch_ras_batch(const T* r, T* z, BoxGeom g, size_t sys_n, int nbox, const
   if (grid > items) grid = items;
   size_t lds = ((((size_t)g.nloc + 3) & ~(size_t)3) + 256) * sizeof(T);
   const size_t tile = tb == 16 ? sizeof(IntTileSmem<T, 16>)
-                                : (tb == 64 ? sizeof(IntTileSmem<T, 64>) : sizeof(IntTileSmem<T, 32>));
+                                : (tb == 64 ? sizeof(GemmSmem<T>) : sizeof(IntTileSmem<T, 32>));
   if (tile > lds) lds = tile;
   if (tb == 16)
     hipLaunchKernelGGL((k_ras_batch<T, 16>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,

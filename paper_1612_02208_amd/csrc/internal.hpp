@@ -233,7 +233,8 @@ void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipS
 // parts: bit 0 = IB boxes (k_ras_ib), bit 1 = interior boxes
 // (k_ras_interior and its slice sum); the smoother launches both.
 // acc: add the local solutions to z on the owned sets instead of storing them;
-// tb: interior tile width (16 or 32 boxes; results do not depend on it)
+// tb: interior product form (16 or 32 boxes per tile, 64: register-blocked
+// 64 x 64 tiles; results do not depend on it)
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
@@ -310,7 +311,7 @@ void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int 
 // shared interior inverse, then (IB box, row chunk) items against each box's
 // own inverse.  Box entries are s * nbox + box id; systems are sys_n apart.
 struct RasBatchPlan {
-  int tb = 32;      // interior tile width (16, 32 or 64 boxes)
+  int tb = 32;      // interior tile width (16, 32, or 64: register-blocked)
   int grid = 0;     // work-groups of the persistent launch
 };
 template <typename T>

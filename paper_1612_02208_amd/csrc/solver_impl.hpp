@@ -359,9 +359,10 @@ class Solver final : public SolverBase {
     return std::max(kPartStride, (size_t)apply_blocks(lev.N) * (kMaxNu + 1));
   }
 
-  // Interior tile width per Schwarz level: time the interior product with
-  // 16- and 32-box tiles (HIP events, on the level's work vectors) and keep
-  // the faster.  Both compute the same sums in the same order.
+  // Interior product form per Schwarz level: time the 16- and 32-box tiles
+  // and the register-blocked 64-box form (HIP events, on the level's work
+  // vectors) and keep the fastest.  All compute the same sums in the same
+  // order.
   void tune_interior(hipStream_t s) {
     if (d_.smoother != IBMG_RAS && d_.smoother != IBMG_RMS) return;
     for (int l = 1; l <= L_; ++l) {
@@ -370,7 +371,7 @@ class Solver final : public SolverBase {
       if (n_int == 0) continue;
       launch_fill<T>(lev.r.p, T(1), 3 * (size_t)lev.N * lev.N, s);
       double best = 1e300;
-      for (int tb : {32, 16}) {
+      for (int tb : {32, 16, 64}) {
         const double ms = time_launches([&] {
           ras_launch(lev, lev.r.p, lev.t.p, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, n_int, s, 2, false, tb);
         }, 5, s);
