@@ -178,6 +178,26 @@ ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* 
  * level's IB operator and smoother data.  Synchronises ``stream``. */
 ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream stream);
 
+/* The right-hand side of one semi-implicit time step (Sec. 2.2, Eq.
+ * matrix-impib, without convection): rhs = [(rho/dt) u + S_h K_h X; 0] on the
+ * finest grid, X the handle's current positions, K_h X the nodal forces of
+ * the linear springs with minimum-image separations on the periodic square.
+ * w: [u | v | p] (the p part is not read); rhs: 3 N^2, distinct from w. */
+ibmg_status ibmg_step_rhs(ibmg_handle* h, const double* w, double* rhs, ibmg_stream stream);
+
+/* One semi-implicit time step (Sec. 2.2, Eqs. imp-momentum to imp-F without
+ * convection): forms the right-hand side above from w = (u^n, .), solves
+ * L_IB(X^n) w^{n+1} = rhs as ibmg_fgmres_solve does (opts, info; transpose
+ * must be 0), moves the structure to X^{n+1} = X^n + dt J_h u^{n+1} (wrapped
+ * into [0, 1)) and rebuilds every level at X^{n+1}, so the handle is ready
+ * for the next step.  w is overwritten with (u, p)^{n+1}.  Synchronises
+ * ``stream``.  IBMG_ERR_NONFINITE if the positions become invalid. */
+ibmg_status ibmg_time_step(ibmg_handle* h, double* w, const ibmg_solve_opts* opts, ibmg_solve_info* info,
+                           ibmg_stream stream);
+
+/* The handle's current structure positions, copied to the host array X [M][2]. */
+ibmg_status ibmg_positions(const ibmg_handle* h, double* X);
+
 /* Setup statistics.  Writes up to cap int64 values: [levels, then per
  * level: n, boxes, boxes with their own inverse (+1 for the shared interior
  * one), IB-touched boxes, entries of the explicit IB rows, box colours of the

@@ -47,7 +47,9 @@ def advance_positions(wl, w):
     N = wl.N
     n = N * N
     U = np.stack([ib.interp_matrix(wl.X, N, c) @ w[c * n:(c + 1) * n] for c in (0, 1)], 1)
-    return np.mod(wl.X + wl.dt * U, 1.0)
+    Xn = np.mod(wl.X + wl.dt * U, 1.0)
+    Xn[Xn >= 1.0] = 0.0     # a tiny negative coordinate rounds up to 1.0 in mod
+    return Xn
 
 
 def time_step(wl, w, rtol=1e-12, max_it=200):

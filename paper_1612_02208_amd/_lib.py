@@ -50,7 +50,7 @@ EXPORTS = [
     "ibmg_prolong_add", "ibmg_smoother_apply", "ibmg_smooth", "ibmg_coarse_solve", "ibmg_vcycle",
     "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats", "ibmg_sc_info",
     "ibmg_batch_create", "ibmg_batch_size", "ibmg_batch_vcycle", "ibmg_batch_fgmres_solve",
-    "ibmg_batch_stats", "ibmg_kernel_time",
+    "ibmg_batch_stats", "ibmg_kernel_time", "ibmg_step_rhs", "ibmg_time_step", "ibmg_positions",
 ]
 
 KERNEL_RAS_IB, KERNEL_RAS_INTERIOR, KERNEL_STENCIL, KERNEL_RAS_BATCH = 0, 1, 2, 3
@@ -91,6 +91,9 @@ def load():
     lib.ibmg_batch_fgmres_solve.argtypes = [vp, vpp, vpp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     lib.ibmg_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
     lib.ibmg_kernel_time.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, _dp, _dp, _dp]
+    lib.ibmg_step_rhs.argtypes = [vp, vp, vp, vp]
+    lib.ibmg_time_step.argtypes = [vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.ibmg_positions.argtypes = [vp, _dp]
     for name in EXPORTS:
         if name != "ibmg_last_error":
             getattr(lib, name).restype = ctypes.c_int

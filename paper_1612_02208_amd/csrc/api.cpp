@@ -294,6 +294,32 @@ ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream st) 
   });
 }
 
+ibmg_status ibmg_step_rhs(ibmg_handle* h, const double* w, double* rhs, ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(w && rhs && w != rhs, "w and rhs must be distinct device pointers");
+    s->step_rhs(w, rhs, S(st));
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_time_step(ibmg_handle* h, double* w, const ibmg_solve_opts* opts, ibmg_solve_info* info,
+                           ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(w != nullptr, "w is NULL");
+    ibmg_solve_opts o{1e-8, 30, 100, 0, 0};
+    if (opts) o = *opts;
+    ibmg::require(o.transpose == 0, "the time step solves with L_IB");
+    return s->time_step(w, o, info, S(st));
+  });
+}
+
+ibmg_status ibmg_positions(const ibmg_handle* h, double* X) {
+  if (!h || !h->s) return IBMG_ERR_STATE;
+  if (!X) return IBMG_ERR_ARG;
+  h->s->positions(X);
+  return IBMG_OK;
+}
+
 ibmg_status ibmg_stats(const ibmg_handle* h, int64_t* out, int32_t cap, int32_t* written) {
   if (!h || !h->s) return IBMG_ERR_STATE;
   if (!written || (cap > 0 && !out)) return IBMG_ERR_ARG;

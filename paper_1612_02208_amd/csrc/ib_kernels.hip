@@ -174,6 +174,62 @@ void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M
   launch_interp_lanes<T>(u, v, fx, fy, M, N, U, 1, s);
 }
 
+// Nodal spring forces F = K_h X on the periodic square (Sec. 5 linear
+// fibres): F_l = sum over springs e at l of kappa_e (X_q - X_l), each
+// separation the minimum-image displacement; X and F interleaved [M][2].
+__global__ void k_fibre_force(const double* __restrict__ X, SpringView<double> sv, double* __restrict__ F) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= sv.M) return;
+  const double x0 = X[2 * l], y0 = X[2 * l + 1];
+  double f0 = 0, f1 = 0;
+  for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
+    const int q = sv.adj_nbr[e];
+    double dx = X[2 * q] - x0, dy = X[2 * q + 1] - y0;
+    dx -= rint(dx);
+    dy -= rint(dy);
+    f0 += sv.adj_k[e] * dx;
+    f1 += sv.adj_k[e] * dy;
+  }
+  F[2 * l] = f0;
+  F[2 * l + 1] = f1;
+}
+
+void launch_fibre_force(const double* X, SpringView<double> sv, double* F, hipStream_t s) {
+  if (!sv.M) return;
+  hipLaunchKernelGGL(k_fibre_force, dim3(cdiv(sv.M, 256)), dim3(256), 0, s, X, sv, F);
+  IBMG_LAUNCH_CHECK();
+}
+
+// rhs = [(rho/dt) u + f_u; (rho/dt) v + f_v; 0]  (f = S_h F on the faces)
+__global__ void k_step_rhs(const double* __restrict__ w, const double* __restrict__ f, double a, size_t nn,
+                           double* __restrict__ rhs) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 3 * nn; i += (size_t)gridDim.x * blockDim.x)
+    rhs[i] = i < 2 * nn ? a * w[i] + f[i] : 0.0;
+}
+
+void launch_step_rhs(const double* w, const double* f, double a, int N, double* rhs, hipStream_t s) {
+  const size_t nn = (size_t)N * N;
+  int g = cdiv(3 * nn, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_step_rhs, dim3(g), dim3(256), 0, s, w, f, a, nn, rhs);
+  IBMG_LAUNCH_CHECK();
+}
+
+// X <- X + dt U (U interleaved [M][2]), wrapped into [0, 1)
+__global__ void k_advance(double* __restrict__ X, const double* __restrict__ U, double dt, int M) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * M) return;
+  double x = X[t] + dt * U[t];
+  x -= floor(x);
+  X[t] = x < 1.0 ? x : 0.0;
+}
+
+void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s) {
+  if (!M) return;
+  hipLaunchKernelGGL(k_advance, dim3(cdiv(2 * (size_t)M, 256)), dim3(256), 0, s, X, U, dt, M);
+  IBMG_LAUNCH_CHECK();
+}
+
 // f_face = scale * sum_(l, slot) w F_l, F interleaved [M][2]; f = [2][N][N].
 __global__ void k_spread(const double* __restrict__ F, FootView<double> fx, FootView<double> fy,
                          int N, double scale, double* __restrict__ f) {

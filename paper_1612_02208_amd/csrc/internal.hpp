@@ -218,6 +218,11 @@ void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, in
 void launch_t_values(FootView<double> f, const int* mask, SpringView<double> sv, int N,
                      double ibs, const int* t_ptr, const int* t_col, double* t_val,
                      hipStream_t s);
+// semi-implicit time step pieces (Sec. 2.2): spring forces on the periodic
+// square, the step's right-hand side, the position update
+void launch_fibre_force(const double* X, SpringView<double> sv, double* F, hipStream_t s);
+void launch_step_rhs(const double* w, const double* f, double a, int N, double* rhs, hipStream_t s);
+void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s);
 void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* unused,
                         int n_springs, int M, double scale, double* out, hipStream_t s);
 

@@ -42,6 +42,10 @@ struct SolverBase {
   // algorithmic bytes and flops per launch
   virtual double kernel_time(int kernel, int level, int reps, hipStream_t s, double* bytes,
                              double* flops) = 0;
+  // semi-implicit time step (Sec. 2.2)
+  virtual void step_rhs(const double* w, double* rhs, hipStream_t s) = 0;
+  virtual int time_step(double* w, const ibmg_solve_opts& o, ibmg_solve_info* info, hipStream_t s) = 0;
+  virtual void positions(double* X) const = 0;
 };
 
 // Many independent systems solved together (batched form): one launch per

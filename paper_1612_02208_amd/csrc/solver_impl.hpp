@@ -701,7 +701,7 @@ class Solver final : public SolverBase {
     Fd_.alloc(4 * (size_t)std::max(M_, 1));   // forces [2][M] then J u [2][M]
     Uw_.alloc(2 * (size_t)std::max(M_, 1));
     Ul_.alloc(2 * (size_t)std::max(M_, 1));
-    IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
+    if (!pinned_) IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
   }
 
   // --------------------------------------------------------------- views
@@ -1142,6 +1142,54 @@ class Solver final : public SolverBase {
     IBMG_HIP(hipStreamSynchronize(s));
   }
 
+  // ------------------------------------------- semi-implicit time step
+  // rhs = [(rho/dt) u + S_h K_h X; 0] on the finest grid (Eq. matrix-impib)
+  void step_rhs(const double* w, double* rhs, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    const double h = 1.0 / lev.N;
+    const size_t m2 = 2 * (size_t)std::max(M_, 1);
+    if (Fs_.n < m2) Fs_.alloc(m2);
+    if (fs_.n < 2 * (size_t)lev.N * lev.N) fs_.alloc(2 * (size_t)lev.N * lev.N);
+    launch_fill<double>(Fs_.p, 0.0, m2, s);
+    launch_fibre_force(d_X_.p, sview<double>(), Fs_.p, s);
+    launch_spread(Fs_.p, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, 1.0 / (h * h), fs_.p, s);
+    launch_step_rhs(w, fs_.p, d_.rho / d_.dt, lev.N, rhs, s);
+  }
+
+  // Solve L_IB(X^n) w^{n+1} = rhs, advance X^{n+1} = X^n + dt J_h u^{n+1}
+  // (Eq. imp-X-new, wrapped into [0, 1)) and rebuild every level at X^{n+1}.
+  int time_step(double* w, const ibmg_solve_opts& o, ibmg_solve_info* info, hipStream_t s) override {
+    Level<T>& lev = levels_[L_];
+    const size_t n = 3 * (size_t)lev.N * lev.N, nn = (size_t)lev.N * lev.N;
+    if (rhs_.n < n) rhs_.alloc(n);
+    step_rhs(w, rhs_.p, s);
+    const int st = fgmres(rhs_.p, w, o, info, s);
+    launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw_.p, s);
+    launch_advance(d_X_.p, Uw_.p, d_.dt, M_, s);
+    if (M_ > 0)
+      IBMG_HIP(hipMemcpyAsync(X_.data(), d_X_.p, 2 * (size_t)M_ * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBMG_HIP(hipStreamSynchronize(s));
+    for (double x : X_)
+      if (!std::isfinite(x) || x < 0.0 || x >= 1.0) throw Error(IBMG_ERR_NONFINITE, "updated positions are invalid");
+    rebuild(s);
+    return st;
+  }
+
+  // every level rebuilt for the current positions X_ (host copy)
+  void rebuild(hipStream_t s) {
+    drop_graph();
+    levels_.clear();
+    build_structure(s);
+    build_numeric(s);
+    alloc_work(s);
+    tune_interior(s);
+    IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  void positions(double* X) const override {
+    std::copy(X_.begin(), X_.end(), X);
+  }
+
   void sc_info(int level, double* lam, int32_t* colours) const override {
     require(level >= 1 && level <= L_, "level out of range");
     const Level<T>& lev = levels_[level];
@@ -1229,6 +1277,7 @@ class Solver final : public SolverBase {
   std::vector<Level<T>> levels_;
   DBuf<double> inv0_;
   DBuf<double> Fd_, Uw_, Ul_;
+  DBuf<double> Fs_, fs_, rhs_;   // time step: nodal forces, spread forces, right-hand side
   // outer FGMRES
   int outer_cap_ = 0;
   DBuf<double> Vo_, Zo_, Ho_, cs_, sn_, g_, y_, osc_, opart_, bp_, rr_;

@@ -206,6 +206,34 @@ class StokesIB:
                        rel_res_true=info.rel_res_true, rhs_null_norm=info.rhs_null_norm,
                        solve_ms=info.solve_ms, vcycles=info.vcycles, history=list(hist[:k]))
 
+    # ---- semi-implicit time step (Sec. 2.2) --------------------------------
+    def step_rhs(self, w):
+        """[(rho/dt) u + S_h K_h X; 0] for w = [u | v | p] at the current positions."""
+        _dev_vec(w, self.n(), "w")
+        rhs = self._new(self.n())
+        self._check(self.lib.ibmg_step_rhs(self.h, _ptr(w), _ptr(rhs), _stream()))
+        return rhs
+
+    def time_step(self, w, rtol=1e-8, restart=30, max_it=100, history=128):
+        """Advance one step: returns (u, p)^{n+1} (a new tensor) and the solve
+        info; the handle's structure moves to X^{n+1} and is rebuilt there."""
+        _dev_vec(w, self.n(), "w")
+        x = w.clone()
+        o = _lib.SolveOpts(float(rtol), int(restart), int(max_it), 0, 0)
+        hist = (ctypes.c_double * history)()
+        info = _lib.SolveInfo()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = history
+        st = self._check(self.lib.ibmg_time_step(self.h, _ptr(x), ctypes.byref(o), ctypes.byref(info), _stream()),
+                         ok=(0, 1))
+        return x, dict(status=_STATUS[st], converged=st == 0, iters=info.iters, rel_res_true=info.rel_res_true,
+                       rhs_null_norm=info.rhs_null_norm, solve_ms=info.solve_ms)
+
+    def positions(self):
+        X = np.empty((self.M, 2), dtype=np.float64)
+        self._check(self.lib.ibmg_positions(self.h, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return X
+
     def spring_gradient(self, w, lam):
         _dev_vec(w, self.n(), "w")
         _dev_vec(lam, self.n(), "lam")

@@ -1,0 +1,94 @@
+"""GPU tests of the semi-implicit time step (Sec. 2.2 without convection):
+the step's right-hand side, one and two steps (the second on the hierarchy
+rebuilt at the moved structure) against the oracle's steps, and Laplace's
+law for a circular membrane at a size the oracle is not run on."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.timestep import step_rhs, time_step
+
+pytestmark = pytest.mark.gpu
+
+OPS_TOL = 1e-12
+SOLVE_TOL = 1e-10
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _cases():
+    X, S = W.annulus(4, 150, 0.2, 0.25)
+    ann = W.Workload("annulus_64_re", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4))
+    th = 2 * np.pi * np.arange(128) / 128
+    Xe = np.stack([0.5 + 0.3 * np.cos(th), 0.5 + 0.2 * np.sin(th)], 1)
+    Se = np.stack([np.arange(128), (np.arange(128) + 1) % 128], 1).astype(np.int32)
+    ell = W.Workload("ellipse_32", 32, 8, 0.0, 1.0, 2e-3, Xe, Se, np.full(128, 1e2))
+    ell_rms = copy.deepcopy(ell)
+    ell_rms.name, ell_rms.smoother = "ellipse_32_rms", "rms"
+    ell_sc = copy.deepcopy(ell)
+    ell_sc.name, ell_sc.smoother = "ellipse_32_sc", "sc"
+    return [ann, ell, ell_rms, ell_sc]
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("wl", CASES, ids=[c.name for c in CASES])
+def test_step_rhs(wl):
+    from paper_1612_02208_amd import StokesIB
+    print(f"[case] step_rhs {wl.name}", flush=True)
+    G = StokesIB(wl)
+    w = np.random.default_rng(3).uniform(-1, 1, 3 * wl.N * wl.N)
+    assert rel(host(G.step_rhs(dev(w))), step_rhs(wl, w)) < OPS_TOL
+    G.close()
+
+
+@pytest.mark.parametrize("wl", CASES, ids=[c.name for c in CASES])
+def test_two_steps_match_oracle(wl):
+    from paper_1612_02208_amd import StokesIB
+    print(f"[case] two steps {wl.name}", flush=True)
+    G = StokesIB(copy.deepcopy(wl))
+    ow = copy.deepcopy(wl)
+    w = 0.1 * np.random.default_rng(4).uniform(-1, 1, 3 * wl.N * wl.N)
+    wg = dev(w)
+    for k in range(2):
+        wg, info = G.time_step(wg, rtol=1e-12, max_it=200)
+        assert info["converged"], (k, info)
+        w, Xn, _ = time_step(ow, w, rtol=1e-12)
+        ow.X = Xn
+        assert rel(host(wg), w) < SOLVE_TOL, (k, rel(host(wg), w))
+        assert np.abs(G.positions() - Xn).max() < 1e-12, k
+    G.close()
+
+
+def test_laplace_law_on_the_gpu():
+    """Pressure jump across a circular membrane of zero-rest-length springs
+    (Stokes flow) against the discrete force density 2 kappa M sin^2(pi/M)/pi,
+    at N = 128 (the oracle's refinement study gives 1.7e-5 there)."""
+    from paper_1612_02208_amd import StokesIB
+    N, M, kap = 128, 512, 1e2
+    X, S = W.membrane(M, 0.25)
+    wl = W.Workload("laplace_128", N, 8, 0.0, 1.0, 1e-3, X, S, np.full(len(S), kap))
+    G = StokesIB(wl)
+    w, info = G.time_step(dev(np.zeros(3 * N * N)), rtol=1e-10)
+    p = host(w)[2 * N * N:].reshape(N, N)
+    c = N // 2
+    dp = p[c - 1:c + 1, c - 1:c + 1].mean() - p[0:2, 0:2].mean()
+    exact = 2 * kap * M * np.sin(np.pi / M) ** 2 / np.pi
+    assert abs(dp / exact - 1) < 1e-4
+    assert np.abs(host(w)[:2 * N * N]).max() < 1e-3
+    G.close()
