@@ -18,7 +18,7 @@ events on the stream it runs on; the other hot kernels; the batched form on
 oracle on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-baseline sample|off]
-                    [--batch on|off]
+                    [--batch on|off] [--rms on|off] [--step on|off]
 """
 import argparse
 import hashlib
@@ -56,6 +56,7 @@ def parse():
     p.add_argument("--overlap", type=int, default=4)
     p.add_argument("--batch", default="on", choices=["on", "off"])
     p.add_argument("--rms", default="on", choices=["on", "off"])
+    p.add_argument("--step", default="on", choices=["on", "off"])
     return p.parse_args()
 
 
@@ -98,6 +99,28 @@ def smoother_bench(wl, b, smoother, box, overlap, reps=3):
             "solve_ms": float(np.median(ms)), "vcycles_per_s": info["vcycles"] / (float(np.median(ms)) / 1e3),
             "rel_res_true": info["rel_res_true"], "setup_s": setup,
             "box_colours": [lv["box_colours"] for lv in st[1:]]}
+
+
+def step_bench(wl, b):
+    """One semi-implicit time step of the same workload (FP64): right-hand
+    side, solve to 1e-8, position update and the rebuild of every level at
+    the moved structure (box inverses included)."""
+    import copy
+    import torch
+    from paper_1612_02208_amd import StokesIB
+    g = StokesIB(copy.copy(wl), precision="fp64")
+    w = torch.zeros_like(b)
+    g.time_step(w, rtol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w2, info = g.time_step(w, rtol=1e-8)
+    torch.cuda.synchronize()
+    total = 1e3 * (time.perf_counter() - t0)
+    X = g.positions()
+    g.close()
+    return {"step_ms": total, "solve_ms": info["solve_ms"], "rebuild_ms": total - info["solve_ms"],
+            "iters": info["iters"], "rel_res_true": info["rel_res_true"],
+            "max_displacement": float(np.abs(X - wl.X).max())}
 
 
 def batch_bench(dev, reps=3):
@@ -305,6 +328,10 @@ def main():
         out["smoothers_fp64"] = [smoother_bench(wl, b, "rms", a.box, a.overlap),
                                  smoother_bench(wl, b, "ras", 8, 2), smoother_bench(wl, b, "rms", 8, 2)]
         print(f"[bench] smoother comparison {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    if a.step == "on":
+        t0 = time.perf_counter()
+        out["time_step_fp64"] = step_bench(wl, b)
+        print(f"[bench] time step {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if a.batch == "on":
         t0 = time.perf_counter()
         out["batch"] = batch_bench(dev)
