@@ -173,3 +173,102 @@ def diff_256(field_seed: int = 1, N: int = 256, M: int = 1024) -> Workload:
 def fd_springs(n_springs: int, count: int = 16, seed: int = 3) -> np.ndarray:
     g = np.random.default_rng(seed)
     return np.sort(g.choice(n_springs, size=count, replace=False))
+
+
+# --------------------------------------------------------------------------
+# The paper's test structures (Sec. 5.1 thick elastic shell, Sec. 5.2 thin
+# elastic membrane) at their stated resolutions, on the periodic unit square
+# --------------------------------------------------------------------------
+
+#: the stiffness scale of Sec. 5.1: alpha = gamma * 3.93 / 0.005 (the largest
+#: stiffness an explicit scheme takes for the shell at h = 1/64, dt = 0.005)
+ALPHA_EXPLICIT = 3.93 / 0.005
+#: thickness and inner radius of the shell, radius of the membrane (Sec. 5.1,
+#: Eq. annulus; Sec. 5.2, Eq. circle); both centred at (0.5, 0.5)
+SHELL_WIDTH = 1.0 / 16.0
+SHELL_RADIUS = 0.25
+MEMBRANE_RADIUS = 0.25
+
+
+def paper_counts(N: int):
+    """(M1, M2) = (19 N / 8, 3 N / 32 + 1) Lagrangian points along and across
+    the fibres (Sec. 5.1); both exact for N a multiple of 32."""
+    if N % 32:
+        raise ValueError("the paper's point counts need N to be a multiple of 32")
+    return 19 * N // 8, 3 * N // 32 + 1
+
+
+def thick_shell(N: int, gamma: float, centre=(0.5, 0.5)):
+    """Thick annulus X(s1, s2) = c + (r + s2)(cos s1, sin s1), s1 in [0, 2 pi),
+    s2 in [0, w] (Sec. 5.1), M1 x M2 nodes; fibres run along s1 only (force
+    density alpha d^2 X / ds1^2, Eq. F-lin-functional).  The half-index
+    differences of App. A.2 with the nodal quadrature weight ds1 ds2 of the
+    spreading sum make the nodal force of node l on fibre m
+        alpha ds2 / ds1 (X_{l+1,m} - 2 X_{l,m} + X_{l-1,m}),
+    i.e. zero-rest-length springs of stiffness kappa = alpha ds2 / ds1 between
+    fibre neighbours.  Returns (X [M1 M2, 2], springs, kappa, (ds1, ds2))."""
+    M1, M2 = paper_counts(N)
+    ds1 = 2.0 * np.pi / M1
+    ds2 = SHELL_WIDTH / (M2 - 1)
+    alpha = gamma * ALPHA_EXPLICIT
+    Xs, S = [], []
+    for m in range(M2):
+        Xs.append(ring(M1, SHELL_RADIUS + m * ds2, centre))
+        S.append(ring_springs(M1, m * M1))
+    S = np.concatenate(S, 0)
+    return np.concatenate(Xs, 0), S, np.full(len(S), alpha * ds2 / ds1), (ds1, ds2)
+
+
+def thin_membrane(N: int, gamma: float, centre=(0.5, 0.5)):
+    """Thin circle X(s1) = c + r (cos s1, sin s1) (Sec. 5.2) with M1 = 19 N / 8
+    nodes and alpha = 7 gamma 3.93 / 0.005; the nodal weight ds1 makes the
+    spring stiffness kappa = alpha / ds1.  Returns (X, springs, kappa, ds1)."""
+    M1, _ = paper_counts(N)
+    ds1 = 2.0 * np.pi / M1
+    alpha = 7.0 * gamma * ALPHA_EXPLICIT
+    X, S = membrane(M1, MEMBRANE_RADIUS, centre)
+    return X, S, np.full(len(S), alpha / ds1), ds1
+
+
+def background_flow(N: int) -> np.ndarray:
+    """A velocity u^n of unit speed for the first step: the periodic cell flow
+    of the stream function psi = sin(2 pi x) sin(2 pi y) / (2 pi), sampled at
+    the grid nodes (i h, j h) and differenced onto the faces,
+        u[j, i] = (psi[j+1, i] - psi[j, i]) / h   at (i h, (j + 1/2) h)
+        v[j, i] = -(psi[j, i+1] - psi[j, i]) / h  at ((i + 1/2) h, j h),
+    so its MAC divergence vanishes to rounding.  Returns [u | v | 0] (3 N^2);
+    it stands in for the unit lid speed that sets the flow scale of the
+    paper's cavity tests."""
+    h = 1.0 / N
+    t = np.arange(N + 1) * h
+    psi = np.outer(np.sin(2 * np.pi * t), np.sin(2 * np.pi * t)) / (2 * np.pi)   # psi[j, i]
+    u = (psi[1:, :-1] - psi[:-1, :-1]) / h
+    v = -(psi[:-1, 1:] - psi[:-1, :-1]) / h
+    return np.concatenate([u.ravel(), v.ravel(), np.zeros(N * N)])
+
+
+#: flow conditions of the results section: Stokes (rho = 0, mu = 1) and
+#: time-dependent flow with rho = 1, mu = 1 / Re
+FLOWS = {"stokes": (0.0, 1.0), "mu1": (1.0, 1.0), "mu0.1": (1.0, 0.1),
+         "mu0.01": (1.0, 0.01), "mu0.001": (1.0, 0.001)}
+
+
+def paper_case(structure: str, N: int, gamma: float, flow: str = "stokes",
+               smoother: str = "ras", box: int = 8, overlap: int = 2, **kw) -> Workload:
+    """One linear system of the results section: the thick shell ("thick") or
+    thin membrane ("thin") at N, stiffness ratio gamma, a flow of ``FLOWS``,
+    dt = 0.32 h, an 8 x 8 coarsest grid (Sec. 5)."""
+    rho, mu = FLOWS[flow]
+    if structure == "thick":
+        X, S, kap, _ = thick_shell(N, gamma)
+    elif structure == "thin":
+        X, S, kap, _ = thin_membrane(N, gamma)
+    else:
+        raise ValueError(f"unknown structure {structure!r}")
+    tag = f"{structure}_N{N}_g{gamma:g}_{flow}_{smoother}"
+    if smoother != "sc":
+        tag += f"_b{box}o{overlap}"
+    w = Workload(tag, N, 8, rho, mu, 0.32 / N, X, S, kap, smoother=smoother, box=box, overlap=overlap)
+    for k, v in kw.items():
+        setattr(w, k, v)
+    return w
