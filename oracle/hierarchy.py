@@ -49,19 +49,38 @@ def level_sizes(N, coarse_N):
     return sizes[::-1]
 
 
+def spring_model(wl):
+    m = getattr(wl, "spring_model", "linear")
+    if m not in ("linear", "tangent"):
+        raise ValueError(f"unknown spring model {m!r}")
+    if m == "linear" and getattr(wl, "rest", None) is not None and np.any(np.asarray(wl.rest) != 0):
+        raise ValueError("rest lengths need the tangent spring model")
+    return m
+
+
+def rest_lengths(wl):
+    r = getattr(wl, "rest", None)
+    return np.zeros(len(wl.springs)) if r is None else np.asarray(r, dtype=np.float64)
+
+
 def build(wl, T_fine=None):
     """Build all levels for a workload (see ``workloads.Workload``)."""
     sizes = level_sizes(wl.N, wl.coarse_N)
     X, S, kap = wl.X, wl.springs, wl.kappa
-    # Finest-level IB term -dt S K J and its structural pattern J^T K J.
-    T = ib.ib_term(X, S, kap, wl.N, wl.dt) if T_fine is None else T_fine
-    KP = ib.stiffness_pattern(X.shape[0], S)
-    pats = []
-    for comp in (0, 1):
-        JP = ib.interp_pattern(X, wl.N, comp)
-        pats.append(JP.T @ (KP @ JP))
-    TP = sp.block_diag(pats, format="csr")
-    TP.data[:] = 1.0
+    # Finest-level IB term -dt S K J and its structural pattern J^T K J; the
+    # tangent model couples the two velocity components (Sec. 6).
+    if spring_model(wl) == "tangent":
+        T = ib.ib_term_tangent(X, S, kap, rest_lengths(wl), wl.N, wl.dt) if T_fine is None else T_fine
+        TP = ib.tangent_pattern(X, S, wl.N)
+    else:
+        T = ib.ib_term(X, S, kap, wl.N, wl.dt) if T_fine is None else T_fine
+        KP = ib.stiffness_pattern(X.shape[0], S)
+        pats = []
+        for comp in (0, 1):
+            JP = ib.interp_pattern(X, wl.N, comp)
+            pats.append(JP.T @ (KP @ JP))
+        TP = sp.block_diag(pats, format="csr")
+        TP.data[:] = 1.0
     levels = [None] * len(sizes)
     for l in range(len(sizes) - 1, -1, -1):
         N = sizes[l]

@@ -126,3 +126,97 @@ def stiffness_pattern(M, springs):
     P = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(M, M)).tocsr()
     P.data[:] = 1.0
     return P
+
+
+# ---- springs with rest lengths and their tangent (Sec. 5, App. A.2, Sec. 6) --
+#
+# The fibre model of Sec. 5 lets the tension be any function of the strain;
+# App. A.2 evaluates tension and unit tangent at half indices.  A spring
+# e = (a, b) with separation d = X_b - X_a (minimum image on the periodic
+# square), length l = |d|, unit vector t = d / l and tension
+# T_e = kappa_e (l - L_e) pulls node a by T_e t and node b by -T_e t; with
+# L_e = 0 this is the linear model above.  A Newton-Krylov treatment of the
+# nonlinear model (Sec. 6) solves systems of the same form with K_h replaced
+# by the force's Jacobian dF/dX at the current configuration.
+
+def _min_image(d):
+    return d - np.round(d)
+
+
+def spring_force(X, springs, kappa, rest):
+    """Nodal forces F(X) of springs with rest lengths (see above)."""
+    X = np.asarray(X, dtype=np.float64)
+    F = np.zeros_like(X)
+    for e in range(springs.shape[0]):
+        a, b = int(springs[e, 0]), int(springs[e, 1])
+        d = _min_image(X[b] - X[a])
+        L = float(rest[e])
+        if L == 0.0:
+            f = kappa[e] * d
+        else:
+            l = float(np.hypot(d[0], d[1]))
+            if l == 0.0:
+                raise ValueError(f"spring {e} has zero length and a nonzero rest length")
+            f = kappa[e] * (l - L) / l * d
+        F[a] += f
+        F[b] -= f
+    return F
+
+
+def tangent_blocks(X, springs, kappa, rest):
+    """Per spring the 2x2 block K_e = dF_a/dX_b: the derivative of
+    kappa (1 - L/|d|) d in d, kappa [(1 - L/l) I + (L/l) t t^T].  [E, 2, 2]."""
+    X = np.asarray(X, dtype=np.float64)
+    out = np.zeros((springs.shape[0], 2, 2))
+    for e in range(springs.shape[0]):
+        a, b = int(springs[e, 0]), int(springs[e, 1])
+        L = float(rest[e])
+        if L == 0.0:
+            out[e] = kappa[e] * np.eye(2)
+            continue
+        d = _min_image(X[b] - X[a])
+        l = float(np.hypot(d[0], d[1]))
+        if l == 0.0:
+            raise ValueError(f"spring {e} has zero length and a nonzero rest length")
+        t = d / l
+        out[e] = kappa[e] * ((1.0 - L / l) * np.eye(2) + (L / l) * np.outer(t, t))
+    return out
+
+
+def tangent_stiffness(X, springs, kappa, rest):
+    """K'_tan = -dF/dX (2M x 2M, planar order: x of every node, then y):
+    spring e adds K_e to the (a, a) and (b, b) blocks and -K_e to (a, b) and
+    (b, a).  Symmetric; with all L_e = 0 it is the linear stiffness
+    -K_h on each coordinate."""
+    M = np.asarray(X).shape[0]
+    Kb = tangent_blocks(X, springs, kappa, rest)
+    rows, cols, vals = [], [], []
+    for e in range(springs.shape[0]):
+        a, b = int(springs[e, 0]), int(springs[e, 1])
+        for c in (0, 1):
+            for cc in (0, 1):
+                k = Kb[e, c, cc]
+                rows += [c * M + a, c * M + a, c * M + b, c * M + b]
+                cols += [cc * M + a, cc * M + b, cc * M + b, cc * M + a]
+                vals += [k, -k, k, -k]
+    return sp.coo_matrix((vals, (rows, cols)), shape=(2 * M, 2 * M)).tocsr()
+
+
+def ib_term_tangent(X, springs, kappa, rest, N, dt):
+    """The IB part of A_IB with the tangent stiffness, dt S_h K'_tan J_h with
+    S_h = diag(S_x, S_y) and J_h = diag(J_x, J_y): 2 N^2 square, coupling the
+    two velocity components through the off-diagonal entries of K_e."""
+    K = tangent_stiffness(X, springs, kappa, rest)
+    S = sp.block_diag([spread_matrix(X, N, 0), spread_matrix(X, N, 1)], format="csr")
+    J = sp.block_diag([interp_matrix(X, N, 0), interp_matrix(X, N, 1)], format="csr")
+    return (dt * (S @ (K @ J))).tocsr()
+
+
+def tangent_pattern(X, springs, N):
+    """Structural pattern of J^T K'_tan J: every component couples to both."""
+    KP = stiffness_pattern(X.shape[0], springs)
+    JP = sp.block_diag([interp_pattern(X, N, 0), interp_pattern(X, N, 1)], format="csr")
+    KP2 = sp.bmat([[KP, KP], [KP, KP]], format="csr")
+    P = (JP.T @ (KP2 @ JP)).tocsr()
+    P.data[:] = 1.0
+    return P

@@ -113,14 +113,13 @@ class SchurSmoother:
         self.A_ib = A_ib
         self.G = level.G
         self.D = level.D
-        # velocity colouring per component on stencil + IB structure
+        # velocity colouring on stencil + IB structure, both components in one
+        # pass (rows in index order); with uncoupled components this is the
+        # per-component colouring, with the tangent model it keeps coupled u
+        # and v rows apart
         St = mac.stencil_pattern(N)
-        TP = level.T_pattern
-        cols = []
-        for c in (0, 1):
-            P = (St + TP[c * n:(c + 1) * n, c * n:(c + 1) * n]).tocsr()
-            cols.append(greedy_colouring(P))
-        self.col_u = np.concatenate(cols)
+        P = (sp.block_diag([St, St]) + level.T_pattern).tocsr()
+        self.col_u = greedy_colouring(P)
         self.sgs_A = SGS(A_ib, self.col_u)
         # approximate Schur complement -M^ = -D diag(A_IB)^{-1} G (PSD)
         dinv = sp.diags(1.0 / A_ib.diagonal())

@@ -12,6 +12,7 @@ lid-driven cavity); this is the reading for a periodic domain.
 import numpy as np
 
 from . import hierarchy, ib
+from .hierarchy import rest_lengths, spring_model
 from .krylov import fgmres
 from .multigrid import Multigrid
 
@@ -57,6 +58,16 @@ def spring_gradient(wl, w, lam):
         S = ib.spread_matrix(wl.X, N, comp)
         Us.append(J @ w[comp * n:(comp + 1) * n])
         Ls.append(S.T @ lam[comp * n:(comp + 1) * n])
+    if spring_model(wl) == "tangent":
+        # K'_tan is linear in each kappa_e: dK'/dkappa_e is spring e's
+        # tangent stiffness at unit kappa
+        U2 = np.concatenate(Us)
+        L2 = np.concatenate(Ls)
+        rest = rest_lengths(wl)
+        for e in range(wl.springs.shape[0]):
+            Ke = ib.tangent_stiffness(wl.X, wl.springs[e:e + 1], np.ones(1), rest[e:e + 1])
+            g[e] = -wl.dt * (L2 @ (Ke @ U2))
+        return g
     for e in range(wl.springs.shape[0]):
         a, b = int(wl.springs[e, 0]), int(wl.springs[e, 1])
         Ke = ib.stiffness_matrix(M, wl.springs[e:e + 1], np.ones(1))

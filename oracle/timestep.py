@@ -12,6 +12,7 @@ minimum-image displacements, and updated positions are wrapped into [0, 1).
 import numpy as np
 
 from . import ib
+from .hierarchy import rest_lengths, spring_model
 from .solver import Problem
 
 
@@ -29,12 +30,23 @@ def fibre_force_periodic(X, springs, kappa):
     return F
 
 
+def nodal_force(wl):
+    """F^n: the linear springs' K_h X^n, or with the tangent model the force
+    of the springs with rest lengths (``ib.spring_force``), whose Jacobian is
+    the operator's stiffness."""
+    if spring_model(wl) == "tangent":
+        return ib.spring_force(wl.X, wl.springs, wl.kappa, rest_lengths(wl))
+    return fibre_force_periodic(wl.X, wl.springs, wl.kappa)
+
+
 def step_rhs(wl, w):
     """[(rho/dt) u^n + S_h F^n; 0] for w = [u; v; p] (the pressure part of w
-    is not used)."""
+    is not used).  With the tangent model the step is linearly implicit:
+    F(X^{n+1}) ~ F^n + dt (dF/dX)(X^n) J_h u^{n+1}, the second term being the
+    operator's IB part."""
     N = wl.N
     n = N * N
-    F = fibre_force_periodic(wl.X, wl.springs, wl.kappa)
+    F = nodal_force(wl)
     rhs = np.zeros(3 * n)
     rhs[:2 * n] = (wl.rho / wl.dt) * np.asarray(w, dtype=np.float64)[:2 * n]
     for c in (0, 1):

@@ -45,6 +45,11 @@ class Workload:
     cheb_its: int = 2
     rhs_seed: int = 0
     extra: dict = field(default_factory=dict)
+    # "linear": zero-rest-length springs, force kappa_e (X_b - X_a);
+    # "tangent": springs with rest lengths ``rest`` [E] (None = all zero), the
+    # operator linearised at X
+    spring_model: str = "linear"
+    rest: Optional[np.ndarray] = None
 
     @property
     def M(self) -> int:
