@@ -17,7 +17,7 @@
  * y-velocity on the face at ((i+1/2) h, j h), p[j][i] the pressure at the cell
  * centre ((i+1/2) h, (j+1/2) h), h = 1/n, all indices periodic.
  * Lagrangian arrays are [M][2] (x, y interleaved).
- * Memory.  Pointers named in a ``desc`` (X, ends, kappa) are HOST pointers,
+ * Memory.  Pointers named in a ``desc`` (X, ends, kappa, rest) are HOST pointers,
  * copied during ibmg_create.  Every vector argument of the other calls is a
  * DEVICE pointer (FP64 unless stated) owned by the caller; the library never
  * frees caller memory.  The library allocates its own device workspace in
@@ -64,6 +64,23 @@ typedef enum {
 enum { IBMG_RAS = 0, IBMG_SC = 1, IBMG_RMS = 2 };
 enum { IBMG_FP64 = 0, IBMG_FP32_SMOOTHER = 1 };  /* precision */
 
+/* Spring model.  Spring e = (a, b) has separation d = X_b - X_a (minimum
+ * image on the periodic square), length l = |d| and unit vector t = d / l.
+ *   IBMG_SPRING_LINEAR   zero rest length (the linear fibre force of Sec. 5,
+ *                        App. A.2): node a feels kappa_e d, node b -kappa_e d,
+ *                        the same operator on each velocity component.
+ *   IBMG_SPRING_TANGENT  rest length L_e: node a feels kappa_e (l - L_e) t
+ *                        (the Sec. 5 fibre model with a tension vanishing at
+ *                        L_e), and the operator's stiffness is this force's
+ *                        Jacobian at the handle's positions (the linearised
+ *                        force of a Newton-Krylov step, Sec. 6): per spring
+ *                        the 2x2 block K_e = kappa_e [(1 - L_e/l) I +
+ *                        (L_e/l) t t^T], which couples the u and v rows of
+ *                        A_IB.  L_e = 0 gives the linear model.  A spring of
+ *                        zero length with L_e > 0 is rejected (IBMG_ERR_ARG).
+ *                        The batched form takes linear springs only. */
+enum { IBMG_SPRING_LINEAR = 0, IBMG_SPRING_TANGENT = 1 };
+
 typedef struct {
   int32_t N;          /* finest grid size; N = coarse_N * 2^k, k >= 1        */
   int32_t coarse_N;   /* coarsest grid (Sec. 5 uses 8); 4 <= coarse_N <= 32   */
@@ -73,8 +90,7 @@ typedef struct {
   const double* X;    /* host [M][2], positions in [0,1)^2 (lagged X^n)      */
   int32_t n_springs;  /* >= 0                                                */
   const int32_t* ends;/* host [n_springs][2] node ids, a != b, in [0, M)     */
-  const double* kappa;/* host [n_springs] spring stiffness >= 0 (zero rest
-                         length, Sec. 5 linear fibre force)                  */
+  const double* kappa;/* host [n_springs] spring stiffness >= 0             */
   int32_t smoother;   /* IBMG_RAS | IBMG_SC | IBMG_RMS                        */
   int32_t box;        /* RAS box size b (cells); must divide every level's
                          n >= 2b, levels below use min(b, n/2)               */
@@ -82,6 +98,9 @@ typedef struct {
   int32_t nu1, nu2;   /* pre/post smoothing: FGMRES iterations, 1..8         */
   int32_t cheb_its;   /* SC: Chebyshev iterations per inner solve, 1..8      */
   int32_t precision;  /* IBMG_FP64 | IBMG_FP32_SMOOTHER                       */
+  int32_t spring_model;/* IBMG_SPRING_LINEAR | IBMG_SPRING_TANGENT (above)    */
+  const double* rest; /* host [n_springs] rest lengths >= 0, or NULL (all
+                         zero); non-zero values need IBMG_SPRING_TANGENT      */
 } ibmg_desc;
 
 typedef struct {
@@ -170,18 +189,24 @@ ibmg_status ibmg_fgmres_solve(ibmg_handle* h, const double* b, double* x,
  *             = -(dt/h^2) sum_c (B_e J lambda_c)(B_e J w_c),
  * B_e J x = (J x)_{b_e} - (J x)_{a_e}: the derivative of a loss through the
  * adjoint solution lambda of L_IB^T lambda = dL/dw (finest level, FP64).
+ * With IBMG_SPRING_TANGENT the sum over c becomes
+ * (B_e J lambda)^T (K_e / kappa_e) (B_e J w) with the spring's 2x2 block
+ * (the operator is linear in kappa_e at fixed positions).
  * w, lambda: 3 N^2; out: [n_springs]. */
 ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* lambda,
                                  double* out, ibmg_stream stream);
 
 /* Replace the spring stiffnesses (host array [n_springs]) and rebuild every
- * level's IB operator and smoother data.  Synchronises ``stream``. */
+ * level's IB operator and smoother data (tangent blocks at the current
+ * positions).  Synchronises ``stream``. */
 ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream stream);
 
 /* The right-hand side of one semi-implicit time step (Sec. 2.2, Eq.
  * matrix-impib, without convection): rhs = [(rho/dt) u + S_h K_h X; 0] on the
- * finest grid, X the handle's current positions, K_h X the nodal forces of
- * the linear springs with minimum-image separations on the periodic square.
+ * finest grid, X the handle's current positions, K_h X the nodal spring
+ * forces of the handle's spring model with minimum-image separations on the
+ * periodic square (with IBMG_SPRING_TANGENT the nonlinear force F(X^n), so the
+ * step is linearly implicit: F(X^{n+1}) ~ F(X^n) + dt K_tan J u^{n+1}).
  * w: [u | v | p] (the p part is not read); rhs: 3 N^2, distinct from w. */
 ibmg_status ibmg_step_rhs(ibmg_handle* h, const double* w, double* rhs, ibmg_stream stream);
 
@@ -190,8 +215,10 @@ ibmg_status ibmg_step_rhs(ibmg_handle* h, const double* w, double* rhs, ibmg_str
  * L_IB(X^n) w^{n+1} = rhs as ibmg_fgmres_solve does (opts, info; transpose
  * must be 0), moves the structure to X^{n+1} = X^n + dt J_h u^{n+1} (wrapped
  * into [0, 1)) and rebuilds every level at X^{n+1}, so the handle is ready
- * for the next step.  w is overwritten with (u, p)^{n+1}.  Synchronises
- * ``stream``.  IBMG_ERR_NONFINITE if the positions become invalid. */
+ * for the next step (tangent blocks re-evaluated there).  w is overwritten
+ * with (u, p)^{n+1}.  Synchronises ``stream``.  IBMG_ERR_NONFINITE if the
+ * positions become invalid; IBMG_ERR_ARG if a spring with a rest length
+ * collapses to zero length. */
 ibmg_status ibmg_time_step(ibmg_handle* h, double* w, const ibmg_solve_opts* opts, ibmg_solve_info* info,
                            ibmg_stream stream);
 

@@ -13,6 +13,7 @@ IBMG_ERR_NONFINITE = -5
 IBMG_ERR_STATE = -6
 
 RAS, SC, RMS = 0, 1, 2
+SPRING_LINEAR, SPRING_TANGENT = 0, 1
 FP64, FP32_SMOOTHER = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -28,6 +29,7 @@ class Desc(ctypes.Structure):
         ("smoother", ctypes.c_int32), ("box", ctypes.c_int32), ("overlap", ctypes.c_int32),
         ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("cheb_its", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("spring_model", ctypes.c_int32), ("rest", _dp),
     ]
 
 

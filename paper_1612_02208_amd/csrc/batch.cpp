@@ -34,6 +34,7 @@ class BatchSolver final : public BatchBase {
     for (int i = 0; i < nsys; ++i) {
       validate_desc(d[i]);
       require(d[i].smoother == IBMG_RAS, "the batched form uses the additive Schwarz smoother");
+      require(d[i].spring_model == IBMG_SPRING_LINEAR, "the batched form takes linear springs");
       require(d[i].coarse_N == d0.coarse_N && d[i].rho == d0.rho && d[i].mu == d0.mu && d[i].dt == d0.dt &&
                   d[i].box == d0.box && d[i].overlap == d0.overlap && d[i].nu1 == d0.nu1 &&
                   d[i].nu2 == d0.nu2 && d[i].precision == d0.precision,
@@ -127,7 +128,8 @@ class BatchSolver final : public BatchBase {
           hr.push_back((int)(b0 + r));
           hp.push_back(hp.back() + (f.tptr[r + 1] - f.tptr[r]));
         }
-        for (int cc : f.tcol) hc.push_back((int)(b0 + cc));
+        // columns index the system's [u | v] vector
+        for (int cc : f.tcol) hc.push_back((int)(base[p] + cc));
         pieces.emplace_back(tvals<U>(f), f.tcol.size());
       }
     }

@@ -25,6 +25,21 @@ struct CsrView {
   const double* val;
 };
 
+// Add an IB entry of a box row: col indexes the level's [u | v] vector; the
+// entry lands on the box's x-face or y-face unknown when that face lies in
+// the enlarged box.
+__device__ __forceinline__ void add_ib_entry(double* Ar, int col, double v, int N, int x0, int y0, int m) {
+  const int NN = N * N;
+  const int comp = col >= NN ? 1 : 0;
+  const int f = col - comp * NN;
+  const int li = pmod(f % N - x0, N), lj = pmod(f / N - y0, N);
+  if (comp == 0) {
+    if (li <= m && lj <= m - 1) Ar[lj * (m + 1) + li] += v;
+  } else {
+    if (li <= m - 1 && lj <= m) Ar[m * (m + 1) + lj * m + li] += v;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_patch_assemble(const int* __restrict__ patch_ids, BoxGeom g,
                                                         StokesCoef<double> c, CsrView tu, CsrView tv,
                                                         double* __restrict__ mats) {
@@ -50,11 +65,7 @@ __global__ void __launch_bounds__(256) k_patch_assemble(const int* __restrict__ 
       if (ii <= m - 1) Ar[p0 + jj * m + ii] += c.gi;
       if (ii >= 1) Ar[p0 + jj * m + ii - 1] -= c.gi;
       const int r = pmod(y0 + jj, N) * N + pmod(x0 + ii, N);
-      for (int k = tu.ptr[r]; k < tu.ptr[r + 1]; ++k) {
-        const int col = tu.col[k];
-        const int li = pmod(col % N - x0, N), lj = pmod(col / N - y0, N);
-        if (li <= m && lj <= m - 1) Ar[lj * (m + 1) + li] += tu.val[k];
-      }
+      for (int k = tu.ptr[r]; k < tu.ptr[r + 1]; ++k) add_ib_entry(Ar, tu.col[k], tu.val[k], N, x0, y0, m);
     } else if (row < p0) {  // y-face (ii, jj)
       const int q = row - nu;
       const int ii = q % m, jj = q / m;
@@ -66,11 +77,7 @@ __global__ void __launch_bounds__(256) k_patch_assemble(const int* __restrict__ 
       if (jj <= m - 1) Ar[p0 + jj * m + ii] += c.gi;
       if (jj >= 1) Ar[p0 + (jj - 1) * m + ii] -= c.gi;
       const int r = pmod(y0 + jj, N) * N + pmod(x0 + ii, N);
-      for (int k = tv.ptr[r]; k < tv.ptr[r + 1]; ++k) {
-        const int col = tv.col[k];
-        const int li = pmod(col % N - x0, N), lj = pmod(col / N - y0, N);
-        if (li <= m - 1 && lj <= m) Ar[nu + lj * m + li] += tv.val[k];
-      }
+      for (int k = tv.ptr[r]; k < tv.ptr[r + 1]; ++k) add_ib_entry(Ar, tv.col[k], tv.val[k], N, x0, y0, m);
     } else {  // cell (ii, jj): -(D u)
       const int q = row - p0;
       const int ii = q % m, jj = q / m;
@@ -920,7 +927,7 @@ __global__ void k_coarse_assemble(int N, StokesCoef<double> c, CsrView tu, CsrVi
     Ar[NN + jp * N + i] -= c.beta;
     Ar[2 * NN + j * N + i] += c.gi;
     Ar[2 * NN + jm * N + i] -= c.gi;
-    for (int k = tv.ptr[q]; k < tv.ptr[q + 1]; ++k) Ar[NN + tv.col[k]] += tv.val[k];
+    for (int k = tv.ptr[q]; k < tv.ptr[q + 1]; ++k) Ar[tv.col[k]] += tv.val[k];
   } else {
     Ar[j * N + ip] -= c.gi;
     Ar[j * N + i] += c.gi;

@@ -1,9 +1,12 @@
 // Immersed-boundary kernels: Peskin four-point weights (App. A.3), their
 // Galerkin coarsening through the velocity prolongation (Sec. 3.1-3.2),
 // interpolation J_h, spreading S_h = J_h^T / h^2 with unit nodal weights,
-// the spring operator K' = sum_e kappa_e B_e^T B_e of zero-rest-length fibres
-// (Sec. 5, App. A.2), the explicit Galerkin IB operator rows used to assemble
-// dense box and coarsest-level matrices, and the stiffness gradient.
+// the spring operator K' = sum_e B_e^T B_e (x) K_e with K_e = kappa_e I for
+// zero-rest-length fibres (Sec. 5, App. A.2) or the 2x2 tangent block of a
+// spring with a rest length (the linearised force of Sec. 6), the explicit
+// Galerkin IB operator rows used to assemble dense box and coarsest-level
+// matrices (columns over the level's [u | v] vector), and the stiffness
+// gradient.
 //
 // Spreading is a gather: every face walks the (point, slot) entries sorted
 // by face at set-up, so results are deterministic and use no atomics.
@@ -131,8 +134,9 @@ __global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, c
   if (live && s == 0) U[interleaved ? 2 * l + comp : comp * M + l] = a;
 }
 
-// F_l = sum over springs e at l of kappa_e (U_l - U_{other end}), both
-// components, from U = J u (planar [2][M]); F is planar [2][M].
+// F_l = sum over springs e at l of K_e (U_l - U_{other end}), from U = J u
+// (planar [2][M]); F is planar [2][M].  K_e = kappa_e I, or the tangent
+// block when sv.adj_k2 is set.
 template <typename T>
 __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __restrict__ F) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,11 +144,21 @@ __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __r
   const int M = sv.M;
   const T U0 = U[l], U1 = U[M + l];
   T f0 = 0, f1 = 0;
-  for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
-    const int q = sv.adj_nbr[e];
-    const T k = sv.adj_k[e];
-    f0 += k * (U0 - U[q]);
-    f1 += k * (U1 - U[M + q]);
+  if (sv.adj_k2) {
+    for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
+      const int q = sv.adj_nbr[e];
+      const T kxx = sv.adj_k[e], kxy = sv.adj_k2[2 * e], kyy = sv.adj_k2[2 * e + 1];
+      const T d0 = U0 - U[q], d1 = U1 - U[M + q];
+      f0 += kxx * d0 + kxy * d1;
+      f1 += kxy * d0 + kyy * d1;
+    }
+  } else {
+    for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
+      const int q = sv.adj_nbr[e];
+      const T k = sv.adj_k[e];
+      f0 += k * (U0 - U[q]);
+      f1 += k * (U1 - U[M + q]);
+    }
   }
   F[l] = f0;
   F[M + l] = f1;
@@ -174,10 +188,13 @@ void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M
   launch_interp_lanes<T>(u, v, fx, fy, M, N, U, 1, s);
 }
 
-// Nodal spring forces F = K_h X on the periodic square (Sec. 5 linear
-// fibres): F_l = sum over springs e at l of kappa_e (X_q - X_l), each
-// separation the minimum-image displacement; X and F interleaved [M][2].
-__global__ void k_fibre_force(const double* __restrict__ X, SpringView<double> sv, double* __restrict__ F) {
+// Nodal spring forces on the periodic square (Sec. 5 fibres): spring e at l
+// with separation d = X_q - X_l (minimum image) and rest length L_e pulls l
+// by kappa_e (1 - L_e / |d|) d, i.e. kappa_e d for L_e = 0 (the linear model,
+// F = K_h X); X and F interleaved [M][2], kappa_e = adj_k (the linear
+// model's stiffness, also with tangent blocks), rest per incidence or null.
+__global__ void k_fibre_force(const double* __restrict__ X, SpringView<double> sv, const double* __restrict__ kap,
+                              const double* __restrict__ rest, double* __restrict__ F) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= sv.M) return;
   const double x0 = X[2 * l], y0 = X[2 * l + 1];
@@ -187,16 +204,19 @@ __global__ void k_fibre_force(const double* __restrict__ X, SpringView<double> s
     double dx = X[2 * q] - x0, dy = X[2 * q + 1] - y0;
     dx -= rint(dx);
     dy -= rint(dy);
-    f0 += sv.adj_k[e] * dx;
-    f1 += sv.adj_k[e] * dy;
+    double k = kap[e];
+    if (rest && rest[e] != 0.0) k *= 1.0 - rest[e] / sqrt(dx * dx + dy * dy);
+    f0 += k * dx;
+    f1 += k * dy;
   }
   F[2 * l] = f0;
   F[2 * l + 1] = f1;
 }
 
-void launch_fibre_force(const double* X, SpringView<double> sv, double* F, hipStream_t s) {
+void launch_fibre_force(const double* X, SpringView<double> sv, const double* kap, const double* rest, double* F,
+                        hipStream_t s) {
   if (!sv.M) return;
-  hipLaunchKernelGGL(k_fibre_force, dim3(cdiv(sv.M, 256)), dim3(256), 0, s, X, sv, F);
+  hipLaunchKernelGGL(k_fibre_force, dim3(cdiv(sv.M, 256)), dim3(256), 0, s, X, sv, kap, rest, F);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -282,18 +302,25 @@ __device__ __forceinline__ void csr_add(const int* __restrict__ cols, double* __
   }
 }
 
-// Row r of the level IB operator dt/h^2 J^T K' J (one component):
-//   T(r, :) = ibs * sum_e kappa_e g_e(r) g_e,   g_e = J_{b_e} - J_{a_e},
-// summing over the springs with an end whose window holds r (a spring with
-// both ends there is counted once, from its lower-numbered end).
-__global__ void k_t_values(FootView<double> f, const int* __restrict__ mask, SpringView<double> sv,
-                           int N, double ibs, const int* __restrict__ t_ptr,
-                           const int* __restrict__ t_col, double* __restrict__ t_val) {
+// Row r of component comp of the level IB operator dt/h^2 J^T K' J:
+//   T(r, (c, col)) = ibs * sum_e g_e(r) K_e[comp][c] g^c_e(col),
+//   g^c_e = J^c_{b_e} - J^c_{a_e},
+// summing over the springs with an end whose comp-window holds r (a spring
+// with both ends there is counted once, from its lower-numbered end), and
+// over the components c that K_e couples (c = comp for the linear model).
+// Columns index the level's [u | v] vector.
+__global__ void k_t_values(FootView<double> f0, FootView<double> f1, const int* __restrict__ mask0,
+                           const int* __restrict__ mask1, SpringView<double> sv, int comp, int N, double ibs,
+                           const int* __restrict__ t_ptr, const int* __restrict__ t_col,
+                           double* __restrict__ t_val) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N * N) return;
   const int lo = t_ptr[r], hi = t_ptr[r + 1];
   if (hi == lo) return;
   for (int k = lo; k < hi; ++k) t_val[k] = 0.0;
+  const FootView<double>& f = comp ? f1 : f0;
+  const int* mask = comp ? mask1 : mask0;
+  const int NN = N * N;
   const int ri = r % N, rj = r / N;
   for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
     const int ent = f.sp_ent[e];
@@ -303,49 +330,64 @@ __global__ void k_t_values(FootView<double> f, const int* __restrict__ mask, Spr
       const int q = sv.adj_nbr[a];
       const int sq = slot_of(f.base, mask, q, ri, rj, N);
       if (sq >= 0 && q < l) continue;  // counted from q's side
-      const double wq_r = sq >= 0 ? f.w[(size_t)q * 16 + sq] : 0.0;
-      const double coef = ibs * sv.adj_k[a] * (wq_r - wl_r);
-      if (coef == 0.0) continue;
-      for (int s = 0; s < 16; ++s) {
-        if (((mask[l] >> s) & 1) == 0) continue;
-        const int ci = wrapi(f.base[2 * l] + (s & 3), N), cj = wrapi(f.base[2 * l + 1] + (s >> 2), N);
-        csr_add(t_col, t_val, lo, hi, cj * N + ci, -coef * f.w[(size_t)l * 16 + s]);
-      }
-      for (int s = 0; s < 16; ++s) {
-        if (((mask[q] >> s) & 1) == 0) continue;
-        const int ci = wrapi(f.base[2 * q] + (s & 3), N), cj = wrapi(f.base[2 * q + 1] + (s >> 2), N);
-        csr_add(t_col, t_val, lo, hi, cj * N + ci, coef * f.w[(size_t)q * 16 + s]);
+      const double g = (sq >= 0 ? f.w[(size_t)q * 16 + sq] : 0.0) - wl_r;
+      for (int c = 0; c < 2; ++c) {
+        double kc;
+        if (sv.adj_k2) kc = comp == 0 ? (c == 0 ? sv.adj_k[a] : sv.adj_k2[2 * a]) : (c == 0 ? sv.adj_k2[2 * a] : sv.adj_k2[2 * a + 1]);
+        else kc = c == comp ? sv.adj_k[a] : 0.0;
+        const double coef = ibs * kc * g;
+        if (coef == 0.0) continue;
+        const FootView<double>& fc = c ? f1 : f0;
+        const int* mc = c ? mask1 : mask0;
+        for (int s = 0; s < 16; ++s) {
+          if (((mc[l] >> s) & 1) == 0) continue;
+          const int ci = wrapi(fc.base[2 * l] + (s & 3), N), cj = wrapi(fc.base[2 * l + 1] + (s >> 2), N);
+          csr_add(t_col, t_val, lo, hi, c * NN + cj * N + ci, -coef * fc.w[(size_t)l * 16 + s]);
+        }
+        for (int s = 0; s < 16; ++s) {
+          if (((mc[q] >> s) & 1) == 0) continue;
+          const int ci = wrapi(fc.base[2 * q] + (s & 3), N), cj = wrapi(fc.base[2 * q + 1] + (s >> 2), N);
+          csr_add(t_col, t_val, lo, hi, c * NN + cj * N + ci, coef * fc.w[(size_t)q * 16 + s]);
+        }
       }
     }
   }
 }
 
-void launch_t_values(FootView<double> f, const int* mask, SpringView<double> sv, int N, double ibs,
-                     const int* t_ptr, const int* t_col, double* t_val, hipStream_t s) {
+void launch_t_values(FootView<double> f0, FootView<double> f1, const int* mask0, const int* mask1,
+                     SpringView<double> sv, int comp, int N, double ibs, const int* t_ptr, const int* t_col,
+                     double* t_val, hipStream_t s) {
   const int n = N * N;
-  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n, 128)), dim3(128), 0, s, f, mask, sv, N, ibs, t_ptr,
-                     t_col, t_val);
+  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n, 128)), dim3(128), 0, s, f0, f1, mask0, mask1, sv, comp, N, ibs,
+                     t_ptr, t_col, t_val);
   IBMG_LAUNCH_CHECK();
 }
 
-// g_e = scale * sum_c (Ul_b - Ul_a)(Uw_b - Uw_a), U interleaved [M][2].
+// g_e = scale * (Ul_b - Ul_a)^T B_e (Uw_b - Uw_a), U interleaved [M][2],
+// B_e = K_e / kappa_e = (B_xx, B_xy; B_xy, B_yy) per spring, or I when
+// blocks is null.
 __global__ void k_spring_grad(const double* __restrict__ Uw, const double* __restrict__ Ul,
-                              const int* __restrict__ ends, int n_springs, double scale,
-                              double* __restrict__ out) {
+                              const int* __restrict__ ends, const double* __restrict__ blocks, int n_springs,
+                              double scale, double* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_springs) return;
   const int a = ends[2 * e], b = ends[2 * e + 1];
-  double g = 0.0;
-  for (int c = 0; c < 2; ++c) g += (Ul[2 * b + c] - Ul[2 * a + c]) * (Uw[2 * b + c] - Uw[2 * a + c]);
+  const double l0 = Ul[2 * b] - Ul[2 * a], l1 = Ul[2 * b + 1] - Ul[2 * a + 1];
+  const double w0 = Uw[2 * b] - Uw[2 * a], w1 = Uw[2 * b + 1] - Uw[2 * a + 1];
+  double g;
+  if (blocks) {
+    const double bxx = blocks[3 * e], bxy = blocks[3 * e + 1], byy = blocks[3 * e + 2];
+    g = l0 * (bxx * w0 + bxy * w1) + l1 * (bxy * w0 + byy * w1);
+  } else {
+    g = l0 * w0 + l1 * w1;
+  }
   out[e] = scale * g;
 }
 
-void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* unused,
-                        int n_springs, int M, double scale, double* out, hipStream_t s) {
-  (void)unused;
-  (void)M;
+void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* blocks,
+                        int n_springs, double scale, double* out, hipStream_t s) {
   if (!n_springs) return;
-  hipLaunchKernelGGL(k_spring_grad, dim3(cdiv(n_springs, 128)), dim3(128), 0, s, Uw, Ul, ends,
+  hipLaunchKernelGGL(k_spring_grad, dim3(cdiv(n_springs, 128)), dim3(128), 0, s, Uw, Ul, ends, blocks,
                      n_springs, scale, out);
   IBMG_LAUNCH_CHECK();
 }
@@ -374,10 +416,9 @@ __global__ void __launch_bounds__(256) k_ib_spmv(const T* __restrict__ x, T* __r
   const int* ptr = comp ? tv.ptr : tu.ptr;
   const int* col = comp ? tv.col : tu.col;
   const T* val = comp ? tv.val : tu.val;
-  const T* xin = x + (size_t)comp * NN;
   const int lo = ptr[r], hi = ptr[r + 1];
   T acc = 0;
-  for (int k = lo + lane; k < hi; k += 64) acc += val[k] * xin[col[k]];
+  for (int k = lo + lane; k < hi; k += 64) acc += val[k] * x[col[k]];   // columns index [u | v]
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) G[wave] = acc;
 }

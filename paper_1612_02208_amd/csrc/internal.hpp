@@ -93,7 +93,9 @@ struct SpringView {
   int M;
   const int* adj_ptr;   // [M + 1]
   const int* adj_nbr;   // neighbour node per incidence
-  const T* adj_k;       // stiffness per incidence
+  const T* adj_k;       // stiffness per incidence (K_e[0][0] with tangent blocks)
+  const T* adj_k2;      // tangent blocks: (K_e[0][1], K_e[1][1]) per incidence,
+                        // nullptr for the linear model (K_e = kappa_e I)
 };
 
 template <typename T>
@@ -215,16 +217,21 @@ void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M
                    T* U, hipStream_t s);
 void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, int M, int N,
                    double scale, double* f, hipStream_t s);
-void launch_t_values(FootView<double> f, const int* mask, SpringView<double> sv, int N,
-                     double ibs, const int* t_ptr, const int* t_col, double* t_val,
-                     hipStream_t s);
+// rows of component comp; f0/f1 and mask0/mask1 the level's two components
+void launch_t_values(FootView<double> f0, FootView<double> f1, const int* mask0, const int* mask1,
+                     SpringView<double> sv, int comp, int N, double ibs, const int* t_ptr,
+                     const int* t_col, double* t_val, hipStream_t s);
 // semi-implicit time step pieces (Sec. 2.2): spring forces on the periodic
 // square, the step's right-hand side, the position update
-void launch_fibre_force(const double* X, SpringView<double> sv, double* F, hipStream_t s);
+// kap: kappa_e per incidence; rest: rest length per incidence, nullptr for
+// zero rest lengths
+void launch_fibre_force(const double* X, SpringView<double> sv, const double* kap, const double* rest, double* F,
+                        hipStream_t s);
 void launch_step_rhs(const double* w, const double* f, double a, int N, double* rhs, hipStream_t s);
 void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s);
-void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* unused,
-                        int n_springs, int M, double scale, double* out, hipStream_t s);
+// blocks: per spring (B_xx, B_xy, B_yy) of K_e / kappa_e, nullptr for B = I
+void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* blocks,
+                        int n_springs, double scale, double* out, hipStream_t s);
 
 // dense boxes and coarsest solve
 void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoef<double> c,

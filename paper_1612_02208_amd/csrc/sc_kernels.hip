@@ -16,7 +16,9 @@ namespace ibmg {
 
 static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 
-// (A_IB x)_r for a velocity row r = comp * N^2 + j * N + i (x = [u | v]).
+// (A_IB x)_r for a velocity row r = comp * N^2 + j * N + i (x = [u | v]);
+// the IB rows' columns index [u | v], so coupled components need nothing
+// extra.
 template <typename T>
 __device__ __forceinline__ T aib_row(const T* __restrict__ x, int r, int N, const StokesCoef<T>& c,
                                      const CsrT<T>& tu, const CsrT<T>& tv) {
@@ -30,7 +32,7 @@ __device__ __forceinline__ T aib_row(const T* __restrict__ x, int r, int N, cons
   const T xc = f[q];
   T a = c.alpha * xc - c.beta * (f[j * N + im] + f[j * N + ip] + f[jm * N + i] + f[jp * N + i] - T(4) * xc);
   const CsrT<T>& t = comp ? tv : tu;
-  for (int k = t.ptr[q]; k < t.ptr[q + 1]; ++k) a += t.val[k] * f[t.col[k]];
+  for (int k = t.ptr[q]; k < t.ptr[q + 1]; ++k) a += t.val[k] * x[t.col[k]];
   return a;
 }
 
@@ -95,7 +97,7 @@ __device__ __forceinline__ void gs_row_group(T* x, const T* __restrict__ b, int 
   const CsrT<T>& tm = comp ? tv : tu;
   T a = 0;
   if (live)
-    for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * f[tm.col[k]];
+    for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * x[tm.col[k]];
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
   if (live && sub == 0) {
@@ -352,7 +354,7 @@ __global__ void k_sc_face_diag(int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, T
   const CsrT<T>& t = comp ? tv : tu;
   T d = c.alpha + T(4) * c.beta;
   for (int k = t.ptr[q]; k < t.ptr[q + 1]; ++k)
-    if (t.col[k] == q) d += t.val[k];
+    if (t.col[k] == r) d += t.val[k];
   diag[r] = d;
   dinv[r] = T(1) / d;
 }

@@ -28,6 +28,20 @@ void validate_desc(const ibmg_desc& d) {
     require(a >= 0 && a < d.M && b >= 0 && b < d.M && a != b, "spring end out of range");
     require(std::isfinite(d.kappa[e]) && d.kappa[e] >= 0.0, "kappa must be finite and >= 0");
   }
+  require(d.spring_model == IBMG_SPRING_LINEAR || d.spring_model == IBMG_SPRING_TANGENT, "unknown spring model");
+  if (d.rest != nullptr)
+    for (int e = 0; e < d.n_springs; ++e) {
+      require(std::isfinite(d.rest[e]) && d.rest[e] >= 0.0, "rest lengths must be finite and >= 0");
+      require(d.rest[e] == 0.0 || d.spring_model == IBMG_SPRING_TANGENT,
+              "non-zero rest lengths need the tangent spring model");
+      if (d.rest[e] == 0.0) continue;
+      // the tangent block needs the spring's direction
+      const int a = d.ends[2 * e], b = d.ends[2 * e + 1];
+      double dx = d.X[2 * b] - d.X[2 * a], dy = d.X[2 * b + 1] - d.X[2 * a + 1];
+      dx -= std::nearbyint(dx);
+      dy -= std::nearbyint(dy);
+      require(std::hypot(dx, dy) > 0.0, "a spring with a rest length has zero length");
+    }
   require(d.smoother == IBMG_RAS || d.smoother == IBMG_SC || d.smoother == IBMG_RMS, "unknown smoother");
   require(d.nu1 >= 1 && d.nu1 <= kMaxNu && d.nu2 >= 1 && d.nu2 <= kMaxNu, "nu1/nu2 must lie in [1, 8]");
   require(d.precision == IBMG_FP64 || d.precision == IBMG_FP32_SMOOTHER, "unknown precision");

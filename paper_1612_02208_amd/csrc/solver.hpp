@@ -9,7 +9,7 @@ struct CompFoot {             // one velocity component on one level
   std::vector<int> base;      // [M][2] wrapped window base (i0, j0)
   std::vector<int> mask;      // [M] structural slots
   std::vector<int> sp_ptr, sp_ent;   // faces -> (point, slot) entries
-  std::vector<int> tptr, tcol;       // Galerkin IB rows (pattern)
+  std::vector<int> tptr, tcol;       // Galerkin IB rows (pattern; columns index [u | v])
   DBuf<int> d_base, d_mask, d_sp_ptr, d_sp_ent, d_tptr, d_tcol;
   DBuf<double> w;             // [M][16]
   DBuf<float> wf;             // FP32 copy for the FP32 smoother

@@ -101,6 +101,14 @@ class Solver final : public SolverBase {
     X_.assign(d.X, d.X + 2 * (size_t)M_);
     ends_.assign(d.ends, d.ends + 2 * (size_t)E_);
     kappa_.assign(d.kappa, d.kappa + E_);
+    tangent_ = d.spring_model == IBMG_SPRING_TANGENT;
+    rest_.assign(E_, 0.0);
+    if (d.rest) rest_.assign(d.rest, d.rest + E_);
+    // the descriptor's host arrays belong to the caller
+    d_.X = nullptr;
+    d_.ends = nullptr;
+    d_.kappa = nullptr;
+    d_.rest = nullptr;
     nu_ = std::max(d.nu1, d.nu2);
     sizes_ = level_sizes(d.N, d.coarse_N);
     L_ = (int)sizes_.size() - 1;
@@ -171,7 +179,10 @@ class Solver final : public SolverBase {
         spread_lists(lev.N, f);
         f.d_sp_ptr.upload(f.sp_ptr, s);
         f.d_sp_ent.upload(f.sp_ent, s);
-        ib_pattern(lev.N, f);
+      }
+      for (int c = 0; c < 2; ++c) {  // IB rows need both components' windows
+        CompFoot& f = lev.f[c];
+        ib_pattern(lev, c);
         f.d_tptr.upload(f.tptr, s);
         f.d_tcol.upload(f.tcol, s);
         f.tval.alloc(f.tcol.size());
@@ -256,21 +267,29 @@ class Solver final : public SolverBase {
         if ((f.mask[l] >> s) & 1) f.sp_ent[fill[face_of(f, l, s, N)]++] = l * 16 + s;
   }
 
-  // Pattern of dt/h^2 J^T K' J: row r couples to every face of every point
-  // that shares a spring (or is itself) with a point whose window holds r.
-  void ib_pattern(int N, CompFoot& f) {
+  // Pattern of the comp rows of dt/h^2 J^T K' J: row r couples to every face
+  // of every point that shares a spring (or is itself) with a point whose
+  // comp-window holds r, in the same component, and with tangent blocks also
+  // in the other one.  Columns index [u | v] (v faces offset by N^2), sorted.
+  void ib_pattern(Level<T>& lev, int comp) {
+    const int N = lev.N;
+    CompFoot& f = lev.f[comp];
     const size_t nf = (size_t)N * N;
     f.tptr.assign(nf + 1, 0);
     f.tcol.clear();
-    std::vector<int> stamp(nf, -1);
+    std::vector<int> stamp(2 * nf, -1);
     std::vector<int> cols;
     auto add_point = [&](int q, int r) {
-      for (int s = 0; s < 16; ++s) {
-        if (!((f.mask[q] >> s) & 1)) continue;
-        const int c = face_of(f, q, s, N);
-        if (stamp[c] != r) {
-          stamp[c] = r;
-          cols.push_back(c);
+      for (int c = 0; c < 2; ++c) {
+        if (c != comp && !tangent_) continue;
+        const CompFoot& fc = lev.f[c];
+        for (int s = 0; s < 16; ++s) {
+          if (!((fc.mask[q] >> s) & 1)) continue;
+          const int col = c * (int)nf + face_of(fc, q, s, N);
+          if (stamp[col] != r) {
+            stamp[col] = r;
+            cols.push_back(col);
+          }
         }
       }
     };
@@ -408,7 +427,10 @@ class Solver final : public SolverBase {
       auto ib_cols = [&](int comp, int i, int j) {
         const CompFoot& f = lev.f[comp];
         const int r = wrapn(j, N) * N + wrapn(i, N);
-        for (int k = f.tptr[r]; k < f.tptr[r + 1]; ++k) touch(owner(f.tcol[k] % N, f.tcol[k] / N));
+        for (int k = f.tptr[r]; k < f.tptr[r + 1]; ++k) {
+          const int face = f.tcol[k] % (N * N);   // columns index [u | v]
+          touch(owner(face % N, face / N));
+        }
       };
       for (int jj = 0; jj <= m; ++jj)
         for (int ii = 0; ii <= m; ++ii) {
@@ -463,10 +485,58 @@ class Solver final : public SolverBase {
     if (!lev.int_list.empty()) lev.uniq.push_back(lev.int_list.front());
   }
 
+  // Per spring the unit block B_e = K_e / kappa_e of the tangent model at the
+  // current positions: (1 - L/l) I + (L/l) t t^T (B_xx, B_xy, B_yy), the
+  // identity for L = 0.
+  std::vector<double> unit_blocks() const {
+    std::vector<double> B(3 * (size_t)E_);
+    for (int e = 0; e < E_; ++e) {
+      const double L = rest_[e];
+      if (L == 0.0) {
+        B[3 * e] = 1.0;
+        B[3 * e + 1] = 0.0;
+        B[3 * e + 2] = 1.0;
+        continue;
+      }
+      const int a = ends_[2 * e], b = ends_[2 * e + 1];
+      double dx = X_[2 * b] - X_[2 * a], dy = X_[2 * b + 1] - X_[2 * a + 1];
+      dx -= std::nearbyint(dx);
+      dy -= std::nearbyint(dy);
+      const double len = std::hypot(dx, dy);
+      require(len > 0.0, "spring " + std::to_string(e) + " has zero length and a non-zero rest length");
+      const double tx = dx / len, ty = dy / len, g = L / len;
+      B[3 * e] = (1.0 - g) + g * tx * tx;
+      B[3 * e + 1] = g * tx * ty;
+      B[3 * e + 2] = (1.0 - g) + g * ty * ty;
+    }
+    return B;
+  }
+
   void build_numeric(hipStream_t s) {
-    // spring stiffness per incidence
-    std::vector<double> ak(adj_nbr_.size());
-    for (size_t a = 0; a < ak.size(); ++a) ak[a] = kappa_[adj_sid_[a]];
+    // spring stiffness per incidence: kappa_e, or the tangent block K_e
+    const size_t na = adj_nbr_.size();
+    std::vector<double> ak(na);
+    for (size_t a = 0; a < na; ++a) ak[a] = kappa_[adj_sid_[a]];
+    if (tangent_) {
+      const std::vector<double> B = unit_blocks();
+      std::vector<double> k00(na), k2(2 * na), rest(na);
+      for (size_t a = 0; a < na; ++a) {
+        const int e = adj_sid_[a];
+        k00[a] = kappa_[e] * B[3 * e];
+        k2[2 * a] = kappa_[e] * B[3 * e + 1];
+        k2[2 * a + 1] = kappa_[e] * B[3 * e + 2];
+        rest[a] = rest_[e];
+      }
+      d_adj_kap_.upload(ak, s);
+      d_adj_rest_.upload(rest, s);
+      d_gblocks_.upload(B, s);
+      ak.swap(k00);
+      d_adj_k2_.upload(k2, s);
+      if (std::is_same<T, float>::value) {
+        std::vector<float> k2f(k2.begin(), k2.end());
+        d_adj_k2f_.upload(k2f, s);
+      }
+    }
     d_adj_k_.upload(ak, s);
     if (std::is_same<T, float>::value) {
       std::vector<float> akf(ak.begin(), ak.end());
@@ -477,8 +547,8 @@ class Solver final : public SolverBase {
       for (int c = 0; c < 2; ++c) {
         CompFoot& f = lev.f[c];
         if (!f.tcol.empty()) {
-          launch_t_values(fview<double>(f), f.d_mask.p, sview<double>(), lev.N, lev.cd.ibs, f.d_tptr.p,
-                          f.d_tcol.p, f.tval.p, s);
+          launch_t_values(fview<double>(lev.f[0]), fview<double>(lev.f[1]), lev.f[0].d_mask.p, lev.f[1].d_mask.p,
+                          sview<double>(), c, lev.N, lev.cd.ibs, f.d_tptr.p, f.d_tcol.p, f.tval.p, s);
           if (std::is_same<T, float>::value)
             launch_cast<double, float>(f.tval.p, f.tvalf.p, f.tcol.size(), s);
         }
@@ -499,20 +569,19 @@ class Solver final : public SolverBase {
     sc.N = N;
     sc.its = d_.cheb_its;
     sc.rho_zero = d_.rho == 0.0;
-    // velocity colours: five-point stencil plus IB rows, per component
-    std::vector<int> colv(2 * (size_t)NN);
-    for (int c = 0; c < 2; ++c) {
-      const CompFoot& f = lev.f[c];
-      std::vector<int> cc = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
-        const int i = r % N, j = r / N;
-        nb.push_back(j * N + (i + 1) % N);
-        nb.push_back(j * N + (i + N - 1) % N);
-        nb.push_back(((j + 1) % N) * N + i);
-        nb.push_back(((j + N - 1) % N) * N + i);
-        for (int k = f.tptr[r]; k < f.tptr[r + 1]; ++k) nb.push_back(f.tcol[k]);
-      });
-      std::copy(cc.begin(), cc.end(), colv.begin() + (size_t)c * NN);
-    }
+    // velocity colours: five-point stencil plus IB rows, both components in
+    // one greedy pass in row order (with uncoupled components this equals
+    // colouring each component alone; tangent blocks couple u and v rows)
+    std::vector<int> colv = greedy_colours(2 * NN, [&](int r, std::vector<int>& nb) {
+      const int comp = r >= NN ? 1 : 0, q = r - comp * NN, o = comp * NN;
+      const int i = q % N, j = q / N;
+      nb.push_back(o + j * N + (i + 1) % N);
+      nb.push_back(o + j * N + (i + N - 1) % N);
+      nb.push_back(o + ((j + 1) % N) * N + i);
+      nb.push_back(o + ((j + N - 1) % N) * N + i);
+      const CompFoot& f = lev.f[comp];
+      for (int k = f.tptr[q]; k < f.tptr[q + 1]; ++k) nb.push_back(f.tcol[k]);
+    });
     sc.colu.build(colv, s);
     sc.colu.long_rows.assign(sc.colu.ncol, 0);
     for (int cc = 0; cc < sc.colu.ncol; ++cc)
@@ -715,9 +784,9 @@ class Solver final : public SolverBase {
   template <typename U>
   SpringView<U> sview() {
     if constexpr (std::is_same<U, double>::value)
-      return SpringView<double>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_k_.p};
+      return SpringView<double>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_k_.p, tangent_ ? d_adj_k2_.p : nullptr};
     else
-      return SpringView<float>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_kf_.p};
+      return SpringView<float>{M_, d_adj_ptr_.p, d_adj_nbr_.p, d_adj_kf_.p, tangent_ ? d_adj_k2f_.p : nullptr};
   }
   template <typename U>
   StokesCoef<U> coef(Level<T>& lev) {
@@ -1129,7 +1198,7 @@ class Solver final : public SolverBase {
     const double h = 1.0 / lev.N;
     launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw_.p, s);
     launch_interp<double>(lam, lam + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Ul_.p, s);
-    launch_spring_grad(Uw_.p, Ul_.p, d_ends_.p, nullptr, E_, M_, -d_.dt / (h * h), out, s);
+    launch_spring_grad(Uw_.p, Ul_.p, d_ends_.p, tangent_ ? d_gblocks_.p : nullptr, E_, -d_.dt / (h * h), out, s);
   }
 
   void set_kappa(const double* kappa, hipStream_t s) override {
@@ -1143,7 +1212,8 @@ class Solver final : public SolverBase {
   }
 
   // ------------------------------------------- semi-implicit time step
-  // rhs = [(rho/dt) u + S_h K_h X; 0] on the finest grid (Eq. matrix-impib)
+  // rhs = [(rho/dt) u + S_h F(X); 0] on the finest grid (Eq. matrix-impib),
+  // F the nodal spring forces (K_h X for the linear model)
   void step_rhs(const double* w, double* rhs, hipStream_t s) override {
     Level<T>& lev = levels_[L_];
     const double h = 1.0 / lev.N;
@@ -1151,7 +1221,8 @@ class Solver final : public SolverBase {
     if (Fs_.n < m2) Fs_.alloc(m2);
     if (fs_.n < 2 * (size_t)lev.N * lev.N) fs_.alloc(2 * (size_t)lev.N * lev.N);
     launch_fill<double>(Fs_.p, 0.0, m2, s);
-    launch_fibre_force(d_X_.p, sview<double>(), Fs_.p, s);
+    launch_fibre_force(d_X_.p, sview<double>(), tangent_ ? d_adj_kap_.p : d_adj_k_.p,
+                       tangent_ ? d_adj_rest_.p : nullptr, Fs_.p, s);
     launch_spread(Fs_.p, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, 1.0 / (h * h), fs_.p, s);
     launch_step_rhs(w, fs_.p, d_.rho / d_.dt, lev.N, rhs, s);
   }
@@ -1268,12 +1339,17 @@ class Solver final : public SolverBase {
  private:
   ibmg_desc d_;
   int M_ = 0, E_ = 0, nu_ = 2, L_ = 0, n0_ = 0;
-  std::vector<double> X_, kappa_;
+  std::vector<double> X_, kappa_, rest_;
+  bool tangent_ = false;   // IBMG_SPRING_TANGENT
   std::vector<int> ends_, sizes_;
   std::vector<int> adj_ptr_, adj_nbr_, adj_sid_;
   DBuf<int> d_adj_ptr_, d_adj_nbr_, d_ends_;
   DBuf<double> d_adj_k_, d_X_;
   DBuf<float> d_adj_kf_;
+  // tangent model: (K_e[0][1], K_e[1][1]) per incidence, kappa_e and L_e per
+  // incidence (spring forces), unit blocks per spring (gradient)
+  DBuf<double> d_adj_k2_, d_adj_kap_, d_adj_rest_, d_gblocks_;
+  DBuf<float> d_adj_k2f_;
   std::vector<Level<T>> levels_;
   DBuf<double> inv0_;
   DBuf<double> Fd_, Uw_, Ul_;

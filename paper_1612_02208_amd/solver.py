@@ -60,7 +60,15 @@ def _make_desc(system, precision):
     d.nu2 = int(getattr(system, "nu2", 2))
     d.cheb_its = int(getattr(system, "cheb_its", 2))
     d.precision = {"fp64": _lib.FP64, "fp32": _lib.FP32_SMOOTHER}[precision]
-    return d, (X, springs, kappa)
+    d.spring_model = {"linear": _lib.SPRING_LINEAR, "tangent": _lib.SPRING_TANGENT}[
+        getattr(system, "spring_model", "linear")]
+    rest = getattr(system, "rest", None)
+    if rest is not None:
+        rest = np.ascontiguousarray(rest, dtype=np.float64)
+        if rest.shape != (springs.shape[0],):
+            raise ValueError("rest must hold one length per spring")
+        d.rest = rest.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d, (X, springs, kappa, rest)
 
 
 def _ptr_array(ts):
@@ -80,7 +88,7 @@ class StokesIB:
             raise RuntimeError("StokesIB needs a HIP device")
         d, keep = _make_desc(system, precision)
         self.N = d.N
-        self.X, self.springs, self.kappa = keep
+        self.X, self.springs, self.kappa, self.rest = keep
         self.M = d.M
         self.E = d.n_springs
         self.rho = d.rho

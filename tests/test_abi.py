@@ -73,6 +73,19 @@ def test_create_rejects_bad_descriptors_without_a_device():
     d = desc()
     d.ends = e2.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     assert lib.ibmg_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.IBMG_ERR_ARG
+    # spring model: unknown model, rest lengths without the tangent model, a
+    # negative rest length, and a zero-length spring with a rest length
+    rest = np.array([0.05])
+    neg = np.array([-0.05])
+    rp = rest.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for bad in (dict(spring_model=2), dict(rest=rp),
+                dict(spring_model=1, rest=neg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))):
+        assert lib.ibmg_create(ctypes.byref(desc(**bad)), None, ctypes.byref(h)) == _lib.IBMG_ERR_ARG, bad
+    Xz = np.array([[0.5, 0.5], [0.5, 0.5]])
+    d = desc(spring_model=1, rest=rp)
+    d.X = Xz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.ibmg_create(ctypes.byref(d), None, ctypes.byref(h)) == _lib.IBMG_ERR_ARG
+    assert b"zero length" in lib.ibmg_last_error(None)
     assert lib.ibmg_destroy(None) == _lib.IBMG_ERR_STATE
 
 
@@ -103,7 +116,7 @@ def test_batch_create_rejects_mismatched_systems_without_a_device():
 
     h = ctypes.c_void_p()
     for bad in ({(1, "mu"): 0.5}, {(1, "box"): 4}, {(0, "smoother"): 1}, {(1, "precision"): 0},
-                {(1, "rho"): 1.0}, {(1, "N"): 40}, {(0, "dt"): 2e-3}):
+                {(1, "rho"): 1.0}, {(1, "N"): 40}, {(0, "dt"): 2e-3}, {(2, "spring_model"): 1}):
         st = lib.ibmg_batch_create(3, descs(3, bad), None, ctypes.byref(h))
         assert st == _lib.IBMG_ERR_ARG, (bad, st)
         assert lib.ibmg_last_error(None)

@@ -70,7 +70,22 @@ def _cases():
     c8.name = "plain_32_rms"
     c9 = W.Workload("annulus_64_rms", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4), smoother="rms")
     c10 = W.Workload("random_48_rms", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, c3.kappa, box=6, overlap=1, smoother="rms")
-    return [c1, c2, c3, c4, c5, c6, c7, c8, c9, c10]
+    # tangent springs with rest lengths (2x2 blocks couple u and v): the
+    # annulus with every spring stretched to 1/0.7 of its rest length, the
+    # Stokes membrane with the Schur-complement smoother, and random springs
+    # (rest lengths 0.3-0.9 of their lengths) with the multiplicative sweep
+    def lengths(X, S):
+        d = X[S[:, 1]] - X[S[:, 0]]
+        d -= np.round(d)
+        return np.hypot(d[:, 0], d[:, 1])
+    c11 = W.Workload("annulus_64_tangent", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4),
+                     spring_model="tangent", rest=0.7 * lengths(X, S))
+    c12 = W.plain_32(smoother="sc", spring_model="tangent")
+    c12.name, c12.rest = "plain_32_tangent_sc", 0.8 * lengths(c12.X, c12.springs)
+    c13 = W.Workload("random_48_tangent_rms", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, c3.kappa, box=6, overlap=1,
+                     smoother="rms", spring_model="tangent",
+                     rest=lengths(Xr, Sr) * rng.uniform(0.3, 0.9, len(Sr)))
+    return [c1, c2, c3, c4, c5, c6, c7, c8, c9, c10, c11, c12, c13]
 
 
 CASES = _cases()
