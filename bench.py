@@ -57,6 +57,7 @@ def parse():
     p.add_argument("--batch", default="on", choices=["on", "off"])
     p.add_argument("--rms", default="on", choices=["on", "off"])
     p.add_argument("--step", default="on", choices=["on", "off"])
+    p.add_argument("--tangent", default="on", choices=["on", "off"])
     return p.parse_args()
 
 
@@ -121,6 +122,51 @@ def step_bench(wl, b):
     return {"step_ms": total, "solve_ms": info["solve_ms"], "rebuild_ms": total - info["solve_ms"],
             "iters": info["iters"], "rel_res_true": info["rel_res_true"],
             "max_displacement": float(np.abs(X - wl.X).max())}
+
+
+def tangent_bench(wl, b, reps=3):
+    """The same workload with tangent springs (rest lengths 0.7 of the
+    springs' lengths, so every spring is stretched): FP64 and FP32-smoother
+    solves to 1e-8, the explicit IB-row entries against the linear model's,
+    and one FP64 time step (right-hand side with the nonlinear force, solve,
+    position update, rebuild with the tangent blocks at X^{n+1})."""
+    import copy
+    import torch
+    from paper_1612_02208_amd import StokesIB
+    d = wl.X[wl.springs[:, 1]] - wl.X[wl.springs[:, 0]]
+    d -= np.round(d)
+    w2 = copy.copy(wl)
+    w2.spring_model, w2.rest = "tangent", 0.7 * np.hypot(d[:, 0], d[:, 1])
+    out = {"rest": "0.7 x spring length"}
+    for prec in ("fp64", "fp32"):
+        t0 = time.perf_counter()
+        g = StokesIB(w2, precision=prec)
+        setup = time.perf_counter() - t0
+        x = torch.empty_like(b)
+        g.solve(b, rtol=1e-8, out=x)
+        ms, info = [], None
+        for _ in range(reps):
+            _, info = g.solve(b, rtol=1e-8, out=x)
+            ms.append(info["solve_ms"])
+        med = float(np.median(ms))
+        out[prec] = {"iters": info["iters"], "solve_ms": med, "vcycles_per_s": info["vcycles"] / (med / 1e3),
+                     "rel_res_true": info["rel_res_true"], "setup_s": setup}
+        if prec == "fp64":
+            out["ib_row_entries"] = sum(lv["ib_nnz"] for lv in g.stats()["levels"])
+            w = torch.zeros_like(b)
+            g.time_step(w, rtol=1e-8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, si = g.time_step(w, rtol=1e-8)
+            torch.cuda.synchronize()
+            tot = 1e3 * (time.perf_counter() - t0)
+            out["time_step"] = {"step_ms": tot, "solve_ms": si["solve_ms"], "rebuild_ms": tot - si["solve_ms"],
+                                "iters": si["iters"]}
+        g.close()
+    g = StokesIB(wl, precision="fp64")
+    out["ib_row_entries_linear"] = sum(lv["ib_nnz"] for lv in g.stats()["levels"])
+    g.close()
+    return out
 
 
 def batch_bench(dev, reps=3):
@@ -332,6 +378,10 @@ def main():
         t0 = time.perf_counter()
         out["time_step_fp64"] = step_bench(wl, b)
         print(f"[bench] time step {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    if a.tangent == "on":
+        t0 = time.perf_counter()
+        out["tangent_fp64_fp32"] = tangent_bench(wl, b)
+        print(f"[bench] tangent springs {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if a.batch == "on":
         t0 = time.perf_counter()
         out["batch"] = batch_bench(dev)
