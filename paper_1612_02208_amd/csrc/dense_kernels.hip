@@ -99,6 +99,29 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
   IBMG_LAUNCH_CHECK();
 }
 
+// Operand layout of the 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its result register v holds D[row][l % 16] with
+// row = 4 (l / 16) + v for FP32 and row = l / 16 + 4 v for FP64 (checked on
+// gfx950 with a one-wave probe).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+
 // ---------------------------------------------------------------------------
 // Batched in-place Gauss-Jordan inversion without pivoting, blocked by 64
 // columns.  The box matrices are ordered velocities first: the velocity block
@@ -106,39 +129,45 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
 // rho/dt - mu Lap + IB with the periodic constants cut off), and the pressure
 // pivots come from the negative definite Schur complement -G^T A^{-1} G, so
 // no pivot vanishes.
-// Step K (columns kb .. kb+w):
-//   panel  (one work-group per matrix): D = A_KK -> D^{-1} in LDS, C = A_:K
-//          saved, A_Kj <- D^{-1} A_Kj (j outside K), A_KK <- D^{-1};
-//   update (64 x 64 tiles of every matrix): A_ij <- [j outside K] A_ij
-//          - sum_k C_ik A_Kj  for i outside K (with A_KK = D^{-1} this also
-//          gives A_iK <- -A_iK D^{-1}).
+// Step K (columns kb .. kb+w, w <= 64), four launches over every matrix:
+//   diag   (a work-group per matrix): D = A_KK -> D^{-1} in LDS, to dinv;
+//   colk   (64-row tiles): C = A_:K saved (A_:K is overwritten below);
+//   rows   (64-column tiles): A_KJ <- D^{-1} A_KJ for J != K, A_KK <- D^{-1};
+//   update (64 x 64 tiles, rows outside K): A_IJ <- [J != K] A_IJ - C_I A_KJ
+//          (with A_KK = D^{-1} this also gives A_IK <- -C_I D^{-1}).
+// The rows and update products are 64 x 64 x 64 tiles on the FP64 matrix
+// cores (16x16x4 MFMA, four waves of 2 x 2 tiles).
 // ---------------------------------------------------------------------------
 constexpr int GJ_NB = 64;
 
-__global__ void __launch_bounds__(256) k_gj_panel(double* __restrict__ mats, int n, int kb,
-                                                  double* __restrict__ colk_all) {
+__global__ void __launch_bounds__(256) k_gj_diag(const double* __restrict__ mats, int n, int kb,
+                                                 double* __restrict__ dinv_all) {
   __shared__ double Dm[GJ_NB][GJ_NB + 1];
-  double* A = mats + (size_t)blockIdx.x * n * n;
-  double* colK = colk_all + (size_t)blockIdx.x * n * GJ_NB;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* A = mats + (size_t)blockIdx.x * n * n;
+  double* Di = dinv_all + (size_t)blockIdx.x * GJ_NB * GJ_NB;
+  const int tid = threadIdx.x;
   const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
-  for (int t = tid; t < GJ_NB * GJ_NB; t += nt) {
-    const int a = t / GJ_NB, b = t % GJ_NB;
-    Dm[a][b] = (a < w && b < w) ? A[(size_t)(kb + a) * n + kb + b] : 0.0;
+  // the padding of a narrow last block is the identity, so the pivots stay
+  // nonzero; the padded rows and columns never reach the matrix
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q, a = t >> 6, b = t & 63;
+    Dm[a][b] = (a < w && b < w) ? A[(size_t)(kb + a) * n + kb + b] : (a == b ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int k = 0; k < w; ++k) {
+  for (int k = 0; k < GJ_NB; ++k) {
     const double ip = 1.0 / Dm[k][k];
     double rk[16], ck[16];
-    int q = 0;
-    for (int t = tid; t < w * w; t += nt, ++q) {
-      rk[q] = Dm[k][t % w];
-      ck[q] = Dm[t / w][k];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q;
+      rk[q] = Dm[k][t & 63];
+      ck[q] = Dm[t >> 6][k];
     }
     __syncthreads();
-    q = 0;
-    for (int t = tid; t < w * w; t += nt, ++q) {
-      const int ti = t / w, tj = t % w;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, ti = t >> 6, tj = t & 63;
       double val = Dm[ti][tj];
       if (ti == k && tj == k) val = ip;
       else if (ti == k) val = rk[q] * ip;
@@ -148,88 +177,137 @@ __global__ void __launch_bounds__(256) k_gj_panel(double* __restrict__ mats, int
     }
     __syncthreads();
   }
-  for (size_t t = tid; t < (size_t)n * GJ_NB; t += nt) {
-    const int i = (int)(t / GJ_NB), k = (int)(t % GJ_NB);
-    colK[t] = k < w ? A[(size_t)i * n + kb + k] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q;
+    Di[t] = Dm[t >> 6][t & 63];
   }
-  __syncthreads();
-  for (int j = tid; j < n; j += nt) {
-    if (j >= kb && j < kb + w) {
-      for (int k = 0; k < w; ++k) A[(size_t)(kb + k) * n + j] = Dm[k][j - kb];
-    } else {
-      double col[GJ_NB];
+}
+
+// C = A[:, K] (n x 64, zero beyond w), 64 rows per work-group
+__global__ void __launch_bounds__(256) k_gj_colk(const double* __restrict__ mats, int n, int kb,
+                                                 double* __restrict__ colk_all) {
+  const double* A = mats + (size_t)blockIdx.y * n * n;
+  double* C = colk_all + (size_t)blockIdx.y * n * GJ_NB;
+  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
+  const int I0 = blockIdx.x * 64;
 #pragma unroll
-      for (int k = 0; k < GJ_NB; ++k) col[k] = k < w ? A[(size_t)(kb + k) * n + j] : 0.0;
-      for (int k = 0; k < w; ++k) {
-        double a = 0.0;
+  for (int q = 0; q < 16; ++q) {
+    const int t = threadIdx.x + 256 * q, a = t >> 6, k = t & 63;
+    const int i = I0 + a;
+    if (i < n) C[(size_t)i * GJ_NB + k] = k < w ? A[(size_t)i * n + kb + k] : 0.0;
+  }
+}
+
+struct Gj64Smem {
+  double Xs[32][65];   // [reduction index of the chunk][row]
+  double Ys[32][65];   // [reduction index of the chunk][column]
+};
+
+// acc = X Y for the wave's 32 x 32 quarter of a 64 x 64 tile: X is a
+// row-major block with 64 columns (rows beyond xrows read as zero), Y the
+// panel rows A[kb .. kb+64)[J0 .. J0+64) (zero beyond the matrix); the
+// reduction runs in two chunks of 32 through LDS.
+__device__ __forceinline__ void gj_tile_product(Gj64Smem& sm, Mfma<double>::acc_t acc[2][2],
+                                                const double* __restrict__ X, int xrows,
+                                                const double* __restrict__ A, int n, int kb, int J0) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
 #pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) a += Dm[k][q] * col[q];
-        A[(size_t)(kb + k) * n + j] = a;
-      }
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < GJ_NB; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = tid + 256 * q;
+      const int row = t >> 5, k = t & 31;
+      sm.Xs[k][row] = row < xrows ? X[(size_t)row * GJ_NB + k0 + k] : 0.0;
+      const int ky = t >> 6, c = t & 63;
+      const int r = kb + k0 + ky, j = J0 + c;
+      sm.Ys[ky][c] = (r < n && j < n) ? A[(size_t)r * n + j] : 0.0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int kk = 4 * st + kq;
+      const double a0 = sm.Xs[kk][32 * wr + ln], a1 = sm.Xs[kk][32 * wr + 16 + ln];
+      const double b0 = sm.Ys[kk][32 * wc + ln], b1 = sm.Ys[kk][32 * wc + 16 + ln];
+      acc[0][0] = Mfma<double>::mma(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<double>::mma(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<double>::mma(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<double>::mma(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256) k_gj_rows(double* __restrict__ mats, int n, int kb,
+                                                 const double* __restrict__ dinv_all) {
+  __shared__ Gj64Smem sm;
+  double* A = mats + (size_t)blockIdx.y * n * n;
+  const double* Di = dinv_all + (size_t)blockIdx.y * GJ_NB * GJ_NB;
+  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
+  const int J0 = blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  if (J0 == kb) {   // A_KK <- D^{-1}
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, a = t >> 6, b = t & 63;
+      if (a < w && b < w) A[(size_t)(kb + a) * n + kb + b] = Di[t];
+    }
+    return;
+  }
+  Mfma<double>::acc_t acc[2][2];
+  gj_tile_product(sm, acc, Di, GJ_NB, A, n, kb, J0);
+  const int wave = tid >> 6, lane = tid & 63, wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 32 * wr + 16 * a + Mfma<double>::row(kq, v);
+        const int j = J0 + 32 * wc + 16 * b + ln;
+        if (row < w && j < n) A[(size_t)(kb + row) * n + j] = acc[a][b][v];
+      }
 }
 
 __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, int n, int kb,
                                                    const double* __restrict__ colk_all) {
-  __shared__ double Cs[64][33];
-  __shared__ double Ps[32][65];
-  double* A = mats + (size_t)blockIdx.z * n * n;
-  const double* colK = colk_all + (size_t)blockIdx.z * n * GJ_NB;
-  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
   const int I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  double acc[4][4];
+  if (I0 == kb) return;   // the rows of K are final
+  __shared__ Gj64Smem sm;
+  double* A = mats + (size_t)blockIdx.z * n * n;
+  const double* C = colk_all + (size_t)blockIdx.z * n * GJ_NB;
+  const int tid = threadIdx.x;
+  Mfma<double>::acc_t acc[2][2];
+  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, A, n, kb, J0);
+  const int wave = tid >> 6, lane = tid & 63, wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
+  const bool diag_cols = J0 == kb;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int k0 = 0; k0 < w; k0 += 32) {
-    for (int t = tid; t < 64 * 32; t += 256) {
-      const int a = t / 32, k = t % 32;
-      const int i = I0 + a;
-      Cs[a][k] = (i < n && k0 + k < w) ? colK[(size_t)i * GJ_NB + k0 + k] : 0.0;
-    }
-    for (int t = tid; t < 32 * 64; t += 256) {
-      const int k = t / 64, b = t % 64;
-      const int j = J0 + b;
-      Ps[k][b] = (j < n && k0 + k < w) ? A[(size_t)(kb + k0 + k) * n + j] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-      double c[4], p[4];
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) c[a] = Cs[ty + 16 * a][k];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) p[b] = Ps[k][tx + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += c[a] * p[b];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = I0 + ty + 16 * a;
-    if (i >= n || (i >= kb && i < kb + w)) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = J0 + tx + 16 * b;
-      if (j >= n) continue;
-      const size_t o = (size_t)i * n + j;
-      const double old = (j >= kb && j < kb + w) ? 0.0 : A[o];
-      A[o] = old - acc[a][b];
-    }
-  }
+      for (int v = 0; v < 4; ++v) {
+        const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
+        const int j = J0 + 32 * wc + 16 * b + ln;
+        if (i >= n || j >= n) continue;
+        const size_t o = (size_t)i * n + j;
+        A[o] = (diag_cols ? 0.0 : A[o]) - acc[a][b][v];
+      }
 }
 
-void launch_gj_invert(double* mats, int n, int count, double* colk, hipStream_t s) {
+void launch_gj_invert(double* mats, int n, int count, double* colk, double* dinv, hipStream_t s) {
   if (!count) return;
   const int tiles = (n + 63) / 64;
   for (int kb = 0; kb < n; kb += GJ_NB) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(count), dim3(256), 0, s, mats, n, kb, colk);
+    hipLaunchKernelGGL(k_gj_diag, dim3(count), dim3(256), 0, s, mats, n, kb, dinv);
+    IBMG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gj_colk, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, colk);
+    IBMG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gj_rows, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, dinv);
     IBMG_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, count), dim3(256), 0, s, mats, n, kb, colk);
     IBMG_LAUNCH_CHECK();
@@ -453,28 +531,6 @@ int ras_ib_ksplit(const BoxGeom& g, int n_ib) {
 // steps.  A fragments stream straight from the chunk layout (16 contiguous
 // rows per reduction index), B fragments come from the boxes' residuals,
 // gathered 64 reduction indices at a time into LDS.
-// Operand layout of the 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; its result register v holds D[row][l % 16] with
-// row = 4 (l / 16) + v for FP32 and row = l / 16 + 4 v for FP64 (checked on
-// gfx950 with a one-wave probe).
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef double acc_t __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
-};
-template <>
-struct Mfma<float> {
-  typedef float acc_t __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
-};
 
 // Reference tile width of the single-system interior product: the number of
 // reduction slices is derived from it, so the sums (and the results) do not

@@ -238,7 +238,8 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
                            const int* tptr_u, const int* tcol_u, const double* tval_u,
                            const int* tptr_v, const int* tcol_v, const double* tval_v,
                            double* mats, hipStream_t s);
-void launch_gj_invert(double* mats, int n, int count, double* colk, hipStream_t s);
+// colk: count x n x 64 and dinv: count x 64 x 64 doubles of workspace
+void launch_gj_invert(double* mats, int n, int count, double* colk, double* dinv, hipStream_t s);
 constexpr int kGjNb = 64;  // block width of the batched Gauss-Jordan inversion
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);

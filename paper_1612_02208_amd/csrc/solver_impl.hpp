@@ -5,6 +5,7 @@
 // sequences launches on one stream.
 #pragma once
 
+#include <map>
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
@@ -555,8 +556,7 @@ class Solver final : public SolverBase {
       }
     }
     build_coarse(s);
-    if (d_.smoother == IBMG_RAS || d_.smoother == IBMG_RMS)
-      for (int l = 1; l <= L_; ++l) build_boxes(levels_[l], s);
+    if (d_.smoother == IBMG_RAS || d_.smoother == IBMG_RMS) build_boxes(s);
     if (d_.smoother == IBMG_SC)
       for (int l = 1; l <= L_; ++l) sc_numeric(levels_[l], s);
   }
@@ -707,9 +707,9 @@ class Solver final : public SolverBase {
     IBMG_HIP(hipStreamSynchronize(s));
   }
 
-  void build_boxes(Level<T>& lev, hipStream_t s) {
+  // Box lists, slice buffers and the inverse storage of one level.
+  void prepare_boxes(Level<T>& lev, hipStream_t s) {
     const BoxGeom& g = lev.g;
-    const size_t per = (size_t)g.nloc * g.nloc;
     lev.d_ib.upload(lev.ib_list, s);
     lev.d_int.upload(lev.int_list, s);
     lev.d_loc.upload(lev.loc_tab, s);
@@ -726,22 +726,57 @@ class Solver final : public SolverBase {
       if (lev.int_part.n < need) lev.int_part.alloc(need);
     }
     lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
-    const size_t budget = (size_t)1 << 30;
-    int batch = (int)std::max<size_t>(1, budget / ((per + (size_t)g.nloc * kGjNb) * sizeof(double)));
-    batch = std::min(batch, lev.n_unique);
-    DBuf<double> mats((size_t)batch * per);
-    DBuf<double> colk((size_t)batch * g.nloc * kGjNb);
-    DBuf<int> ids;
-    ids.upload(lev.uniq, s);
-    for (int b0 = 0; b0 < lev.n_unique; b0 += batch) {
-      const int cnt = std::min(batch, lev.n_unique - b0);
-      launch_patch_assemble(ids.p + b0, cnt, g, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p,
-                            lev.f[0].tval.p, lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p,
-                            mats.p, s);
-      launch_gj_invert(mats.p, g.nloc, cnt, colk.p, s);
-      launch_extract_owned<T>(mats.p, cnt, g, lev.inv.p + (size_t)b0 * box_stride(lev), s);
+  }
+
+  // The unique box inverses of every Schwarz level: assembled per level,
+  // inverted in batches that mix levels whose boxes have the same number of
+  // unknowns (one Gauss-Jordan sweep serves them all), owned rows extracted
+  // per level.  Batches hold as many matrices as half the free device memory
+  // (at most 16 GiB) allows, and at most 512.
+  void build_boxes(hipStream_t s) {
+    std::map<int, std::vector<std::pair<int, int>>> groups;   // nloc -> (level, unique index)
+    std::vector<DBuf<int>> ids(L_ + 1);
+    for (int l = 1; l <= L_; ++l) {
+      Level<T>& lev = levels_[l];
+      prepare_boxes(lev, s);
+      ids[l].upload(lev.uniq, s);
+      for (int u = 0; u < lev.n_unique; ++u) groups[lev.g.nloc].push_back({l, u});
     }
-    IBMG_HIP(hipStreamSynchronize(s));
+    size_t free_b = 0, total_b = 0;
+    IBMG_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t budget = std::max<size_t>((size_t)1 << 30, std::min<size_t>((size_t)16 << 30, free_b / 2));
+    for (auto& grp : groups) {
+      const int n = grp.first;
+      const auto& items = grp.second;
+      const size_t per = ((size_t)n * n + (size_t)n * kGjNb + (size_t)kGjNb * kGjNb) * sizeof(double);
+      const int batch = (int)std::min<size_t>({items.size(), std::max<size_t>(1, budget / per), (size_t)512});
+      DBuf<double> mats((size_t)batch * n * n), colk((size_t)batch * n * kGjNb), dinv((size_t)batch * kGjNb * kGjNb);
+      for (size_t b0 = 0; b0 < items.size(); b0 += batch) {
+        const int cnt = (int)std::min<size_t>(batch, items.size() - b0);
+        // runs of one level with consecutive unique indices
+        auto for_runs = [&](auto fn) {
+          size_t i = b0;
+          while (i < b0 + cnt) {
+            size_t j = i + 1;
+            while (j < b0 + cnt && items[j].first == items[i].first && items[j].second == items[j - 1].second + 1) ++j;
+            fn(items[i].first, items[i].second, (int)(j - i), i - b0);
+            i = j;
+          }
+        };
+        for_runs([&](int l, int u0, int count, size_t slot) {
+          Level<T>& lev = levels_[l];
+          launch_patch_assemble(ids[l].p + u0, count, lev.g, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p,
+                                lev.f[0].tval.p, lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p,
+                                mats.p + slot * n * n, s);
+        });
+        launch_gj_invert(mats.p, n, cnt, colk.p, dinv.p, s);
+        for_runs([&](int l, int u0, int count, size_t slot) {
+          Level<T>& lev = levels_[l];
+          launch_extract_owned<T>(mats.p + slot * n * n, count, lev.g, lev.inv.p + (size_t)u0 * box_stride(lev), s);
+        });
+      }
+      IBMG_HIP(hipStreamSynchronize(s));
+    }
   }
 
   void alloc_work(hipStream_t s) {
