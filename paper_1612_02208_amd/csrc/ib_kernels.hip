@@ -291,15 +291,12 @@ __device__ __forceinline__ int slot_of(const int* __restrict__ base, const int* 
   return ((mask[q] >> s) & 1) ? s : -1;
 }
 
-__device__ __forceinline__ void csr_add(const int* __restrict__ cols, double* __restrict__ vals,
-                                        int lo, int hi, int col, double v) {
-  int a = lo, b = hi - 1;
-  while (a <= b) {
-    const int m = (a + b) >> 1;
-    const int c = cols[m];
-    if (c == col) { vals[m] += v; return; }
-    if (c < col) a = m + 1; else b = m - 1;
-  }
+
+// Weight of face (i, j) in point q's window of one component (0 outside).
+__device__ __forceinline__ double window_weight(const FootView<double>& f, const int* __restrict__ mask, int q,
+                                                int i, int j, int N) {
+  const int s = slot_of(f.base, mask, q, i, j, N);
+  return s >= 0 ? f.w[(size_t)q * 16 + s] : 0.0;
 }
 
 // Row r of component comp of the level IB operator dt/h^2 J^T K' J:
@@ -308,57 +305,62 @@ __device__ __forceinline__ void csr_add(const int* __restrict__ cols, double* __
 // summing over the springs with an end whose comp-window holds r (a spring
 // with both ends there is counted once, from its lower-numbered end), and
 // over the components c that K_e couples (c = comp for the linear model).
-// Columns index the level's [u | v] vector.
-__global__ void k_t_values(FootView<double> f0, FootView<double> f1, const int* __restrict__ mask0,
-                           const int* __restrict__ mask1, SpringView<double> sv, int comp, int N, double ibs,
-                           const int* __restrict__ t_ptr, const int* __restrict__ t_col,
-                           double* __restrict__ t_val) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N * N) return;
+// Columns index the level's [u | v] vector.  One wave per row: every lane
+// walks the row's (point, spring) pairs in the same order and accumulates
+// the columns it owns (pattern entries lane, lane + 64, ...), so each entry
+// is a fixed-order sum.
+__global__ void __launch_bounds__(256) k_t_values(FootView<double> f0, FootView<double> f1,
+                                                  const int* __restrict__ mask0, const int* __restrict__ mask1,
+                                                  SpringView<double> sv, int comp, int N, double ibs,
+                                                  const int* __restrict__ t_ptr, const int* __restrict__ t_col,
+                                                  double* __restrict__ t_val) {
+  const int r = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int NN = N * N;
+  if (r >= NN) return;
   const int lo = t_ptr[r], hi = t_ptr[r + 1];
   if (hi == lo) return;
-  for (int k = lo; k < hi; ++k) t_val[k] = 0.0;
   const FootView<double>& f = comp ? f1 : f0;
   const int* mask = comp ? mask1 : mask0;
-  const int NN = N * N;
   const int ri = r % N, rj = r / N;
-  for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
-    const int ent = f.sp_ent[e];
-    const int l = ent >> 4;
-    const double wl_r = f.w[ent];
-    for (int a = sv.adj_ptr[l]; a < sv.adj_ptr[l + 1]; ++a) {
-      const int q = sv.adj_nbr[a];
-      const int sq = slot_of(f.base, mask, q, ri, rj, N);
-      if (sq >= 0 && q < l) continue;  // counted from q's side
-      const double g = (sq >= 0 ? f.w[(size_t)q * 16 + sq] : 0.0) - wl_r;
-      for (int c = 0; c < 2; ++c) {
+  for (int k = lo + lane; k - lane < hi; k += 64) {
+    const bool live = k < hi;
+    const int col = live ? t_col[k] : 0;
+    const int c = col >= NN ? 1 : 0;
+    const int face = col - c * NN;
+    const int ci = face % N, cj = face / N;
+    const FootView<double>& fc = c ? f1 : f0;
+    const int* mc = c ? mask1 : mask0;
+    double acc = 0.0;
+    for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
+      const int ent = f.sp_ent[e];
+      const int l = ent >> 4;
+      const double wl_r = f.w[ent];
+      const int a0 = sv.adj_ptr[l], a1 = sv.adj_ptr[l + 1];
+      if (a0 == a1) continue;
+      const double wl_c = window_weight(fc, mc, l, ci, cj, N);
+      for (int a = a0; a < a1; ++a) {
+        const int q = sv.adj_nbr[a];
+        const int sq = slot_of(f.base, mask, q, ri, rj, N);
+        if (sq >= 0 && q < l) continue;  // counted from q's side
+        const double g = (sq >= 0 ? f.w[(size_t)q * 16 + sq] : 0.0) - wl_r;
         double kc;
         if (sv.adj_k2) kc = comp == 0 ? (c == 0 ? sv.adj_k[a] : sv.adj_k2[2 * a]) : (c == 0 ? sv.adj_k2[2 * a] : sv.adj_k2[2 * a + 1]);
         else kc = c == comp ? sv.adj_k[a] : 0.0;
         const double coef = ibs * kc * g;
         if (coef == 0.0) continue;
-        const FootView<double>& fc = c ? f1 : f0;
-        const int* mc = c ? mask1 : mask0;
-        for (int s = 0; s < 16; ++s) {
-          if (((mc[l] >> s) & 1) == 0) continue;
-          const int ci = wrapi(fc.base[2 * l] + (s & 3), N), cj = wrapi(fc.base[2 * l + 1] + (s >> 2), N);
-          csr_add(t_col, t_val, lo, hi, c * NN + cj * N + ci, -coef * fc.w[(size_t)l * 16 + s]);
-        }
-        for (int s = 0; s < 16; ++s) {
-          if (((mc[q] >> s) & 1) == 0) continue;
-          const int ci = wrapi(fc.base[2 * q] + (s & 3), N), cj = wrapi(fc.base[2 * q + 1] + (s >> 2), N);
-          csr_add(t_col, t_val, lo, hi, c * NN + cj * N + ci, coef * fc.w[(size_t)q * 16 + s]);
-        }
+        acc += coef * (window_weight(fc, mc, q, ci, cj, N) - wl_c);
       }
     }
+    if (live) t_val[k] = acc;
   }
 }
 
 void launch_t_values(FootView<double> f0, FootView<double> f1, const int* mask0, const int* mask1,
                      SpringView<double> sv, int comp, int N, double ibs, const int* t_ptr, const int* t_col,
                      double* t_val, hipStream_t s) {
-  const int n = N * N;
-  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n, 128)), dim3(128), 0, s, f0, f1, mask0, mask1, sv, comp, N, ibs,
+  const size_t n = (size_t)N * N;
+  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n * 64, 256)), dim3(256), 0, s, f0, f1, mask0, mask1, sv, comp, N, ibs,
                      t_ptr, t_col, t_val);
   IBMG_LAUNCH_CHECK();
 }

@@ -5,7 +5,9 @@
 // sequences launches on one stream.
 #pragma once
 
+#include <atomic>
 #include <map>
+#include <thread>
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
@@ -276,36 +278,74 @@ class Solver final : public SolverBase {
     const int N = lev.N;
     CompFoot& f = lev.f[comp];
     const size_t nf = (size_t)N * N;
-    f.tptr.assign(nf + 1, 0);
-    f.tcol.clear();
-    std::vector<int> stamp(2 * nf, -1);
-    std::vector<int> cols;
-    auto add_point = [&](int q, int r) {
-      for (int c = 0; c < 2; ++c) {
-        if (c != comp && !tangent_) continue;
-        const CompFoot& fc = lev.f[c];
-        for (int s = 0; s < 16; ++s) {
-          if (!((fc.mask[q] >> s) & 1)) continue;
-          const int col = c * (int)nf + face_of(fc, q, s, N);
-          if (stamp[col] != r) {
-            stamp[col] = r;
-            cols.push_back(col);
+    // rows in chunks claimed by worker threads; each chunk keeps its own
+    // columns and the chunks are joined in order, so the pattern does not
+    // depend on the thread count
+    constexpr size_t kChunk = 2048;
+    const size_t nchunks = (nf + kChunk - 1) / kChunk;
+    std::vector<std::vector<int>> ccols(nchunks), clen(nchunks);
+    std::atomic<size_t> next{0};
+    auto worker = [&]() {
+      std::vector<int> stamp(2 * nf, -1);
+      std::vector<int> cols;
+      auto add_point = [&](int q, int r) {
+        for (int c = 0; c < 2; ++c) {
+          if (c != comp && !tangent_) continue;
+          const CompFoot& fc = lev.f[c];
+          for (int s = 0; s < 16; ++s) {
+            if (!((fc.mask[q] >> s) & 1)) continue;
+            const int col = c * (int)nf + face_of(fc, q, s, N);
+            if (stamp[col] != r) {
+              stamp[col] = r;
+              cols.push_back(col);
+            }
           }
+        }
+      };
+      for (;;) {
+        const size_t ch = next++;
+        if (ch >= nchunks) break;
+        const size_t r0 = ch * kChunk, r1 = std::min(nf, r0 + kChunk);
+        std::vector<int>& out = ccols[ch];
+        std::vector<int>& len = clen[ch];
+        len.assign(r1 - r0, 0);
+        for (size_t r = r0; r < r1; ++r) {
+          if (f.sp_ptr[r + 1] == f.sp_ptr[r]) continue;
+          cols.clear();
+          for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
+            const int l = f.sp_ent[e] >> 4;
+            if (adj_ptr_[l + 1] == adj_ptr_[l]) continue;
+            add_point(l, (int)r);
+            for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a], (int)r);
+          }
+          std::sort(cols.begin(), cols.end());
+          out.insert(out.end(), cols.begin(), cols.end());
+          len[r - r0] = (int)cols.size();
         }
       }
     };
-    for (size_t r = 0; r < nf; ++r) {
-      cols.clear();
-      for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
-        const int l = f.sp_ent[e] >> 4;
-        if (adj_ptr_[l + 1] == adj_ptr_[l]) continue;
-        add_point(l, (int)r);
-        for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a], (int)r);
-      }
-      std::sort(cols.begin(), cols.end());
-      f.tcol.insert(f.tcol.end(), cols.begin(), cols.end());
-      f.tptr[r + 1] = (int)f.tcol.size();
+    // each worker keeps a stamp over [u | v]: at most 1 GiB of stamps in all
+    const size_t by_mem = std::max<size_t>(1, ((size_t)1 << 30) / (2 * nf * sizeof(int)));
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nth = std::min({(size_t)16, hw, by_mem, nchunks});
+    if (nth <= 1) {
+      worker();
+    } else {
+      std::vector<std::thread> th;
+      for (size_t t = 0; t < nth; ++t) th.emplace_back(worker);
+      for (auto& t : th) t.join();
     }
+    f.tptr.assign(nf + 1, 0);
+    size_t tot = 0;
+    for (size_t ch = 0; ch < nchunks; ++ch) tot += ccols[ch].size();
+    f.tcol.clear();
+    f.tcol.reserve(tot);
+    for (size_t ch = 0; ch < nchunks; ++ch) {
+      const size_t r0 = ch * kChunk;
+      for (size_t i = 0; i < clen[ch].size(); ++i) f.tptr[r0 + i + 1] = clen[ch][i];
+      f.tcol.insert(f.tcol.end(), ccols[ch].begin(), ccols[ch].end());
+    }
+    for (size_t r = 0; r < nf; ++r) f.tptr[r + 1] += f.tptr[r];
   }
 
   // A box needs its own inverse when one of its faces carries an IB row;
