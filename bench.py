@@ -58,6 +58,7 @@ def parse():
     p.add_argument("--rms", default="on", choices=["on", "off"])
     p.add_argument("--step", default="on", choices=["on", "off"])
     p.add_argument("--tangent", default="on", choices=["on", "off"])
+    p.add_argument("--large", default="on", choices=["on", "off"])
     return p.parse_args()
 
 
@@ -166,6 +167,43 @@ def tangent_bench(wl, b, reps=3):
     g = StokesIB(wl, precision="fp64")
     out["ib_row_entries_linear"] = sum(lv["ib_nnz"] for lv in g.stats()["levels"])
     g.close()
+    return out
+
+
+def large_bench(reps=20):
+    """The grid and coupling kernels where their data cannot stay in the
+    caches: a 4096^2 periodic grid (fields of 400 MB), FP64, with 2^20 points
+    and no springs, in two layouts: a suspension of 32 x 32 membranes of
+    1024 points each (radius 0.35/32, points in fibre order, as the paper's
+    structures come) and the same count scattered uniformly (seed 7, no
+    spatial order: the worst case for the point gathers).  Stencil,
+    restriction and prolongation on the finest level, spreading and
+    interpolation of all points; algorithmic bytes as for the main
+    workload."""
+    import torch
+    import workloads as W
+    from paper_1612_02208_amd import StokesIB
+    N, M = 4096, 1 << 20
+    out = {}
+    layouts = (("suspension", W.suspension_points(32, 0.35 / 32, 1024)), ("uniform_random", W.random_points(M, 7)))
+    for tag, X in layouts:
+        wl = W.Workload(f"grid_{N}_{tag}", N, 8, 1.0, 1e-2, 5e-4, X, np.zeros((0, 2), dtype=np.int32),
+                        np.zeros(0), box=8, overlap=2)
+        t0 = time.perf_counter()
+        g = StokesIB(wl, precision="fp64")
+        rec = {"workload": f"{N}x{N} periodic grid, {X.shape[0]} points ({tag.replace('_', ' ')}), "
+                           f"no springs, FP64", "setup_s": time.perf_counter() - t0}
+        kinds = (("stencil", "k_apply<double>"), ("restrict", "k_restrict<double>"),
+                 ("prolong", "k_prolong_add<double>"), ("spread", "k_spread"), ("interp", "k_interp_lanes<double>"))
+        for kind, name in kinds:
+            if tag != "suspension" and kind in ("stencil", "restrict", "prolong"):
+                continue   # the grid kernels do not see the points
+            t = g.kernel_time(kind, -1, reps)
+            rec[name] = {"bound": "hbm", "avg_ms": t["ms"], "alg_bytes": t["bytes"],
+                         "gbs": t["bytes"] / t["ms"] / 1e6, "frac": t["bytes"] / t["ms"] / 1e6 / HBM_PEAK_GBS}
+        g.close()
+        out[tag] = rec
+    torch.cuda.synchronize()
     return out
 
 
@@ -336,6 +374,15 @@ def main():
         kernels[f"k_apply<{tag}>"] = {"bound": "hbm", "avg_ms": sc["ms"], "alg_bytes": sc["bytes"],
                                       "gbs": sc["bytes"] / sc["ms"] / 1e6,
                                       "frac": sc["bytes"] / sc["ms"] / 1e6 / HBM_PEAK_GBS}
+        # grid transfers on the finest level; spreading and interpolation (FP64
+        # on both handles, so timed once)
+        names = [("restrict", f"k_restrict<{tag}>"), ("prolong", f"k_prolong_add<{tag}>")]
+        if tag == "double":
+            names += [("spread", "k_spread"), ("interp", "k_interp_lanes<double>")]
+        for kind, name in names:
+            t = g.kernel_time(kind, -1, a.roofline_reps)
+            kernels[name] = {"bound": "hbm", "avg_ms": t["ms"], "alg_bytes": t["bytes"],
+                             "gbs": t["bytes"] / t["ms"] / 1e6, "frac": t["bytes"] / t["ms"] / 1e6 / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC,
@@ -382,6 +429,10 @@ def main():
         t0 = time.perf_counter()
         out["tangent_fp64_fp32"] = tangent_bench(wl, b)
         print(f"[bench] tangent springs {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    if a.large == "on":
+        t0 = time.perf_counter()
+        out["kernels_large_grid"] = large_bench()
+        print(f"[bench] large-grid kernels {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if a.batch == "on":
         t0 = time.perf_counter()
         out["batch"] = batch_bench(dev)

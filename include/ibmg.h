@@ -257,12 +257,26 @@ ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32
  *                             values
  *   IBMG_KERNEL_RAS_BATCH     (batch handles) the persistent batched Schwarz
  *                             launch of a level with its tuned plan
+ *   IBMG_KERNEL_RESTRICT      restriction from `level` (>= 1) to the next
+ *                             coarser level: 3 n_f^2 + 3 n_c^2 values
+ *   IBMG_KERNEL_PROLONG       prolongation from the next coarser level added
+ *                             into `level` (>= 1): 3 n_c^2 + 2 (3 n_f^2) values
+ *   IBMG_KERNEL_SPREAD        spreading on the finest level (FP64): every
+ *                             (point, slot) entry's weight and index, the face
+ *                             list offsets, 2 M forces, 2 N^2 faces written
+ *   IBMG_KERNEL_INTERP        interpolation on the finest level (FP64): 2 M x 16
+ *                             weights, the window bases, every face some
+ *                             window touches, 2 M values written
  * Synchronises ``stream``; IBMG_ERR_ARG if the level has no such work. */
 typedef enum {
   IBMG_KERNEL_RAS_IB = 0,
   IBMG_KERNEL_RAS_INTERIOR = 1,
   IBMG_KERNEL_STENCIL = 2,
-  IBMG_KERNEL_RAS_BATCH = 3
+  IBMG_KERNEL_RAS_BATCH = 3,
+  IBMG_KERNEL_RESTRICT = 4,
+  IBMG_KERNEL_PROLONG = 5,
+  IBMG_KERNEL_SPREAD = 6,
+  IBMG_KERNEL_INTERP = 7
 } ibmg_kernel;
 ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int32_t reps,
                              ibmg_stream stream, double* avg_ms, double* alg_bytes,

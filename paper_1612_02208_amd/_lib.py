@@ -56,6 +56,7 @@ EXPORTS = [
 ]
 
 KERNEL_RAS_IB, KERNEL_RAS_INTERIOR, KERNEL_STENCIL, KERNEL_RAS_BATCH = 0, 1, 2, 3
+KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_SPREAD, KERNEL_INTERP = 4, 5, 6, 7
 
 _lib = None
 

@@ -8,8 +8,9 @@ namespace ibmg {
 static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
-// L_IB w (or its transpose, or the residual b - L_IB w).  One thread per
-// (i, j) computes the x-face, y-face and cell rows of that index:
+// L_IB w (or its transpose, or the residual b - L_IB w).  A thread computes
+// the x-face, y-face and cell rows of the indices (i, j) of its rows of one
+// column:
 //   y_u = alpha u - mu Lap u + (p_ij - p_{i-1,j}) / h + dt/h^2 (J^T K' J u)
 //   y_v = alpha v - mu Lap v + (p_ij - p_{i,j-1}) / h + dt/h^2 (J^T K' J v)
 //   y_p = -(u_{i+1,j} - u_ij + v_{i,j+1} - v_ij) / h
@@ -18,94 +19,119 @@ static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 // The transposed form evaluates -D^T p and G^T u directly; the IB block is
 // the same J^T K' J chain with J standing in for S^T (S = J^* / h^2).
 // ---------------------------------------------------------------------------
-template <typename T, bool TRANS, bool RESID, int IBM>
-__device__ __forceinline__ void apply_point(const T* __restrict__ w, T* __restrict__ y, const T* __restrict__ b,
+// Rows per thread: grids below 2048 keep one point per thread (their fields
+// stay in the caches, and more waves hide the latency); larger grids march
+// four rows per thread with the vertical neighbours carried in registers and
+// store with non-temporal hints (fields of 100 MB and more do not stay in
+// cache), which brings the stencil close to the rate of a plain copy.
+constexpr int kStripMinN = 2048;
+static inline int apply_rows(int N) { return N >= kStripMinN ? 4 : 1; }
+// work-group shape: 64 x 4 points for one row per thread, a 256-wide run of
+// one row's columns for the marching form
+static inline dim3 apply_block(int rows) { return rows > 1 ? dim3(256, 1) : dim3(64, 4); }
+
+template <int RJ, typename T>
+__device__ __forceinline__ void store_out(T* p, T v) {
+  if constexpr (RJ > 1) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Rows j0 .. j0+RJ-1 (those below N) of column i; emit(c0, y_u, y_v, y_p)
+// receives each point's three rows.
+template <typename T, bool TRANS, bool RESID, int IBM, int RJ, typename Emit>
+__device__ __forceinline__ void apply_strip(const T* __restrict__ w, const T* __restrict__ b,
                                             const T* __restrict__ F, const T* __restrict__ Gib,
                                             const FootView<T>& fx, const FootView<T>& fy, int N, int M,
-                                            const StokesCoef<T>& c, int i, int j, T out[3]) {
+                                            const StokesCoef<T>& c, int i, int j0, Emit emit) {
   const size_t n = (size_t)N * N;
   const T* u = w;
   const T* v = w + n;
   const T* p = w + 2 * n;
   const int im = i == 0 ? N - 1 : i - 1;
   const int ip = i == N - 1 ? 0 : i + 1;
-  const int jm = j == 0 ? N - 1 : j - 1;
-  const int jp = j == N - 1 ? 0 : j + 1;
-  const size_t c0 = (size_t)j * N + i;
-  const size_t cl = (size_t)j * N + im, cr = (size_t)j * N + ip;
-  const size_t cd = (size_t)jm * N + i, ct = (size_t)jp * N + i;
-  const T uc = u[c0], ul = u[cl], ur = u[cr], ud = u[cd], ut = u[ct];
-  const T vc = v[c0], vl = v[cl], vr = v[cr], vd = v[cd], vt = v[ct];
-  const T pc = p[c0], pl = p[cl], pd = p[cd];
-  T ibu = 0, ibv = 0;
-  if (IBM == 2) {
-    ibu = Gib[c0];
-    ibv = Gib[n + c0];
-  } else if (IBM == 1) {
-    const int a0 = fx.sp_ptr[c0], a1 = fx.sp_ptr[c0 + 1];
-    for (int e = a0; e < a1; ++e) {
-      const int ent = fx.sp_ent[e];
-      ibu += fx.w[ent] * F[ent >> 4];
-    }
-    const int b0 = fy.sp_ptr[c0], b1 = fy.sp_ptr[c0 + 1];
-    for (int e = b0; e < b1; ++e) {
-      const int ent = fy.sp_ent[e];
-      ibv += fy.w[ent] * F[M + (ent >> 4)];
-    }
-  }
+  const int jm0 = j0 == 0 ? N - 1 : j0 - 1;
+  T ud = u[(size_t)jm0 * N + i], vd = v[(size_t)jm0 * N + i], pd = p[(size_t)jm0 * N + i];
+  T uc = u[(size_t)j0 * N + i], vc = v[(size_t)j0 * N + i], pc = p[(size_t)j0 * N + i];
   // the precomputed Galerkin rows already carry the factor dt/h^2
   const T ibs = IBM == 2 ? T(1) : c.ibs;
-  const T lapu = ul + ur + ud + ut - T(4) * uc;
-  const T lapv = vl + vr + vd + vt - T(4) * vc;
-  T yu, yv, yp;
-  if (!TRANS) {
-    yu = c.alpha * uc - c.beta * lapu + c.gi * (pc - pl) + ibs * ibu;
-    yv = c.alpha * vc - c.beta * lapv + c.gi * (pc - pd) + ibs * ibv;
-    yp = -c.gi * (ur - uc + vt - vc);
-  } else {
-    // (-D^T p) on the x-face (i, j): D maps the face to cells (i, j) with -1/h
-    // and (i-1, j) with +1/h.  G^T u on cell (i, j): G maps the cell to faces
-    // (i, j) with +1/h and (i+1, j) with -1/h (likewise in y).
-    yu = c.alpha * uc - c.beta * lapu - c.gi * (pl - pc) + ibs * ibu;
-    yv = c.alpha * vc - c.beta * lapv - c.gi * (pd - pc) + ibs * ibv;
-    yp = c.gi * (uc - ur + vc - vt);
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    const int j = j0 + r;
+    if (j >= N) break;
+    const int jp = j == N - 1 ? 0 : j + 1;
+    const size_t row = (size_t)j * N, c0 = row + i;
+    const size_t ct = (size_t)jp * N + i;
+    const T ut = u[ct], vt = v[ct];
+    const T ul = u[row + im], ur = u[row + ip], vl = v[row + im], vr = v[row + ip], pl = p[row + im];
+    T ibu = 0, ibv = 0;
+    if (IBM == 2) {
+      ibu = Gib[c0];
+      ibv = Gib[n + c0];
+    } else if (IBM == 1) {
+      const int a0 = fx.sp_ptr[c0], a1 = fx.sp_ptr[c0 + 1];
+      for (int e = a0; e < a1; ++e) ibu += fx.sw[e] * F[fx.sp_ent[e] >> 4];
+      const int b0 = fy.sp_ptr[c0], b1 = fy.sp_ptr[c0 + 1];
+      for (int e = b0; e < b1; ++e) ibv += fy.sw[e] * F[M + (fy.sp_ent[e] >> 4)];
+    }
+    const T lapu = ul + ur + ud + ut - T(4) * uc;
+    const T lapv = vl + vr + vd + vt - T(4) * vc;
+    T yu, yv, yp;
+    if (!TRANS) {
+      yu = c.alpha * uc - c.beta * lapu + c.gi * (pc - pl) + ibs * ibu;
+      yv = c.alpha * vc - c.beta * lapv + c.gi * (pc - pd) + ibs * ibv;
+      yp = -c.gi * (ur - uc + vt - vc);
+    } else {
+      // (-D^T p) on the x-face (i, j): D maps the face to cells (i, j) with -1/h
+      // and (i-1, j) with +1/h.  G^T u on cell (i, j): G maps the cell to faces
+      // (i, j) with +1/h and (i+1, j) with -1/h (likewise in y).
+      yu = c.alpha * uc - c.beta * lapu - c.gi * (pl - pc) + ibs * ibu;
+      yv = c.alpha * vc - c.beta * lapv - c.gi * (pd - pc) + ibs * ibv;
+      yp = c.gi * (uc - ur + vc - vt);
+    }
+    if (RESID) {
+      yu = b[c0] - yu;
+      yv = b[n + c0] - yv;
+      yp = b[2 * n + c0] - yp;
+    }
+    emit(c0, yu, yv, yp);
+    if (r + 1 < RJ) {
+      ud = uc;
+      vd = vc;
+      pd = pc;
+      uc = ut;
+      vc = vt;
+      pc = p[ct];
+    }
   }
-  if (RESID) {
-    yu = b[c0] - yu;
-    yv = b[n + c0] - yv;
-    yp = b[2 * n + c0] - yp;
-  }
-  y[c0] = yu;
-  y[n + c0] = yv;
-  y[2 * n + c0] = yp;
-  out[0] = yu;
-  out[1] = yv;
-  out[2] = yp;
 }
 
-template <typename T, bool TRANS, bool RESID, int IBM>
+template <typename T, bool TRANS, bool RESID, int IBM, int RJ>
 __global__ void __launch_bounds__(256) k_apply(const T* __restrict__ w, T* __restrict__ y,
                                                const T* __restrict__ b, const T* __restrict__ F,
                                                const T* __restrict__ Gib, FootView<T> fx,
                                                FootView<T> fy, int N, int M, StokesCoef<T> c,
                                                size_t bs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
+  const int j0 = (blockIdx.y * blockDim.y + threadIdx.y) * RJ;
+  if (i >= N || j0 >= N) return;
   // batched launches: system blockIdx.z, systems bs apart
   w += blockIdx.z * bs;
   y += blockIdx.z * bs;
   if (RESID) b += blockIdx.z * bs;
-  T out[3];
-  apply_point<T, TRANS, RESID, IBM>(w, y, b, F, Gib, fx, fy, N, M, c, i, j, out);
+  const size_t n = (size_t)N * N;
+  apply_strip<T, TRANS, RESID, IBM, RJ>(w, b, F, Gib, fx, fy, N, M, c, i, j0, [&](size_t c0, T yu, T yv, T yp) {
+    store_out<RJ>(y + c0, yu);
+    store_out<RJ>(y + n + c0, yv);
+    store_out<RJ>(y + 2 * n + c0, yp);
+  });
 }
 
 // The same (non-transposed) with the first Gram-Schmidt dot products fused:
 // partial[blk * nvec + q] = this block's sum of V_q . y over its rows
-// (V = null: nvec = 1 and the sum of y . y), reduced over the block's four
-// waves by shuffles and shared memory in a fixed order; blk = the block's
-// linear index.
-template <typename T, bool RESID, int IBM>
+// (V = null: nvec = 1 and the sum of y . y), each thread's points summed in
+// row order, then reduced over the block's four waves by shuffles and shared
+// memory in a fixed order; blk = the block's linear index.
+template <typename T, bool RESID, int IBM, int RJ>
 __global__ void __launch_bounds__(256) k_apply_dots(const T* __restrict__ w, T* __restrict__ y,
                                                     const T* __restrict__ b, const T* __restrict__ F,
                                                     const T* __restrict__ Gib, FootView<T> fx, FootView<T> fy,
@@ -113,27 +139,36 @@ __global__ void __launch_bounds__(256) k_apply_dots(const T* __restrict__ w, T* 
                                                     int nvec, size_t vstride, double* __restrict__ partial) {
   __shared__ double red[9][4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const bool live = i < N && j < N;
+  const int j0 = (blockIdx.y * blockDim.y + threadIdx.y) * RJ;
+  const bool live = i < N && j0 < N;
   const size_t n = (size_t)N * N;
-  T out[3] = {0, 0, 0};
-  if (live) apply_point<T, false, RESID, IBM>(w, y, b, F, Gib, fx, fy, N, M, c, i, j, out);
-  const size_t c0 = (size_t)j * N + i;
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int q = 0; q < nvec; ++q) {
-    double d = 0.0;
-    if (live) {
-      if (V) {
-        const T* vq = V + (size_t)q * vstride;
-        d = (double)vq[c0] * (double)out[0] + (double)vq[n + c0] * (double)out[1] +
-            (double)vq[2 * n + c0] * (double)out[2];
-      } else {
-        d = (double)out[0] * (double)out[0] + (double)out[1] * (double)out[1] + (double)out[2] * (double)out[2];
-      }
-    }
+  double d[9];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-    if (lane == 0) red[q][wave] = d;
+  for (int q = 0; q < 9; ++q) d[q] = 0.0;
+  if (live)
+    apply_strip<T, false, RESID, IBM, RJ>(w, b, F, Gib, fx, fy, N, M, c, i, j0, [&](size_t c0, T yu, T yv, T yp) {
+      store_out<RJ>(y + c0, yu);
+      store_out<RJ>(y + n + c0, yv);
+      store_out<RJ>(y + 2 * n + c0, yp);
+      if (V) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+          if (q < nvec) {
+            const T* vq = V + (size_t)q * vstride;
+            d[q] += (double)vq[c0] * (double)yu + (double)vq[n + c0] * (double)yv + (double)vq[2 * n + c0] * (double)yp;
+          }
+      } else {
+        d[0] += (double)yu * (double)yu + (double)yv * (double)yv + (double)yp * (double)yp;
+      }
+    });
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    if (q >= nvec) break;
+    double a = d[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane == 0) red[q][wave] = a;
   }
   __syncthreads();
   if (tid < nvec)
@@ -142,24 +177,32 @@ __global__ void __launch_bounds__(256) k_apply_dots(const T* __restrict__ w, T* 
 }
 
 
+template <typename T, int IBM, int RJ>
+static void launch_apply_r(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+                           FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose,
+                           hipStream_t s, int nsys, size_t bs) {
+  const dim3 blk = apply_block(RJ);
+  dim3 grd((N + blk.x - 1) / blk.x, (N + blk.y * RJ - 1) / (blk.y * RJ), nsys);
+  if (b) {
+    if (transpose)
+      hipLaunchKernelGGL((k_apply<T, true, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+    else
+      hipLaunchKernelGGL((k_apply<T, false, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+  } else {
+    if (transpose)
+      hipLaunchKernelGGL((k_apply<T, true, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+    else
+      hipLaunchKernelGGL((k_apply<T, false, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+  }
+  IBMG_LAUNCH_CHECK();
+}
+
 template <typename T, int IBM>
 static void launch_apply_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
                            FootView<T> fy, int N, int M, StokesCoef<T> c, bool transpose,
                            hipStream_t s, int nsys = 1, size_t bs = 0) {
-  dim3 blk(64, 4);
-  dim3 grd((N + 63) / 64, (N + 3) / 4, nsys);
-  if (b) {
-    if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
-    else
-      hipLaunchKernelGGL((k_apply<T, false, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
-  } else {
-    if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
-    else
-      hipLaunchKernelGGL((k_apply<T, false, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
-  }
-  IBMG_LAUNCH_CHECK();
+  if (apply_rows(N) == 4) launch_apply_r<T, IBM, 4>(w, y, b, F, G, fx, fy, N, M, c, transpose, s, nsys, bs);
+  else launch_apply_r<T, IBM, 1>(w, y, b, F, G, fx, fy, N, M, c, transpose, s, nsys, bs);
 }
 
 // IB source: G (precomputed dt/h^2 J^T K' J u rows) if non-null, else the
@@ -175,22 +218,35 @@ void launch_apply(const T* w, T* y, const T* b, const T* F, const T* G, FootView
     launch_apply_m<T, 0>(w, y, b, F, G, fx, fy, N, M, c, transpose, s);
 }
 
-template <typename T, int IBM>
-static void launch_apply_dots_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+template <typename T, int IBM, int RJ>
+static void launch_apply_dots_r(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
                                 FootView<T> fy, int N, int M, StokesCoef<T> c, const T* V, int nvec,
                                 size_t vstride, double* partial, hipStream_t s) {
-  dim3 blk(64, 4);
-  dim3 grd((N + 63) / 64, (N + 3) / 4);
+  const dim3 blk = apply_block(RJ);
+  dim3 grd((N + blk.x - 1) / blk.x, (N + blk.y * RJ - 1) / (blk.y * RJ));
   if (b)
-    hipLaunchKernelGGL((k_apply_dots<T, true, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
+    hipLaunchKernelGGL((k_apply_dots<T, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
                        vstride, partial);
   else
-    hipLaunchKernelGGL((k_apply_dots<T, false, IBM>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
+    hipLaunchKernelGGL((k_apply_dots<T, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
                        vstride, partial);
   IBMG_LAUNCH_CHECK();
 }
 
-int apply_blocks(int N) { return ((N + 63) / 64) * ((N + 3) / 4); }
+template <typename T, int IBM>
+static void launch_apply_dots_m(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx,
+                                FootView<T> fy, int N, int M, StokesCoef<T> c, const T* V, int nvec,
+                                size_t vstride, double* partial, hipStream_t s) {
+  if (apply_rows(N) == 4) launch_apply_dots_r<T, IBM, 4>(w, y, b, F, G, fx, fy, N, M, c, V, nvec, vstride, partial, s);
+  else launch_apply_dots_r<T, IBM, 1>(w, y, b, F, G, fx, fy, N, M, c, V, nvec, vstride, partial, s);
+}
+
+int apply_blocks(int N) {
+  const int rj = apply_rows(N);
+  const dim3 blk = apply_block(rj);
+  const int rows = (int)blk.y * rj;
+  return ((N + (int)blk.x - 1) / (int)blk.x) * ((N + rows - 1) / rows);
+}
 
 template <typename T>
 void launch_apply_dots(const T* w, T* y, const T* b, const T* F, const T* G, FootView<T> fx, FootView<T> fy,
@@ -211,7 +267,7 @@ template <typename T>
 void launch_apply_batch(const T* w, T* y, const T* b, int N, StokesCoef<T> c, int nsys, size_t bs,
                         hipStream_t s) {
   if (nsys <= 0) return;
-  FootView<T> none{nullptr, nullptr, nullptr, nullptr};
+  FootView<T> none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   launch_apply_m<T, 0>(w, y, b, nullptr, nullptr, none, none, N, 0, c, false, s, nsys, bs);
 }
 

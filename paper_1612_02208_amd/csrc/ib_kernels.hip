@@ -100,6 +100,23 @@ __global__ void k_fp_coarsen(const int* __restrict__ fbase, const double* __rest
   for (int s = 0; s < 16; ++s) cw[(size_t)l * 16 + s] = acc[s];
 }
 
+template <typename T>
+__global__ void k_gather_weights(const double* __restrict__ w, const int* __restrict__ ent, size_t n,
+                                 T* __restrict__ sw) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    sw[e] = (T)w[ent[e]];
+}
+
+template <typename T>
+void launch_gather_weights(const double* w, const int* ent, size_t n, T* sw, hipStream_t s) {
+  if (!n) return;
+  const int g = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_gather_weights<T>), dim3(g), dim3(256), 0, s, w, ent, n, sw);
+  IBMG_LAUNCH_CHECK();
+}
+template void launch_gather_weights<double>(const double*, const int*, size_t, double*, hipStream_t);
+template void launch_gather_weights<float>(const double*, const int*, size_t, float*, hipStream_t);
+
 void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int M, int comp,
                        int Nf, int Nc, double* cw, hipStream_t s) {
   (void)Nf;
@@ -111,8 +128,9 @@ void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int
 
 // (J u)_l for every point and component: 16 lanes per (point, component),
 // lane s taking window slot s (masked slots carry weight 0), the lanes' terms
-// summed by shuffles in a fixed order.  Output planar U[comp * M + l] or
-// interleaved U[2 l + comp].
+// summed by shuffles in a fixed order.  Points are taken in cell order
+// (f.order), so neighbouring lane groups read neighbouring faces.  Output
+// planar U[comp * M + l] or interleaved U[2 l + comp].
 template <typename T>
 __global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, const T* __restrict__ v,
                                                       FootView<T> fx, FootView<T> fy, int M, int N,
@@ -121,7 +139,7 @@ __global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, c
   const int g = (int)(t / 16), s = (int)(t % 16);
   const bool live = g < 2 * M;
   const int comp = live && g >= M ? 1 : 0;
-  const int l = live ? g - comp * M : 0;
+  const int l = live ? fx.order[g - comp * M] : 0;
   T a = 0;
   if (live) {
     const FootView<T>& f = comp ? fy : fx;
@@ -258,14 +276,8 @@ __global__ void k_spread(const double* __restrict__ F, FootView<double> fx, Foot
   if (i >= N || j >= N) return;
   const size_t c0 = (size_t)j * N + i;
   double a = 0, b = 0;
-  for (int e = fx.sp_ptr[c0]; e < fx.sp_ptr[c0 + 1]; ++e) {
-    const int ent = fx.sp_ent[e];
-    a += fx.w[ent] * F[2 * (ent >> 4)];
-  }
-  for (int e = fy.sp_ptr[c0]; e < fy.sp_ptr[c0 + 1]; ++e) {
-    const int ent = fy.sp_ent[e];
-    b += fy.w[ent] * F[2 * (ent >> 4) + 1];
-  }
+  for (int e = fx.sp_ptr[c0]; e < fx.sp_ptr[c0 + 1]; ++e) a += fx.sw[e] * F[2 * (fx.sp_ent[e] >> 4)];
+  for (int e = fy.sp_ptr[c0]; e < fy.sp_ptr[c0 + 1]; ++e) b += fy.sw[e] * F[2 * (fy.sp_ent[e] >> 4) + 1];
   f[c0] = scale * a;
   f[(size_t)N * N + c0] = scale * b;
 }
@@ -333,9 +345,8 @@ __global__ void __launch_bounds__(256) k_t_values(FootView<double> f0, FootView<
     const int* mc = c ? mask1 : mask0;
     double acc = 0.0;
     for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
-      const int ent = f.sp_ent[e];
-      const int l = ent >> 4;
-      const double wl_r = f.w[ent];
+      const int l = f.sp_ent[e] >> 4;
+      const double wl_r = f.sw[e];
       const int a0 = sv.adj_ptr[l], a1 = sv.adj_ptr[l + 1];
       if (a0 == a1) continue;
       const double wl_c = window_weight(fc, mc, l, ci, cj, N);

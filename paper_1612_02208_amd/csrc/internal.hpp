@@ -86,6 +86,8 @@ struct FootView {       // one component of one level
   const T* w;           // [M][16] weights
   const int* sp_ptr;    // [n*n + 1] faces -> entries
   const int* sp_ent;    // entries l*16 + slot
+  const T* sw;          // weights in face-list order: sw[e] = w[sp_ent[e]]
+  const int* order;     // [M] points in cell order (point-wise kernels walk it)
 };
 
 template <typename T>
@@ -207,6 +209,9 @@ void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const d
 // immersed boundary
 void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
                     double* w, hipStream_t s);
+// sw[e] = w[ent[e]] for n entries (face-ordered copy of the weights)
+template <typename T>
+void launch_gather_weights(const double* w, const int* ent, size_t n, T* sw, hipStream_t s);
 void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int M, int comp,
                        int Nf, int Nc, double* cw, hipStream_t s);
 template <typename T>

@@ -13,6 +13,8 @@ struct CompFoot {             // one velocity component on one level
   DBuf<int> d_base, d_mask, d_sp_ptr, d_sp_ent, d_tptr, d_tcol;
   DBuf<double> w;             // [M][16]
   DBuf<float> wf;             // FP32 copy for the FP32 smoother
+  DBuf<double> sw;            // weights in face-list order
+  DBuf<float> swf;            // FP32 copy
   DBuf<double> tval;
   DBuf<float> tvalf;          // FP32 copy for the FP32 smoother
   int max_list = 0;           // longest face -> point list

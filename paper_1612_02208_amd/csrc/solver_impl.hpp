@@ -7,6 +7,7 @@
 
 #include <atomic>
 #include <map>
+#include <numeric>
 #include <thread>
 #include <algorithm>
 #include <chrono>
@@ -182,6 +183,13 @@ class Solver final : public SolverBase {
         spread_lists(lev.N, f);
         f.d_sp_ptr.upload(f.sp_ptr, s);
         f.d_sp_ent.upload(f.sp_ent, s);
+        f.sw.alloc(std::max<size_t>(f.sp_ent.size(), 1));
+        launch_gather_weights<double>(f.w.p, f.d_sp_ent.p, f.sp_ent.size(), f.sw.p, s);
+        if (std::is_same<T, float>::value) {
+          f.swf.alloc(std::max<size_t>(f.sp_ent.size(), 1));
+          launch_gather_weights<float>(f.w.p, f.d_sp_ent.p, f.sp_ent.size(), f.swf.p, s);
+        }
+        if (l == L_ && c == 0) point_order(lev.N, f, s);
       }
       for (int c = 0; c < 2; ++c) {  // IB rows need both components' windows
         CompFoot& f = lev.f[c];
@@ -199,6 +207,19 @@ class Solver final : public SolverBase {
       if (l >= 1 && d_.smoother == IBMG_RMS) colour_boxes(lev);
       if (l >= 1 && d_.smoother == IBMG_SC) sc_structure(lev, s);
     }
+  }
+
+  // Points in cell order (row-major by the finest x-window base, ties in
+  // index order), the order in which the point-wise kernels walk them.
+  void point_order(int N, const CompFoot& f, hipStream_t s) {
+    std::vector<int> ord(std::max(M_, 1), 0);
+    std::iota(ord.begin(), ord.begin() + M_, 0);
+    std::stable_sort(ord.begin(), ord.begin() + M_, [&](int a, int b) {
+      const long long ka = (long long)f.base[2 * a + 1] * N + f.base[2 * a];
+      const long long kb = (long long)f.base[2 * b + 1] * N + f.base[2 * b];
+      return ka < kb;
+    });
+    d_order_.upload(ord, s);
   }
 
   // Finest windows: t = X N - shift, i0 = floor(t) - 1, slots with |t - k| < 2.
@@ -852,9 +873,9 @@ class Solver final : public SolverBase {
   template <typename U>
   FootView<U> fview(CompFoot& f) {
     if constexpr (std::is_same<U, double>::value)
-      return FootView<double>{f.d_base.p, f.w.p, f.d_sp_ptr.p, f.d_sp_ent.p};
+      return FootView<double>{f.d_base.p, f.w.p, f.d_sp_ptr.p, f.d_sp_ent.p, f.sw.p, d_order_.p};
     else
-      return FootView<float>{f.d_base.p, f.wf.p, f.d_sp_ptr.p, f.d_sp_ent.p};
+      return FootView<float>{f.d_base.p, f.wf.p, f.d_sp_ptr.p, f.d_sp_ent.p, f.swf.p, d_order_.p};
   }
   template <typename U>
   SpringView<U> sview() {
@@ -1388,6 +1409,43 @@ class Solver final : public SolverBase {
         launch_apply<T>(lev.r.p, lev.t.p, nullptr, nullptr, nullptr, fview<T>(lev.f[0]), fview<T>(lev.f[1]), lev.N,
                         M_, coef<T>(lev), false, s);
       }, reps, s);
+    } else if (kernel == IBMG_KERNEL_RESTRICT || kernel == IBMG_KERNEL_PROLONG) {
+      require(level >= 1, "transfers need a level >= 1");
+      Level<T>& cl = levels_[level - 1];
+      const size_t nc = 3 * (size_t)cl.N * cl.N;
+      if (kernel == IBMG_KERNEL_RESTRICT) {
+        by = (double)(n + nc) * ts;
+        ms = time_launches([&] { launch_restrict<T>(lev.r.p, cl.t.p, cl.N, s); }, reps, s);
+      } else {
+        by = (double)(nc + 2 * n) * ts;
+        launch_fill<T>(cl.r.p, T(1), nc, s);
+        ms = time_launches([&] { launch_prolong_add<T>(cl.r.p, lev.t.p, cl.N, s); }, reps, s);
+      }
+    } else if (kernel == IBMG_KERNEL_SPREAD || kernel == IBMG_KERNEL_INTERP) {
+      require(level == L_, "spreading and interpolation run on the finest level");
+      require(M_ > 0, "the structure has no points");
+      const size_t nn = (size_t)lev.N * lev.N;
+      if (fs_.n < 2 * nn) fs_.alloc(2 * nn);
+      launch_fill<double>(fs_.p, 1.0, 2 * nn, s);
+      launch_fill<double>(Fd_.p, 1.0, 2 * (size_t)M_, s);
+      size_t ents = 0, touched = 0;
+      for (int c = 0; c < 2; ++c) {
+        ents += lev.f[c].sp_ent.size();
+        for (size_t r = 0; r < nn; ++r) touched += lev.f[c].sp_ptr[r + 1] > lev.f[c].sp_ptr[r];
+      }
+      const double h = 1.0 / lev.N;
+      if (kernel == IBMG_KERNEL_SPREAD) {
+        by = (double)ents * 12.0 + (double)(2 * (nn + 1)) * 4.0 + 2.0 * M_ * 8.0 + 2.0 * nn * 8.0;
+        ms = time_launches([&] {
+          launch_spread(Fd_.p, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, 1.0 / (h * h), fs_.p, s);
+        }, reps, s);
+      } else {
+        by = 2.0 * M_ * 16 * 8.0 + 2.0 * M_ * 2 * 4.0 + (double)touched * 8.0 + 2.0 * M_ * 8.0;
+        ms = time_launches([&] {
+          launch_interp<double>(fs_.p, fs_.p + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N,
+                                Uw_.p, s);
+        }, reps, s);
+      }
     } else {
       require(false, "unknown kernel");
     }
@@ -1419,6 +1477,7 @@ class Solver final : public SolverBase {
   std::vector<int> ends_, sizes_;
   std::vector<int> adj_ptr_, adj_nbr_, adj_sid_;
   DBuf<int> d_adj_ptr_, d_adj_nbr_, d_ends_;
+  DBuf<int> d_order_;   // points in cell order
   DBuf<double> d_adj_k_, d_X_;
   DBuf<float> d_adj_kf_;
   // tangent model: (K_e[0][1], K_e[1][1]) per incidence, kappa_e and L_e per

@@ -35,9 +35,13 @@ def main():
     wl.box, wl.overlap = a.box, a.overlap
     g = StokesIB(wl, precision=a.precision)
     suffix = "<double>" if a.precision == "fp64" else "<float>"
-    for kern, name in (("ras_ib", "k_ras_ib"), ("ras_interior", "k_ras_interior"), ("stencil", "k_apply")):
+    kinds = [("ras_ib", "k_ras_ib"), ("ras_interior", "k_ras_interior"), ("stencil", "k_apply"),
+             ("restrict", "k_restrict"), ("prolong", "k_prolong_add")]
+    if a.precision == "fp64":
+        kinds += [("spread", "k_spread"), ("interp", "k_interp_lanes")]
+    for kern, name in kinds:
         t = g.kernel_time(kern, -1, a.reps)
-        rec = dict(kernel=name + suffix, level=g.n_levels - 1, N=a.N, reps=a.reps, avg_ms=t["ms"],
+        rec = dict(kernel=name + ("" if kern == "spread" else suffix), level=g.n_levels - 1, N=a.N, reps=a.reps, avg_ms=t["ms"],
                    alg_bytes=t["bytes"], alg_flops=t["flops"], gbs=t["bytes"] / t["ms"] / 1e6,
                    tflops=t["flops"] / t["ms"] / 1e9)
         print(json.dumps(rec), flush=True)

@@ -268,10 +268,12 @@ class StokesIB:
     def kernel_time(self, kernel, level=-1, reps=50):
         """Average duration (ms) of one launch of a single library kernel on
         this handle's stream, with its algorithmic bytes and flops per launch.
-        kernel: "ras_ib", "ras_interior", "stencil" (single handles) or
-        "ras_batch" (batch handles)."""
+        kernel: "ras_ib", "ras_interior", "stencil", "restrict", "prolong",
+        "spread", "interp" (single handles) or "ras_batch" (batch handles)."""
         k = {"ras_ib": _lib.KERNEL_RAS_IB, "ras_interior": _lib.KERNEL_RAS_INTERIOR,
-             "stencil": _lib.KERNEL_STENCIL, "ras_batch": _lib.KERNEL_RAS_BATCH}[kernel]
+             "stencil": _lib.KERNEL_STENCIL, "ras_batch": _lib.KERNEL_RAS_BATCH,
+             "restrict": _lib.KERNEL_RESTRICT, "prolong": _lib.KERNEL_PROLONG,
+             "spread": _lib.KERNEL_SPREAD, "interp": _lib.KERNEL_INTERP}[kernel]
         ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._check(self.lib.ibmg_kernel_time(self.h, k, level % self.n_levels, int(reps), _stream(),
                                               ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)))

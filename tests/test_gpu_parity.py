@@ -270,3 +270,31 @@ def test_single_kernel_timing_every_level(pair):
     r = np.random.default_rng(12).uniform(-1, 1, P.levels[-1].n)
     z = host(G.smoother_apply(-1, dev(r)))
     assert rel(z, P.mg.smoothers[-1](r)) < SOLVE_TOL
+
+
+def test_transfer_and_coupling_kernel_timing(pair):
+    """ibmg_kernel_time for the transfers on every level and for spreading
+    and interpolation on the finest: algorithmic bytes follow the grid sizes
+    and the structure's window entries, and the handle's results are
+    unchanged afterwards."""
+    wl, P, G = pair
+    for l in range(1, len(P.levels)):
+        nf, nc = P.levels[l].n, P.levels[l - 1].n
+        t = G.kernel_time("restrict", l, 2)
+        assert t["ms"] > 0 and t["bytes"] == 8.0 * (nf + nc)
+        t = G.kernel_time("prolong", l, 2)
+        assert t["ms"] > 0 and t["bytes"] == 8.0 * (nc + 2 * nf)
+    N, M = wl.N, wl.M
+    ents = sum(int(oib.interp_pattern(wl.X, N, c).nnz) for c in (0, 1))
+    t = G.kernel_time("spread", -1, 2)
+    assert t["ms"] > 0 and t["bytes"] == ents * 12.0 + 2 * (N * N + 1) * 4.0 + 2 * M * 8.0 + 2 * N * N * 8.0
+    touched = sum(int((oib.interp_pattern(wl.X, N, c).sum(0) > 0).sum()) for c in (0, 1))
+    t = G.kernel_time("interp", -1, 2)
+    assert t["ms"] > 0 and t["bytes"] == 2 * M * 16 * 8.0 + 2 * M * 2 * 4.0 + touched * 8.0 + 2 * M * 8.0
+    with pytest.raises(Exception):
+        G.kernel_time("restrict", 0, 1)
+    rng = np.random.default_rng(2)
+    F = rng.uniform(-1, 1, (wl.M, 2))
+    f = host(G.spread(dev(F.ravel())))
+    ref = np.concatenate([oib.spread_matrix(wl.X, N, c) @ F[:, c] for c in (0, 1)])
+    assert rel(f, ref) < OPS_TOL

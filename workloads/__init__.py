@@ -107,6 +107,19 @@ def rhs(N: int, seed: int) -> np.ndarray:
     return np.concatenate([bu, bv, bp])
 
 
+def suspension_points(n_side: int, radius: float, per_ring: int) -> np.ndarray:
+    """Points of a suspension of n_side x n_side circular membranes (the
+    layout of the paper's suspension test, Sec. 5.3, at any count): ring
+    (a, b) is centred at ((a + 1/2), (b + 1/2)) / n_side with the given
+    radius and per_ring equally spaced points; rings follow each other in
+    row-major order and each ring's points run along the fibre."""
+    out = []
+    for b_ in range(n_side):
+        for a_ in range(n_side):
+            out.append(ring(per_ring, radius, ((a_ + 0.5) / n_side, (b_ + 0.5) / n_side)))
+    return np.concatenate(out, 0)
+
+
 def random_points(M: int, seed: int) -> np.ndarray:
     g = np.random.default_rng(seed)
     return g.uniform(0.0, 1.0, (M, 2))
