@@ -126,17 +126,18 @@ void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int
   IBMG_LAUNCH_CHECK();
 }
 
-// (J u)_l for every point and component: 16 lanes per (point, component),
-// lane s taking window slot s (masked slots carry weight 0), the lanes' terms
-// summed by shuffles in a fixed order.  Points are taken in cell order
-// (f.order), so neighbouring lane groups read neighbouring faces.  Output
-// planar U[comp * M + l] or interleaved U[2 l + comp].
+// (J u)_l for every point and component: 4 lanes per (point, component),
+// lane b taking row b of the 4 x 4 window (its four weights are contiguous;
+// masked slots carry weight 0), the row sums added by shuffles in a fixed
+// order.  Points are taken in cell order (f.order), so neighbouring lane
+// groups read neighbouring faces.  Output planar U[comp * M + l] or
+// interleaved U[2 l + comp].
 template <typename T>
 __global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, const T* __restrict__ v,
                                                       FootView<T> fx, FootView<T> fy, int M, int N,
                                                       T* __restrict__ U, int interleaved) {
   const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int g = (int)(t / 16), s = (int)(t % 16);
+  const int g = (int)(t / 4), b = (int)(t % 4);
   const bool live = g < 2 * M;
   const int comp = live && g >= M ? 1 : 0;
   const int l = live ? fx.order[g - comp * M] : 0;
@@ -144,14 +145,16 @@ __global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, c
   if (live) {
     const FootView<T>& f = comp ? fy : fx;
     const T* src = comp ? v : u;
-    const int i = wrapi(f.base[2 * l] + (s & 3), N), j = wrapi(f.base[2 * l + 1] + (s >> 2), N);
-    a = f.w[(size_t)l * 16 + s] * src[(size_t)j * N + i];
-  }
+    const int i0 = f.base[2 * l];
+    const T* row = src + (size_t)wrapi(f.base[2 * l + 1] + b, N) * N;
+    const T* w = f.w + (size_t)l * 16 + 4 * b;
 #pragma unroll
-  for (int off = 8; off > 0; off >>= 1) a += __shfl_xor(a, off, 16);
-  if (live && s == 0) U[interleaved ? 2 * l + comp : comp * M + l] = a;
+    for (int q = 0; q < 4; ++q) a += w[q] * row[wrapi(i0 + q, N)];
+  }
+  a += __shfl_xor(a, 1, 4);
+  a += __shfl_xor(a, 2, 4);
+  if (live && b == 0) U[interleaved ? 2 * l + comp : comp * M + l] = a;
 }
-
 // F_l = sum over springs e at l of K_e (U_l - U_{other end}), from U = J u
 // (planar [2][M]); F is planar [2][M].  K_e = kappa_e I, or the tangent
 // block when sv.adj_k2 is set.
@@ -185,7 +188,7 @@ __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __r
 template <typename T>
 static void launch_interp_lanes(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
                                 int interleaved, hipStream_t s) {
-  hipLaunchKernelGGL((k_interp_lanes<T>), dim3(cdiv((size_t)2 * M * 16, 256)), dim3(256), 0, s, u, v, fx, fy, M, N,
+  hipLaunchKernelGGL((k_interp_lanes<T>), dim3(cdiv((size_t)2 * M * 4, 256)), dim3(256), 0, s, u, v, fx, fy, M, N,
                      U, interleaved);
   IBMG_LAUNCH_CHECK();
 }
@@ -269,25 +272,45 @@ void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s)
 }
 
 // f_face = scale * sum_(l, slot) w F_l, F interleaved [M][2]; f = [2][N][N].
-__global__ void k_spread(const double* __restrict__ F, FootView<double> fx, FootView<double> fy,
-                         int N, double scale, double* __restrict__ f) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
-  const size_t c0 = (size_t)j * N + i;
-  double a = 0, b = 0;
-  for (int e = fx.sp_ptr[c0]; e < fx.sp_ptr[c0 + 1]; ++e) a += fx.sw[e] * F[2 * (fx.sp_ent[e] >> 4)];
-  for (int e = fy.sp_ptr[c0]; e < fy.sp_ptr[c0 + 1]; ++e) b += fy.sw[e] * F[2 * (fy.sp_ent[e] >> 4) + 1];
-  f[c0] = scale * a;
-  f[(size_t)N * N + c0] = scale * b;
+// One work-group per 256 consecutive faces of one component: their
+// (point, slot) entries are contiguous in face order, so the work-group
+// forms the entries' terms w F_l in chunks through LDS (every thread, in
+// entry order, with coalesced reads of the weights and indices), and then
+// each thread adds its face's terms in list order.  Long lists near a
+// densely sampled structure are thereby spread over the work-group instead
+// of one thread, and every face's sum keeps a fixed order.
+constexpr int kSpreadTile = 256, kSpreadChunk = 2048;
+
+__global__ void __launch_bounds__(256) k_spread(const double* __restrict__ F, FootView<double> fx,
+                                                FootView<double> fy, int N, double scale, double* __restrict__ f) {
+  __shared__ double terms[kSpreadChunk];
+  const int comp = blockIdx.y;
+  const FootView<double>& fv = comp ? fy : fx;
+  const int nf = N * N;
+  const int f0 = blockIdx.x * kSpreadTile;
+  const int face = f0 + threadIdx.x;
+  const bool live = face < nf;
+  const int fend = f0 + kSpreadTile < nf ? f0 + kSpreadTile : nf;
+  const int e0 = fv.sp_ptr[f0], e1 = fv.sp_ptr[fend];
+  const int my_lo = live ? fv.sp_ptr[face] : e1, my_hi = live ? fv.sp_ptr[face + 1] : e1;
+  double a = 0.0;
+  for (int c0 = e0; c0 < e1; c0 += kSpreadChunk) {
+    const int c1 = c0 + kSpreadChunk < e1 ? c0 + kSpreadChunk : e1;
+    for (int e = c0 + (int)threadIdx.x; e < c1; e += kSpreadTile)
+      terms[e - c0] = fv.sw[e] * F[2 * (fv.sp_ent[e] >> 4) + comp];
+    __syncthreads();
+    const int lo = my_lo > c0 ? my_lo : c0, hi = my_hi < c1 ? my_hi : c1;
+    for (int e = lo; e < hi; ++e) a += terms[e - c0];
+    __syncthreads();
+  }
+  if (live) f[(size_t)comp * nf + face] = scale * a;
 }
 
 void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, int M, int N,
                    double scale, double* f, hipStream_t s) {
   (void)M;
-  dim3 blk(64, 4);
-  dim3 grd((N + 63) / 64, (N + 3) / 4);
-  hipLaunchKernelGGL(k_spread, grd, blk, 0, s, F, fx, fy, N, scale, f);
+  dim3 grd(cdiv((size_t)N * N, kSpreadTile), 2);
+  hipLaunchKernelGGL(k_spread, grd, dim3(kSpreadTile), 0, s, F, fx, fy, N, scale, f);
   IBMG_LAUNCH_CHECK();
 }
 
