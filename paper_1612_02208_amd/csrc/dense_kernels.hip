@@ -823,10 +823,122 @@ int ras_interior_ksplit(const BoxGeom& g, int n_int) {
   return ks;
 }
 
+// ---------------------------------------------------------------------------
+// Interior product on gathered operands: the boxes' local residuals are
+// gathered once into X[k][box] (nloc x nbp, boxes padded to 128), then
+// Z = M X runs as 64-row x 128-box tiles on the matrix cores: four waves of
+// 2 x 4 16x16x4 tiles, the reduction staged through LDS 32 indices at a time.
+// The reduction slices and the order of each output's MFMA steps are those
+// of the tile kernels above, so the results are the same.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_int_gather(const T* __restrict__ r, T* __restrict__ X, BoxGeom g,
+                                                    const int* __restrict__ boxes, int nlist, int nbp,
+                                                    const int* __restrict__ loc_tab) {
+  const int N = g.N;
+  const size_t nn = (size_t)N * N, tot = (size_t)g.nloc * nbp;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t / nbp), b = (int)(t % nbp);
+    T v = 0;
+    if (b < nlist) {
+      const int pid = boxes[b];
+      const int code = loc_tab[k];
+      int ii = (code & 0xfff) + (pid % g.npd) * g.b - g.o, jj = ((code >> 12) & 0xfff) + (pid / g.npd) * g.b - g.o;
+      ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
+      jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
+      v = r[(size_t)(code >> 24) * nn + (size_t)jj * N + ii];
+    }
+    X[t] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_int_gemm(const T* __restrict__ M, const T* __restrict__ X, T* __restrict__ z,
+                                                  BoxGeom g, const int* __restrict__ boxes, int nlist, int nbp,
+                                                  T* __restrict__ part, int ksplit, bool acc_mode) {
+  constexpr int KC = 32;
+  __shared__ T As[KC][64];
+  __shared__ T Bs[KC][128];
+  using acc_t = typename Mfma<T>::acc_t;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wb = wave >> 1, kq = lane >> 4, ln = lane & 15;
+  const int chunk = blockIdx.x, B0 = blockIdx.y * 128, kslice = blockIdx.z;
+  const int nchunk = (g.nloc + 63) / 64;
+  const int per = (nchunk + ksplit - 1) / ksplit;
+  const int c0 = kslice * per, c1 = c0 + per < nchunk ? c0 + per : nchunk;
+  const int kb = c0 * 64, ke = c1 * 64;   // reduction indices beyond nloc read as zero
+  const T* Mc = M + (size_t)chunk * g.nloc * 64;
+  acc_t acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  T ga[8], gb[16];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = tid + 256 * u, kk = t >> 6, row = t & 63, k = k0 + kk;
+      ga[u] = k < g.nloc ? Mc[(size_t)k * 64 + row] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = tid + 256 * u, kk = t >> 7, c = t & 127, k = k0 + kk;
+      gb[u] = k < g.nloc ? X[(size_t)k * nbp + B0 + c] : (T)0;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = tid + 256 * u;
+      As[t >> 6][t & 63] = ga[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = tid + 256 * u;
+      Bs[t >> 7][t & 127] = gb[u];
+    }
+    __syncthreads();
+    if (k0 + KC < ke) load(k0 + KC);   // in flight during the MFMAs below
+#pragma unroll
+    for (int st = 0; st < KC / 4; ++st) {
+      const int kk = 4 * st + kq;
+      const T a0 = As[kk][32 * wr + ln], a1 = As[kk][32 * wr + 16 + ln];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const T bv = Bs[kk][64 * wb + 16 * b + ln];
+        acc[0][b] = Mfma<T>::mma(a0, bv, acc[0][b]);
+        acc[1][b] = Mfma<T>::mma(a1, bv, acc[1][b]);
+      }
+    }
+    __syncthreads();
+  }
+  const int nown_pad = g.nch * 64;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = chunk * 64 + 32 * wr + 16 * a + Mfma<T>::row(kq, v);
+        const int box = B0 + 64 * wb + 16 * b + ln;
+        if (row >= g.nown || box >= nlist) continue;
+        if (ksplit == 1) {
+          const size_t o = own_glob(g, boxes[box], row);
+          z[o] = acc_mode ? z[o] + acc[a][b][v] : acc[a][b][v];
+        } else {
+          part[((size_t)kslice * nlist + box) * nown_pad + row] = acc[a][b][v];
+        }
+      }
+}
+
+// nloc x (boxes rounded up to 128): the gathered operand of the product
+size_t int_gather_elems(const BoxGeom& g, int n_int) { return (size_t)g.nloc * (size_t)((n_int + 127) / 128 * 128); }
+
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s, int parts, bool acc, int tb) {
+                      T* part, hipStream_t s, int parts, bool acc, int tb, T* xg, size_t xg_elems) {
   if ((parts & 1) && n_ib > 0) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
     const int ks = ras_ib_ksplit(g, n_ib);
@@ -842,7 +954,16 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   }
   if ((parts & 2) && n_int > 0) {
     const int ks = ras_interior_ksplit(g, n_int);
-    if (tb == 64)
+    if (tb == 128 && xg && xg_elems >= int_gather_elems(g, n_int)) {
+      const int nbp = (n_int + 127) / 128 * 128;
+      const size_t tot = (size_t)g.nloc * nbp;
+      int grid = cdiv(tot, 256);
+      if (grid > 8192) grid = 8192;
+      hipLaunchKernelGGL((k_int_gather<T>), dim3(grid), dim3(256), 0, s, r, xg, g, int_boxes, n_int, nbp, loc_tab);
+      IBMG_LAUNCH_CHECK();
+      hipLaunchKernelGGL((k_int_gemm<T>), dim3(g.nch, nbp / 128, ks), dim3(256), 0, s, shared_inv, xg, z, g,
+                         int_boxes, n_int, nbp, part, ks, acc);
+    } else if (tb == 64)
       hipLaunchKernelGGL((k_ras_interior_g<T>), dim3((n_int + 63) / 64, g.nch, ks), dim3(256), 0, s, r, z, g,
                          shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
     else if (tb == 16)
@@ -1100,10 +1221,10 @@ template void launch_extract_owned<double>(const double*, int, BoxGeom, double*,
 template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t);
 template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*, int,
                                        const double*, const int*, int, const int*, double*,
-                                       hipStream_t, int, bool, int);
+                                       hipStream_t, int, bool, int, double*, size_t);
 template void launch_ras_apply<float>(const float*, float*, BoxGeom, const float*, const int*, int,
                                       const float*, const int*, int, const int*, float*,
-                                      hipStream_t, int, bool, int);
+                                      hipStream_t, int, bool, int, float*, size_t);
 template void launch_coarse_apply<double>(const double*, int, const double*, double*, hipStream_t);
 template void launch_coarse_apply<float>(const double*, int, const float*, float*, hipStream_t);
 template void launch_coarse_apply_batch<double>(const double*, int, const double*, double*, int, hipStream_t);

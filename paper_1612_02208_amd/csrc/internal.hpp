@@ -252,11 +252,15 @@ void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipS
 // (k_ras_interior and its slice sum); the smoother launches both.
 // acc: add the local solutions to z on the owned sets instead of storing them;
 // tb: interior product form (16 or 32 boxes per tile, 64: register-blocked
-// 64 x 64 tiles; results do not depend on it)
+// 64 x 64 tiles, 128: residuals gathered into xg (at least
+// int_gather_elems(g, n_int) elements) and 64 x 128 tiles; results do not
+// depend on it)
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
-                      T* part, hipStream_t s, int parts = 3, bool acc = false, int tb = 32);
+                      T* part, hipStream_t s, int parts = 3, bool acc = false, int tb = 32, T* xg = nullptr,
+                      size_t xg_elems = 0);
+size_t int_gather_elems(const BoxGeom& g, int n_int);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);
 // column slices of the IB-box kernel (part holds ksplit * n_ib * nch * 64);

@@ -77,6 +77,7 @@ struct Level {
   DBuf<int> d_ib, d_int, d_loc;
   DBuf<T> inv;            // [n_unique][nch][nloc][64]
   DBuf<T> int_part;       // reduction slices of the interior-box product
+  DBuf<T> int_x;          // gathered residuals of the interior boxes (product form 128)
   // restricted multiplicative Schwarz: box colours; ib_list and int_list
   // sorted by colour, colour c spanning [ib_off[c], ib_off[c+1]) and
   // [int_off[c], int_off[c+1])
@@ -431,7 +432,7 @@ class Solver final : public SolverBase {
                 lev.int_part.n >= ib_part_need(lev.g, (parts & 1) ? n_ib : 0),
             "Schwarz slice buffer too small");
     launch_ras_apply<T>(r, z, lev.g, inv, ib, n_ib, lev.inv.p + (size_t)lev.n_ib * box_stride(lev), in, n_int,
-                        lev.d_loc.p, lev.int_part.p, s, parts, acc, tb);
+                        lev.d_loc.p, lev.int_part.p, s, parts, acc, tb, lev.int_x.p, lev.int_x.n);
   }
 
   // partial-sum buffers of a level: the reductions' blocks x vectors, and the
@@ -440,19 +441,28 @@ class Solver final : public SolverBase {
     return std::max(kPartStride, (size_t)apply_blocks(lev.N) * (kMaxNu + 1));
   }
 
-  // Interior product form per Schwarz level: time the 16- and 32-box tiles
-  // and the register-blocked 64-box form (HIP events, on the level's work
-  // vectors) and keep the fastest.  All compute the same sums in the same
-  // order.
+  // Interior product form per Schwarz level: time the 16- and 32-box tiles,
+  // the register-blocked 64-box form and the gathered 128-box form (HIP
+  // events, on the level's work vectors) and keep the fastest.  All compute
+  // the same sums in the same order.  IBMG_INTERIOR_FORM=16|32|64|128 in the
+  // environment fixes the form instead (where the level supports it).
   void tune_interior(hipStream_t s) {
     if (d_.smoother != IBMG_RAS && d_.smoother != IBMG_RMS) return;
+    int forced = 0;
+    if (const char* e = std::getenv("IBMG_INTERIOR_FORM")) forced = std::atoi(e);
     for (int l = 1; l <= L_; ++l) {
       Level<T>& lev = levels_[l];
       const int n_int = (int)lev.int_list.size();
       if (n_int == 0) continue;
+      if (forced == 16 || forced == 32 || forced == 64 ||
+          (forced == 128 && lev.int_x.n >= int_gather_elems(lev.g, n_int))) {
+        lev.int_tb = forced;
+        continue;
+      }
       launch_fill<T>(lev.r.p, T(1), 3 * (size_t)lev.N * lev.N, s);
       double best = 1e300;
-      for (int tb : {32, 16, 64}) {
+      for (int tb : {32, 16, 64, 128}) {
+        if (tb == 128 && lev.int_x.n < int_gather_elems(lev.g, n_int)) continue;
         const double ms = time_launches([&] {
           ras_launch(lev, lev.r.p, lev.t.p, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, n_int, s, 2, false, tb);
         }, 5, s);
@@ -787,6 +797,9 @@ class Solver final : public SolverBase {
       if (lev.int_part.n < need) lev.int_part.alloc(need);
     }
     lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
+    // the gathered operand of the 128-box product form, up to 512 MB a level
+    const size_t xe = int_gather_elems(g, (int)lev.int_list.size());
+    if (!lev.int_list.empty() && xe * sizeof(T) <= ((size_t)512 << 20)) lev.int_x.alloc(xe);
   }
 
   // The unique box inverses of every Schwarz level: assembled per level,

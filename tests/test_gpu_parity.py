@@ -298,3 +298,24 @@ def test_transfer_and_coupling_kernel_timing(pair):
     f = host(G.spread(dev(F.ravel())))
     ref = np.concatenate([oib.spread_matrix(wl.X, N, c) @ F[:, c] for c in (0, 1)])
     assert rel(f, ref) < OPS_TOL
+
+
+@pytest.mark.parametrize("name", ["small_64", "annulus_64_box16", "random_48_rms"])
+def test_interior_product_forms_agree(name, monkeypatch):
+    """The interior-box product forms (16- and 32-box tiles, 64 x 64
+    register blocks, gathered 64 x 128 tiles) use the same reduction slices
+    and the same order of MFMA steps per output, so the smoother's result is
+    bitwise the same whichever form a level runs; and it is the oracle's."""
+    from paper_1612_02208_amd import StokesIB
+    wl = [c for c in CASES if c.name == name][0]
+    P = Problem(wl)
+    r = np.random.default_rng(31).uniform(-1, 1, P.levels[-1].n)
+    outs = {}
+    for form in ("16", "32", "64", "128"):
+        monkeypatch.setenv("IBMG_INTERIOR_FORM", form)
+        G = StokesIB(wl)
+        outs[form] = host(G.smoother_apply(-1, dev(r)))
+        G.close()
+    for form, z in outs.items():
+        assert np.array_equal(z, outs["32"]), form
+    assert rel(outs["128"], P.mg.smoothers[-1](r)) < SOLVE_TOL
