@@ -537,12 +537,36 @@ int ras_ib_ksplit(const BoxGeom& g, int n_ib) {
 // depend on the tile width a level runs with (16 or 32, picked by timing).
 constexpr int kIntTile = 32;
 
+// Gathers of a box's local residual.  The level's local-unknown table holds
+// nloc codes (comp << 24 | jj << 12 | ii) followed by nloc linear offsets
+// comp N^2 + jj N + ii.  A box whose enlarged region (corner x0, y0, faces up
+// to x0 + m, y0 + m) lies clear of the periodic edges reads unknown k at
+// base + y0 N + x0 + offset[k] (box_lin returns that start, or -1 where the
+// region wraps and each coordinate is reduced instead).
+__device__ __forceinline__ long long box_lin(const BoxGeom& g, size_t base, int x0, int y0) {
+  const bool clear = x0 >= 0 && y0 >= 0 && x0 + g.m < g.N && y0 + g.m < g.N;
+  return clear ? (long long)base + (long long)y0 * g.N + x0 : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T box_value(const T* __restrict__ r, const BoxGeom& g, const int* __restrict__ loc_tab,
+                                       int k, size_t base, long long lin, int x0, int y0) {
+  if (lin >= 0) return r[lin + loc_tab[g.nloc + k]];
+  const int N = g.N;
+  const int code = loc_tab[k];
+  int ii = (code & 0xfff) + x0, jj = ((code >> 12) & 0xfff) + y0;
+  ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
+  jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
+  return r[base + (size_t)(code >> 24) * N * N + (size_t)jj * N + ii];
+}
+
 // Shared memory of one interior tile: the gathered residual columns and the
 // tile's box table.
 template <typename T, int TB>
 struct IntTileSmem {
   T Xs[64][TB + 1];
   size_t base[TB];   // system offset of each box's vectors
+  long long lin[TB];  // see box_lin
   int bid[TB], bx0[TB], by0[TB];
 };
 
@@ -560,8 +584,6 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
   using acc_t = typename Mfma<T>::acc_t;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int bt = tile * TB;
-  const int N = g.N;
-  const size_t nn = (size_t)N * N;
   if (tid < TB) {
     const int b = bt + tid;
     int pid = -1, sy = 0;
@@ -575,6 +597,7 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
     sm.base[tid] = (size_t)sy * sys_n;
     sm.bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
     sm.by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
+    sm.lin[tid] = box_lin(g, sm.base[tid], sm.bx0[tid], sm.by0[tid]);
   }
   __syncthreads();
   // this item's slice of the reduction index: chunks [c0, c1) of KC columns
@@ -600,19 +623,20 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
       const int k = t % KC, b = t / KC;
       const int jk = j0 + k;
       T val = 0;
-      if (jk < g.nloc && sm.bid[b] >= 0) {
-        const int code = loc_tab[jk];
-        int ii = (code & 0xfff) + sm.bx0[b], jj = ((code >> 12) & 0xfff) + sm.by0[b];
-        ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
-        jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
-        val = r[sm.base[b] + (size_t)(code >> 24) * nn + (size_t)jj * N + ii];
-      }
+      if (jk < g.nloc && sm.bid[b] >= 0)
+        val = box_value<T>(r, g, loc_tab, jk, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
       gxo[u] = val;
     }
+    if (j0 + KC <= g.nloc) {   // a full chunk: no bounds to test
+      const T* Mj = Mrow + (size_t)(j0 + kq) * 64;
 #pragma unroll
-    for (int s = 0; s < AS; ++s) {
-      const int jk = j0 + 4 * s + kq;
-      gao[s] = jk < g.nloc ? Mrow[(size_t)jk * 64] : (T)0;
+      for (int s = 0; s < AS; ++s) gao[s] = Mj[(size_t)s * 256];
+    } else {
+#pragma unroll
+      for (int s = 0; s < AS; ++s) {
+        const int jk = j0 + 4 * s + kq;
+        gao[s] = jk < g.nloc ? Mrow[(size_t)jk * 64] : (T)0;
+      }
     }
   };
   if (c0 < c1) load_chunk(c0, gx, ga);
@@ -669,6 +693,7 @@ struct GemmSmem {
   T As[32][64];        // [reduction index][row of the chunk]
   T Bs[32][65];        // [reduction index][box]
   size_t base[64];
+  long long lin[64];
   int bid[64], bx0[64], by0[64];
 };
 
@@ -684,8 +709,6 @@ __device__ __forceinline__ void ras_int_gemm(const T* __restrict__ r, T* __restr
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave & 1, wb = wave >> 1;
   const int bt = tile * TBX;
-  const int N = g.N;
-  const size_t nn = (size_t)N * N;
   if (tid < TBX) {
     const int b = bt + tid;
     int pid = -1, sy = 0;
@@ -699,6 +722,7 @@ __device__ __forceinline__ void ras_int_gemm(const T* __restrict__ r, T* __restr
     sm.base[tid] = (size_t)sy * sys_n;
     sm.bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
     sm.by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
+    sm.lin[tid] = box_lin(g, sm.base[tid], sm.bx0[tid], sm.by0[tid]);
   }
   __syncthreads();
   const int nchunk = (g.nloc + 63) / 64;
@@ -723,13 +747,8 @@ __device__ __forceinline__ void ras_int_gemm(const T* __restrict__ r, T* __restr
       const int kx = t % KC, b = t / KC;     // X: consecutive indices of one box
       const int jx = k0 + kx;
       T val = 0;
-      if (jx < g.nloc && sm.bid[b] >= 0) {
-        const int code = loc_tab[jx];
-        int ii = (code & 0xfff) + sm.bx0[b], jj = ((code >> 12) & 0xfff) + sm.by0[b];
-        ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
-        jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
-        val = r[sm.base[b] + (size_t)(code >> 24) * nn + (size_t)jj * N + ii];
-      }
+      if (jx < g.nloc && sm.bid[b] >= 0)
+        val = box_value<T>(r, g, loc_tab, jx, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
       gb[u] = val;
     }
   };
@@ -835,18 +854,14 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_int_gather(const T* __restrict__ r, T* __restrict__ X, BoxGeom g,
                                                     const int* __restrict__ boxes, int nlist, int nbp,
                                                     const int* __restrict__ loc_tab) {
-  const int N = g.N;
-  const size_t nn = (size_t)N * N, tot = (size_t)g.nloc * nbp;
+  const size_t tot = (size_t)g.nloc * nbp;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
     const int k = (int)(t / nbp), b = (int)(t % nbp);
     T v = 0;
     if (b < nlist) {
       const int pid = boxes[b];
-      const int code = loc_tab[k];
-      int ii = (code & 0xfff) + (pid % g.npd) * g.b - g.o, jj = ((code >> 12) & 0xfff) + (pid / g.npd) * g.b - g.o;
-      ii = ii < 0 ? ii + N : (ii >= N ? ii - N : ii);
-      jj = jj < 0 ? jj + N : (jj >= N ? jj - N : jj);
-      v = r[(size_t)(code >> 24) * nn + (size_t)jj * N + ii];
+      const int x0 = (pid % g.npd) * g.b - g.o, y0 = (pid / g.npd) * g.b - g.o;
+      v = box_value<T>(r, g, loc_tab, k, 0, box_lin(g, 0, x0, y0), x0, y0);
     }
     X[t] = v;
   }

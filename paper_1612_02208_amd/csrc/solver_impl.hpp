@@ -73,7 +73,7 @@ struct Level {
   int n_unique = 0, n_ib = 0;
   std::vector<int> uniq;  // unique box ids (IB boxes, then one interior representative)
   std::vector<int> ib_list, int_list;
-  std::vector<int> loc_tab;  // local unknown -> (comp << 24) | (jj << 12) | ii
+  std::vector<int> loc_tab;  // local unknown -> (comp << 24) | (jj << 12) | ii, then -> comp N^2 + jj N + ii
   DBuf<int> d_ib, d_int, d_loc;
   DBuf<T> inv;            // [n_unique][nch][nloc][64]
   DBuf<T> int_part;       // reduction slices of the interior-box product
@@ -393,14 +393,17 @@ class Solver final : public SolverBase {
       if (ib) lev.ib_list.push_back(p);
       else lev.int_list.push_back(p);
     }
-    lev.loc_tab.assign(lev.g.nloc, 0);
-    for (int k = 0; k < lev.g.nloc; ++k) {
+    // codes, then linear offsets from the box's corner (the gathers' table)
+    const int nloc = lev.g.nloc;
+    lev.loc_tab.assign(2 * (size_t)nloc, 0);
+    for (int k = 0; k < nloc; ++k) {
       const int nu = m * (m + 1);
       int comp, ii, jj;
       if (k < nu) { comp = 0; ii = k % (m + 1); jj = k / (m + 1); }
       else if (k < 2 * nu) { comp = 1; ii = (k - nu) % m; jj = (k - nu) / m; }
       else { comp = 2; ii = (k - 2 * nu) % m; jj = (k - 2 * nu) / m; }
       lev.loc_tab[k] = (comp << 24) | (jj << 12) | ii;
+      lev.loc_tab[nloc + k] = (int)((int64_t)comp * N * N + (int64_t)jj * N + ii);
     }
     lev.n_ib = (int)lev.ib_list.size();
     lev.uniq = lev.ib_list;
