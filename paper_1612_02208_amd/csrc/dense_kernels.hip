@@ -217,17 +217,29 @@ __device__ __forceinline__ void gj_tile_product(Gj64Smem& sm, Mfma<double>::acc_
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < GJ_NB; k0 += 32) {
+  // the second chunk's values load into registers during the first's steps
+  double xr[8], yr[8];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int t = tid + 256 * q;
       const int row = t >> 5, k = t & 31;
-      sm.Xs[k][row] = row < xrows ? X[(size_t)row * GJ_NB + k0 + k] : 0.0;
+      xr[q] = row < xrows ? X[(size_t)row * GJ_NB + k0 + k] : 0.0;
       const int ky = t >> 6, c = t & 63;
       const int r = kb + k0 + ky, j = J0 + c;
-      sm.Ys[ky][c] = (r < n && j < n) ? A[(size_t)r * n + j] : 0.0;
+      yr[q] = (r < n && j < n) ? A[(size_t)r * n + j] : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < GJ_NB; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = tid + 256 * q;
+      sm.Xs[t & 31][t >> 5] = xr[q];
+      sm.Ys[t >> 6][t & 63] = yr[q];
     }
     __syncthreads();
+    if (k0 + 32 < GJ_NB) load(k0 + 32);
 #pragma unroll
     for (int st = 0; st < 8; ++st) {
       const int kk = 4 * st + kq;
@@ -281,10 +293,23 @@ __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, in
   double* A = mats + (size_t)blockIdx.z * n * n;
   const double* C = colk_all + (size_t)blockIdx.z * n * GJ_NB;
   const int tid = threadIdx.x;
-  Mfma<double>::acc_t acc[2][2];
-  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, A, n, kb, J0);
   const int wave = tid >> 6, lane = tid & 63, wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
   const bool diag_cols = J0 == kb;
+  // the tile's old values load first, so their trip from memory overlaps the
+  // product (no work-group of this launch writes rows K or the saved C)
+  double old[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
+        const int j = J0 + 32 * wc + 16 * b + ln;
+        old[a][b][v] = (!diag_cols && i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
+      }
+  Mfma<double>::acc_t acc[2][2];
+  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, A, n, kb, J0);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -294,8 +319,7 @@ __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, in
         const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
         const int j = J0 + 32 * wc + 16 * b + ln;
         if (i >= n || j >= n) continue;
-        const size_t o = (size_t)i * n + j;
-        A[o] = (diag_cols ? 0.0 : A[o]) - acc[a][b][v];
+        A[(size_t)i * n + j] = old[a][b][v] - acc[a][b][v];
       }
 }
 
