@@ -123,21 +123,28 @@ struct Mfma<float> {
 };
 
 // ---------------------------------------------------------------------------
-// Batched in-place Gauss-Jordan inversion without pivoting, blocked by 64
-// columns.  The box matrices are ordered velocities first: the velocity block
-// R_k A_IB R_k^T is symmetric positive definite (a principal submatrix of
-// rho/dt - mu Lap + IB with the periodic constants cut off), and the pressure
-// pivots come from the negative definite Schur complement -G^T A^{-1} G, so
-// no pivot vanishes.
-// Step K (columns kb .. kb+w, w <= 64), four launches over every matrix:
-//   diag   (a work-group per matrix): D = A_KK -> D^{-1} in LDS, to dinv;
-//   colk   (64-row tiles): C = A_:K saved (A_:K is overwritten below);
-//   rows   (64-column tiles): A_KJ <- D^{-1} A_KJ for J != K, A_KK <- D^{-1};
-//   update (64 x 64 tiles, rows outside K): A_IJ <- [J != K] A_IJ - C_I A_KJ
-//          (with A_KK = D^{-1} this also gives A_IK <- -C_I D^{-1}).
-// The rows and update products are 64 x 64 x 64 tiles on the FP64 matrix
+// Batched in-place inversion of the symmetric box matrices by block sweeps
+// (the symmetric form of Gauss-Jordan elimination, no pivoting), 64 columns
+// per step.  The box matrices are ordered velocities first: the velocity
+// block R_k A_IB R_k^T is symmetric positive definite (a principal submatrix
+// of rho/dt - mu Lap + IB with the periodic constants cut off), and the
+// pressure pivots come from the negative definite Schur complement
+// -G^T A^{-1} G, so no pivot vanishes.  L_IB is symmetric (G = -D^T,
+// S = J^*), so every swept matrix is too, and only the tiles on or below the
+// diagonal (64 x 64 tiles I >= J, diagonal tiles in full) are kept.
+// Sweeping block K of a symmetric S with D = S_KK:
+//   S_IJ <- S_IJ - S_IK D^{-1} S_KJ   (I, J != K),
+//   S_IK <- S_IK D^{-1},  S_KK <- -D^{-1};
+// after every block S = -A^{-1}.  Step K, five launches over every matrix:
+//   diag       (a work-group per matrix): D^{-1} in LDS, to dinv;
+//   panel read (64-row tiles): C = S_:K from the kept tiles (rows above K
+//              from row K's tiles, transposed) and its transpose C^T;
+//   scale      (64-row tiles): E = C D^{-1};
+//   update     (kept 64 x 64 tiles outside row and column K):
+//              S_IJ <- S_IJ - E_I C_J^T;
+//   panel write: S_IK <- E_I below K, S_KI <- E_I^T above it, S_KK <- -D^{-1}.
+// The scale and update products are 64 x 64 x 64 tiles on the FP64 matrix
 // cores (16x16x4 MFMA, four waves of 2 x 2 tiles).
-// ---------------------------------------------------------------------------
 constexpr int GJ_NB = 64;
 
 __global__ void __launch_bounds__(256) k_gj_diag(const double* __restrict__ mats, int n, int kb,
@@ -181,21 +188,6 @@ __global__ void __launch_bounds__(256) k_gj_diag(const double* __restrict__ mats
   for (int q = 0; q < 16; ++q) {
     const int t = tid + 256 * q;
     Di[t] = Dm[t >> 6][t & 63];
-  }
-}
-
-// C = A[:, K] (n x 64, zero beyond w), 64 rows per work-group
-__global__ void __launch_bounds__(256) k_gj_colk(const double* __restrict__ mats, int n, int kb,
-                                                 double* __restrict__ colk_all) {
-  const double* A = mats + (size_t)blockIdx.y * n * n;
-  double* C = colk_all + (size_t)blockIdx.y * n * GJ_NB;
-  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
-  const int I0 = blockIdx.x * 64;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = threadIdx.x + 256 * q, a = t >> 6, k = t & 63;
-    const int i = I0 + a;
-    if (i < n) C[(size_t)i * GJ_NB + k] = k < w ? A[(size_t)i * n + kb + k] : 0.0;
   }
 }
 
@@ -254,25 +246,58 @@ __device__ __forceinline__ void gj_tile_product(Gj64Smem& sm, Mfma<double>::acc_
   }
 }
 
-__global__ void __launch_bounds__(256) k_gj_rows(double* __restrict__ mats, int n, int kb,
-                                                 const double* __restrict__ dinv_all) {
-  __shared__ Gj64Smem sm;
-  double* A = mats + (size_t)blockIdx.y * n * n;
-  const double* Di = dinv_all + (size_t)blockIdx.y * GJ_NB * GJ_NB;
+// C = S[:, K] and C^T (n x 64 and 64 x n, zero beyond w) for one 64-row tile
+// I: tiles at or below K hold S_IK; above K, S_IK = S_KI^T is read from row
+// K's tile.  work holds C, C^T and E per matrix.
+__global__ void __launch_bounds__(256) k_sw_panel_read(const double* __restrict__ mats, int n, int kb,
+                                                       double* __restrict__ work) {
+  __shared__ double Ts[64][65];   // [row of the tile][column of K]
+  const int I0 = blockIdx.x * 64, K = kb / 64;
+  const double* A = mats + (size_t)blockIdx.y * n * n;
+  double* C = work + (size_t)blockIdx.y * 3 * n * GJ_NB;
+  double* Ct = C + (size_t)n * GJ_NB;
   const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
-  const int J0 = blockIdx.x * 64;
   const int tid = threadIdx.x;
-  if (J0 == kb) {   // A_KK <- D^{-1}
+  if ((int)blockIdx.x >= K) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, a = t >> 6, b = t & 63;
-      if (a < w && b < w) A[(size_t)(kb + a) * n + kb + b] = Di[t];
+      const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+      Ts[a][k] = (i < n && k < w) ? A[(size_t)i * n + kb + k] : 0.0;
     }
-    return;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, k = t >> 6, c = t & 63, i = I0 + c;
+      Ts[c][k] = (k < w && i < n) ? A[(size_t)(kb + k) * n + i] : 0.0;
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+    if (i < n) C[(size_t)i * GJ_NB + k] = Ts[a][k];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q, k = t >> 6, a = t & 63, i = I0 + a;
+    if (i < n) Ct[(size_t)k * n + i] = Ts[a][k];
+  }
+}
+
+// E_I = C_I D^{-1} for one 64-row tile I != K
+__global__ void __launch_bounds__(256) k_sw_scale(const double* __restrict__ dinv_all, int n, int kb,
+                                                  double* __restrict__ work) {
+  const int I0 = blockIdx.x * 64;
+  if (I0 == kb) return;   // E_K is not used
+  __shared__ Gj64Smem sm;
+  const double* C = work + (size_t)blockIdx.y * 3 * n * GJ_NB;
+  double* E = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)2 * n * GJ_NB;
+  const double* Di = dinv_all + (size_t)blockIdx.y * GJ_NB * GJ_NB;
+  const int rows = n - I0 < 64 ? n - I0 : 64;
   Mfma<double>::acc_t acc[2][2];
-  gj_tile_product(sm, acc, Di, GJ_NB, A, n, kb, J0);
-  const int wave = tid >> 6, lane = tid & 63, wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
+  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, rows, Di, GJ_NB, 0, 0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -280,23 +305,29 @@ __global__ void __launch_bounds__(256) k_gj_rows(double* __restrict__ mats, int 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 32 * wr + 16 * a + Mfma<double>::row(kq, v);
-        const int j = J0 + 32 * wc + 16 * b + ln;
-        if (row < w && j < n) A[(size_t)(kb + row) * n + j] = acc[a][b][v];
+        if (row < rows) E[(size_t)(I0 + row) * GJ_NB + 32 * wc + 16 * b + ln] = acc[a][b][v];
       }
 }
 
-__global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, int n, int kb,
-                                                   const double* __restrict__ colk_all) {
-  const int I0 = blockIdx.y * 64, J0 = blockIdx.x * 64;
-  if (I0 == kb) return;   // the rows of K are final
+// S_IJ <- S_IJ - E_I C_J^T over the kept tiles I >= J outside row and column
+// K; work-group p takes the p-th tile of the lower triangle in row order.
+__global__ void __launch_bounds__(256) k_sw_update(double* __restrict__ mats, int n, int kb,
+                                                   const double* __restrict__ work) {
+  const int p = blockIdx.x;
+  int I = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+  while (I * (I + 1) / 2 > p) --I;
+  while ((I + 1) * (I + 2) / 2 <= p) ++I;
+  const int J = p - I * (I + 1) / 2, K = kb / 64;
+  if (I == K || J == K) return;
   __shared__ Gj64Smem sm;
-  double* A = mats + (size_t)blockIdx.z * n * n;
-  const double* C = colk_all + (size_t)blockIdx.z * n * GJ_NB;
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
-  const bool diag_cols = J0 == kb;
+  const int I0 = I * 64, J0 = J * 64;
+  double* A = mats + (size_t)blockIdx.y * n * n;
+  const double* Ct = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)n * GJ_NB;
+  const double* E = Ct + (size_t)n * GJ_NB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
   // the tile's old values load first, so their trip from memory overlaps the
-  // product (no work-group of this launch writes rows K or the saved C)
+  // product (no work-group of this launch writes another's tile, E or C^T)
   double old[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -306,10 +337,10 @@ __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, in
       for (int v = 0; v < 4; ++v) {
         const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
         const int j = J0 + 32 * wc + 16 * b + ln;
-        old[a][b][v] = (!diag_cols && i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
+        old[a][b][v] = (i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
       }
   Mfma<double>::acc_t acc[2][2];
-  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, A, n, kb, J0);
+  gj_tile_product(sm, acc, E + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, Ct, n, 0, J0);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -318,22 +349,65 @@ __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ mats, in
       for (int v = 0; v < 4; ++v) {
         const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
         const int j = J0 + 32 * wc + 16 * b + ln;
-        if (i >= n || j >= n) continue;
-        A[(size_t)i * n + j] = old[a][b][v] - acc[a][b][v];
+        if (i < n && j < n) A[(size_t)i * n + j] = old[a][b][v] - acc[a][b][v];
       }
 }
 
-void launch_gj_invert(double* mats, int n, int count, double* colk, double* dinv, hipStream_t s) {
+// Row and column K of the swept matrix, one 64-row tile I per work-group
+__global__ void __launch_bounds__(256) k_sw_panel_write(double* __restrict__ mats, int n, int kb,
+                                                        const double* __restrict__ work,
+                                                        const double* __restrict__ dinv_all) {
+  __shared__ double Ts[64][65];
+  const int I0 = blockIdx.x * 64, K = kb / 64, I = blockIdx.x;
+  double* A = mats + (size_t)blockIdx.y * n * n;
+  const double* E = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)2 * n * GJ_NB;
+  const double* Di = dinv_all + (size_t)blockIdx.y * GJ_NB * GJ_NB;
+  const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
+  const int tid = threadIdx.x;
+  if (I == K) {   // S_KK <- -D^{-1}
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, a = t >> 6, b = t & 63;
+      if (a < w && b < w) A[(size_t)(kb + a) * n + kb + b] = -Di[t];
+    }
+    return;
+  }
+  if (I > K) {    // S_IK <- E_I
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+      if (i < n && k < w) A[(size_t)i * n + kb + k] = E[(size_t)i * GJ_NB + k];
+    }
+    return;
+  }
+  // above K the kept tile is S_KI <- E_I^T
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+    Ts[a][k] = i < n ? E[(size_t)i * GJ_NB + k] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q, k = t >> 6, c = t & 63, i = I0 + c;
+    if (k < w && i < n) A[(size_t)(kb + k) * n + i] = Ts[c][k];
+  }
+}
+
+void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv, hipStream_t s) {
   if (!count) return;
   const int tiles = (n + 63) / 64;
+  const int pairs = tiles * (tiles + 1) / 2;
   for (int kb = 0; kb < n; kb += GJ_NB) {
     hipLaunchKernelGGL(k_gj_diag, dim3(count), dim3(256), 0, s, mats, n, kb, dinv);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gj_colk, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, colk);
+    hipLaunchKernelGGL(k_sw_panel_read, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gj_rows, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, dinv);
+    hipLaunchKernelGGL(k_sw_scale, dim3(tiles, count), dim3(256), 0, s, dinv, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, count), dim3(256), 0, s, mats, n, kb, colk);
+    hipLaunchKernelGGL(k_sw_update, dim3(pairs, count), dim3(256), 0, s, mats, n, kb, work);
+    IBMG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sw_panel_write, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work, dinv);
     IBMG_LAUNCH_CHECK();
   }
 }
@@ -398,7 +472,13 @@ __global__ void k_extract_owned(const double* __restrict__ mats, int count, BoxG
     const int j = (int)(rem / 64), rr = (int)(rem % 64);
     const int row = c * 64 + rr;
     const double* A = mats + blk * g.nloc * g.nloc;
-    out[t] = row < g.nown ? (T)A[(size_t)own_local(row, g) * g.nloc + j] : (T)0;
+    // the swept matrix holds -A^{-1} in the tiles on or below the diagonal
+    T v = 0;
+    if (row < g.nown) {
+      const int lr = own_local(row, g);
+      v = (T)(-((lr >> 6) >= (j >> 6) ? A[(size_t)lr * g.nloc + j] : A[(size_t)j * g.nloc + lr]));
+    }
+    out[t] = v;
   }
 }
 

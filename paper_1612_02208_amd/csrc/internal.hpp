@@ -243,9 +243,12 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
                            const int* tptr_u, const int* tcol_u, const double* tval_u,
                            const int* tptr_v, const int* tcol_v, const double* tval_v,
                            double* mats, hipStream_t s);
-// colk: count x n x 64 and dinv: count x 64 x 64 doubles of workspace
-void launch_gj_invert(double* mats, int n, int count, double* colk, double* dinv, hipStream_t s);
-constexpr int kGjNb = 64;  // block width of the batched Gauss-Jordan inversion
+// In-place block sweeps of count symmetric n x n matrices: afterwards the
+// tiles on or below the diagonal (64 x 64, diagonal tiles in full) hold
+// -A^{-1}; launch_extract_owned reads them.  work: count x 3 x n x 64 and
+// dinv: count x 64 x 64 doubles of workspace.
+void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv, hipStream_t s);
+constexpr int kGjNb = 64;  // block width of the batched inversion
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
 // parts: bit 0 = IB boxes (k_ras_ib), bit 1 = interior boxes

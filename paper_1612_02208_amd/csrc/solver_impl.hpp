@@ -825,9 +825,10 @@ class Solver final : public SolverBase {
     for (auto& grp : groups) {
       const int n = grp.first;
       const auto& items = grp.second;
-      const size_t per = ((size_t)n * n + (size_t)n * kGjNb + (size_t)kGjNb * kGjNb) * sizeof(double);
+      const size_t per = ((size_t)n * n + 3 * (size_t)n * kGjNb + (size_t)kGjNb * kGjNb) * sizeof(double);
       const int batch = (int)std::min<size_t>({items.size(), std::max<size_t>(1, budget / per), (size_t)512});
-      DBuf<double> mats((size_t)batch * n * n), colk((size_t)batch * n * kGjNb), dinv((size_t)batch * kGjNb * kGjNb);
+      DBuf<double> mats((size_t)batch * n * n), work(3 * (size_t)batch * n * kGjNb),
+          dinv((size_t)batch * kGjNb * kGjNb);
       for (size_t b0 = 0; b0 < items.size(); b0 += batch) {
         const int cnt = (int)std::min<size_t>(batch, items.size() - b0);
         // runs of one level with consecutive unique indices
@@ -846,7 +847,7 @@ class Solver final : public SolverBase {
                                 lev.f[0].tval.p, lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p,
                                 mats.p + slot * n * n, s);
         });
-        launch_gj_invert(mats.p, n, cnt, colk.p, dinv.p, s);
+        launch_gj_invert(mats.p, n, cnt, work.p, dinv.p, s);
         for_runs([&](int l, int u0, int count, size_t slot) {
           Level<T>& lev = levels_[l];
           launch_extract_owned<T>(mats.p + slot * n * n, count, lev.g, lev.inv.p + (size_t)u0 * box_stride(lev), s);
