@@ -6,6 +6,12 @@ per dispatch, the copy calibrating the counters' units):
     python -m paper_1612_02208_amd.profile_kernels [--N 512] [--box 16]
         [--overlap 4] [--precision fp64] [--reps 5] [--copy-mib 1024]
 
+With ``--large`` it times the grid and coupling kernels on a 4096^2 grid
+with 2^20 points instead (fields of 400 MB, beyond the caches): a
+suspension of 32 x 32 membranes in fibre order for the stencil, the
+transfers, spreading and interpolation, then the same count of uniformly
+scattered points for spreading and interpolation.
+
 Prints one JSON line per kernel.
 """
 import argparse
@@ -26,10 +32,31 @@ def main():
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--reps", type=int, default=5)
     p.add_argument("--copy-mib", type=int, default=1024)
+    p.add_argument("--large", action="store_true")
     a = p.parse_args()
+    import numpy as np
     import torch
     import workloads as W
     from paper_1612_02208_amd import StokesIB
+
+    if a.large:
+        N, M = 4096, 1 << 20
+        for tag, X in (("suspension", W.suspension_points(32, 0.35 / 32, 1024)),
+                       ("uniform_random", W.random_points(M, 7))):
+            wl = W.Workload(f"grid_{N}_{tag}", N, 8, 1.0, 1e-2, 5e-4, X, np.zeros((0, 2), dtype=np.int32),
+                            np.zeros(0), box=8, overlap=2)
+            g = StokesIB(wl, precision="fp64")
+            kinds = [("spread", "k_spread"), ("interp", "k_interp_lanes<double>")]
+            if tag == "suspension":
+                kinds = [("stencil", "k_apply<double>"), ("restrict", "k_restrict<double>"),
+                         ("prolong", "k_prolong_add<double>")] + kinds
+            for kern, name in kinds:
+                t = g.kernel_time(kern, -1, a.reps)
+                print(json.dumps(dict(kernel=name, layout=tag, N=N, points=int(X.shape[0]), reps=a.reps,
+                                      avg_ms=t["ms"], alg_bytes=t["bytes"], gbs=t["bytes"] / t["ms"] / 1e6)),
+                      flush=True)
+            g.close()
+        return
 
     wl = W.annulus_512(N=a.N)
     wl.box, wl.overlap = a.box, a.overlap
