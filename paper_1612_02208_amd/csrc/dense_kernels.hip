@@ -666,12 +666,15 @@ __device__ __forceinline__ T box_value(const T* __restrict__ r, const BoxGeom& g
 
 // Shared memory of one interior tile: the gathered residual columns and the
 // tile's box table.
+constexpr int kIntLinTab = 2048;   // linear offsets of one item's reduction range kept in LDS
+
 template <typename T, int TB>
 struct IntTileSmem {
   T Xs[64][TB + 1];
   size_t base[TB];   // system offset of each box's vectors
   long long lin[TB];  // see box_lin
   int bid[TB], bx0[TB], by0[TB];
+  int ltab[kIntLinTab];
 };
 
 // One interior tile (boxes ents[tile * TB ..], 64-row chunk, reduction slice
@@ -703,23 +706,29 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
     sm.by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
     sm.lin[tid] = box_lin(g, sm.base[tid], sm.bx0[tid], sm.by0[tid]);
   }
-  __syncthreads();
   // this item's slice of the reduction index: chunks [c0, c1) of KC columns
   const int nchunk = (g.nloc + KC - 1) / KC;
   const int per = (nchunk + ksplit - 1) / ksplit;
   const int c0 = kslice * per;
   const int c1 = c0 + per < nchunk ? c0 + per : nchunk;
+  // the slice's linear offsets in LDS (when they fit), so a gather waits on
+  // one trip to memory, not two
+  const int kb0 = c0 * KC, kspan = (c1 - c0) * KC;
+  const bool ltab_lds = kspan <= kIntLinTab;
+  if (ltab_lds)
+    for (int k = tid; k < kspan; k += 256) sm.ltab[k] = kb0 + k < g.nloc ? loc_tab[g.nloc + kb0 + k] : 0;
+  __syncthreads();
   const T* Mrow = M + (size_t)chunk * g.nloc * 64 + 16 * wave + (lane & 15);
   const int kq = lane >> 4, bl = lane & 15;
   constexpr int NT = TB / 16;  // 16 x 16 output tiles per wave
   acc_t acc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = acc_t{0, 0, 0, 0};
-  T gx[GPT], ga[AS];
+  T ga[AS];
   // the gather runs along the reduction index (a wave reads 64 consecutive
   // local unknowns of one box, mostly contiguous rows of the grid) and is
   // transposed into Xs[k][box]
-  auto load_chunk = [&](int c, T* gxo, T* gao) {
+  auto gather = [&](int c, T* gxo) {
     const int j0 = c * KC;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
@@ -727,10 +736,15 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
       const int k = t % KC, b = t / KC;
       const int jk = j0 + k;
       T val = 0;
-      if (jk < g.nloc && sm.bid[b] >= 0)
-        val = box_value<T>(r, g, loc_tab, jk, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
+      if (jk < g.nloc && sm.bid[b] >= 0) {
+        if (ltab_lds && sm.lin[b] >= 0) val = r[sm.lin[b] + sm.ltab[jk - kb0]];
+        else val = box_value<T>(r, g, loc_tab, jk, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
+      }
       gxo[u] = val;
     }
+  };
+  auto load_a = [&](int c, T* gao) {
+    const int j0 = c * KC;
     if (j0 + KC <= g.nloc) {   // a full chunk: no bounds to test
       const T* Mj = Mrow + (size_t)(j0 + kq) * 64;
 #pragma unroll
@@ -743,7 +757,12 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
       }
     }
   };
-  if (c0 < c1) load_chunk(c0, gx, ga);
+  // the next chunk's gather and inverse rows load during the MFMAs
+  T gx[GPT];
+  if (c0 < c1) {
+    gather(c0, gx);
+    load_a(c0, ga);
+  }
   for (int c = c0; c < c1; ++c) {
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
@@ -754,7 +773,10 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
     T a[AS];
 #pragma unroll
     for (int s = 0; s < AS; ++s) a[s] = ga[s];
-    if (c + 1 < c1) load_chunk(c + 1, gx, ga);   // in flight during the MFMAs below
+    if (c + 1 < c1) {
+      gather(c + 1, gx);
+      load_a(c + 1, ga);
+    }
 #pragma unroll
     for (int s = 0; s < AS; ++s) {
 #pragma unroll

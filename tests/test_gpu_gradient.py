@@ -37,7 +37,7 @@ def _loss_and_grad(wl, wt, b):
     w = StiffnessSolve.apply(kap, G, b, 1e-13)
     loss = 0.5 * torch.sum((w[:n2] - ut[:n2]) ** 2)
     loss.backward()
-    return G, Gt, ut, w.detach(), kap.grad.detach().cpu().numpy(), float(loss)
+    return G, Gt, ut, w.detach(), kap.grad.detach().cpu().numpy(), float(loss.detach())
 
 
 def test_gradient_matches_oracle_small():
