@@ -255,9 +255,9 @@ def cpu_baseline(wl, nboxes):
     L_IB apply per level; a V-cycle performs (nu1 + nu2) box solves per box of
     every level >= 1 and six operator applies per level."""
     import scipy.linalg as la
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import hierarchy, schwarz
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     levels = hierarchy.build(wl)
     fine = levels[-1]
     parts = schwarz.patches(fine.N, wl.box, wl.overlap)
@@ -265,29 +265,43 @@ def cpu_baseline(wl, nboxes):
     sample = parts[::step][:nboxes]
     Lc = fine.L.tocsr()
     facs = [la.lu_factor(Lc[p.idx][:, p.idx].toarray()) for p in sample]
-    rng = np.random.default_rng(0)
-    r = rng.uniform(-1, 1, fine.n)
-    z = np.zeros_like(r)
-    t0 = time.perf_counter()
-    for p, f in zip(sample, facs):
-        y = la.lu_solve(f, r[p.idx])
-        z[p.own_global] = y[p.own_local]
-    t_box = (time.perf_counter() - t0) / len(sample)
-    t_ops = 0.0
-    for lev in levels:
-        w = rng.uniform(-1, 1, lev.n)
-        t0 = time.perf_counter()
-        for _ in range(3):
-            lev.L @ w
-        t_ops += 6 * (time.perf_counter() - t0) / 3
     box_solves = (wl.nu1 + wl.nu2) * sum(len(schwarz.patches(l.N, wl.box, wl.overlap)) for l in levels[1:])
-    t_vc = box_solves * t_box + t_ops
+
+    def timed():
+        rng = np.random.default_rng(0)
+        r = rng.uniform(-1, 1, fine.n)
+        z = np.zeros_like(r)
+        t0 = time.perf_counter()
+        for p, f in zip(sample, facs):
+            y = la.lu_solve(f, r[p.idx])
+            z[p.own_global] = y[p.own_local]
+        t_box = (time.perf_counter() - t0) / len(sample)
+        t_ops = 0.0
+        for lev in levels:
+            w = rng.uniform(-1, 1, lev.n)
+            t0 = time.perf_counter()
+            for _ in range(3):
+                lev.L @ w
+            t_ops += 6 * (time.perf_counter() - t0) / 3
+        return t_box, t_ops, box_solves * t_box + t_ops
+
+    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    t_box, t_ops, t_vc = timed()
+    with threadpool_limits(limits=1, user_api="blas"):
+        _, _, t_vc1 = timed()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / t_vc, "unit": "V-cycles/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle on the N={wl.N} annulus: {len(sample)} of {len(parts)} finest boxes "
                        f"(LU solve + scatter, {t_box * 1e3:.3f} ms/box) scaled to the {box_solves} box "
                        f"solves of one V-cycle, plus 6 sparse L_IB applies per level "
-                       f"({t_ops * 1e3:.1f} ms); factorisation and set-up excluded"),
-            "vcycle_s": t_vc}
+                       f"({t_ops * 1e3:.1f} ms); factorisation and set-up excluded; cores = BLAS threads"),
+            "vcycle_s": t_vc, "cpu_model": model, "host_cpus": os.cpu_count(),
+            "single_thread": {"value": 1.0 / t_vc1, "vcycle_s": t_vc1}}
 
 
 def main():
@@ -338,8 +352,10 @@ def main():
     i64, i32 = recs[-1]
     diff = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
 
-    # standalone V-cycle throughput (back-to-back, FP64 and FP32 smoother)
-    def vc_rate(g, reps=20):
+    # standalone V-cycle throughput (100 back-to-back calls on a fixed r, FP64
+    # and FP32 smoother, graph-replayed; and FP64 launched kernel by kernel
+    # from a handle made with IBMG_GRAPH=0)
+    def vc_rate(g, reps=100):
         r = torch.from_numpy(b_h).to(dev)
         z = torch.empty_like(r)
         g.vcycle(r, out=z)
@@ -351,6 +367,17 @@ def main():
         return reps / (time.perf_counter() - t)
 
     vc64, vc32 = vc_rate(g64), vc_rate(g32)
+    prev = os.environ.get("IBMG_GRAPH")
+    os.environ["IBMG_GRAPH"] = "0"
+    try:
+        g64e = StokesIB(wl, precision="fp64")
+    finally:
+        if prev is None:
+            del os.environ["IBMG_GRAPH"]
+        else:
+            os.environ["IBMG_GRAPH"] = prev
+    vc64e = vc_rate(g64e)
+    g64e.close()
 
     # roofline of the dominant kernel: k_ras_ib<double>, the finest level's
     # Schwarz boxes with their own inverse (HBM streaming of the owned
@@ -408,7 +435,7 @@ def main():
         "iters_fp64": i64["iters"], "iters_fp32": i32["iters"],
         "rel_res_true_fp64": i64["rel_res_true"], "rel_res_true_fp32": i32["rel_res_true"],
         "fp32_vs_fp64_rel_diff": diff,
-        "vcycles_per_s_fp64": vc64, "vcycles_per_s_fp32": vc32,
+        "vcycles_per_s_fp64": vc64, "vcycles_per_s_fp32": vc32, "vcycles_per_s_fp64_no_graph": vc64e,
         "setup_s_fp64": t_setup64, "setup_s_fp32": t_setup32,
         "roofline": {"bound": "hbm", "kernel": "k_ras_ib<double> (finest level)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

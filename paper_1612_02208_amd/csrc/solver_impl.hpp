@@ -807,7 +807,7 @@ class Solver final : public SolverBase {
 
   // The unique box inverses of every Schwarz level: assembled per level,
   // inverted in batches that mix levels whose boxes have the same number of
-  // unknowns (one Gauss-Jordan sweep serves them all), owned rows extracted
+  // unknowns (one run of block sweeps serves them all), owned rows extracted
   // per level.  Batches hold as many matrices as half the free device memory
   // (at most 16 GiB) allows, and at most 512.
   void build_boxes(hipStream_t s) {
