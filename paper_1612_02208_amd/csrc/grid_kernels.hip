@@ -434,7 +434,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_dots(const T* __restrict__ V, int nvec, size_t stride,
                                               const T* __restrict__ t, BSeg sg,
                                               double* __restrict__ partial, size_t pstride) {
-  __shared__ double red[8][256];
+  __shared__ double red[32];
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
   const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
@@ -454,18 +454,7 @@ __global__ void __launch_bounds__(256) k_dots(const T* __restrict__ V, int nvec,
       for (int q = 0; q < 8; ++q)
         if (q < nv) acc[q] += (double)V[(size_t)(v0 + q) * stride + i] * ti;
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) red[q][tid] = acc[q];
-    __syncthreads();
-    for (int sft = 128; sft > 0; sft >>= 1) {
-      if (tid < sft) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) red[q][tid] += red[q][tid + sft];
-      }
-      __syncthreads();
-    }
-    if (tid < nv) partial[(size_t)blockIdx.x * nvec + v0 + tid] = red[tid][0];
-    __syncthreads();
+    block_sums256<8>(acc, nv, red, partial + (size_t)blockIdx.x * nvec + v0, tid);
   }
 }
 
@@ -488,22 +477,27 @@ void launch_dots(const T* V, int nvec, size_t stride, const T* t, size_t n, doub
 __global__ void __launch_bounds__(256) k_dots_finish(const double* __restrict__ partial, int nvec,
                                                      int nblk, size_t pstride, double* out1, double* out2,
                                                      size_t ostride, int mode) {
-  __shared__ double red[256];
+  __shared__ double red[32];
+  __shared__ double sums[8];
   const int tid = threadIdx.x;
   partial += blockIdx.x * pstride;
   out1 += blockIdx.x * ostride;
   if (out2) out2 += blockIdx.x * ostride;
-  for (int q = 0; q < nvec; ++q) {
-    double a = 0.0;
-    for (int b = tid; b < nblk; b += 256) a += partial[(size_t)b * nvec + q];
-    red[tid] = a;
-    __syncthreads();
-    for (int sft = 128; sft > 0; sft >>= 1) {
-      if (tid < sft) red[tid] += red[tid + sft];
-      __syncthreads();
+  for (int q0 = 0; q0 < nvec; q0 += 8) {
+    const int nq = nvec - q0 < 8 ? nvec - q0 : 8;
+    double a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = 0.0;
+    for (int b = tid; b < nblk; b += 256) {
+      const double* pb = partial + (size_t)b * nvec + q0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nq) a[q] += pb[q];
     }
-    if (tid == 0) {
-      const double sres = red[0];
+    block_sums256<8>(a, nq, red, sums, tid);
+    if (tid < nq) {
+      const int q = q0 + tid;
+      const double sres = sums[tid];
       if (mode == 0) {
         out1[q] = sres;
       } else if (mode == 1) {
@@ -747,7 +741,7 @@ void launch_backsolve(const double* H, int ldh, int k, const double* g, double* 
 template <typename T>
 __global__ void __launch_bounds__(256) k_block_sums(const T* __restrict__ a, size_t nn,
                                                     double* __restrict__ partial, size_t bs, size_t pstride) {
-  __shared__ double red[3][256];
+  __shared__ double red[12];
   a += blockIdx.y * bs;
   partial += blockIdx.y * pstride;
   const int tid = threadIdx.x;
@@ -757,19 +751,8 @@ __global__ void __launch_bounds__(256) k_block_sums(const T* __restrict__ a, siz
     s1 += (double)a[nn + i];
     s2 += (double)a[2 * nn + i];
   }
-  red[0][tid] = s0;
-  red[1][tid] = s1;
-  red[2][tid] = s2;
-  __syncthreads();
-  for (int sft = 128; sft > 0; sft >>= 1) {
-    if (tid < sft) {
-      red[0][tid] += red[0][tid + sft];
-      red[1][tid] += red[1][tid + sft];
-      red[2][tid] += red[2][tid + sft];
-    }
-    __syncthreads();
-  }
-  if (tid < 3) partial[(size_t)blockIdx.x * 3 + tid] = red[tid][0];
+  const double v[3] = {s0, s1, s2};
+  block_sums256<3>(v, 3, red, partial + (size_t)blockIdx.x * 3, tid);
 }
 
 template <typename T>

@@ -128,6 +128,30 @@ __device__ __forceinline__ size_t seg_len(const BSeg& g, int s) {
 }
 __device__ __forceinline__ bool seg_on(const BSeg& g, int s) { return !g.active || g.active[s] != 0; }
 
+// Sums of nv <= K per-thread values over a block of 256 threads, in the same
+// fixed order in every block (deterministic): a butterfly over the 64 lanes
+// of each wave (every lane ends with identical bits), then the four wave
+// sums as (w0 + w1) + (w2 + w3).  Threads tid < nv write sum q = tid to
+// out[tid]; red holds 4 K doubles of shared memory.  Every thread of the
+// block must call it (two barriers); out may be shared memory, visible to
+// all threads on return.
+template <int K>
+__device__ __forceinline__ void block_sums256(const double (&v)[K], int nv, double* red, double* out, int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    if (q < nv) {
+      double a = v[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+      if (lane == 0) red[q * 4 + wave] = a;
+    }
+  }
+  __syncthreads();
+  if (tid < nv) out[tid] = (red[tid * 4] + red[tid * 4 + 1]) + (red[tid * 4 + 2] + red[tid * 4 + 3]);
+  __syncthreads();
+}
+
 // Largest RAS box: b + 2 o <= 32 cells per side
 constexpr int kMaxBoxSide = 32;
 constexpr int kMaxNloc = 2 * kMaxBoxSide * (kMaxBoxSide + 1) + kMaxBoxSide * kMaxBoxSide;

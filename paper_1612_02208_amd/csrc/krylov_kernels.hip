@@ -22,21 +22,23 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// out[q] = sum_b partial[b * k + q], q < k, in a fixed tree order.
+// out[q] = sum_b partial[b * k + q], q < k (out in shared memory), eight
+// sums at a time in a fixed order.
 __device__ void reduce_partials(const double* __restrict__ partial, int nblk, int k, double* out,
                                 double* red) {
   const int tid = threadIdx.x;
-  for (int q = 0; q < k; ++q) {
-    double a = 0.0;
-    for (int b = tid; b < nblk; b += kThreads) a += partial[(size_t)b * k + q];
-    red[tid] = a;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
+  for (int q0 = 0; q0 < k; q0 += 8) {
+    const int nq = k - q0 < 8 ? k - q0 : 8;
+    double a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = 0.0;
+    for (int b = tid; b < nblk; b += kThreads) {
+      const double* pb = partial + (size_t)b * k + q0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nq) a[q] += pb[q];
     }
-    if (tid == 0) out[q] = red[0];
-    __syncthreads();
+    block_sums256<8>(a, nq, red, out + q0, tid);
   }
 }
 
@@ -44,7 +46,7 @@ __device__ void reduce_partials(const double* __restrict__ partial, int nblk, in
 // partial[blockIdx.x * k + q]
 template <typename T>
 __device__ void block_dots(const T* __restrict__ V, int k, size_t stride, const T* t, size_t n,
-                           double* __restrict__ partial, double (*red)[kThreads]) {
+                           double* __restrict__ partial, double* red) {
   const int tid = threadIdx.x;
   for (int v0 = 0; v0 < k; v0 += 8) {
     const int nv = k - v0 < 8 ? k - v0 : 8;
@@ -58,18 +60,7 @@ __device__ void block_dots(const T* __restrict__ V, int k, size_t stride, const 
       for (int q = 0; q < 8; ++q)
         if (q < nv) acc[q] += (double)V[(size_t)(v0 + q) * stride + i] * ti;
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) red[q][tid] = acc[q];
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) red[q][tid] += red[q][tid + s];
-      }
-      __syncthreads();
-    }
-    if (tid < nv) partial[(size_t)blockIdx.x * k + v0 + tid] = red[tid][0];
-    __syncthreads();
+    block_sums256<8>(acc, nv, red, partial + (size_t)blockIdx.x * k + v0, tid);
   }
 }
 
@@ -82,7 +73,7 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
                                                        BSeg sg, const double* __restrict__ pin, int nblk_in,
                                                        size_t pstride, double* __restrict__ hcol,
                                                        size_t hstride, double* __restrict__ pout) {
-  __shared__ double red[8][kThreads];
+  __shared__ double red[32];
   __shared__ double h[64];
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
@@ -92,7 +83,7 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
   pin += sy * pstride;
   pout += sy * pstride;
   hcol += sy * hstride;
-  reduce_partials(pin, nblk_in, k, h, red[0]);
+  reduce_partials(pin, nblk_in, k, h, red);
   if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] = h[threadIdx.x];
 #pragma unroll 4
   for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
@@ -111,7 +102,7 @@ __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict
                                                        BSeg sg, const double* __restrict__ pin, int nblk_in,
                                                        size_t pstride, double* __restrict__ hcol,
                                                        size_t hstride, double* __restrict__ pout) {
-  __shared__ double red[8][kThreads];
+  __shared__ double red[32];
   __shared__ double h[64];
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
@@ -121,7 +112,7 @@ __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict
   pin += sy * pstride;
   pout += sy * pstride;
   hcol += sy * hstride;
-  reduce_partials(pin, nblk_in, k, h, red[0]);
+  reduce_partials(pin, nblk_in, k, h, red);
   if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] += h[threadIdx.x];
   double acc = 0.0;
 #pragma unroll 4
@@ -132,13 +123,8 @@ __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict
     t[i] = tn;
     acc += (double)tn * (double)tn;
   }
-  red[0][threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[0][threadIdx.x] += red[0][threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) pout[blockIdx.x] = red[0][0];
+  const double a1[1] = {acc};
+  block_sums256<1>(a1, 1, red, pout + blockIdx.x, threadIdx.x);
 }
 
 // v = t / sqrt(sum partials) (v = 0 on an exact breakdown); block 0 stores the
@@ -148,7 +134,7 @@ __global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, BSeg s
                                                         const double* __restrict__ pin, int nblk_in,
                                                         size_t pstride, double* __restrict__ hout,
                                                         size_t hstride) {
-  __shared__ double red[kThreads];
+  __shared__ double red[32];
   __shared__ double nrm;
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;

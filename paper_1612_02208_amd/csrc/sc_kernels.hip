@@ -382,16 +382,12 @@ void launch_sc_diag(int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, T ih2, T* di
 // x -= (sum of the partial sums of x) / n
 template <typename T>
 __global__ void __launch_bounds__(256) k_sub_mean(T* x, size_t n, const double* __restrict__ partial, int nblk) {
-  __shared__ double red[256];
-  double a = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256) a += partial[b];
-  red[threadIdx.x] = a;
-  __syncthreads();
-  for (int sft = 128; sft > 0; sft >>= 1) {
-    if (threadIdx.x < sft) red[threadIdx.x] += red[threadIdx.x + sft];
-    __syncthreads();
-  }
-  const double mean = red[0] / (double)n;
+  __shared__ double red[4];
+  __shared__ double tot;
+  double a[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256) a[0] += partial[b];
+  block_sums256<1>(a, 1, red, &tot, threadIdx.x);
+  const double mean = tot / (double)n;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     x[i] = (T)((double)x[i] - mean);
 }
