@@ -508,12 +508,12 @@ template <typename T>
 struct Vec16;
 template <>
 struct Vec16<double> {
-  using type = double2;
+  typedef double type __attribute__((ext_vector_type(2)));
   static constexpr int n = 2;
 };
 template <>
 struct Vec16<float> {
-  using type = float4;
+  typedef float type __attribute__((ext_vector_type(4)));
   static constexpr int n = 4;
 };
 
@@ -540,13 +540,16 @@ __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restr
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0;
   int j = j0 + cph;
-  // eight 16-byte loads in flight per lane, summed in a fixed tree
+  // eight 16-byte loads in flight per lane, summed in a fixed tree; the
+  // inverse streams through once per sweep, so its loads are non-temporal
+  // and leave the caches to the level's vectors
   constexpr int UNR = 8;
   for (; j + (UNR - 1) * VEC < j1; j += UNR * VEC) {
     V m[UNR];
     T xv[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) m[u] = *reinterpret_cast<const V*>(Mc + (size_t)(j + u * VEC) * 64);
+    for (int u = 0; u < UNR; ++u)
+      m[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)(j + u * VEC) * 64));
 #pragma unroll
     for (int u = 0; u < UNR; ++u) xv[u] = x[j + u * VEC];
 #pragma unroll
@@ -558,7 +561,7 @@ __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restr
     }
   }
   for (; j < j1; j += VEC) {
-    const V m0 = *reinterpret_cast<const V*>(Mc + (size_t)j * 64);
+    const V m0 = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)j * 64));
     const T* a0 = reinterpret_cast<const T*>(&m0);
     const T x0 = x[j];
 #pragma unroll
