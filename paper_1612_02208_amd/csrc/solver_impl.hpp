@@ -192,9 +192,12 @@ class Solver final : public SolverBase {
         }
         if (l == L_ && c == 0) point_order(lev.N, f, s);
       }
-      for (int c = 0; c < 2; ++c) {  // IB rows need both components' windows
+    }
+    ib_patterns();   // IB rows need both components' windows
+    for (int l = L_; l >= 0; --l) {
+      Level<T>& lev = levels_[l];
+      for (int c = 0; c < 2; ++c) {
         CompFoot& f = lev.f[c];
-        ib_pattern(lev, c);
         f.d_tptr.upload(f.tptr, s);
         f.d_tcol.upload(f.tcol, s);
         f.tval.alloc(f.tcol.size());
@@ -296,60 +299,79 @@ class Solver final : public SolverBase {
   // of every point that shares a spring (or is itself) with a point whose
   // comp-window holds r, in the same component, and with tangent blocks also
   // in the other one.  Columns index [u | v] (v faces offset by N^2), sorted.
-  void ib_pattern(Level<T>& lev, int comp) {
-    const int N = lev.N;
-    CompFoot& f = lev.f[comp];
-    const size_t nf = (size_t)N * N;
-    // rows in chunks claimed by worker threads; each chunk keeps its own
-    // columns and the chunks are joined in order, so the pattern does not
-    // depend on the thread count
+  // The IB rows' columns on every level and component (the Galerkin
+  // pattern): one pool of worker threads takes chunks of rows of all (level,
+  // component) pairs.  Each chunk keeps its own columns and the chunks join
+  // in order, so the pattern does not depend on the thread count.  A worker
+  // marks the columns of the row in hand with a tag it never reuses, so one
+  // stamp array serves every pair without being cleared.
+  void ib_patterns() {
+    struct Task {
+      int l, comp;
+      size_t r0, r1;
+    };
     constexpr size_t kChunk = 2048;
-    const size_t nchunks = (nf + kChunk - 1) / kChunk;
-    std::vector<std::vector<int>> ccols(nchunks), clen(nchunks);
+    std::vector<Task> tasks;
+    std::vector<size_t> first(2 * (size_t)(L_ + 1) + 1, 0);   // first task of pair 2 l + comp
+    for (int l = 0; l <= L_; ++l)
+      for (int c = 0; c < 2; ++c) {
+        first[2 * l + c] = tasks.size();
+        const size_t nf = (size_t)levels_[l].N * levels_[l].N;
+        for (size_t r0 = 0; r0 < nf; r0 += kChunk) tasks.push_back({l, c, r0, std::min(nf, r0 + kChunk)});
+      }
+    first[2 * (size_t)(L_ + 1)] = tasks.size();
+    std::vector<std::vector<int>> ccols(tasks.size()), clen(tasks.size());
+    const size_t nf_max = (size_t)levels_[L_].N * levels_[L_].N;
     std::atomic<size_t> next{0};
     auto worker = [&]() {
-      std::vector<int> stamp(2 * nf, -1);
+      std::vector<int> stamp(2 * nf_max, -1);
       std::vector<int> cols;
-      auto add_point = [&](int q, int r) {
-        for (int c = 0; c < 2; ++c) {
-          if (c != comp && !tangent_) continue;
-          const CompFoot& fc = lev.f[c];
-          for (int s = 0; s < 16; ++s) {
-            if (!((fc.mask[q] >> s) & 1)) continue;
-            const int col = c * (int)nf + face_of(fc, q, s, N);
-            if (stamp[col] != r) {
-              stamp[col] = r;
-              cols.push_back(col);
+      int tag = -1;
+      for (;;) {
+        const size_t ti = next++;
+        if (ti >= tasks.size()) break;
+        const Task& tk = tasks[ti];
+        const Level<T>& lev = levels_[tk.l];
+        const int N = lev.N;
+        const size_t nf = (size_t)N * N;
+        const CompFoot& f = lev.f[tk.comp];
+        auto add_point = [&](int q) {
+          for (int c = 0; c < 2; ++c) {
+            if (c != tk.comp && !tangent_) continue;
+            const CompFoot& fc = lev.f[c];
+            for (int sl = 0; sl < 16; ++sl) {
+              if (!((fc.mask[q] >> sl) & 1)) continue;
+              const int col = c * (int)nf + face_of(fc, q, sl, N);
+              if (stamp[col] != tag) {
+                stamp[col] = tag;
+                cols.push_back(col);
+              }
             }
           }
-        }
-      };
-      for (;;) {
-        const size_t ch = next++;
-        if (ch >= nchunks) break;
-        const size_t r0 = ch * kChunk, r1 = std::min(nf, r0 + kChunk);
-        std::vector<int>& out = ccols[ch];
-        std::vector<int>& len = clen[ch];
-        len.assign(r1 - r0, 0);
-        for (size_t r = r0; r < r1; ++r) {
+        };
+        std::vector<int>& out = ccols[ti];
+        std::vector<int>& len = clen[ti];
+        len.assign(tk.r1 - tk.r0, 0);
+        for (size_t r = tk.r0; r < tk.r1; ++r) {
           if (f.sp_ptr[r + 1] == f.sp_ptr[r]) continue;
+          ++tag;
           cols.clear();
           for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
             const int l = f.sp_ent[e] >> 4;
             if (adj_ptr_[l + 1] == adj_ptr_[l]) continue;
-            add_point(l, (int)r);
-            for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a], (int)r);
+            add_point(l);
+            for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a]);
           }
           std::sort(cols.begin(), cols.end());
           out.insert(out.end(), cols.begin(), cols.end());
-          len[r - r0] = (int)cols.size();
+          len[r - tk.r0] = (int)cols.size();
         }
       }
     };
-    // each worker keeps a stamp over [u | v]: at most 1 GiB of stamps in all
-    const size_t by_mem = std::max<size_t>(1, ((size_t)1 << 30) / (2 * nf * sizeof(int)));
+    // each worker keeps a stamp over the finest [u | v]: at most 1 GiB in all
+    const size_t by_mem = std::max<size_t>(1, ((size_t)1 << 30) / (2 * nf_max * sizeof(int)));
     const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nth = std::min({(size_t)16, hw, by_mem, nchunks});
+    const size_t nth = std::min({(size_t)16, hw, by_mem, tasks.size()});
     if (nth <= 1) {
       worker();
     } else {
@@ -357,17 +379,22 @@ class Solver final : public SolverBase {
       for (size_t t = 0; t < nth; ++t) th.emplace_back(worker);
       for (auto& t : th) t.join();
     }
-    f.tptr.assign(nf + 1, 0);
-    size_t tot = 0;
-    for (size_t ch = 0; ch < nchunks; ++ch) tot += ccols[ch].size();
-    f.tcol.clear();
-    f.tcol.reserve(tot);
-    for (size_t ch = 0; ch < nchunks; ++ch) {
-      const size_t r0 = ch * kChunk;
-      for (size_t i = 0; i < clen[ch].size(); ++i) f.tptr[r0 + i + 1] = clen[ch][i];
-      f.tcol.insert(f.tcol.end(), ccols[ch].begin(), ccols[ch].end());
-    }
-    for (size_t r = 0; r < nf; ++r) f.tptr[r + 1] += f.tptr[r];
+    for (int l = 0; l <= L_; ++l)
+      for (int c = 0; c < 2; ++c) {
+        CompFoot& f = levels_[l].f[c];
+        const size_t nf = (size_t)levels_[l].N * levels_[l].N;
+        const size_t t0 = first[2 * l + c], t1 = first[2 * l + c + 1];
+        f.tptr.assign(nf + 1, 0);
+        size_t tot = 0;
+        for (size_t t = t0; t < t1; ++t) tot += ccols[t].size();
+        f.tcol.clear();
+        f.tcol.reserve(tot);
+        for (size_t t = t0; t < t1; ++t) {
+          for (size_t i = 0; i < clen[t].size(); ++i) f.tptr[tasks[t].r0 + i + 1] = clen[t][i];
+          f.tcol.insert(f.tcol.end(), ccols[t].begin(), ccols[t].end());
+        }
+        for (size_t r = 0; r < nf; ++r) f.tptr[r + 1] += f.tptr[r];
+      }
   }
 
   // A box needs its own inverse when one of its faces carries an IB row;
