@@ -340,24 +340,32 @@ __device__ __forceinline__ double window_weight(const FootView<double>& f, const
 // summing over the springs with an end whose comp-window holds r (a spring
 // with both ends there is counted once, from its lower-numbered end), and
 // over the components c that K_e couples (c = comp for the linear model).
-// Columns index the level's [u | v] vector.  One wave per row: every lane
-// walks the row's (point, spring) pairs in the same order and accumulates
-// the columns it owns (pattern entries lane, lane + 64, ...), so each entry
-// is a fixed-order sum.
+// Columns index the level's [u | v] vector.  One wave per row and slice:
+// every lane walks the slice's (point, spring) pairs in the same order and
+// accumulates the columns it owns (pattern entries lane, lane + 64, ...), so
+// each entry is a fixed-order sum.  With nslice > 1 the row's point list is
+// cut into nslice contiguous slices (for coarse levels, whose faces carry
+// thousands of points), slice s writes its sums to part[s * nnz + k], and
+// k_t_sum adds the slices in order.
 __global__ void __launch_bounds__(256) k_t_values(FootView<double> f0, FootView<double> f1,
                                                   const int* __restrict__ mask0, const int* __restrict__ mask1,
                                                   SpringView<double> sv, int comp, int N, double ibs,
                                                   const int* __restrict__ t_ptr, const int* __restrict__ t_col,
-                                                  double* __restrict__ t_val) {
-  const int r = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+                                                  double* __restrict__ t_val, int nslice, size_t nnz,
+                                                  double* __restrict__ part) {
+  const size_t wv = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int NN = N * N;
-  if (r >= NN) return;
+  if (wv >= (size_t)NN * nslice) return;
+  const int r = (int)(wv / nslice), sl = (int)(wv % nslice);
   const int lo = t_ptr[r], hi = t_ptr[r + 1];
   if (hi == lo) return;
   const FootView<double>& f = comp ? f1 : f0;
   const int* mask = comp ? mask1 : mask0;
   const int ri = r % N, rj = r / N;
+  const int el = f.sp_ptr[r], elen = f.sp_ptr[r + 1] - el;
+  const int e0 = el + (int)((long long)elen * sl / nslice), e1 = el + (int)((long long)elen * (sl + 1) / nslice);
+  double* out = nslice > 1 ? part + (size_t)sl * nnz : t_val;
   for (int k = lo + lane; k - lane < hi; k += 64) {
     const bool live = k < hi;
     const int col = live ? t_col[k] : 0;
@@ -367,7 +375,7 @@ __global__ void __launch_bounds__(256) k_t_values(FootView<double> f0, FootView<
     const FootView<double>& fc = c ? f1 : f0;
     const int* mc = c ? mask1 : mask0;
     double acc = 0.0;
-    for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
+    for (int e = e0; e < e1; ++e) {
       const int l = f.sp_ent[e] >> 4;
       const double wl_r = f.sw[e];
       const int a0 = sv.adj_ptr[l], a1 = sv.adj_ptr[l + 1];
@@ -386,17 +394,33 @@ __global__ void __launch_bounds__(256) k_t_values(FootView<double> f0, FootView<
         acc += coef * (window_weight(fc, mc, q, ci, cj, N) - wl_c);
       }
     }
-    if (live) t_val[k] = acc;
+    if (live) out[k] = acc;
+  }
+}
+
+// t_val[k] = sum over the slices of part[s * nnz + k], slices in order
+__global__ void k_t_sum(const double* __restrict__ part, int nslice, size_t nnz, double* __restrict__ t_val) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nnz; k += (size_t)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int sl = 0; sl < nslice; ++sl) a += part[(size_t)sl * nnz + k];
+    t_val[k] = a;
   }
 }
 
 void launch_t_values(FootView<double> f0, FootView<double> f1, const int* mask0, const int* mask1,
                      SpringView<double> sv, int comp, int N, double ibs, const int* t_ptr, const int* t_col,
-                     double* t_val, hipStream_t s) {
+                     double* t_val, int nslice, size_t nnz, double* part, hipStream_t s) {
+  if (nslice < 1 || (nslice > 1 && !part)) throw Error(IBMG_ERR_ARG, "IB-row slices need a partial buffer");
   const size_t n = (size_t)N * N;
-  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n * 64, 256)), dim3(256), 0, s, f0, f1, mask0, mask1, sv, comp, N, ibs,
-                     t_ptr, t_col, t_val);
+  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n * nslice * 64, 256)), dim3(256), 0, s, f0, f1, mask0, mask1, sv, comp,
+                     N, ibs, t_ptr, t_col, t_val, nslice, nnz, part);
   IBMG_LAUNCH_CHECK();
+  if (nslice > 1) {
+    int grid = cdiv(nnz, 256);
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_t_sum, dim3(grid < 1 ? 1 : grid), dim3(256), 0, s, part, nslice, nnz, t_val);
+    IBMG_LAUNCH_CHECK();
+  }
 }
 
 // g_e = scale * (Ul_b - Ul_a)^T B_e (Uw_b - Uw_a), U interleaved [M][2],

@@ -246,10 +246,12 @@ void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M
                    T* U, hipStream_t s);
 void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, int M, int N,
                    double scale, double* f, hipStream_t s);
-// rows of component comp; f0/f1 and mask0/mask1 the level's two components
+// rows of component comp; f0/f1 and mask0/mask1 the level's two components.
+// nslice > 1 splits each row's point list over that many waves, whose sums
+// go to part (nslice x nnz doubles) and are added in slice order.
 void launch_t_values(FootView<double> f0, FootView<double> f1, const int* mask0, const int* mask1,
                      SpringView<double> sv, int comp, int N, double ibs, const int* t_ptr,
-                     const int* t_col, double* t_val, hipStream_t s);
+                     const int* t_col, double* t_val, int nslice, size_t nnz, double* part, hipStream_t s);
 // semi-implicit time step pieces (Sec. 2.2): spring forces on the periodic
 // square, the step's right-hand side, the position update
 // kap: kappa_e per incidence; rest: rest length per incidence, nullptr for

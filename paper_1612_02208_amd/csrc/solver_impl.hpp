@@ -649,8 +649,14 @@ class Solver final : public SolverBase {
       for (int c = 0; c < 2; ++c) {
         CompFoot& f = lev.f[c];
         if (!f.tcol.empty()) {
+          // faces of coarse levels carry thousands of points: their rows'
+          // point lists are shared out over several waves
+          const int nslice = std::min(32, std::max(1, f.max_list / 64));
+          const size_t nnz = f.tcol.size();
+          if (nslice > 1 && tpart_.n < (size_t)nslice * nnz) tpart_.alloc((size_t)nslice * nnz);
           launch_t_values(fview<double>(lev.f[0]), fview<double>(lev.f[1]), lev.f[0].d_mask.p, lev.f[1].d_mask.p,
-                          sview<double>(), c, lev.N, lev.cd.ibs, f.d_tptr.p, f.d_tcol.p, f.tval.p, s);
+                          sview<double>(), c, lev.N, lev.cd.ibs, f.d_tptr.p, f.d_tcol.p, f.tval.p, nslice, nnz,
+                          tpart_.p, s);
           if (std::is_same<T, float>::value)
             launch_cast<double, float>(f.tval.p, f.tvalf.p, f.tcol.size(), s);
         }
@@ -1542,6 +1548,7 @@ class Solver final : public SolverBase {
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t gexec_ = nullptr;
   DBuf<double> vin_, vout_;
+  DBuf<double> tpart_;   // slice sums of the IB-row values on coarse levels
 
   static bool graphs_enabled() {
     const char* e = std::getenv("IBMG_GRAPH");
