@@ -1272,6 +1272,7 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug
   __shared__ double vmax[1024];
   __shared__ int imax[1024];
   __shared__ double fac[1024];
+  __shared__ double rowk[2048];   // the scaled pivot row (2 nn <= 2048)
   const int ld = 2 * nn;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int k = 0; k < nn; ++k) {
@@ -1303,20 +1304,27 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug
     __syncthreads();
     const double ip = 1.0 / aug[(size_t)k * ld + k];
     __syncthreads();
-    for (int j = tid; j < ld; j += nt) aug[(size_t)k * ld + j] *= ip;
+    for (int j = tid; j < ld; j += nt) {
+      const double v = aug[(size_t)k * ld + j] * ip;
+      aug[(size_t)k * ld + j] = v;
+      rowk[j] = v;
+    }
     for (int i = tid; i < nn; i += nt) fac[i] = aug[(size_t)i * ld + k];
     __syncthreads();
-    for (size_t t = tid; t < (size_t)nn * ld; t += nt) {
-      const int i = (int)(t / ld);
+    // a wave per row, its lanes along the row
+    const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
+    for (int i = wave; i < nn; i += nw) {
       if (i == k) continue;
-      const int j = (int)(t % ld);
-      aug[t] -= fac[i] * aug[(size_t)k * ld + j];
+      const double fi = fac[i];
+      double* Ai = aug + (size_t)i * ld;
+      for (int j = lane; j < ld; j += 64) Ai[j] -= fi * rowk[j];
     }
     __syncthreads();
   }
 }
 
 void launch_coarse_invert(double* aug, int nn, hipStream_t s) {
+  if (nn > 1024) throw Error(IBMG_ERR_ARG, "coarsest system too large for one work-group");
   hipLaunchKernelGGL(k_coarse_invert, dim3(1), dim3(1024), 0, s, aug, nn);
   IBMG_LAUNCH_CHECK();
 }
