@@ -46,7 +46,22 @@ class BatchSolver final : public BatchBase {
     order_.resize(nsys);
     std::iota(order_.begin(), order_.end(), 0);
     std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) { return d[a].N > d[b].N; });
-    for (int p = 0; p < nsys; ++p) sys_.emplace_back(new Solver<T>(d[order_[p]], s));
+    for (int p = 0; p < nsys; ++p) sys_.emplace_back(new Solver<T>(d[order_[p]], s, true));
+    {
+      // every system's bordered coarsest system has the same size (shared
+      // coarse_N and rho): all are inverted in one launch
+      const int nn = sys_[0]->nn0_;
+      const size_t stride = (size_t)nn * 2 * nn;
+      DBuf<double> augs(stride * nsys);
+      for (int p = 0; p < nsys; ++p) {
+        require(sys_[p]->nn0_ == nn && sys_[p]->aug0_.n == stride, "coarsest systems differ in size");
+        IBMG_HIP(hipMemcpyAsync(augs.p + p * stride, sys_[p]->aug0_.p, stride * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+      }
+      launch_coarse_invert(augs.p, nn, nsys, stride, s);
+      for (int p = 0; p < nsys; ++p) sys_[p]->finish_coarse(augs.p + p * stride, s);
+      IBMG_HIP(hipStreamSynchronize(s));
+    }
     Lmax_ = sys_[0]->L_;
     nact_.assign(Lmax_ + 2, 0);
     for (int p = 0; p < nsys; ++p)

@@ -1268,11 +1268,12 @@ void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, cons
   IBMG_LAUNCH_CHECK();
 }
 
-__global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug, int nn) {
+__global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug, int nn, size_t stride) {
   __shared__ double vmax[1024];
   __shared__ int imax[1024];
   __shared__ double fac[1024];
   __shared__ double rowk[2048];   // the scaled pivot row (2 nn <= 2048)
+  aug += blockIdx.x * stride;     // one system per work-group
   const int ld = 2 * nn;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int k = 0; k < nn; ++k) {
@@ -1323,9 +1324,10 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug
   }
 }
 
-void launch_coarse_invert(double* aug, int nn, hipStream_t s) {
+void launch_coarse_invert(double* aug, int nn, int count, size_t stride, hipStream_t s) {
   if (nn > 1024) throw Error(IBMG_ERR_ARG, "coarsest system too large for one work-group");
-  hipLaunchKernelGGL(k_coarse_invert, dim3(1), dim3(1024), 0, s, aug, nn);
+  if (count < 1) return;
+  hipLaunchKernelGGL(k_coarse_invert, dim3(count), dim3(1024), 0, s, aug, nn, stride);
   IBMG_LAUNCH_CHECK();
 }
 

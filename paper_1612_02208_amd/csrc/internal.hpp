@@ -298,7 +298,8 @@ int ras_ib_ksplit(const BoxGeom& g, int n_ib);
 void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,
                             const double* tval_u, const int* tptr_v, const int* tcol_v,
                             const double* tval_v, int nb, double* aug, hipStream_t s);
-void launch_coarse_invert(double* aug, int n, hipStream_t s);
+// count augmented systems [A | I] (n x 2n each, stride doubles apart), a work-group each
+void launch_coarse_invert(double* aug, int n, int count, size_t stride, hipStream_t s);
 void launch_coarse_extract(const double* aug, int n, int n0, double* inv, hipStream_t s);
 template <typename T>
 void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_t s);

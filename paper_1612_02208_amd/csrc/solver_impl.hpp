@@ -100,7 +100,10 @@ class Solver final : public SolverBase {
   friend class BatchSolver<T>;
 
  public:
-  Solver(const ibmg_desc& d, hipStream_t s) : d_(d) {
+  // defer_coarse: assemble the coarsest system but leave its inversion to
+  // the caller (the batched form inverts every system's in one launch and
+  // hands each back through finish_coarse)
+  Solver(const ibmg_desc& d, hipStream_t s, bool defer_coarse = false) : d_(d), defer_coarse_(defer_coarse) {
     M_ = d.M;
     E_ = d.n_springs;
     X_.assign(d.X, d.X + 2 * (size_t)M_);
@@ -804,14 +807,28 @@ class Solver final : public SolverBase {
     const int nb = d_.rho == 0.0 ? 3 : 1;
     n0_ = 3 * N * N;
     const int nn = n0_ + nb;
+    nn0_ = nn;
     DBuf<double> aug((size_t)nn * 2 * nn);
     launch_fill<double>(aug.p, 0.0, aug.n, s);
     launch_coarse_assemble(N, lev.cd, lev.f[0].d_tptr.p, lev.f[0].d_tcol.p, lev.f[0].tval.p,
                            lev.f[1].d_tptr.p, lev.f[1].d_tcol.p, lev.f[1].tval.p, nb, aug.p, s);
-    launch_coarse_invert(aug.p, nn, s);
+    if (defer_coarse_) {
+      aug0_ = std::move(aug);
+      IBMG_HIP(hipStreamSynchronize(s));
+      return;
+    }
+    launch_coarse_invert(aug.p, nn, 1, 0, s);
     inv0_.alloc((size_t)n0_ * n0_);
     launch_coarse_extract(aug.p, nn, n0_, inv0_.p, s);
     IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  // the coarsest inverse from the caller's inverted copy of aug0_
+  void finish_coarse(const double* inverted, hipStream_t s) {
+    inv0_.alloc((size_t)n0_ * n0_);
+    launch_coarse_extract(inverted, nn0_, n0_, inv0_.p, s);
+    aug0_.release();
+    defer_coarse_ = false;
   }
 
   // Box lists, slice buffers and the inverse storage of one level.
@@ -1549,6 +1566,9 @@ class Solver final : public SolverBase {
   hipGraphExec_t gexec_ = nullptr;
   DBuf<double> vin_, vout_;
   DBuf<double> tpart_;   // slice sums of the IB-row values on coarse levels
+  bool defer_coarse_ = false;
+  int nn0_ = 0;          // size of the bordered coarsest system
+  DBuf<double> aug0_;    // its assembled [A | I] while the inversion is deferred
 
   static bool graphs_enabled() {
     const char* e = std::getenv("IBMG_GRAPH");
