@@ -49,18 +49,23 @@ class BatchSolver final : public BatchBase {
     for (int p = 0; p < nsys; ++p) sys_.emplace_back(new Solver<T>(d[order_[p]], s, true));
     {
       // every system's bordered coarsest system has the same size (shared
-      // coarse_N and rho): all are inverted in one launch
+      // coarse_N and rho): they are inverted a group at a time, one launch
+      // per group of up to 1 GiB of augmented matrices
       const int nn = sys_[0]->nn0_;
       const size_t stride = (size_t)nn * 2 * nn;
-      DBuf<double> augs(stride * nsys);
-      for (int p = 0; p < nsys; ++p) {
-        require(sys_[p]->nn0_ == nn && sys_[p]->aug0_.n == stride, "coarsest systems differ in size");
-        IBMG_HIP(hipMemcpyAsync(augs.p + p * stride, sys_[p]->aug0_.p, stride * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
+      const int grp = (int)std::max<size_t>(1, std::min<size_t>(nsys, ((size_t)1 << 27) / stride));
+      DBuf<double> augs(stride * grp);
+      for (int p0 = 0; p0 < nsys; p0 += grp) {
+        const int cnt = std::min(grp, nsys - p0);
+        for (int p = p0; p < p0 + cnt; ++p) {
+          require(sys_[p]->nn0_ == nn && sys_[p]->aug0_.n == stride, "coarsest systems differ in size");
+          IBMG_HIP(hipMemcpyAsync(augs.p + (p - p0) * stride, sys_[p]->aug0_.p, stride * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+        launch_coarse_invert(augs.p, nn, cnt, stride, s);
+        for (int p = p0; p < p0 + cnt; ++p) sys_[p]->finish_coarse(augs.p + (p - p0) * stride, s);
+        IBMG_HIP(hipStreamSynchronize(s));
       }
-      launch_coarse_invert(augs.p, nn, nsys, stride, s);
-      for (int p = 0; p < nsys; ++p) sys_[p]->finish_coarse(augs.p + p * stride, s);
-      IBMG_HIP(hipStreamSynchronize(s));
     }
     Lmax_ = sys_[0]->L_;
     nact_.assign(Lmax_ + 2, 0);

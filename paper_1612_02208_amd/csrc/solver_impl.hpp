@@ -654,8 +654,9 @@ class Solver final : public SolverBase {
         if (!f.tcol.empty()) {
           // faces of coarse levels carry thousands of points: their rows'
           // point lists are shared out over several waves
-          const int nslice = std::min(32, std::max(1, f.max_list / 64));
           const size_t nnz = f.tcol.size();
+          int nslice = std::min(32, std::max(1, f.max_list / 64));
+          while (nslice > 1 && (size_t)nslice * nnz > ((size_t)1 << 27)) nslice /= 2;   // <= 1 GiB of slices
           if (nslice > 1 && tpart_.n < (size_t)nslice * nnz) tpart_.alloc((size_t)nslice * nnz);
           launch_t_values(fview<double>(lev.f[0]), fview<double>(lev.f[1]), lev.f[0].d_mask.p, lev.f[1].d_mask.p,
                           sview<double>(), c, lev.N, lev.cd.ibs, f.d_tptr.p, f.d_tcol.p, f.tval.p, nslice, nnz,
