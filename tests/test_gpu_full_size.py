@@ -18,7 +18,10 @@ configuration the benchmark runs (default handles, V-cycle graphs on).
     deterministic and positively homogeneous, bit for bit (scaling the input
     by 2 scales every intermediate exactly, FGMRES smoothing included);
   - the FGMRES solve to 1e-8 in both precisions: the true residual under the
-    oracle's operator, and the FP32-smoother solution against the FP64 one.
+    oracle's operator, and the FP32-smoother solution against the FP64 one;
+  - the same annulus with tangent springs at 0.7 of their lengths: the
+    operator with its 2 x 2 blocks on the whole vector, and the solve to 1e-8
+    in both precisions through its true residual.
 * The 256 x 256 Stokes membrane (1024 points, 6 levels) with kappa over
   {1e0, 1e2, 1e4, 1e6}, RAS and the Schur-complement smoother side by side:
   the whole oracle runs here, so FGMRES after a fixed number of iterations
@@ -157,6 +160,40 @@ def test_a512_solve_both_precisions(a512):
         xs[prec] = xh
     # both meet the same residual; the solutions agree to what that allows
     assert rel(xs["fp32"], xs["fp64"]) < 1e-6
+
+
+def test_a512_tangent_springs_operator_and_solve():
+    """The same annulus with tangent springs at 0.7 of their lengths (every
+    spring stretched; Sec. 5 fibre model, Sec. 6 linearised force), as the
+    benchmark runs it: the operator with the 2 x 2 blocks against the
+    oracle's on the whole vector, and the solve to 1e-8 in both precisions
+    through its true residual under that operator."""
+    from paper_1612_02208_amd import StokesIB
+    wl = W.annulus_512()
+    wl.box, wl.overlap = 16, 4
+    d = wl.X[wl.springs[:, 1]] - wl.X[wl.springs[:, 0]]
+    d -= np.round(d)
+    wl.spring_model, wl.rest = "tangent", 0.7 * np.hypot(d[:, 0], d[:, 1])
+    print(f"[case] {wl.name} tangent N={wl.N} M={wl.M}", flush=True)
+    N = wl.N
+    IB = oib.ib_term_tangent(wl.X, wl.springs, wl.kappa, wl.rest, N, wl.dt)
+    A = mac.momentum(N, wl.rho, wl.mu, wl.dt) + IB
+    L = mac.stokes_ib(A.tocsr(), mac.gradient(N), mac.divergence(N)).tocsr()
+    b = W.rhs(N, 0)
+    bp = hierarchy.project_range(b, N, wl.rho)
+    for prec in ("fp64", "fp32"):
+        g = StokesIB(wl, precision=prec)
+        try:
+            if prec == "fp64":
+                w = np.random.default_rng(35).uniform(-1, 1, L.shape[0])
+                assert rel(host(g.apply(dev(w))), L @ w) < OPS_TOL
+            x, info = g.solve(dev(b), rtol=1e-8)
+            assert info["converged"], (prec, info)
+            true = np.linalg.norm(bp - L @ host(x)) / np.linalg.norm(bp)
+            print(f"  {prec}: {info['iters']} iterations, true rel. residual {true:.3e}", flush=True)
+            assert true <= 1.2e-8, (prec, true)
+        finally:
+            g.close()
 
 
 # ------------------------------------- 256 x 256 membrane, kappa sweep, RAS / SC
