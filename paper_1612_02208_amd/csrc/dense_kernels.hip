@@ -605,17 +605,26 @@ __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __re
                   part, acc, cb < ce ? cb : ce, ce, pout);
 }
 
-// z[owned rows of IB box b] (=, or += with acc) the sum of the column
-// slices' row sums, in slice order.
+// z[owned rows] (=, or += with acc) the sum of a split launch's slices, in
+// slice order, for the IB boxes (pa: ksa slices of na boxes) and the interior
+// boxes (pb: ksb slices of nb boxes) of one sweep in one launch; slice sl of
+// box b holds row `row` at p[(sl * n + b) * nch * 64 + row].  A list that was
+// not split has n = 0.
 template <typename T>
-__global__ void k_ras_ib_sum(const T* __restrict__ spart, T* __restrict__ z, BoxGeom g,
-                             const int* __restrict__ boxes, int n_ib, int ks, bool acc) {
-  const size_t tot = (size_t)n_ib * g.nown;
+__global__ void k_ras_sum(const T* __restrict__ pa, const int* __restrict__ ba, int na, int ksa,
+                          const T* __restrict__ pb, const int* __restrict__ bb, int nb, int ksb,
+                          T* __restrict__ z, BoxGeom g, bool acc) {
+  const int nown_pad = g.nch * 64;
+  const size_t ta = (size_t)na * g.nown, tot = ta + (size_t)nb * g.nown;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(t / g.nown), row = (int)(t % g.nown);
+    const bool first = t < ta;
+    const size_t u = first ? t : t - ta;
+    const int b = (int)(u / g.nown), row = (int)(u % g.nown);
+    const T* p = first ? pa : pb;
+    const int n = first ? na : nb, ks = first ? ksa : ksb;
     T a = 0;
-    for (int sl = 0; sl < ks; ++sl) a += spart[(((size_t)sl * n_ib + b) * g.nch + row / 64) * 64 + row % 64];
-    const size_t o = own_glob(g, boxes[b], row);
+    for (int sl = 0; sl < ks; ++sl) a += p[((size_t)sl * n + b) * nown_pad + row];
+    const size_t o = own_glob(g, (first ? ba : bb)[b], row);
     z[o] = acc ? z[o] + a : a;
   }
 }
@@ -945,21 +954,6 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
                       loc_tab, nullptr, part, sm, acc);
 }
 
-// z[owned rows of interior box b] = sum over the reduction slices, in order.
-template <typename T>
-__global__ void k_ras_interior_sum(const T* __restrict__ part, T* __restrict__ z, BoxGeom g,
-                                   const int* __restrict__ boxes, int nlist, int ksplit, bool acc) {
-  const int nown_pad = g.nch * 64;
-  const size_t tot = (size_t)nlist * g.nown;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(t / g.nown), row = (int)(t % g.nown);
-    T a = 0;
-    for (int s = 0; s < ksplit; ++s) a += part[((size_t)s * nlist + b) * nown_pad + row];
-    const size_t o = own_glob(g, boxes[b], row);
-    z[o] = acc ? z[o] + a : a;
-  }
-}
-
 // Reduction slices for the interior product: enough blocks to cover the
 // device (>= 768) while every slice keeps at least two column chunks.
 int ras_interior_ksplit(const BoxGeom& g, int n_int) {
@@ -1083,21 +1077,22 @@ template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
                       T* part, hipStream_t s, int parts, bool acc, int tb, T* xg, size_t xg_elems) {
-  if ((parts & 1) && n_ib > 0) {
+  // slices of a split IB launch first in part, those of the interior product
+  // after them; one sum launch finishes both
+  const bool do_ib = (parts & 1) && n_ib > 0, do_int = (parts & 2) && n_int > 0;
+  const int ks_ib = do_ib ? ras_ib_ksplit(g, n_ib) : 1;
+  const int ks_int = do_int ? ras_interior_ksplit(g, n_int) : 1;
+  const size_t nown_pad = (size_t)g.nch * 64;
+  T* ipart = part;
+  T* tpart = part + (ks_ib > 1 ? (size_t)ks_ib * n_ib * nown_pad : 0);
+  if (do_ib) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
-    const int ks = ras_ib_ksplit(g, n_ib);
-    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch, ks), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc, part);
+    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch, ks_ib), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc,
+                       ipart);
     IBMG_LAUNCH_CHECK();
-    if (ks > 1) {
-      const size_t tot = (size_t)n_ib * g.nown;
-      int grid = cdiv(tot, 256);
-      if (grid > 4096) grid = 4096;
-      hipLaunchKernelGGL((k_ras_ib_sum<T>), dim3(grid), dim3(256), 0, s, part, z, g, ib_boxes, n_ib, ks, acc);
-      IBMG_LAUNCH_CHECK();
-    }
   }
-  if ((parts & 2) && n_int > 0) {
-    const int ks = ras_interior_ksplit(g, n_int);
+  if (do_int) {
+    const int ks = ks_int;
     if (tb == 128 && xg && xg_elems >= int_gather_elems(g, n_int)) {
       const int nbp = (n_int + 127) / 128 * 128;
       const size_t tot = (size_t)g.nloc * nbp;
@@ -1106,25 +1101,25 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
       hipLaunchKernelGGL((k_int_gather<T>), dim3(grid), dim3(256), 0, s, r, xg, g, int_boxes, n_int, nbp, loc_tab);
       IBMG_LAUNCH_CHECK();
       hipLaunchKernelGGL((k_int_gemm<T>), dim3(g.nch, nbp / 128, ks), dim3(256), 0, s, shared_inv, xg, z, g,
-                         int_boxes, n_int, nbp, part, ks, acc);
+                         int_boxes, n_int, nbp, tpart, ks, acc);
     } else if (tb == 64)
       hipLaunchKernelGGL((k_ras_interior_g<T>), dim3((n_int + 63) / 64, g.nch, ks), dim3(256), 0, s, r, z, g,
-                         shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
+                         shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
     else if (tb == 16)
       hipLaunchKernelGGL((k_ras_interior<T, 16>), dim3((n_int + 15) / 16, g.nch, ks), dim3(256), 0, s, r, z, g,
-                         shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
+                         shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
     else
       hipLaunchKernelGGL((k_ras_interior<T, 32>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
-                         shared_inv, int_boxes, n_int, loc_tab, part, ks, acc);
+                         shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
     IBMG_LAUNCH_CHECK();
-    if (ks > 1) {
-      const size_t tot = (size_t)n_int * g.nown;
-      int grid = cdiv(tot, 256);
-      if (grid > 4096) grid = 4096;
-      hipLaunchKernelGGL((k_ras_interior_sum<T>), dim3(grid), dim3(256), 0, s, part, z, g, int_boxes, n_int, ks,
-                         acc);
-      IBMG_LAUNCH_CHECK();
-    }
+  }
+  const int na = ks_ib > 1 ? n_ib : 0, nb = ks_int > 1 ? n_int : 0;
+  if (na + nb > 0) {
+    int grid = cdiv((size_t)(na + nb) * g.nown, 256);
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL((k_ras_sum<T>), dim3(grid), dim3(256), 0, s, ipart, ib_boxes, na, ks_ib, tpart, int_boxes, nb,
+                       ks_int, z, g, acc);
+    IBMG_LAUNCH_CHECK();
   }
 }
 
@@ -1343,11 +1338,14 @@ void launch_coarse_extract(const double* aug, int nn, int n0, double* inv, hipSt
   IBMG_LAUNCH_CHECK();
 }
 
-// z = inv r on the coarsest level, FP64 arithmetic whatever T is.
+// z = inv r on the coarsest level, FP64 arithmetic whatever T is: one wave
+// per row, the lanes reading the row (and r) contiguously, then a butterfly
+// over the wave.
 template <typename T>
-__global__ void k_coarse_apply(const double* __restrict__ inv, int n0, const T* __restrict__ r,
-                               T* __restrict__ z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_coarse_apply(const double* __restrict__ inv, int n0,
+                                                      const T* __restrict__ r, T* __restrict__ z) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n0) return;
   // batched: system blockIdx.y, inverses n0^2 and vectors n0 apart
   inv += (size_t)blockIdx.y * n0 * n0;
@@ -1355,14 +1353,16 @@ __global__ void k_coarse_apply(const double* __restrict__ inv, int n0, const T* 
   z += (size_t)blockIdx.y * n0;
   const double* row = inv + (size_t)i * n0;
   double a = 0.0;
-  for (int j = 0; j < n0; ++j) a += row[j] * (double)r[j];
-  z[i] = (T)a;
+  for (int j = lane; j < n0; j += 64) a += row[j] * (double)r[j];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+  if (lane == 0) z[i] = (T)a;
 }
 
 template <typename T>
 void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cdiv(n0, 64), nsys), dim3(64), 0, s, inv, n0, r, z);
+  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cdiv(n0, 4), nsys), dim3(256), 0, s, inv, n0, r, z);
   IBMG_LAUNCH_CHECK();
 }
 

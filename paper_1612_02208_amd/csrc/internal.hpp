@@ -278,7 +278,8 @@ constexpr int kGjNb = 64;  // block width of the batched inversion
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
 // parts: bit 0 = IB boxes (k_ras_ib), bit 1 = interior boxes
-// (k_ras_interior and its slice sum); the smoother launches both.
+// (k_ras_interior); the smoother launches both, and one k_ras_sum adds the
+// slices of whichever was split.
 // acc: add the local solutions to z on the owned sets instead of storing them;
 // tb: interior product form (16 or 32 boxes per tile, 64: register-blocked
 // 64 x 64 tiles, 128: residuals gathered into xg (at least
@@ -292,8 +293,8 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
 size_t int_gather_elems(const BoxGeom& g, int n_int);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);
-// column slices of the IB-box kernel (part holds ksplit * n_ib * nch * 64);
-// the IB and interior launches of one sweep use the slice buffer in turn
+// column slices of the IB-box kernel (part holds ksplit * n_ib * nch * 64,
+// followed by the interior product's slices when both are launched)
 int ras_ib_ksplit(const BoxGeom& g, int n_ib);
 void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, const int* tcol_u,
                             const double* tval_u, const int* tptr_v, const int* tcol_v,

@@ -458,11 +458,12 @@ class Solver final : public SolverBase {
   }
 
   // Every Schwarz launch goes through here: the slice buffer must hold the
-  // launch's column slices (IB boxes) and reduction slices (interior).
+  // launch's column slices (IB boxes) followed by its reduction slices
+  // (interior).
   void ras_launch(Level<T>& lev, const T* r, T* z, const T* inv, const int* ib, int n_ib, const int* in, int n_int,
                   hipStream_t s, int parts, bool acc, int tb) {
-    require(lev.int_part.n >= interior_part_need(lev.g, (parts & 2) ? n_int : 0) &&
-                lev.int_part.n >= ib_part_need(lev.g, (parts & 1) ? n_ib : 0),
+    require(lev.int_part.n >= ib_part_need(lev.g, (parts & 1) ? n_ib : 0) +
+                                   interior_part_need(lev.g, (parts & 2) ? n_int : 0),
             "Schwarz slice buffer too small");
     launch_ras_apply<T>(r, z, lev.g, inv, ib, n_ib, lev.inv.p + (size_t)lev.n_ib * box_stride(lev), in, n_int,
                         lev.d_loc.p, lev.int_part.p, s, parts, acc, tb, lev.int_x.p, lev.int_x.n);
@@ -839,15 +840,14 @@ class Solver final : public SolverBase {
     lev.d_int.upload(lev.int_list, s);
     lev.d_loc.upload(lev.loc_tab, s);
     {
-      // reduction slices of the interior product: the whole list (additive
-      // sweep, tuning, single-kernel timing) and each colour's range
-      // (multiplicative sweep)
-      size_t need = std::max(interior_part_need(g, (int)lev.int_list.size()), ib_part_need(g, lev.n_ib));
+      // column slices of the IB boxes followed by the reduction slices of
+      // the interior product: the whole lists (additive sweep, tuning,
+      // single-kernel timing) and each colour's ranges (multiplicative sweep)
+      size_t need = interior_part_need(g, (int)lev.int_list.size()) + ib_part_need(g, lev.n_ib);
       if (d_.smoother == IBMG_RMS)
-        for (int c = 0; c < lev.ncolour; ++c) {
-          need = std::max(need, interior_part_need(g, lev.int_off[c + 1] - lev.int_off[c]));
-          need = std::max(need, ib_part_need(g, lev.ib_off[c + 1] - lev.ib_off[c]));
-        }
+        for (int c = 0; c < lev.ncolour; ++c)
+          need = std::max(need, interior_part_need(g, lev.int_off[c + 1] - lev.int_off[c]) +
+                                    ib_part_need(g, lev.ib_off[c + 1] - lev.ib_off[c]));
       if (lev.int_part.n < need) lev.int_part.alloc(need);
     }
     lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
