@@ -520,38 +520,40 @@ struct Vec16<float> {
 // One (box, 64-row chunk) item over columns [cb, ce) of the chunk: Mc is the
 // chunk of the box's owned-row inverse, r and z the box's system vectors; x
 // holds nloc values (LDS, indexed by column), part 256.  With pout the 64
-// row sums of this column slice go to pout instead of z.
-template <typename T>
+// row sums of this column slice go to pout instead of z.  PRE issues the
+// first loads of the inverse before the gather (it holds their registers
+// across it, which the batched kernel cannot spare).
+template <typename T, bool PRE>
 __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
                                              const T* __restrict__ Mc, int pid, int chunk, T* x, T* part,
                                              bool acc_mode, int cb, int ce, T* __restrict__ pout) {
   using V = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   constexpr int LPC = 64 / VEC;  // lanes per column
-  for (int k = cb + threadIdx.x; k < ce; k += blockDim.x) x[k] = r[box_glob(g, pid, k)];
-  __syncthreads();
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int cph = lane / LPC;           // column phase 0..VEC-1
   const int rl = (lane % LPC) * VEC;    // first of this lane's VEC rows
   const int per = ((ce - cb + 4 * VEC - 1) / (4 * VEC)) * VEC;
   const int j0 = cb + q * per, j1 = j0 + per < ce ? j0 + per : ce;
   Mc += rl;
-  T acc[VEC];
-#pragma unroll
-  for (int v = 0; v < VEC; ++v) acc[v] = 0;
   int j = j0 + cph;
   // eight 16-byte loads in flight per lane, summed in a fixed tree; the
   // inverse streams through once per sweep, so its loads are non-temporal
-  // and leave the caches to the level's vectors
+  // and leave the caches to the level's vectors.  With PRE the first eight
+  // are issued before the residual gather, so that they overlap it.
   constexpr int UNR = 8;
-  for (; j + (UNR - 1) * VEC < j1; j += UNR * VEC) {
-    V m[UNR];
-    T xv[UNR];
+  auto load8 = [&](V* m, int jj) {
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
-      m[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)(j + u * VEC) * 64));
+      m[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)(jj + u * VEC) * 64));
+  };
+  T acc[VEC];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) xv[u] = x[j + u * VEC];
+  for (int v = 0; v < VEC; ++v) acc[v] = 0;
+  auto fma8 = [&](const V* m, int jj) {
+    T xv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) xv[u] = x[jj + u * VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       T t[UNR];
@@ -559,6 +561,20 @@ __device__ __forceinline__ void ras_ib_chunk(const T* __restrict__ r, T* __restr
       for (int u = 0; u < UNR; ++u) t[u] = reinterpret_cast<const T*>(&m[u])[v] * xv[u];
       acc[v] += ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
     }
+  };
+  const bool first = PRE && j + (UNR - 1) * VEC < j1;
+  V m0[UNR];
+  if (first) load8(m0, j);
+  for (int k = cb + threadIdx.x; k < ce; k += blockDim.x) x[k] = r[box_glob(g, pid, k)];
+  __syncthreads();
+  if (first) {
+    fma8(m0, j);
+    j += UNR * VEC;
+  }
+  for (; j + (UNR - 1) * VEC < j1; j += UNR * VEC) {
+    V m[UNR];
+    load8(m, j);
+    fma8(m, j);
   }
   for (; j < j1; j += VEC) {
     const V m0 = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)j * 64));
@@ -601,8 +617,8 @@ __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __re
   const int cs = ((g.nloc + ks - 1) / ks + 63) / 64 * 64;
   const int cb = blockIdx.z * cs, ce = cb + cs < g.nloc ? cb + cs : g.nloc;
   T* pout = ks > 1 ? spart + (((size_t)blockIdx.z * gridDim.x + slot) * g.nch + blockIdx.y) * 64 : nullptr;
-  ras_ib_chunk<T>(r, z, g, inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64, boxes[slot], blockIdx.y, x,
-                  part, acc, cb < ce ? cb : ce, ce, pout);
+  ras_ib_chunk<T, true>(r, z, g, inv + ((size_t)slot * g.nch + blockIdx.y) * g.nloc * 64, boxes[slot],
+                        blockIdx.y, x, part, acc, cb < ce ? cb : ce, ce, pout);
 }
 
 // z[owned rows] (=, or += with acc) the sum of a split launch's slices, in
@@ -1160,8 +1176,9 @@ __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* _
       const int ent = ib_ents[e], sy = ent / nbox;
       if (active && !active[sy]) continue;
       T* x = reinterpret_cast<T*>(smem_raw);
-      ras_ib_chunk<T>(r + (size_t)sy * sys_n, z + (size_t)sy * sys_n, g, ib_inv[e] + (size_t)c * g.nloc * 64,
-                      ent - sy * nbox, c, x, x + ((g.nloc + 3) & ~3), false, 0, g.nloc, nullptr);
+      ras_ib_chunk<T, false>(r + (size_t)sy * sys_n, z + (size_t)sy * sys_n, g,
+                             ib_inv[e] + (size_t)c * g.nloc * 64, ent - sy * nbox, c, x,
+                             x + ((g.nloc + 3) & ~3), false, 0, g.nloc, nullptr);
     }
     __syncthreads();
   }
