@@ -297,13 +297,14 @@ void launch_ib_rows(const T* x, T* y, const int* rows, const int* ptr, const int
 
 // ---------------------------------------------------------------------------
 // Restriction (Sec. 3.2): R_u = P_u^T / 4 (adjoint of the Raviart-Thomas
-// prolongation), R_p = mean of the four fine cells.
+// prolongation), R_p = mean of the four fine cells.  With partial (single
+// system, 64 x 4 blocks) each block also stores the sum of squares of its
+// coarse values at partial[block], the first norm the coarse level's
+// smoother needs: a wave butterfly, then (w0 + w1) + (w2 + w3).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_restrict(const T* __restrict__ f, T* __restrict__ cz, int Nc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= Nc || j >= Nc) return;
+__device__ __forceinline__ void restrict_point(const T* __restrict__ f, T* __restrict__ cz, int Nc, int i, int j,
+                                               double& sq) {
   const int Nf = 2 * Nc;
   const size_t nf = (size_t)Nf * Nf, nc = (size_t)Nc * Nc;
   f += blockIdx.z * 3 * nf;
@@ -323,6 +324,23 @@ __global__ void k_restrict(const T* __restrict__ f, T* __restrict__ cz, int Nc) 
   cz[o] = ru;
   cz[nc + o] = rv;
   cz[2 * nc + o] = rp;
+  sq = (double)ru * (double)ru + (double)rv * (double)rv + (double)rp * (double)rp;
+}
+
+template <typename T>
+__global__ void k_restrict(const T* __restrict__ f, T* __restrict__ cz, int Nc, double* __restrict__ partial) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  double sq = 0.0;
+  if (i < Nc && j < Nc) restrict_point<T>(f, cz, Nc, i, j, sq);
+  if (!partial) return;
+  __shared__ double red[4];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();
+  if (tid == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 template <typename T>
@@ -330,13 +348,23 @@ void launch_restrict_batch(const T* fine, T* coarse, int Nc, int nsys, hipStream
   if (nsys <= 0) return;
   dim3 blk(64, 4);
   dim3 grd((Nc + 63) / 64, (Nc + 3) / 4, nsys);
-  hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc);
+  hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc, nullptr);
   IBMG_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s) {
   launch_restrict_batch<T>(fine, coarse, Nc, 1, s);
+}
+
+int restrict_blocks(int Nc) { return ((Nc + 63) / 64) * ((Nc + 3) / 4); }
+
+template <typename T>
+void launch_restrict_norm(const T* fine, T* coarse, int Nc, double* partial, hipStream_t s) {
+  dim3 blk(64, 4);
+  dim3 grd((Nc + 63) / 64, (Nc + 3) / 4, 1);
+  hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc, partial);
+  IBMG_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -810,6 +838,7 @@ void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_
   template void launch_apply<T>(const T*, T*, const T*, const T*, const T*, FootView<T>,          \
                                 FootView<T>, int, int, StokesCoef<T>, bool, hipStream_t);         \
   template void launch_restrict<T>(const T*, T*, int, hipStream_t);                               \
+  template void launch_restrict_norm<T>(const T*, T*, int, double*, hipStream_t);                 \
   template void launch_prolong_add<T>(const T*, T*, int, hipStream_t);                            \
   template void launch_fill<T>(T*, T, size_t, hipStream_t);                                       \
   template void launch_dots<T>(const T*, int, size_t, const T*, size_t, double*, int, hipStream_t); \

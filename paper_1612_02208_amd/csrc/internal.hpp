@@ -181,6 +181,11 @@ template <typename T>
 void launch_ib_spmv(const T* x, T* G, CsrT<T> tu, CsrT<T> tv, int N, hipStream_t s);
 template <typename T>
 void launch_restrict(const T* fine, T* coarse, int Nc, hipStream_t s);
+// the same, and partial[0..restrict_blocks(Nc)) = per-block sums of the
+// squared coarse values (launch_scale_red reduces them)
+template <typename T>
+void launch_restrict_norm(const T* fine, T* coarse, int Nc, double* partial, hipStream_t s);
+int restrict_blocks(int Nc);
 template <typename T>
 void launch_prolong_add(const T* coarse, T* fine, int Nc, hipStream_t s);
 template <typename Ts, typename Td>
@@ -228,7 +233,7 @@ void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, d
                       hipStream_t s);
 template <typename T>
 void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
-                       const double* beta, double* yout, hipStream_t s);
+                       const double* beta, double* yout, hipStream_t s, bool assign = false);
 
 // immersed boundary
 void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
@@ -355,7 +360,7 @@ void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const 
 template <typename T>
 void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
                          const double* H, int ldh, size_t hstride, const double* beta, double* yout,
-                         size_t sstride, hipStream_t s);
+                         size_t sstride, hipStream_t s, bool assign = false);
 template <typename T>
 void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s);
 

@@ -153,12 +153,13 @@ __global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, BSeg s
 
 // Least squares min || beta e1 - H y || ((k+1) x k Hessenberg, column-major,
 // leading dimension ldh) by Givens rotations in every block, then
-// x += sum_q y_q Z_q; block 0 stores y.
+// x += sum_q y_q Z_q (assign: x = sum_q y_q Z_q, the same bits as adding to
+// a zeroed x); block 0 stores y.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, const T* __restrict__ Z, int k,
                                                          size_t stride, BSeg sg, const double* __restrict__ H,
                                                          int ldh, size_t hstride, const double* __restrict__ beta,
-                                                         double* __restrict__ yout, size_t sstride) {
+                                                         double* __restrict__ yout, size_t sstride, bool assign) {
   __shared__ double y[16];
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, cons
   }
   __syncthreads();
   for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
-    double a = (double)x[i];
+    double a = assign ? 0.0 : (double)x[i];
     for (int q = 0; q < k; ++q) a += y[q] * (double)Z[(size_t)q * stride + i];
     x[i] = (T)a;
   }
@@ -249,10 +250,10 @@ void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const 
 template <typename T>
 void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
                          const double* H, int ldh, size_t hstride, const double* beta, double* yout,
-                         size_t sstride, hipStream_t s) {
+                         size_t sstride, hipStream_t s, bool assign) {
   if (nsys <= 0) return;
   hipLaunchKernelGGL((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
-                     sg, H, ldh, hstride, beta, yout, sstride);
+                     sg, H, ldh, hstride, beta, yout, sstride, assign);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -276,8 +277,8 @@ void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, d
 
 template <typename T>
 void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
-                       const double* beta, double* yout, hipStream_t s) {
-  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s);
+                       const double* beta, double* yout, hipStream_t s, bool assign) {
+  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign);
 }
 
 #define IBMG_INST_KRY(T)                                                                               \
@@ -287,7 +288,7 @@ void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const d
                                    double*, hipStream_t);                                              \
   template void launch_scale_red<T>(const T*, T*, size_t, const double*, int, double*, hipStream_t);   \
   template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, const double*, int,            \
-                                     const double*, double*, hipStream_t);                             \
+                                     const double*, double*, hipStream_t, bool);                       \
   template void launch_upd_dots_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
                                      double*, size_t, double*, hipStream_t, int);                      \
   template void launch_upd_norm_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
@@ -295,7 +296,7 @@ void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const d
   template void launch_scale_red_b<T>(const T*, T*, BSeg, int, size_t, const double*, int, size_t,     \
                                       double*, size_t, hipStream_t);                                   \
   template void launch_combine_ls_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, const double*,   \
-                                       int, size_t, const double*, double*, size_t, hipStream_t);
+                                       int, size_t, const double*, double*, size_t, hipStream_t, bool);
 
 IBMG_INST_KRY(double)
 IBMG_INST_KRY(float)

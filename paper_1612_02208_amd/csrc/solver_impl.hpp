@@ -1046,14 +1046,16 @@ class Solver final : public SolverBase {
   }
 
   // w <- w + e, e = nu FGMRES iterations (CGS2) on L e = b - L w from e = 0.
-  void smooth_t(int l, T* w, const T* b, int nu, bool w_zero, hipStream_t s) {
+  // With w_zero, w is not read (the result is stored into it) and b_nblk > 0
+  // says the level's partial-sum buffer already holds b_nblk block sums of
+  // |b|^2 (left there by the restriction that produced b).
+  void smooth_t(int l, T* w, const T* b, int nu, bool w_zero, hipStream_t s, int b_nblk = 0) {
     Level<T>& lev = levels_[l];
     const size_t n = 3 * (size_t)lev.N * lev.N;
     const int nblk = dots_blocks(n, 1024);  // at most nu + 1 vectors
     const int ldh = kMaxNu + 1;
     const T* r0;
     if (w_zero) {
-      launch_fill<T>(w, T(0), n, s);
       r0 = b;
     } else {
       // r = b - L w with its squared norm's block sums
@@ -1066,7 +1068,9 @@ class Solver final : public SolverBase {
     const int nab = apply_blocks(lev.N);  // blocks of the fused operator + dots kernel
     T* V = lev.V.p;
     T* Z = lev.Z.p;
-    if (w_zero) {
+    if (w_zero && b_nblk > 0) {
+      launch_scale_red<T>(r0, V, n, pa, b_nblk, beta, s);
+    } else if (w_zero) {
       launch_dots<T>(r0, 1, n, r0, n, pa, nblk, s);
       launch_scale_red<T>(r0, V, n, pa, nblk, beta, s);
     } else {
@@ -1084,7 +1088,7 @@ class Solver final : public SolverBase {
       launch_upd_norm<T>(t, V, k + 1, n, n, pb, nblk, hcol, pa, s);
       launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
     }
-    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s);
+    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s, w_zero);
   }
 
   // Classical Gram-Schmidt twice against V[0..k): h (first pass + second
@@ -1098,18 +1102,24 @@ class Solver final : public SolverBase {
     launch_upd_norm<U>(t, V, k, n, n, pb, nblk, hcol, pa, s);
   }
 
-  // w = MG(0, b) on level l (Alg. 1)
-  void mg(int l, const T* b, T* w, hipStream_t s) {
+  // w = MG(0, b) on level l (Alg. 1); b_nblk as for smooth_t
+  void mg(int l, const T* b, T* w, hipStream_t s, int b_nblk = 0) {
     if (l == 0) {
       launch_coarse_apply<T>(inv0_.p, n0_, b, w, s);
       return;
     }
     Level<T>& lev = levels_[l];
     Level<T>& crs = levels_[l - 1];
-    smooth_t(l, w, b, d_.nu1, true, s);
+    smooth_t(l, w, b, d_.nu1, true, s, b_nblk);
     op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
-    launch_restrict<T>(lev.r.p, crs.b.p, crs.N, s);
-    mg(l - 1, crs.b.p, crs.w.p, s);
+    int c_nblk = 0;
+    if (l - 1 >= 1 && restrict_blocks(crs.N) <= (int)part_stride(crs)) {
+      launch_restrict_norm<T>(lev.r.p, crs.b.p, crs.N, crs.part.p, s);
+      c_nblk = restrict_blocks(crs.N);
+    } else {
+      launch_restrict<T>(lev.r.p, crs.b.p, crs.N, s);
+    }
+    mg(l - 1, crs.b.p, crs.w.p, s, c_nblk);
     launch_prolong_add<T>(crs.w.p, w, crs.N, s);
     smooth_t(l, w, b, d_.nu2, false, s);
   }
