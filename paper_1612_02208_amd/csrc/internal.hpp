@@ -227,7 +227,7 @@ void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const dou
                      double* hcol, double* pout, hipStream_t s, int nblk_in = 0);
 template <typename T>
 void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
-                     double* hcol, double* pout, hipStream_t s);
+                     double* hcol, double* pout, hipStream_t s, int nblk_in = 0);
 template <typename T>
 void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, double* hout,
                       hipStream_t s);
@@ -353,7 +353,8 @@ void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
                        int nblk_in = 0);
 template <typename T>
 void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
-                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s);
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
+                       int nblk_in = 0);
 template <typename T>
 void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const double* pin, int nblk,
                         size_t pstride, double* hout, size_t hstride, hipStream_t s);

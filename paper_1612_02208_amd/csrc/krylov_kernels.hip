@@ -231,10 +231,11 @@ void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
 
 template <typename T>
 void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
-                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s) {
+                       int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
+                       int nblk_in) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_upd_norm<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin, nblk,
-                     pstride, hcol, hstride, pout);
+  hipLaunchKernelGGL((k_upd_norm<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
+                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -265,8 +266,8 @@ void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const dou
 
 template <typename T>
 void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
-                     double* hcol, double* pout, hipStream_t s) {
-  launch_upd_norm_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s);
+                     double* hcol, double* pout, hipStream_t s, int nblk_in) {
+  launch_upd_norm_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s, nblk_in);
 }
 
 template <typename T>
@@ -285,14 +286,14 @@ void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const d
   template void launch_upd_dots<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,     \
                                    double*, hipStream_t, int);                                         \
   template void launch_upd_norm<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,     \
-                                   double*, hipStream_t);                                              \
+                                   double*, hipStream_t, int);                                         \
   template void launch_scale_red<T>(const T*, T*, size_t, const double*, int, double*, hipStream_t);   \
   template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, const double*, int,            \
                                      const double*, double*, hipStream_t, bool);                       \
   template void launch_upd_dots_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
                                      double*, size_t, double*, hipStream_t, int);                      \
   template void launch_upd_norm_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
-                                     double*, size_t, double*, hipStream_t);                           \
+                                     double*, size_t, double*, hipStream_t, int);                      \
   template void launch_scale_red_b<T>(const T*, T*, BSeg, int, size_t, const double*, int, size_t,     \
                                       double*, size_t, hipStream_t);                                   \
   template void launch_combine_ls_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, const double*,   \

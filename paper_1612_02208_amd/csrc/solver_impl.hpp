@@ -31,6 +31,10 @@ constexpr int kScalTmp = 20;  // scal[20..]: second Gram-Schmidt pass
 constexpr int kSpmvListThreshold = 24;
 // partial-sum buffers: two of kPartStride doubles (blocks x vectors)
 constexpr size_t kPartStride = (size_t)256 * 65;
+// the outer solve's Gram-Schmidt passes: up to kOuterBlocks blocks of up to
+// 65 vectors, folded by one block before their consumers
+constexpr int kOuterBlocks = 1024;
+constexpr size_t kOuterPartStride = (size_t)kOuterBlocks * 65;
 
 inline int wrapn(int a, int N) {
   a %= N;
@@ -1102,6 +1106,20 @@ class Solver final : public SolverBase {
     launch_upd_norm<U>(t, V, k, n, n, pb, nblk, hcol, pa, s);
   }
 
+  // The same for the outer solve's long vectors, on up to kOuterBlocks
+  // blocks: one block folds each pass's partial sums (the pass-1 dots, then
+  // the pass-2 dots) before the next kernel, so that kernel's blocks read k
+  // values instead of every block's k partials.
+  void orthogonalise_outer(const double* V, int k, size_t n, double* t, double* hcol, int nblk, hipStream_t s) {
+    double* pa = opart_.p;
+    double* pb = opart_.p + kOuterPartStride;
+    launch_dots<double>(V, k, n, t, n, pa, nblk, s);
+    launch_dots_finish(pa, k, nblk, ofold_.p, nullptr, 0, s);
+    launch_upd_dots<double>(t, V, k, n, n, ofold_.p, nblk, hcol, pb, s, 1);
+    launch_dots_finish(pb, k, nblk, ofold_.p + 72, nullptr, 0, s);
+    launch_upd_norm<double>(t, V, k, n, n, ofold_.p + 72, nblk, hcol, pa, s, 1);
+  }
+
   // w = MG(0, b) on level l (Alg. 1); b_nblk as for smooth_t
   void mg(int l, const T* b, T* w, hipStream_t s, int b_nblk = 0) {
     if (l == 0) {
@@ -1248,7 +1266,8 @@ class Solver final : public SolverBase {
     g_.alloc(restart + 2);
     y_.alloc(restart + 1);
     osc_.alloc(256);
-    opart_.alloc(2 * kPartStride);
+    opart_.alloc(2 * kOuterPartStride);
+    ofold_.alloc(2 * 72);
     bp_.alloc(n);
     rr_.alloc(n);
     outer_cap_ = restart;
@@ -1280,7 +1299,7 @@ class Solver final : public SolverBase {
     const bool trans = o.transpose != 0;
     const int N = d_.N;
     const size_t n = 3 * (size_t)N * N;
-    const int nblk = dots_blocks(n);
+    const int gs_nblk = dots_blocks(n, kOuterBlocks);
     const int ldh = o.restart + 1;
     int hist_n = 0;
     auto push_hist = [&](double v) {
@@ -1336,8 +1355,8 @@ class Solver final : public SolverBase {
         ++vcycles;
         op<double>(L_, zk, t, nullptr, trans, Fd_.p, s);
         double* hcol = Ho_.p + (size_t)k * ldh;
-        orthogonalise<double>(Vo_.p, k + 1, n, t, hcol, opart_.p, opart_.p + kPartStride, nblk, s);
-        launch_scale_red<double>(t, t, n, opart_.p, nblk, hcol + k + 1, s);
+        orthogonalise_outer(Vo_.p, k + 1, n, t, hcol, gs_nblk, s);
+        launch_scale_red<double>(t, t, n, opart_.p, gs_nblk, hcol + k + 1, s);
         launch_givens(Ho_.p, ldh, k, cs_.p, sn_.p, g_.p, osc_.p + 1, s);
         est = read_scalar(osc_.p + 1, s);
         ++k;
@@ -1568,7 +1587,7 @@ class Solver final : public SolverBase {
   DBuf<double> Fs_, fs_, rhs_;   // time step: nodal forces, spread forces, right-hand side
   // outer FGMRES
   int outer_cap_ = 0;
-  DBuf<double> Vo_, Zo_, Ho_, cs_, sn_, g_, y_, osc_, opart_, bp_, rr_;
+  DBuf<double> Vo_, Zo_, Ho_, cs_, sn_, g_, y_, osc_, opart_, ofold_, bp_, rr_;
   double* pinned_ = nullptr;
   // V-cycle graph
   bool use_graph_ = graphs_enabled();
