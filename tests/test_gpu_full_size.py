@@ -21,13 +21,18 @@ configuration the benchmark runs (default handles, V-cycle graphs on).
     oracle's operator, and the FP32-smoother solution against the FP64 one;
   - the same annulus with tangent springs at 0.7 of their lengths: the
     operator with its 2 x 2 blocks on the whole vector, and the solve to 1e-8
-    in both precisions through its true residual.
+    in both precisions through its true residual;
+  - two time steps with the rebuild at the moved points: each step's
+    right-hand side, its solve's true residual under the oracle's operator
+    at that step's positions, and the moved points.
 * The 256 x 256 Stokes membrane (1024 points, 6 levels) with kappa over
   {1e0, 1e2, 1e4, 1e6}, RAS and the Schur-complement smoother side by side:
   the whole oracle runs here, so FGMRES after a fixed number of iterations
   is compared element by element, and the solve to 1e-8 by its iteration
   count and true residual.
 """
+import copy
+
 import numpy as np
 import pytest
 import scipy.linalg as la
@@ -36,6 +41,7 @@ import torch
 import workloads as W
 from oracle import hierarchy, krylov, mac, transfer
 from oracle import ib as oib
+from oracle import timestep as ots
 from oracle.schwarz import patches
 from oracle.solver import Problem
 
@@ -194,6 +200,42 @@ def test_a512_tangent_springs_operator_and_solve():
             assert true <= 1.2e-8, (prec, true)
         finally:
             g.close()
+
+
+def test_a512_two_time_steps_with_rebuild():
+    """Two semi-implicit steps of the annulus as the benchmark runs them
+    (Sec. 2 time stepping: solve at X^n, move the points, rebuild the
+    hierarchy at X^{n+1}), each checked through the oracle at that step's
+    positions: the right-hand side, the solve's true residual under the
+    oracle's operator L(X^n), and the moved points X^n + dt J u^{n+1}."""
+    from paper_1612_02208_amd import StokesIB
+    wl = W.annulus_512()
+    wl.box, wl.overlap = 16, 4
+    print(f"[case] {wl.name} two steps N={wl.N} M={wl.M}", flush=True)
+    N = wl.N
+    ow = copy.deepcopy(wl)
+    w = 0.1 * np.random.default_rng(36).uniform(-1, 1, 3 * N * N)
+    G = StokesIB(wl)
+    try:
+        wg = dev(w)
+        for k in range(2):
+            rhs = ots.step_rhs(ow, w)
+            assert rel(host(G.step_rhs(wg)), rhs) < OPS_TOL, k
+            wg, info = G.time_step(wg, rtol=1e-8)
+            assert info["converged"], (k, info)
+            w = host(wg)
+            IB = oib.ib_term(ow.X, ow.springs, ow.kappa, N, ow.dt)
+            L = mac.stokes_ib((mac.momentum(N, ow.rho, ow.mu, ow.dt) + IB).tocsr(), mac.gradient(N),
+                              mac.divergence(N)).tocsr()
+            bp = hierarchy.project_range(rhs, N, ow.rho)
+            true = np.linalg.norm(bp - L @ w) / np.linalg.norm(bp)
+            print(f"  step {k}: {info['iters']} iterations, true rel. residual {true:.3e}", flush=True)
+            assert true <= 1.2e-8, (k, true)
+            Xn = ots.advance_positions(ow, w)
+            assert np.abs(G.positions() - Xn).max() < 1e-12, k
+            ow.X = Xn
+    finally:
+        G.close()
 
 
 # ------------------------------------- 256 x 256 membrane, kappa sweep, RAS / SC
