@@ -1,7 +1,7 @@
 """Flexible GMRES (Saad 1993, cited in Sec. 3.3) with classical Gram-Schmidt
-applied twice, used both as the outer Krylov solver and, with a fixed number
-of iterations, to wrap each basic smoother (Sec. 3.3: "a fixed number of
-flexible GMRES iterations preconditioned by the basic algorithm").
+applied twice, used both as the outer Krylov solver and, run for a fixed
+number of iterations with the basic smoother as its preconditioner, as the
+smoothing step itself (Sec. 3.3).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 

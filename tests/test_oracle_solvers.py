@@ -6,6 +6,9 @@ oracle's own formulas:
 * FGMRES with a fixed preconditioner sequence returns x0 + Z y with y the
   least-squares minimiser of ||b - A Z y|| (brute force over the recorded Z);
   with the identity it is GMRES, the minimal residual over the Krylov space.
+* Restarted FGMRES: every cycle adds to x the minimiser of the residual over
+  that cycle's Krylov space of the current residual (brute force per cycle),
+  and each recorded estimate is the true residual of the partial minimiser.
 * RAS: owned sets partition the unknowns; for any e supported in a box's index
   set, RAS(L e) reproduces e on that box's owned set.
 * SC composition with exact inner solves is L_IB^{-1} (Eq. fact-Stokes-IB).
@@ -62,6 +65,49 @@ def test_fgmres_flexible_minimises_over_z():
     Z = np.stack(Zs, 1)
     y = np.linalg.lstsq(A @ Z, b, rcond=None)[0]
     np.testing.assert_allclose(dx, Z @ y, rtol=1e-9, atol=1e-11)
+
+
+def _restarted_gmres_brute(A, b, restart, iters):
+    """Restarted GMRES written from its definition: per cycle, the residual
+    minimiser over span{r, A r, ..., A^(k-1) r} of the current residual r,
+    added to x; returns x and the residual norm after every iteration."""
+    x = np.zeros_like(b)
+    hist = []
+    done = 0
+    while done < iters:
+        r = b - A @ x
+        k = min(restart, iters - done)
+        best = None
+        for j in range(1, k + 1):
+            Kr = np.stack([np.linalg.matrix_power(A, i) @ r for i in range(j)], 1)
+            Q, _ = np.linalg.qr(Kr)
+            y = np.linalg.lstsq(A @ Q, r, rcond=None)[0]
+            best = Q @ y
+            hist.append(float(np.linalg.norm(r - A @ best)))
+        x = x + best
+        done += k
+    return x, hist
+
+
+def test_fgmres_restarts_accumulate_minimal_residual_cycles():
+    """FGMRES(3) with the identity preconditioner for 12 iterations is four
+    GMRES(3) cycles (Saad's restarted GMRES, the outer method of Sec. 3): the
+    iterate keeps every cycle's correction, and the history holds each
+    iteration's minimal residual.  A restart that dropped x, reused a stale
+    residual or skipped the last partial cycle fails here."""
+    rng = np.random.default_rng(21)
+    n = 36
+    A = np.diag(np.linspace(1.0, 12.0, n)) + 0.4 * rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n)
+    for restart, iters in ((3, 12), (5, 12), (4, 9)):
+        x, info = krylov.fgmres(lambda v: A @ v, lambda v: v, b, restart=restart, rtol=1e-300, max_it=iters)
+        assert info["iters"] == iters and not info["converged"]
+        xb, hb = _restarted_gmres_brute(A, b, restart, iters)
+        np.testing.assert_allclose(x, xb, rtol=1e-9, atol=1e-12 * np.linalg.norm(xb))
+        np.testing.assert_allclose(info["history"], hb, rtol=1e-8)
+        # restarting loses optimality: one unrestarted cycle does better
+        xf, _ = krylov.fgmres(lambda v: A @ v, lambda v: v, b, restart=iters, rtol=1e-300, max_it=iters)
+        assert np.linalg.norm(b - A @ xf) < np.linalg.norm(b - A @ x)
 
 
 def test_ras_partition_and_local_reproduction():

@@ -4,6 +4,9 @@
 * Raviart-Thomas prolongation preserves divergence: D_f P_u u_c equals D_c u_c
   copied to the four fine cells of each coarse cell.
 * P_u and P_p reproduce constants; R_p P_p maps constants to themselves.
+* R_p is the four-cell mean: it returns a coarse field from its piecewise
+  constant injection, and R_u G_f = G_c R_p holds exactly (the transpose of
+  the RT0 divergence identity, with G = -D^T and R_u = P_u^T / 4).
 * The Galerkin coarse IB operator R_u [SKJ]^{l+1} P_u equals
   dt/h_l^2 J_l^T K' J_l with J_l = J_{l+1} P_u (composed in the test), is
   symmetric positive semidefinite and annihilates constant velocities.
@@ -50,6 +53,29 @@ def test_transfers_reproduce_constants():
     np.testing.assert_allclose(Ru @ f, c)
     np.testing.assert_allclose(Pp @ np.full(Nc * Nc, 3.0), 3.0)
     np.testing.assert_allclose(Rp @ (Pp @ np.full(Nc * Nc, 3.0)), 3.0)
+
+
+def test_pressure_restriction_inverts_injection():
+    """A fine field constant on every 2 x 2 block of a coarse cell restricts
+    to that coarse field (Sec. 3.2: R_p averages the four fine cells)."""
+    rng = np.random.default_rng(11)
+    for Nc in (3, 4, 8):
+        pc = rng.standard_normal((Nc, Nc))
+        pf = np.kron(pc, np.ones((2, 2))).ravel()
+        np.testing.assert_allclose(transfer.pressure_restriction(Nc) @ pf, pc.ravel(), rtol=0, atol=1e-14)
+
+
+def test_pressure_restriction_commutes_with_gradient():
+    """R_u G_f p = G_c R_p p for every fine p.  RT0 prolongation preserves the
+    divergence, D_f P_u = I_0 D_c with I_0 the injection into the four fine
+    cells; transposing with G = -D^T, R_u = P_u^T / 4 (h_f / h_c = 1/2) and
+    R_p = I_0^T / 4 gives the identity, with no rounding beyond the sums."""
+    rng = np.random.default_rng(12)
+    for Nc in (4, 6, 8):
+        p = rng.standard_normal(4 * Nc * Nc)
+        lhs = transfer.velocity_restriction(Nc) @ (mac.gradient(2 * Nc) @ p)
+        rhs = mac.gradient(Nc) @ (transfer.pressure_restriction(Nc) @ p)
+        assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(lhs).max()
 
 
 def test_pressure_prolongation_is_bilinear():
