@@ -8,7 +8,13 @@ transposed-operator FGMRES path and returns
 from the spring-gradient kernel (dL_IB/dkappa_e is the IB block of spring e
 alone, Eq. matrix-impib with K_h of one spring).  Everything runs in libibmg;
 this module only sequences the calls.
+
+The handle's operator is the one built for the last ``set_kappa``.  Each
+forward keeps its own stiffness field, and backward rebuilds the handle for
+that field when another forward (or a ``set_kappa``) has changed it since, so
+the adjoint always uses the operator the forward solved with.
 """
+import numpy as np
 import torch
 
 
@@ -22,11 +28,13 @@ class StiffnessSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, kappa, solver, b, rtol=1e-12):
-        solver.set_kappa(kappa.detach().to("cpu", torch.float64).numpy())
+        k = np.array(kappa.detach().to("cpu", torch.float64).numpy(), copy=True)
+        solver.set_kappa(k)
         w, info = solver.solve(b, rtol=rtol, max_it=400)
         if not info["converged"]:
             raise RuntimeError(f"forward solve did not converge: {info['status']}")
         ctx.solver = solver
+        ctx.kappa_host = k
         ctx.rtol = rtol
         ctx.kappa_device = kappa.device
         ctx.save_for_backward(w)
@@ -36,6 +44,8 @@ class StiffnessSolve(torch.autograd.Function):
     def backward(ctx, grad_w):
         (w,) = ctx.saved_tensors
         solver = ctx.solver
+        if not np.array_equal(solver.kappa, ctx.kappa_host):
+            solver.set_kappa(ctx.kappa_host)
         g = grad_w.contiguous().to(torch.float64)
         lam, info = solver.solve(g, rtol=ctx.rtol, max_it=400, transpose=True)
         if not info["converged"]:

@@ -1,0 +1,135 @@
+"""GPU parity with the whole oracle on the benchmark's structure at a grid the
+oracle can set up in test time.
+
+The structure is the benchmark's exactly: the thick annulus r in [0.2, 0.25]
+(Sec. 5.1 geometry) as 4 rings x 2048 points with ring and radial springs,
+kappa = 1e4, at nonzero Reynolds number (rho = 1, mu = 1e-2, dt = 5e-4), with
+the benchmark's 16 x 16 boxes and overlap 4 (Alg. 2).  The grid is 128 x 128
+(5 levels, 128 -> 8) instead of 512, so the oracle builds every level.  On
+this grid the points crowd the faces (0.08 h apart), so the finest level runs
+the explicit Galerkin-row IB term as well as the coarse ones.
+
+Both handles are checked call by call: the FP64 handle to the FP64 bounds
+(1e-12 operators, 1e-10 solves), the FP32-smoother handle to the binary32
+bound (1e-4 per row class, about 1700 unit roundoffs).  Solves: both
+precisions to 1e-8 by the true residual under the oracle's operator, with
+the distance to the oracle's 1e-12 solution recorded, and both to 1e-12
+against that solution at the FP64 bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import krylov, transfer
+from oracle.solver import Problem
+from _parity import assert_classes, level_classes
+
+pytestmark = pytest.mark.gpu
+
+OPS_TOL = 1e-12
+SOLVE_TOL = 1e-10
+FP32_TOL = 1e-4
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    from paper_1612_02208_amd import StokesIB
+    wl = W.annulus_512(N=128, box=16, overlap=4)
+    print(f"[case] {wl.name} N={wl.N} M={wl.M} box 16/4", flush=True)
+    P = Problem(wl)
+    handles = {"fp64": StokesIB(wl, precision="fp64"), "fp32": StokesIB(wl, precision="fp32")}
+    yield wl, P, handles
+    for h in handles.values():
+        h.close()
+
+
+def lc(P, l=-1):
+    lev = P.levels[l]
+    return level_classes(lev.N, lev.T)
+
+
+def test_operators_and_transfers_every_level(c3):
+    wl, P, H = c3
+    G = H["fp64"]
+    rng = np.random.default_rng(1)
+    for l, lev in enumerate(P.levels):
+        w = rng.uniform(-1, 1, lev.n)
+        assert_classes(host(G.apply(dev(w), level=l)), lev.L @ w, lc(P, l), OPS_TOL, f"apply {l}")
+        if l >= 1:
+            Nc = P.levels[l - 1].N
+            assert_classes(host(G.restrict(l, dev(w))), transfer.restriction(Nc) @ w, lc(P, l - 1), OPS_TOL,
+                           f"restrict {l}")
+            e = rng.uniform(-1, 1, P.levels[l - 1].n)
+            out = host(G.prolong_add(l, dev(e), dev(w)))
+            assert_classes(out, w + transfer.prolongation(Nc) @ e, lc(P, l), OPS_TOL, f"prolong {l}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_smoother_and_smoothing_every_level(c3, prec):
+    wl, P, H = c3
+    G = H[prec]
+    tol = SOLVE_TOL if prec == "fp64" else FP32_TOL
+    rng = np.random.default_rng(6)
+    for l in range(1, len(P.levels)):
+        lev = P.levels[l]
+        r = rng.uniform(-1, 1, lev.n)
+        e1 = assert_classes(host(G.smoother_apply(l, dev(r))), P.mg.smoothers[l](r), lc(P, l), tol,
+                            f"{prec} smoother {l}")
+        w = rng.uniform(-1, 1, lev.n)
+        out = host(G.smooth(l, dev(w), dev(r), 2))
+        ref = krylov.fgmres_smooth(lambda x: lev.L @ x, P.mg.smoothers[l], w, r, 2)
+        e2 = assert_classes(out, ref, lc(P, l), tol, f"{prec} smooth {l}")
+        print(f"[c3-128 {prec}] level {l}: smoother {e1} smooth {e2}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vcycle(c3, prec):
+    wl, P, H = c3
+    r = P.project(W.rhs(wl.N, 11))
+    e = assert_classes(host(H[prec].vcycle(dev(r))), P.mg.vcycle(r), lc(P),
+                       SOLVE_TOL if prec == "fp64" else FP32_TOL, f"{prec} V-cycle")
+    print(f"[c3-128 {prec}] V-cycle {e}")
+
+
+def test_fgmres_fixed_iterations_with_restart(c3):
+    wl, P, H = c3
+    G = H["fp64"]
+    b = W.rhs(wl.N, 0)
+    bp = P.project(b)
+    x, info = G.solve(dev(b), rtol=1e-300, restart=3, max_it=7)
+    assert info["iters"] == 7 and info["restarts"] == 3
+    xo, io = krylov.fgmres(P.apply, P.mg, bp, restart=3, rtol=1e-300, max_it=7)
+    assert_classes(host(x), P.project(xo), lc(P), SOLVE_TOL, "FGMRES(3), 7 iterations")
+    np.testing.assert_allclose(info["history"], np.array(io["history"]) / np.linalg.norm(bp), rtol=1e-8)
+
+
+def test_solves_both_precisions(c3):
+    wl, P, H = c3
+    b = W.rhs(wl.N, 0)
+    bp = P.project(b)
+    xo8, io8 = P.solve(b, rtol=1e-8)
+    xo12, io12 = P.solve(b, rtol=1e-12, max_it=200)
+    for prec, G in H.items():
+        x8, i8 = G.solve(dev(b), rtol=1e-8)
+        assert i8["converged"], prec
+        x8 = host(x8)
+        true = np.linalg.norm(bp - P.L @ x8) / np.linalg.norm(bp)
+        assert true <= 1.2e-8, (prec, true)
+        if prec == "fp64":
+            assert abs(i8["iters"] - io8["iters"]) <= 1
+        e8 = assert_classes(x8, xo12, lc(P), 1e-5, f"{prec} at 1e-8 vs oracle at 1e-12")
+        x12, i12 = G.solve(dev(b), rtol=1e-12, max_it=200)
+        assert i12["converged"], prec
+        e12 = assert_classes(host(x12), xo12, lc(P), SOLVE_TOL, f"{prec} at 1e-12 vs oracle at 1e-12")
+        print(f"[c3-128 {prec}] 1e-8: {i8['iters']} its (oracle {io8['iters']}), true {true:.2e}, "
+              f"vs oracle {e8}; 1e-12: {i12['iters']} its (oracle {io12['iters']}), vs oracle {e12}")

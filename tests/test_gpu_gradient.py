@@ -103,3 +103,63 @@ def test_adjoint_solve_uses_transposed_path():
     assert i1["converged"] and i2["converged"]
     assert float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1)) < 1e-10
     G.close()
+
+
+def _golden_c5():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle_gradient.txt")
+    loss = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# loss"):
+                loss = float(line.split()[2])
+    return np.loadtxt(path), loss
+
+
+def test_gradient_matches_oracle_at_full_size():
+    """The differentiation workload at its full size (256 x 256, 1024
+    springs): the library's gradient and loss against the oracle's, stored in
+    tests/golden/c5_oracle_gradient.txt by a script that runs the oracle
+    alone (its three solves to 1e-13 take minutes on the host)."""
+    wl, wt = _setup(256, 1024)
+    print("[case] gradient vs oracle N=256 M=1024", flush=True)
+    b = torch.from_numpy(W.rhs(wl.N, 0)).cuda()
+    G, Gt, ut, w, g, loss = _loss_and_grad(wl, wt, b)
+    go, loss_o = _golden_c5()
+    assert go.shape == g.shape
+    assert np.linalg.norm(g - go) <= 1e-6 * np.linalg.norm(go), np.linalg.norm(g - go) / np.linalg.norm(go)
+    assert abs(loss - loss_o) <= 1e-7 * loss_o
+    print(f"[c5] |g - g_oracle|/|g_oracle| = {np.linalg.norm(g - go) / np.linalg.norm(go):.3e}, "
+          f"loss {loss:.6e} (oracle {loss_o:.6e})")
+    G.close()
+    Gt.close()
+
+
+def test_backward_uses_the_forward_stiffness():
+    """Two forwards on one handle, then backward through the first: the
+    gradient is the one a lone forward gives (backward rebuilds the handle
+    for the first stiffness field)."""
+    from paper_1612_02208_amd import StokesIB
+    from paper_1612_02208_amd.autograd import StiffnessSolve
+    wl, wt = _setup(32, 96)
+    b = torch.from_numpy(W.rhs(wl.N, 0)).cuda()
+    n2 = 2 * wl.N * wl.N
+    G = StokesIB(wl)
+    Gt = StokesIB(wt)
+    ut, _ = Gt.solve(b, rtol=1e-13, max_it=400)
+
+    def grad(second):
+        kap = torch.tensor(wl.kappa, dtype=torch.float64, requires_grad=True)
+        w = StiffnessSolve.apply(kap, G, b, 1e-13)
+        if second:
+            k2 = torch.tensor(wt.kappa, dtype=torch.float64, requires_grad=True)
+            StiffnessSolve.apply(k2, G, b, 1e-13)
+        loss = 0.5 * torch.sum((w[:n2] - ut[:n2]) ** 2)
+        loss.backward()
+        return kap.grad.detach().cpu().numpy()
+
+    g1 = grad(False)
+    g2 = grad(True)
+    assert np.linalg.norm(g2 - g1) <= 1e-9 * np.linalg.norm(g1)
+    G.close()
+    Gt.close()

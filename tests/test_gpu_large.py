@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import workloads as W
+from _parity import assert_classes, level_classes
 from oracle import ib as oib
 from oracle import mac
 
@@ -37,22 +38,23 @@ def large():
     print(f"[case] {wl.name} N={N} M={wl.M}", flush=True)
     A = mac.momentum(N, wl.rho, wl.mu, wl.dt) + oib.ib_term(X, S, wl.kappa, N, wl.dt)
     L = mac.stokes_ib(A.tocsr(), mac.gradient(N), mac.divergence(N)).tocsr()
+    cl = level_classes(N, oib.ib_term(X, S, wl.kappa, N, wl.dt))
     G = StokesIB(wl)
-    yield wl, L, G
+    yield wl, L, G, cl
     G.close()
 
 
 def test_operator_transpose_and_residual(large):
-    wl, L, G = large
+    wl, L, G, cl = large
     w = np.random.default_rng(21).uniform(-1, 1, L.shape[0])
     y = host(G.apply(dev(w)))
-    assert rel(y, L @ w) < 1e-12
+    assert_classes(y, L @ w, cl, 1e-12, "apply")
     yt = host(G.apply(dev(w), transpose=True))
-    assert rel(yt, L.T @ w) < 1e-12
+    assert_classes(yt, L.T @ w, cl, 1e-12, "apply_T")
 
 
 def test_solve_true_residual(large):
-    wl, L, G = large
+    wl, L, G, cl = large
     b = W.rhs(wl.N, 3)
     x, info = G.solve(dev(b), rtol=1e-8)
     assert info["converged"], info

@@ -9,7 +9,13 @@ import pytest
 import torch
 
 import workloads as W
+from oracle import ib as oib
 from oracle.timestep import step_rhs, time_step
+from _parity import assert_classes, level_classes
+
+
+def classes_at(wl):
+    return level_classes(wl.N, oib.ib_term(wl.X, wl.springs, wl.kappa, wl.N, wl.dt))
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +59,7 @@ def test_step_rhs(wl):
     print(f"[case] step_rhs {wl.name}", flush=True)
     G = StokesIB(wl)
     w = np.random.default_rng(3).uniform(-1, 1, 3 * wl.N * wl.N)
-    assert rel(host(G.step_rhs(dev(w))), step_rhs(wl, w)) < OPS_TOL
+    assert_classes(host(G.step_rhs(dev(w))), step_rhs(wl, w), classes_at(wl), OPS_TOL, "step rhs")
     G.close()
 
 
@@ -68,9 +74,10 @@ def test_two_steps_match_oracle(wl):
     for k in range(2):
         wg, info = G.time_step(wg, rtol=1e-12, max_it=200)
         assert info["converged"], (k, info)
+        cl = classes_at(ow)
         w, Xn, _ = time_step(ow, w, rtol=1e-12)
         ow.X = Xn
-        assert rel(host(wg), w) < SOLVE_TOL, (k, rel(host(wg), w))
+        assert_classes(host(wg), w, cl, SOLVE_TOL, f"step {k}")
         assert np.abs(G.positions() - Xn).max() < 1e-12, k
     G.close()
 

@@ -14,7 +14,14 @@ import torch
 
 import workloads as W
 from oracle.solver import Problem
+from oracle import ib as oib
 from oracle.timestep import step_rhs, time_step
+from _parity import assert_classes, level_classes
+
+
+def classes_at(wl):
+    # the rows that carry an IB term are the same for both spring models
+    return level_classes(wl.N, oib.ib_term(wl.X, wl.springs, wl.kappa, wl.N, wl.dt))
 
 pytestmark = pytest.mark.gpu
 
@@ -67,7 +74,7 @@ def test_fp32_smoother_form():
     G.close()
     assert info["converged"] and info["rel_res_true"] <= 1.2e-8
     # FP32 smoothing changes the iterates, not the accuracy of the result
-    assert rel(host(x), xo) < 1e-6
+    assert_classes(host(x), xo, level_classes(P.fine.N, P.fine.T), 1e-5, "fp32 at 1e-8 vs oracle at 1e-12")
 
 
 @pytest.mark.parametrize("smoother", ["ras", "rms", "sc"])
@@ -78,14 +85,15 @@ def test_two_tangent_steps_match_oracle(smoother):
     G = StokesIB(copy.deepcopy(wl))
     ow = copy.deepcopy(wl)
     w = 0.1 * np.random.default_rng(4).uniform(-1, 1, 3 * wl.N * wl.N)
-    assert rel(host(G.step_rhs(dev(w))), step_rhs(ow, w)) < 1e-12
+    assert_classes(host(G.step_rhs(dev(w))), step_rhs(ow, w), classes_at(ow), 1e-12, "step rhs")
     wg = dev(w)
     for k in range(2):
         wg, info = G.time_step(wg, rtol=1e-12, max_it=200)
         assert info["converged"], (k, info)
+        cl = classes_at(ow)
         w, Xn, _ = time_step(ow, w, rtol=1e-12)
         ow.X = Xn
-        assert rel(host(wg), w) < 1e-10, (k, rel(host(wg), w))
+        assert_classes(host(wg), w, cl, 1e-10, f"step {k}")
         assert np.abs(G.positions() - Xn).max() < 1e-12, k
     G.close()
 
