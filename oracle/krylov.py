@@ -92,6 +92,15 @@ def fgmres_smooth(apply_A, apply_B, w, b, nu):
     return w + e
 
 
+def richardson_smooth(apply_A, apply_B, w, b, nu):
+    """nu undamped Richardson steps w <- w + B (b - A w) with the basic
+    smoother B: the reading of a smoothing sweep as a plain Richardson
+    iteration (Sec. 6, on the large-box Vanka smoother)."""
+    for _ in range(nu):
+        w = w + apply_B(b - apply_A(w))
+    return w
+
+
 def arnoldi_ritz_max(apply_op, v0, steps):
     """Largest real part among the Ritz values (eigenvalues of the square
     Hessenberg matrix) after ``steps`` Arnoldi steps from v0."""

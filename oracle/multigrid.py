@@ -13,7 +13,7 @@ import scipy.linalg as la
 
 from . import transfer
 from .hierarchy import null_space
-from .krylov import fgmres_smooth
+from .krylov import fgmres_smooth, richardson_smooth
 from .schur import SchurSmoother
 from .schwarz import RAS, RMS, structural_pattern
 
@@ -43,8 +43,11 @@ class Multigrid:
         self.P = [None]
         for l in range(1, len(levels)):
             lev = levels[l]
+            combine = getattr(wl, "combine", "restricted")
+            if combine != "restricted" and wl.smoother != "ras":
+                raise ValueError("the summed combination applies to additive Schwarz only")
             if wl.smoother == "ras":
-                self.smoothers.append(RAS(lev.L, lev.N, wl.box, wl.overlap))
+                self.smoothers.append(RAS(lev.L, lev.N, wl.box, wl.overlap, combine))
             elif wl.smoother == "rms":
                 self.smoothers.append(RMS(lev.L, structural_pattern(lev), lev.N, wl.box, wl.overlap))
             elif wl.smoother == "sc":
@@ -56,7 +59,15 @@ class Multigrid:
             self.P.append(transfer.prolongation(Nc))
 
     def smooth(self, l, w, b, nu):
+        """Sec. 3.3 smoothing: nu FGMRES iterations preconditioned by the basic
+        smoother, or (sweep "richardson", the Sec. 6 reading) nu Richardson
+        steps with it."""
         L = self.levels[l].L
+        sweep = getattr(self.wl, "sweep", "fgmres")
+        if sweep == "richardson":
+            return richardson_smooth(lambda x: L @ x, self.smoothers[l], w, b, nu)
+        if sweep != "fgmres":
+            raise ValueError(sweep)
         return fgmres_smooth(lambda x: L @ x, self.smoothers[l], w, b, nu)
 
     def mg(self, l, w, b):

@@ -62,9 +62,16 @@ def patches(N, box, overlap) -> List[Patch]:
 
 class RAS:
     """z = sum_k R~_k^T (L_k)^{-1} R_k r with L_k = R_k L R_k^T (Alg. 2 applied
-    from a zero initial guess, so r is the given right-hand side)."""
+    from a zero initial guess, so r is the given right-hand side).
 
-    def __init__(self, L, N, box, overlap):
+    combine="sum" replaces the restriction R~_k^T by R_k^T: every unknown
+    of G_k receives box k's local solution, summed over the boxes holding it
+    (plain additive Schwarz), boxes taken in index order."""
+
+    def __init__(self, L, N, box, overlap, combine="restricted"):
+        if combine not in ("restricted", "sum"):
+            raise ValueError(combine)
+        self.combine = combine
         self.parts = patches(N, box, overlap)
         self.factors = []
         Lc = L.tocsr()
@@ -76,7 +83,10 @@ class RAS:
         z = np.zeros_like(r)
         for p, f in zip(self.parts, self.factors):
             y = la.lu_solve(f, r[p.idx])
-            z[p.own_global] = y[p.own_local]
+            if self.combine == "sum":
+                z[p.idx] += y      # the indices of one box are distinct
+            else:
+                z[p.own_global] = y[p.own_local]
         return z
 
     __call__ = apply

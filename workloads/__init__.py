@@ -50,6 +50,12 @@ class Workload:
     # operator linearised at X
     spring_model: str = "linear"
     rest: Optional[np.ndarray] = None
+    # additive Schwarz combination: "restricted" (each unknown from its owner
+    # box) or "sum" (summed over every box holding it)
+    combine: str = "restricted"
+    # a smoothing step: "fgmres" (FGMRES iterations preconditioned by the
+    # basic smoother) or "richardson" (undamped Richardson steps)
+    sweep: str = "fgmres"
 
     @property
     def M(self) -> int:
