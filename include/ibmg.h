@@ -20,8 +20,13 @@
  * Memory.  Pointers named in a ``desc`` (X, ends, kappa, rest) are HOST pointers,
  * copied during ibmg_create.  Every vector argument of the other calls is a
  * DEVICE pointer (FP64 unless stated) owned by the caller; the library never
- * frees caller memory.  The library allocates its own device workspace in
- * ibmg_create and frees it in ibmg_destroy.
+ * frees caller memory.  The library allocates no device memory: every device
+ * buffer of a handle (operators, box inverses, work vectors, set-up
+ * temporaries) lies in the one workspace region the caller passes to
+ * ibmg_create / ibmg_batch_create (256-byte aligned, at least the size
+ * ibmg_workspace_bytes / ibmg_batch_workspace_bytes report), which must stay
+ * allocated and untouched until ibmg_destroy.  A handle also holds 64 bytes
+ * of pinned host memory for its scalar reads.
  * Streams.  Calls enqueue work on the given HIP stream and return without
  * synchronising, except ibmg_create, ibmg_set_kappa and the *_solve calls,
  * which synchronise that stream.  A handle is not thread-safe; distinct
@@ -49,7 +54,13 @@ typedef enum {
   IBMG_OK = 0,
   IBMG_NOT_CONVERGED = 1, /* result valid, tolerance not reached in max_it */
   IBMG_ERR_ARG = -1,      /* invalid argument; nothing was enqueued */
-  IBMG_ERR_HIP = -2,      /* HIP runtime error (allocation, launch, fault) */
+  IBMG_ERR_HIP = -2,      /* HIP runtime error (launch, fault) */
+  IBMG_ERR_WORKSPACE = -3,/* the caller's workspace is too small (or misaligned);
+                             after a rebuild (ibmg_time_step, ibmg_set_kappa)
+                             the handle is then unusable (IBMG_ERR_STATE)     */
+  IBMG_ERR_BREAKDOWN = -4,/* a set-up factorisation broke down: a box matrix,
+                             the coarsest bordered matrix or an SC Chebyshev
+                             bound came out singular or non-finite            */
   IBMG_ERR_NONFINITE = -5,/* NaN/Inf in an input vector or in the iteration */
   IBMG_ERR_STATE = -6     /* call not valid for this handle */
 } ibmg_status;
@@ -63,6 +74,24 @@ typedef enum {
  * sweep equals Alg. 3 with the boxes in colour-major order. */
 enum { IBMG_RAS = 0, IBMG_SC = 1, IBMG_RMS = 2 };
 enum { IBMG_FP64 = 0, IBMG_FP32_SMOOTHER = 1 };  /* precision */
+
+/* combine: how the additive Schwarz smoother joins the boxes' local solutions
+ * z_k = L_k^{-1} R_k r (Alg. 2):
+ *   IBMG_COMBINE_RESTRICTED  each unknown takes the value of the one box that
+ *                            owns it (R~_k^T, the paper's restricted form)
+ *   IBMG_COMBINE_SUM         each unknown takes the sum over every box whose
+ *                            index set holds it (R_k^T: plain additive
+ *                            Schwarz), added in box-index order (deterministic,
+ *                            no atomics).  IBMG_RAS only.
+ * sweep_kind: what one of the nu1 / nu2 smoothing steps is (Sec. 3.3, Sec. 6):
+ *   IBMG_SWEEP_FGMRES        nu FGMRES iterations on L e = b - L w from e = 0,
+ *                            preconditioned by the basic smoother (default)
+ *   IBMG_SWEEP_RICHARDSON    nu undamped Richardson steps w <- w + B (b - L w)
+ *                            with the basic smoother B (the reading of Sec. 6,
+ *                            where the large-box Vanka smoother is a Richardson
+ *                            iteration).  Single-system handles only. */
+enum { IBMG_COMBINE_RESTRICTED = 0, IBMG_COMBINE_SUM = 1 };
+enum { IBMG_SWEEP_FGMRES = 0, IBMG_SWEEP_RICHARDSON = 1 };
 
 /* Spring model.  Spring e = (a, b) has separation d = X_b - X_a (minimum
  * image on the periodic square), length l = |d| and unit vector t = d / l.
@@ -83,7 +112,7 @@ enum { IBMG_SPRING_LINEAR = 0, IBMG_SPRING_TANGENT = 1 };
 
 typedef struct {
   int32_t N;          /* finest grid size; N = coarse_N * 2^k, k >= 1        */
-  int32_t coarse_N;   /* coarsest grid (Sec. 5 uses 8); 4 <= coarse_N <= 32   */
+  int32_t coarse_N;   /* coarsest grid (Sec. 5 uses 8); 4 <= coarse_N <= 16   */
   double rho, mu, dt; /* A = rho/dt I - mu Lap_h (Eq. system-impib); rho >= 0,
                          mu > 0, dt > 0                                      */
   int32_t M;          /* Lagrangian points, >= 0                             */
@@ -101,11 +130,15 @@ typedef struct {
   int32_t spring_model;/* IBMG_SPRING_LINEAR | IBMG_SPRING_TANGENT (above)    */
   const double* rest; /* host [n_springs] rest lengths >= 0, or NULL (all
                          zero); non-zero values need IBMG_SPRING_TANGENT      */
+  int32_t combine;    /* IBMG_COMBINE_RESTRICTED | IBMG_COMBINE_SUM (above)   */
+  int32_t sweep_kind; /* IBMG_SWEEP_FGMRES | IBMG_SWEEP_RICHARDSON (above)    */
+  int32_t max_restart;/* longest outer FGMRES restart the workspace holds,
+                         1..64; 0 means 30                                    */
 } ibmg_desc;
 
 typedef struct {
   double rtol;        /* stop at ||b - L x|| <= rtol ||b|| (Arnoldi estimate) */
-  int32_t restart;    /* FGMRES restart length, 1..64 (30)                    */
+  int32_t restart;    /* FGMRES restart length, 1..max_restart (30)           */
   int32_t max_it;     /* total iteration cap (100, the paper's Sec. 5 cap)    */
   int32_t use_x0;     /* 1: x holds the initial guess; 0: start from zero     */
   int32_t transpose;  /* 1: solve L_IB^T x = b (adjoint system; the Krylov
@@ -123,13 +156,30 @@ typedef struct {
   int32_t vcycles;      /* V-cycles applied                                  */
 } ibmg_solve_info;
 
+/* Bytes of device workspace ibmg_create needs for ``desc``: the exact
+ * high-water mark of the set-up's buffers (every level's operators, box
+ * inverses and work vectors, the outer FGMRES basis for max_restart, and the
+ * set-up's temporaries, among them up to 8 GiB of box matrices inverted in
+ * one batch).  Runs the set-up's host planning (no device work).  A rebuild
+ * at moved positions (ibmg_time_step) re-lays the position-dependent buffers
+ * and needs more when the structure touches more boxes, so time-stepping
+ * callers add headroom.  Errors: IBMG_ERR_ARG as ibmg_create. */
+ibmg_status ibmg_workspace_bytes(const ibmg_desc* desc, size_t* bytes);
+
 /* Create a solver for one system: copies the structure, builds every level's
  * operators (rediscretised A, G, D; Galerkin IB operator, Sec. 3.1), the
  * smoother data (RAS box inverses, Alg. 2; or SC colourings and Chebyshev
- * bounds) and the coarsest direct solve.  Synchronises ``stream``.
+ * bounds) and the coarsest direct solve, all inside ``workspace`` (a device
+ * region of ``bytes`` bytes, 256-byte aligned, owned by the caller).
+ * Synchronises ``stream``.
  * Errors: IBMG_ERR_ARG for an invalid desc (non-finite values, bad sizes,
- * out-of-range ids), IBMG_ERR_HIP on allocation or kernel failure. */
-ibmg_status ibmg_create(const ibmg_desc* desc, ibmg_stream stream, ibmg_handle** out);
+ * out-of-range ids), IBMG_ERR_WORKSPACE if the workspace is NULL, misaligned
+ * or smaller than ibmg_workspace_bytes, IBMG_ERR_BREAKDOWN if a box or the
+ * coarsest system cannot be inverted, IBMG_ERR_HIP on kernel failure. */
+ibmg_status ibmg_create(const ibmg_desc* desc, void* workspace, size_t bytes, ibmg_stream stream,
+                        ibmg_handle** out);
+/* Bytes of the handle's workspace in use now and the most ever in use. */
+ibmg_status ibmg_workspace_used(const ibmg_handle* h, size_t* in_use, size_t* peak);
 ibmg_status ibmg_destroy(ibmg_handle* h);
 const char* ibmg_last_error(const ibmg_handle* h);
 
@@ -295,8 +345,9 @@ ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int3
  * doubles in the single-system layout.  Single-system calls on a batch
  * handle (and batch calls on a single handle) return IBMG_ERR_STATE.
  * ---------------------------------------------------------------------- */
-ibmg_status ibmg_batch_create(int32_t nsys, const ibmg_desc* descs, ibmg_stream stream,
-                              ibmg_handle** out);
+ibmg_status ibmg_batch_workspace_bytes(int32_t nsys, const ibmg_desc* descs, size_t* bytes);
+ibmg_status ibmg_batch_create(int32_t nsys, const ibmg_desc* descs, void* workspace, size_t bytes,
+                              ibmg_stream stream, ibmg_handle** out);
 
 /* Number of systems of a batch handle. */
 ibmg_status ibmg_batch_size(const ibmg_handle* h, int32_t* nsys);

@@ -9,12 +9,16 @@ IBMG_OK = 0
 IBMG_NOT_CONVERGED = 1
 IBMG_ERR_ARG = -1
 IBMG_ERR_HIP = -2
+IBMG_ERR_WORKSPACE = -3
+IBMG_ERR_BREAKDOWN = -4
 IBMG_ERR_NONFINITE = -5
 IBMG_ERR_STATE = -6
 
 RAS, SC, RMS = 0, 1, 2
 SPRING_LINEAR, SPRING_TANGENT = 0, 1
 FP64, FP32_SMOOTHER = 0, 1
+COMBINE_RESTRICTED, COMBINE_SUM = 0, 1
+SWEEP_FGMRES, SWEEP_RICHARDSON = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -30,6 +34,7 @@ class Desc(ctypes.Structure):
         ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("cheb_its", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("spring_model", ctypes.c_int32), ("rest", _dp),
+        ("combine", ctypes.c_int32), ("sweep_kind", ctypes.c_int32), ("max_restart", ctypes.c_int32),
     ]
 
 
@@ -47,11 +52,11 @@ class SolveInfo(ctypes.Structure):
 
 
 EXPORTS = [
-    "ibmg_create", "ibmg_destroy", "ibmg_last_error", "ibmg_levels", "ibmg_level_n",
+    "ibmg_workspace_bytes", "ibmg_create", "ibmg_workspace_used", "ibmg_destroy", "ibmg_last_error", "ibmg_levels", "ibmg_level_n",
     "ibmg_apply_A_IB", "ibmg_apply_A_IB_T", "ibmg_spread", "ibmg_interp", "ibmg_restrict",
     "ibmg_prolong_add", "ibmg_smoother_apply", "ibmg_smooth", "ibmg_coarse_solve", "ibmg_vcycle",
     "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats", "ibmg_sc_info",
-    "ibmg_batch_create", "ibmg_batch_size", "ibmg_batch_vcycle", "ibmg_batch_fgmres_solve",
+    "ibmg_batch_workspace_bytes", "ibmg_batch_create", "ibmg_batch_size", "ibmg_batch_vcycle", "ibmg_batch_fgmres_solve",
     "ibmg_batch_stats", "ibmg_kernel_time", "ibmg_step_rhs", "ibmg_time_step", "ibmg_positions",
 ]
 
@@ -70,7 +75,10 @@ def load():
         raise RuntimeError(f"libibmg.so is not built ({LIB_PATH}); run paper_1612_02208_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
-    lib.ibmg_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+    sz = ctypes.c_size_t
+    lib.ibmg_workspace_bytes.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(sz)]
+    lib.ibmg_create.argtypes = [ctypes.POINTER(Desc), vp, sz, vp, ctypes.POINTER(vp)]
+    lib.ibmg_workspace_used.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.ibmg_destroy.argtypes = [vp]
     lib.ibmg_last_error.argtypes = [vp]
     lib.ibmg_last_error.restype = ctypes.c_char_p
@@ -87,7 +95,8 @@ def load():
     lib.ibmg_set_kappa.argtypes = [vp, _dp, vp]
     lib.ibmg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
     lib.ibmg_sc_info.argtypes = [vp, ctypes.c_int32, _dp, _ip]
-    lib.ibmg_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+    lib.ibmg_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), ctypes.POINTER(sz)]
+    lib.ibmg_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), vp, sz, vp, ctypes.POINTER(vp)]
     lib.ibmg_batch_size.argtypes = [vp, _ip]
     vpp = ctypes.POINTER(vp)
     lib.ibmg_batch_vcycle.argtypes = [vp, vpp, vpp, vp]

@@ -6,9 +6,16 @@
 #include "solver.hpp"
 
 struct ibmg_handle {
+  // the caller's workspace: every device buffer of the handle lies in it
+  std::unique_ptr<ibmg::Arena> arena;
   ibmg::SolverBase* s = nullptr;  // single system
   ibmg::BatchBase* b = nullptr;   // batched systems
   std::string err;
+  ~ibmg_handle() {
+    ibmg::ArenaScope as(arena.get());
+    delete s;
+    delete b;
+  }
 };
 
 namespace {
@@ -18,7 +25,12 @@ thread_local std::string g_create_error;
 template <typename F>
 ibmg_status guarded(ibmg_handle* h, F&& f) {
   if (!h || !h->s) return IBMG_ERR_STATE;
+  if (!h->s->valid()) {
+    h->err = "the handle lost its set-up in a failed rebuild";
+    return IBMG_ERR_STATE;
+  }
   try {
+    ibmg::ArenaScope as(h->arena.get());
     return (ibmg_status)f(h->s);
   } catch (const ibmg::Error& e) {
     h->err = e.what();
@@ -33,6 +45,7 @@ template <typename F>
 ibmg_status guarded_b(ibmg_handle* h, F&& f) {
   if (!h || !h->b) return IBMG_ERR_STATE;
   try {
+    ibmg::ArenaScope as(h->arena.get());
     return (ibmg_status)f(h->b);
   } catch (const ibmg::Error& e) {
     h->err = e.what();
@@ -49,68 +62,119 @@ void check_level(ibmg::SolverBase* s, int level, int lo) {
   ibmg::require(level >= lo && level < s->levels(), "level out of range");
 }
 
+// Runs make() with the thread's errors caught into g_create_error.
+template <typename F>
+ibmg_status creating(F&& make) {
+  try {
+    return make();
+  } catch (const ibmg::Error& e) {
+    g_create_error = e.what();
+    return (ibmg_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return IBMG_ERR_HIP;
+  }
+}
+
+// The set-up's sizing pass: placement without device work.
+template <typename F>
+size_t sizing_pass(F&& build) {
+  ibmg::Arena a = ibmg::Arena::sizing();
+  {
+    ibmg::ArenaScope as(&a);
+    ibmg::DryScope dry;
+    build();
+  }
+  return a.peak();
+}
+
+void check_workspace(void* ws, size_t bytes) {
+  if (!ws || bytes == 0) throw ibmg::Error(IBMG_ERR_WORKSPACE, "workspace is NULL or empty");
+  if ((uintptr_t)ws % ibmg::Arena::kAlign != 0)
+    throw ibmg::Error(IBMG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+}
+
 }  // namespace
 
 extern "C" {
 
-ibmg_status ibmg_create(const ibmg_desc* desc, ibmg_stream stream, ibmg_handle** out) {
+ibmg_status ibmg_workspace_bytes(const ibmg_desc* desc, size_t* bytes) {
+  if (!desc || !bytes) {
+    g_create_error = "desc or bytes is NULL";
+    return IBMG_ERR_ARG;
+  }
+  return creating([&] {
+    *bytes = sizing_pass([&] { std::unique_ptr<ibmg::SolverBase> s(ibmg::make_solver(*desc, nullptr)); });
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_create(const ibmg_desc* desc, void* workspace, size_t bytes, ibmg_stream stream,
+                        ibmg_handle** out) {
   if (!out) return IBMG_ERR_ARG;
   *out = nullptr;
   if (!desc) {
     g_create_error = "desc is NULL";
     return IBMG_ERR_ARG;
   }
-  try {
-    auto* h = new ibmg_handle();
-    try {
+  return creating([&] {
+    ibmg::validate_desc(*desc);
+    check_workspace(workspace, bytes);
+    std::unique_ptr<ibmg_handle> h(new ibmg_handle());
+    h->arena.reset(new ibmg::Arena(workspace, bytes));
+    {
+      ibmg::ArenaScope as(h->arena.get());
       h->s = ibmg::make_solver(*desc, S(stream));
-    } catch (...) {
-      delete h;
-      throw;
     }
-    *out = h;
+    *out = h.release();
     return IBMG_OK;
-  } catch (const ibmg::Error& e) {
-    g_create_error = e.what();
-    return (ibmg_status)e.code;
-  } catch (const std::exception& e) {
-    g_create_error = e.what();
-    return IBMG_ERR_HIP;
-  }
+  });
+}
+
+ibmg_status ibmg_workspace_used(const ibmg_handle* h, size_t* in_use, size_t* peak) {
+  if (!h || !h->arena) return IBMG_ERR_STATE;
+  if (in_use) *in_use = h->arena->in_use();
+  if (peak) *peak = h->arena->peak();
+  return IBMG_OK;
 }
 
 ibmg_status ibmg_destroy(ibmg_handle* h) {
   if (!h) return IBMG_ERR_STATE;
-  delete h->s;
-  delete h->b;
   delete h;
   return IBMG_OK;
 }
 
-ibmg_status ibmg_batch_create(int32_t nsys, const ibmg_desc* descs, ibmg_stream stream, ibmg_handle** out) {
+ibmg_status ibmg_batch_workspace_bytes(int32_t nsys, const ibmg_desc* descs, size_t* bytes) {
+  if (!descs || !bytes || nsys < 1) {
+    g_create_error = "descs or bytes is NULL, or nsys < 1";
+    return IBMG_ERR_ARG;
+  }
+  return creating([&] {
+    *bytes = sizing_pass([&] { std::unique_ptr<ibmg::BatchBase> b(ibmg::make_batch(nsys, descs, nullptr)); });
+    return IBMG_OK;
+  });
+}
+
+ibmg_status ibmg_batch_create(int32_t nsys, const ibmg_desc* descs, void* workspace, size_t bytes,
+                              ibmg_stream stream, ibmg_handle** out) {
   if (!out) return IBMG_ERR_ARG;
   *out = nullptr;
   if (!descs || nsys < 1) {
     g_create_error = "descs is NULL or nsys < 1";
     return IBMG_ERR_ARG;
   }
-  try {
-    auto* h = new ibmg_handle();
-    try {
+  return creating([&] {
+    ibmg::validate_batch(nsys, descs);
+    check_workspace(workspace, bytes);
+    std::unique_ptr<ibmg_handle> h(new ibmg_handle());
+    h->arena.reset(new ibmg::Arena(workspace, bytes));
+    {
+      ibmg::ArenaScope as(h->arena.get());
       h->b = ibmg::make_batch(nsys, descs, S(stream));
-    } catch (...) {
-      delete h;
-      throw;
     }
-    *out = h;
+    *out = h.release();
     return IBMG_OK;
-  } catch (const ibmg::Error& e) {
-    g_create_error = e.what();
-    return (ibmg_status)e.code;
-  } catch (const std::exception& e) {
-    g_create_error = e.what();
-    return IBMG_ERR_HIP;
-  }
+  });
 }
 
 ibmg_status ibmg_batch_size(const ibmg_handle* h, int32_t* nsys) {
@@ -140,7 +204,9 @@ ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int3
                              double* avg_ms, double* alg_bytes, double* alg_flops) {
   if (!h || (!h->s && !h->b)) return IBMG_ERR_STATE;
   if (!avg_ms) return IBMG_ERR_ARG;
+  if (h->s && !h->s->valid()) return IBMG_ERR_STATE;
   try {
+    ibmg::ArenaScope as(h->arena.get());
     *avg_ms = h->s ? h->s->kernel_time(kernel, level, reps, S(st), alg_bytes, alg_flops)
                    : h->b->kernel_time(kernel, level, reps, S(st), alg_bytes, alg_flops);
     return IBMG_OK;

@@ -24,24 +24,35 @@ constexpr size_t kScalStride = 64;  // per-system smoother scalars (beta, y)
 
 }  // namespace
 
+// Host checks of a batch's descriptors (every one valid, the shared
+// parameters equal, the options the batched form runs).
+void validate_batch(int nsys, const ibmg_desc* d) {
+  require(nsys >= 1 && nsys <= 4096, "nsys must lie in [1, 4096]");
+  require(d != nullptr, "descs is NULL");
+  const ibmg_desc& d0 = d[0];
+  for (int i = 0; i < nsys; ++i) {
+    validate_desc(d[i]);
+    require(d[i].smoother == IBMG_RAS, "the batched form uses the additive Schwarz smoother");
+    require(d[i].spring_model == IBMG_SPRING_LINEAR, "the batched form takes linear springs");
+    require(d[i].combine == IBMG_COMBINE_RESTRICTED && d[i].sweep_kind == IBMG_SWEEP_FGMRES,
+            "the batched form runs the restricted combination with FGMRES smoothing");
+    require(d[i].coarse_N == d0.coarse_N && d[i].rho == d0.rho && d[i].mu == d0.mu && d[i].dt == d0.dt &&
+                d[i].box == d0.box && d[i].overlap == d0.overlap && d[i].nu1 == d0.nu1 &&
+                d[i].nu2 == d0.nu2 && d[i].precision == d0.precision && d[i].max_restart == d0.max_restart,
+            "batched systems must share coarse_N, rho, mu, dt, box, overlap, nu1, nu2, precision and "
+            "max_restart");
+  }
+}
+
 template <typename T>
 class BatchSolver final : public BatchBase {
  public:
   BatchSolver(int nsys, const ibmg_desc* d, hipStream_t s) : ns_(nsys) {
-    require(nsys >= 1 && nsys <= 4096, "nsys must lie in [1, 4096]");
-    require(d != nullptr, "descs is NULL");
+    validate_batch(nsys, d);
     const ibmg_desc& d0 = d[0];
-    for (int i = 0; i < nsys; ++i) {
-      validate_desc(d[i]);
-      require(d[i].smoother == IBMG_RAS, "the batched form uses the additive Schwarz smoother");
-      require(d[i].spring_model == IBMG_SPRING_LINEAR, "the batched form takes linear springs");
-      require(d[i].coarse_N == d0.coarse_N && d[i].rho == d0.rho && d[i].mu == d0.mu && d[i].dt == d0.dt &&
-                  d[i].box == d0.box && d[i].overlap == d0.overlap && d[i].nu1 == d0.nu1 &&
-                  d[i].nu2 == d0.nu2 && d[i].precision == d0.precision,
-              "batched systems must share coarse_N, rho, mu, dt, box, overlap, nu1, nu2 and precision");
-    }
     nu1_ = d0.nu1;
     nu2_ = d0.nu2;
+    max_restart_ = d0.max_restart > 0 ? d0.max_restart : 30;
     rho_zero_ = d0.rho == 0.0;
     order_.resize(nsys);
     std::iota(order_.begin(), order_.end(), 0);
@@ -66,6 +77,7 @@ class BatchSolver final : public BatchBase {
         for (int p = p0; p < p0 + cnt; ++p) sys_[p]->finish_coarse(augs.p + (p - p0) * stride, s);
         IBMG_HIP(hipStreamSynchronize(s));
       }
+      for (int p = 0; p < nsys; ++p) sys_[p]->check_breakdown(s, true);
     }
     Lmax_ = sys_[0]->L_;
     nact_.assign(Lmax_ + 2, 0);
@@ -86,6 +98,7 @@ class BatchSolver final : public BatchBase {
     build_levels(s);
     build_outer_rows(s);
     build_coarse(s);
+    alloc_outer(max_restart_);
     tune(s);
     IBMG_HIP(hipStreamSynchronize(s));
   }
@@ -244,6 +257,7 @@ class BatchSolver final : public BatchBase {
   // candidates compute the same sums in the same order, so the choice
   // changes the time only.
   void tune(hipStream_t s) {
+    if (dry_run()) return;
     hipEvent_t e0, e1;
     IBMG_HIP(hipEventCreate(&e0));
     IBMG_HIP(hipEventCreate(&e1));
@@ -361,8 +375,6 @@ class BatchSolver final : public BatchBase {
   // The batched V-cycle is captured once into a HIP graph (kernel nodes
   // only) reading vin_ and writing vout_.
   void build_graph() {
-    vin_.alloc(ntot_);
-    vout_.alloc(ntot_);
     if (!gstream_) IBMG_HIP(hipStreamCreateWithFlags(&gstream_, hipStreamNonBlocking));
     launch_fill<double>(vin_.p, 0.0, ntot_, gstream_);
     launch_fill<double>(vout_.p, 0.0, ntot_, gstream_);
@@ -417,7 +429,6 @@ class BatchSolver final : public BatchBase {
  public:
   void vcycle(const double* const* r, double* const* z, hipStream_t s) override {
     require(r && z, "NULL pointer array");
-    ensure_io();
     set_all_active(s);
     gather(r, io_in_.p, s);
     vcycle_ragged(io_in_.p, io_out_.p, s);
@@ -425,11 +436,6 @@ class BatchSolver final : public BatchBase {
   }
 
  private:
-  void ensure_io() {
-    if (io_in_.n == ntot_) return;
-    io_in_.alloc(ntot_);
-    io_out_.alloc(ntot_);
-  }
 
   void set_all_active(hipStream_t s) {
     for (int p = 0; p < ns_; ++p) pin_i_[p] = 1;
@@ -476,9 +482,13 @@ class BatchSolver final : public BatchBase {
     IBMG_HIP(hipStreamSynchronize(s));
   }
 
-  void ensure_outer(int restart) {
-    ensure_io();
-    if (restart <= outer_cap_) return;
+  // every buffer of the outer solve and the V-cycle's input and output,
+  // for restarts up to max_restart (placed at creation)
+  void alloc_outer(int restart) {
+    io_in_.alloc(ntot_);
+    io_out_.alloc(ntot_);
+    vin_.alloc(ntot_);
+    vout_.alloc(ntot_);
     Vo_.alloc((size_t)(restart + 1) * ntot_);
     Zo_.alloc((size_t)restart * ntot_);
     launch_fill<double>(Vo_.p, 0.0, Vo_.n, nullptr);
@@ -506,7 +516,6 @@ class BatchSolver final : public BatchBase {
     rr_.alloc(ntot_);
     kcnt_.alloc(ns_);
     nmax_ = nmax;
-    IBMG_HIP(hipDeviceSynchronize());
     outer_cap_ = restart;
   }
 
@@ -520,11 +529,11 @@ class BatchSolver final : public BatchBase {
              hipStream_t s) override {
     const auto t0 = std::chrono::steady_clock::now();
     require(b && x, "NULL pointer array");
-    require(o.restart >= 1 && o.restart <= kMaxRestart, "restart must lie in [1, 64]");
+    require(o.restart >= 1 && o.restart <= outer_cap_,
+            "restart must lie in [1, max_restart = " + std::to_string(outer_cap_) + "]");
     require(o.max_it >= 1, "max_it must be >= 1");
     require(std::isfinite(o.rtol) && o.rtol > 0.0, "rtol must be finite and > 0");
     require(o.transpose == 0, "the batched form solves with L_IB only");
-    ensure_outer(o.restart);
     const int m = o.restart;
     set_all_active(s);
     gather(b, bp_.p, s);
@@ -694,7 +703,7 @@ class BatchSolver final : public BatchBase {
   }
 
  private:
-  int ns_ = 0, Lmax_ = 0, nu1_ = 2, nu2_ = 2, n0_ = 0;
+  int ns_ = 0, Lmax_ = 0, nu1_ = 2, nu2_ = 2, n0_ = 0, max_restart_ = 30;
   bool rho_zero_ = false;
   std::vector<int> order_, nact_;
   std::vector<std::unique_ptr<Solver<T>>> sys_;

@@ -95,7 +95,7 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
                            hipStream_t s) {
   if (!count) return;
   CsrView tu{tptr_u, tcol_u, tval_u}, tv{tptr_v, tcol_v, tval_v};
-  hipLaunchKernelGGL(k_patch_assemble, dim3(count), dim3(256), 0, s, patch_ids, g, c, tu, tv, mats);
+  IBMG_KLAUNCH(k_patch_assemble, dim3(count), dim3(256), 0, s, patch_ids, g, c, tu, tv, mats);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -399,15 +399,15 @@ void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv
   const int tiles = (n + 63) / 64;
   const int pairs = tiles * (tiles + 1) / 2;
   for (int kb = 0; kb < n; kb += GJ_NB) {
-    hipLaunchKernelGGL(k_gj_diag, dim3(count), dim3(256), 0, s, mats, n, kb, dinv);
+    IBMG_KLAUNCH(k_gj_diag, dim3(count), dim3(256), 0, s, mats, n, kb, dinv);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sw_panel_read, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work);
+    IBMG_KLAUNCH(k_sw_panel_read, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sw_scale, dim3(tiles, count), dim3(256), 0, s, dinv, n, kb, work);
+    IBMG_KLAUNCH(k_sw_scale, dim3(tiles, count), dim3(256), 0, s, dinv, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sw_update, dim3(pairs, count), dim3(256), 0, s, mats, n, kb, work);
+    IBMG_KLAUNCH(k_sw_update, dim3(pairs, count), dim3(256), 0, s, mats, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sw_panel_write, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work, dinv);
+    IBMG_KLAUNCH(k_sw_panel_write, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work, dinv);
     IBMG_LAUNCH_CHECK();
   }
 }
@@ -461,7 +461,7 @@ __device__ __forceinline__ size_t own_glob(const BoxGeom& g, int pid, int r) {
 // contiguous stream of nloc * 64 values.
 template <typename T>
 __global__ void k_extract_owned(const double* __restrict__ mats, int count, BoxGeom g,
-                                T* __restrict__ out) {
+                                T* __restrict__ out, bool full) {
   const size_t per = (size_t)g.nch * g.nloc * 64;
   const size_t tot = per * count;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
@@ -475,7 +475,7 @@ __global__ void k_extract_owned(const double* __restrict__ mats, int count, BoxG
     // the swept matrix holds -A^{-1} in the tiles on or below the diagonal
     T v = 0;
     if (row < g.nown) {
-      const int lr = own_local(row, g);
+      const int lr = full ? row : own_local(row, g);
       v = (T)(-((lr >> 6) >= (j >> 6) ? A[(size_t)lr * g.nloc + j] : A[(size_t)j * g.nloc + lr]));
     }
     out[t] = v;
@@ -483,12 +483,12 @@ __global__ void k_extract_owned(const double* __restrict__ mats, int count, BoxG
 }
 
 template <typename T>
-void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s) {
+void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s, bool full) {
   if (!count) return;
   size_t tot = (size_t)g.nch * g.nloc * 64 * count;
   int grid = cdiv(tot, 256);
   if (grid > 16384) grid = 16384;
-  hipLaunchKernelGGL((k_extract_owned<T>), dim3(grid), dim3(256), 0, s, mats, count, g, out);
+  IBMG_KLAUNCH((k_extract_owned<T>), dim3(grid), dim3(256), 0, s, mats, count, g, out, full);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -1103,7 +1103,7 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   T* tpart = part + (ks_ib > 1 ? (size_t)ks_ib * n_ib * nown_pad : 0);
   if (do_ib) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
-    hipLaunchKernelGGL((k_ras_ib<T>), dim3(n_ib, g.nch, ks_ib), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc,
+    IBMG_KLAUNCH((k_ras_ib<T>), dim3(n_ib, g.nch, ks_ib), dim3(256), lds, s, r, z, g, inv, ib_boxes, acc,
                        ipart);
     IBMG_LAUNCH_CHECK();
   }
@@ -1114,18 +1114,18 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
       const size_t tot = (size_t)g.nloc * nbp;
       int grid = cdiv(tot, 256);
       if (grid > 8192) grid = 8192;
-      hipLaunchKernelGGL((k_int_gather<T>), dim3(grid), dim3(256), 0, s, r, xg, g, int_boxes, n_int, nbp, loc_tab);
+      IBMG_KLAUNCH((k_int_gather<T>), dim3(grid), dim3(256), 0, s, r, xg, g, int_boxes, n_int, nbp, loc_tab);
       IBMG_LAUNCH_CHECK();
-      hipLaunchKernelGGL((k_int_gemm<T>), dim3(g.nch, nbp / 128, ks), dim3(256), 0, s, shared_inv, xg, z, g,
+      IBMG_KLAUNCH((k_int_gemm<T>), dim3(g.nch, nbp / 128, ks), dim3(256), 0, s, shared_inv, xg, z, g,
                          int_boxes, n_int, nbp, tpart, ks, acc);
     } else if (tb == 64)
-      hipLaunchKernelGGL((k_ras_interior_g<T>), dim3((n_int + 63) / 64, g.nch, ks), dim3(256), 0, s, r, z, g,
+      IBMG_KLAUNCH((k_ras_interior_g<T>), dim3((n_int + 63) / 64, g.nch, ks), dim3(256), 0, s, r, z, g,
                          shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
     else if (tb == 16)
-      hipLaunchKernelGGL((k_ras_interior<T, 16>), dim3((n_int + 15) / 16, g.nch, ks), dim3(256), 0, s, r, z, g,
+      IBMG_KLAUNCH((k_ras_interior<T, 16>), dim3((n_int + 15) / 16, g.nch, ks), dim3(256), 0, s, r, z, g,
                          shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
     else
-      hipLaunchKernelGGL((k_ras_interior<T, 32>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
+      IBMG_KLAUNCH((k_ras_interior<T, 32>), dim3((n_int + 31) / 32, g.nch, ks), dim3(256), 0, s, r, z, g,
                          shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
     IBMG_LAUNCH_CHECK();
   }
@@ -1133,10 +1133,79 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   if (na + nb > 0) {
     int grid = cdiv((size_t)(na + nb) * g.nown, 256);
     if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL((k_ras_sum<T>), dim3(grid), dim3(256), 0, s, ipart, ib_boxes, na, ks_ib, tpart, int_boxes, nb,
+    IBMG_KLAUNCH((k_ras_sum<T>), dim3(grid), dim3(256), 0, s, ipart, ib_boxes, na, ks_ib, tpart, int_boxes, nb,
                        ks_int, z, g, acc);
     IBMG_LAUNCH_CHECK();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Summed additive Schwarz (the plain R_k^T combination).  First every box's
+// whole local solution y_k = L_k^{-1} R_k r: a work-group per (box, 64-row
+// chunk) streams that chunk of the box's full inverse as the IB-box kernel
+// does (interior boxes share one inverse) and writes the 64 rows to
+// Y[(box * nch + chunk) * 64 + row].  Then every unknown gathers its entries
+// from the boxes whose index set holds it: no two work-groups write one
+// unknown, and no atomics are needed.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_asm_local(const T* __restrict__ r, BoxGeom g, const T* __restrict__ inv,
+                                                   const int* __restrict__ box_inv, T* __restrict__ Y) {
+  extern __shared__ char smem_raw[];
+  T* x = reinterpret_cast<T*>(smem_raw);
+  T* part = x + ((g.nloc + 3) & ~3);
+  const int pid = blockIdx.x, chunk = blockIdx.y;
+  const T* Mc = inv + ((size_t)box_inv[pid] * g.nch + chunk) * g.nloc * 64;
+  ras_ib_chunk<T, true>(r, nullptr, g, Mc, pid, chunk, x, part, false, 0, g.nloc,
+                        Y + ((size_t)pid * g.nch + chunk) * 64);
+}
+
+// z[d] = sum of unknown d's entries over the boxes that hold it.  Along each
+// axis the boxes holding a coordinate lie within reach (b + o) / b + 1 of its
+// owner box (on levels with fewer boxes than that window, every box is
+// tried); they are visited rows of boxes first, in increasing offset from
+// the owner, a fixed order per unknown.
+template <typename T>
+__global__ void k_asm_gather(const T* __restrict__ Y, T* __restrict__ z, BoxGeom g) {
+  const int N = g.N, m = g.m, nu = m * (m + 1), npd = g.npd;
+  const size_t nn = (size_t)N * N, tot = 3 * nn;
+  const int reach = (g.b + g.o) / g.b + 1;
+  const bool every = 2 * reach + 1 >= npd;
+  const int cnt = every ? npd : 2 * reach + 1;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int comp = (int)(t / nn);
+    const size_t q = t - (size_t)comp * nn;
+    const int i = (int)(q % N), j = (int)(q / N);
+    const int ext_x = comp == 0 ? m + 1 : m, ext_y = comp == 1 ? m + 1 : m;
+    const int ox = i / g.b, oy = j / g.b;
+    T acc = 0;
+    for (int ty = 0; ty < cnt; ++ty) {
+      const int by = every ? ty : pmod(oy - reach + ty, npd);
+      const int jj = pmod(j - (by * g.b - g.o), N);
+      if (jj >= ext_y) continue;
+      for (int tx = 0; tx < cnt; ++tx) {
+        const int bx = every ? tx : pmod(ox - reach + tx, npd);
+        const int ii = pmod(i - (bx * g.b - g.o), N);
+        if (ii >= ext_x) continue;
+        const int k = comp == 0 ? jj * (m + 1) + ii : (comp == 1 ? nu + jj * m + ii : 2 * nu + jj * m + ii);
+        acc += Y[((size_t)(by * npd + bx) * g.nch + (k >> 6)) * 64 + (k & 63)];
+      }
+    }
+    z[t] = acc;
+  }
+}
+
+template <typename T>
+void launch_asm_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* box_inv, T* Y, hipStream_t s) {
+  const int nbox = g.npd * g.npd;
+  const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
+  IBMG_KLAUNCH((k_asm_local<T>), dim3(nbox, g.nch), dim3(256), lds, s, r, g, inv, box_inv, Y);
+  IBMG_LAUNCH_CHECK();
+  const size_t tot = 3 * (size_t)g.N * g.N;
+  int grid = cdiv(tot, 256);
+  if (grid > 8192) grid = 8192;
+  IBMG_KLAUNCH((k_asm_gather<T>), dim3(grid), dim3(256), 0, s, Y, z, g);
+  IBMG_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -1203,13 +1272,13 @@ void launch_ras_batch(const T* r, T* z, BoxGeom g, size_t sys_n, int nbox, const
                                 : (tb == 64 ? sizeof(GemmSmem<T>) : sizeof(IntTileSmem<T, 32>));
   if (tile > lds) lds = tile;
   if (tb == 16)
-    hipLaunchKernelGGL((k_ras_batch<T, 16>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
+    IBMG_KLAUNCH((k_ras_batch<T, 16>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
                        int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
   else if (tb == 64)
-    hipLaunchKernelGGL((k_ras_batch<T, 64>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
+    IBMG_KLAUNCH((k_ras_batch<T, 64>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
                        int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
   else
-    hipLaunchKernelGGL((k_ras_batch<T, 32>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
+    IBMG_KLAUNCH((k_ras_batch<T, 32>), dim3(grid), dim3(256), lds, s, r, z, g, sys_n, nbox, shared_inv,
                        int_ents, n_int, ib_ents, ib_inv, n_ib, loc_tab, active);
   IBMG_LAUNCH_CHECK();
 }
@@ -1276,7 +1345,7 @@ void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, cons
                             const double* tval_v, int nb, double* aug, hipStream_t s) {
   CsrView tu{tptr_u, tcol_u, tval_u}, tv{tptr_v, tcol_v, tval_v};
   const int nn = 3 * N * N + nb;
-  hipLaunchKernelGGL(k_coarse_assemble, dim3(cdiv(nn, 64)), dim3(64), 0, s, N, c, tu, tv, nb, aug);
+  IBMG_KLAUNCH(k_coarse_assemble, dim3(cdiv(nn, 64)), dim3(64), 0, s, N, c, tu, tv, nb, aug);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -1339,7 +1408,7 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug
 void launch_coarse_invert(double* aug, int nn, int count, size_t stride, hipStream_t s) {
   if (nn > 1024) throw Error(IBMG_ERR_ARG, "coarsest system too large for one work-group");
   if (count < 1) return;
-  hipLaunchKernelGGL(k_coarse_invert, dim3(count), dim3(1024), 0, s, aug, nn, stride);
+  IBMG_KLAUNCH(k_coarse_invert, dim3(count), dim3(1024), 0, s, aug, nn, stride);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -1351,7 +1420,7 @@ __global__ void k_coarse_extract(const double* __restrict__ aug, int nn, int n0,
 }
 
 void launch_coarse_extract(const double* aug, int nn, int n0, double* inv, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_extract, dim3(cdiv((size_t)n0 * n0, 256)), dim3(256), 0, s, aug, nn, n0, inv);
+  IBMG_KLAUNCH(k_coarse_extract, dim3(cdiv((size_t)n0 * n0, 256)), dim3(256), 0, s, aug, nn, n0, inv);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -1379,7 +1448,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply(const double* __restrict__
 template <typename T>
 void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cdiv(n0, 4), nsys), dim3(256), 0, s, inv, n0, r, z);
+  IBMG_KLAUNCH((k_coarse_apply<T>), dim3(cdiv(n0, 4), nsys), dim3(256), 0, s, inv, n0, r, z);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -1388,8 +1457,11 @@ void launch_coarse_apply(const double* inv, int n0, const T* r, T* z, hipStream_
   launch_coarse_apply_batch<T>(inv, n0, r, z, 1, s);
 }
 
-template void launch_extract_owned<double>(const double*, int, BoxGeom, double*, hipStream_t);
-template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t);
+template void launch_extract_owned<double>(const double*, int, BoxGeom, double*, hipStream_t, bool);
+template void launch_extract_owned<float>(const double*, int, BoxGeom, float*, hipStream_t, bool);
+template void launch_asm_apply<double>(const double*, double*, BoxGeom, const double*, const int*, double*,
+                                       hipStream_t);
+template void launch_asm_apply<float>(const float*, float*, BoxGeom, const float*, const int*, float*, hipStream_t);
 template void launch_ras_apply<double>(const double*, double*, BoxGeom, const double*, const int*, int,
                                        const double*, const int*, int, const int*, double*,
                                        hipStream_t, int, bool, int, double*, size_t);

@@ -185,14 +185,14 @@ static void launch_apply_r(const T* w, T* y, const T* b, const T* F, const T* G,
   dim3 grd((N + blk.x - 1) / blk.x, (N + blk.y * RJ - 1) / (blk.y * RJ), nsys);
   if (b) {
     if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+      IBMG_KLAUNCH((k_apply<T, true, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
     else
-      hipLaunchKernelGGL((k_apply<T, false, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+      IBMG_KLAUNCH((k_apply<T, false, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
   } else {
     if (transpose)
-      hipLaunchKernelGGL((k_apply<T, true, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+      IBMG_KLAUNCH((k_apply<T, true, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
     else
-      hipLaunchKernelGGL((k_apply<T, false, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
+      IBMG_KLAUNCH((k_apply<T, false, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, bs);
   }
   IBMG_LAUNCH_CHECK();
 }
@@ -225,10 +225,10 @@ static void launch_apply_dots_r(const T* w, T* y, const T* b, const T* F, const 
   const dim3 blk = apply_block(RJ);
   dim3 grd((N + blk.x - 1) / blk.x, (N + blk.y * RJ - 1) / (blk.y * RJ));
   if (b)
-    hipLaunchKernelGGL((k_apply_dots<T, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
+    IBMG_KLAUNCH((k_apply_dots<T, true, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
                        vstride, partial);
   else
-    hipLaunchKernelGGL((k_apply_dots<T, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
+    IBMG_KLAUNCH((k_apply_dots<T, false, IBM, RJ>), grd, blk, 0, s, w, y, b, F, G, fx, fy, N, M, c, V, nvec,
                        vstride, partial);
   IBMG_LAUNCH_CHECK();
 }
@@ -291,7 +291,7 @@ template <typename T>
 void launch_ib_rows(const T* x, T* y, const int* rows, const int* ptr, const int* col, const T* val,
                     int nrows, T sign, hipStream_t s) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL((k_ib_rows<T>), dim3(cdiv(nrows, 4)), dim3(256), 0, s, x, y, rows, ptr, col, val, nrows, sign);
+  IBMG_KLAUNCH((k_ib_rows<T>), dim3(cdiv(nrows, 4)), dim3(256), 0, s, x, y, rows, ptr, col, val, nrows, sign);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -348,7 +348,7 @@ void launch_restrict_batch(const T* fine, T* coarse, int Nc, int nsys, hipStream
   if (nsys <= 0) return;
   dim3 blk(64, 4);
   dim3 grd((Nc + 63) / 64, (Nc + 3) / 4, nsys);
-  hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc, nullptr);
+  IBMG_KLAUNCH((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc, nullptr);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -363,7 +363,7 @@ template <typename T>
 void launch_restrict_norm(const T* fine, T* coarse, int Nc, double* partial, hipStream_t s) {
   dim3 blk(64, 4);
   dim3 grd((Nc + 63) / 64, (Nc + 3) / 4, 1);
-  hipLaunchKernelGGL((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc, partial);
+  IBMG_KLAUNCH((k_restrict<T>), grd, blk, 0, s, fine, coarse, Nc, partial);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -404,7 +404,7 @@ void launch_prolong_add_batch(const T* coarse, T* fine, int Nc, int nsys, hipStr
   const int Nf = 2 * Nc;
   dim3 blk(64, 4);
   dim3 grd((Nf + 63) / 64, (Nf + 3) / 4, nsys);
-  hipLaunchKernelGGL((k_prolong_add<T>), grd, blk, 0, s, coarse, fine, Nc);
+  IBMG_KLAUNCH((k_prolong_add<T>), grd, blk, 0, s, coarse, fine, Nc);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -427,7 +427,7 @@ void launch_cast(const Ts* a, Td* b, size_t n, hipStream_t s) {
   if (!n) return;
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_cast<Ts, Td>), dim3(g), dim3(256), 0, s, a, b, n);
+  IBMG_KLAUNCH((k_cast<Ts, Td>), dim3(g), dim3(256), 0, s, a, b, n);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -442,7 +442,43 @@ void launch_fill(T* a, T v, size_t n, hipStream_t s) {
   if (!n) return;
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_fill<T>), dim3(g), dim3(256), 0, s, a, v, n);
+  IBMG_KLAUNCH((k_fill<T>), dim3(g), dim3(256), 0, s, a, v, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+// y += x
+template <typename T>
+__global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
+template <typename T>
+void launch_axpy(T* y, const T* x, size_t n, hipStream_t s) {
+  if (!n) return;
+  int g = cdiv(n, 256);
+  if (g > 4096) g = 4096;
+  IBMG_KLAUNCH((k_axpy<T>), dim3(g), dim3(256), 0, s, y, x, n);
+  IBMG_LAUNCH_CHECK();
+}
+
+// *flag = 1 if any of a[0..n) is NaN or infinite (every writer stores the
+// same value, so the unsynchronised stores need no ordering)
+template <typename T>
+__global__ void k_count_nonfinite(const T* __restrict__ a, size_t n, int* __restrict__ flag) {
+  bool bad = false;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(a[i]);
+  if (bad) *flag = 1;
+}
+
+template <typename T>
+void launch_count_nonfinite(const T* a, size_t n, int* flag, hipStream_t s) {
+  if (!n) return;
+  int g = cdiv(n, 256 * 8);
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  IBMG_KLAUNCH((k_count_nonfinite<T>), dim3(g), dim3(256), 0, s, a, n, flag);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -490,7 +526,7 @@ template <typename T>
 void launch_dots_b(const T* V, int nvec, size_t stride, const T* t, BSeg sg, int nsys, double* partial,
                    size_t pstride, int nblk, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_dots<T>), dim3(nblk, nsys), dim3(256), 0, s, V, nvec, stride, t, sg, partial, pstride);
+  IBMG_KLAUNCH((k_dots<T>), dim3(nblk, nsys), dim3(256), 0, s, V, nvec, stride, t, sg, partial, pstride);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -544,7 +580,7 @@ __global__ void __launch_bounds__(256) k_dots_finish(const double* __restrict__ 
 void launch_dots_finish_b(const double* partial, int nvec, int nblk, size_t pstride, double* out1,
                           double* out2, size_t ostride, int mode, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL(k_dots_finish, dim3(nsys), dim3(256), 0, s, partial, nvec, nblk, pstride, out1, out2,
+  IBMG_KLAUNCH(k_dots_finish, dim3(nsys), dim3(256), 0, s, partial, nvec, nblk, pstride, out1, out2,
                      ostride, mode);
   IBMG_LAUNCH_CHECK();
 }
@@ -570,7 +606,7 @@ void launch_update(T* t, const T* V, int nvec, size_t stride, const double* coef
                    size_t n, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL((k_update<T>), dim3(g), dim3(256), 0, s, t, V, nvec, stride, coef, sign, n);
+  IBMG_KLAUNCH((k_update<T>), dim3(g), dim3(256), 0, s, t, V, nvec, stride, coef, sign, n);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -594,7 +630,7 @@ void launch_scale_b(const T* t, T* v, const double* denom, size_t dstride, BSeg 
   int g = cdiv(nmax, 256);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL((k_scale<T>), dim3(g, nsys), dim3(256), 0, s, t, v, denom, dstride, sg);
+  IBMG_KLAUNCH((k_scale<T>), dim3(g, nsys), dim3(256), 0, s, t, v, denom, dstride, sg);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -629,7 +665,7 @@ void launch_combine_b(T* x, const T* Z, size_t stride, const double* y, size_t y
   int g = cdiv(nmax, 256);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL((k_combine<T>), dim3(g, nsys), dim3(256), 0, s, x, Z, 0, stride, y, ystride, kcnt, sg);
+  IBMG_KLAUNCH((k_combine<T>), dim3(g, nsys), dim3(256), 0, s, x, Z, 0, stride, y, ystride, kcnt, sg);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -637,7 +673,7 @@ template <typename T>
 void launch_combine(T* x, const T* Z, int k, size_t stride, const double* y, size_t n, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL((k_combine<T>), dim3(g, 1), dim3(256), 0, s, x, Z, k, stride, y, (size_t)0,
+  IBMG_KLAUNCH((k_combine<T>), dim3(g, 1), dim3(256), 0, s, x, Z, k, stride, y, (size_t)0,
                      (const int*)nullptr, seg1(n));
   IBMG_LAUNCH_CHECK();
 }
@@ -683,7 +719,7 @@ __global__ void k_small_ls(const double* __restrict__ H, int ldh, int k, const d
 }
 
 void launch_small_ls(double* H, int ldh, int k, const double* beta, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_ls, dim3(1), dim3(64), 0, s, H, ldh, k, beta, y);
+  IBMG_KLAUNCH(k_small_ls, dim3(1), dim3(64), 0, s, H, ldh, k, beta, y);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -723,7 +759,7 @@ __global__ void k_givens(double* __restrict__ H, int ldh, size_t hstride, int k,
 void launch_givens_b(double* H, int ldh, size_t hstride, int k, double* cs, double* sn, double* g,
                      size_t rstride, double* res, const int* active, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL(k_givens, dim3(nsys), dim3(64), 0, s, H, ldh, hstride, k, cs, sn, g, rstride, res, active);
+  IBMG_KLAUNCH(k_givens, dim3(nsys), dim3(64), 0, s, H, ldh, hstride, k, cs, sn, g, rstride, res, active);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -753,12 +789,12 @@ __global__ void k_backsolve(const double* __restrict__ H, int ldh, size_t hstrid
 void launch_backsolve_b(const double* H, int ldh, size_t hstride, const int* kcnt, const double* g,
                         double* y, size_t rstride, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL(k_backsolve, dim3(nsys), dim3(64), 0, s, H, ldh, hstride, 0, kcnt, g, y, rstride);
+  IBMG_KLAUNCH(k_backsolve, dim3(nsys), dim3(64), 0, s, H, ldh, hstride, 0, kcnt, g, y, rstride);
   IBMG_LAUNCH_CHECK();
 }
 
 void launch_backsolve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, (size_t)0, k, (const int*)nullptr, g, y,
+  IBMG_KLAUNCH(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, (size_t)0, k, (const int*)nullptr, g, y,
                      (size_t)0);
   IBMG_LAUNCH_CHECK();
 }
@@ -787,7 +823,7 @@ template <typename T>
 void launch_block_sums_b(const T* a, int N, size_t bs, double* partial, int nblk, size_t pstride, int nsys,
                          hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_block_sums<T>), dim3(nblk, nsys), dim3(256), 0, s, a, (size_t)N * N, partial, bs,
+  IBMG_KLAUNCH((k_block_sums<T>), dim3(nblk, nsys), dim3(256), 0, s, a, (size_t)N * N, partial, bs,
                      pstride);
   IBMG_LAUNCH_CHECK();
 }
@@ -822,7 +858,7 @@ void launch_subtract_means_b(T* a, int N, size_t bs, const double* sums, size_t 
   size_t nn = (size_t)N * N;
   int g = cdiv(nn, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_subtract_means<T>), dim3(g, nsys), dim3(256), 0, s, a, nn, sums, nvel, bs, sstride);
+  IBMG_KLAUNCH((k_subtract_means<T>), dim3(g, nsys), dim3(256), 0, s, a, nn, sums, nvel, bs, sstride);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -841,6 +877,8 @@ void launch_subtract_means(T* a, int N, const double* sums, int nvel, hipStream_
   template void launch_restrict_norm<T>(const T*, T*, int, double*, hipStream_t);                 \
   template void launch_prolong_add<T>(const T*, T*, int, hipStream_t);                            \
   template void launch_fill<T>(T*, T, size_t, hipStream_t);                                       \
+  template void launch_axpy<T>(T*, const T*, size_t, hipStream_t);                                \
+  template void launch_count_nonfinite<T>(const T*, size_t, int*, hipStream_t);                   \
   template void launch_dots<T>(const T*, int, size_t, const T*, size_t, double*, int, hipStream_t); \
   template void launch_update<T>(T*, const T*, int, size_t, const double*, double, size_t,        \
                                  hipStream_t);                                                    \
@@ -873,5 +911,6 @@ IBMG_INST_GRID(float)
 template void launch_cast<double, float>(const double*, float*, size_t, hipStream_t);
 template void launch_cast<float, double>(const float*, double*, size_t, hipStream_t);
 template void launch_cast<double, double>(const double*, double*, size_t, hipStream_t);
+template void launch_fill<int>(int*, int, size_t, hipStream_t);
 
 }  // namespace ibmg

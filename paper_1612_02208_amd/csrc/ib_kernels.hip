@@ -57,7 +57,7 @@ __global__ void k_fp_fine(const double* __restrict__ X, int M, int N, int comp,
 void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
                     double* w, hipStream_t s) {
   if (!M) return;
-  hipLaunchKernelGGL(k_fp_fine, dim3(cdiv(M, 128)), dim3(128), 0, s, X, M, N, comp, base, mask, w);
+  IBMG_KLAUNCH(k_fp_fine, dim3(cdiv(M, 128)), dim3(128), 0, s, X, M, N, comp, base, mask, w);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -111,7 +111,7 @@ template <typename T>
 void launch_gather_weights(const double* w, const int* ent, size_t n, T* sw, hipStream_t s) {
   if (!n) return;
   const int g = (int)std::min<size_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_gather_weights<T>), dim3(g), dim3(256), 0, s, w, ent, n, sw);
+  IBMG_KLAUNCH((k_gather_weights<T>), dim3(g), dim3(256), 0, s, w, ent, n, sw);
   IBMG_LAUNCH_CHECK();
 }
 template void launch_gather_weights<double>(const double*, const int*, size_t, double*, hipStream_t);
@@ -122,7 +122,7 @@ void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int
   (void)Nf;
   (void)Nc;
   if (!M) return;
-  hipLaunchKernelGGL(k_fp_coarsen, dim3(cdiv(M, 128)), dim3(128), 0, s, fbase, fw, cbase, M, comp, cw);
+  IBMG_KLAUNCH(k_fp_coarsen, dim3(cdiv(M, 128)), dim3(128), 0, s, fbase, fw, cbase, M, comp, cw);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -188,7 +188,7 @@ __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __r
 template <typename T>
 static void launch_interp_lanes(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
                                 int interleaved, hipStream_t s) {
-  hipLaunchKernelGGL((k_interp_lanes<T>), dim3(cdiv((size_t)2 * M * 4, 256)), dim3(256), 0, s, u, v, fx, fy, M, N,
+  IBMG_KLAUNCH((k_interp_lanes<T>), dim3(cdiv((size_t)2 * M * 4, 256)), dim3(256), 0, s, u, v, fx, fy, M, N,
                      U, interleaved);
   IBMG_LAUNCH_CHECK();
 }
@@ -198,7 +198,7 @@ void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, Spr
                      int N, T* U, T* F, hipStream_t s) {
   if (!sv.M) return;
   launch_interp_lanes<T>(u, v, fx, fy, sv.M, N, U, 0, s);
-  hipLaunchKernelGGL((k_spring_force<T>), dim3(cdiv(sv.M, 256)), dim3(256), 0, s, U, sv, F);
+  IBMG_KLAUNCH((k_spring_force<T>), dim3(cdiv(sv.M, 256)), dim3(256), 0, s, U, sv, F);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -237,7 +237,7 @@ __global__ void k_fibre_force(const double* __restrict__ X, SpringView<double> s
 void launch_fibre_force(const double* X, SpringView<double> sv, const double* kap, const double* rest, double* F,
                         hipStream_t s) {
   if (!sv.M) return;
-  hipLaunchKernelGGL(k_fibre_force, dim3(cdiv(sv.M, 256)), dim3(256), 0, s, X, sv, kap, rest, F);
+  IBMG_KLAUNCH(k_fibre_force, dim3(cdiv(sv.M, 256)), dim3(256), 0, s, X, sv, kap, rest, F);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -252,7 +252,7 @@ void launch_step_rhs(const double* w, const double* f, double a, int N, double* 
   const size_t nn = (size_t)N * N;
   int g = cdiv(3 * nn, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_step_rhs, dim3(g), dim3(256), 0, s, w, f, a, nn, rhs);
+  IBMG_KLAUNCH(k_step_rhs, dim3(g), dim3(256), 0, s, w, f, a, nn, rhs);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -267,7 +267,7 @@ __global__ void k_advance(double* __restrict__ X, const double* __restrict__ U, 
 
 void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s) {
   if (!M) return;
-  hipLaunchKernelGGL(k_advance, dim3(cdiv(2 * (size_t)M, 256)), dim3(256), 0, s, X, U, dt, M);
+  IBMG_KLAUNCH(k_advance, dim3(cdiv(2 * (size_t)M, 256)), dim3(256), 0, s, X, U, dt, M);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -310,7 +310,7 @@ void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, in
                    double scale, double* f, hipStream_t s) {
   (void)M;
   dim3 grd(cdiv((size_t)N * N, kSpreadTile), 2);
-  hipLaunchKernelGGL(k_spread, grd, dim3(kSpreadTile), 0, s, F, fx, fy, N, scale, f);
+  IBMG_KLAUNCH(k_spread, grd, dim3(kSpreadTile), 0, s, F, fx, fy, N, scale, f);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -412,13 +412,13 @@ void launch_t_values(FootView<double> f0, FootView<double> f1, const int* mask0,
                      double* t_val, int nslice, size_t nnz, double* part, hipStream_t s) {
   if (nslice < 1 || (nslice > 1 && !part)) throw Error(IBMG_ERR_ARG, "IB-row slices need a partial buffer");
   const size_t n = (size_t)N * N;
-  hipLaunchKernelGGL(k_t_values, dim3(cdiv(n * nslice * 64, 256)), dim3(256), 0, s, f0, f1, mask0, mask1, sv, comp,
+  IBMG_KLAUNCH(k_t_values, dim3(cdiv(n * nslice * 64, 256)), dim3(256), 0, s, f0, f1, mask0, mask1, sv, comp,
                      N, ibs, t_ptr, t_col, t_val, nslice, nnz, part);
   IBMG_LAUNCH_CHECK();
   if (nslice > 1) {
     int grid = cdiv(nnz, 256);
     if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL(k_t_sum, dim3(grid < 1 ? 1 : grid), dim3(256), 0, s, part, nslice, nnz, t_val);
+    IBMG_KLAUNCH(k_t_sum, dim3(grid < 1 ? 1 : grid), dim3(256), 0, s, part, nslice, nnz, t_val);
     IBMG_LAUNCH_CHECK();
   }
 }
@@ -447,7 +447,7 @@ __global__ void k_spring_grad(const double* __restrict__ Uw, const double* __res
 void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* blocks,
                         int n_springs, double scale, double* out, hipStream_t s) {
   if (!n_springs) return;
-  hipLaunchKernelGGL(k_spring_grad, dim3(cdiv(n_springs, 128)), dim3(128), 0, s, Uw, Ul, ends, blocks,
+  IBMG_KLAUNCH(k_spring_grad, dim3(cdiv(n_springs, 128)), dim3(128), 0, s, Uw, Ul, ends, blocks,
                      n_springs, scale, out);
   IBMG_LAUNCH_CHECK();
 }
@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(256) k_ib_spmv(const T* __restrict__ x, T* __r
 template <typename T>
 void launch_ib_spmv(const T* x, T* G, CsrT<T> tu, CsrT<T> tv, int N, hipStream_t s) {
   const size_t waves = 2 * (size_t)N * N;
-  hipLaunchKernelGGL((k_ib_spmv<T>), dim3(cdiv(waves * 64, 256)), dim3(256), 0, s, x, G, tu, tv, N);
+  IBMG_KLAUNCH((k_ib_spmv<T>), dim3(cdiv(waves * 64, 256)), dim3(256), 0, s, x, G, tu, tv, N);
   IBMG_LAUNCH_CHECK();
 }
 

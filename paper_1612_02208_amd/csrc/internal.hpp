@@ -18,6 +18,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -32,43 +34,171 @@ struct Error : public std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
-#define IBMG_HIP(expr)                                                              \
-  do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
-    if (e_ != hipSuccess)                                                           \
-      throw ::ibmg::Error(IBMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+// Sizing pass.  ibmg_workspace_bytes runs the whole set-up with this flag
+// set: host planning and buffer placement happen as in ibmg_create, but no
+// kernel is launched and no HIP runtime call is made, so the placement's
+// high-water mark is the exact workspace the real set-up needs.
+inline bool& dry_run_flag() {
+  static thread_local bool f = false;
+  return f;
+}
+inline bool dry_run() { return dry_run_flag(); }
+struct DryScope {
+  bool prev;
+  DryScope() : prev(dry_run_flag()) { dry_run_flag() = true; }
+  ~DryScope() { dry_run_flag() = prev; }
+};
+
+#define IBMG_HIP(expr)                                                                      \
+  do {                                                                                      \
+    if (!::ibmg::dry_run()) {                                                               \
+      hipError_t e_ = (expr);                                                               \
+      if (e_ != hipSuccess)                                                                 \
+        throw ::ibmg::Error(IBMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                                       \
   } while (0)
 
 #define IBMG_LAUNCH_CHECK() IBMG_HIP(hipGetLastError())
+
+// every kernel launch of the library (skipped in the sizing pass)
+#define IBMG_KLAUNCH(...)                                    \
+  do {                                                       \
+    if (!::ibmg::dry_run()) hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
 
 inline void require(bool ok, const std::string& msg) {
   if (!ok) throw Error(IBMG_ERR_ARG, msg);
 }
 
-// Owning device buffer.
+// Device memory of one handle: the single region the caller passes to
+// ibmg_create.  Blocks are 256-byte aligned and placed first-fit from a
+// free list ordered by offset; freed blocks merge with free neighbours and
+// a freed block at the top lowers it.  The placement depends only on the
+// sequence of sizes, so a sizing arena (no memory behind it: it hands out
+// addresses of a virtual region that nothing dereferences) run through the
+// same sequence reports the exact size needed as its high-water mark.
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  Arena(void* base, size_t cap) : base_(static_cast<char*>(base)), cap_(cap) {}
+  static Arena sizing() { return Arena(nullptr, ~(size_t)0); }
+  bool is_sizing() const { return base_ == nullptr; }
+  size_t capacity() const { return cap_; }
+  size_t in_use() const { return used_bytes_; }
+  size_t peak() const { return peak_; }
+
+  void* alloc(size_t bytes) {
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    if (bytes == 0) bytes = kAlign;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, rem = it->second - bytes;
+      free_.erase(it);
+      if (rem) free_[off + bytes] = rem;
+      return take(off, bytes);
+    }
+    if (bytes > cap_ - top_)
+      throw Error(IBMG_ERR_WORKSPACE, "workspace too small: " + std::to_string(top_ + bytes) +
+                                          " bytes needed at this point, " + std::to_string(cap_) + " given");
+    const size_t off = top_;
+    top_ += bytes;
+    if (top_ > peak_) peak_ = top_;
+    return take(off, bytes);
+  }
+
+  void release(void* p) {
+    if (!p) return;
+    size_t off = (size_t)(static_cast<char*>(p) - origin());
+    auto it = used_.find(off);
+    if (it == used_.end()) return;
+    size_t sz = it->second;
+    used_.erase(it);
+    used_bytes_ -= sz;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + sz) {
+      sz += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        sz += pv->second;
+        free_.erase(pv);
+      }
+    }
+    if (off + sz == top_) top_ = off;
+    else free_[off] = sz;
+  }
+
+ private:
+  // the virtual region of a sizing arena starts at a fixed non-null address
+  char* origin() const { return base_ ? base_ : reinterpret_cast<char*>((uintptr_t)1 << 40); }
+  void* take(size_t off, size_t bytes) {
+    used_[off] = bytes;
+    used_bytes_ += bytes;
+    return origin() + off;
+  }
+  char* base_;
+  size_t cap_;
+  size_t top_ = 0, peak_ = 0, used_bytes_ = 0;
+  std::map<size_t, size_t> free_, used_;   // offset -> size
+};
+
+// The arena the current ABI call allocates from (set per call by the entry
+// points; a DBuf remembers its arena for the release).
+inline Arena*& current_arena() {
+  static thread_local Arena* a = nullptr;
+  return a;
+}
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(current_arena()) { current_arena() = a; }
+  ~ArenaScope() { current_arena() = prev; }
+};
+
+// Owning device buffer (a block of the current arena).
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  Arena* a = nullptr;
   DBuf() = default;
   explicit DBuf(size_t count) { alloc(count); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), a(o.a) {
+    o.p = nullptr;
+    o.n = 0;
+    o.a = nullptr;
+  }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      a = o.a;
+      o.p = nullptr;
+      o.n = 0;
+      o.a = nullptr;
+    }
     return *this;
   }
   ~DBuf() { release(); }
   void alloc(size_t count) {
     release();
+    if (!count) return;
+    Arena* ar = current_arena();
+    if (!ar) throw Error(IBMG_ERR_STATE, "device buffer requested outside a handle's workspace");
+    p = static_cast<T*>(ar->alloc(count * sizeof(T)));
     n = count;
-    if (count) IBMG_HIP(hipMalloc(&p, count * sizeof(T)));
+    a = ar;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && a) a->release(p);
     p = nullptr;
     n = 0;
+    a = nullptr;
   }
   void upload(const T* h, size_t count, hipStream_t s) {
     if (count > n) alloc(count);
@@ -192,6 +322,12 @@ template <typename Ts, typename Td>
 void launch_cast(const Ts* a, Td* b, size_t n, hipStream_t s);
 template <typename T>
 void launch_fill(T* a, T v, size_t n, hipStream_t s);
+// y += x
+template <typename T>
+void launch_axpy(T* y, const T* x, size_t n, hipStream_t s);
+// *flag = 1 if a[0..n) holds NaN or Inf (flag is left alone otherwise)
+template <typename T>
+void launch_count_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
 
 // Krylov helpers (T = vector type, reductions in double)
 template <typename T>
@@ -280,8 +416,16 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
 // dinv: count x 64 x 64 doubles of workspace.
 void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv, hipStream_t s);
 constexpr int kGjNb = 64;  // block width of the batched inversion
+// full: every row of the inverse (g.nown = nloc, the summed combination)
 template <typename T>
-void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s);
+void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s, bool full = false);
+// Summed additive Schwarz (IBMG_COMBINE_SUM): every box's whole local
+// solution L_k^{-1} R_k r into Y (box id-major, g.nch chunks of 64 rows; inv
+// holds full inverses, box_inv[box id] the inverse of each box), then every
+// unknown z = the sum of its entries over the boxes whose index set holds it
+// (boxes in a fixed order per unknown).
+template <typename T>
+void launch_asm_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* box_inv, T* Y, hipStream_t s);
 // parts: bit 0 = IB boxes (k_ras_ib), bit 1 = interior boxes
 // (k_ras_interior); the smoother launches both, and one k_ras_sum adds the
 // slices of whichever was split.

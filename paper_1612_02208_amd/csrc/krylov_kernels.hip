@@ -224,7 +224,7 @@ void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
                        int nblk_in) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_upd_dots<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
+  IBMG_KLAUNCH((k_upd_dots<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
                      nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout);
   IBMG_LAUNCH_CHECK();
 }
@@ -234,7 +234,7 @@ void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
                        int nblk_in) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_upd_norm<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
+  IBMG_KLAUNCH((k_upd_norm<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
                      nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout);
   IBMG_LAUNCH_CHECK();
 }
@@ -243,7 +243,7 @@ template <typename T>
 void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const double* pin, int nblk,
                         size_t pstride, double* hout, size_t hstride, hipStream_t s) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_scale_red<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, t, v, sg, pin,
+  IBMG_KLAUNCH((k_scale_red<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, t, v, sg, pin,
                      nblk, pstride, hout, hstride);
   IBMG_LAUNCH_CHECK();
 }
@@ -253,7 +253,7 @@ void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int ns
                          const double* H, int ldh, size_t hstride, const double* beta, double* yout,
                          size_t sstride, hipStream_t s, bool assign) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
+  IBMG_KLAUNCH((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
                      sg, H, ldh, hstride, beta, yout, sstride, assign);
   IBMG_LAUNCH_CHECK();
 }

@@ -151,22 +151,22 @@ void launch_gs_sweep(T* x, const T* b, const int* cptr_dev, const std::vector<in
     const int cnt = cptr[col + 1] - cptr[col];
     if (!cnt) return;
     if (!mhat && col < (int)long_rows.size() && long_rows[col]) {
-      hipLaunchKernelGGL((k_gs_colour_g<T>), dim3(cdiv((size_t)cnt * kGsGroup, 256)), dim3(256), 0, s, x, b,
+      IBMG_KLAUNCH((k_gs_colour_g<T>), dim3(cdiv((size_t)cnt * kGsGroup, 256)), dim3(256), 0, s, x, b,
                          rows + cptr[col], cnt, N, c, tu, tv, diag);
     } else if (mhat)
-      hipLaunchKernelGGL((k_gs_colour<T, true>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
+      IBMG_KLAUNCH((k_gs_colour<T, true>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
                          cnt, N, c, tu, tv, diag, dinv, ih2);
     else
-      hipLaunchKernelGGL((k_gs_colour<T, false>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
+      IBMG_KLAUNCH((k_gs_colour<T, false>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
                          cnt, N, c, tu, tv, diag, dinv, ih2);
     IBMG_LAUNCH_CHECK();
   };
   auto band = [&](int first, int last, int step) {
     if (mhat)
-      hipLaunchKernelGGL((k_gs_band_p<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N,
+      IBMG_KLAUNCH((k_gs_band_p<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N,
                          diag, dinv, ih2);
     else
-      hipLaunchKernelGGL((k_gs_band<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N, c,
+      IBMG_KLAUNCH((k_gs_band<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N, c,
                          tu, tv, diag);
     IBMG_LAUNCH_CHECK();
   };
@@ -279,50 +279,50 @@ __global__ void k_weyl(T* x, size_t n) {
 
 template <typename T>
 void launch_aib_apply(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s) {
-  hipLaunchKernelGGL((k_aib_apply<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, x, y, N, c, tu, tv);
+  IBMG_KLAUNCH((k_aib_apply<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, x, y, N, c, tu, tv);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_grad(const T* p, T* f, int N, T gi, hipStream_t s) {
-  hipLaunchKernelGGL((k_grad<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, p, f, N, gi);
+  IBMG_KLAUNCH((k_grad<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, p, f, N, gi);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_div_comb(const T* u, const T* y, T* out, int N, T gi, T a, T b, hipStream_t s) {
-  hipLaunchKernelGGL((k_div_comb<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, u, y, out, N, gi, a, b);
+  IBMG_KLAUNCH((k_div_comb<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, u, y, out, N, gi, a, b);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_axpby(size_t n, T a, const T* x, T b, const T* y, T* out, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_axpby<T>), dim3(g), dim3(256), 0, s, n, a, x, b, y, out);
+  IBMG_KLAUNCH((k_axpby<T>), dim3(g), dim3(256), 0, s, n, a, x, b, y, out);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_cheb_init(size_t n, T theta_inv, const T* sv, T* d, T* x, const T* r, T* rc, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_cheb_init<T>), dim3(g), dim3(256), 0, s, n, theta_inv, sv, d, x, r, rc);
+  IBMG_KLAUNCH((k_cheb_init<T>), dim3(g), dim3(256), 0, s, n, theta_inv, sv, d, x, r, rc);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_cheb_step(size_t n, T c1, T c2, const T* sv, T* d, T* x, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_cheb_step<T>), dim3(g), dim3(256), 0, s, n, c1, c2, sv, d, x);
+  IBMG_KLAUNCH((k_cheb_step<T>), dim3(g), dim3(256), 0, s, n, c1, c2, sv, d, x);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_aib_sub(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s) {
-  hipLaunchKernelGGL((k_aib_sub<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, x, y, N, c, tu, tv);
+  IBMG_KLAUNCH((k_aib_sub<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, x, y, N, c, tu, tv);
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_weyl(T* x, size_t n, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_weyl<T>), dim3(g), dim3(256), 0, s, x, n);
+  IBMG_KLAUNCH((k_weyl<T>), dim3(g), dim3(256), 0, s, x, n);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -372,10 +372,10 @@ __global__ void k_sc_cell_diag(int N, const T* __restrict__ dinv, T ih2, T* mdia
 template <typename T>
 void launch_sc_diag(int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, T ih2, T* diag, T* dinv, T* mdiag,
                     hipStream_t s) {
-  hipLaunchKernelGGL((k_sc_face_diag<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, N, c, tu, tv,
+  IBMG_KLAUNCH((k_sc_face_diag<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, N, c, tu, tv,
                      diag, dinv);
   IBMG_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_sc_cell_diag<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, N, dinv, ih2, mdiag);
+  IBMG_KLAUNCH((k_sc_cell_diag<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, N, dinv, ih2, mdiag);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -396,7 +396,7 @@ template <typename T>
 void launch_sub_mean(T* x, size_t n, const double* partial, int nblk, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 1024) g = 1024;
-  hipLaunchKernelGGL((k_sub_mean<T>), dim3(g), dim3(256), 0, s, x, n, partial, nblk);
+  IBMG_KLAUNCH((k_sub_mean<T>), dim3(g), dim3(256), 0, s, x, n, partial, nblk);
   IBMG_LAUNCH_CHECK();
 }
 

@@ -45,6 +45,11 @@ void validate_desc(const ibmg_desc& d) {
   require(d.smoother == IBMG_RAS || d.smoother == IBMG_SC || d.smoother == IBMG_RMS, "unknown smoother");
   require(d.nu1 >= 1 && d.nu1 <= kMaxNu && d.nu2 >= 1 && d.nu2 <= kMaxNu, "nu1/nu2 must lie in [1, 8]");
   require(d.precision == IBMG_FP64 || d.precision == IBMG_FP32_SMOOTHER, "unknown precision");
+  require(d.combine == IBMG_COMBINE_RESTRICTED || d.combine == IBMG_COMBINE_SUM, "unknown combine");
+  require(d.combine == IBMG_COMBINE_RESTRICTED || d.smoother == IBMG_RAS,
+          "the summed combination applies to the additive Schwarz smoother only");
+  require(d.sweep_kind == IBMG_SWEEP_FGMRES || d.sweep_kind == IBMG_SWEEP_RICHARDSON, "unknown sweep_kind");
+  require(d.max_restart >= 0 && d.max_restart <= kMaxRestart, "max_restart must lie in [0, 64]");
   if (d.smoother == IBMG_SC) require(d.cheb_its >= 1 && d.cheb_its <= 8, "cheb_its must lie in [1, 8]");
   if (d.smoother == IBMG_RAS || d.smoother == IBMG_RMS) {
     require(d.box >= 1 && d.overlap >= 0, "box must be >= 1 and overlap >= 0");

@@ -48,6 +48,8 @@ struct SolverBase {
   virtual void step_rhs(const double* w, double* rhs, hipStream_t s) = 0;
   virtual int time_step(double* w, const ibmg_solve_opts& o, ibmg_solve_info* info, hipStream_t s) = 0;
   virtual void positions(double* X) const = 0;
+  // false after a rebuild failed part-way (the handle is then unusable)
+  virtual bool valid() const { return true; }
 };
 
 // Many independent systems solved together (batched form): one launch per
@@ -91,5 +93,6 @@ double time_launches(F&& fn, int reps, hipStream_t s) {
 SolverBase* make_solver(const ibmg_desc& d, hipStream_t s);
 BatchBase* make_batch(int nsys, const ibmg_desc* d, hipStream_t s);
 void validate_desc(const ibmg_desc& d);
+void validate_batch(int nsys, const ibmg_desc* d);
 
 }  // namespace ibmg

@@ -89,6 +89,12 @@ struct Level {
   std::vector<int> box_colour, ib_off, int_off;
   int int_tb = 32;        // interior tile width, picked by timing at set-up
   DBuf<T> rr;             // residual between colours
+  // summed combination (IBMG_COMBINE_SUM): g.nown = nloc, every row of every
+  // box inverse is kept; box_inv maps a box id to its inverse (IB boxes their
+  // own, interior boxes the shared one), Y holds every box's local solution
+  bool sum_mode = false;
+  DBuf<int> d_box_inv;
+  DBuf<T> Y;
   // work vectors
   DBuf<T> w, b, r, t, V, Z, F;
   DBuf<double> H, scal, part;
@@ -124,11 +130,91 @@ class Solver final : public SolverBase {
     nu_ = std::max(d.nu1, d.nu2);
     sizes_ = level_sizes(d.N, d.coarse_N);
     L_ = (int)sizes_.size() - 1;
+    outer_cap_ = d.max_restart > 0 ? d.max_restart : 30;
+    alloc_fixed(s);
+    build_all(s);
+  }
+
+  // Buffers whose sizes do not depend on the structure's positions, placed
+  // first in the workspace: a rebuild at moved positions releases everything
+  // above them and lays it out again in the same order.  A member of a batch
+  // keeps only its hierarchy (the batch has its own work and outer vectors).
+  void alloc_fixed(hipStream_t s) {
+    (void)s;
+    if (defer_coarse_) return;
+    const size_t n = 3 * (size_t)d_.N * d_.N, m2 = 2 * (size_t)std::max(M_, 1);
+    const int R = outer_cap_;
+    Vo_.alloc((size_t)(R + 1) * n);
+    Zo_.alloc((size_t)R * n);
+    Ho_.alloc((size_t)(R + 1) * R);
+    cs_.alloc(R + 1);
+    sn_.alloc(R + 1);
+    g_.alloc(R + 2);
+    y_.alloc(R + 1);
+    osc_.alloc(256);
+    opart_.alloc(2 * kOuterPartStride);
+    ofold_.alloc(2 * 72);
+    bp_.alloc(n);
+    rr_.alloc(n);
+    vin_.alloc(n);
+    vout_.alloc(n);
+    Fd_.alloc(2 * m2);   // forces [2][M] then J u [2][M]
+    Uw_.alloc(m2);
+    Ul_.alloc(m2);
+    Fs_.alloc(m2);
+    fs_.alloc(2 * (size_t)d_.N * d_.N);
+    rhs_.alloc(n);
+    if (!pinned_) IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
+  }
+
+  // Every position-dependent part of the set-up, in workspace order.
+  void build_all(hipStream_t s) {
     build_structure(s);
+    if (!defer_coarse_) alloc_work(s);
     build_numeric(s);
-    alloc_work(s);
-    tune_interior(s);
+    check_breakdown(s);
+    if (!defer_coarse_) tune_interior(s);
     IBMG_HIP(hipStreamSynchronize(s));
+  }
+
+  // Release everything alloc_fixed did not place (the whole hierarchy, the
+  // structure's device arrays, the coarsest inverse and the set-up's slice
+  // buffer), leaving the workspace as it was right after alloc_fixed.
+  void release_dependent() {
+    levels_.clear();
+    for (DBuf<int>* b : {&d_adj_ptr_, &d_adj_nbr_, &d_ends_, &d_order_}) b->release();
+    for (DBuf<double>* b : {&d_adj_k_, &d_X_, &d_adj_k2_, &d_adj_kap_, &d_adj_rest_, &d_gblocks_, &inv0_, &tpart_,
+                            &aug0_})
+      b->release();
+    d_adj_kf_.release();
+    d_adj_k2f_.release();
+  }
+
+  // A set-up factorisation that broke down leaves non-finite entries in its
+  // inverse (a zero pivot divides by zero); so does a non-finite operator.
+  // The coarsest inverse and every level's box inverses are scanned once,
+  // and the SC Chebyshev bounds must be finite and positive.
+  void check_breakdown(hipStream_t s, bool coarse_only = false) {
+    DBuf<int> flag(1);
+    if (dry_run()) return;
+    int bad = 0;
+    auto scan = [&](const auto* a, size_t n, const char* what) {
+      if (!n) return;
+      launch_fill<int>(flag.p, 0, 1, s);
+      launch_count_nonfinite(a, n, flag.p, s);
+      IBMG_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      IBMG_HIP(hipStreamSynchronize(s));
+      if (bad) throw Error(IBMG_ERR_BREAKDOWN, std::string(what) + " has non-finite entries (singular or non-finite matrix)");
+    };
+    if (inv0_.n) scan(inv0_.p, inv0_.n, "the coarsest inverse");
+    for (int l = 1; l <= L_ && !coarse_only; ++l) {
+      Level<T>& lev = levels_[l];
+      if (lev.inv.n) scan(lev.inv.p, lev.inv.n, ("the box inverses of level " + std::to_string(l)).c_str());
+      if (lev.sc)
+        if (!(std::isfinite(lev.sc->lamA) && lev.sc->lamA > 0.0 && std::isfinite(lev.sc->lamM) && lev.sc->lamM > 0.0))
+          throw Error(IBMG_ERR_BREAKDOWN, "Schur-complement Chebyshev bound of level " + std::to_string(l) +
+                                              " is not finite and positive");
+    }
   }
 
   ~Solver() override {
@@ -443,6 +529,12 @@ class Solver final : public SolverBase {
     lev.uniq = lev.ib_list;
     if (!lev.int_list.empty()) lev.uniq.push_back(lev.int_list.front());
     lev.n_unique = (int)lev.uniq.size();
+    if (d_.combine == IBMG_COMBINE_SUM) {
+      // every row of every box inverse: the whole local solution is summed
+      lev.sum_mode = true;
+      lev.g.nown = nloc;
+      lev.g.nch = (nloc + 63) / 64;
+    }
   }
 
   size_t box_stride(const Level<T>& lev) const { return (size_t)lev.g.nch * lev.g.nloc * 64; }
@@ -486,6 +578,7 @@ class Solver final : public SolverBase {
   // environment fixes the form instead (where the level supports it).
   void tune_interior(hipStream_t s) {
     if (d_.smoother != IBMG_RAS && d_.smoother != IBMG_RMS) return;
+    if (dry_run() || d_.combine == IBMG_COMBINE_SUM) return;
     int forced = 0;
     if (const char* e = std::getenv("IBMG_INTERIOR_FORM")) forced = std::atoi(e);
     for (int l = 1; l <= L_; ++l) {
@@ -731,6 +824,7 @@ class Solver final : public SolverBase {
     constexpr int steps = 10;
     DBuf<T> V((size_t)(steps + 1) * n);
     DBuf<double> part(2 * kPartStride), hd(64);
+    if (dry_run()) return 1.0;
     const int nblk = dots_blocks(n, 256);
     std::vector<double> H((steps + 1) * steps, 0.0), h(steps + 1), h2(steps + 1);
     auto norm_of = [&](const T* x) {
@@ -843,6 +937,14 @@ class Solver final : public SolverBase {
     lev.d_ib.upload(lev.ib_list, s);
     lev.d_int.upload(lev.int_list, s);
     lev.d_loc.upload(lev.loc_tab, s);
+    if (lev.sum_mode) {
+      std::vector<int> bi((size_t)g.npd * g.npd, lev.n_ib);
+      for (int i = 0; i < lev.n_ib; ++i) bi[lev.ib_list[i]] = i;
+      lev.d_box_inv.upload(bi, s);
+      lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
+      lev.Y.alloc((size_t)g.npd * g.npd * g.nch * 64);
+      return;
+    }
     {
       // column slices of the IB boxes followed by the reduction slices of
       // the interior product: the whole lists (additive sweep, tuning,
@@ -863,8 +965,8 @@ class Solver final : public SolverBase {
   // The unique box inverses of every Schwarz level: assembled per level,
   // inverted in batches that mix levels whose boxes have the same number of
   // unknowns (one run of block sweeps serves them all), owned rows extracted
-  // per level.  Batches hold as many matrices as half the free device memory
-  // (at most 16 GiB) allows, and at most 512.
+  // per level.  Batches hold at most 512 matrices and 8 GiB of them with
+  // their sweep workspace (a set-up temporary of the handle's workspace).
   void build_boxes(hipStream_t s) {
     std::map<int, std::vector<std::pair<int, int>>> groups;   // nloc -> (level, unique index)
     std::vector<DBuf<int>> ids(L_ + 1);
@@ -874,9 +976,7 @@ class Solver final : public SolverBase {
       ids[l].upload(lev.uniq, s);
       for (int u = 0; u < lev.n_unique; ++u) groups[lev.g.nloc].push_back({l, u});
     }
-    size_t free_b = 0, total_b = 0;
-    IBMG_HIP(hipMemGetInfo(&free_b, &total_b));
-    const size_t budget = std::max<size_t>((size_t)1 << 30, std::min<size_t>((size_t)16 << 30, free_b / 2));
+    const size_t budget = (size_t)8 << 30;
     for (auto& grp : groups) {
       const int n = grp.first;
       const auto& items = grp.second;
@@ -905,7 +1005,8 @@ class Solver final : public SolverBase {
         launch_gj_invert(mats.p, n, cnt, work.p, dinv.p, s);
         for_runs([&](int l, int u0, int count, size_t slot) {
           Level<T>& lev = levels_[l];
-          launch_extract_owned<T>(mats.p + slot * n * n, count, lev.g, lev.inv.p + (size_t)u0 * box_stride(lev), s);
+          launch_extract_owned<T>(mats.p + slot * n * n, count, lev.g, lev.inv.p + (size_t)u0 * box_stride(lev), s,
+                                  lev.sum_mode);
         });
       }
       IBMG_HIP(hipStreamSynchronize(s));
@@ -935,10 +1036,6 @@ class Solver final : public SolverBase {
       lev.scal.alloc(64);
       lev.part.alloc(2 * part_stride(lev));
     }
-    Fd_.alloc(4 * (size_t)std::max(M_, 1));   // forces [2][M] then J u [2][M]
-    Uw_.alloc(2 * (size_t)std::max(M_, 1));
-    Ul_.alloc(2 * (size_t)std::max(M_, 1));
-    if (!pinned_) IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
   }
 
   // --------------------------------------------------------------- views
@@ -1029,6 +1126,10 @@ class Solver final : public SolverBase {
       lev.sc->apply(v, z, s);
       return;
     }
+    if (lev.sum_mode) {
+      launch_asm_apply<T>(v, z, lev.g, lev.inv.p, lev.d_box_inv.p, lev.Y.p, s);
+      return;
+    }
     if (d_.smoother == IBMG_RMS) {
       // Alg. 3 colour by colour from z = 0: each colour's boxes add their
       // restricted local solutions of the residual of the current z
@@ -1056,6 +1157,20 @@ class Solver final : public SolverBase {
   void smooth_t(int l, T* w, const T* b, int nu, bool w_zero, hipStream_t s, int b_nblk = 0) {
     Level<T>& lev = levels_[l];
     const size_t n = 3 * (size_t)lev.N * lev.N;
+    if (d_.sweep_kind == IBMG_SWEEP_RICHARDSON) {
+      // nu undamped Richardson steps w <- w + B (b - L w); from w = 0 the
+      // first step is w = B b
+      for (int k = 0; k < nu; ++k) {
+        if (k == 0 && w_zero) {
+          basic_smoother(l, b, w, s);
+          continue;
+        }
+        op<T>(l, w, lev.r.p, b, false, lev.F.p, s);
+        basic_smoother(l, lev.r.p, lev.t.p, s);
+        launch_axpy<T>(w, lev.t.p, n, s);
+      }
+      return;
+    }
     const int nblk = dots_blocks(n, 1024);  // at most nu + 1 vectors
     const int ldh = kMaxNu + 1;
     const T* r0;
@@ -1213,9 +1328,6 @@ class Solver final : public SolverBase {
   // is captured once into a HIP graph reading vin_ and writing vout_, then
   // replayed; the graph holds kernel nodes only.
   void build_graph() {
-    const size_t n = 3 * (size_t)d_.N * d_.N;
-    vin_.alloc(n);
-    vout_.alloc(n);
     if (!gstream_) IBMG_HIP(hipStreamCreateWithFlags(&gstream_, hipStreamNonBlocking));
     IBMG_HIP(hipStreamBeginCapture(gstream_, hipStreamCaptureModeThreadLocal));
     try {
@@ -1255,24 +1367,6 @@ class Solver final : public SolverBase {
     return pinned_[0];
   }
 
-  void ensure_outer(int restart) {
-    const size_t n = 3 * (size_t)d_.N * d_.N;
-    if (restart <= outer_cap_) return;
-    Vo_.alloc((size_t)(restart + 1) * n);
-    Zo_.alloc((size_t)restart * n);
-    Ho_.alloc((size_t)(restart + 1) * restart);
-    cs_.alloc(restart + 1);
-    sn_.alloc(restart + 1);
-    g_.alloc(restart + 2);
-    y_.alloc(restart + 1);
-    osc_.alloc(256);
-    opart_.alloc(2 * kOuterPartStride);
-    ofold_.alloc(2 * 72);
-    bp_.alloc(n);
-    rr_.alloc(n);
-    outer_cap_ = restart;
-  }
-
   void project(double* a, hipStream_t s) {
     Level<T>& top = levels_[L_];
     launch_block_sums<double>(a, top.N, opart_.p, 64, s);
@@ -1290,10 +1384,10 @@ class Solver final : public SolverBase {
   int fgmres(const double* b, double* x, const ibmg_solve_opts& o, ibmg_solve_info* info,
              hipStream_t s) override {
     const auto t0 = std::chrono::steady_clock::now();
-    require(o.restart >= 1 && o.restart <= kMaxRestart, "restart must lie in [1, 64]");
+    require(o.restart >= 1 && o.restart <= outer_cap_,
+            "restart must lie in [1, max_restart = " + std::to_string(outer_cap_) + "]");
     require(o.max_it >= 1, "max_it must be >= 1");
     require(std::isfinite(o.rtol) && o.rtol > 0.0, "rtol must be finite and > 0");
-    ensure_outer(o.restart);
     // the adjoint system uses the transposed operator path; L_IB is
     // symmetric, so the same V-cycle preconditions it
     const bool trans = o.transpose != 0;
@@ -1399,9 +1493,7 @@ class Solver final : public SolverBase {
     for (int e = 0; e < E_; ++e)
       require(std::isfinite(kappa[e]) && kappa[e] >= 0.0, "kappa must be finite and >= 0");
     kappa_.assign(kappa, kappa + E_);
-    drop_graph();  // the box inverses are reallocated
-    build_numeric(s);
-    IBMG_HIP(hipStreamSynchronize(s));
+    rebuild(s);
   }
 
   // ------------------------------------------- semi-implicit time step
@@ -1411,8 +1503,6 @@ class Solver final : public SolverBase {
     Level<T>& lev = levels_[L_];
     const double h = 1.0 / lev.N;
     const size_t m2 = 2 * (size_t)std::max(M_, 1);
-    if (Fs_.n < m2) Fs_.alloc(m2);
-    if (fs_.n < 2 * (size_t)lev.N * lev.N) fs_.alloc(2 * (size_t)lev.N * lev.N);
     launch_fill<double>(Fs_.p, 0.0, m2, s);
     launch_fibre_force(d_X_.p, sview<double>(), tangent_ ? d_adj_kap_.p : d_adj_k_.p,
                        tangent_ ? d_adj_rest_.p : nullptr, Fs_.p, s);
@@ -1424,8 +1514,7 @@ class Solver final : public SolverBase {
   // (Eq. imp-X-new, wrapped into [0, 1)) and rebuild every level at X^{n+1}.
   int time_step(double* w, const ibmg_solve_opts& o, ibmg_solve_info* info, hipStream_t s) override {
     Level<T>& lev = levels_[L_];
-    const size_t n = 3 * (size_t)lev.N * lev.N, nn = (size_t)lev.N * lev.N;
-    if (rhs_.n < n) rhs_.alloc(n);
+    const size_t nn = (size_t)lev.N * lev.N;
     step_rhs(w, rhs_.p, s);
     const int st = fgmres(rhs_.p, w, o, info, s);
     launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw_.p, s);
@@ -1439,16 +1528,19 @@ class Solver final : public SolverBase {
     return st;
   }
 
-  // every level rebuilt for the current positions X_ (host copy)
+  // Every level rebuilt for the current positions X_ (host copy) and
+  // stiffnesses, laid out again above the fixed buffers.  If the rebuild
+  // fails part-way (a workspace too small for the new layout), the handle
+  // stays unusable.
   void rebuild(hipStream_t s) {
     drop_graph();
-    levels_.clear();
-    build_structure(s);
-    build_numeric(s);
-    alloc_work(s);
-    tune_interior(s);
-    IBMG_HIP(hipStreamSynchronize(s));
+    valid_ = false;
+    release_dependent();
+    build_all(s);
+    valid_ = true;
   }
+
+  bool valid() const override { return valid_; }
 
   void positions(double* X) const override {
     std::copy(X_.begin(), X_.end(), X);
@@ -1484,6 +1576,7 @@ class Solver final : public SolverBase {
     const BoxGeom& g = lev.g;
     if (kernel == IBMG_KERNEL_RAS_IB || kernel == IBMG_KERNEL_RAS_INTERIOR) {
       require(level >= 1 && !lev.sc, "Schwarz kernels need a Schwarz smoother level >= 1");
+      require(!lev.sum_mode, "the restricted Schwarz kernels do not run with the summed combination");
       const int n_int = (int)lev.int_list.size();
       if (kernel == IBMG_KERNEL_RAS_IB) {
         require(lev.n_ib > 0, "the level has no IB boxes");
@@ -1522,7 +1615,6 @@ class Solver final : public SolverBase {
       require(level == L_, "spreading and interpolation run on the finest level");
       require(M_ > 0, "the structure has no points");
       const size_t nn = (size_t)lev.N * lev.N;
-      if (fs_.n < 2 * nn) fs_.alloc(2 * nn);
       launch_fill<double>(fs_.p, 1.0, 2 * nn, s);
       launch_fill<double>(Fd_.p, 1.0, 2 * (size_t)M_, s);
       size_t ents = 0, touched = 0;
@@ -1596,7 +1688,8 @@ class Solver final : public SolverBase {
   hipGraphExec_t gexec_ = nullptr;
   DBuf<double> vin_, vout_;
   DBuf<double> tpart_;   // slice sums of the IB-row values on coarse levels
-  bool defer_coarse_ = false;
+  bool defer_coarse_ = false;   // a member of a batch: the batch inverts the coarsest system
+  bool valid_ = true;
   int nn0_ = 0;          // size of the bordered coarsest system
   DBuf<double> aug0_;    // its assembled [A | I] while the inversion is deferred
 

@@ -1,9 +1,11 @@
 """Python binding of libibmg: one ``StokesIB`` object per Stokes-IB system,
 or one ``StokesIBBatch`` for many independent systems solved together.
 
-Only argument marshalling happens here: torch supplies device memory and the
-current HIP stream, every computation runs in the library's kernels.  Vectors
-are float64 CUDA tensors laid out [u | v | p] (see include/ibmg.h).
+Only argument marshalling happens here: torch supplies every byte of device
+memory (each handle's workspace is one torch tensor, sized by the library's
+sizing call) and the current HIP stream; every computation runs in the
+library's kernels.  Vectors are float64 CUDA tensors laid out [u | v | p]
+(see include/ibmg.h).
 """
 import ctypes
 
@@ -12,8 +14,13 @@ import torch
 
 from . import _lib
 
-_STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_HIP", -5: "ERR_NONFINITE",
-           -6: "ERR_STATE"}
+_STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_WORKSPACE",
+           -4: "ERR_BREAKDOWN", -5: "ERR_NONFINITE", -6: "ERR_STATE"}
+
+# Extra workspace beyond the set-up's exact size: a rebuild at moved
+# positions (time steps) may touch more boxes than the first set-up.
+WORKSPACE_HEADROOM = 0.125
+WORKSPACE_EXTRA = 64 << 20
 
 
 class IbmgError(RuntimeError):
@@ -62,6 +69,11 @@ def _make_desc(system, precision):
     d.precision = {"fp64": _lib.FP64, "fp32": _lib.FP32_SMOOTHER}[precision]
     d.spring_model = {"linear": _lib.SPRING_LINEAR, "tangent": _lib.SPRING_TANGENT}[
         getattr(system, "spring_model", "linear")]
+    d.combine = {"restricted": _lib.COMBINE_RESTRICTED, "sum": _lib.COMBINE_SUM}[
+        getattr(system, "combine", "restricted")]
+    d.sweep_kind = {"fgmres": _lib.SWEEP_FGMRES, "richardson": _lib.SWEEP_RICHARDSON}[
+        getattr(system, "sweep", "fgmres")]
+    d.max_restart = int(getattr(system, "max_restart", 30))
     rest = getattr(system, "rest", None)
     if rest is not None:
         rest = np.ascontiguousarray(rest, dtype=np.float64)
@@ -75,6 +87,16 @@ def _ptr_array(ts):
     return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 
 
+def _workspace(lib, nbytes, headroom):
+    """The handle's device workspace: one uint8 torch tensor (torch's caching
+    allocator aligns it to at least 256 bytes)."""
+    total = int(nbytes * (1.0 + headroom)) + (WORKSPACE_EXTRA if headroom > 0 else 0)
+    ws = torch.empty(max(total, 256), dtype=torch.uint8, device="cuda")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace tensor is not 256-byte aligned")
+    return ws
+
+
 class StokesIB:
     """Multigrid-preconditioned solver for one periodic Stokes-IB system.
 
@@ -82,7 +104,7 @@ class StokesIB:
     X [M,2], springs [E,2], kappa [E], smoother ("ras"|"sc"), box, overlap,
     nu1, nu2, cheb_its (e.g. ``workloads.Workload``)."""
 
-    def __init__(self, system, precision="fp64"):
+    def __init__(self, system, precision="fp64", workspace_headroom=WORKSPACE_HEADROOM):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("StokesIB needs a HIP device")
@@ -94,8 +116,15 @@ class StokesIB:
         self.rho = d.rho
         self.precision = precision
         self.desc = d
+        nb = ctypes.c_size_t()
+        st = self.lib.ibmg_workspace_bytes(ctypes.byref(d), ctypes.byref(nb))
+        if st != 0:
+            raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
+        self.workspace_bytes = nb.value
+        self.workspace = _workspace(self.lib, nb.value, workspace_headroom)
         h = ctypes.c_void_p()
-        st = self.lib.ibmg_create(ctypes.byref(d), _stream(), ctypes.byref(h))
+        st = self.lib.ibmg_create(ctypes.byref(d), _ptr(self.workspace), self.workspace.numel(), _stream(),
+                                  ctypes.byref(h))
         if st != 0:
             raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
         self.h = h
@@ -117,12 +146,19 @@ class StokesIB:
         if getattr(self, "h", None):
             self.lib.ibmg_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+    def workspace_used(self):
+        """(bytes in use now, most bytes ever in use) of the handle's workspace."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.lib.ibmg_workspace_used(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def n(self, level=-1):
         N = self.level_sizes[level]
@@ -298,7 +334,7 @@ class StokesIBBatch:
     a list of system descriptions as for ``StokesIB``; they may differ in N,
     structure and stiffness but must share the fluid and box parameters."""
 
-    def __init__(self, systems, precision="fp32"):
+    def __init__(self, systems, precision="fp32", workspace_headroom=0.0):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("StokesIBBatch needs a HIP device")
@@ -311,8 +347,15 @@ class StokesIBBatch:
         self.nsys = len(systems)
         self.sizes = [int(sy.N) for sy in systems]
         self.precision = precision
+        nb = ctypes.c_size_t()
+        st = self.lib.ibmg_batch_workspace_bytes(self.nsys, descs, ctypes.byref(nb))
+        if st != 0:
+            raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
+        self.workspace_bytes = nb.value
+        self.workspace = _workspace(self.lib, nb.value, workspace_headroom)
         h = ctypes.c_void_p()
-        st = self.lib.ibmg_batch_create(self.nsys, descs, _stream(), ctypes.byref(h))
+        st = self.lib.ibmg_batch_create(self.nsys, descs, _ptr(self.workspace), self.workspace.numel(), _stream(),
+                                        ctypes.byref(h))
         if st != 0:
             raise IbmgError(st, self.lib.ibmg_last_error(None).decode())
         self.h = h
@@ -327,6 +370,7 @@ class StokesIBBatch:
         if getattr(self, "h", None):
             self.lib.ibmg_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -335,6 +379,7 @@ class StokesIBBatch:
             pass
 
     kernel_time = StokesIB.kernel_time
+    workspace_used = StokesIB.workspace_used
 
     def _vecs(self, ts, name):
         if len(ts) != self.nsys:

@@ -94,7 +94,19 @@ def _cases():
     c13 = W.Workload("random_48_tangent_rms", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, c3.kappa, box=6, overlap=1,
                      smoother="rms", spring_model="tangent",
                      rest=lengths(Xr, Sr) * rng.uniform(0.3, 0.9, len(Sr)))
-    return [c1, c2, c3, c4, c5, c6, c7, c8, c9, c10, c11, c12, c13]
+    # smoother options: the summed additive Schwarz combination (plain
+    # R_k^T) and undamped Richardson sweeps (Sec. 6) with the restricted
+    # additive, multiplicative and SC smoothers
+    c14 = W.Workload("annulus_64_sum", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4), combine="sum")
+    c15 = W.plain_32(sweep="richardson")
+    c15.name = "plain_32_richardson"
+    c16 = W.Workload("annulus_64_sc_richardson", 64, 8, 1.0, 1e-2, 5e-4, X, S, np.full(len(S), 1e4),
+                     smoother="sc", sweep="richardson")
+    c17 = W.Workload("random_48_rms_richardson", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, c3.kappa, box=6, overlap=1,
+                     smoother="rms", sweep="richardson")
+    c18 = W.Workload("random_48_sum_box16", 48, 6, 0.0, 0.3, 2e-2, Xr, Sr, c3.kappa, box=12, overlap=3,
+                     combine="sum")
+    return [c1, c2, c3, c4, c5, c6, c7, c8, c9, c10, c11, c12, c13, c14, c15, c16, c17, c18]
 
 
 CASES = _cases()
@@ -178,7 +190,7 @@ def test_smooth(pair):
         w = rng.uniform(-1, 1, lev.n)
         b = rng.uniform(-1, 1, lev.n)
         out = host(G.smooth(l, dev(w), dev(b), 2))
-        ref = krylov.fgmres_smooth(lambda x: lev.L @ x, P.mg.smoothers[l], w, b, 2)
+        ref = P.mg.smooth(l, w, b, 2)   # the handle's sweep kind
         assert_classes(out, ref, lc(P, l), SOLVE_TOL, f"smooth level {l}")
 
 
@@ -220,7 +232,7 @@ def test_fgmres_restarts_fixed_iterations(pair):
     hg = np.array(info["history"])
     ho = np.array(io["history"]) / np.linalg.norm(bp)
     floor = ho < 1e-11
-    np.testing.assert_allclose(hg[~floor], ho[~floor], rtol=1e-8)
+    np.testing.assert_allclose(hg[~floor], ho[~floor], rtol=1e-8, atol=1e-14)
     assert np.all(hg[floor] < 1e-11)
     assert (~floor).sum() >= 4
 
@@ -289,6 +301,10 @@ def test_single_kernel_timing_every_level(pair):
     wl, P, G = pair
     if wl.smoother == "sc":
         pytest.skip("Schur-complement smoother")
+    if wl.combine == "sum":
+        with pytest.raises(Exception):
+            G.kernel_time("ras_ib", len(P.levels) - 1, 1)
+        pytest.skip("the restricted Schwarz kernels do not run with the summed combination")
     st = G.stats()["levels"]
     for l in range(1, len(P.levels)):
         lv = st[l]
@@ -367,7 +383,7 @@ def test_interior_product_forms_agree(name, monkeypatch):
 # ---------------------------------------------------------------------------
 FP32_TOL = 1e-4
 FP32_CASES = ["plain_32", "annulus_64_box16", "random_48", "plain_32_sc", "annulus_64_rms",
-              "annulus_64_tangent"]
+              "annulus_64_tangent", "annulus_64_sum", "plain_32_richardson"]
 
 
 @pytest.fixture(scope="module", params=FP32_CASES)
@@ -399,7 +415,7 @@ def test_fp32_smooth(pair32):
         w = rng.uniform(-1, 1, lev.n)
         b = rng.uniform(-1, 1, lev.n)
         out = host(G.smooth(l, dev(w), dev(b), 2))
-        ref = krylov.fgmres_smooth(lambda x: lev.L @ x, P.mg.smoothers[l], w, b, 2)
+        ref = P.mg.smooth(l, w, b, 2)   # the handle's sweep kind
         e = assert_classes(out, ref, lc(P, l), FP32_TOL, f"fp32 smooth level {l}")
         print(f"[fp32] {wl.name} smooth level {l}: {e}")
 
