@@ -246,6 +246,19 @@ ibmg_status ibmg_fgmres_solve(ibmg_handle* h, const double* b, double* x,
 ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* lambda,
                                  double* out, ibmg_stream stream);
 
+/* ibmg_spring_gradient without the handle's workspace, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Its scratch (J w and J lambda per
+ * point) is a fixed device array inside the library, 8 MiB per GPU, held
+ * from the first call on a GPU until the process ends; it allocates nothing
+ * and calls no allocating routine.  Structures of more than 2^18 points are
+ * rejected (IBMG_ERR_ARG).  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other streams, other threads, other handles)
+ * race and must be ordered by the caller.  Same arguments and results as
+ * ibmg_spring_gradient. */
+ibmg_status ibmg_spring_gradient_static(ibmg_handle* h, const double* w, const double* lambda,
+                                        double* out, ibmg_stream stream);
+
 /* Replace the spring stiffnesses (host array [n_springs]) and rebuild every
  * level's IB operator and smoother data (tangent blocks at the current
  * positions).  Synchronises ``stream``. */

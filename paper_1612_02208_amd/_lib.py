@@ -55,7 +55,7 @@ EXPORTS = [
     "ibmg_workspace_bytes", "ibmg_create", "ibmg_workspace_used", "ibmg_destroy", "ibmg_last_error", "ibmg_levels", "ibmg_level_n",
     "ibmg_apply_A_IB", "ibmg_apply_A_IB_T", "ibmg_spread", "ibmg_interp", "ibmg_restrict",
     "ibmg_prolong_add", "ibmg_smoother_apply", "ibmg_smooth", "ibmg_coarse_solve", "ibmg_vcycle",
-    "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_set_kappa", "ibmg_stats", "ibmg_sc_info",
+    "ibmg_fgmres_solve", "ibmg_spring_gradient", "ibmg_spring_gradient_static", "ibmg_set_kappa", "ibmg_stats", "ibmg_sc_info",
     "ibmg_batch_workspace_bytes", "ibmg_batch_create", "ibmg_batch_size", "ibmg_batch_vcycle", "ibmg_batch_fgmres_solve",
     "ibmg_batch_stats", "ibmg_kernel_time", "ibmg_step_rhs", "ibmg_time_step", "ibmg_positions",
 ]
@@ -92,6 +92,7 @@ def load():
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.ibmg_fgmres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     lib.ibmg_spring_gradient.argtypes = [vp, vp, vp, vp, vp]
+    lib.ibmg_spring_gradient_static.argtypes = [vp, vp, vp, vp, vp]
     lib.ibmg_set_kappa.argtypes = [vp, _dp, vp]
     lib.ibmg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _ip]
     lib.ibmg_sc_info.argtypes = [vp, ctypes.c_int32, _dp, _ip]

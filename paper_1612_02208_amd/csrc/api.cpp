@@ -353,6 +353,19 @@ ibmg_status ibmg_spring_gradient(ibmg_handle* h, const double* w, const double* 
   });
 }
 
+ibmg_status ibmg_spring_gradient_static(ibmg_handle* h, const double* w, const double* lambda, double* out,
+                                        ibmg_stream st) {
+  return guarded(h, [&](ibmg::SolverBase* s) {
+    ibmg::require(w && lambda, "NULL vector");
+    ibmg::require(s->points() <= ibmg::kStaticGradPoints,
+                  "the structure has " + std::to_string(s->points()) + " points; the allocation-free gradient holds " +
+                      std::to_string(ibmg::kStaticGradPoints));
+    double* scratch = ibmg::static_grad_scratch();
+    s->spring_gradient_in(w, lambda, out, scratch, scratch + 2 * (size_t)ibmg::kStaticGradPoints, S(st));
+    return IBMG_OK;
+  });
+}
+
 ibmg_status ibmg_set_kappa(ibmg_handle* h, const double* kappa, ibmg_stream st) {
   return guarded(h, [&](ibmg::SolverBase* s) {
     s->set_kappa(kappa, S(st));

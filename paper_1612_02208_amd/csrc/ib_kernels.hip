@@ -10,6 +10,8 @@
 //
 // Spreading is a gather: every face walks the (point, slot) entries sorted
 // by face at set-up, so results are deterministic and use no atomics.
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace ibmg {
@@ -450,6 +452,30 @@ void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, con
   IBMG_KLAUNCH(k_spring_grad, dim3(cdiv(n_springs, 128)), dim3(128), 0, s, Uw, Ul, ends, blocks,
                      n_springs, scale, out);
   IBMG_LAUNCH_CHECK();
+}
+
+// Scratch of the allocation-free spring gradient: J w then J lambda, each
+// [kStaticGradPoints][2] doubles.  Each GPU holds its own copy for the life
+// of the process.  Host code never names the array in a launch or a copy: it
+// asks the runtime for the array's device address once per device and uses
+// that address.
+static __device__ __align__(256) double scratch[4 * (size_t)kStaticGradPoints];
+
+double* static_grad_scratch() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  int dev = 0;
+  IBMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(IBMG_ERR_STATE, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    IBMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(IBMG_ERR_HIP, "no device address for the gradient scratch");
+    ptr[dev] = static_cast<double*>(p);
+  }
+  return ptr[dev];
 }
 
 template void launch_ib_force<double>(const double*, const double*, FootView<double>,

@@ -404,6 +404,11 @@ void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s)
 // blocks: per spring (B_xx, B_xy, B_yy) of K_e / kappa_e, nullptr for B = I
 void launch_spring_grad(const double* Uw, const double* Ul, const int* ends, const double* blocks,
                         int n_springs, double scale, double* out, hipStream_t s);
+// The allocation-free gradient's scratch: a file-scope device array of
+// 4 kStaticGradPoints doubles (J w and J lambda); its device address on the
+// current device, looked up once per device.
+constexpr int kStaticGradPoints = 1 << 18;
+double* static_grad_scratch();
 
 // dense boxes and coarsest solve
 void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoef<double> c,

@@ -37,6 +37,10 @@ struct SolverBase {
   virtual int fgmres(const double* b, double* x, const ibmg_solve_opts& o, ibmg_solve_info* info,
                      hipStream_t s) = 0;
   virtual void spring_gradient(const double* w, const double* lam, double* out, hipStream_t s) = 0;
+  // the same with J w and J lambda in caller-given device scratch (2 M each)
+  virtual void spring_gradient_in(const double* w, const double* lam, double* out, double* Uw, double* Ul,
+                                  hipStream_t s) = 0;
+  virtual int points() const = 0;
   virtual void set_kappa(const double* kappa, hipStream_t s) = 0;
   virtual std::vector<int64_t> stats() const = 0;
   virtual void sc_info(int level, double* lam, int32_t* colours) const = 0;

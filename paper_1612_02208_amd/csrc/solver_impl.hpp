@@ -1480,13 +1480,20 @@ class Solver final : public SolverBase {
   }
 
   void spring_gradient(const double* w, const double* lam, double* out, hipStream_t s) override {
+    spring_gradient_in(w, lam, out, Uw_.p, Ul_.p, s);
+  }
+
+  void spring_gradient_in(const double* w, const double* lam, double* out, double* Uw, double* Ul,
+                          hipStream_t s) override {
     Level<T>& lev = levels_[L_];
     const size_t nn = (size_t)lev.N * lev.N;
     const double h = 1.0 / lev.N;
-    launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw_.p, s);
-    launch_interp<double>(lam, lam + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Ul_.p, s);
-    launch_spring_grad(Uw_.p, Ul_.p, d_ends_.p, tangent_ ? d_gblocks_.p : nullptr, E_, -d_.dt / (h * h), out, s);
+    launch_interp<double>(w, w + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Uw, s);
+    launch_interp<double>(lam, lam + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N, Ul, s);
+    launch_spring_grad(Uw, Ul, d_ends_.p, tangent_ ? d_gblocks_.p : nullptr, E_, -d_.dt / (h * h), out, s);
   }
+
+  int points() const override { return M_; }
 
   void set_kappa(const double* kappa, hipStream_t s) override {
     require(E_ == 0 || kappa != nullptr, "kappa is NULL");
