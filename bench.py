@@ -13,12 +13,19 @@ right-hand side, both to 1e-8 (set-up excluded; inputs resident in HBM).
 
 Also reported: the roofline of the dominant kernel (k_ras_ib<double>, the
 finest level's Schwarz boxes with their own inverse), timed alone with HIP
-events on the stream it runs on; the other hot kernels; the batched form on
-64 independent systems (N in {64, 128, 256}, FP32 smoother); and the FP64 CPU
-oracle on a bounded sample of the same workload.
+events on the stream it runs on; the other hot kernels, the smoothing step's
+Krylov kernels among them; each solve's true residual under the oracle's
+operator, and at 128^2 (the same structure) the distance of both precisions'
+solutions to the oracle's; the plain 32^2 system and the 256^2 smoother
+comparison (four stiffnesses, additive Schwarz and the Schur-complement
+smoother) against the oracle; the differentiation workload (forward and
+adjoint solves, gradient kernel, gradient against the oracle's); the batched
+form on 64 independent systems (N in {64, 128, 256}, FP32 smoother); and the
+FP64 CPU oracle on a bounded sample, its complete V-cycles and solves timed
+with set-up apart.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-baseline sample|off]
-                    [--batch on|off] [--rms on|off] [--step on|off]
+                    [--batch on|off] [--rms on|off] [--step on|off] [--configs on|off]
 """
 import argparse
 import hashlib
@@ -47,7 +54,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--N", type=int, default=512)
     p.add_argument("--cpu-baseline", default="sample", choices=["sample", "off"])
-    p.add_argument("--cpu-boxes", type=int, default=1024)
+    p.add_argument("--cpu-boxes", type=int, default=128)
     p.add_argument("--roofline-reps", type=int, default=50)
     # 16 x 16 boxes with overlap 4: at mu = 1e-2 the paper finds that only the
     # largest boxes and overlaps give an effective smoother (Sec. 5.1.1, 5.2.1);
@@ -59,6 +66,7 @@ def parse():
     p.add_argument("--step", default="on", choices=["on", "off"])
     p.add_argument("--tangent", default="on", choices=["on", "off"])
     p.add_argument("--large", default="on", choices=["on", "off"])
+    p.add_argument("--configs", default="on", choices=["on", "off"])
     return p.parse_args()
 
 
@@ -248,60 +256,258 @@ def batch_bench(dev, reps=3):
     return out
 
 
+def oracle_operator(wl):
+    """The oracle's finest-level L_IB (assembled sparse, FP64) and the
+    projection of the right-hand side onto its range."""
+    from oracle import hierarchy, ib as oib, mac
+    N = wl.N
+    if getattr(wl, "spring_model", "linear") == "tangent":
+        IB = oib.ib_term_tangent(wl.X, wl.springs, wl.kappa, wl.rest, N, wl.dt)
+    else:
+        IB = oib.ib_term(wl.X, wl.springs, wl.kappa, N, wl.dt)
+    L = mac.stokes_ib((mac.momentum(N, wl.rho, wl.mu, wl.dt) + IB).tocsr(), mac.gradient(N), mac.divergence(N))
+    return L.tocsr(), (lambda v: hierarchy.project_range(v, N, wl.rho))
+
+
+def true_residual(L, proj, b, x):
+    bp = proj(b)
+    return float(np.linalg.norm(bp - L @ x) / np.linalg.norm(bp))
+
+
+def rel_err(x, ref):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+def gpu_solve(g, b, rtol=1e-8, reps=3, max_it=100):
+    """Median solve time of ``reps`` solves after one warm-up; the last
+    solution and info."""
+    import torch
+    x = torch.empty_like(b)
+    g.solve(b, rtol=rtol, out=x, max_it=max_it)
+    ms, info = [], None
+    for _ in range(reps):
+        _, info = g.solve(b, rtol=rtol, out=x, max_it=max_it)
+        ms.append(info["solve_ms"])
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info, float(np.median(ms))
+
+
+def c3_oracle_128(dev):
+    """The benchmark's structure (4 x 2048-point annulus, kappa = 1e4, rho = 1,
+    mu = 1e-2, RAS 16/4) on a 128^2 grid, where the whole oracle runs: both
+    precisions' solutions to 1e-8 against the oracle's 1e-12 solution, with
+    the oracle's set-up, V-cycle and solve timed."""
+    import torch
+    import workloads as W
+    from oracle.solver import Problem
+    from paper_1612_02208_amd import StokesIB
+    wl = W.annulus_512(N=128, box=16, overlap=4)
+    b_h = W.rhs(wl.N, 0)
+    b = torch.from_numpy(b_h).to(dev)
+    t0 = time.perf_counter()
+    P = Problem(wl)
+    t_setup = time.perf_counter() - t0
+    r = P.project(b_h)
+    t0 = time.perf_counter()
+    P.mg.vcycle(r)
+    t_vc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xo, io = P.solve(b_h, rtol=1e-8)
+    t_solve = time.perf_counter() - t0
+    xo12, _ = P.solve(b_h, rtol=1e-12, max_it=200)
+    out = {"workload": "annulus 4x2048 points, kappa=1e4, rho=1 mu=1e-2 dt=5e-4, 128x128, 5 levels, RAS 16x16/4",
+           "oracle": {"setup_s": t_setup, "vcycle_s": t_vc, "solve_s": t_solve, "iters": io["iters"]}}
+    for prec in ("fp64", "fp32"):
+        g = StokesIB(wl, precision=prec)
+        x, info, ms = gpu_solve(g, b)
+        g.close()
+        out[prec] = {"iters": info["iters"], "solve_ms": ms, "rel_res_true": true_residual(P.L, P.project, b_h, x),
+                     "rel_err_vs_oracle_1e-12": rel_err(x, xo12), "rel_err_vs_oracle_1e-8": rel_err(x, xo)}
+    return out
+
+
+def c1_bench(dev):
+    """Plain FP64 solve (32^2 Stokes membrane, 128 points, kappa = 1e2, 3
+    levels, RAS 8/2) against the oracle."""
+    import torch
+    import workloads as W
+    from oracle.solver import Problem
+    from paper_1612_02208_amd import StokesIB
+    wl = W.plain_32()
+    b_h = W.rhs(wl.N, 0)
+    b = torch.from_numpy(b_h).to(dev)
+    g = StokesIB(wl)
+    x, info, ms = gpu_solve(g, b, reps=5)
+    g.close()
+    P = Problem(wl)
+    t0 = time.perf_counter()
+    xo, io = P.solve(b_h, rtol=1e-8)
+    t_solve = time.perf_counter() - t0
+    return {"workload": "32x32 Stokes, membrane r=0.25 of 128 points, kappa=1e2, 3 levels, RAS 8x8/2, FP64",
+            "iters": info["iters"], "oracle_iters": io["iters"], "solve_ms": ms, "oracle_solve_s": t_solve,
+            "rel_res_true": true_residual(P.L, P.project, b_h, x), "rel_err_vs_oracle": rel_err(x, xo)}
+
+
+def c2_bench(dev):
+    """Smoother comparison: 256^2 Stokes membrane of 1024 points, kappa in
+    {1, 1e2, 1e4, 1e6}, additive Schwarz 8/2 and the Schur-complement
+    smoother, 6 levels, FP64, each to 1e-8.  Every solve's true residual is
+    taken under the oracle's operator; the oracle solves too for every SC
+    case and for RAS at kappa = 1e4 (its RAS set-up factors 1360 boxes per
+    stiffness), and the distance of the solutions is reported."""
+    import torch
+    import workloads as W
+    from oracle.solver import Problem
+    from paper_1612_02208_amd import StokesIB
+    b_h = W.rhs(256, 0)
+    b = torch.from_numpy(b_h).to(dev)
+    out = []
+    for kappa in (1e0, 1e2, 1e4, 1e6):
+        for sm in ("ras", "sc"):
+            wl = W.smoother_256(kappa, sm)
+            t0 = time.perf_counter()
+            g = StokesIB(wl)
+            setup = time.perf_counter() - t0
+            x, info, ms = gpu_solve(g, b)
+            st = g.stats()["levels"]
+            g.close()
+            rec = {"kappa": kappa, "smoother": sm, "box": "8x8/2" if sm == "ras" else None, "iters": info["iters"],
+                   "solve_ms": ms, "vcycles_per_s": info["vcycles"] / (ms / 1e3), "setup_s": setup}
+            if sm == "sc" or kappa == 1e4:
+                t0 = time.perf_counter()
+                P = Problem(wl)
+                t_set = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                xo, io = P.solve(b_h, rtol=1e-8)
+                rec.update(oracle_iters=io["iters"], oracle_setup_s=t_set, oracle_solve_s=time.perf_counter() - t0,
+                           rel_err_vs_oracle=rel_err(x, xo), rel_res_true=true_residual(P.L, P.project, b_h, x))
+            else:
+                L, proj = oracle_operator(wl)
+                rec["rel_res_true"] = true_residual(L, proj, b_h, x)
+            out.append(rec)
+            print(f"[bench] C2 kappa={kappa:g} {sm}: {rec['iters']} its, {ms:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def c5_bench(dev, reps=3):
+    """Differentiation form: 256^2 Stokes membrane of 1024 points,
+    kappa_i = 1e3 (1 + 0.5 u_i); loss 0.5 ||u - u_t||^2 with u_t from a
+    second stiffness field.  Forward solve, adjoint solve (transposed
+    operator path) to 1e-12 and the gradient kernel timed apart; the gradient
+    against the oracle's (tests/golden/c5_oracle_gradient.txt)."""
+    import torch
+    import workloads as W
+    from paper_1612_02208_amd import StokesIB
+    wl, wt = W.diff_256(field_seed=1), W.diff_256(field_seed=2)
+    b = torch.from_numpy(W.rhs(256, 0)).to(dev)
+    G, Gt = StokesIB(wl), StokesIB(wt)
+    ut, _ = Gt.solve(b, rtol=1e-12, max_it=400)
+    n2 = 2 * 256 * 256
+    fw, aw, gk = [], [], []
+    for _ in range(reps + 1):
+        w, iw = G.solve(b, rtol=1e-12, max_it=400)
+        rhs = torch.zeros_like(w)
+        rhs[:n2] = w[:n2] - ut[:n2]
+        lam, il = G.solve(rhs, rtol=1e-12, max_it=400, transpose=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            g = G.spring_gradient(w, lam)
+        e1.record()
+        torch.cuda.synchronize()
+        fw.append(iw["solve_ms"])
+        aw.append(il["solve_ms"])
+        gk.append(e0.elapsed_time(e1) / 20)
+    gh = g.cpu().numpy()
+    G.close()
+    Gt.close()
+    golden = os.path.join(ROOT, "tests", "golden", "c5_oracle_gradient.txt")
+    go = np.loadtxt(golden)
+    return {"workload": "256x256 Stokes, membrane of 1024 points, kappa_i = 1e3 (1 + 0.5 u_i), loss 0.5|u - u_t|^2",
+            "forward_ms": float(np.median(fw[1:])), "forward_iters": iw["iters"],
+            "adjoint_ms": float(np.median(aw[1:])), "adjoint_iters": il["iters"],
+            "gradient_kernel_ms": float(np.median(gk[1:])), "springs": int(len(wl.springs)),
+            "rel_err_vs_oracle_gradient": rel_err(gh, go)}
+
+
 def cpu_baseline(wl, nboxes):
-    """Time the plain FP64 oracle on a bounded sample of the same workload and
-    scale it to V-cycles/s: the box solves of the finest level (gather,
-    LU solve, owned-set scatter) on ``nboxes`` of its boxes, and one
-    L_IB apply per level; a V-cycle performs (nu1 + nu2) box solves per box of
-    every level >= 1 and six operator applies per level."""
+    """The plain FP64 oracle on the host cores, on a bounded sample of the
+    workload.  (1) Complete oracle V-cycles (Alg. 1: FGMRES-wrapped RAS
+    smoothing on every level, transfers, the coarsest direct solve) of the
+    same structure, fluid, boxes and smoothing on a 128^2 grid, set-up timed
+    apart, with all BLAS threads and with one.  (2) The 512^2 finest level's
+    box solves (gather, LU solve, owned-set scatter) on ``nboxes`` boxes.
+    ``value`` scales (1) to 512^2 by the ratio of box solves per V-cycle
+    (every level's boxes, each level at its own box size); the per-box cost
+    of (2) checks that the boxes cost the same at both sizes."""
     import scipy.linalg as la
     from threadpoolctl import threadpool_info, threadpool_limits
+    import workloads as W
     from oracle import hierarchy, schwarz
+    from oracle.solver import Problem
 
-    levels = hierarchy.build(wl)
-    fine = levels[-1]
+    def box_solves(N):
+        sizes = hierarchy.level_sizes(N, wl.coarse_N)[1:]
+        return (wl.nu1 + wl.nu2) * sum(len(schwarz.patches(n, wl.box, wl.overlap)) for n in sizes)
+
+    small = W.annulus_512(N=128, box=wl.box, overlap=wl.overlap)
+    t0 = time.perf_counter()
+    P = Problem(small)
+    t_setup = time.perf_counter() - t0
+    r = P.project(W.rhs(small.N, 0))
+
+    def vcycle_s(reps=2):
+        P.mg.vcycle(r)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.mg.vcycle(r)
+        return (time.perf_counter() - t0) / reps
+
+    t_vc128 = vcycle_s()
+    with threadpool_limits(limits=1, user_api="blas"):
+        t_vc128_1 = vcycle_s(1)
+    ratio = box_solves(wl.N) / box_solves(small.N)
+    # the 512^2 finest level's box solves on a sample
+    fine = hierarchy.build(wl)[-1]
     parts = schwarz.patches(fine.N, wl.box, wl.overlap)
     step = max(1, len(parts) // nboxes)
     sample = parts[::step][:nboxes]
     Lc = fine.L.tocsr()
     facs = [la.lu_factor(Lc[p.idx][:, p.idx].toarray()) for p in sample]
-    box_solves = (wl.nu1 + wl.nu2) * sum(len(schwarz.patches(l.N, wl.box, wl.overlap)) for l in levels[1:])
-
-    def timed():
-        rng = np.random.default_rng(0)
-        r = rng.uniform(-1, 1, fine.n)
-        z = np.zeros_like(r)
-        t0 = time.perf_counter()
-        for p, f in zip(sample, facs):
-            y = la.lu_solve(f, r[p.idx])
-            z[p.own_global] = y[p.own_local]
-        t_box = (time.perf_counter() - t0) / len(sample)
-        t_ops = 0.0
-        for lev in levels:
-            w = rng.uniform(-1, 1, lev.n)
-            t0 = time.perf_counter()
-            for _ in range(3):
-                lev.L @ w
-            t_ops += 6 * (time.perf_counter() - t0) / 3
-        return t_box, t_ops, box_solves * t_box + t_ops
-
+    rr = np.random.default_rng(0).uniform(-1, 1, fine.n)
+    z = np.zeros_like(rr)
+    t0 = time.perf_counter()
+    for p, f in zip(sample, facs):
+        y = la.lu_solve(f, rr[p.idx])
+        z[p.own_global] = y[p.own_local]
+    t_box512 = (time.perf_counter() - t0) / len(sample)
+    parts128 = schwarz.patches(small.N, wl.box, wl.overlap)
+    L128 = P.levels[-1].L.tocsr()
+    f128 = [la.lu_factor(L128[p.idx][:, p.idx].toarray()) for p in parts128[:16]]
+    r128 = np.random.default_rng(1).uniform(-1, 1, P.levels[-1].n)
+    t0 = time.perf_counter()
+    for p, f in zip(parts128[:16], f128):
+        la.lu_solve(f, r128[p.idx])
+    t_box128 = (time.perf_counter() - t0) / 16
     threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
-    t_box, t_ops, t_vc = timed()
-    with threadpool_limits(limits=1, user_api="blas"):
-        _, _, t_vc1 = timed()
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
+    t_vc = t_vc128 * ratio
     return {"value": 1.0 / t_vc, "unit": "V-cycles/s", "cores": threads, "kind": "oracle",
-            "sample": (f"FP64 oracle on the N={wl.N} annulus: {len(sample)} of {len(parts)} finest boxes "
-                       f"(LU solve + scatter, {t_box * 1e3:.3f} ms/box) scaled to the {box_solves} box "
-                       f"solves of one V-cycle, plus 6 sparse L_IB applies per level "
-                       f"({t_ops * 1e3:.1f} ms); factorisation and set-up excluded; cores = BLAS threads"),
-            "vcycle_s": t_vc, "cpu_model": model, "host_cpus": os.cpu_count(),
-            "single_thread": {"value": 1.0 / t_vc1, "vcycle_s": t_vc1}}
+            "sample": (f"FP64 oracle: complete V-cycles of the same structure, fluid, boxes and smoothing on "
+                       f"128x128 ({t_vc128:.2f} s each, set-up {t_setup:.1f} s apart), scaled by the ratio "
+                       f"of box solves per V-cycle at {wl.N}x{wl.N} and 128x128 ({ratio:.2f}); box solves "
+                       f"cost {t_box512 * 1e3:.2f} ms at {wl.N} ({len(sample)} sampled) and "
+                       f"{t_box128 * 1e3:.2f} ms at 128; cores = BLAS threads"),
+            "vcycle_s": t_vc, "vcycle_128_s": t_vc128, "setup_128_s": t_setup, "box_solve_ratio": ratio,
+            "box_solve_ms_512": 1e3 * t_box512, "box_solve_ms_128": 1e3 * t_box128,
+            "cpu_model": model, "host_cpus": os.cpu_count(),
+            "single_thread": {"value": 1.0 / (t_vc128_1 * ratio), "vcycle_128_s": t_vc128_1}}
 
 
 def main():
@@ -410,6 +616,15 @@ def main():
             t = g.kernel_time(kind, -1, a.roofline_reps)
             kernels[name] = {"bound": "hbm", "avg_ms": t["ms"], "alg_bytes": t["bytes"],
                              "gbs": t["bytes"] / t["ms"] / 1e6, "frac": t["bytes"] / t["ms"] / 1e6 / HBM_PEAK_GBS}
+        # the smoothing step's Krylov kernels on the finest level (basis of
+        # nu = 2 vectors); at 512^2 their vectors fit the Infinity Cache, so
+        # the rates are against HBM peak but the data may come from cache
+        for kind, name in (("apply_dots", f"k_apply_dots<{tag}>"), ("upd_dots", f"k_upd_dots<{tag}>"),
+                           ("upd_norm", f"k_upd_norm<{tag}>"), ("scale_red", f"k_scale_red<{tag}>"),
+                           ("combine_ls", f"k_combine_ls<{tag}>")):
+            t = g.kernel_time(kind, -1, a.roofline_reps)
+            kernels[name] = {"bound": "hbm", "avg_ms": t["ms"], "alg_bytes": t["bytes"],
+                             "gbs": t["bytes"] / t["ms"] / 1e6, "frac": t["bytes"] / t["ms"] / 1e6 / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC,
@@ -443,6 +658,19 @@ def main():
                      "launch_ms": ras_ms, "alg_bytes_per_launch": alg_bytes},
         "kernels": kernels,
     }
+    # each solve's true residual under the oracle's operator (the whole
+    # oracle does not set up at this size in bench time; the same structure
+    # at 128^2 is compared with the oracle's solutions below)
+    L_or, proj = oracle_operator(wl)
+    out["oracle_rel_res_true_fp64"] = true_residual(L_or, proj, b_h, x64.cpu().numpy())
+    out["oracle_rel_res_true_fp32"] = true_residual(L_or, proj, b_h, x32.cpu().numpy())
+    del L_or
+    if a.configs == "on":
+        for key, fn in (("c3_structure_128_vs_oracle", c3_oracle_128), ("c1_plain_32", c1_bench),
+                        ("c2_smoothers_256", c2_bench), ("c5_gradient_256", c5_bench)):
+            t0 = time.perf_counter()
+            out[key] = fn(dev)
+            print(f"[bench] {key} {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if a.rms == "on":
         t0 = time.perf_counter()
         out["smoothers_fp64"] = [smoother_bench(wl, b, "rms", a.box, a.overlap),

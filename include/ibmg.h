@@ -330,6 +330,17 @@ ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32
  *   IBMG_KERNEL_INTERP        interpolation on the finest level (FP64): 2 M x 16
  *                             weights, the window bases, every face some
  *                             window touches, 2 M values written
+ * and the Krylov kernels of one smoothing step on `level` (>= 1), the basis
+ * at its largest, k = max(nu1, nu2) vectors of n = 3 n_l^2 values (Sec. 3.3):
+ *   IBMG_KERNEL_APPLY_DOTS    L_IB^l z with the first Gram-Schmidt pass fused:
+ *                             z read, the product written, k vectors read
+ *                             ((k + 2) n values)
+ *   IBMG_KERNEL_UPD_DOTS      t -= V h, then the second pass's dots: t read and
+ *                             written, k vectors read ((k + 2) n)
+ *   IBMG_KERNEL_UPD_NORM      t -= V h2, then |t|^2: (k + 2) n
+ *   IBMG_KERNEL_SCALE_RED     v = t / |t|: 2 n
+ *   IBMG_KERNEL_COMBINE_LS    w += sum_q y_q Z_q after the small least squares:
+ *                             k vectors and w read, w written ((k + 2) n)
  * Synchronises ``stream``; IBMG_ERR_ARG if the level has no such work. */
 typedef enum {
   IBMG_KERNEL_RAS_IB = 0,
@@ -339,7 +350,12 @@ typedef enum {
   IBMG_KERNEL_RESTRICT = 4,
   IBMG_KERNEL_PROLONG = 5,
   IBMG_KERNEL_SPREAD = 6,
-  IBMG_KERNEL_INTERP = 7
+  IBMG_KERNEL_INTERP = 7,
+  IBMG_KERNEL_APPLY_DOTS = 8,
+  IBMG_KERNEL_UPD_DOTS = 9,
+  IBMG_KERNEL_UPD_NORM = 10,
+  IBMG_KERNEL_SCALE_RED = 11,
+  IBMG_KERNEL_COMBINE_LS = 12
 } ibmg_kernel;
 ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int32_t reps,
                              ibmg_stream stream, double* avg_ms, double* alg_bytes,

@@ -62,20 +62,42 @@ __global__ void k_gs_colour(T* x, const T* __restrict__ b, const int* __restrict
   x[r] += (b[r] - ax) / diag[r];
 }
 
-// colours [c_first, c_last] in order (step +1 or -1) inside one work-group
-// (pressure rows: one thread per row)
+// The first colour of a sweep from x = 0: every row is written, colour 0's
+// rows with b / diag (their whole update from a zero iterate), the others
+// with 0 (the zero fill).
+template <typename T>
+__global__ void k_gs_init(T* __restrict__ x, const T* __restrict__ b, const int* __restrict__ colour, size_t n,
+                          const T* __restrict__ diag) {
+  for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < n; r += (size_t)gridDim.x * blockDim.x)
+    x[r] = colour[r] == 0 ? (b[r] - T(0)) / diag[r] : T(0);
+}
+
+// Colours sweep over a span of small colours inside one work-group: colours
+// f0..f1 ascending, then g0..g1 descending (either part may be empty),
+// colours separated by work-group barriers (all waves of a work-group share
+// one CU, so global writes are visible to the group after the barrier).
+__device__ __forceinline__ int span_steps(int f0, int f1, int g0, int g1) {
+  return (f1 >= f0 ? f1 - f0 + 1 : 0) + (g0 >= g1 ? g0 - g1 + 1 : 0);
+}
+__device__ __forceinline__ int span_colour(int k, int f0, int f1, int g0) {
+  const int na = f1 >= f0 ? f1 - f0 + 1 : 0;
+  return k < na ? f0 + k : g0 - (k - na);
+}
+
+// pressure rows (-M^): one thread per row
 template <typename T>
 __global__ void __launch_bounds__(1024) k_gs_band_p(T* x, const T* __restrict__ b, const int* __restrict__ cptr,
-                                                    const int* __restrict__ rows, int c_first, int c_last, int step,
+                                                    const int* __restrict__ rows, int f0, int f1, int g0, int g1,
                                                     int N, const T* __restrict__ diag, const T* __restrict__ dinv,
                                                     T ih2) {
-  for (int col = c_first;; col += step) {
+  const int ns = span_steps(f0, f1, g0, g1);
+  for (int k = 0; k < ns; ++k) {
+    const int col = span_colour(k, f0, f1, g0);
     for (int t = cptr[col] + threadIdx.x; t < cptr[col + 1]; t += blockDim.x) {
       const int r = rows[t];
       x[r] += (b[r] - mhat_row<T>(x, r, N, ih2, dinv)) / diag[r];
     }
     __syncthreads();
-    if (col == c_last) break;
   }
 }
 
@@ -111,24 +133,37 @@ __device__ __forceinline__ void gs_row_group(T* x, const T* __restrict__ b, int 
   }
 }
 
-// one colour over the grid, a lane group per row
+// One large colour over the grid: its nlong long rows (listed first) with a
+// lane group per row in the first nbl work-groups, its other rows one
+// thread per row in the rest.
 template <typename T>
-__global__ void k_gs_colour_g(T* x, const T* __restrict__ b, const int* __restrict__ rows, int count, int N,
-                              StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, const T* __restrict__ diag) {
-  const int g = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kGsGroup);
-  const bool live = g < count;
-  gs_row_group<T>(x, b, live ? rows[g] : 0, live, threadIdx.x % kGsGroup, N, c, tu, tv, diag);
+__global__ void k_gs_colour_split(T* x, const T* __restrict__ b, const int* __restrict__ rows, int nlong,
+                                  int count, int nbl, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
+                                  const T* __restrict__ diag) {
+  if ((int)blockIdx.x < nbl) {
+    const int g = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kGsGroup);
+    const bool live = g < nlong;
+    gs_row_group<T>(x, b, live ? rows[g] : 0, live, threadIdx.x % kGsGroup, N, c, tu, tv, diag);
+    return;
+  }
+  const int t = nlong + (int)((blockIdx.x - nbl) * (size_t)blockDim.x + threadIdx.x);
+  if (t >= count) return;
+  const int r = rows[t];
+  x[r] += (b[r] - aib_row<T>(x, r, N, c, tu, tv)) / diag[r];
 }
 
-// colours [c_first, c_last] in order inside one work-group, lane groups per row
+// a span of small velocity colours inside one work-group, lane groups per row
+// (runs too large for the LDS kernel)
 template <typename T>
 __global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b, const int* __restrict__ cptr,
-                                                  const int* __restrict__ rows, int c_first, int c_last,
-                                                  int step, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
+                                                  const int* __restrict__ rows, int f0, int f1, int g0, int g1,
+                                                  int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
                                                   const T* __restrict__ diag) {
   constexpr int G = kGsGroup;
   const int grp = threadIdx.x / G, sub = threadIdx.x % G;
-  for (int col = c_first;; col += step) {
+  const int ns = span_steps(f0, f1, g0, g1);
+  for (int k = 0; k < ns; ++k) {
+    const int col = span_colour(k, f0, f1, g0);
     const int r0 = cptr[col], r1 = cptr[col + 1];
     // uniform trip count across the work-group (shuffles inside)
     for (int base = r0; base < r1; base += blockDim.x / G) {
@@ -137,63 +172,198 @@ __global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b,
       gs_row_group<T>(x, b, live ? rows[t] : 0, live, sub, N, c, tu, tv, diag);
     }
     __syncthreads();
-    if (col == c_last) break;
+  }
+}
+
+// LDS barrier: the work-group's LDS writes complete, then the barrier;
+// global loads already issued stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// A run of small velocity colours with the run's rows in LDS (BandRun):
+// the prologue loads each slot's iterate and its right-hand side minus the
+// outer entries (columns outside the run do not change while it is swept),
+// a group of kBandG lanes per slot, and the run's colour offsets.  Each
+// colour then updates its slots from LDS, a group of kBandG lanes per row;
+// the epilogue stores the slots.  A colour's slots (fewer than
+// kGsBigColour: one pass of the work-group) load their band entries (a
+// wave's loads contiguous in the transposed layout) into registers during
+// the previous colour; the barriers between colours wait on LDS only, so
+// those loads stay in flight across them.  Colours are run-relative: f0..f1
+// ascending, then g0..g1 descending.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_gs_band_lds(T* x, const T* __restrict__ b, BandView<T> v, int f0, int f1,
+                                                      int g0, int g1) {
+  extern __shared__ char smem_raw[];
+  T* xl = reinterpret_cast<T*>(smem_raw);
+  T* cb = xl + v.nb;
+  int* cp = reinterpret_cast<int*>(cb + v.nb);
+  const int tid = threadIdx.x;
+  const int grp = tid / kBandG, sub = tid % kBandG, ngrp = blockDim.x / kBandG;
+  for (int i = tid; i <= v.ncol; i += blockDim.x) cp[i] = v.cptr[i];
+  for (int base = 0; base < v.nb; base += ngrp) {
+    const int i = base + grp;
+    T a = 0;
+    if (i < v.nb)
+      for (int e = v.optr[i] + sub; e < v.optr[i + 1]; e += kBandG) a += v.oval[e] * x[v.ocol[e]];
+#pragma unroll
+    for (int off = kBandG / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kBandG);
+    if (i < v.nb && sub == 0) {
+      const int r = v.brow[i];
+      cb[i] = b[r] - a;
+      xl[i] = x[r];
+    }
+  }
+  lds_barrier();
+  const int ns = span_steps(f0, f1, g0, g1);
+  const int per = v.stride / kBandG;   // entries per lane, <= kBandK
+  int ent[kBandK];
+  T val[kBandK];
+  int row = -1;
+  T dg = T(1);
+  auto fetch = [&](int k) {
+    row = -1;
+    if (k >= ns) return;
+    const int col = span_colour(k, f0, f1, g0);
+    const int s0 = cp[col], n = cp[col + 1] - s0;
+    if (grp >= n) return;
+    row = s0 + grp;
+    dg = v.bdiag[row];
+    const size_t at = (size_t)s0 * v.stride + (size_t)grp * kBandG + sub;
+    const size_t step = (size_t)n * kBandG;
+#pragma unroll
+    for (int q = 0; q < kBandK; ++q) {
+      ent[q] = q < per ? v.bent[at + q * step] : 0;
+      val[q] = q < per ? v.bval[at + q * step] : T(0);
+    }
+  };
+  fetch(0);
+  for (int k = 0; k < ns; ++k) {
+    T a = 0;
+    if (row >= 0) {
+#pragma unroll
+      for (int q = 0; q < kBandK; ++q) a += val[q] * xl[ent[q]];
+    }
+#pragma unroll
+    for (int off = kBandG / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kBandG);
+    const int myrow = row;
+    const T mydg = dg;
+    fetch(k + 1);
+    if (myrow >= 0 && sub == 0) xl[myrow] += (cb[myrow] - a) / mydg;
+    lds_barrier();
+  }
+  for (int i = tid; i < v.nb; i += blockDim.x) x[v.brow[i]] = xl[i];
+}
+
+// Values of a run's entries from their codes: (IB index + 1) * 4 + stencil
+// kind, the IB index over the u rows' Galerkin entries, then the v rows'
+// (padding: code 0, value 0); and each slot's diagonal.
+template <typename T>
+__device__ __forceinline__ T band_value(int code, const StokesCoef<T>& c, const CsrT<T>& tu, const CsrT<T>& tv,
+                                        int nnz_u) {
+  const int kind = code & 3, k = (code >> 2) - 1;
+  T v = kind == 1 ? c.alpha + T(4) * c.beta : (kind == 2 ? -c.beta : T(0));
+  if (k >= 0) v += k < nnz_u ? tu.val[k] : tv.val[k - nnz_u];
+  return v;
+}
+
+template <typename T>
+__global__ void k_band_values(const int* __restrict__ bcode, T* __restrict__ bval, size_t nbe,
+                              const int* __restrict__ ocode, T* __restrict__ oval, size_t noe,
+                              const int* __restrict__ brow, T* __restrict__ bdiag, int nb, const T* __restrict__ diag,
+                              StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, int nnz_u) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nbe + noe + nb;
+       e += (size_t)gridDim.x * blockDim.x) {
+    if (e < nbe) bval[e] = band_value(bcode[e], c, tu, tv, nnz_u);
+    else if (e < nbe + noe) oval[e - nbe] = band_value(ocode[e - nbe], c, tu, tv, nnz_u);
+    else bdiag[e - nbe - noe] = diag[brow[e - nbe - noe]];
   }
 }
 
 template <typename T>
-void launch_gs_sweep(T* x, const T* b, const int* cptr_dev, const std::vector<int>& cptr, const int* rows,
-                     int ncol, bool mhat, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, const T* diag,
-                     const T* dinv, T ih2, int nbig, const std::vector<char>& long_rows, hipStream_t s) {
-  // forward over colours then backward; colours >= nbig rows are full-grid
-  // launches, with lane groups per row when they hold long IB rows
-  auto big = [&](int col) {
-    const int cnt = cptr[col + 1] - cptr[col];
-    if (!cnt) return;
-    if (!mhat && col < (int)long_rows.size() && long_rows[col]) {
-      IBMG_KLAUNCH((k_gs_colour_g<T>), dim3(cdiv((size_t)cnt * kGsGroup, 256)), dim3(256), 0, s, x, b,
-                         rows + cptr[col], cnt, N, c, tu, tv, diag);
-    } else if (mhat)
-      IBMG_KLAUNCH((k_gs_colour<T, true>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
-                         cnt, N, c, tu, tv, diag, dinv, ih2);
-    else
-      IBMG_KLAUNCH((k_gs_colour<T, false>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows + cptr[col],
-                         cnt, N, c, tu, tv, diag, dinv, ih2);
+void launch_band_values(BandRun<T>& run, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, int N, const T* diag,
+                        hipStream_t s) {
+  (void)N;
+  if (!run.nb) return;
+  const size_t nbe = run.hbent.size(), noe = run.hocol.size(), tot = nbe + noe + run.nb;
+  int grid = cdiv(tot, 256);
+  if (grid > 4096) grid = 4096;
+  IBMG_KLAUNCH((k_band_values<T>), dim3(grid), dim3(256), 0, s, run.bcode.p, run.bval.p, nbe, run.ocode.p,
+               run.oval.p, noe, run.brow.p, run.bdiag.p, run.nb, diag, c, tu, tv, run.nnz_u);
+  IBMG_LAUNCH_CHECK();
+}
+
+// One symmetric multicolour sweep from x = 0: colours 1 .. C-1 after the
+// fused colour 0, then C-2 .. 0 (the last colour's second update is zero in
+// exact arithmetic: its rows are mutually uncoupled, so after the first
+// their residuals vanish).  Large colours run over the grid; each maximal
+// span of small colours in that sequence runs in one work-group.
+template <typename T>
+void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s) {
+  const ColourLists& cl = *g.cl;
+  const int C = cl.ncol;
+  const size_t n = cl.colour.size();
+  if (!C) return;
+  {
+    int grid = cdiv(n, 256);
+    if (grid > 4096) grid = 4096;
+    IBMG_KLAUNCH((k_gs_init<T>), dim3(grid), dim3(256), 0, s, x, b, cl.d_colour.p, n, g.diag);
     IBMG_LAUNCH_CHECK();
-  };
-  auto band = [&](int first, int last, int step) {
-    if (mhat)
-      IBMG_KLAUNCH((k_gs_band_p<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N,
-                         diag, dinv, ih2);
-    else
-      IBMG_KLAUNCH((k_gs_band<T>), dim3(1), dim3(1024), 0, s, x, b, cptr_dev, rows, first, last, step, N, c,
-                         tu, tv, diag);
-    IBMG_LAUNCH_CHECK();
-  };
-  // a colour with at least nbig rows gets its own full-grid launch; runs of
-  // smaller colours go through one work-group in sequence
-  auto is_big = [&](int col) { return cptr[col + 1] - cptr[col] >= nbig; };
-  for (int col = 0; col < ncol;) {
-    if (is_big(col)) {
-      big(col);
-      ++col;
-      continue;
-    }
-    int last = col;
-    while (last + 1 < ncol && !is_big(last + 1)) ++last;
-    band(col, last, 1);
-    col = last + 1;
   }
-  for (int col = ncol - 1; col >= 0;) {
-    if (is_big(col)) {
-      big(col);
-      --col;
+  std::vector<int> seq;
+  for (int c = 1; c < C; ++c) seq.push_back(c);
+  for (int c = C - 2; c >= 0; --c) seq.push_back(c);
+  for (size_t a = 0; a < seq.size();) {
+    const int col = seq[a];
+    if (cl.big(col)) {
+      const int cnt = cl.ptr[col + 1] - cl.ptr[col];
+      const int* rows = cl.d_rows.p + cl.ptr[col];
+      if (g.mhat) {
+        IBMG_KLAUNCH((k_gs_colour<T, true>), dim3(cdiv(cnt, 256)), dim3(256), 0, s, x, b, rows, cnt, g.N, g.c,
+                     g.tu, g.tv, g.diag, g.dinv, g.ih2);
+      } else {
+        const int nl = cl.nlong[col];
+        const int nbl = cdiv((size_t)nl * kGsGroup, 256);
+        IBMG_KLAUNCH((k_gs_colour_split<T>), dim3(nbl + cdiv(cnt - nl, 256)), dim3(256), 0, s, x, b, rows, nl,
+                     cnt, nbl, g.N, g.c, g.tu, g.tv, g.diag);
+      }
+      IBMG_LAUNCH_CHECK();
+      ++a;
       continue;
     }
-    int first = col;
-    while (first - 1 >= 0 && !is_big(first - 1)) --first;
-    band(col, first, -1);
-    col = first - 1;
+    // the span of small colours seq[a..z]: its entries up to the turnaround
+    // (seq index C - 2, colour C - 1) ascend, the rest descend
+    size_t z = a;
+    while (z + 1 < seq.size() && !cl.big(seq[z + 1])) ++z;
+    const size_t turn = (size_t)(C - 2);
+    int f0 = 0, f1 = -1, g0 = -1, g1 = 0;
+    if (a <= turn) {
+      f0 = seq[a];
+      f1 = seq[std::min(z, turn)];
+    }
+    if (z > turn) {
+      g0 = seq[std::max(a, turn + 1)];
+      g1 = seq[z];
+    }
+    const BandRun<T>* run = nullptr;
+    if (g.runs)
+      for (const BandRun<T>& rr : *g.runs)
+        if (rr.cf <= seq[a] && seq[a] <= rr.cl) run = &rr;
+    if (run && run->lds) {
+      const int nc = run->cl - run->cf + 1;
+      const BandView<T> v{run->nb, nc, run->stride, run->cptr.p, run->brow.p, run->bent.p, run->optr.p,
+                          run->ocol.p, run->bval.p, run->oval.p, run->bdiag.p};
+      const int o = run->cf;
+      const size_t lds = 2 * (size_t)run->nb * sizeof(T) + (nc + 1) * sizeof(int);
+      IBMG_KLAUNCH((k_gs_band_lds<T>), dim3(1), dim3(1024), lds, s, x, b, v, f0 - o, f1 - o, g0 - o, g1 - o);
+    } else if (g.mhat) {
+      IBMG_KLAUNCH((k_gs_band_p<T>), dim3(1), dim3(1024), 0, s, x, b, cl.d_ptr.p, cl.d_rows.p, f0, f1, g0, g1, g.N,
+                   g.diag, g.dinv, g.ih2);
+    } else {
+      IBMG_KLAUNCH((k_gs_band<T>), dim3(1), dim3(1024), 0, s, x, b, cl.d_ptr.p, cl.d_rows.p, f0, f1, g0, g1, g.N,
+                   g.c, g.tu, g.tv, g.diag);
+    }
+    IBMG_LAUNCH_CHECK();
+    a = z + 1;
   }
 }
 
@@ -327,9 +497,9 @@ void launch_weyl(T* x, size_t n, hipStream_t s) {
 }
 
 #define IBMG_INST_SC(T)                                                                                      \
-  template void launch_gs_sweep<T>(T*, const T*, const int*, const std::vector<int>&, const int*, int, bool,  \
-                                   int, StokesCoef<T>, CsrT<T>, CsrT<T>, const T*, const T*, T, int,          \
-                                   const std::vector<char>&, hipStream_t);                                   \
+  template void launch_gs_sweep<T>(T*, const T*, const GsSweep<T>&, hipStream_t);                          \
+  template void launch_band_values<T>(BandRun<T>&, StokesCoef<T>, CsrT<T>, CsrT<T>, int, const T*,          \
+                                      hipStream_t);                                                          \
   template void launch_aib_apply<T>(const T*, T*, int, StokesCoef<T>, CsrT<T>, CsrT<T>, hipStream_t);        \
   template void launch_grad<T>(const T*, T*, int, T, hipStream_t);                                           \
   template void launch_div_comb<T>(const T*, const T*, T*, int, T, T, T, hipStream_t);                       \

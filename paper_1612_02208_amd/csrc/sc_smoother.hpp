@@ -29,14 +29,70 @@ namespace ibmg {
 // runs of smaller colours are swept inside one work-group.
 constexpr int kGsBigColour = 256;
 
-template <typename T>
-void launch_gs_sweep(T* x, const T* b, const int* cptr_dev, const std::vector<int>& cptr, const int* rows,
-                     int ncol, bool mhat, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, const T* diag,
-                     const T* dinv, T ih2, int nbig, const std::vector<char>& long_rows, hipStream_t s);
-
-// a colour whose longest IB row exceeds this many entries is swept with
-// lane groups per row
+// a velocity row whose IB part exceeds this many entries is swept with a
+// lane group per row
 constexpr int kGsLongRow = 8;
+
+// LDS of the band kernel: the run's iterate and right-hand side, 2 nb values
+constexpr size_t kGsBandLds = 64 << 10;
+
+// A run of consecutive small colours of the velocity sweep, swept by one
+// work-group with the run's rows resident in LDS.  Slots 0..nb-1 are the
+// run's rows in colour order (colour cf + k holds slots [cptr[k],
+// cptr[k+1])).  Each slot's row of A_IB (stencil and IB entries merged by
+// column) is split into band entries (columns that are slots of the run)
+// and outer entries (every other column, constant while the run is swept).
+// Band entries are padded to stride per row (zero entries) and stored per
+// colour transposed: colour k's rows (slots s0 .. s0 + n - 1) hold entry
+// q * kBandG + g of local row li at s0 * stride + (q * n + li) * kBandG + g,
+// so the lanes of a wave (consecutive rows, kBandG lanes each) read
+// consecutive addresses.  Entry codes: (IB index + 1) * 4 + stencil kind (0
+// none, 1 diagonal alpha + 4 beta, 2 neighbour -beta), the IB index running
+// over the u rows' Galerkin entries, then the v rows'; the values are formed
+// on the device from the level's coefficients and Galerkin rows.
+template <typename T>
+struct BandRun {
+  int cf = 0, cl = 0, nb = 0, stride = 0, nnz_u = 0;
+  bool lds = false;
+  std::vector<int> hcptr, hbrow, hbent, hbcode, hoptr, hocol, hocode;
+  DBuf<int> cptr, brow, bent, bcode, optr, ocol, ocode;
+  DBuf<T> bval, oval, bdiag;
+};
+
+template <typename T>
+struct BandView {
+  int nb, ncol, stride;
+  const int *cptr, *brow, *bent, *optr, *ocol;
+  const T *bval, *oval, *bdiag;
+};
+
+// band kernel shape: lanes per row, and padded entries a lane holds
+constexpr int kBandG = 4;
+constexpr int kBandK = 16;
+
+struct ColourLists;
+
+// one symmetric multicolour sweep (colour 0 from x = 0 fused with the zero
+// fill; the turnaround colour once)
+template <typename T>
+struct GsSweep {
+  const ColourLists* cl;
+  const std::vector<BandRun<T>>* runs;   // velocity: LDS runs (may be empty)
+  bool mhat;
+  int N;
+  StokesCoef<T> c;
+  CsrT<T> tu, tv;
+  const T* diag;
+  const T* dinv;
+  T ih2;
+};
+template <typename T>
+void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s);
+// band values and diagonals of a run (after the level's diagonals and
+// Galerkin rows are ready)
+template <typename T>
+void launch_band_values(BandRun<T>& run, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, int N, const T* diag,
+                        hipStream_t s);
 template <typename T>
 void launch_aib_apply(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s);
 template <typename T>
@@ -85,22 +141,128 @@ std::vector<int> greedy_colours(int n, F nbrs) {
 }
 
 struct ColourLists {
-  std::vector<int> ptr, rows;  // rows grouped by colour, ascending within a colour
-  std::vector<char> long_rows;  // per colour: holds an IB row longer than kGsLongRow
-  DBuf<int> d_ptr, d_rows;
+  std::vector<int> ptr, rows;  // rows grouped by colour (a colour's long rows first, each part ascending)
+  std::vector<int> nlong;      // per colour: rows whose IB part exceeds kGsLongRow
+  std::vector<int> colour;     // per row
+  DBuf<int> d_ptr, d_rows, d_colour;
   int ncol = 0;
-  void build(const std::vector<int>& col, hipStream_t s) {
+  bool big(int c) const { return ptr[c + 1] - ptr[c] >= kGsBigColour; }
+  // is_long(r): the row is swept with a lane group
+  template <typename L>
+  void build(const std::vector<int>& col, L is_long, hipStream_t s) {
+    colour = col;
     ncol = col.empty() ? 0 : *std::max_element(col.begin(), col.end()) + 1;
     ptr.assign(ncol + 1, 0);
     for (int c : col) ptr[c + 1]++;
     for (int c = 0; c < ncol; ++c) ptr[c + 1] += ptr[c];
     rows.assign(col.size(), 0);
-    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
-    for (int r = 0; r < (int)col.size(); ++r) rows[fill[col[r]]++] = r;
+    nlong.assign(ncol, 0);
+    for (int r = 0; r < (int)col.size(); ++r)
+      if (is_long(r)) nlong[col[r]]++;
+    std::vector<int> fl(ptr.begin(), ptr.end() - 1), fs(ncol);
+    for (int c = 0; c < ncol; ++c) fs[c] = ptr[c] + nlong[c];
+    for (int r = 0; r < (int)col.size(); ++r) rows[is_long(r) ? fl[col[r]]++ : fs[col[r]]++] = r;
     d_ptr.upload(ptr, s);
     d_rows.upload(rows, s);
+    d_colour.upload(colour, s);
   }
 };
+
+// The runs of consecutive small colours of a velocity colouring, with their
+// band and outer entries (host pattern; values by launch_band_values).
+// tptr_c / tcol_c are the level's Galerkin IB rows of component c (columns
+// index [u | v]).
+template <typename T>
+void build_band_runs(const ColourLists& cl, const std::vector<int>& tptr_u, const std::vector<int>& tcol_u,
+                     const std::vector<int>& tptr_v, const std::vector<int>& tcol_v, int N,
+                     std::vector<BandRun<T>>& runs, hipStream_t s) {
+  const std::vector<int>* tptr[2] = {&tptr_u, &tptr_v};
+  const std::vector<int>* tcol[2] = {&tcol_u, &tcol_v};
+  runs.clear();
+  const int NN = N * N;
+  std::vector<int> slot(2 * (size_t)NN, -1);
+  for (int c0 = 0; c0 < cl.ncol;) {
+    if (cl.big(c0)) {
+      ++c0;
+      continue;
+    }
+    int c1 = c0;
+    while (c1 + 1 < cl.ncol && !cl.big(c1 + 1)) ++c1;
+    runs.emplace_back();
+    BandRun<T>& run = runs.back();
+    run.cf = c0;
+    run.cl = c1;
+    const int s0 = cl.ptr[c0], s1 = cl.ptr[c1 + 1];
+    run.nb = s1 - s0;
+    run.hbrow.assign(cl.rows.begin() + s0, cl.rows.begin() + s1);
+    for (int i = 0; i < run.nb; ++i) slot[run.hbrow[i]] = i;
+    run.hcptr.clear();
+    for (int c = c0; c <= c1 + 1; ++c) run.hcptr.push_back(cl.ptr[c] - s0);
+    run.hoptr.assign(1, 0);
+    run.hocol.clear();
+    run.hocode.clear();
+    std::vector<std::vector<std::pair<int, int>>> band(run.nb);   // per slot: (slot, code)
+    std::vector<std::pair<int, int>> ents;   // (column, code)
+    for (int i = 0; i < run.nb; ++i) {
+      const int r = run.hbrow[i], comp = r >= NN ? 1 : 0, q = r - comp * NN, o = comp * NN;
+      const int ii = q % N, jj = q / N;
+      ents.clear();
+      ents.push_back({r, 1});
+      ents.push_back({o + jj * N + (ii + 1) % N, 2});
+      ents.push_back({o + jj * N + (ii + N - 1) % N, 2});
+      ents.push_back({o + ((jj + 1) % N) * N + ii, 2});
+      ents.push_back({o + ((jj + N - 1) % N) * N + ii, 2});
+      const int ib0 = comp ? (int)tcol_u.size() : 0;
+      for (int k = (*tptr[comp])[q]; k < (*tptr[comp])[q + 1]; ++k)
+        ents.push_back({(*tcol[comp])[k], (ib0 + k + 1) * 4});
+      std::sort(ents.begin(), ents.end());
+      for (size_t a = 0; a < ents.size();) {
+        const int col = ents[a].first;
+        int code = 0;
+        for (; a < ents.size() && ents[a].first == col; ++a) code += ents[a].second;
+        if (slot[col] >= 0) {
+          band[i].push_back({slot[col], code});
+        } else {
+          run.hocol.push_back(col);
+          run.hocode.push_back(code);
+        }
+      }
+      run.hoptr.push_back((int)run.hocol.size());
+    }
+    for (int i = 0; i < run.nb; ++i) slot[run.hbrow[i]] = -1;
+    size_t longest = 1;
+    for (const auto& bi : band) longest = std::max(longest, bi.size());
+    run.stride = (int)((longest + kBandG - 1) / kBandG * kBandG);
+    run.lds = run.stride <= kBandG * kBandK &&
+              2 * (size_t)run.nb * sizeof(T) + (run.hcptr.size() + 1) * sizeof(int) <= kGsBandLds;
+    run.nnz_u = (int)tcol_u.size();
+    run.hbent.assign((size_t)run.nb * run.stride, 0);
+    run.hbcode.assign((size_t)run.nb * run.stride, 0);
+    for (int k = 0; k + 1 < (int)run.hcptr.size(); ++k) {
+      const int a0 = run.hcptr[k], n = run.hcptr[k + 1] - a0;
+      for (int li = 0; li < n; ++li) {
+        const auto& bi = band[a0 + li];
+        for (size_t e = 0; e < bi.size(); ++e) {
+          const size_t q = e / kBandG, g = e % kBandG;
+          const size_t at = (size_t)a0 * run.stride + (q * n + li) * kBandG + g;
+          run.hbent[at] = bi[e].first;
+          run.hbcode[at] = bi[e].second;
+        }
+      }
+    }
+    run.cptr.upload(run.hcptr, s);
+    run.brow.upload(run.hbrow, s);
+    run.bent.upload(run.hbent, s);
+    run.bcode.upload(run.hbcode, s);
+    run.optr.upload(run.hoptr, s);
+    run.ocol.upload(run.hocol, s);
+    run.ocode.upload(run.hocode, s);
+    run.bval.alloc(std::max<size_t>(run.hbent.size(), 1));
+    run.oval.alloc(std::max<size_t>(run.hocol.size(), 1));
+    run.bdiag.alloc(std::max(run.nb, 1));
+    c0 = c1 + 1;
+  }
+}
 
 template <typename T>
 struct ScLevel {
@@ -110,6 +272,7 @@ struct ScLevel {
   CsrT<T> tu{}, tv{};
   T ih2 = 0;
   ColourLists colu, colp;
+  std::vector<BandRun<T>> runs_u;   // LDS runs of the velocity sweep
   DBuf<T> diag, dinv, mdiag;  // A_IB diagonal (and inverse) on faces, -M^ diagonal on cells
   // Chebyshev coefficients: x = d0 + d1 + ..., d0 = B^{-1} r / theta,
   // d_{k+1} = c1[k] d_k + c2[k] B^{-1} r_{k+1}
@@ -135,17 +298,12 @@ struct ScLevel {
     }
   }
 
+  // one symmetric Gauss-Seidel sweep from x = 0 (x is overwritten)
   void sgs_a(const T* b, T* x, hipStream_t st) {
-    const size_t n2 = 2 * (size_t)N * N;
-    launch_axpby<T>(n2, T(0), b, T(0), nullptr, x, st);
-    launch_gs_sweep<T>(x, b, colu.d_ptr.p, colu.ptr, colu.d_rows.p, colu.ncol, false, N, c, tu, tv, diag.p,
-                       dinv.p, ih2, kGsBigColour, colu.long_rows, st);
+    launch_gs_sweep<T>(x, b, GsSweep<T>{&colu, &runs_u, false, N, c, tu, tv, diag.p, dinv.p, ih2}, st);
   }
   void sgs_m(const T* b, T* x, hipStream_t st) {
-    const size_t n1 = (size_t)N * N;
-    launch_axpby<T>(n1, T(0), b, T(0), nullptr, x, st);
-    launch_gs_sweep<T>(x, b, colp.d_ptr.p, colp.ptr, colp.d_rows.p, colp.ncol, true, N, c, tu, tv, mdiag.p,
-                       dinv.p, ih2, kGsBigColour, colp.long_rows, st);
+    launch_gs_sweep<T>(x, b, GsSweep<T>{&colp, nullptr, true, N, c, tu, tv, mdiag.p, dinv.p, ih2}, st);
   }
 
   // x = A~^{-1} r (velocity vectors); residual r_k = r - A x kept in ar

@@ -791,14 +791,12 @@ class Solver final : public SolverBase {
       const CompFoot& f = lev.f[comp];
       for (int k = f.tptr[q]; k < f.tptr[q + 1]; ++k) nb.push_back(f.tcol[k]);
     });
-    sc.colu.build(colv, s);
-    sc.colu.long_rows.assign(sc.colu.ncol, 0);
-    for (int cc = 0; cc < sc.colu.ncol; ++cc)
-      for (int t = sc.colu.ptr[cc]; t < sc.colu.ptr[cc + 1]; ++t) {
-        const int r = sc.colu.rows[t], comp = r >= NN ? 1 : 0, q = r - comp * NN;
-        const CompFoot& f = lev.f[comp];
-        if (f.tptr[q + 1] - f.tptr[q] > kGsLongRow) sc.colu.long_rows[cc] = 1;
-      }
+    sc.colu.build(colv, [&](int r) {
+      const int comp = r >= NN ? 1 : 0, q = r - comp * NN;
+      const CompFoot& f = lev.f[comp];
+      return f.tptr[q + 1] - f.tptr[q] > kGsLongRow;
+    }, s);
+    build_band_runs<T>(sc.colu, lev.f[0].tptr, lev.f[0].tcol, lev.f[1].tptr, lev.f[1].tcol, N, sc.runs_u, s);
     std::vector<int> colp = greedy_colours(NN, [&](int r, std::vector<int>& nb) {
       const int i = r % N, j = r / N;
       nb.push_back(j * N + (i + 1) % N);
@@ -806,7 +804,7 @@ class Solver final : public SolverBase {
       nb.push_back(((j + 1) % N) * N + i);
       nb.push_back(((j + N - 1) % N) * N + i);
     });
-    sc.colp.build(colp, s);
+    sc.colp.build(colp, [](int) { return false; }, s);
     const size_t n2 = 2 * (size_t)NN, n1 = NN;
     sc.diag.alloc(n2);
     sc.dinv.alloc(n2);
@@ -873,6 +871,7 @@ class Solver final : public SolverBase {
     sc.tv = csr<T>(lev.f[1]);
     sc.ih2 = (T)((double)N * N);
     launch_sc_diag<T>(N, sc.c, sc.tu, sc.tv, sc.ih2, sc.diag.p, sc.dinv.p, sc.mdiag.p, s);
+    for (BandRun<T>& run : sc.runs_u) launch_band_values<T>(run, sc.c, sc.tu, sc.tv, N, sc.diag.p, s);
     const int nb1 = dots_blocks(n1, 256);
     // lam for SGS(A_IB)^{-1} A_IB, start vector with the velocity means
     // removed when rho = 0
@@ -1640,6 +1639,46 @@ class Solver final : public SolverBase {
         ms = time_launches([&] {
           launch_interp<double>(fs_.p, fs_.p + nn, fview<double>(lev.f[0]), fview<double>(lev.f[1]), M_, lev.N,
                                 Uw_.p, s);
+        }, reps, s);
+      }
+    } else if (kernel >= IBMG_KERNEL_APPLY_DOTS && kernel <= IBMG_KERNEL_COMBINE_LS) {
+      // one smoothing step's Krylov kernels with the basis at its largest
+      // (k = nu vectors): zero first-pass dots leave t as it is, unit
+      // partial norms give a unit scale, and a diagonal Hessenberg keeps the
+      // least squares well posed, so repeated launches see the same values
+      require(level >= 1, "the smoothing kernels run on levels >= 1");
+      const int k = nu_;
+      const int nblk = dots_blocks(n, 1024), nab = apply_blocks(lev.N), ldh = kMaxNu + 1;
+      double* pa = lev.part.p;
+      double* pb = lev.part.p + part_stride(lev);
+      T* V = lev.V.p;
+      T* Z = lev.Z.p;
+      T* t = V + (size_t)k * n;
+      launch_fill<T>(V, T(1), (size_t)(k + 1) * n, s);
+      launch_fill<T>(Z, T(1), (size_t)k * n, s);
+      launch_fill<double>(pa, 0.0, 2 * part_stride(lev), s);
+      launch_fill<double>(lev.H.p, 0.0, (size_t)(kMaxNu + 1) * kMaxNu, s);
+      launch_fill<double>(lev.scal.p, 1.0, 1, s);
+      for (int q = 0; q < k; ++q) launch_fill<double>(lev.H.p + (size_t)q * ldh + q, 1.0, 1, s);
+      double* hcol = lev.H.p + (size_t)(k - 1) * ldh;
+      if (kernel == IBMG_KERNEL_APPLY_DOTS) {
+        by = (double)(k + 2) * n * ts;
+        ms = time_launches([&] { op_dots<T>(level, Z, lev.t.p, nullptr, V, k, n, pa, lev.F.p, s); }, reps, s);
+      } else if (kernel == IBMG_KERNEL_UPD_DOTS) {
+        by = (double)(k + 2) * n * ts;
+        ms = time_launches([&] { launch_upd_dots<T>(t, V, k, n, n, pb, nblk, hcol, pa, s, nab); }, reps, s);
+      } else if (kernel == IBMG_KERNEL_UPD_NORM) {
+        by = (double)(k + 2) * n * ts;
+        ms = time_launches([&] { launch_upd_norm<T>(t, V, k, n, n, pb, nblk, hcol, pa, s); }, reps, s);
+      } else if (kernel == IBMG_KERNEL_SCALE_RED) {
+        by = 2.0 * n * ts;
+        launch_fill<double>(pb, 1.0, (size_t)nblk, s);
+        ms = time_launches([&] { launch_scale_red<T>(t, lev.t.p, n, pb, nblk, lev.scal.p + kScalTmp, s); },
+                           reps, s);
+      } else {
+        by = (double)(k + 2) * n * ts;
+        ms = time_launches([&] {
+          launch_combine_ls<T>(lev.w.p, Z, k, n, n, lev.H.p, ldh, lev.scal.p, lev.scal.p + kScalY, s, false);
         }, reps, s);
       }
     } else {

@@ -6,6 +6,11 @@ per dispatch, the copy calibrating the counters' units):
     python -m paper_1612_02208_amd.profile_kernels [--N 512] [--box 16]
         [--overlap 4] [--precision fp64] [--reps 5] [--copy-mib 1024]
 
+With ``--solve membrane256`` it instead runs whole FGMRES solves to 1e-8 (a
+warm-up, then ``--reps`` timed) of the 256^2 Stokes membrane (1024 points,
+``--kappa``, ``--smoother ras|sc``), so that a kernel trace attributes a
+solve's time to its kernels.
+
 With ``--large`` it times the grid and coupling kernels on a 4096^2 grid
 with 2^20 points instead (fields of 400 MB, beyond the caches): a
 suspension of 32 x 32 membranes in fibre order for the stencil, the
@@ -33,11 +38,33 @@ def main():
     p.add_argument("--reps", type=int, default=5)
     p.add_argument("--copy-mib", type=int, default=1024)
     p.add_argument("--large", action="store_true")
+    p.add_argument("--solve", default="", choices=["", "membrane256"])
+    p.add_argument("--kappa", type=float, default=1e4)
+    p.add_argument("--smoother", default="sc", choices=["ras", "sc", "rms"])
     a = p.parse_args()
     import numpy as np
     import torch
     import workloads as W
     from paper_1612_02208_amd import StokesIB
+
+    if a.solve:
+        wl = W.smoother_256(a.kappa, a.smoother)
+        g = StokesIB(wl, precision=a.precision)
+        b = torch.from_numpy(W.rhs(wl.N, 0)).cuda()
+        x, info = g.solve(b, rtol=1e-8)
+        st = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(a.reps):
+            x, info = g.solve(b, rtol=1e-8)
+        e1.record(st)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(workload=wl.name, precision=a.precision, reps=a.reps, iters=info["iters"],
+                              converged=info["converged"], solve_ms=e0.elapsed_time(e1) / a.reps,
+                              vcycles=info["vcycles"])), flush=True)
+        g.close()
+        return
 
     if a.large:
         N, M = 4096, 1 << 20
