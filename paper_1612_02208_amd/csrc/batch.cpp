@@ -345,11 +345,13 @@ class BatchSolver final : public BatchBase {
       double* hcol = L.H.p + (size_t)k * ldh;
       launch_dots_b<T>(L.V.p, k + 1, bn, t, sg, ns, L.pa.p, L.pst, L.nblk, s);
       launch_upd_dots_b<T>(t, L.V.p, k + 1, bn, sg, ns, L.pa.p, L.nblk, L.pst, hcol, hst, L.pb.p, s);
-      launch_upd_norm_b<T>(t, L.V.p, k + 1, bn, sg, ns, L.pb.p, L.nblk, L.pst, hcol, hst, L.pa.p, s);
-      launch_scale_red_b<T>(t, t, sg, ns, n, L.pa.p, L.nblk, L.pst, hcol + k + 1, hst, s);
+      // the last basis vector's norm goes straight to the least squares
+      const bool last = k + 1 == nu;
+      launch_upd_norm_b<T>(t, L.V.p, k + 1, bn, sg, ns, L.pb.p, L.nblk, L.pst, hcol, hst, L.pa.p, s, 0, !last);
+      if (!last) launch_scale_red_b<T>(t, t, sg, ns, n, L.pa.p, L.nblk, L.pst, hcol + k + 1, hst, s);
     }
     launch_combine_ls_b<T>(w, L.Z.p, nu, bn, sg, ns, n, L.H.p, ldh, hst, L.scal.p, L.scal.p + kScalY,
-                           kScalStride, s);
+                           kScalStride, s, false, L.pa.p, L.nblk, L.pst);
   }
 
   // Alg. 1 on every system: r and z are ragged batch vectors (FP64).

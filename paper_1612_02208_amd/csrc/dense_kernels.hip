@@ -708,7 +708,7 @@ struct IntTileSmem {
 // One interior tile (boxes ents[tile * TB ..], 64-row chunk, reduction slice
 // kslice of ksplit): box entry e = s * nbox + box id, system s at r + s
 // sys_n; boxes of inactive systems are left out.
-template <typename T, int TB>
+template <typename T, int TB, bool REGPLAN = true>
 __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restrict__ z, const BoxGeom& g,
                                              size_t sys_n, int nbox, const T* __restrict__ M,
                                              const int* __restrict__ ents, int nlist, int tile, int chunk,
@@ -755,18 +755,49 @@ __device__ __forceinline__ void ras_int_tile(const T* __restrict__ r, T* __restr
   T ga[AS];
   // the gather runs along the reduction index (a wave reads 64 consecutive
   // local unknowns of one box, mostly contiguous rows of the grid) and is
-  // transposed into Xs[k][box]
+  // transposed into Xs[k][box].  A thread's reduction index within a chunk
+  // (tid mod KC) and its boxes (one per u) are fixed, so the boxes' linear
+  // starts stay in registers and a chunk costs one offset read per thread;
+  // boxes that wrap the periodic edges (or an offset table not in LDS) take
+  // the general path.
+  // (REGPLAN = false, the batched launch: the boxes' starts are re-read from
+  // LDS per value, which keeps that kernel's register count down)
+  long long glin[GPT];
+  bool gslow = false;
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+    const int b = (tid + u * 256) / KC;
+    glin[u] = sm.bid[b] >= 0 ? sm.lin[b] : -2;
+    gslow |= sm.bid[b] >= 0 && (!ltab_lds || sm.lin[b] < 0);
+  }
   auto gather = [&](int c, T* gxo) {
-    const int j0 = c * KC;
+    if constexpr (!REGPLAN) {
+      const int j0 = c * KC;
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        const int t = tid + u * 256;
+        const int k = t % KC, b = t / KC;
+        const int jk = j0 + k;
+        T val = 0;
+        if (jk < g.nloc && sm.bid[b] >= 0) {
+          if (ltab_lds && sm.lin[b] >= 0) val = r[sm.lin[b] + sm.ltab[jk - kb0]];
+          else val = box_value<T>(r, g, loc_tab, jk, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
+        }
+        gxo[u] = val;
+      }
+      return;
+    }
+    const int jk = c * KC + tid % KC;
+    const bool in = jk < g.nloc;
+    const int off = in && ltab_lds ? sm.ltab[jk - kb0] : 0;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
-      const int t = tid + u * 256;
-      const int k = t % KC, b = t / KC;
-      const int jk = j0 + k;
       T val = 0;
-      if (jk < g.nloc && sm.bid[b] >= 0) {
-        if (ltab_lds && sm.lin[b] >= 0) val = r[sm.lin[b] + sm.ltab[jk - kb0]];
-        else val = box_value<T>(r, g, loc_tab, jk, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
+      if (in && glin[u] >= 0 && ltab_lds) {
+        val = r[glin[u] + off];
+      } else if (in && gslow && glin[u] != -2) {
+        const int b = (tid + u * 256) / KC;
+        val = box_value<T>(r, g, loc_tab, jk, sm.base[b], sm.lin[b], sm.bx0[b], sm.by0[b]);
       }
       gxo[u] = val;
     }
@@ -970,6 +1001,170 @@ __global__ void __launch_bounds__(256) k_ras_interior(const T* __restrict__ r, T
                       loc_tab, nullptr, part, sm, acc);
 }
 
+// Pipelined form of the interior product: a work-group owns a 64-row chunk,
+// 64 boxes and one reduction slice; wave w the chunk's rows 16w..16w+15
+// against all 64 boxes (four 16 x 16 output tiles), its inverse fragments
+// loading straight into registers.  The boxes' gathered residuals pass
+// through two LDS buffers, 32 reduction indices at a time: the next step's
+// inverse fragments and gathers load while the MFMAs read the current
+// buffer, and one barrier per step hands the buffers over.  The grid is one
+// dimensional and remapped so that the work-groups one XCD receives (the
+// hardware deals them to the eight XCDs in turn) form a contiguous run of
+// tasks, chunk-major: each XCD's L2 then serves few chunks of the shared
+// inverse.  Slices and the order of every output's MFMA steps are those of
+// the tile kernels above, so the sums agree bit for bit.
+constexpr int kPipeKC = 32;
+
+template <typename T>
+struct PipeSmem {
+  T Xs[2][kPipeKC][65];   // [buffer][reduction index][box]
+  size_t base[64];
+  long long lin[64];
+  int bid[64], bx0[64], by0[64];
+  int ltab[kIntLinTab];
+};
+
+// Task of work-group wg of nwg: XCD x = wg mod 8 receives wg = x, x + 8, ...;
+// those map to the run [x q + min(x, rem), ...) of length q + (x < rem),
+// q = nwg / 8, rem = nwg mod 8, a bijection onto [0, nwg).
+__device__ __forceinline__ int xcd_task(int wg, int nwg) {
+  const int q = nwg >> 3, rem = nwg & 7, x = wg & 7, u = wg >> 3;
+  return x * q + (x < rem ? x : rem) + u;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ras_interior_p(const T* __restrict__ r, T* __restrict__ z, BoxGeom g,
+                                                        const T* __restrict__ M, const int* __restrict__ boxes,
+                                                        int nlist, const int* __restrict__ loc_tab,
+                                                        T* __restrict__ part, int ksplit, bool acc_mode) {
+  constexpr int TB = 64, KC = kPipeKC, GPT = KC * TB / 256, AS = KC / 4, NT = TB / 16;
+  __shared__ PipeSmem<T> sm;
+  using acc_t = typename Mfma<T>::acc_t;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ntb = (nlist + TB - 1) / TB;
+  const int task = xcd_task(blockIdx.x, gridDim.x);
+  const int tile = task % ntb, cs = task / ntb;
+  const int kslice = cs % ksplit, chunk = cs / ksplit;
+  const int bt = tile * TB;
+  if (tid < TB) {
+    const int b = bt + tid;
+    const int pid = b < nlist ? boxes[b] : -1;
+    sm.bid[tid] = pid;
+    sm.base[tid] = 0;
+    sm.bx0[tid] = pid >= 0 ? (pid % g.npd) * g.b - g.o : 0;
+    sm.by0[tid] = pid >= 0 ? (pid / g.npd) * g.b - g.o : 0;
+    sm.lin[tid] = box_lin(g, 0, sm.bx0[tid], sm.by0[tid]);
+  }
+  // the slice: 64-column chunks [c0, c1) of the reduction index, as above
+  const int nchunk = (g.nloc + 63) / 64;
+  const int per = (nchunk + ksplit - 1) / ksplit;
+  const int c0 = kslice * per;
+  const int c1 = c0 + per < nchunk ? c0 + per : nchunk;
+  const int kb = c0 * 64, kspan = c1 > c0 ? (c1 - c0) * 64 : 0;
+  const bool ltab_lds = kspan <= kIntLinTab;
+  if (ltab_lds)
+    for (int k = tid; k < kspan; k += 256) sm.ltab[k] = kb + k < g.nloc ? loc_tab[g.nloc + kb + k] : 0;
+  __syncthreads();
+  const T* Mrow = M + (size_t)chunk * g.nloc * 64 + 16 * wave + (lane & 15);
+  const int kq = lane >> 4, bl = lane & 15;
+  acc_t acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = acc_t{0, 0, 0, 0};
+  // as in the tile kernels: fixed reduction index and boxes per thread, the
+  // boxes' linear starts in registers, one offset read per step
+  long long glin[GPT];
+  bool gslow = false;
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+    const int b = (tid + u * 256) / KC;
+    glin[u] = sm.bid[b] >= 0 ? sm.lin[b] : -2;
+    gslow |= sm.bid[b] >= 0 && (!ltab_lds || sm.lin[b] < 0);
+  }
+  auto gather = [&](int j0, T* gxo) {
+    const int jk = j0 + tid % KC;
+    const bool in = jk < g.nloc;
+    const int off = in && ltab_lds ? sm.ltab[jk - kb] : 0;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      T val = 0;
+      if (in && glin[u] >= 0 && ltab_lds) {
+        val = r[glin[u] + off];
+      } else if (in && gslow && glin[u] != -2) {
+        const int b = (tid + u * 256) / KC;
+        val = box_value<T>(r, g, loc_tab, jk, 0, sm.lin[b], sm.bx0[b], sm.by0[b]);
+      }
+      gxo[u] = val;
+    }
+  };
+  auto load_a = [&](int j0, T* gao) {
+    if (j0 + KC <= g.nloc) {
+      const T* Mj = Mrow + (size_t)(j0 + kq) * 64;
+#pragma unroll
+      for (int s = 0; s < AS; ++s) gao[s] = Mj[(size_t)s * 256];
+    } else {
+#pragma unroll
+      for (int s = 0; s < AS; ++s) {
+        const int jk = j0 + 4 * s + kq;
+        gao[s] = jk < g.nloc ? Mrow[(size_t)jk * 64] : (T)0;
+      }
+    }
+  };
+  auto stage = [&](int buf, const T* gxi) {
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      const int t = tid + u * 256;
+      sm.Xs[buf][t % KC][t / KC] = gxi[u];
+    }
+  };
+  const int nsteps = kspan / KC;
+  T ga[AS], gx[GPT];
+  if (nsteps > 0) {
+    load_a(kb, ga);
+    gather(kb, gx);
+    stage(0, gx);
+  }
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
+    T a[AS];
+#pragma unroll
+    for (int s = 0; s < AS; ++s) a[s] = ga[s];
+    const bool more = st + 1 < nsteps;
+    if (more) {
+      load_a(kb + (st + 1) * KC, ga);
+      gather(kb + (st + 1) * KC, gx);
+    }
+#pragma unroll
+    for (int s = 0; s < AS; ++s) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[q] = Mfma<T>::mma(a[s], sm.Xs[buf][4 * s + kq][16 * q + bl], acc[q]);
+    }
+    if (more) stage(buf ^ 1, gx);
+    __syncthreads();
+  }
+  const int nown_pad = g.nch * 64;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = chunk * 64 + 16 * wave + Mfma<T>::row(kq, v);
+    if (row >= g.nown) continue;
+    if (ksplit == 1) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int bb = 16 * q + bl;
+        if (sm.bid[bb] >= 0) {
+          const size_t o = own_glob(g, sm.bid[bb], row);
+          z[o] = acc_mode ? z[o] + acc[q][v] : acc[q][v];
+        }
+      }
+    } else {
+      T* pp = part + (size_t)kslice * nlist * nown_pad;
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+        if (bt + 16 * q + bl < nlist) pp[(size_t)(bt + 16 * q + bl) * nown_pad + row] = acc[q][v];
+    }
+  }
+}
+
 // Reduction slices for the interior product: enough blocks to cover the
 // device (>= 768) while every slice keeps at least two column chunks.
 int ras_interior_ksplit(const BoxGeom& g, int n_int) {
@@ -1118,6 +1313,11 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
       IBMG_LAUNCH_CHECK();
       IBMG_KLAUNCH((k_int_gemm<T>), dim3(g.nch, nbp / 128, ks), dim3(256), 0, s, shared_inv, xg, z, g,
                          int_boxes, n_int, nbp, tpart, ks, acc);
+    } else if (tb == kIntFormPipe) {
+      const long long nwg = (long long)((n_int + 63) / 64) * g.nch * ks;
+      if (nwg > 0x7fffffffLL) throw Error(IBMG_ERR_ARG, "interior product grid too large");
+      IBMG_KLAUNCH((k_ras_interior_p<T>), dim3((unsigned)nwg), dim3(256), 0, s, r, z, g, shared_inv, int_boxes,
+                   n_int, loc_tab, tpart, ks, acc);
     } else if (tb == 64)
       IBMG_KLAUNCH((k_ras_interior_g<T>), dim3((n_int + 63) / 64, g.nch, ks), dim3(256), 0, s, r, z, g,
                          shared_inv, int_boxes, n_int, loc_tab, tpart, ks, acc);
@@ -1238,8 +1438,9 @@ __global__ void __launch_bounds__(256) k_ras_batch(const T* __restrict__ r, T* _
         ras_int_gemm<T>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab, active,
                         nullptr, *reinterpret_cast<GemmSmem<T>*>(smem_raw), false);
       else
-        ras_int_tile<T, TB>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1, loc_tab,
-                            active, nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw), false);
+        ras_int_tile<T, TB, false>(r, z, g, sys_n, nbox, M, int_ents, n_int, ti / g.nch, ti % g.nch, 0, 1,
+                                   loc_tab, active, nullptr, *reinterpret_cast<IntTileSmem<T, TB>*>(smem_raw),
+                                   false);
     } else {
       const int q = (int)before, e = q / g.nch, c = q % g.nch;
       const int ent = ib_ents[e], sy = ent / nbox;

@@ -128,50 +128,73 @@ void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int
   IBMG_LAUNCH_CHECK();
 }
 
-// (J u)_l for every point and component: 4 lanes per (point, component),
-// lane b taking row b of the 4 x 4 window (its four weights are contiguous;
-// masked slots carry weight 0), the row sums added by shuffles in a fixed
-// order.  Points are taken in cell order (f.order), so neighbouring lane
-// groups read neighbouring faces.  Output planar U[comp * M + l] or
-// interleaved U[2 l + comp].
+// (J u)_l for every point, both components: 8 lanes per point, lane
+// 4 c + b taking row b of component c's 4 x 4 window (its four weights are
+// contiguous; masked slots carry weight 0), the row sums added by shuffles in
+// a fixed order.  Points are taken in cell order (f.order), so neighbouring
+// lane groups read neighbouring faces, and their bases and weights are read
+// from copies laid out in that order (obase, ow), so those reads are
+// contiguous.  Output interleaved U[2 l + c]: a point's two values are
+// stored side by side.
 template <typename T>
 __global__ void __launch_bounds__(256) k_interp_lanes(const T* __restrict__ u, const T* __restrict__ v,
                                                       FootView<T> fx, FootView<T> fy, int M, int N,
-                                                      T* __restrict__ U, int interleaved) {
+                                                      T* __restrict__ U) {
   const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int g = (int)(t / 4), b = (int)(t % 4);
-  const bool live = g < 2 * M;
-  const int comp = live && g >= M ? 1 : 0;
-  const int l = live ? fx.order[g - comp * M] : 0;
+  const int g = (int)(t / 8), comp = (int)(t / 4) & 1, b = (int)(t % 4);
+  const bool live = g < M;
   T a = 0;
+  int l = 0;
   if (live) {
     const FootView<T>& f = comp ? fy : fx;
+    l = fx.order[g];
     const T* src = comp ? v : u;
-    const int i0 = f.base[2 * l];
-    const T* row = src + (size_t)wrapi(f.base[2 * l + 1] + b, N) * N;
-    const T* w = f.w + (size_t)l * 16 + 4 * b;
+    const int i0 = f.obase[2 * g];
+    const T* row = src + (size_t)wrapi(f.obase[2 * g + 1] + b, N) * N;
+    const T* w = f.ow + (size_t)g * 16 + 4 * b;
 #pragma unroll
     for (int q = 0; q < 4; ++q) a += w[q] * row[wrapi(i0 + q, N)];
   }
   a += __shfl_xor(a, 1, 4);
   a += __shfl_xor(a, 2, 4);
-  if (live && b == 0) U[interleaved ? 2 * l + comp : comp * M + l] = a;
+  if (live && b == 0) U[2 * (size_t)l + comp] = a;
 }
+
+template <typename T>
+__global__ void k_walk_order(const int* __restrict__ order, const int* __restrict__ base, const T* __restrict__ w,
+                             int M, int* __restrict__ obase, T* __restrict__ ow) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (t >= (size_t)M * 16) return;
+  const int g = (int)(t / 16), s = (int)(t % 16);
+  const int l = order[g];
+  ow[t] = w[(size_t)l * 16 + s];
+  if (s < 2) obase[2 * (size_t)g + s] = base[2 * (size_t)l + s];
+}
+
+template <typename T>
+void launch_walk_order(const int* order, const int* base, const T* w, int M, int* obase, T* ow, hipStream_t s) {
+  if (!M) return;
+  IBMG_KLAUNCH((k_walk_order<T>), dim3(cdiv((size_t)M * 16, 256)), dim3(256), 0, s, order, base, w, M, obase, ow);
+  IBMG_LAUNCH_CHECK();
+}
+template void launch_walk_order<double>(const int*, const int*, const double*, int, int*, double*, hipStream_t);
+template void launch_walk_order<float>(const int*, const int*, const float*, int, int*, float*, hipStream_t);
+
 // F_l = sum over springs e at l of K_e (U_l - U_{other end}), from U = J u
-// (planar [2][M]); F is planar [2][M].  K_e = kappa_e I, or the tangent
+// (interleaved [M][2]); F is planar [2][M].  K_e = kappa_e I, or the tangent
 // block when sv.adj_k2 is set.
 template <typename T>
 __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __restrict__ F) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= sv.M) return;
   const int M = sv.M;
-  const T U0 = U[l], U1 = U[M + l];
+  const T U0 = U[2 * (size_t)l], U1 = U[2 * (size_t)l + 1];
   T f0 = 0, f1 = 0;
   if (sv.adj_k2) {
     for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
       const int q = sv.adj_nbr[e];
       const T kxx = sv.adj_k[e], kxy = sv.adj_k2[2 * e], kyy = sv.adj_k2[2 * e + 1];
-      const T d0 = U0 - U[q], d1 = U1 - U[M + q];
+      const T d0 = U0 - U[2 * (size_t)q], d1 = U1 - U[2 * (size_t)q + 1];
       f0 += kxx * d0 + kxy * d1;
       f1 += kxy * d0 + kyy * d1;
     }
@@ -179,8 +202,8 @@ __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __r
     for (int e = sv.adj_ptr[l]; e < sv.adj_ptr[l + 1]; ++e) {
       const int q = sv.adj_nbr[e];
       const T k = sv.adj_k[e];
-      f0 += k * (U0 - U[q]);
-      f1 += k * (U1 - U[M + q]);
+      f0 += k * (U0 - U[2 * (size_t)q]);
+      f1 += k * (U1 - U[2 * (size_t)q + 1]);
     }
   }
   F[l] = f0;
@@ -189,9 +212,8 @@ __global__ void k_spring_force(const T* __restrict__ U, SpringView<T> sv, T* __r
 
 template <typename T>
 static void launch_interp_lanes(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
-                                int interleaved, hipStream_t s) {
-  IBMG_KLAUNCH((k_interp_lanes<T>), dim3(cdiv((size_t)2 * M * 4, 256)), dim3(256), 0, s, u, v, fx, fy, M, N,
-                     U, interleaved);
+                                hipStream_t s) {
+  IBMG_KLAUNCH((k_interp_lanes<T>), dim3(cdiv((size_t)M * 8, 256)), dim3(256), 0, s, u, v, fx, fy, M, N, U);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -199,7 +221,7 @@ template <typename T>
 void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
                      int N, T* U, T* F, hipStream_t s) {
   if (!sv.M) return;
-  launch_interp_lanes<T>(u, v, fx, fy, sv.M, N, U, 0, s);
+  launch_interp_lanes<T>(u, v, fx, fy, sv.M, N, U, s);
   IBMG_KLAUNCH((k_spring_force<T>), dim3(cdiv(sv.M, 256)), dim3(256), 0, s, U, sv, F);
   IBMG_LAUNCH_CHECK();
 }
@@ -208,7 +230,7 @@ template <typename T>
 void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N, T* U,
                    hipStream_t s) {
   if (!M) return;
-  launch_interp_lanes<T>(u, v, fx, fy, M, N, U, 1, s);
+  launch_interp_lanes<T>(u, v, fx, fy, M, N, U, s);
 }
 
 // Nodal spring forces on the periodic square (Sec. 5 fibres): spring e at l
@@ -274,45 +296,48 @@ void launch_advance(double* X, const double* U, double dt, int M, hipStream_t s)
 }
 
 // f_face = scale * sum_(l, slot) w F_l, F interleaved [M][2]; f = [2][N][N].
-// One work-group per 256 consecutive faces of one component: their
-// (point, slot) entries are contiguous in face order, so the work-group
-// forms the entries' terms w F_l in chunks through LDS (every thread, in
-// entry order, with coalesced reads of the weights and indices), and then
-// each thread adds its face's terms in list order.  Long lists near a
-// densely sampled structure are thereby spread over the work-group instead
-// of one thread, and every face's sum keeps a fixed order.
+// One work-group per 256 consecutive faces, x-faces and then the y-faces of
+// the same indices: their (point, slot) entries are contiguous in face
+// order, so the work-group forms the entries' terms w F_l in chunks through
+// LDS (every thread, in entry order, with coalesced reads of the weights and
+// indices), and then each thread adds its face's terms in list order.  Long
+// lists near a densely sampled structure are thereby spread over the
+// work-group instead of one thread, and every face's sum keeps a fixed
+// order.  The y-faces' entries mostly name the points the x-faces' entries
+// just read, whose two force components share a cache line, so the second
+// pass finds them in cache.
 constexpr int kSpreadTile = 256, kSpreadChunk = 2048;
 
 __global__ void __launch_bounds__(256) k_spread(const double* __restrict__ F, FootView<double> fx,
                                                 FootView<double> fy, int N, double scale, double* __restrict__ f) {
   __shared__ double terms[kSpreadChunk];
-  const int comp = blockIdx.y;
-  const FootView<double>& fv = comp ? fy : fx;
   const int nf = N * N;
   const int f0 = blockIdx.x * kSpreadTile;
   const int face = f0 + threadIdx.x;
   const bool live = face < nf;
   const int fend = f0 + kSpreadTile < nf ? f0 + kSpreadTile : nf;
-  const int e0 = fv.sp_ptr[f0], e1 = fv.sp_ptr[fend];
-  const int my_lo = live ? fv.sp_ptr[face] : e1, my_hi = live ? fv.sp_ptr[face + 1] : e1;
-  double a = 0.0;
-  for (int c0 = e0; c0 < e1; c0 += kSpreadChunk) {
-    const int c1 = c0 + kSpreadChunk < e1 ? c0 + kSpreadChunk : e1;
-    for (int e = c0 + (int)threadIdx.x; e < c1; e += kSpreadTile)
-      terms[e - c0] = fv.sw[e] * F[2 * (fv.sp_ent[e] >> 4) + comp];
-    __syncthreads();
-    const int lo = my_lo > c0 ? my_lo : c0, hi = my_hi < c1 ? my_hi : c1;
-    for (int e = lo; e < hi; ++e) a += terms[e - c0];
-    __syncthreads();
+  for (int comp = 0; comp < 2; ++comp) {
+    const FootView<double>& fv = comp ? fy : fx;
+    const int e0 = fv.sp_ptr[f0], e1 = fv.sp_ptr[fend];
+    const int my_lo = live ? fv.sp_ptr[face] : e1, my_hi = live ? fv.sp_ptr[face + 1] : e1;
+    double a = 0.0;
+    for (int c0 = e0; c0 < e1; c0 += kSpreadChunk) {
+      const int c1 = c0 + kSpreadChunk < e1 ? c0 + kSpreadChunk : e1;
+      for (int e = c0 + (int)threadIdx.x; e < c1; e += kSpreadTile)
+        terms[e - c0] = fv.sw[e] * F[2 * (fv.sp_ent[e] >> 4) + comp];
+      __syncthreads();
+      const int lo = my_lo > c0 ? my_lo : c0, hi = my_hi < c1 ? my_hi : c1;
+      for (int e = lo; e < hi; ++e) a += terms[e - c0];
+      __syncthreads();
+    }
+    if (live) f[(size_t)comp * nf + face] = scale * a;
   }
-  if (live) f[(size_t)comp * nf + face] = scale * a;
 }
 
 void launch_spread(const double* F, FootView<double> fx, FootView<double> fy, int M, int N,
                    double scale, double* f, hipStream_t s) {
   (void)M;
-  dim3 grd(cdiv((size_t)N * N, kSpreadTile), 2);
-  IBMG_KLAUNCH(k_spread, grd, dim3(kSpreadTile), 0, s, F, fx, fy, N, scale, f);
+  IBMG_KLAUNCH(k_spread, dim3(cdiv((size_t)N * N, kSpreadTile)), dim3(kSpreadTile), 0, s, F, fx, fy, N, scale, f);
   IBMG_LAUNCH_CHECK();
 }
 

@@ -218,6 +218,8 @@ struct FootView {       // one component of one level
   const int* sp_ent;    // entries l*16 + slot
   const T* sw;          // weights in face-list order: sw[e] = w[sp_ent[e]]
   const int* order;     // [M] points in cell order (point-wise kernels walk it)
+  const int* obase;     // [M][2] bases in walk order: obase[2 g] = base[2 order[g]]
+  const T* ow;          // [M][16] weights in walk order
 };
 
 template <typename T>
@@ -361,15 +363,19 @@ int dots_blocks(size_t n, int cap = 256);
 template <typename T>
 void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
                      double* hcol, double* pout, hipStream_t s, int nblk_in = 0);
+// store = false: only the partial sums of |t - V h2|^2, t left unchanged
 template <typename T>
 void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
-                     double* hcol, double* pout, hipStream_t s, int nblk_in = 0);
+                     double* hcol, double* pout, hipStream_t s, int nblk_in = 0, bool store = true);
 template <typename T>
 void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, double* hout,
                       hipStream_t s);
+// npart != null: H[k][k-1] = sqrt(sum of the nnblk partials at npart),
+// stored into H by the kernel
 template <typename T>
-void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
-                       const double* beta, double* yout, hipStream_t s, bool assign = false);
+void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, double* H, int ldh,
+                       const double* beta, double* yout, hipStream_t s, bool assign = false,
+                       const double* npart = nullptr, int nnblk = 0);
 
 // immersed boundary
 void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,
@@ -379,9 +385,12 @@ template <typename T>
 void launch_gather_weights(const double* w, const int* ent, size_t n, T* sw, hipStream_t s);
 void launch_fp_coarsen(const int* fbase, const double* fw, const int* cbase, int M, int comp,
                        int Nf, int Nc, double* cw, hipStream_t s);
+// walk-ordered copies of one component's window bases and weights
+template <typename T>
+void launch_walk_order(const int* order, const int* base, const T* w, int M, int* obase, T* ow, hipStream_t s);
 template <typename T>
 void launch_ib_force(const T* u, const T* v, FootView<T> fx, FootView<T> fy, SpringView<T> sv,
-                     int N, T* U, T* F, hipStream_t s);   // U: [2][M] scratch (J u)
+                     int N, T* U, T* F, hipStream_t s);   // U: [M][2] scratch (J u, interleaved)
 template <typename T>
 void launch_interp(const T* u, const T* v, FootView<T> fx, FootView<T> fy, int M, int N,
                    T* U, hipStream_t s);
@@ -447,6 +456,10 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
 size_t int_gather_elems(const BoxGeom& g, int n_int);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);
+// interior product forms (launch_ras_apply's tb): 16, 32 = boxes per tile of
+// the narrow kernels, 64 = register-blocked tiles, 128 = gathered operand,
+// kIntFormPipe = the pipelined XCD-ordered 64-box tiles
+constexpr int kIntFormPipe = 1;
 // column slices of the IB-box kernel (part holds ksplit * n_ib * nch * 64,
 // followed by the interior product's slices when both are launched)
 int ras_ib_ksplit(const BoxGeom& g, int n_ib);
@@ -503,14 +516,15 @@ void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
 template <typename T>
 void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
-                       int nblk_in = 0);
+                       int nblk_in = 0, bool store = true);
 template <typename T>
 void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const double* pin, int nblk,
                         size_t pstride, double* hout, size_t hstride, hipStream_t s);
 template <typename T>
 void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
-                         const double* H, int ldh, size_t hstride, const double* beta, double* yout,
-                         size_t sstride, hipStream_t s, bool assign = false);
+                         double* H, int ldh, size_t hstride, const double* beta, double* yout,
+                         size_t sstride, hipStream_t s, bool assign = false, const double* npart = nullptr,
+                         int nnblk = 0, size_t pstride = 0);
 template <typename T>
 void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s);
 

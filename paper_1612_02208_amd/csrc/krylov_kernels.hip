@@ -85,6 +85,32 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
   hcol += sy * hstride;
   reduce_partials(pin, nblk_in, k, h, red);
   if (blockIdx.x == 0 && threadIdx.x < k) hcol[threadIdx.x] = h[threadIdx.x];
+  if (k <= 8) {
+    // one pass: each basis value feeds the update and then the pass-2 dot
+    // of the updated entry; every thread visits its entries in the order
+    // block_dots would, so the sums are those of the two-pass form
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+#pragma unroll 2
+    for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+      double vq[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vq[q] = q < k ? (double)V[(size_t)q * stride + i] : 0.0;
+      double a = (double)t[i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < k) a -= h[q] * vq[q];
+      const T tn = (T)a;
+      t[i] = tn;
+      const double ti = (double)tn;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < k) acc[q] += vq[q] * ti;
+    }
+    block_sums256<8>(acc, k, red, pout + (size_t)blockIdx.x * k, threadIdx.x);
+    return;
+  }
 #pragma unroll 4
   for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
     double a = (double)t[i];
@@ -96,12 +122,14 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
 }
 
 // t -= V h2 (h2 from pass-2 partials, added into hcol by block 0), then the
-// partial sums of |t|^2.
+// partial sums of |t|^2.  store = false leaves t as it was and only forms
+// the norm's partial sums (the last basis vector of a smoothing step is
+// never read: its norm alone enters the Hessenberg matrix).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict__ V, int k, size_t stride,
                                                        BSeg sg, const double* __restrict__ pin, int nblk_in,
                                                        size_t pstride, double* __restrict__ hcol,
-                                                       size_t hstride, double* __restrict__ pout) {
+                                                       size_t hstride, double* __restrict__ pout, bool store) {
   __shared__ double red[32];
   __shared__ double h[64];
   const int sy = blockIdx.y;
@@ -120,7 +148,7 @@ __global__ void __launch_bounds__(kThreads) k_upd_norm(T* t, const T* __restrict
     double a = (double)t[i];
     for (int q = 0; q < k; ++q) a -= h[q] * (double)V[(size_t)q * stride + i];
     const T tn = (T)a;
-    t[i] = tn;
+    if (store) t[i] = tn;
     acc += (double)tn * (double)tn;
   }
   const double a1[1] = {acc};
@@ -154,13 +182,19 @@ __global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, BSeg s
 // Least squares min || beta e1 - H y || ((k+1) x k Hessenberg, column-major,
 // leading dimension ldh) by Givens rotations in every block, then
 // x += sum_q y_q Z_q (assign: x = sum_q y_q Z_q, the same bits as adding to
-// a zeroed x); block 0 stores y.
+// a zeroed x); block 0 stores y.  npart != null: the last subdiagonal entry
+// H[k][k-1] is the square root of the nnblk partial sums there (reduced as
+// k_scale_red reduces them; block 0 stores it into H).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, const T* __restrict__ Z, int k,
-                                                         size_t stride, BSeg sg, const double* __restrict__ H,
+                                                         size_t stride, BSeg sg, double* __restrict__ H,
                                                          int ldh, size_t hstride, const double* __restrict__ beta,
-                                                         double* __restrict__ yout, size_t sstride, bool assign) {
+                                                         double* __restrict__ yout, size_t sstride, bool assign,
+                                                         const double* __restrict__ npart, int nnblk,
+                                                         size_t pstride) {
   __shared__ double y[16];
+  __shared__ double red[32];
+  __shared__ double nrm;
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
   const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
@@ -169,11 +203,18 @@ __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, cons
   H += sy * hstride;
   beta += sy * sstride;
   yout += sy * sstride;
+  double hlast = 0.0;
+  if (npart) {
+    reduce_partials(npart + sy * pstride, nnblk, 1, &nrm, red);
+    hlast = sqrt(nrm);
+    if (blockIdx.x == 0 && threadIdx.x == 0) H[k + (size_t)(k - 1) * ldh] = hlast;
+  }
   if (threadIdx.x == 0) {
     double R[17][16];
     double g[17], cs[16], sn[16];
     for (int j = 0; j < k; ++j)
       for (int i = 0; i <= k; ++i) R[i][j] = H[i + (size_t)j * ldh];
+    if (npart) R[k][k - 1] = hlast;
     for (int i = 0; i <= k; ++i) g[i] = 0.0;
     g[0] = beta[0];
     for (int j = 0; j < k; ++j) {
@@ -232,10 +273,10 @@ void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
 template <typename T>
 void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
-                       int nblk_in) {
+                       int nblk_in, bool store) {
   if (nsys <= 0) return;
   IBMG_KLAUNCH((k_upd_norm<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
-                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout);
+                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout, store);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -250,11 +291,13 @@ void launch_scale_red_b(const T* t, T* v, BSeg sg, int nsys, size_t nmax, const 
 
 template <typename T>
 void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
-                         const double* H, int ldh, size_t hstride, const double* beta, double* yout,
-                         size_t sstride, hipStream_t s, bool assign) {
+                         double* H, int ldh, size_t hstride, const double* beta, double* yout,
+                         size_t sstride, hipStream_t s, bool assign, const double* npart, int nnblk,
+                         size_t pstride) {
   if (nsys <= 0) return;
+  if (k < 1 || k > 16) throw Error(IBMG_ERR_ARG, "the smoothing least squares takes 1..16 columns");
   IBMG_KLAUNCH((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
-                     sg, H, ldh, hstride, beta, yout, sstride, assign);
+                     sg, H, ldh, hstride, beta, yout, sstride, assign, npart, nnblk, pstride);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -266,8 +309,8 @@ void launch_upd_dots(T* t, const T* V, int k, size_t stride, size_t n, const dou
 
 template <typename T>
 void launch_upd_norm(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
-                     double* hcol, double* pout, hipStream_t s, int nblk_in) {
-  launch_upd_norm_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s, nblk_in);
+                     double* hcol, double* pout, hipStream_t s, int nblk_in, bool store) {
+  launch_upd_norm_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s, nblk_in, store);
 }
 
 template <typename T>
@@ -277,27 +320,29 @@ void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, d
 }
 
 template <typename T>
-void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, const double* H, int ldh,
-                       const double* beta, double* yout, hipStream_t s, bool assign) {
-  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign);
+void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, double* H, int ldh,
+                       const double* beta, double* yout, hipStream_t s, bool assign, const double* npart,
+                       int nnblk) {
+  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign, npart, nnblk, 0);
 }
 
 #define IBMG_INST_KRY(T)                                                                               \
   template void launch_upd_dots<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,     \
                                    double*, hipStream_t, int);                                         \
   template void launch_upd_norm<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,     \
-                                   double*, hipStream_t, int);                                         \
+                                   double*, hipStream_t, int, bool);                                   \
   template void launch_scale_red<T>(const T*, T*, size_t, const double*, int, double*, hipStream_t);   \
-  template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, const double*, int,            \
-                                     const double*, double*, hipStream_t, bool);                       \
+  template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, double*, int, const double*,   \
+                                     double*, hipStream_t, bool, const double*, int);                  \
   template void launch_upd_dots_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
                                      double*, size_t, double*, hipStream_t, int);                      \
   template void launch_upd_norm_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
-                                     double*, size_t, double*, hipStream_t, int);                      \
+                                     double*, size_t, double*, hipStream_t, int, bool);                \
   template void launch_scale_red_b<T>(const T*, T*, BSeg, int, size_t, const double*, int, size_t,     \
                                       double*, size_t, hipStream_t);                                   \
-  template void launch_combine_ls_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, const double*,   \
-                                       int, size_t, const double*, double*, size_t, hipStream_t, bool);
+  template void launch_combine_ls_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, double*, int,     \
+                                       size_t, const double*, double*, size_t, hipStream_t, bool,      \
+                                       const double*, int, size_t);
 
 IBMG_INST_KRY(double)
 IBMG_INST_KRY(float)

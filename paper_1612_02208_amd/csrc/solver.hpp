@@ -15,6 +15,9 @@ struct CompFoot {             // one velocity component on one level
   DBuf<float> wf;             // FP32 copy for the FP32 smoother
   DBuf<double> sw;            // weights in face-list order
   DBuf<float> swf;            // FP32 copy
+  DBuf<int> d_obase;          // [M][2] window bases in walk (cell) order
+  DBuf<double> ow;            // [M][16] weights in walk order
+  DBuf<float> owf;            // FP32 copy
   DBuf<double> tval;
   DBuf<float> tvalf;          // FP32 copy for the FP32 smoother
   int max_list = 0;           // longest face -> point list

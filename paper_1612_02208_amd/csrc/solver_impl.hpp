@@ -11,6 +11,7 @@
 #include <thread>
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <type_traits>
@@ -167,13 +168,29 @@ class Solver final : public SolverBase {
     if (!pinned_) IBMG_HIP(hipHostMalloc((void**)&pinned_, 8 * sizeof(double), hipHostMallocDefault));
   }
 
-  // Every position-dependent part of the set-up, in workspace order.
+  // Every position-dependent part of the set-up, in workspace order.  With
+  // IBMG_SETUP_TIMES set in the environment each phase waits for the device
+  // and its wall time goes to stderr (a measurement aid; it serialises the
+  // phases).
   void build_all(hipStream_t s) {
-    build_structure(s);
+    const bool timed = !dry_run() && std::getenv("IBMG_SETUP_TIMES") != nullptr;
+    auto t = std::chrono::steady_clock::now();
+    auto mark = [&](const char* what) {
+      if (!timed) return;
+      IBMG_HIP(hipStreamSynchronize(s));
+      const auto now = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "[ibmg set-up] %-16s %8.3f ms\n", what,
+                   std::chrono::duration<double, std::milli>(now - t).count());
+      t = now;
+    };
+    build_structure(s, mark);
     if (!defer_coarse_) alloc_work(s);
-    build_numeric(s);
+    mark("work buffers");
+    build_numeric(s, mark);
     check_breakdown(s);
+    mark("breakdown scan");
     if (!defer_coarse_) tune_interior(s);
+    mark("interior tuning");
     IBMG_HIP(hipStreamSynchronize(s));
   }
 
@@ -227,7 +244,8 @@ class Solver final : public SolverBase {
   int level_n(int l) const override { return sizes_.at(l); }
 
   // ---------------------------------------------------------------- set-up
-  void build_structure(hipStream_t s) {
+  template <typename Mark>
+  void build_structure(hipStream_t s, Mark& mark) {
     // spring adjacency (node -> incident springs in spring order)
     adj_ptr_.assign(M_ + 1, 0);
     for (int e = 0; e < E_; ++e) {
@@ -284,9 +302,20 @@ class Solver final : public SolverBase {
           launch_gather_weights<float>(f.w.p, f.d_sp_ent.p, f.sp_ent.size(), f.swf.p, s);
         }
         if (l == L_ && c == 0) point_order(lev.N, f, s);
+        // the interpolation walks points in cell order and reads their
+        // windows there, so it gets copies laid out in that order
+        f.d_obase.alloc(2 * (size_t)M_);
+        f.ow.alloc((size_t)M_ * 16);
+        launch_walk_order<double>(d_order_.p, f.d_base.p, f.w.p, M_, f.d_obase.p, f.ow.p, s);
+        if (std::is_same<T, float>::value) {
+          f.owf.alloc((size_t)M_ * 16);
+          launch_walk_order<float>(d_order_.p, f.d_base.p, f.wf.p, M_, f.d_obase.p, f.owf.p, s);
+        }
       }
     }
+    mark("windows, lists");
     ib_patterns();   // IB rows need both components' windows
+    mark("IB row patterns");
     for (int l = L_; l >= 0; --l) {
       Level<T>& lev = levels_[l];
       for (int c = 0; c < 2; ++c) {
@@ -304,6 +333,7 @@ class Solver final : public SolverBase {
       if (l >= 1 && d_.smoother == IBMG_RMS) colour_boxes(lev);
       if (l >= 1 && d_.smoother == IBMG_SC) sc_structure(lev, s);
     }
+    mark("box classes");
   }
 
   // Points in cell order (row-major by the finest x-window base, ties in
@@ -571,11 +601,12 @@ class Solver final : public SolverBase {
     return std::max(kPartStride, (size_t)apply_blocks(lev.N) * (kMaxNu + 1));
   }
 
-  // Interior product form per Schwarz level: time the 16- and 32-box tiles,
-  // the register-blocked 64-box form and the gathered 128-box form (HIP
-  // events, on the level's work vectors) and keep the fastest.  All compute
-  // the same sums in the same order.  IBMG_INTERIOR_FORM=16|32|64|128 in the
-  // environment fixes the form instead (where the level supports it).
+  // Interior product form per Schwarz level: time the pipelined XCD-ordered
+  // 64-box tiles, the 16- and 32-box tiles, the register-blocked 64-box form
+  // and the gathered 128-box form (HIP events, on the level's work vectors)
+  // and keep the fastest.  All compute the same sums in the same order.
+  // IBMG_INTERIOR_FORM=1|16|32|64|128 in the environment fixes the form
+  // instead (1 = pipelined; where the level supports it).
   void tune_interior(hipStream_t s) {
     if (d_.smoother != IBMG_RAS && d_.smoother != IBMG_RMS) return;
     if (dry_run() || d_.combine == IBMG_COMBINE_SUM) return;
@@ -585,14 +616,23 @@ class Solver final : public SolverBase {
       Level<T>& lev = levels_[l];
       const int n_int = (int)lev.int_list.size();
       if (n_int == 0) continue;
-      if (forced == 16 || forced == 32 || forced == 64 ||
+      if (forced == 16 || forced == 32 || forced == 64 || forced == kIntFormPipe ||
           (forced == 128 && lev.int_x.n >= int_gather_elems(lev.g, n_int))) {
         lev.int_tb = forced;
         continue;
       }
+      // a rebuild at moved points keeps a level's earlier pick while its
+      // interior box count stays within an eighth of the count it was timed
+      // at (the forms give the same bits, so only speed is at stake)
+      if ((int)int_forms_.size() > l && int_forms_[l].first > 0 &&
+          8 * std::abs(n_int - int_forms_[l].first) <= int_forms_[l].first &&
+          (int_forms_[l].second != 128 || lev.int_x.n >= int_gather_elems(lev.g, n_int))) {
+        lev.int_tb = int_forms_[l].second;
+        continue;
+      }
       launch_fill<T>(lev.r.p, T(1), 3 * (size_t)lev.N * lev.N, s);
       double best = 1e300;
-      for (int tb : {32, 16, 64, 128}) {
+      for (int tb : {kIntFormPipe, 32, 16, 64, 128}) {
         if (tb == 128 && lev.int_x.n < int_gather_elems(lev.g, n_int)) continue;
         const double ms = time_launches([&] {
           ras_launch(lev, lev.r.p, lev.t.p, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, n_int, s, 2, false, tb);
@@ -602,6 +642,8 @@ class Solver final : public SolverBase {
           lev.int_tb = tb;
         }
       }
+      if ((int)int_forms_.size() <= l) int_forms_.resize(l + 1, {0, 0});
+      int_forms_[l] = {n_int, lev.int_tb};
     }
   }
 
@@ -715,7 +757,8 @@ class Solver final : public SolverBase {
     return B;
   }
 
-  void build_numeric(hipStream_t s) {
+  template <typename Mark>
+  void build_numeric(hipStream_t s, Mark& mark) {
     // spring stiffness per incidence: kappa_e, or the tangent block K_e
     const size_t na = adj_nbr_.size();
     std::vector<double> ak(na);
@@ -764,10 +807,13 @@ class Solver final : public SolverBase {
         }
       }
     }
+    mark("IB rows");
     build_coarse(s);
+    mark("coarsest");
     if (d_.smoother == IBMG_RAS || d_.smoother == IBMG_RMS) build_boxes(s);
     if (d_.smoother == IBMG_SC)
       for (int l = 1; l <= L_; ++l) sc_numeric(levels_[l], s);
+    mark("smoother data");
   }
 
   // ------------------------------------------------ Schur-complement set-up
@@ -1041,9 +1087,11 @@ class Solver final : public SolverBase {
   template <typename U>
   FootView<U> fview(CompFoot& f) {
     if constexpr (std::is_same<U, double>::value)
-      return FootView<double>{f.d_base.p, f.w.p, f.d_sp_ptr.p, f.d_sp_ent.p, f.sw.p, d_order_.p};
+      return FootView<double>{f.d_base.p, f.w.p, f.d_sp_ptr.p, f.d_sp_ent.p, f.sw.p, d_order_.p, f.d_obase.p,
+                              f.ow.p};
     else
-      return FootView<float>{f.d_base.p, f.wf.p, f.d_sp_ptr.p, f.d_sp_ent.p, f.swf.p, d_order_.p};
+      return FootView<float>{f.d_base.p, f.wf.p, f.d_sp_ptr.p, f.d_sp_ent.p, f.swf.p, d_order_.p, f.d_obase.p,
+                             f.owf.p};
   }
   template <typename U>
   SpringView<U> sview() {
@@ -1203,10 +1251,13 @@ class Solver final : public SolverBase {
       op_dots<T>(l, zk, t, nullptr, V, k + 1, n, pa, lev.F.p, s);
       double* hcol = lev.H.p + (size_t)k * ldh;
       launch_upd_dots<T>(t, V, k + 1, n, n, pa, nblk, hcol, pb, s, nab);
-      launch_upd_norm<T>(t, V, k + 1, n, n, pb, nblk, hcol, pa, s);
-      launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
+      // the last basis vector is never read: only its norm enters H, and
+      // the least-squares kernel takes it from the norm's partial sums
+      const bool last = k + 1 == nu;
+      launch_upd_norm<T>(t, V, k + 1, n, n, pb, nblk, hcol, pa, s, 0, !last);
+      if (!last) launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
     }
-    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s, w_zero);
+    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s, w_zero, pa, nblk);
   }
 
   // Classical Gram-Schmidt twice against V[0..k): h (first pass + second
@@ -1734,6 +1785,7 @@ class Solver final : public SolverBase {
   hipGraphExec_t gexec_ = nullptr;
   DBuf<double> vin_, vout_;
   DBuf<double> tpart_;   // slice sums of the IB-row values on coarse levels
+  std::vector<std::pair<int, int>> int_forms_;   // per level: interior boxes when timed, the form picked
   bool defer_coarse_ = false;   // a member of a batch: the batch inverts the coarsest system
   bool valid_ = true;
   int nn0_ = 0;          // size of the bordered coarsest system

@@ -350,25 +350,28 @@ def test_transfer_and_coupling_kernel_timing(pair):
     assert_classes(f, ref, face_classes(N, touched), OPS_TOL, "spread after timing")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["small_64", "annulus_64_box16", "random_48_rms"])
-def test_interior_product_forms_agree(name, monkeypatch):
-    """The interior-box product forms (16- and 32-box tiles, 64 x 64
-    register blocks, gathered 64 x 128 tiles) use the same reduction slices
-    and the same order of MFMA steps per output, so the smoother's result is
-    bitwise the same whichever form a level runs; and it is the oracle's."""
+def test_interior_product_forms_agree(name, precision, monkeypatch):
+    """The interior-box product forms (pipelined 64-box tiles in XCD order,
+    16- and 32-box tiles, 64 x 64 register blocks, gathered 64 x 128 tiles)
+    use the same reduction slices and the same order of MFMA steps per
+    output, so the smoother's result is bitwise the same whichever form a
+    level runs; and it is the oracle's."""
     from paper_1612_02208_amd import StokesIB
     wl = [c for c in CASES if c.name == name][0]
     P = Problem(wl)
     r = np.random.default_rng(31).uniform(-1, 1, P.levels[-1].n)
     outs = {}
-    for form in ("16", "32", "64", "128"):
+    for form in ("1", "16", "32", "64", "128"):
         monkeypatch.setenv("IBMG_INTERIOR_FORM", form)
-        G = StokesIB(wl)
+        G = StokesIB(wl, precision=precision)
         outs[form] = host(G.smoother_apply(-1, dev(r)))
         G.close()
     for form, z in outs.items():
         assert np.array_equal(z, outs["32"]), form
-    assert_classes(outs["128"], P.mg.smoothers[-1](r), lc(P), SOLVE_TOL, "interior forms")
+    tol = SOLVE_TOL if precision == "fp64" else FP32_TOL
+    assert_classes(outs["128"], P.mg.smoothers[-1](r), lc(P), tol, "interior forms")
 
 
 # ---------------------------------------------------------------------------
