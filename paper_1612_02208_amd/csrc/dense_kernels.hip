@@ -124,92 +124,117 @@ struct Mfma<float> {
 
 // ---------------------------------------------------------------------------
 // Batched in-place inversion of the symmetric box matrices by block sweeps
-// (the symmetric form of Gauss-Jordan elimination, no pivoting), 64 columns
+// (the symmetric form of Gauss-Jordan elimination, no pivoting), 128 columns
 // per step.  The box matrices are ordered velocities first: the velocity
 // block R_k A_IB R_k^T is symmetric positive definite (a principal submatrix
 // of rho/dt - mu Lap + IB with the periodic constants cut off), and the
 // pressure pivots come from the negative definite Schur complement
 // -G^T A^{-1} G, so no pivot vanishes.  L_IB is symmetric (G = -D^T,
-// S = J^*), so every swept matrix is too, and only the tiles on or below the
-// diagonal (64 x 64 tiles I >= J, diagonal tiles in full) are kept.
-// Sweeping block K of a symmetric S with D = S_KK:
-//   S_IJ <- S_IJ - S_IK D^{-1} S_KJ   (I, J != K),
+// S = J^*), so every swept matrix is too, and only the 64 x 64 tiles on or
+// below the diagonal (tiles I >= J, diagonal tiles in full) are kept.
+// Sweeping block K (columns kb .. kb+127, tiles K0 = kb/64 and K1 = K0 + 1)
+// of a symmetric S with D = S_KK:
+//   S_IJ <- S_IJ - S_IK D^{-1} S_KJ   (I, J outside K),
 //   S_IK <- S_IK D^{-1},  S_KK <- -D^{-1};
 // after every block S = -A^{-1}.  Step K, five launches over every matrix:
-//   diag       (a work-group per matrix): D^{-1} in LDS, to dinv;
-//   panel read (64-row tiles): C = S_:K from the kept tiles (rows above K
-//              from row K's tiles, transposed) and its transpose C^T;
-//   scale      (64-row tiles): E = C D^{-1};
-//   update     (kept 64 x 64 tiles outside row and column K):
-//              S_IJ <- S_IJ - E_I C_J^T;
+//   diag       (a work-group per matrix): D^{-1} in LDS (128 x 128, the
+//              160 KB of gfx950), to dinv;
+//   panel read (64-row tiles): C = S_:K from the kept tiles (a tile above
+//              K0 or K1 from that tile row's tile, transposed) and C^T;
+//   scale      (64-row tiles x two column halves): E = C D^{-1};
+//   update     (kept 64 x 64 tiles outside K): S_IJ <- S_IJ - E_I C_J^T;
 //   panel write: S_IK <- E_I below K, S_KI <- E_I^T above it, S_KK <- -D^{-1}.
-// The scale and update products are 64 x 64 x 64 tiles on the FP64 matrix
-// cores (16x16x4 MFMA, four waves of 2 x 2 tiles).
-constexpr int GJ_NB = 64;
+// The last block may be narrower (w < 128 columns): D is padded with the
+// identity, and the panel columns beyond w are zero, so they change nothing.
+// The scale and update products are 64 x 64 tiles with a 128-long reduction
+// on the FP64 matrix cores (16x16x4 MFMA, four waves of 2 x 2 tiles): twice
+// the flops per pass over the kept tiles of 64-column steps.
+constexpr int GJ_NB = kGjNb;   // 128
+static_assert(GJ_NB == 128, "the sweep kernels are written for 128-column blocks of two 64-wide tiles");
 
-__global__ void __launch_bounds__(256) k_gj_diag(const double* __restrict__ mats, int n, int kb,
-                                                 double* __restrict__ dinv_all) {
-  __shared__ double Dm[GJ_NB][GJ_NB + 1];
+// D^{-1} of the 128 x 128 pivot block by in-place Gauss-Jordan, one
+// work-group of 1024 threads per matrix.  Thread t holds column t mod 128 of
+// rows t / 128 + 8 q (q < 16) in registers; per pivot k only row k and
+// column k pass through LDS (two buffers by pivot parity, so one barrier per
+// pivot): the threads holding them publish them, and every thread updates
+// its sixteen entries from its column's row-k value and its rows' column-k
+// values (the latter the same for a whole wave, read as broadcasts).
+__global__ void __launch_bounds__(1024) k_gj_diag(const double* __restrict__ mats, int n, int kb,
+                                                  double* __restrict__ dinv_all) {
+  __shared__ double rowk[2][GJ_NB];
+  __shared__ double colk[2][GJ_NB];
   const double* A = mats + (size_t)blockIdx.x * n * n;
   double* Di = dinv_all + (size_t)blockIdx.x * GJ_NB * GJ_NB;
   const int tid = threadIdx.x;
+  const int b = tid & 127, a0 = tid >> 7;   // column, first row (rows a0 + 8 q)
   const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
   // the padding of a narrow last block is the identity, so the pivots stay
-  // nonzero; the padded rows and columns never reach the matrix
+  // nonzero; the padded rows and columns never reach the matrix.  Above the
+  // diagonal tiles only tile (K1, K0) is kept: D[a][b] with a in the first
+  // half and b in the second is read as D[b][a].
+  double v[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q, a = t >> 6, b = t & 63;
-    Dm[a][b] = (a < w && b < w) ? A[(size_t)(kb + a) * n + kb + b] : (a == b ? 1.0 : 0.0);
+    const int a = a0 + 8 * q;
+    double x = a == b ? 1.0 : 0.0;
+    if (a < w && b < w) {
+      const bool upper = (a >> 6) < (b >> 6);
+      x = upper ? A[(size_t)(kb + b) * n + kb + a] : A[(size_t)(kb + a) * n + kb + b];
+    }
+    v[q] = x;
   }
-  __syncthreads();
   for (int k = 0; k < GJ_NB; ++k) {
-    const double ip = 1.0 / Dm[k][k];
-    double rk[16], ck[16];
+    const int buf = k & 1;
+    // publish row k (the thread holding row k of column b) and column k
+    if ((k & 7) == a0) rowk[buf][b] = v[k >> 3];
+    if (b == k) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q;
-      rk[q] = Dm[k][t & 63];
-      ck[q] = Dm[t >> 6][k];
+      for (int q = 0; q < 16; ++q) colk[buf][a0 + 8 * q] = v[q];
     }
     __syncthreads();
+    // every LDS read is issued before any arithmetic, and the update is
+    // branch-free, so a pivot costs one round trip to LDS, not sixteen
+    const double pk = rowk[buf][k];
+    const double rk = rowk[buf][b];
+    double ck[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ck[q] = colk[buf][a0 + 8 * q];
+    const double ip = 1.0 / pk;
+    const double rip = rk * ip;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, ti = t >> 6, tj = t & 63;
-      double val = Dm[ti][tj];
-      if (ti == k && tj == k) val = ip;
-      else if (ti == k) val = rk[q] * ip;
-      else if (tj == k) val = -ck[q] * ip;
-      else val = val - ck[q] * rk[q] * ip;
-      Dm[ti][tj] = val;
+      const int a = a0 + 8 * q;
+      const double gen = v[q] - ck[q] * rip;
+      const double colv = -ck[q] * ip;
+      const double rowv = b == k ? ip : rip;
+      v[q] = a == k ? rowv : (b == k ? colv : gen);
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q;
-    Di[t] = Dm[t >> 6][t & 63];
-  }
+  for (int q = 0; q < 16; ++q) Di[(size_t)(a0 + 8 * q) * GJ_NB + b] = v[q];
 }
 
-struct Gj64Smem {
+struct GjTileSmem {
   double Xs[32][65];   // [reduction index of the chunk][row]
   double Ys[32][65];   // [reduction index of the chunk][column]
 };
 
 // acc = X Y for the wave's 32 x 32 quarter of a 64 x 64 tile: X is a
-// row-major block with 64 columns (rows beyond xrows read as zero), Y the
-// panel rows A[kb .. kb+64)[J0 .. J0+64) (zero beyond the matrix); the
-// reduction runs in two chunks of 32 through LDS.
-__device__ __forceinline__ void gj_tile_product(Gj64Smem& sm, Mfma<double>::acc_t acc[2][2],
+// row-major block with GJ_NB columns (rows beyond xrows read as zero), Y the
+// rows 0 .. GJ_NB-1 of a row-major array with row stride ldy, columns
+// J0 .. J0+63 (zero for rows >= yrows or columns >= ycols); the reduction runs
+// in chunks of 32 through LDS, the next chunk's values loading into
+// registers during the current chunk's MFMA steps.
+__device__ __forceinline__ void gj_tile_product(GjTileSmem& sm, Mfma<double>::acc_t acc[2][2],
                                                 const double* __restrict__ X, int xrows,
-                                                const double* __restrict__ A, int n, int kb, int J0) {
+                                                const double* __restrict__ Y, size_t ldy, int yrows, int ycols,
+                                                int J0) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::acc_t{0, 0, 0, 0};
-  // the second chunk's values load into registers during the first's steps
   double xr[8], yr[8];
   auto load = [&](int k0) {
 #pragma unroll
@@ -218,8 +243,8 @@ __device__ __forceinline__ void gj_tile_product(Gj64Smem& sm, Mfma<double>::acc_
       const int row = t >> 5, k = t & 31;
       xr[q] = row < xrows ? X[(size_t)row * GJ_NB + k0 + k] : 0.0;
       const int ky = t >> 6, c = t & 63;
-      const int r = kb + k0 + ky, j = J0 + c;
-      yr[q] = (r < n && j < n) ? A[(size_t)r * n + j] : 0.0;
+      const int r = k0 + ky, j = J0 + c;
+      yr[q] = (r < yrows && j < ycols) ? Y[(size_t)r * ldy + j] : 0.0;
     }
   };
   load(0);
@@ -246,56 +271,62 @@ __device__ __forceinline__ void gj_tile_product(Gj64Smem& sm, Mfma<double>::acc_
   }
 }
 
-// C = S[:, K] and C^T (n x 64 and 64 x n, zero beyond w) for one 64-row tile
-// I: tiles at or below K hold S_IK; above K, S_IK = S_KI^T is read from row
-// K's tile.  work holds C, C^T and E per matrix.
+// C = S[:, K] and C^T (n x 128 and 128 x n, zero beyond w) for one 64-row
+// tile I, one 64-column half h at a time (tile Kh = K0 + h): I >= Kh holds
+// S_I,Kh; above Kh, S_I,Kh = S_Kh,I^T is read from tile row Kh.  work holds
+// C, C^T and E per matrix.
 __global__ void __launch_bounds__(256) k_sw_panel_read(const double* __restrict__ mats, int n, int kb,
                                                        double* __restrict__ work) {
-  __shared__ double Ts[64][65];   // [row of the tile][column of K]
-  const int I0 = blockIdx.x * 64, K = kb / 64;
+  __shared__ double Ts[64][65];   // [row of the tile][column of the half]
+  const int I0 = blockIdx.x * 64, I = blockIdx.x;
   const double* A = mats + (size_t)blockIdx.y * n * n;
   double* C = work + (size_t)blockIdx.y * 3 * n * GJ_NB;
   double* Ct = C + (size_t)n * GJ_NB;
   const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
   const int tid = threadIdx.x;
-  if ((int)blockIdx.x >= K) {
+  for (int h = 0; h < 2; ++h) {
+    const int kbh = kb + 64 * h, Kh = kbh / 64;
+    const int wh = w - 64 * h;   // live columns of this half (<= 0: none)
+    if (I >= Kh) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+        Ts[a][k] = (i < n && k < wh) ? A[(size_t)i * n + kbh + k] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int t = tid + 256 * q, k = t >> 6, c = t & 63, i = I0 + c;
+        Ts[c][k] = (k < wh && i < n) ? A[(size_t)(kbh + k) * n + i] : 0.0;
+      }
+    }
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
-      Ts[a][k] = (i < n && k < w) ? A[(size_t)i * n + kb + k] : 0.0;
+      if (i < n) C[(size_t)i * GJ_NB + 64 * h + k] = Ts[a][k];
     }
-  } else {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, k = t >> 6, c = t & 63, i = I0 + c;
-      Ts[c][k] = (k < w && i < n) ? A[(size_t)(kb + k) * n + i] : 0.0;
+      const int t = tid + 256 * q, k = t >> 6, a = t & 63, i = I0 + a;
+      if (i < n) Ct[(size_t)(64 * h + k) * n + i] = Ts[a][k];
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
-    if (i < n) C[(size_t)i * GJ_NB + k] = Ts[a][k];
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q, k = t >> 6, a = t & 63, i = I0 + a;
-    if (i < n) Ct[(size_t)k * n + i] = Ts[a][k];
+    __syncthreads();
   }
 }
 
-// E_I = C_I D^{-1} for one 64-row tile I != K
+// E_I (columns 64 h .. 64 h + 63) = C_I D^{-1} for one 64-row tile I outside K
 __global__ void __launch_bounds__(256) k_sw_scale(const double* __restrict__ dinv_all, int n, int kb,
                                                   double* __restrict__ work) {
-  const int I0 = blockIdx.x * 64;
-  if (I0 == kb) return;   // E_K is not used
-  __shared__ Gj64Smem sm;
+  const int I0 = blockIdx.x * 64, I = blockIdx.x, K0 = kb / 64, h = blockIdx.z;
+  if (I == K0 || I == K0 + 1) return;   // E_K is not used
+  __shared__ GjTileSmem sm;
   const double* C = work + (size_t)blockIdx.y * 3 * n * GJ_NB;
   double* E = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)2 * n * GJ_NB;
   const double* Di = dinv_all + (size_t)blockIdx.y * GJ_NB * GJ_NB;
   const int rows = n - I0 < 64 ? n - I0 : 64;
   Mfma<double>::acc_t acc[2][2];
-  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, rows, Di, GJ_NB, 0, 0);
+  gj_tile_product(sm, acc, C + (size_t)I0 * GJ_NB, rows, Di, GJ_NB, GJ_NB, GJ_NB, 64 * h);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
 #pragma unroll
@@ -305,21 +336,22 @@ __global__ void __launch_bounds__(256) k_sw_scale(const double* __restrict__ din
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 32 * wr + 16 * a + Mfma<double>::row(kq, v);
-        if (row < rows) E[(size_t)(I0 + row) * GJ_NB + 32 * wc + 16 * b + ln] = acc[a][b][v];
+        if (row < rows) E[(size_t)(I0 + row) * GJ_NB + 64 * h + 32 * wc + 16 * b + ln] = acc[a][b][v];
       }
 }
 
-// S_IJ <- S_IJ - E_I C_J^T over the kept tiles I >= J outside row and column
-// K; work-group p takes the p-th tile of the lower triangle in row order.
+// S_IJ <- S_IJ - E_I C_J^T over the kept tiles I >= J outside K (tiles K0
+// and K0 + 1); work-group p takes the p-th tile of the lower triangle in
+// row order.
 __global__ void __launch_bounds__(256) k_sw_update(double* __restrict__ mats, int n, int kb,
                                                    const double* __restrict__ work) {
   const int p = blockIdx.x;
   int I = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
   while (I * (I + 1) / 2 > p) --I;
   while ((I + 1) * (I + 2) / 2 <= p) ++I;
-  const int J = p - I * (I + 1) / 2, K = kb / 64;
-  if (I == K || J == K) return;
-  __shared__ Gj64Smem sm;
+  const int J = p - I * (I + 1) / 2, K0 = kb / 64;
+  if (I == K0 || I == K0 + 1 || J == K0 || J == K0 + 1) return;
+  __shared__ GjTileSmem sm;
   const int I0 = I * 64, J0 = J * 64;
   double* A = mats + (size_t)blockIdx.y * n * n;
   const double* Ct = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)n * GJ_NB;
@@ -340,7 +372,7 @@ __global__ void __launch_bounds__(256) k_sw_update(double* __restrict__ mats, in
         old[a][b][v] = (i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
       }
   Mfma<double>::acc_t acc[2][2];
-  gj_tile_product(sm, acc, E + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, Ct, n, 0, J0);
+  gj_tile_product(sm, acc, E + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, Ct, n, GJ_NB, n, J0);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -353,44 +385,56 @@ __global__ void __launch_bounds__(256) k_sw_update(double* __restrict__ mats, in
       }
 }
 
-// Row and column K of the swept matrix, one 64-row tile I per work-group
+// Row and column K of the swept matrix, one 64-row tile I per work-group:
+// the kept tiles of S_KK (K0,K0), (K1,K0), (K1,K1) <- -D^{-1}; below K,
+// S_I,Kh <- E_I's half h; above K, S_Kh,I <- that half transposed.
 __global__ void __launch_bounds__(256) k_sw_panel_write(double* __restrict__ mats, int n, int kb,
                                                         const double* __restrict__ work,
                                                         const double* __restrict__ dinv_all) {
   __shared__ double Ts[64][65];
-  const int I0 = blockIdx.x * 64, K = kb / 64, I = blockIdx.x;
+  const int I0 = blockIdx.x * 64, K0 = kb / 64, I = blockIdx.x;
   double* A = mats + (size_t)blockIdx.y * n * n;
   const double* E = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)2 * n * GJ_NB;
   const double* Di = dinv_all + (size_t)blockIdx.y * GJ_NB * GJ_NB;
   const int w = n - kb < GJ_NB ? n - kb : GJ_NB;
   const int tid = threadIdx.x;
-  if (I == K) {   // S_KK <- -D^{-1}
+  if (I == K0 || I == K0 + 1) {
+    // row tile I of D's kept lower part: columns 0 .. 64 (I - K0) + 63
+    const int r0 = 64 * (I - K0);
+    for (int h = 0; h <= I - K0; ++h) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, a = t >> 6, b = t & 63;
-      if (a < w && b < w) A[(size_t)(kb + a) * n + kb + b] = -Di[t];
+      for (int q = 0; q < 16; ++q) {
+        const int t = tid + 256 * q, a = t >> 6, b = t & 63;
+        const int ra = r0 + a, cb = 64 * h + b;
+        if (ra < w && cb < w) A[(size_t)(kb + ra) * n + kb + cb] = -Di[(size_t)ra * GJ_NB + cb];
+      }
     }
     return;
   }
-  if (I > K) {    // S_IK <- E_I
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+  if (I > K0 + 1) {    // S_IK <- E_I
+#pragma unroll 4
+    for (int q = 0; q < 32; ++q) {
+      const int t = tid + 256 * q, a = t >> 7, k = t & 127, i = I0 + a;
       if (i < n && k < w) A[(size_t)i * n + kb + k] = E[(size_t)i * GJ_NB + k];
     }
     return;
   }
-  // above K the kept tile is S_KI <- E_I^T
+  // above K the kept tiles are S_Kh,I <- (E_I's half h)^T
+  for (int h = 0; h < 2; ++h) {
+    const int wh = w - 64 * h;
+    if (wh <= 0) break;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
-    Ts[a][k] = i < n ? E[(size_t)i * GJ_NB + k] : 0.0;
-  }
-  __syncthreads();
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, a = t >> 6, k = t & 63, i = I0 + a;
+      Ts[a][k] = i < n ? E[(size_t)i * GJ_NB + 64 * h + k] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q, k = t >> 6, c = t & 63, i = I0 + c;
-    if (k < w && i < n) A[(size_t)(kb + k) * n + i] = Ts[c][k];
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, k = t >> 6, c = t & 63, i = I0 + c;
+      if (k < wh && i < n) A[(size_t)(kb + 64 * h + k) * n + i] = Ts[c][k];
+    }
+    __syncthreads();
   }
 }
 
@@ -399,11 +443,11 @@ void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv
   const int tiles = (n + 63) / 64;
   const int pairs = tiles * (tiles + 1) / 2;
   for (int kb = 0; kb < n; kb += GJ_NB) {
-    IBMG_KLAUNCH(k_gj_diag, dim3(count), dim3(256), 0, s, mats, n, kb, dinv);
+    IBMG_KLAUNCH(k_gj_diag, dim3(count), dim3(1024), 0, s, mats, n, kb, dinv);
     IBMG_LAUNCH_CHECK();
     IBMG_KLAUNCH(k_sw_panel_read, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    IBMG_KLAUNCH(k_sw_scale, dim3(tiles, count), dim3(256), 0, s, dinv, n, kb, work);
+    IBMG_KLAUNCH(k_sw_scale, dim3(tiles, count, 2), dim3(256), 0, s, dinv, n, kb, work);
     IBMG_LAUNCH_CHECK();
     IBMG_KLAUNCH(k_sw_update, dim3(pairs, count), dim3(256), 0, s, mats, n, kb, work);
     IBMG_LAUNCH_CHECK();
@@ -1550,14 +1594,20 @@ void launch_coarse_assemble(int N, StokesCoef<double> c, const int* tptr_u, cons
   IBMG_LAUNCH_CHECK();
 }
 
+// Gauss-Jordan with partial pivoting on [A | I] in one work-group of 1024
+// threads.  Per pivot: the column's largest magnitude (ties to the lower
+// row) by a butterfly within each wave and one pass over the 16 wave
+// results; the row swap; the scaled pivot row and the column's factors
+// staged in LDS; then the elimination over the whole matrix as one flat
+// loop, so each thread keeps several independent loads in flight.
 __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug, int nn, size_t stride) {
-  __shared__ double vmax[1024];
-  __shared__ int imax[1024];
+  __shared__ double wmax[16];
+  __shared__ int wimax[16];
   __shared__ double fac[1024];
   __shared__ double rowk[2048];   // the scaled pivot row (2 nn <= 2048)
   aug += blockIdx.x * stride;     // one system per work-group
   const int ld = 2 * nn;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   for (int k = 0; k < nn; ++k) {
     double best = -1.0;
     int bi = k;
@@ -1565,18 +1615,24 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug
       const double a = fabs(aug[(size_t)i * ld + k]);
       if (a > best) { best = a; bi = i; }
     }
-    vmax[tid] = best;
-    imax[tid] = bi;
-    __syncthreads();
-    for (int sft = nt / 2; sft > 0; sft >>= 1) {
-      if (tid < sft) {
-        const double o = vmax[tid + sft];
-        const int oi = imax[tid + sft];
-        if (o > vmax[tid] || (o == vmax[tid] && oi < imax[tid])) { vmax[tid] = o; imax[tid] = oi; }
-      }
-      __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
     }
-    const int p = imax[0];
+    if (lane == 0) {
+      wmax[wave] = best;
+      wimax[wave] = bi;
+    }
+    __syncthreads();
+    double bv = wmax[0];
+    int p = wimax[0];
+    for (int q = 1; q < (nt >> 6); ++q) {
+      const double o = wmax[q];
+      const int oi = wimax[q];
+      if (o > bv || (o == bv && oi < p)) { bv = o; p = oi; }
+    }
     if (p != k) {
       for (int j = tid; j < ld; j += nt) {
         const double t = aug[(size_t)k * ld + j];
@@ -1594,13 +1650,11 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* __restrict__ aug
     }
     for (int i = tid; i < nn; i += nt) fac[i] = aug[(size_t)i * ld + k];
     __syncthreads();
-    // a wave per row, its lanes along the row
-    const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
-    for (int i = wave; i < nn; i += nw) {
-      if (i == k) continue;
-      const double fi = fac[i];
-      double* Ai = aug + (size_t)i * ld;
-      for (int j = lane; j < ld; j += 64) Ai[j] -= fi * rowk[j];
+    const int tot = nn * ld;
+#pragma unroll 8
+    for (int t = tid; t < tot; t += nt) {
+      const int i = t / ld, j = t - i * ld;
+      if (i != k) aug[(size_t)i * ld + j] -= fac[i] * rowk[j];
     }
     __syncthreads();
   }

@@ -429,7 +429,7 @@ void launch_patch_assemble(const int* patch_ids, int count, BoxGeom g, StokesCoe
 // -A^{-1}; launch_extract_owned reads them.  work: count x 3 x n x 64 and
 // dinv: count x 64 x 64 doubles of workspace.
 void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv, hipStream_t s);
-constexpr int kGjNb = 64;  // block width of the batched inversion
+constexpr int kGjNb = 128;  // block width of the batched inversion
 // full: every row of the inverse (g.nown = nloc, the summed combination)
 template <typename T>
 void launch_extract_owned(const double* mats, int count, BoxGeom g, T* out, hipStream_t s, bool full = false);

@@ -173,7 +173,7 @@ class Solver final : public SolverBase {
   // and its wall time goes to stderr (a measurement aid; it serialises the
   // phases).
   void build_all(hipStream_t s) {
-    const bool timed = !dry_run() && std::getenv("IBMG_SETUP_TIMES") != nullptr;
+    const bool timed = std::getenv("IBMG_SETUP_TIMES") != nullptr;
     auto t = std::chrono::steady_clock::now();
     auto mark = [&](const char* what) {
       if (!timed) return;
@@ -198,6 +198,10 @@ class Solver final : public SolverBase {
   // structure's device arrays, the coarsest inverse and the set-up's slice
   // buffer), leaving the workspace as it was right after alloc_fixed.
   void release_dependent() {
+    if (coarse_aug_.n) {   // a set-up that stopped before joining the coarsest inversion
+      if (side_) IBMG_HIP(hipStreamSynchronize(side_));
+      coarse_aug_.release();
+    }
     levels_.clear();
     for (DBuf<int>* b : {&d_adj_ptr_, &d_adj_nbr_, &d_ends_, &d_order_}) b->release();
     for (DBuf<double>* b : {&d_adj_k_, &d_X_, &d_adj_k2_, &d_adj_kap_, &d_adj_rest_, &d_gblocks_, &inv0_, &tpart_,
@@ -235,6 +239,13 @@ class Solver final : public SolverBase {
   }
 
   ~Solver() override {
+    if (est_ev_) (void)hipEventDestroy(est_ev_);
+    if (side_) {
+      (void)hipStreamSynchronize(side_);
+      (void)hipStreamDestroy(side_);
+      (void)hipEventDestroy(ev_fork_);
+      (void)hipEventDestroy(ev_join_);
+    }
     drop_graph();
     if (gstream_) (void)hipStreamDestroy(gstream_);
     if (pinned_) (void)hipHostFree(pinned_);
@@ -448,7 +459,8 @@ class Solver final : public SolverBase {
     std::atomic<size_t> next{0};
     auto worker = [&]() {
       std::vector<int> stamp(2 * nf_max, -1);
-      std::vector<int> cols;
+      std::vector<int> pstamp(std::max(M_, 1), -1);   // points already taken for this row
+      std::vector<int> cols, pts;
       int tag = -1;
       for (;;) {
         const size_t ti = next++;
@@ -475,16 +487,26 @@ class Solver final : public SolverBase {
         std::vector<int>& out = ccols[ti];
         std::vector<int>& len = clen[ti];
         len.assign(tk.r1 - tk.r0, 0);
+        // the points whose windows the row reaches: each spring-carrying
+        // point in the face's list and its spring neighbours, each taken once
+        auto take = [&](int q) {
+          if (pstamp[q] != tag) {
+            pstamp[q] = tag;
+            pts.push_back(q);
+          }
+        };
         for (size_t r = tk.r0; r < tk.r1; ++r) {
           if (f.sp_ptr[r + 1] == f.sp_ptr[r]) continue;
           ++tag;
           cols.clear();
+          pts.clear();
           for (int e = f.sp_ptr[r]; e < f.sp_ptr[r + 1]; ++e) {
             const int l = f.sp_ent[e] >> 4;
             if (adj_ptr_[l + 1] == adj_ptr_[l]) continue;
-            add_point(l);
-            for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) add_point(adj_nbr_[a]);
+            take(l);
+            for (int a = adj_ptr_[l]; a < adj_ptr_[l + 1]; ++a) take(adj_nbr_[a]);
           }
+          for (int q : pts) add_point(q);
           std::sort(cols.begin(), cols.end());
           out.insert(out.end(), cols.begin(), cols.end());
           len[r - tk.r0] = (int)cols.size();
@@ -809,10 +831,11 @@ class Solver final : public SolverBase {
     }
     mark("IB rows");
     build_coarse(s);
-    mark("coarsest");
+    mark("coarsest (queued)");
     if (d_.smoother == IBMG_RAS || d_.smoother == IBMG_RMS) build_boxes(s);
     if (d_.smoother == IBMG_SC)
       for (int l = 1; l <= L_; ++l) sc_numeric(levels_[l], s);
+    join_coarse(s);
     mark("smoother data");
   }
 
@@ -962,10 +985,29 @@ class Solver final : public SolverBase {
       IBMG_HIP(hipStreamSynchronize(s));
       return;
     }
-    launch_coarse_invert(aug.p, nn, 1, 0, s);
+    // The inversion is one work-group's latency-bound loop: it runs on a
+    // second stream (default priority) beside the box inversions and is
+    // joined by join_coarse before anything reads the inverse.
     inv0_.alloc((size_t)n0_ * n0_);
-    launch_coarse_extract(aug.p, nn, n0_, inv0_.p, s);
-    IBMG_HIP(hipStreamSynchronize(s));
+    if (!dry_run() && !side_) {
+      IBMG_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+      IBMG_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+      IBMG_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+    }
+    IBMG_HIP(hipEventRecord(ev_fork_, s));
+    IBMG_HIP(hipStreamWaitEvent(side_, ev_fork_, 0));
+    launch_coarse_invert(aug.p, nn, 1, 0, side_);
+    launch_coarse_extract(aug.p, nn, n0_, inv0_.p, side_);
+    IBMG_HIP(hipEventRecord(ev_join_, side_));
+    coarse_aug_ = std::move(aug);
+  }
+
+  // The caller's stream waits for the coarsest inversion; its work matrix
+  // is then released (later work on the stream is ordered after the join).
+  void join_coarse(hipStream_t s) {
+    if (!coarse_aug_.n) return;
+    IBMG_HIP(hipStreamWaitEvent(s, ev_join_, 0));
+    coarse_aug_.release();
   }
 
   // the coarsest inverse from the caller's inverted copy of aug0_
@@ -1021,12 +1063,16 @@ class Solver final : public SolverBase {
       ids[l].upload(lev.uniq, s);
       for (int u = 0; u < lev.n_unique; ++u) groups[lev.g.nloc].push_back({l, u});
     }
-    const size_t budget = (size_t)8 << 30;
+    // matrices of one size are inverted together, at most 10 GiB of them at
+    // a time, split into equal batches
+    const size_t budget = (size_t)10 << 30;
     for (auto& grp : groups) {
       const int n = grp.first;
       const auto& items = grp.second;
       const size_t per = ((size_t)n * n + 3 * (size_t)n * kGjNb + (size_t)kGjNb * kGjNb) * sizeof(double);
-      const int batch = (int)std::min<size_t>({items.size(), std::max<size_t>(1, budget / per), (size_t)512});
+      const size_t cap = std::min<size_t>(std::max<size_t>(1, budget / per), 512);
+      const size_t nbatch = (items.size() + cap - 1) / cap;
+      const int batch = (int)((items.size() + nbatch - 1) / nbatch);
       DBuf<double> mats((size_t)batch * n * n), work(3 * (size_t)batch * n * kGjNb),
           dinv((size_t)batch * kGjNb * kGjNb);
       for (size_t b0 = 0; b0 < items.size(); b0 += batch) {
@@ -1479,7 +1525,8 @@ class Solver final : public SolverBase {
     const double target = o.rtol * bnorm;
     int its = 0, restarts = 0, vcycles = 0;
     bool converged = false;
-    double est = bnorm;
+    double est = bnorm, prev_est = 0.0;
+    if (!est_ev_) IBMG_HIP(hipEventCreateWithFlags(&est_ev_, hipEventDisableTiming));
     while (its < o.max_it) {
       double* V0 = Vo_.p;
       op<double>(L_, x, V0, bp_.p, trans, Fd_.p, s);
@@ -1491,18 +1538,36 @@ class Solver final : public SolverBase {
       launch_fill<double>(g_.p, 0.0, (size_t)o.restart + 2, s);
       IBMG_HIP(hipMemcpyAsync(g_.p, osc_.p + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
       int k = 0;
+      bool queued = false;   // z_k's V-cycle already queued by the previous iteration
       for (; k < o.restart && its < o.max_it;) {
         double* vk = Vo_.p + (size_t)k * n;
         double* zk = Zo_.p + (size_t)k * n;
         double* t = Vo_.p + (size_t)(k + 1) * n;
-        vcycle(vk, zk, s);
+        if (!queued) vcycle(vk, zk, s);
+        queued = false;
         ++vcycles;
         op<double>(L_, zk, t, nullptr, trans, Fd_.p, s);
         double* hcol = Ho_.p + (size_t)k * ldh;
         orthogonalise_outer(Vo_.p, k + 1, n, t, hcol, gs_nblk, s);
         launch_scale_red<double>(t, t, n, opart_.p, gs_nblk, hcol + k + 1, s);
         launch_givens(Ho_.p, ldh, k, cs_.p, sn_.p, g_.p, osc_.p + 1, s);
-        est = read_scalar(osc_.p + 1, s);
+        // The estimate is read on the host after this iteration's work.
+        // While the last two estimates say that even one more step at their
+        // rate would stay above the target, the next iteration's V-cycle
+        // (its input, the normalised t, is already queued) is queued before
+        // the host waits, so the device does not idle through the read.  A
+        // wrong guess leaves one unused V-cycle behind the solve's tail; it
+        // is not counted in vcycles.
+        IBMG_HIP(hipMemcpyAsync(pinned_, osc_.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        IBMG_HIP(hipEventRecord(est_ev_, s));
+        const double rate = prev_est > 0.0 ? std::min(1.0, est / prev_est) : 1.0;
+        if (k + 1 < o.restart && its + 1 < o.max_it && its >= 2 && est * rate * rate > target) {
+          vcycle(t, Zo_.p + (size_t)(k + 1) * n, s);
+          queued = true;
+        }
+        IBMG_HIP(hipEventSynchronize(est_ev_));
+        prev_est = est;
+        est = pinned_[0];
         ++k;
         ++its;
         push_hist(est / bnorm);
@@ -1786,6 +1851,10 @@ class Solver final : public SolverBase {
   DBuf<double> vin_, vout_;
   DBuf<double> tpart_;   // slice sums of the IB-row values on coarse levels
   std::vector<std::pair<int, int>> int_forms_;   // per level: interior boxes when timed, the form picked
+  hipEvent_t est_ev_ = nullptr;   // the outer loop's estimate copy
+  hipStream_t side_ = nullptr;    // the coarsest inversion beside the box inversions
+  hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+  DBuf<double> coarse_aug_;       // its work matrix until the join
   bool defer_coarse_ = false;   // a member of a batch: the batch inverts the coarsest system
   bool valid_ = true;
   int nn0_ = 0;          // size of the bordered coarsest system

@@ -95,6 +95,7 @@ def main():
                                       avg_ms=t["ms"], alg_bytes=t["bytes"], gbs=t["bytes"] / t["ms"] / 1e6)),
                       flush=True)
             g.close()
+        copy_calibration(a.copy_mib, a.reps)
         return
 
     wl = W.annulus_512(N=a.N)

@@ -14,6 +14,9 @@ configuration the benchmark runs (default handles, V-cycle graphs on).
     GPU's z against a dense LU solve of that box's local matrix, for boxes
     with IB rows, interior boxes (shared inverse on the matrix cores) and
     boxes that wrap across the periodic edges;
+  - every coarser level as well: its operator (the Galerkin IB term, Sec.
+    3.1) on the whole vector and sampled boxes of its sweep, in both
+    precisions;
   - the V-cycle (Alg. 1) through properties that hold at any size: it is
     deterministic and positively homogeneous, bit for bit (scaling the input
     by 2 scales every intermediate exactly, FGMRES smoothing included);
@@ -162,6 +165,58 @@ def test_a512_schwarz_sweep_sampled_boxes(a512):
         sub = {c: m[p.own_global] for c, m in cl.items()}
         err = assert_classes(z[p.own_global], y[p.own_local], sub, SOLVE_TOL, f"box {k}")
         print(f"  box {k} ib={bool(has_ib[k])} class errors {err}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def a512_levels(a512):
+    """The oracle's operator on every level of the 512 hierarchy (the
+    Galerkin IB term by its literal triple product, Sec. 3.1); no box is
+    factorised here."""
+    wl = a512[0]
+    return hierarchy.build(wl)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_a512_every_level_operator_and_sampled_boxes(a512, a512_levels, prec):
+    """Every level of the benchmark's hierarchy, both precisions: the level
+    operator L_IB^l on the whole vector (per row class, FP64 handle), and
+    the Schwarz sweep (Alg. 2) on sampled boxes of each level (boxes with IB
+    rows, interior boxes, the corner box and the last box) against dense LU
+    solves of the oracle's local matrices.  FP32 handles apply FP32
+    inverses, so their boxes are held to the FP32 bound."""
+    wl, L, IB, g64, g32 = a512
+    g = g64 if prec == "fp64" else g32
+    tol = SOLVE_TOL if prec == "fp64" else 1e-4
+    rng = np.random.default_rng(35)
+    for l, lev in enumerate(a512_levels):
+        cl = level_classes(lev.N, lev.T)
+        if prec == "fp64":
+            w = rng.uniform(-1, 1, lev.n)
+            err = assert_classes(host(g.apply(dev(w), level=l)), lev.L @ w, cl, OPS_TOL, f"level {l} operator")
+            print(f"  level {l} N={lev.N} operator class errors {err}", flush=True)
+        if l == 0:
+            continue
+        parts = patches(lev.N, wl.box, wl.overlap)
+        nv = 2 * lev.N * lev.N
+        ib_rows = np.diff(lev.T.tocsr().indptr) > 0
+        has_ib = np.array([ib_rows[p.idx[p.idx < nv]].any() for p in parts])
+        pick = set()
+        for group in (np.flatnonzero(has_ib), np.flatnonzero(~has_ib)):
+            if group.size:
+                pick |= set(rng.choice(group, min(3, group.size), replace=False).tolist())
+        pick |= {0, len(parts) - 1}
+        r = rng.uniform(-1, 1, lev.n)
+        z = host(g.smoother_apply(l, dev(r)))
+        Lc = lev.L.tocsr()
+        worst = {}
+        for k in sorted(pick):
+            p = parts[k]
+            y = la.lu_solve(la.lu_factor(Lc[p.idx][:, p.idx].toarray()), r[p.idx])
+            sub = {c: m[p.own_global] for c, m in cl.items()}
+            e = assert_classes(z[p.own_global], y[p.own_local], sub, tol, f"level {l} box {k}")
+            for c, v in e.items():
+                worst[c] = max(worst.get(c, 0.0), v)
+        print(f"  level {l} N={lev.N} {prec} boxes {sorted(pick)} worst class errors {worst}", flush=True)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
