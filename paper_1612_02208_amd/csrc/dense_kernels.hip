@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const double* __restrict__ mat
       for (int q = 0; q < 16; ++q) colk[buf][a0 + 8 * q] = v[q];
     }
     __syncthreads();
-    // every LDS read is issued before any arithmetic, and the update is
-    // branch-free, so a pivot costs one round trip to LDS, not sixteen
+    // every LDS read is issued before any arithmetic, so a pivot costs one
+    // round trip to LDS, not sixteen
     const double pk = rowk[buf][k];
     const double rk = rowk[buf][b];
     double ck[16];
@@ -201,13 +201,18 @@ __global__ void __launch_bounds__(1024) k_gj_diag(const double* __restrict__ mat
     for (int q = 0; q < 16; ++q) ck[q] = colk[buf][a0 + 8 * q];
     const double ip = 1.0 / pk;
     const double rip = rk * ip;
+    // the pivot block's FP64 vector work bounds this kernel (one CU per
+    // matrix): the common entries take one FMA, and only row k (held at
+    // q = k / 8 by the threads with a0 = k mod 8) and column k (the threads
+    // of column k) are set apart
+    if (b != k) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int a = a0 + 8 * q;
-      const double gen = v[q] - ck[q] * rip;
-      const double colv = -ck[q] * ip;
-      const double rowv = b == k ? ip : rip;
-      v[q] = a == k ? rowv : (b == k ? colv : gen);
+      for (int q = 0; q < 16; ++q) v[q] = v[q] - ck[q] * rip;
+      if ((k & 7) == a0) v[k >> 3] = rip;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = -ck[q] * ip;
+      if ((k & 7) == a0) v[k >> 3] = ip;
     }
   }
 #pragma unroll
@@ -342,8 +347,11 @@ __global__ void __launch_bounds__(256) k_sw_scale(const double* __restrict__ din
 
 // S_IJ <- S_IJ - E_I C_J^T over the kept tiles I >= J outside K (tiles K0
 // and K0 + 1); work-group p takes the p-th tile of the lower triangle in
-// row order.
-__global__ void __launch_bounds__(256) k_sw_update(double* __restrict__ mats, int n, int kb,
+// row order.  Eight waves per tile, each a 32 x 16 block (two 16 x 16 MFMA
+// tiles), so four waves share each SIMD and hide one another's waits; the
+// reduction runs in chunks of 32 through LDS, the next chunk's values
+// loading into registers during the current chunk's MFMA steps.
+__global__ void __launch_bounds__(512) k_sw_update(double* __restrict__ mats, int n, int kb,
                                                    const double* __restrict__ work) {
   const int p = blockIdx.x;
   int I = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
@@ -355,34 +363,62 @@ __global__ void __launch_bounds__(256) k_sw_update(double* __restrict__ mats, in
   const int I0 = I * 64, J0 = J * 64;
   double* A = mats + (size_t)blockIdx.y * n * n;
   const double* Ct = work + (size_t)blockIdx.y * 3 * n * GJ_NB + (size_t)n * GJ_NB;
-  const double* E = Ct + (size_t)n * GJ_NB;
+  const double* E = Ct + (size_t)n * GJ_NB + (size_t)I0 * GJ_NB;
+  const int xrows = n - I0 < 64 ? n - I0 : 64;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;
+  const int wr = wave & 1, wc = wave >> 1, kq = lane >> 4, ln = lane & 15;   // rows 32 wr, columns 16 wc
   // the tile's old values load first, so their trip from memory overlaps the
   // product (no work-group of this launch writes another's tile, E or C^T)
-  double old[2][2][4];
+  double old[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int v = 0; v < 4; ++v) {
+      const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
+      const int j = J0 + 16 * wc + ln;
+      old[a][v] = (i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
+    }
+  Mfma<double>::acc_t acc[2];
+  acc[0] = acc[1] = Mfma<double>::acc_t{0, 0, 0, 0};
+  double xr[4], yr[4];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
-        const int j = J0 + 32 * wc + 16 * b + ln;
-        old[a][b][v] = (i < n && j < n) ? A[(size_t)i * n + j] : 0.0;
-      }
-  Mfma<double>::acc_t acc[2][2];
-  gj_tile_product(sm, acc, E + (size_t)I0 * GJ_NB, n - I0 < 64 ? n - I0 : 64, Ct, n, GJ_NB, n, J0);
+    for (int q = 0; q < 4; ++q) {
+      const int t = tid + 512 * q;
+      const int row = t >> 5, k = t & 31;
+      xr[q] = row < xrows ? E[(size_t)row * GJ_NB + k0 + k] : 0.0;
+      const int ky = t >> 6, c = t & 63, j = J0 + c;
+      yr[q] = j < n ? Ct[(size_t)(k0 + ky) * n + j] : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < GJ_NB; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = tid + 512 * q;
+      sm.Xs[t & 31][t >> 5] = xr[q];
+      sm.Ys[t >> 6][t & 63] = yr[q];
+    }
+    __syncthreads();
+    if (k0 + 32 < GJ_NB) load(k0 + 32);
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int kk = 4 * st + kq;
+      const double a0 = sm.Xs[kk][32 * wr + ln], a1 = sm.Xs[kk][32 * wr + 16 + ln];
+      const double b0 = sm.Ys[kk][16 * wc + ln];
+      acc[0] = Mfma<double>::mma(a0, b0, acc[0]);
+      acc[1] = Mfma<double>::mma(a1, b0, acc[1]);
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
-        const int j = J0 + 32 * wc + 16 * b + ln;
-        if (i < n && j < n) A[(size_t)i * n + j] = old[a][b][v] - acc[a][b][v];
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int i = I0 + 32 * wr + 16 * a + Mfma<double>::row(kq, v);
+      const int j = J0 + 16 * wc + ln;
+      if (i < n && j < n) A[(size_t)i * n + j] = old[a][v] - acc[a][v];
+    }
 }
 
 // Row and column K of the swept matrix, one 64-row tile I per work-group:
@@ -449,7 +485,7 @@ void launch_gj_invert(double* mats, int n, int count, double* work, double* dinv
     IBMG_LAUNCH_CHECK();
     IBMG_KLAUNCH(k_sw_scale, dim3(tiles, count, 2), dim3(256), 0, s, dinv, n, kb, work);
     IBMG_LAUNCH_CHECK();
-    IBMG_KLAUNCH(k_sw_update, dim3(pairs, count), dim3(256), 0, s, mats, n, kb, work);
+    IBMG_KLAUNCH(k_sw_update, dim3(pairs, count), dim3(512), 0, s, mats, n, kb, work);
     IBMG_LAUNCH_CHECK();
     IBMG_KLAUNCH(k_sw_panel_write, dim3(tiles, count), dim3(256), 0, s, mats, n, kb, work, dinv);
     IBMG_LAUNCH_CHECK();
