@@ -11,8 +11,9 @@ One step = one FP64 solve plus one FP32-smoother solve of the same
 right-hand side, both to 1e-8 (set-up excluded; inputs resident in HBM).
 ``value`` = V-cycles applied in the timed steps / timed wall time.
 
-Also reported: the roofline of the dominant kernel (k_ras_ib<double>, the
-finest level's Schwarz boxes with their own inverse), timed alone with HIP
+Also reported: the roofline of the dominant kernel (k_ras_ib_sym<double>
+with its sums: the finest level's Schwarz boxes with their own inverse,
+streamed from the symmetric storage of their owned rows), timed alone with HIP
 events on the stream it runs on; the other hot kernels, the smoothing step's
 Krylov kernels among them; each solve's true residual under the oracle's
 operator, and at 128^2 (the same structure) the distance of both precisions'
@@ -71,7 +72,7 @@ def parse():
 
 
 def measured_traffic(alg_bytes):
-    """HBM bytes per launch of k_ras_ib<double> from the committed
+    """HBM bytes per launch of the IB-box sweep (k_ras_ib_sym and its sums) from the committed
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes, each scaled by what the
     same counter reads for a plain copy of known size; None when no
     counters are recorded or the kernel source changed since they were."""
@@ -585,10 +586,11 @@ def main():
     vc64e = vc_rate(g64e)
     g64e.close()
 
-    # roofline of the dominant kernel: k_ras_ib<double>, the finest level's
-    # Schwarz boxes with their own inverse (HBM streaming of the owned
-    # inverse rows), launched alone by the library with HIP events on this
-    # stream; the other hot kernels for reference
+    # roofline of the dominant kernel: the finest level's Schwarz boxes with
+    # their own inverse (HBM streaming of the stored owned rows: the lower
+    # owned tiles and every non-owned column, k_ras_ib_sym, with the launch
+    # that adds its row and column sums), launched alone by the library with
+    # HIP events on this stream; the other hot kernels for reference
     kt = g64.kernel_time("ras_ib", -1, a.roofline_reps)
     ras_ms, alg_bytes = kt["ms"], kt["bytes"]
     achieved = alg_bytes / (ras_ms * 1e-3) / 1e9
@@ -652,7 +654,8 @@ def main():
         "fp32_vs_fp64_rel_diff": diff,
         "vcycles_per_s_fp64": vc64, "vcycles_per_s_fp32": vc32, "vcycles_per_s_fp64_no_graph": vc64e,
         "setup_s_fp64": t_setup64, "setup_s_fp32": t_setup32,
-        "roofline": {"bound": "hbm", "kernel": "k_ras_ib<double> (finest level)",
+        "roofline": {"bound": "hbm", "kernel": "k_ras_ib_sym<double> + k_ras_sum (finest level IB boxes, "
+                                               "symmetric storage of their owned rows)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launch_ms": ras_ms, "alg_bytes_per_launch": alg_bytes},

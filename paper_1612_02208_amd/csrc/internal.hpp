@@ -448,11 +448,28 @@ void launch_asm_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* box_
 // 64 x 64 tiles, 128: residuals gathered into xg (at least
 // int_gather_elems(g, n_int) elements) and 64 x 128 tiles; results do not
 // depend on it)
+// Symmetric storage of the IB boxes' owned rows (restricted sweep): chunk c
+// keeps the owned columns of tiles 0..c and every non-owned column, in the
+// permuted local order perm (owned unknowns first, in owned order); the
+// owned columns of later tiles are added as the transposed column sums of
+// the chunks that hold them, through per-box partials.
+struct SymIB {
+  const void* inv;   // T[n_ib * sym_box_stride(g)]
+  const int* perm;   // [nloc]
+  void* part;        // T[n_ib * sym_part_len(g)]
+};
+size_t sym_box_stride(const BoxGeom& g);
+int sym_part_len(const BoxGeom& g);
+template <typename T>
+void launch_extract_sym(const double* mats, int count, BoxGeom g, const int* perm, T* out, hipStream_t s);
+
+// sym != null: the IB boxes run from the symmetric storage (parts & 1),
+// their rows summed with the interior slices in one launch
 template <typename T>
 void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_boxes, int n_ib,
                       const T* shared_inv, const int* int_boxes, int n_int, const int* loc_tab,
                       T* part, hipStream_t s, int parts = 3, bool acc = false, int tb = 32, T* xg = nullptr,
-                      size_t xg_elems = 0);
+                      size_t xg_elems = 0, const SymIB* sym = nullptr);
 size_t int_gather_elems(const BoxGeom& g, int n_int);
 // reduction slices of the interior-box product (part holds ksplit * n_int * nch * 64)
 int ras_interior_ksplit(const BoxGeom& g, int n_int);

@@ -83,6 +83,11 @@ struct Level {
   DBuf<T> inv;            // [n_unique][nch][nloc][64]
   DBuf<T> int_part;       // reduction slices of the interior-box product
   DBuf<T> int_x;          // gathered residuals of the interior boxes (product form 128)
+  // symmetric storage of the IB boxes' owned rows (restricted additive
+  // sweep): the permuted local order, the storage, the per-box partials
+  bool use_sym = false;
+  DBuf<int> d_perm;
+  DBuf<T> inv_sym, sym_part;
   // restricted multiplicative Schwarz: box colours; ib_list and int_list
   // sorted by colour, colour c spanning [ib_off[c], ib_off[c+1]) and
   // [int_off[c], int_off[c+1])
@@ -608,13 +613,17 @@ class Solver final : public SolverBase {
   // Every Schwarz launch goes through here: the slice buffer must hold the
   // launch's column slices (IB boxes) followed by its reduction slices
   // (interior).
+  // sym: the IB boxes (the level's whole list) from the symmetric copy
   void ras_launch(Level<T>& lev, const T* r, T* z, const T* inv, const int* ib, int n_ib, const int* in, int n_int,
-                  hipStream_t s, int parts, bool acc, int tb) {
+                  hipStream_t s, int parts, bool acc, int tb, bool sym = false) {
     require(lev.int_part.n >= ib_part_need(lev.g, (parts & 1) ? n_ib : 0) +
                                    interior_part_need(lev.g, (parts & 2) ? n_int : 0),
             "Schwarz slice buffer too small");
+    require(!sym || (lev.use_sym && n_ib == lev.n_ib), "symmetric IB storage is for the whole IB list");
+    const SymIB sy = sym_of(lev);
     launch_ras_apply<T>(r, z, lev.g, inv, ib, n_ib, lev.inv.p + (size_t)lev.n_ib * box_stride(lev), in, n_int,
-                        lev.d_loc.p, lev.int_part.p, s, parts, acc, tb, lev.int_x.p, lev.int_x.n);
+                        lev.d_loc.p, lev.int_part.p, s, parts, acc, tb, lev.int_x.p, lev.int_x.n,
+                        sym ? &sy : nullptr);
   }
 
   // partial-sum buffers of a level: the reductions' blocks x vectors, and the
@@ -1047,7 +1056,33 @@ class Solver final : public SolverBase {
     // the gathered operand of the 128-box product form, up to 512 MB a level
     const size_t xe = int_gather_elems(g, (int)lev.int_list.size());
     if (!lev.int_list.empty() && xe * sizeof(T) <= ((size_t)512 << 20)) lev.int_x.alloc(xe);
+    // The additive sweep streams the IB boxes' owned rows from a symmetric
+    // copy (lower owned tiles only) where the IB-box kernel runs unsplit:
+    // single systems, whole 64-row chunks.  The chunked copy above stays
+    // for the multiplicative sweep and the batched form.
+    lev.use_sym = d_.smoother == IBMG_RAS && !defer_coarse_ && lev.n_ib > 0 && g.nown % 64 == 0 &&
+                  ras_ib_ksplit(g, lev.n_ib) == 1 && std::getenv("IBMG_NO_SYM") == nullptr;
+    if (lev.use_sym) {
+      std::vector<int> perm;
+      perm.reserve(g.nloc);
+      std::vector<char> owned(g.nloc, 0);
+      const int bb = g.b * g.b, m = g.m;
+      for (int r = 0; r < g.nown; ++r) {
+        const int comp = r / bb, q = r % bb;
+        const int oi = q % g.b + g.o, oj = q / g.b + g.o;
+        const int k = comp == 0 ? oj * (m + 1) + oi : (comp == 1 ? m * (m + 1) + oj * m + oi : 2 * m * (m + 1) + oj * m + oi);
+        perm.push_back(k);
+        owned[k] = 1;
+      }
+      for (int k = 0; k < g.nloc; ++k)
+        if (!owned[k]) perm.push_back(k);
+      lev.d_perm.upload(perm, s);
+      lev.inv_sym.alloc((size_t)lev.n_ib * sym_box_stride(g));
+      lev.sym_part.alloc((size_t)lev.n_ib * sym_part_len(g));
+    }
   }
+
+  SymIB sym_of(Level<T>& lev) { return SymIB{lev.inv_sym.p, lev.d_perm.p, lev.sym_part.p}; }
 
   // The unique box inverses of every Schwarz level: assembled per level,
   // inverted in batches that mix levels whose boxes have the same number of
@@ -1098,6 +1133,11 @@ class Solver final : public SolverBase {
           Level<T>& lev = levels_[l];
           launch_extract_owned<T>(mats.p + slot * n * n, count, lev.g, lev.inv.p + (size_t)u0 * box_stride(lev), s,
                                   lev.sum_mode);
+          // unique indices below n_ib are the IB boxes
+          const int nsym = lev.use_sym ? std::min(count, std::max(0, lev.n_ib - u0)) : 0;
+          if (nsym > 0)
+            launch_extract_sym<T>(mats.p + slot * n * n, nsym, lev.g, lev.d_perm.p,
+                                  lev.inv_sym.p + (size_t)u0 * sym_box_stride(lev.g), s);
         });
       }
       IBMG_HIP(hipStreamSynchronize(s));
@@ -1240,7 +1280,7 @@ class Solver final : public SolverBase {
       return;
     }
     ras_launch(lev, v, z, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, (int)lev.int_list.size(), s, 3, false,
-               lev.int_tb);
+               lev.int_tb, lev.use_sym);
   }
 
   // w <- w + e, e = nu FGMRES iterations (CGS2) on L e = b - L w from e = 0.
@@ -1702,7 +1742,10 @@ class Solver final : public SolverBase {
       const int n_int = (int)lev.int_list.size();
       if (kernel == IBMG_KERNEL_RAS_IB) {
         require(lev.n_ib > 0, "the level has no IB boxes");
-        by = (double)lev.n_ib * ((double)g.nown * g.nloc + g.nloc + g.nown) * ts;
+        // the symmetric copy (as the additive sweep runs it, with the row
+        // sums' launch) streams only its stored rows
+        const double stored = lev.use_sym ? (double)sym_box_stride(g) : (double)g.nown * g.nloc;
+        by = (double)lev.n_ib * (stored + g.nloc + g.nown) * ts;
         fl = 2.0 * lev.n_ib * g.nown * g.nloc;
       } else {
         require(n_int > 0, "the level has no interior boxes");
@@ -1712,7 +1755,7 @@ class Solver final : public SolverBase {
       const int part = kernel == IBMG_KERNEL_RAS_IB ? 1 : 2;
       ms = time_launches([&] {
         ras_launch(lev, lev.r.p, lev.t.p, lev.inv.p, lev.d_ib.p, lev.n_ib, lev.d_int.p, n_int, s, part, false,
-                   lev.int_tb);
+                   lev.int_tb, part == 1 && lev.use_sym);
       }, reps, s);
     } else if (kernel == IBMG_KERNEL_STENCIL) {
       by = 2.0 * (double)n * ts;
