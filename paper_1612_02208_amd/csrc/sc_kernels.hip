@@ -179,77 +179,155 @@ __global__ void __launch_bounds__(1024) k_gs_band(T* x, const T* __restrict__ b,
 // global loads already issued stay in flight across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// A run of small velocity colours with the run's rows in LDS (BandRun):
-// the prologue loads each slot's iterate and its right-hand side minus the
-// outer entries (columns outside the run do not change while it is swept),
-// a group of kBandG lanes per slot, and the run's colour offsets.  Each
-// colour then updates its slots from LDS, a group of kBandG lanes per row;
-// the epilogue stores the slots.  A colour's slots (fewer than
-// kGsBigColour: one pass of the work-group) load their band entries (a
-// wave's loads contiguous in the transposed layout) into registers during
-// the previous colour; the barriers between colours wait on LDS only, so
-// those loads stay in flight across them.  Colours are run-relative: f0..f1
-// ascending, then g0..g1 descending.
+// A lane's value after a DPP move within its row of 16 lanes (CTRL: a
+// quad_perm pattern here).
+template <int CTRL>
+__device__ __forceinline__ double quad_move(double x) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float quad_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+// sum over the kBandG = 4 lanes of a row: lanes 2 apart, then neighbours
 template <typename T>
+__device__ __forceinline__ T quad_sum(T a) {
+  a += quad_move<0x4E>(a);   // quad_perm [2,3,0,1]
+  a += quad_move<0xB1>(a);   // quad_perm [1,0,3,2]
+  return a;
+}
+
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
+// A run of small velocity colours with the run's rows in LDS (BandRun).
+// The prologue loads each slot's iterate and its right-hand side minus the
+// outer entries (columns outside the run do not change while it is swept),
+// a group of kBandG lanes per slot, the loads of four slot passes issued
+// together; and the run's colour offsets.  Each colour then updates its
+// slots from LDS, a group of kBandG lanes per row (a colour has fewer than
+// kGsBigColour rows: one pass of the work-group); the epilogue stores the
+// slots.  Band entries are read S colours ahead into S register stages
+// (KP entry pairs per lane each), every load unconditional (lanes without
+// a row, and steps past the span, read the last valid row), so the loads
+// for the next S - 1 colours stay in flight while a colour is summed and
+// across the barriers, which wait on LDS only.  A stage is refilled right
+// after its colour's update, so its registers are reused in place.  Steps are padded to a
+// multiple of S with empty ones.  Colours are run-relative: f0..f1
+// ascending, then g0..g1 descending.  The sums run in the order of the
+// row's entries per lane, then over lanes 2 apart and neighbours.
+template <typename T, int KP, int S>
 __global__ void __launch_bounds__(1024) k_gs_band_lds(T* x, const T* __restrict__ b, BandView<T> v, int f0, int f1,
                                                       int g0, int g1) {
+  using T2 = typename Pair<T>::type;
   extern __shared__ char smem_raw[];
   T* xl = reinterpret_cast<T*>(smem_raw);
   T* cb = xl + v.nb;
   int* cp = reinterpret_cast<int*>(cb + v.nb);
+  const char* xlb = reinterpret_cast<const char*>(xl);
   const int tid = threadIdx.x;
   const int grp = tid / kBandG, sub = tid % kBandG, ngrp = blockDim.x / kBandG;
   for (int i = tid; i <= v.ncol; i += blockDim.x) cp[i] = v.cptr[i];
-  for (int base = 0; base < v.nb; base += ngrp) {
-    const int i = base + grp;
-    T a = 0;
-    if (i < v.nb)
-      for (int e = v.optr[i] + sub; e < v.optr[i + 1]; e += kBandG) a += v.oval[e] * x[v.ocol[e]];
+  constexpr int U = 4, E = 3;   // slot passes per batch, outer entries per lane before the tail
+  for (int base = 0; base < v.nb; base += U * ngrp) {
+    int lo[U], hi[U], r[U];
 #pragma unroll
-    for (int off = kBandG / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kBandG);
-    if (i < v.nb && sub == 0) {
-      const int r = v.brow[i];
-      cb[i] = b[r] - a;
-      xl[i] = x[r];
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * ngrp + grp;
+      const int ic = i < v.nb ? i : v.nb - 1;
+      lo[u] = v.optr[ic];
+      const int h = v.optr[ic + 1];
+      hi[u] = i < v.nb ? h : lo[u];
+      r[u] = v.brow[ic];
+    }
+    int oc[U][E];
+    T ov[U][E];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int at = lo[u] + sub + kBandG * e;
+        const bool ok = at < hi[u];
+        const int c = v.ocol[ok ? at : 0];
+        const T w = v.oval[ok ? at : 0];
+        oc[u][e] = ok ? c : 0;
+        ov[u][e] = ok ? w : T(0);
+      }
+    T a[U], br[U], xr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      br[u] = b[r[u]];
+      xr[u] = x[r[u]];
+      T xo[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) xo[e] = x[oc[u][e]];
+      a[u] = T(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (lo[u] + sub + kBandG * e < hi[u]) a[u] += ov[u][e] * xo[e];
+      for (int at = lo[u] + sub + kBandG * E; at < hi[u]; at += kBandG) a[u] += v.oval[at] * x[v.ocol[at]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T s2 = quad_sum(a[u]);
+      const int i = base + u * ngrp + grp;
+      if (i < v.nb && sub == 0) {
+        cb[i] = br[u] - s2;
+        xl[i] = xr[u];
+      }
     }
   }
   lds_barrier();
   const int ns = span_steps(f0, f1, g0, g1);
-  const int per = v.stride / kBandG;   // entries per lane, <= kBandK
-  int ent[kBandK];
-  T val[kBandK];
-  int row = -1;
-  T dg = T(1);
-  auto fetch = [&](int k) {
-    row = -1;
-    if (k >= ns) return;
-    const int col = span_colour(k, f0, f1, g0);
-    const int s0 = cp[col], n = cp[col + 1] - s0;
-    if (grp >= n) return;
-    row = s0 + grp;
-    dg = v.bdiag[row];
-    const size_t at = (size_t)s0 * v.stride + (size_t)grp * kBandG + sub;
-    const size_t step = (size_t)n * kBandG;
+  if (ns > 0) {
+    const unsigned* __restrict__ went = v.bent;
+    const T2* __restrict__ wval = reinterpret_cast<const T2*>(v.bval);
+    unsigned w[S][KP];
+    T2 val[S][KP];
+    T dg[S];
+    int s0[S], n[S];
+    auto fetch = [&](int st, int k) {
+      const int col = span_colour(k < ns ? k : ns - 1, f0, f1, g0);
+      const int c0 = cp[col], cn = cp[col + 1] - c0;
+      s0[st] = k < ns ? c0 : 0;
+      n[st] = k < ns ? cn : 0;
+      const int li = grp < cn ? grp : cn - 1;
+      dg[st] = v.bdiag[c0 + li];
+      const size_t at = (size_t)c0 * (v.stride / 2) + (size_t)li * kBandG + sub;
+      const size_t step = (size_t)cn * kBandG;
 #pragma unroll
-    for (int q = 0; q < kBandK; ++q) {
-      ent[q] = q < per ? v.bent[at + q * step] : 0;
-      val[q] = q < per ? v.bval[at + q * step] : T(0);
+      for (int q = 0; q < KP; ++q) {
+        w[st][q] = went[at + q * step];
+        val[st][q] = wval[at + q * step];
+      }
+    };
+
+    // the first stages' loads in stage order, as the loop refills them
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      fetch(st, st);
+      asm volatile("" ::: "memory");
     }
-  };
-  fetch(0);
-  for (int k = 0; k < ns; ++k) {
-    T a = 0;
-    if (row >= 0) {
+    for (int k0 = 0; k0 < ns; k0 += S) {
 #pragma unroll
-      for (int q = 0; q < kBandK; ++q) a += val[q] * xl[ent[q]];
+      for (int st = 0; st < S; ++st) {
+        T a = 0;
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+          a += val[st][q].x * *reinterpret_cast<const T*>(xlb + (w[st][q] & 0xffffu));
+          a += val[st][q].y * *reinterpret_cast<const T*>(xlb + (w[st][q] >> 16));
+        }
+        a = quad_sum(a);
+        const int myrow = grp < n[st] ? s0[st] + grp : -1;
+        if (myrow >= 0 && sub == 0) xl[myrow] += (cb[myrow] - a) / dg[st];
+        fetch(st, k0 + st + S);
+        lds_barrier();
+      }
     }
-#pragma unroll
-    for (int off = kBandG / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kBandG);
-    const int myrow = row;
-    const T mydg = dg;
-    fetch(k + 1);
-    if (myrow >= 0 && sub == 0) xl[myrow] += (cb[myrow] - a) / mydg;
-    lds_barrier();
   }
   for (int i = tid; i < v.nb; i += blockDim.x) x[v.brow[i]] = xl[i];
 }
@@ -284,7 +362,7 @@ void launch_band_values(BandRun<T>& run, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv
                         hipStream_t s) {
   (void)N;
   if (!run.nb) return;
-  const size_t nbe = run.hbent.size(), noe = run.hocol.size(), tot = nbe + noe + run.nb;
+  const size_t nbe = run.hbcode.size(), noe = run.hocol.size(), tot = nbe + noe + run.nb;
   int grid = cdiv(tot, 256);
   if (grid > 4096) grid = 4096;
   IBMG_KLAUNCH((k_band_values<T>), dim3(grid), dim3(256), 0, s, run.bcode.p, run.bval.p, nbe, run.ocode.p,
@@ -350,11 +428,19 @@ void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s) {
         if (rr.cf <= seq[a] && seq[a] <= rr.cl) run = &rr;
     if (run && run->lds) {
       const int nc = run->cl - run->cf + 1;
-      const BandView<T> v{run->nb, nc, run->stride, run->cptr.p, run->brow.p, run->bent.p, run->optr.p,
-                          run->ocol.p, run->bval.p, run->oval.p, run->bdiag.p};
+      const BandView<T> v{run->nb,   nc,          run->stride, run->cptr.p, run->brow.p, run->optr.p,
+                          run->ocol.p, run->bent.p, run->bval.p, run->oval.p, run->bdiag.p};
       const int o = run->cf;
       const size_t lds = 2 * (size_t)run->nb * sizeof(T) + (nc + 1) * sizeof(int);
-      IBMG_KLAUNCH((k_gs_band_lds<T>), dim3(1), dim3(1024), lds, s, x, b, v, f0 - o, f1 - o, g0 - o, g1 - o);
+      const int a0 = f0 - o, a1 = f1 - o, b0 = g0 - o, b1 = g1 - o;
+      switch (run->kp) {
+        case 1: IBMG_KLAUNCH((k_gs_band_lds<T, 1, 4>), dim3(1), dim3(1024), lds, s, x, b, v, a0, a1, b0, b1); break;
+        case 2: IBMG_KLAUNCH((k_gs_band_lds<T, 2, 4>), dim3(1), dim3(1024), lds, s, x, b, v, a0, a1, b0, b1); break;
+        case 3: IBMG_KLAUNCH((k_gs_band_lds<T, 3, 4>), dim3(1), dim3(1024), lds, s, x, b, v, a0, a1, b0, b1); break;
+        case 4: IBMG_KLAUNCH((k_gs_band_lds<T, 4, 3>), dim3(1), dim3(1024), lds, s, x, b, v, a0, a1, b0, b1); break;
+        case 6: IBMG_KLAUNCH((k_gs_band_lds<T, 6, 3>), dim3(1), dim3(1024), lds, s, x, b, v, a0, a1, b0, b1); break;
+        default: IBMG_KLAUNCH((k_gs_band_lds<T, 8, 2>), dim3(1), dim3(1024), lds, s, x, b, v, a0, a1, b0, b1); break;
+      }
     } else if (g.mhat) {
       IBMG_KLAUNCH((k_gs_band_p<T>), dim3(1), dim3(1024), 0, s, x, b, cl.d_ptr.p, cl.d_rows.p, f0, f1, g0, g1, g.N,
                    g.diag, g.dinv, g.ih2);

@@ -42,33 +42,45 @@ constexpr size_t kGsBandLds = 64 << 10;
 // cptr[k+1])).  Each slot's row of A_IB (stencil and IB entries merged by
 // column) is split into band entries (columns that are slots of the run)
 // and outer entries (every other column, constant while the run is swept).
-// Band entries are padded to stride per row (zero entries) and stored per
-// colour transposed: colour k's rows (slots s0 .. s0 + n - 1) hold entry
-// q * kBandG + g of local row li at s0 * stride + (q * n + li) * kBandG + g,
-// so the lanes of a wave (consecutive rows, kBandG lanes each) read
-// consecutive addresses.  Entry codes: (IB index + 1) * 4 + stencil kind (0
-// none, 1 diagonal alpha + 4 beta, 2 neighbour -beta), the IB index running
-// over the u rows' Galerkin entries, then the v rows'; the values are formed
-// on the device from the level's coefficients and Galerkin rows.
+// A row's band entries go to kBandG lanes, entry e to lane e % kBandG as
+// its entry q = e / kBandG; each lane holds kp pairs (q = 2p, 2p + 1), so
+// rows are padded (zero entries) to stride = 2 kBandG kp.  Storage is per
+// colour and transposed: colour k's rows (slots s0 .. s0 + n - 1) keep pair
+// p of lane g of local row li at word s0 * stride / 2 + (p * n + li) *
+// kBandG + g, so the lanes of a wave (consecutive rows, kBandG lanes each)
+// read consecutive words.  A word of bent holds the two entries' columns as
+// LDS byte offsets (slot * sizeof(T)), 16 bits each, low half first; bval
+// holds the two values at 2 word and 2 word + 1.  Entry codes (in bval's
+// order): (IB index + 1) * 4 + stencil kind (0 none, 1 diagonal alpha + 4
+// beta, 2 neighbour -beta), the IB index running over the u rows' Galerkin
+// entries, then the v rows'; the values are formed on the device from the
+// level's coefficients and Galerkin rows.
 template <typename T>
 struct BandRun {
-  int cf = 0, cl = 0, nb = 0, stride = 0, nnz_u = 0;
+  int cf = 0, cl = 0, nb = 0, stride = 0, kp = 0, nnz_u = 0;
   bool lds = false;
-  std::vector<int> hcptr, hbrow, hbent, hbcode, hoptr, hocol, hocode;
-  DBuf<int> cptr, brow, bent, bcode, optr, ocol, ocode;
+  std::vector<int> hcptr, hbrow, hbcode, hoptr, hocol, hocode;
+  std::vector<unsigned> hbent;
+  DBuf<int> cptr, brow, bcode, optr, ocol, ocode;
+  DBuf<unsigned> bent;
   DBuf<T> bval, oval, bdiag;
 };
 
 template <typename T>
 struct BandView {
   int nb, ncol, stride;
-  const int *cptr, *brow, *bent, *optr, *ocol;
+  const int *cptr, *brow, *optr, *ocol;
+  const unsigned* bent;
   const T *bval, *oval, *bdiag;
 };
 
-// band kernel shape: lanes per row, and padded entries a lane holds
+// band kernel shape: lanes per row, and the most padded entries a lane holds
 constexpr int kBandG = 4;
 constexpr int kBandK = 16;
+
+// entry pairs per lane of the band kernel's forms (the smallest that holds
+// a run's longest row is used)
+constexpr int kBandPairs[] = {1, 2, 3, 4, 6, 8};
 
 struct ColourLists;
 
@@ -232,32 +244,41 @@ void build_band_runs(const ColourLists& cl, const std::vector<int>& tptr_u, cons
     for (int i = 0; i < run.nb; ++i) slot[run.hbrow[i]] = -1;
     size_t longest = 1;
     for (const auto& bi : band) longest = std::max(longest, bi.size());
-    run.stride = (int)((longest + kBandG - 1) / kBandG * kBandG);
-    run.lds = run.stride <= kBandG * kBandK &&
+    const int pairs = (int)((longest + 2 * kBandG - 1) / (2 * kBandG));
+    run.kp = 0;
+    for (int kp : kBandPairs)
+      if (!run.kp && kp >= pairs) run.kp = kp;
+    bool nonempty = true;
+    for (int k = 0; k + 1 < (int)run.hcptr.size(); ++k) nonempty = nonempty && run.hcptr[k + 1] > run.hcptr[k];
+    run.lds = run.kp > 0 && nonempty && (size_t)run.nb * sizeof(T) < 65536 &&
               2 * (size_t)run.nb * sizeof(T) + (run.hcptr.size() + 1) * sizeof(int) <= kGsBandLds;
+    if (!run.kp) run.kp = kBandK / 2;
+    run.stride = 2 * kBandG * run.kp;
     run.nnz_u = (int)tcol_u.size();
-    run.hbent.assign((size_t)run.nb * run.stride, 0);
-    run.hbcode.assign((size_t)run.nb * run.stride, 0);
-    for (int k = 0; k + 1 < (int)run.hcptr.size(); ++k) {
-      const int a0 = run.hcptr[k], n = run.hcptr[k + 1] - a0;
-      for (int li = 0; li < n; ++li) {
-        const auto& bi = band[a0 + li];
-        for (size_t e = 0; e < bi.size(); ++e) {
-          const size_t q = e / kBandG, g = e % kBandG;
-          const size_t at = (size_t)a0 * run.stride + (q * n + li) * kBandG + g;
-          run.hbent[at] = bi[e].first;
-          run.hbcode[at] = bi[e].second;
+    run.hbent.assign(run.lds ? (size_t)run.nb * run.stride / 2 : 0, 0u);
+    run.hbcode.assign(run.lds ? (size_t)run.nb * run.stride : 0, 0);
+    if (run.lds)
+      for (int k = 0; k + 1 < (int)run.hcptr.size(); ++k) {
+        const int a0 = run.hcptr[k], n = run.hcptr[k + 1] - a0;
+        for (int li = 0; li < n; ++li) {
+          const auto& bi = band[a0 + li];
+          for (size_t e = 0; e < bi.size(); ++e) {
+            const size_t q = e / kBandG, g = e % kBandG, pr = q / 2, h = q % 2;
+            const size_t w = (size_t)a0 * run.stride / 2 + (pr * n + li) * kBandG + g;
+            run.hbent[w] |= (unsigned)(bi[e].first * sizeof(T)) << (16 * h);
+            run.hbcode[2 * w + h] = bi[e].second;
+          }
         }
       }
-    }
     run.cptr.upload(run.hcptr, s);
     run.brow.upload(run.hbrow, s);
     run.bent.upload(run.hbent, s);
     run.bcode.upload(run.hbcode, s);
     run.optr.upload(run.hoptr, s);
     run.ocol.upload(run.hocol, s);
+    if (!run.ocol.p) run.ocol.alloc(1);   // the band kernel's prologue reads index 0 of an empty list
     run.ocode.upload(run.hocode, s);
-    run.bval.alloc(std::max<size_t>(run.hbent.size(), 1));
+    run.bval.alloc(std::max<size_t>(run.hbcode.size(), 1));
     run.oval.alloc(std::max<size_t>(run.hocol.size(), 1));
     run.bdiag.alloc(std::max(run.nb, 1));
     c0 = c1 + 1;
