@@ -591,9 +591,10 @@ __host__ __device__ inline size_t sym_chunk_off(const BoxGeom& g, int c) {
 }
 __host__ __device__ inline size_t sym_stride(const BoxGeom& g) { return sym_chunk_off(g, g.nch); }
 size_t sym_box_stride(const BoxGeom& g) { return sym_stride(g); }
-// partials per box: chunk c's 64 row sums, then its 64 c column sums
-__host__ __device__ inline int sym_part_off(int c) { return 64 * c + 32 * c * (c - 1); }
-int sym_part_len(const BoxGeom& g) { return sym_part_off(g.nch); }
+// partials per box, the chunks' columns cut into ks slices: chunk c's 64
+// row sums of each slice, then its 64 c column sums
+__host__ __device__ inline int sym_part_off(int c, int ks) { return 64 * ks * c + 32 * c * (c - 1); }
+int sym_part_len(const BoxGeom& g, int n_ib) { return sym_part_off(g.nch, ras_ib_ksplit(g, n_ib)); }
 
 template <typename T>
 __global__ void k_extract_sym(const double* __restrict__ mats, int count, BoxGeom g, const int* __restrict__ perm,
@@ -757,16 +758,18 @@ __global__ void __launch_bounds__(256) k_ras_ib(const T* __restrict__ r, T* __re
                         blockIdx.y, x, part, acc, cb < ce ? cb : ce, ce, pout);
 }
 
-// IB boxes from the symmetric storage: work-group = (box, 64-row chunk c).
-// R_k r is gathered into LDS in the permuted local order.  The chunk's
-// columns stream in batches of UNR x VEC (16-byte loads, eight in flight
-// per lane), batches dealt to the four waves in turn.  Every column adds
+// IB boxes from the symmetric storage: work-group = (box, 64-row chunk c,
+// column slice).  R_k r is gathered into LDS in the permuted local order.
+// The chunk's stored columns are cut into gridDim.z slices of whole
+// 64-column tiles; a slice's columns stream in batches of UNR x VEC
+// (16-byte loads, eight in flight per lane), batches dealt to the four
+// waves in turn.  Every column adds
 // its entries times x_q to the rows (lane sums, as in k_ras_ib); a column
 // of an earlier owned tile (q < 64 c) also forms its transposed product,
 // the sum over the chunk's rows of M[row][q] x_row, reduced over the lanes
 // of its column phase, which belongs to owned row q of an earlier chunk.
-// The box's partials: the chunk's row sums at sym_part_off(c), its column
-// sums after them.
+// The box's partials: the chunk's row sums per slice at sym_part_off(c,
+// ks), its column sums after them (each column in one slice).
 // Sum over the 16 lanes of a DPP row (every lane of the row ends with the
 // same bits): swap neighbours and pairs within quads, then mirror within
 // halves and within the row, adding after each step.
@@ -802,15 +805,17 @@ __global__ void __launch_bounds__(256) k_ras_ib_sym(const T* __restrict__ r, Box
   T* xs = reinterpret_cast<T*>(smem_raw);
   T* red = xs + ((g.nloc + 3) & ~3);   // 4 waves x 64 row sums
   T* tcol = red + 256;                 // the chunk's 64 c column sums
-  const int slot = blockIdx.x, c = blockIdx.y, pid = boxes[slot];
+  const int slot = blockIdx.x, c = blockIdx.y, sl = blockIdx.z, ks = gridDim.z, pid = boxes[slot];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cph = lane / LPC, rl = (lane % LPC) * VEC;
   const int nq = 64 * (c + 1), ntr = 64 * c, ncol = nq + (g.nloc - g.nown);
+  const int cs = ((ncol + ks - 1) / ks + 63) / 64 * 64;
+  const int cb = sl * cs < ncol ? sl * cs : ncol, ce = cb + cs < ncol ? cb + cs : ncol;
   const T* Mc = inv + (size_t)slot * sym_stride(g) + sym_chunk_off(g, c) + rl;
   // the wave's first batch of the inverse is issued before the residual
   // gather, so its trip from memory overlaps the gather
-  const int jb0 = wave * B;
-  const bool pre = jb0 + B <= ncol;
+  const int jb0 = cb + wave * B;
+  const bool pre = jb0 + B <= ce;
   V m0[UNR];
   if (pre)
 #pragma unroll
@@ -848,21 +853,21 @@ __global__ void __launch_bounds__(256) k_ras_ib_sym(const T* __restrict__ r, Box
     for (int u = 0; u < UNR; ++u) column(m0[u], jb0 + cph + u * VEC, tr);
     jstart += 4 * B;
   }
-  for (int jb = jstart; jb < ncol; jb += 4 * B) {
-    if (jb + B <= ncol) {
+  for (int jb = jstart; jb < ce; jb += 4 * B) {
+    if (jb + B <= ce) {
       V m[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
         m[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)(jb + cph + u * VEC) * 64));
-      const bool tr = jb + B <= ntr;   // batches never straddle ntr (a multiple of 64)
+      const bool tr = jb + B <= ntr;   // batches never straddle ntr (slices start at multiples of 64)
 #pragma unroll
       for (int u = 0; u < UNR; ++u) column(m[u], jb + cph + u * VEC, tr);
     } else {
       for (int u = 0; u < UNR; ++u) {
         const int q = jb + cph + u * VEC;
-        if (q >= ncol) break;
+        if (q >= ce) break;
         const V m0 = __builtin_nontemporal_load(reinterpret_cast<const V*>(Mc + (size_t)q * 64));
-        column(m0, q, false);   // the tail lies in the non-owned columns
+        column(m0, q, false);   // a partial batch only ends the last slice, in the non-owned columns
       }
     }
   }
@@ -875,9 +880,9 @@ __global__ void __launch_bounds__(256) k_ras_ib_sym(const T* __restrict__ r, Box
 #pragma unroll
     for (int v = 0; v < VEC; ++v) red[wave * 64 + rl + v] = acc[v];
   __syncthreads();
-  T* pb = part + (size_t)slot * sym_part_off(g.nch) + sym_part_off(c);
-  if (tid < 64) pb[tid] = (red[tid] + red[64 + tid]) + (red[128 + tid] + red[192 + tid]);
-  for (int q = tid; q < ntr; q += 256) pb[64 + q] = tcol[q];
+  T* pb = part + (size_t)slot * sym_part_off(g.nch, ks) + sym_part_off(c, ks);
+  if (tid < 64) pb[64 * sl + tid] = (red[tid] + red[64 + tid]) + (red[128 + tid] + red[192 + tid]);
+  for (int q = cb + tid; q < (ce < ntr ? ce : ntr); q += 256) pb[64 * ks + q] = tcol[q];
 }
 
 // z[owned rows] (=, or += with acc) the sum of a split launch's slices, in
@@ -885,13 +890,14 @@ __global__ void __launch_bounds__(256) k_ras_ib_sym(const T* __restrict__ r, Box
 // boxes (pb: ksb slices of nb boxes) of one sweep in one launch; slice sl of
 // box b holds row `row` at p[(sl * n + b) * nch * 64 + row].  A list that was
 // not split has n = 0.
-// The symmetric IB list (ps: partials of ns boxes) comes first: owned row
-// r = 64 c + i is chunk c's row sum i plus the column sums at r of every
-// later chunk, added in chunk order.
+// The symmetric IB list (ps: partials of ns boxes, kss column slices) comes
+// first: owned row r = 64 c + i is chunk c's row sums i of its slices, in
+// slice order, plus the column sums at r of every later chunk, added in
+// chunk order.
 template <typename T>
 __global__ void k_ras_sum(const T* __restrict__ pa, const int* __restrict__ ba, int na, int ksa,
                           const T* __restrict__ pb, const int* __restrict__ bb, int nb, int ksb,
-                          const T* __restrict__ ps, int ns, T* __restrict__ z, BoxGeom g, bool acc) {
+                          const T* __restrict__ ps, int ns, int kss, T* __restrict__ z, BoxGeom g, bool acc) {
   const int nown_pad = g.nch * 64;
   const size_t t0 = (size_t)ns * g.nown;
   const size_t ta = (size_t)na * g.nown, tot = t0 + ta + (size_t)nb * g.nown;
@@ -899,9 +905,11 @@ __global__ void k_ras_sum(const T* __restrict__ pa, const int* __restrict__ ba, 
     if (t < t0) {
       const int b = (int)(t / g.nown), row = (int)(t % g.nown);
       const int cr = row >> 6;
-      const T* pp = ps + (size_t)b * sym_part_off(g.nch);
-      T a = pp[sym_part_off(cr) + (row & 63)];
-      for (int c = cr + 1; c < g.nch; ++c) a += pp[sym_part_off(c) + 64 + row];
+      const T* pp = ps + (size_t)b * sym_part_off(g.nch, kss);
+      const T* pr = pp + sym_part_off(cr, kss) + (row & 63);
+      T a = pr[0];
+      for (int sl = 1; sl < kss; ++sl) a += pr[64 * sl];
+      for (int c = cr + 1; c < g.nch; ++c) a += pp[sym_part_off(c, kss) + 64 * kss + row];
       const size_t o = own_glob(g, ba[b], row);
       z[o] = acc ? z[o] + a : a;
       continue;
@@ -1567,6 +1575,7 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   const bool do_ib = (parts & 1) && n_ib > 0, do_int = (parts & 2) && n_int > 0;
   const bool use_sym = do_ib && sym != nullptr;
   const int ks_ib = do_ib && !use_sym ? ras_ib_ksplit(g, n_ib) : 1;
+  const int ks_sym = use_sym ? ras_ib_ksplit(g, n_ib) : 1;
   const int ks_int = do_int ? ras_interior_ksplit(g, n_int) : 1;
   const size_t nown_pad = (size_t)g.nch * 64;
   T* ipart = part;
@@ -1575,8 +1584,8 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
   if (use_sym) {
     if (g.nown % 64) throw Error(IBMG_ERR_ARG, "symmetric storage needs whole 64-row chunks");
     const size_t lds = ((((size_t)g.nloc + 3) & ~(size_t)3) + 256 + 64 * (size_t)(g.nch - 1)) * sizeof(T);
-    IBMG_KLAUNCH((k_ras_ib_sym<T>), dim3(n_ib, g.nch), dim3(256), lds, s, r, g, static_cast<const T*>(sym->inv),
-                 ib_boxes, sym->perm, spart);
+    IBMG_KLAUNCH((k_ras_ib_sym<T>), dim3(n_ib, g.nch, ks_sym), dim3(256), lds, s, r, g,
+                 static_cast<const T*>(sym->inv), ib_boxes, sym->perm, spart);
     IBMG_LAUNCH_CHECK();
   } else if (do_ib) {
     const size_t lds = (((size_t)g.nloc + 3) & ~(size_t)3) * sizeof(T) + 256 * sizeof(T);
@@ -1616,7 +1625,7 @@ void launch_ras_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* ib_b
     int grid = cdiv((size_t)(na + nb + ns) * g.nown, 256);
     if (grid > 4096) grid = 4096;
     IBMG_KLAUNCH((k_ras_sum<T>), dim3(grid), dim3(256), 0, s, ipart, ib_boxes, na, ks_ib, tpart, int_boxes, nb,
-                       ks_int, spart, ns, z, g, acc);
+                       ks_int, spart, ns, ks_sym, z, g, acc);
     IBMG_LAUNCH_CHECK();
   }
 }

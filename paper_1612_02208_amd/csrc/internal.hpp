@@ -456,10 +456,11 @@ void launch_asm_apply(const T* r, T* z, BoxGeom g, const T* inv, const int* box_
 struct SymIB {
   const void* inv;   // T[n_ib * sym_box_stride(g)]
   const int* perm;   // [nloc]
-  void* part;        // T[n_ib * sym_part_len(g)]
+  void* part;        // T[n_ib * sym_part_len(g, n_ib)]
 };
 size_t sym_box_stride(const BoxGeom& g);
-int sym_part_len(const BoxGeom& g);
+// partials per box (the column slices follow the IB-box kernel's split)
+int sym_part_len(const BoxGeom& g, int n_ib);
 template <typename T>
 void launch_extract_sym(const double* mats, int count, BoxGeom g, const int* perm, T* out, hipStream_t s);
 

@@ -1056,12 +1056,17 @@ class Solver final : public SolverBase {
     // the gathered operand of the 128-box product form, up to 512 MB a level
     const size_t xe = int_gather_elems(g, (int)lev.int_list.size());
     if (!lev.int_list.empty() && xe * sizeof(T) <= ((size_t)512 << 20)) lev.int_x.alloc(xe);
-    // The additive sweep streams the IB boxes' owned rows from a symmetric
-    // copy (lower owned tiles only) where the IB-box kernel runs unsplit:
-    // single systems, whole 64-row chunks.  The chunked copy above stays
-    // for the multiplicative sweep and the batched form.
+    // The additive sweep of a single system streams the IB boxes' owned
+    // rows from a symmetric copy (lower owned tiles only; whole 64-row
+    // chunks) on levels with enough IB boxes: at least 256 (box, chunk)
+    // pairs, the IB-box kernel cut into at most four column slices in FP64,
+    // two in FP32 (measured: below that the symmetric form's uneven slices
+    // and longer sums cost more than its fewer bytes save).  The chunked
+    // copy above stays for the other levels, the multiplicative sweep and
+    // the batched form.
     lev.use_sym = d_.smoother == IBMG_RAS && !defer_coarse_ && lev.n_ib > 0 && g.nown % 64 == 0 &&
-                  ras_ib_ksplit(g, lev.n_ib) == 1 && std::getenv("IBMG_NO_SYM") == nullptr;
+                  lev.n_ib * g.nch >= 256 && ras_ib_ksplit(g, lev.n_ib) <= (sizeof(T) == 8 ? 4 : 2) &&
+                  std::getenv("IBMG_NO_SYM") == nullptr;
     if (lev.use_sym) {
       std::vector<int> perm;
       perm.reserve(g.nloc);
@@ -1078,7 +1083,7 @@ class Solver final : public SolverBase {
         if (!owned[k]) perm.push_back(k);
       lev.d_perm.upload(perm, s);
       lev.inv_sym.alloc((size_t)lev.n_ib * sym_box_stride(g));
-      lev.sym_part.alloc((size_t)lev.n_ib * sym_part_len(g));
+      lev.sym_part.alloc((size_t)lev.n_ib * sym_part_len(g, lev.n_ib));
     }
   }
 
