@@ -19,21 +19,28 @@ static inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 // (A_IB x)_r for a velocity row r = comp * N^2 + j * N + i (x = [u | v]);
 // the IB rows' columns index [u | v], so coupled components need nothing
 // extra.
-template <typename T>
-__device__ __forceinline__ T aib_row(const T* __restrict__ x, int r, int N, const StokesCoef<T>& c,
-                                     const CsrT<T>& tu, const CsrT<T>& tv) {
+// x given by a loader: xv(k) is entry k of [u | v]
+template <typename T, typename Ld>
+__device__ __forceinline__ T aib_row_l(Ld xv, int r, int N, const StokesCoef<T>& c, const CsrT<T>& tu,
+                                       const CsrT<T>& tv) {
   const int NN = N * N;
   const int comp = r >= NN ? 1 : 0;
   const int q = r - comp * NN;
   const int i = q % N, j = q / N;
-  const T* f = x + (size_t)comp * NN;
+  const int o = comp * NN;
   const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
   const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-  const T xc = f[q];
-  T a = c.alpha * xc - c.beta * (f[j * N + im] + f[j * N + ip] + f[jm * N + i] + f[jp * N + i] - T(4) * xc);
+  const T xc = xv(o + q);
+  T a = c.alpha * xc -
+        c.beta * (xv(o + j * N + im) + xv(o + j * N + ip) + xv(o + jm * N + i) + xv(o + jp * N + i) - T(4) * xc);
   const CsrT<T>& t = comp ? tv : tu;
-  for (int k = t.ptr[q]; k < t.ptr[q + 1]; ++k) a += t.val[k] * x[t.col[k]];
+  for (int k = t.ptr[q]; k < t.ptr[q + 1]; ++k) a += t.val[k] * xv(t.col[k]);
   return a;
+}
+template <typename T>
+__device__ __forceinline__ T aib_row(const T* __restrict__ x, int r, int N, const StokesCoef<T>& c,
+                                     const CsrT<T>& tu, const CsrT<T>& tv) {
+  return aib_row_l<T>([x](int k) { return x[k]; }, r, N, c, tu, tv);
 }
 
 // (-M^ p)_ij = (1/h^2) sum over the 4 faces of (p_ij - p_nb) / diag(A_IB)_face
@@ -70,6 +77,22 @@ __global__ void k_gs_init(T* __restrict__ x, const T* __restrict__ b, const int*
                           const T* __restrict__ diag) {
   for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < n; r += (size_t)gridDim.x * blockDim.x)
     x[r] = colour[r] == 0 ? (b[r] - T(0)) / diag[r] : T(0);
+}
+
+// The same for a velocity sweep whose right-hand side is b = G p: each face
+// forms and stores its entry of G p (as k_grad does) before its update.
+template <typename T>
+__global__ void k_grad_init(T* __restrict__ x, T* __restrict__ b, const T* __restrict__ p,
+                            const int* __restrict__ colour, int N, T gi, const T* __restrict__ diag) {
+  const int NN = N * N;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < 2 * NN; r += gridDim.x * blockDim.x) {
+    const int comp = r >= NN ? 1 : 0, q = r - comp * NN;
+    const int i = q % N, j = q / N;
+    const int im = i == 0 ? N - 1 : i - 1, jm = j == 0 ? N - 1 : j - 1;
+    const T g = gi * (p[q] - p[comp ? jm * N + i : j * N + im]);
+    b[r] = g;
+    x[r] = colour[r] == 0 ? (g - T(0)) / diag[r] : T(0);
+  }
 }
 
 // Colours sweep over a span of small colours inside one work-group: colours
@@ -384,7 +407,14 @@ void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s) {
   {
     int grid = cdiv(n, 256);
     if (grid > 4096) grid = 4096;
-    IBMG_KLAUNCH((k_gs_init<T>), dim3(grid), dim3(256), 0, s, x, b, cl.d_colour.p, n, g.diag);
+    if (g.grad_p) {
+      if (g.mhat || n != 2 * (size_t)g.N * g.N || g.grad_out != b)
+        throw Error(IBMG_ERR_ARG, "the fused gradient start is for velocity sweeps on b = G p");
+      IBMG_KLAUNCH((k_grad_init<T>), dim3(grid), dim3(256), 0, s, x, g.grad_out, g.grad_p, cl.d_colour.p, g.N,
+                   g.c.gi, g.diag);
+    } else {
+      IBMG_KLAUNCH((k_gs_init<T>), dim3(grid), dim3(256), 0, s, x, b, cl.d_colour.p, n, g.diag);
+    }
     IBMG_LAUNCH_CHECK();
   }
   std::vector<int> seq;
@@ -523,6 +553,52 @@ __global__ void k_aib_sub(const T* __restrict__ x, T* __restrict__ y, int N, Sto
   y[r] = y[r] - aib_row<T>(x, r, N, c, tu, tv);
 }
 
+// Chebyshev start with the first residual update: d = theta_inv s, x = d,
+// rc = r - A_IB d, the neighbours' d formed from s as the start forms it
+template <typename T>
+__global__ void k_cheb_init_sub(int N, T theta_inv, const T* __restrict__ sv, T* __restrict__ d, T* __restrict__ x,
+                                const T* __restrict__ r, T* __restrict__ rc, StokesCoef<T> c, CsrT<T> tu,
+                                CsrT<T> tv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * N * N) return;
+  const T di = theta_inv * sv[i];
+  d[i] = di;
+  x[i] = di;
+  rc[i] = r[i] - aib_row_l<T>([=](int k) { return theta_inv * sv[k]; }, i, N, c, tu, tv);
+}
+
+// A velocity iterate whose last Chebyshev step is still to be added:
+// x + (c1 d + c2 s), rounded as k_cheb_step rounds it
+template <typename T>
+__device__ __forceinline__ T cheb_final(const T* __restrict__ x, const T* __restrict__ d, const T* __restrict__ sv,
+                                        T c1, T c2, size_t k) {
+  const T dk = c1 * d[k] + c2 * sv[k];
+  return x[k] + dk;
+}
+
+// out = a D u + b y with u = x + (c1 d + c2 s) formed on the fly (u is not
+// stored); out may be y
+template <typename T>
+__global__ void k_cheb_div(const T* __restrict__ x, const T* __restrict__ d, const T* __restrict__ sv, T c1, T c2,
+                           const T* y, T* out, int N, T gi, T a, T b) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * N) return;
+  const int i = q % N, j = q / N;
+  const int ip = i == N - 1 ? 0 : i + 1, jp = j == N - 1 ? 0 : j + 1;
+  const size_t NN = (size_t)N * N;
+  const T dv = gi * (cheb_final(x, d, sv, c1, c2, (size_t)j * N + ip) - cheb_final(x, d, sv, c1, c2, q) +
+                     cheb_final(x, d, sv, c1, c2, NN + (size_t)jp * N + i) - cheb_final(x, d, sv, c1, c2, NN + q));
+  out[q] = a * dv + (y ? b * y[q] : T(0));
+}
+
+// z = w - (x + (c1 d + c2 s))
+template <typename T>
+__global__ void k_cheb_sub(size_t n, T c1, T c2, const T* __restrict__ sv, const T* __restrict__ d,
+                           const T* __restrict__ x, const T* __restrict__ w, T* __restrict__ z) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    z[i] = w[i] - cheb_final(x, d, sv, c1, c2, i);
+}
+
 // x = frac(k g) - 1/2, g = (sqrt 5 - 1) / 2 (deterministic Arnoldi start vector)
 template <typename T>
 __global__ void k_weyl(T* x, size_t n) {
@@ -575,6 +651,27 @@ void launch_aib_sub(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T
   IBMG_LAUNCH_CHECK();
 }
 template <typename T>
+void launch_cheb_init_sub(int N, T theta_inv, const T* sv, T* d, T* x, const T* r, T* rc, StokesCoef<T> c,
+                          CsrT<T> tu, CsrT<T> tv, hipStream_t s) {
+  IBMG_KLAUNCH((k_cheb_init_sub<T>), dim3(cdiv(2 * (size_t)N * N, 256)), dim3(256), 0, s, N, theta_inv, sv, d, x, r,
+               rc, c, tu, tv);
+  IBMG_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_cheb_div(const T* x, const T* d, const T* sv, T c1, T c2, const T* y, T* out, int N, T gi, T a, T b,
+                     hipStream_t s) {
+  IBMG_KLAUNCH((k_cheb_div<T>), dim3(cdiv((size_t)N * N, 256)), dim3(256), 0, s, x, d, sv, c1, c2, y, out, N, gi,
+               a, b);
+  IBMG_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_cheb_sub(size_t n, T c1, T c2, const T* sv, const T* d, const T* x, const T* w, T* z, hipStream_t s) {
+  int g = cdiv(n, 256);
+  if (g > 4096) g = 4096;
+  IBMG_KLAUNCH((k_cheb_sub<T>), dim3(g), dim3(256), 0, s, n, c1, c2, sv, d, x, w, z);
+  IBMG_LAUNCH_CHECK();
+}
+template <typename T>
 void launch_weyl(T* x, size_t n, hipStream_t s) {
   int g = cdiv(n, 256);
   if (g > 4096) g = 4096;
@@ -593,6 +690,10 @@ void launch_weyl(T* x, size_t n, hipStream_t s) {
   template void launch_weyl<T>(T*, size_t, hipStream_t);                                                     \
   template void launch_cheb_init<T>(size_t, T, const T*, T*, T*, const T*, T*, hipStream_t);                  \
   template void launch_cheb_step<T>(size_t, T, T, const T*, T*, T*, hipStream_t);                             \
+  template void launch_cheb_init_sub<T>(int, T, const T*, T*, T*, const T*, T*, StokesCoef<T>, CsrT<T>, CsrT<T>, \
+                                        hipStream_t);                                                        \
+  template void launch_cheb_div<T>(const T*, const T*, const T*, T, T, const T*, T*, int, T, T, T, hipStream_t); \
+  template void launch_cheb_sub<T>(size_t, T, T, const T*, const T*, const T*, const T*, T*, hipStream_t);      \
   template void launch_aib_sub<T>(const T*, T*, int, StokesCoef<T>, CsrT<T>, CsrT<T>, hipStream_t);
 
 IBMG_INST_SC(double)

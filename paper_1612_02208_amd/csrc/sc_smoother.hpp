@@ -97,6 +97,10 @@ struct GsSweep {
   const T* diag;
   const T* dinv;
   T ih2;
+  // velocity sweep on b = G grad_p: the first colour's launch forms b
+  // (grad_out, the same buffer as b) from the pressure grad_p
+  const T* grad_p = nullptr;
+  T* grad_out = nullptr;
 };
 template <typename T>
 void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s);
@@ -121,6 +125,18 @@ template <typename T>
 void launch_cheb_step(size_t n, T c1, T c2, const T* sv, T* d, T* x, hipStream_t s);
 template <typename T>
 void launch_aib_sub(const T* x, T* y, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, hipStream_t s);
+// Fused forms (the same roundings as the separate launches they replace):
+// d = theta_inv s, x = d, rc = r - A_IB d
+template <typename T>
+void launch_cheb_init_sub(int N, T theta_inv, const T* sv, T* d, T* x, const T* r, T* rc, StokesCoef<T> c,
+                          CsrT<T> tu, CsrT<T> tv, hipStream_t s);
+// out = a D (x + c1 d + c2 s) + b y (the last Chebyshev step folded into D)
+template <typename T>
+void launch_cheb_div(const T* x, const T* d, const T* sv, T c1, T c2, const T* y, T* out, int N, T gi, T a, T b,
+                     hipStream_t s);
+// z = w - (x + c1 d + c2 s)
+template <typename T>
+void launch_cheb_sub(size_t n, T c1, T c2, const T* sv, const T* d, const T* x, const T* w, T* z, hipStream_t s);
 template <typename T>
 void launch_sc_diag(int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv, T ih2, T* diag, T* dinv, T* mdiag,
                     hipStream_t s);
@@ -301,7 +317,7 @@ struct ScLevel {
   std::vector<T> a_c1, a_c2, m_c1, m_c2;
   T a_theta_inv = 0, m_theta_inv = 0;
   // work vectors (velocity: 2 N^2, cells: N^2)
-  DBuf<T> yu, ga, gx, ad, ar, at, as, s, md, mr, mt, ms, ones;
+  DBuf<T> yu, ga, gx, ad, ar, at, as, md, mr, mt, ms, ones;
   DBuf<double> part;
 
   static void cheb_coefs(double lam, int its, T* theta_inv, std::vector<T>& c1, std::vector<T>& c2) {
@@ -319,44 +335,62 @@ struct ScLevel {
     }
   }
 
-  // one symmetric Gauss-Seidel sweep from x = 0 (x is overwritten)
-  void sgs_a(const T* b, T* x, hipStream_t st) {
-    launch_gs_sweep<T>(x, b, GsSweep<T>{&colu, &runs_u, false, N, c, tu, tv, diag.p, dinv.p, ih2}, st);
+  // one symmetric Gauss-Seidel sweep from x = 0 (x is overwritten);
+  // grad_p: b = G grad_p, formed by the sweep's first launch
+  void sgs_a(const T* b, T* x, hipStream_t st, const T* grad_p = nullptr) {
+    GsSweep<T> g{&colu, &runs_u, false, N, c, tu, tv, diag.p, dinv.p, ih2};
+    if (grad_p) {
+      g.grad_p = grad_p;
+      g.grad_out = const_cast<T*>(b);
+    }
+    launch_gs_sweep<T>(x, b, g, st);
   }
   void sgs_m(const T* b, T* x, hipStream_t st) {
     launch_gs_sweep<T>(x, b, GsSweep<T>{&colp, nullptr, true, N, c, tu, tv, mdiag.p, dinv.p, ih2}, st);
   }
 
-  // x = A~^{-1} r (velocity vectors); residual r_k = r - A x kept in ar
-  void a_tilde(const T* r, T* x, hipStream_t st) {
+  // x = A~^{-1} r (velocity vectors); residual r_k = r - A x kept in ar.
+  // grad_p: r = G grad_p is formed by the first sweep (r is its buffer).
+  // defer: the last Chebyshev step is left to the caller's next kernel,
+  // which forms x + (a_c1[its - 2] ad + a_c2[its - 2] as) itself; returns
+  // whether it was left (never with one iteration).
+  bool a_tilde(const T* r, T* x, hipStream_t st, const T* grad_p = nullptr, bool defer = false) {
     const size_t n2 = 2 * (size_t)N * N;
-    sgs_a(r, as.p, st);
-    launch_cheb_init<T>(n2, a_theta_inv, as.p, ad.p, x, r, its > 1 ? ar.p : nullptr, st);
+    sgs_a(r, as.p, st, grad_p);
+    if (its > 1)
+      launch_cheb_init_sub<T>(N, a_theta_inv, as.p, ad.p, x, r, ar.p, c, tu, tv, st);
+    else
+      launch_cheb_init<T>(n2, a_theta_inv, as.p, ad.p, x, r, nullptr, st);
     for (int k = 0; k + 1 < its; ++k) {
-      launch_aib_sub<T>(ad.p, ar.p, N, c, tu, tv, st);
+      if (k > 0) launch_aib_sub<T>(ad.p, ar.p, N, c, tu, tv, st);
       sgs_a(ar.p, as.p, st);
+      if (defer && k + 2 == its) return true;
       launch_cheb_step<T>(n2, a_c1[k], a_c2[k], as.p, ad.p, x, st);
     }
+    return false;
   }
 
   // out = -D A~^{-1} G q (cells)
   void schur_op(const T* q, T* out, hipStream_t st) {
-    launch_grad<T>(q, ga.p, N, c.gi, st);
-    a_tilde(ga.p, gx.p, st);
-    launch_div_comb<T>(gx.p, nullptr, out, N, c.gi, T(-1), T(0), st);
+    if (a_tilde(ga.p, gx.p, st, q, true))
+      launch_cheb_div<T>(gx.p, ad.p, as.p, a_c1[its - 2], a_c2[its - 2], nullptr, out, N, c.gi, T(-1), T(0), st);
+    else
+      launch_div_comb<T>(gx.p, nullptr, out, N, c.gi, T(-1), T(0), st);
   }
 
   // y = M~^{-1} s: Chebyshev on -D A~^{-1} G with right-hand side -s;
-  // residual kept in mr (mr - (-D A~^{-1} G d) = mr + D A~^{-1} G d)
+  // residual kept in mr (mr - (-D A~^{-1} G d) = mr + D A~^{-1} G d).
+  // s_in == nullptr: mr already holds -s.
   void m_tilde(const T* s_in, T* y, hipStream_t st) {
     const size_t n1 = (size_t)N * N;
-    launch_axpby<T>(n1, T(-1), s_in, T(0), nullptr, mr.p, st);
+    if (s_in) launch_axpby<T>(n1, T(-1), s_in, T(0), nullptr, mr.p, st);
     sgs_m(mr.p, ms.p, st);
     launch_cheb_init<T>(n1, m_theta_inv, ms.p, md.p, y, nullptr, nullptr, st);
     for (int k = 0; k + 1 < its; ++k) {
-      launch_grad<T>(md.p, ga.p, N, c.gi, st);
-      a_tilde(ga.p, gx.p, st);
-      launch_div_comb<T>(gx.p, mr.p, mr.p, N, c.gi, T(1), T(1), st);
+      if (a_tilde(ga.p, gx.p, st, md.p, true))
+        launch_cheb_div<T>(gx.p, ad.p, as.p, a_c1[its - 2], a_c2[its - 2], mr.p, mr.p, N, c.gi, T(1), T(1), st);
+      else
+        launch_div_comb<T>(gx.p, mr.p, mr.p, N, c.gi, T(1), T(1), st);
       sgs_m(mr.p, ms.p, st);
       launch_cheb_step<T>(n1, m_c1[k], m_c2[k], ms.p, md.p, y, st);
     }
@@ -369,11 +403,13 @@ struct ScLevel {
   void apply(const T* r, T* z, hipStream_t st) {
     const size_t n1 = (size_t)N * N, n2 = 2 * n1;
     a_tilde(r, yu.p, st);
-    launch_div_comb<T>(yu.p, r + n2, s.p, N, c.gi, T(1), T(1), st);
-    m_tilde(s.p, z + n2, st);
-    launch_grad<T>(z + n2, ga.p, N, c.gi, st);
-    a_tilde(ga.p, gx.p, st);
-    launch_axpby<T>(n2, T(1), yu.p, T(-1), gx.p, z, st);
+    // M~^{-1} takes the negated right-hand side -(r_p + D yu), formed here
+    launch_div_comb<T>(yu.p, r + n2, mr.p, N, c.gi, T(-1), T(-1), st);
+    m_tilde(nullptr, z + n2, st);
+    if (a_tilde(ga.p, gx.p, st, z + n2, true))
+      launch_cheb_sub<T>(n2, a_c1[its - 2], a_c2[its - 2], as.p, ad.p, gx.p, yu.p, z, st);
+    else
+      launch_axpby<T>(n2, T(1), yu.p, T(-1), gx.p, z, st);
   }
 };
 

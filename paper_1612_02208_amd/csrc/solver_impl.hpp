@@ -888,7 +888,7 @@ class Solver final : public SolverBase {
     sc.dinv.alloc(n2);
     sc.mdiag.alloc(n1);
     for (DBuf<T>* b : {&sc.yu, &sc.ga, &sc.gx, &sc.ad, &sc.ar, &sc.at, &sc.as}) b->alloc(n2);
-    for (DBuf<T>* b : {&sc.s, &sc.md, &sc.mr, &sc.mt, &sc.ms, &sc.ones}) b->alloc(n1);
+    for (DBuf<T>* b : {&sc.md, &sc.mr, &sc.mt, &sc.ms, &sc.ones}) b->alloc(n1);
     sc.part.alloc(1024);
     launch_fill<T>(sc.ones.p, T(1), n1, s);
   }
