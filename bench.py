@@ -622,8 +622,7 @@ def main():
         # nu = 2 vectors); at 512^2 their vectors fit the Infinity Cache, so
         # the rates are against HBM peak but the data may come from cache
         for kind, name in (("apply_dots", f"k_apply_dots<{tag}>"), ("upd_dots", f"k_upd_dots<{tag}>"),
-                           ("upd_norm", f"k_upd_norm<{tag}>"), ("scale_red", f"k_scale_red<{tag}>"),
-                           ("combine_ls", f"k_combine_ls<{tag}>")):
+                           ("scale_upd", f"k_scale_upd<{tag}>"), ("combine_ls", f"k_combine_ls<{tag}>")):
             t = g.kernel_time(kind, -1, a.roofline_reps)
             kernels[name] = {"bound": "hbm", "avg_ms": t["ms"], "alg_bytes": t["bytes"],
                              "gbs": t["bytes"] / t["ms"] / 1e6, "frac": t["bytes"] / t["ms"] / 1e6 / HBM_PEAK_GBS}

@@ -335,12 +335,17 @@ ibmg_status ibmg_sc_info(const ibmg_handle* h, int32_t level, double* lam, int32
  *   IBMG_KERNEL_APPLY_DOTS    L_IB^l z with the first Gram-Schmidt pass fused:
  *                             z read, the product written, k vectors read
  *                             ((k + 2) n values)
- *   IBMG_KERNEL_UPD_DOTS      t -= V h, then the second pass's dots: t read and
+ *   IBMG_KERNEL_UPD_DOTS      t -= V h, then the second pass's dots and |t|^2:
+ *                             t read and written, k vectors read ((k + 2) n)
+ *   IBMG_KERNEL_SCALE_UPD     t = (t - V h2) / |t - V h2|, the norm taken as
+ *                             sqrt(|t|^2 - |h2|^2) from those sums: t read and
  *                             written, k vectors read ((k + 2) n)
- *   IBMG_KERNEL_UPD_NORM      t -= V h2, then |t|^2: (k + 2) n
- *   IBMG_KERNEL_SCALE_RED     v = t / |t|: 2 n
  *   IBMG_KERNEL_COMBINE_LS    w += sum_q y_q Z_q after the small least squares:
  *                             k vectors and w read, w written ((k + 2) n)
+ * and two kernels of the outer solve's (and the batched smoothing's) second
+ * pass, timed on the same vectors:
+ *   IBMG_KERNEL_UPD_NORM      t -= V h2, then |t|^2: (k + 2) n
+ *   IBMG_KERNEL_SCALE_RED     v = t / |t|: 2 n
  * Synchronises ``stream``; IBMG_ERR_ARG if the level has no such work. */
 typedef enum {
   IBMG_KERNEL_RAS_IB = 0,
@@ -355,7 +360,8 @@ typedef enum {
   IBMG_KERNEL_UPD_DOTS = 9,
   IBMG_KERNEL_UPD_NORM = 10,
   IBMG_KERNEL_SCALE_RED = 11,
-  IBMG_KERNEL_COMBINE_LS = 12
+  IBMG_KERNEL_COMBINE_LS = 12,
+  IBMG_KERNEL_SCALE_UPD = 13
 } ibmg_kernel;
 ibmg_status ibmg_kernel_time(ibmg_handle* h, int32_t kernel, int32_t level, int32_t reps,
                              ibmg_stream stream, double* avg_ms, double* alg_bytes,

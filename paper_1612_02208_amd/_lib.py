@@ -63,6 +63,7 @@ EXPORTS = [
 KERNEL_RAS_IB, KERNEL_RAS_INTERIOR, KERNEL_STENCIL, KERNEL_RAS_BATCH = 0, 1, 2, 3
 KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_SPREAD, KERNEL_INTERP = 4, 5, 6, 7
 KERNEL_APPLY_DOTS, KERNEL_UPD_DOTS, KERNEL_UPD_NORM, KERNEL_SCALE_RED, KERNEL_COMBINE_LS = 8, 9, 10, 11, 12
+KERNEL_SCALE_UPD = 13
 
 _lib = None
 

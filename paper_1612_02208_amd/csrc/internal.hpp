@@ -371,11 +371,24 @@ template <typename T>
 void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, double* hout,
                       hipStream_t s);
 // npart != null: H[k][k-1] = sqrt(sum of the nnblk partials at npart),
-// stored into H by the kernel
+// stored into H by the kernel.  pass2: npart holds launch_upd_dots_n's
+// partials of the last column instead (its second-pass coefficients and the
+// squared norm before them, k + 1 per block), added to that column inside
+// the kernel
 template <typename T>
 void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, double* H, int ldh,
                        const double* beta, double* yout, hipStream_t s, bool assign = false,
-                       const double* npart = nullptr, int nnblk = 0);
+                       const double* npart = nullptr, int nnblk = 0, bool pass2 = false);
+// launch_upd_dots whose partials also carry |t|^2 of the updated t (k + 1
+// values per block, the norm last; k <= 8)
+template <typename T>
+void launch_upd_dots_n(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
+                       double* hcol, double* pout, hipStream_t s, int nblk_in = 0);
+// from those partials: t = (t - V h2) / |t - V h2| with the norm taken as
+// sqrt(|t|^2 - |h2|^2); hcol[0..k) += h2, hcol[k] = the norm
+template <typename T>
+void launch_scale_upd(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk_in,
+                      double* hcol, hipStream_t s);
 
 // immersed boundary
 void launch_fp_fine(const double* X, int M, int N, int comp, const int* base, const int* mask,

@@ -67,13 +67,15 @@ __device__ void block_dots(const T* __restrict__ V, int k, size_t stride, const 
 }  // namespace
 
 // t -= V h (h from pass-1 partials, stored into hcol by block 0), then the
-// pass-2 partial dots of the updated t.
+// pass-2 partial dots of the updated t.  with_norm (k <= 8): each block's
+// partials also carry |t|^2 of the updated t after its k dots (k + 1 values
+// per block).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict__ V, int k, size_t stride,
                                                        BSeg sg, const double* __restrict__ pin, int nblk_in,
                                                        size_t pstride, double* __restrict__ hcol,
-                                                       size_t hstride, double* __restrict__ pout) {
-  __shared__ double red[32];
+                                                       size_t hstride, double* __restrict__ pout, bool with_norm) {
+  __shared__ double red[36];
   __shared__ double h[64];
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
@@ -89,9 +91,10 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
     // one pass: each basis value feeds the update and then the pass-2 dot
     // of the updated entry; every thread visits its entries in the order
     // block_dots would, so the sums are those of the two-pass form
-    double acc[8];
+    double acc[9];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    double nn = 0.0;
 #pragma unroll 2
     for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
       double vq[8];
@@ -107,8 +110,16 @@ __global__ void __launch_bounds__(kThreads) k_upd_dots(T* t, const T* __restrict
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (q < k) acc[q] += vq[q] * ti;
+      nn += ti * ti;
     }
-    block_sums256<8>(acc, k, red, pout + (size_t)blockIdx.x * k, threadIdx.x);
+    if (with_norm) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        if (q == k) acc[q] = nn;
+      block_sums256<9>(acc, k + 1, red, pout + (size_t)blockIdx.x * (k + 1), threadIdx.x);
+    } else {
+      block_sums256<9>(acc, k, red, pout + (size_t)blockIdx.x * k, threadIdx.x);
+    }
     return;
   }
 #pragma unroll 4
@@ -179,22 +190,55 @@ __global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, BSeg s
     v[i] = (T)((double)t[i] * inv);
 }
 
+// The second Gram-Schmidt pass finished with the normalisation, from
+// k_upd_dots' with_norm partials (h2 = V^T t and |t|^2, k + 1 per block):
+// t2 = t - V h2, whose norm is sqrt(|t|^2 - |h2|^2) (t2 is orthogonal to the
+// orthonormal V), and t = t2 / |t2| (0 on an exact breakdown); block 0 adds
+// h2 into hcol[0..k) and stores |t2| into hcol[k].
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scale_upd(T* t, const T* __restrict__ V, int k, size_t stride,
+                                                        size_t n, const double* __restrict__ pin, int nblk_in,
+                                                        double* __restrict__ hcol) {
+  __shared__ double red[32];
+  __shared__ double h[64];
+  reduce_partials(pin, nblk_in, k + 1, h, red);
+  double hh = 0.0;
+  for (int q = 0; q < k; ++q) hh += h[q] * h[q];
+  const double r2 = h[k] - hh;
+  const double d = r2 > 0.0 ? sqrt(r2) : 0.0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < k) hcol[threadIdx.x] += h[threadIdx.x];
+    if (threadIdx.x == 0) hcol[k] = d;
+  }
+  const double inv = d != 0.0 ? 1.0 / d : 0.0;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    double a = (double)t[i];
+    for (int q = 0; q < k; ++q) a -= h[q] * (double)V[(size_t)q * stride + i];
+    t[i] = (T)((double)(T)a * inv);
+  }
+}
+
 // Least squares min || beta e1 - H y || ((k+1) x k Hessenberg, column-major,
 // leading dimension ldh) by Givens rotations in every block, then
 // x += sum_q y_q Z_q (assign: x = sum_q y_q Z_q, the same bits as adding to
 // a zeroed x); block 0 stores y.  npart != null: the last subdiagonal entry
 // H[k][k-1] is the square root of the nnblk partial sums there (reduced as
-// k_scale_red reduces them; block 0 stores it into H).
+// k_scale_red reduces them; block 0 stores it into H).  pass2: npart holds
+// instead k_upd_dots' with_norm partials of the last column (h2 and |t|^2,
+// k + 1 per block): the column gains h2 and its subdiagonal entry is
+// sqrt(|t|^2 - |h2|^2), as k_scale_upd forms it (H itself keeps the first
+// pass's coefficients of that column: no block writes what others read).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, const T* __restrict__ Z, int k,
                                                          size_t stride, BSeg sg, double* __restrict__ H,
                                                          int ldh, size_t hstride, const double* __restrict__ beta,
                                                          double* __restrict__ yout, size_t sstride, bool assign,
                                                          const double* __restrict__ npart, int nnblk,
-                                                         size_t pstride) {
+                                                         size_t pstride, bool pass2) {
   __shared__ double y[16];
   __shared__ double red[32];
   __shared__ double nrm;
+  __shared__ double h2[17];
   const int sy = blockIdx.y;
   if (!seg_on(sg, sy)) return;
   const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
@@ -204,7 +248,13 @@ __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, cons
   beta += sy * sstride;
   yout += sy * sstride;
   double hlast = 0.0;
-  if (npart) {
+  if (npart && pass2) {
+    reduce_partials(npart + sy * pstride, nnblk, k + 1, h2, red);
+    double hh = 0.0;
+    for (int q = 0; q < k; ++q) hh += h2[q] * h2[q];
+    const double r2 = h2[k] - hh;
+    hlast = r2 > 0.0 ? sqrt(r2) : 0.0;
+  } else if (npart) {
     reduce_partials(npart + sy * pstride, nnblk, 1, &nrm, red);
     hlast = sqrt(nrm);
     if (blockIdx.x == 0 && threadIdx.x == 0) H[k + (size_t)(k - 1) * ldh] = hlast;
@@ -214,6 +264,8 @@ __global__ void __launch_bounds__(kThreads) k_combine_ls(T* __restrict__ x, cons
     double g[17], cs[16], sn[16];
     for (int j = 0; j < k; ++j)
       for (int i = 0; i <= k; ++i) R[i][j] = H[i + (size_t)j * ldh];
+    if (npart && pass2)
+      for (int i = 0; i < k; ++i) R[i][k - 1] += h2[i];
     if (npart) R[k][k - 1] = hlast;
     for (int i = 0; i <= k; ++i) g[i] = 0.0;
     g[0] = beta[0];
@@ -266,7 +318,7 @@ void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys
                        int nblk_in) {
   if (nsys <= 0) return;
   IBMG_KLAUNCH((k_upd_dots<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
-                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout);
+                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout, false);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -297,7 +349,7 @@ void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int ns
   if (nsys <= 0) return;
   if (k < 1 || k > 16) throw Error(IBMG_ERR_ARG, "the smoothing least squares takes 1..16 columns");
   IBMG_KLAUNCH((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
-                     sg, H, ldh, hstride, beta, yout, sstride, assign, npart, nnblk, pstride);
+                     sg, H, ldh, hstride, beta, yout, sstride, assign, npart, nnblk, pstride, false);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -322,8 +374,33 @@ void launch_scale_red(const T* t, T* v, size_t n, const double* pin, int nblk, d
 template <typename T>
 void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, double* H, int ldh,
                        const double* beta, double* yout, hipStream_t s, bool assign, const double* npart,
-                       int nnblk) {
-  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign, npart, nnblk, 0);
+                       int nnblk, bool pass2) {
+  if (!pass2) {
+    launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign, npart, nnblk, 0);
+    return;
+  }
+  if (k < 1 || k > 16 || !npart) throw Error(IBMG_ERR_ARG, "the smoothing least squares takes 1..16 columns");
+  IBMG_KLAUNCH((k_combine_ls<T>), dim3(stream_blocks(n), 1), dim3(kThreads), 0, s, x, Z, k, stride, seg1(n), H,
+               ldh, (size_t)0, beta, yout, (size_t)0, assign, npart, nnblk, (size_t)0, true);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_upd_dots_n(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
+                       double* hcol, double* pout, hipStream_t s, int nblk_in) {
+  if (k < 1 || k > 8) throw Error(IBMG_ERR_ARG, "the norm-carrying second pass takes 1..8 basis vectors");
+  IBMG_KLAUNCH((k_upd_dots<T>), dim3(nblk, 1), dim3(kThreads), 0, s, t, V, k, stride, seg1(n), pin,
+               nblk_in > 0 ? nblk_in : nblk, (size_t)0, hcol, (size_t)0, pout, true);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_scale_upd(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk_in,
+                      double* hcol, hipStream_t s) {
+  if (k < 1 || k > 8) throw Error(IBMG_ERR_ARG, "the norm-carrying second pass takes 1..8 basis vectors");
+  IBMG_KLAUNCH((k_scale_upd<T>), dim3(stream_blocks(n)), dim3(kThreads), 0, s, t, V, k, stride, n, pin, nblk_in,
+               hcol);
+  IBMG_LAUNCH_CHECK();
 }
 
 #define IBMG_INST_KRY(T)                                                                               \
@@ -333,7 +410,11 @@ void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, double*
                                    double*, hipStream_t, int, bool);                                   \
   template void launch_scale_red<T>(const T*, T*, size_t, const double*, int, double*, hipStream_t);   \
   template void launch_combine_ls<T>(T*, const T*, int, size_t, size_t, double*, int, const double*,   \
-                                     double*, hipStream_t, bool, const double*, int);                  \
+                                     double*, hipStream_t, bool, const double*, int, bool);            \
+  template void launch_upd_dots_n<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,   \
+                                     double*, hipStream_t, int);                                       \
+  template void launch_scale_upd<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,    \
+                                    hipStream_t);                                                      \
   template void launch_upd_dots_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
                                      double*, size_t, double*, hipStream_t, int);                      \
   template void launch_upd_norm_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \

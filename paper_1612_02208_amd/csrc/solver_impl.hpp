@@ -1341,14 +1341,15 @@ class Solver final : public SolverBase {
       // t = L z with the pass-1 dots V_q . t; pass 2 and the norm follow
       op_dots<T>(l, zk, t, nullptr, V, k + 1, n, pa, lev.F.p, s);
       double* hcol = lev.H.p + (size_t)k * ldh;
-      launch_upd_dots<T>(t, V, k + 1, n, n, pa, nblk, hcol, pb, s, nab);
-      // the last basis vector is never read: only its norm enters H, and
-      // the least-squares kernel takes it from the norm's partial sums
-      const bool last = k + 1 == nu;
-      launch_upd_norm<T>(t, V, k + 1, n, n, pb, nblk, hcol, pa, s, 0, !last);
-      if (!last) launch_scale_red<T>(t, t, n, pa, nblk, hcol + k + 1, s);
+      // pass 2's dots with |t|^2 beside them: t - V h2 is orthogonal to the
+      // orthonormal basis, so its norm is sqrt(|t|^2 - |h2|^2) and the
+      // update, the norm and the normalisation take one more sweep
+      launch_upd_dots_n<T>(t, V, k + 1, n, n, pa, nblk, hcol, pb, s, nab);
+      // the last basis vector is never read: the least-squares kernel takes
+      // its coefficients and norm from these partials
+      if (k + 1 < nu) launch_scale_upd<T>(t, V, k + 1, n, n, pb, nblk, hcol, s);
     }
-    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s, w_zero, pa, nblk);
+    launch_combine_ls<T>(w, Z, nu, n, n, lev.H.p, ldh, beta, lev.scal.p + kScalY, s, w_zero, pb, nblk, true);
   }
 
   // Classical Gram-Schmidt twice against V[0..k): h (first pass + second
@@ -1805,7 +1806,7 @@ class Solver final : public SolverBase {
                                 Uw_.p, s);
         }, reps, s);
       }
-    } else if (kernel >= IBMG_KERNEL_APPLY_DOTS && kernel <= IBMG_KERNEL_COMBINE_LS) {
+    } else if (kernel >= IBMG_KERNEL_APPLY_DOTS && kernel <= IBMG_KERNEL_SCALE_UPD) {
       // one smoothing step's Krylov kernels with the basis at its largest
       // (k = nu vectors): zero first-pass dots leave t as it is, unit
       // partial norms give a unit scale, and a diagonal Hessenberg keeps the
@@ -1830,7 +1831,14 @@ class Solver final : public SolverBase {
         ms = time_launches([&] { op_dots<T>(level, Z, lev.t.p, nullptr, V, k, n, pa, lev.F.p, s); }, reps, s);
       } else if (kernel == IBMG_KERNEL_UPD_DOTS) {
         by = (double)(k + 2) * n * ts;
-        ms = time_launches([&] { launch_upd_dots<T>(t, V, k, n, n, pb, nblk, hcol, pa, s, nab); }, reps, s);
+        ms = time_launches([&] { launch_upd_dots_n<T>(t, V, k, n, n, pb, nblk, hcol, pa, s, nab); }, reps, s);
+      } else if (kernel == IBMG_KERNEL_SCALE_UPD) {
+        // zero second-pass dots and a unit |t|^2 in every block's partials:
+        // t keeps its values and is scaled by the same factor each launch
+        by = (double)(k + 2) * n * ts;
+        launch_fill<double>(pb, 0.0, (size_t)nblk * (k + 1), s);
+        launch_fill<double>(pb + k, 1.0, 1, s);
+        ms = time_launches([&] { launch_scale_upd<T>(t, V, k, n, n, pb, nblk, hcol, s); }, reps, s);
       } else if (kernel == IBMG_KERNEL_UPD_NORM) {
         by = (double)(k + 2) * n * ts;
         ms = time_launches([&] { launch_upd_norm<T>(t, V, k, n, n, pb, nblk, hcol, pa, s); }, reps, s);

@@ -306,15 +306,16 @@ class StokesIB:
         this handle's stream, with its algorithmic bytes and flops per launch.
         kernel: "ras_ib", "ras_interior", "stencil", "restrict", "prolong",
         "spread", "interp", the smoothing step's Krylov kernels "apply_dots",
-        "upd_dots", "upd_norm", "scale_red", "combine_ls" (single handles) or
-        "ras_batch" (batch handles)."""
+        "upd_dots", "scale_upd", "combine_ls", the outer solve's second-pass
+        kernels "upd_norm", "scale_red" (single handles) or "ras_batch"
+        (batch handles)."""
         k = {"ras_ib": _lib.KERNEL_RAS_IB, "ras_interior": _lib.KERNEL_RAS_INTERIOR,
              "stencil": _lib.KERNEL_STENCIL, "ras_batch": _lib.KERNEL_RAS_BATCH,
              "restrict": _lib.KERNEL_RESTRICT, "prolong": _lib.KERNEL_PROLONG,
              "spread": _lib.KERNEL_SPREAD, "interp": _lib.KERNEL_INTERP,
              "apply_dots": _lib.KERNEL_APPLY_DOTS, "upd_dots": _lib.KERNEL_UPD_DOTS,
              "upd_norm": _lib.KERNEL_UPD_NORM, "scale_red": _lib.KERNEL_SCALE_RED,
-             "combine_ls": _lib.KERNEL_COMBINE_LS}[kernel]
+             "combine_ls": _lib.KERNEL_COMBINE_LS, "scale_upd": _lib.KERNEL_SCALE_UPD}[kernel]
         ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._check(self.lib.ibmg_kernel_time(self.h, k, level % self.n_levels, int(reps), _stream(),
                                               ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)))

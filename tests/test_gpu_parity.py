@@ -321,6 +321,28 @@ def test_single_kernel_timing_every_level(pair):
     assert_classes(z, P.mg.smoothers[-1](r), lc(P), SOLVE_TOL, "smoother after timing")
 
 
+def test_krylov_kernel_timing(pair):
+    """ibmg_kernel_time for the smoothing step's Krylov kernels (and the
+    outer solve's second-pass pair) on every level: the basis at its largest
+    (k = max(nu1, nu2) vectors of n = 3 N_l^2), bytes as documented; a solve
+    afterwards still matches the oracle's."""
+    wl, P, G = pair
+    k = max(wl.nu1, wl.nu2)
+    for l in range(1, len(P.levels)):
+        n = P.levels[l].n
+        for kind in ("apply_dots", "upd_dots", "scale_upd", "upd_norm", "combine_ls"):
+            t = G.kernel_time(kind, l, 2)
+            assert t["ms"] > 0 and t["bytes"] == 8.0 * (k + 2) * n, (kind, l)
+        t = G.kernel_time("scale_red", l, 2)
+        assert t["ms"] > 0 and t["bytes"] == 16.0 * n
+    with pytest.raises(Exception):
+        G.kernel_time("scale_upd", 0, 1)
+    b = W.rhs(wl.N, 0)
+    x, _ = G.solve(dev(b), rtol=1e-300, restart=30, max_it=4)
+    xo, _ = krylov.fgmres(P.apply, P.mg, P.project(b), restart=30, rtol=1e-300, max_it=4)
+    assert_classes(host(x), P.project(xo), lc(P), SOLVE_TOL, "FGMRES(30), 4 iterations after Krylov timing")
+
+
 def test_transfer_and_coupling_kernel_timing(pair):
     """ibmg_kernel_time for the transfers on every level and for spreading
     and interpolation on the finest: algorithmic bytes follow the grid sizes
