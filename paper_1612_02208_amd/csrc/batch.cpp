@@ -344,14 +344,15 @@ class BatchSolver final : public BatchBase {
       op(l, zk, t, nullptr, s);
       double* hcol = L.H.p + (size_t)k * ldh;
       launch_dots_b<T>(L.V.p, k + 1, bn, t, sg, ns, L.pa.p, L.pst, L.nblk, s);
-      launch_upd_dots_b<T>(t, L.V.p, k + 1, bn, sg, ns, L.pa.p, L.nblk, L.pst, hcol, hst, L.pb.p, s);
-      // the last basis vector's norm goes straight to the least squares
-      const bool last = k + 1 == nu;
-      launch_upd_norm_b<T>(t, L.V.p, k + 1, bn, sg, ns, L.pb.p, L.nblk, L.pst, hcol, hst, L.pa.p, s, 0, !last);
-      if (!last) launch_scale_red_b<T>(t, t, sg, ns, n, L.pa.p, L.nblk, L.pst, hcol + k + 1, hst, s);
+      // the second pass with |t|^2 beside its dots; one more sweep updates
+      // and normalises (the norm from those sums), none for the last basis
+      // vector, whose coefficients and norm go straight to the least squares
+      launch_upd_dots_b<T>(t, L.V.p, k + 1, bn, sg, ns, L.pa.p, L.nblk, L.pst, hcol, hst, L.pb.p, s, 0, true);
+      if (k + 1 < nu)
+        launch_scale_upd_b<T>(t, L.V.p, k + 1, bn, sg, ns, n, L.pb.p, L.nblk, L.pst, hcol, hst, s);
     }
     launch_combine_ls_b<T>(w, L.Z.p, nu, bn, sg, ns, n, L.H.p, ldh, hst, L.scal.p, L.scal.p + kScalY,
-                           kScalStride, s, false, L.pa.p, L.nblk, L.pst);
+                           kScalStride, s, false, L.pb.p, L.nblk, L.pst, true);
   }
 
   // Alg. 1 on every system: r and z are ragged batch vectors (FP64).

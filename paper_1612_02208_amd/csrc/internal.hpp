@@ -540,10 +540,16 @@ void launch_block_sums_b(const T* a, int N, size_t bs, double* partial, int nblk
 template <typename T>
 void launch_subtract_means_b(T* a, int N, size_t bs, const double* sums, size_t sstride, int nvel, int nsys,
                              hipStream_t s);
+// with_norm: as launch_upd_dots_n (k + 1 partials per block, |t|^2 last)
 template <typename T>
 void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
-                       int nblk_in = 0);
+                       int nblk_in = 0, bool with_norm = false);
+// launch_scale_upd on every active system
+template <typename T>
+void launch_scale_upd_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
+                        const double* pin, int nblk_in, size_t pstride, double* hcol, size_t hstride,
+                        hipStream_t s);
 template <typename T>
 void launch_upd_norm_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
@@ -555,7 +561,7 @@ template <typename T>
 void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
                          double* H, int ldh, size_t hstride, const double* beta, double* yout,
                          size_t sstride, hipStream_t s, bool assign = false, const double* npart = nullptr,
-                         int nnblk = 0, size_t pstride = 0);
+                         int nnblk = 0, size_t pstride = 0, bool pass2 = false);
 template <typename T>
 void launch_coarse_apply_batch(const double* inv, int n0, const T* r, T* z, int nsys, hipStream_t s);
 

@@ -197,10 +197,18 @@ __global__ void __launch_bounds__(kThreads) k_scale_red(const T* t, T* v, BSeg s
 // h2 into hcol[0..k) and stores |t2| into hcol[k].
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_scale_upd(T* t, const T* __restrict__ V, int k, size_t stride,
-                                                        size_t n, const double* __restrict__ pin, int nblk_in,
-                                                        double* __restrict__ hcol) {
+                                                        BSeg sg, const double* __restrict__ pin, int nblk_in,
+                                                        size_t pstride, double* __restrict__ hcol,
+                                                        size_t hstride) {
   __shared__ double red[32];
   __shared__ double h[64];
+  const int sy = blockIdx.y;
+  if (!seg_on(sg, sy)) return;
+  const size_t o = seg_begin(sg, sy), n = seg_len(sg, sy);
+  t += o;
+  V += o;
+  pin += sy * pstride;
+  hcol += sy * hstride;
   reduce_partials(pin, nblk_in, k + 1, h, red);
   double hh = 0.0;
   for (int q = 0; q < k; ++q) hh += h[q] * h[q];
@@ -315,10 +323,12 @@ static int stream_blocks(size_t n) {
 template <typename T>
 void launch_upd_dots_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, const double* pin,
                        int nblk, size_t pstride, double* hcol, size_t hstride, double* pout, hipStream_t s,
-                       int nblk_in) {
+                       int nblk_in, bool with_norm) {
   if (nsys <= 0) return;
+  if (with_norm && (k < 1 || k > 8))
+    throw Error(IBMG_ERR_ARG, "the norm-carrying second pass takes 1..8 basis vectors");
   IBMG_KLAUNCH((k_upd_dots<T>), dim3(nblk, nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
-                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout, false);
+                     nblk_in > 0 ? nblk_in : nblk, pstride, hcol, hstride, pout, with_norm);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -345,11 +355,23 @@ template <typename T>
 void launch_combine_ls_b(T* x, const T* Z, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
                          double* H, int ldh, size_t hstride, const double* beta, double* yout,
                          size_t sstride, hipStream_t s, bool assign, const double* npart, int nnblk,
-                         size_t pstride) {
+                         size_t pstride, bool pass2) {
   if (nsys <= 0) return;
-  if (k < 1 || k > 16) throw Error(IBMG_ERR_ARG, "the smoothing least squares takes 1..16 columns");
+  if (k < 1 || k > 16 || (pass2 && !npart))
+    throw Error(IBMG_ERR_ARG, "the smoothing least squares takes 1..16 columns");
   IBMG_KLAUNCH((k_combine_ls<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, x, Z, k, stride,
-                     sg, H, ldh, hstride, beta, yout, sstride, assign, npart, nnblk, pstride, false);
+                     sg, H, ldh, hstride, beta, yout, sstride, assign, npart, nnblk, pstride, pass2);
+  IBMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_scale_upd_b(T* t, const T* V, int k, size_t stride, BSeg sg, int nsys, size_t nmax,
+                        const double* pin, int nblk_in, size_t pstride, double* hcol, size_t hstride,
+                        hipStream_t s) {
+  if (nsys <= 0) return;
+  if (k < 1 || k > 8) throw Error(IBMG_ERR_ARG, "the norm-carrying second pass takes 1..8 basis vectors");
+  IBMG_KLAUNCH((k_scale_upd<T>), dim3(stream_blocks(nmax), nsys), dim3(kThreads), 0, s, t, V, k, stride, sg, pin,
+               nblk_in, pstride, hcol, hstride);
   IBMG_LAUNCH_CHECK();
 }
 
@@ -375,32 +397,20 @@ template <typename T>
 void launch_combine_ls(T* x, const T* Z, int k, size_t stride, size_t n, double* H, int ldh,
                        const double* beta, double* yout, hipStream_t s, bool assign, const double* npart,
                        int nnblk, bool pass2) {
-  if (!pass2) {
-    launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign, npart, nnblk, 0);
-    return;
-  }
-  if (k < 1 || k > 16 || !npart) throw Error(IBMG_ERR_ARG, "the smoothing least squares takes 1..16 columns");
-  IBMG_KLAUNCH((k_combine_ls<T>), dim3(stream_blocks(n), 1), dim3(kThreads), 0, s, x, Z, k, stride, seg1(n), H,
-               ldh, (size_t)0, beta, yout, (size_t)0, assign, npart, nnblk, (size_t)0, true);
-  IBMG_LAUNCH_CHECK();
+  launch_combine_ls_b<T>(x, Z, k, stride, seg1(n), 1, n, H, ldh, 0, beta, yout, 0, s, assign, npart, nnblk, 0,
+                         pass2);
 }
 
 template <typename T>
 void launch_upd_dots_n(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk,
                        double* hcol, double* pout, hipStream_t s, int nblk_in) {
-  if (k < 1 || k > 8) throw Error(IBMG_ERR_ARG, "the norm-carrying second pass takes 1..8 basis vectors");
-  IBMG_KLAUNCH((k_upd_dots<T>), dim3(nblk, 1), dim3(kThreads), 0, s, t, V, k, stride, seg1(n), pin,
-               nblk_in > 0 ? nblk_in : nblk, (size_t)0, hcol, (size_t)0, pout, true);
-  IBMG_LAUNCH_CHECK();
+  launch_upd_dots_b<T>(t, V, k, stride, seg1(n), 1, pin, nblk, 0, hcol, 0, pout, s, nblk_in, true);
 }
 
 template <typename T>
 void launch_scale_upd(T* t, const T* V, int k, size_t stride, size_t n, const double* pin, int nblk_in,
                       double* hcol, hipStream_t s) {
-  if (k < 1 || k > 8) throw Error(IBMG_ERR_ARG, "the norm-carrying second pass takes 1..8 basis vectors");
-  IBMG_KLAUNCH((k_scale_upd<T>), dim3(stream_blocks(n)), dim3(kThreads), 0, s, t, V, k, stride, n, pin, nblk_in,
-               hcol);
-  IBMG_LAUNCH_CHECK();
+  launch_scale_upd_b<T>(t, V, k, stride, seg1(n), 1, n, pin, nblk_in, 0, hcol, 0, s);
 }
 
 #define IBMG_INST_KRY(T)                                                                               \
@@ -416,14 +426,16 @@ void launch_scale_upd(T* t, const T* V, int k, size_t stride, size_t n, const do
   template void launch_scale_upd<T>(T*, const T*, int, size_t, size_t, const double*, int, double*,    \
                                     hipStream_t);                                                      \
   template void launch_upd_dots_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
-                                     double*, size_t, double*, hipStream_t, int);                      \
+                                     double*, size_t, double*, hipStream_t, int, bool);                \
+  template void launch_scale_upd_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, const double*, int, \
+                                      size_t, double*, size_t, hipStream_t);                           \
   template void launch_upd_norm_b<T>(T*, const T*, int, size_t, BSeg, int, const double*, int, size_t, \
                                      double*, size_t, double*, hipStream_t, int, bool);                \
   template void launch_scale_red_b<T>(const T*, T*, BSeg, int, size_t, const double*, int, size_t,     \
                                       double*, size_t, hipStream_t);                                   \
   template void launch_combine_ls_b<T>(T*, const T*, int, size_t, BSeg, int, size_t, double*, int,     \
                                        size_t, const double*, double*, size_t, hipStream_t, bool,      \
-                                       const double*, int, size_t);
+                                       const double*, int, size_t, bool);
 
 IBMG_INST_KRY(double)
 IBMG_INST_KRY(float)
