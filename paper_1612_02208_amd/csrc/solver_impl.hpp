@@ -236,6 +236,7 @@ class Solver final : public SolverBase {
     for (int l = 1; l <= L_ && !coarse_only; ++l) {
       Level<T>& lev = levels_[l];
       if (lev.inv.n) scan(lev.inv.p, lev.inv.n, ("the box inverses of level " + std::to_string(l)).c_str());
+      if (lev.inv_sym.n) scan(lev.inv_sym.p, lev.inv_sym.n, ("the IB box inverses of level " + std::to_string(l)).c_str());
       if (lev.sc)
         if (!(std::isfinite(lev.sc->lamA) && lev.sc->lamA > 0.0 && std::isfinite(lev.sc->lamM) && lev.sc->lamM > 0.0))
           throw Error(IBMG_ERR_BREAKDOWN, "Schur-complement Chebyshev bound of level " + std::to_string(l) +
@@ -621,9 +622,9 @@ class Solver final : public SolverBase {
             "Schwarz slice buffer too small");
     require(!sym || (lev.use_sym && n_ib == lev.n_ib), "symmetric IB storage is for the whole IB list");
     const SymIB sy = sym_of(lev);
-    launch_ras_apply<T>(r, z, lev.g, inv, ib, n_ib, lev.inv.p + (size_t)lev.n_ib * box_stride(lev), in, n_int,
-                        lev.d_loc.p, lev.int_part.p, s, parts, acc, tb, lev.int_x.p, lev.int_x.n,
-                        sym ? &sy : nullptr);
+    require(sym || !lev.use_sym || !(parts & 1) || n_ib == 0, "the IB boxes of this level are in symmetric storage");
+    launch_ras_apply<T>(r, z, lev.g, inv, ib, n_ib, shared_inv(lev), in, n_int, lev.d_loc.p, lev.int_part.p, s,
+                        parts, acc, tb, lev.int_x.p, lev.int_x.n, sym ? &sy : nullptr);
   }
 
   // partial-sum buffers of a level: the reductions' blocks x vectors, and the
@@ -1052,7 +1053,6 @@ class Solver final : public SolverBase {
                                     ib_part_need(g, lev.ib_off[c + 1] - lev.ib_off[c]));
       if (lev.int_part.n < need) lev.int_part.alloc(need);
     }
-    lev.inv.alloc((size_t)lev.n_unique * box_stride(lev));
     // the gathered operand of the 128-box product form, up to 512 MB a level
     const size_t xe = int_gather_elems(g, (int)lev.int_list.size());
     if (!lev.int_list.empty() && xe * sizeof(T) <= ((size_t)512 << 20)) lev.int_x.alloc(xe);
@@ -1062,8 +1062,9 @@ class Solver final : public SolverBase {
     // pairs, the IB-box kernel cut into at most four column slices in FP64,
     // two in FP32 (measured: below that the symmetric form's uneven slices
     // and longer sums cost more than its fewer bytes save).  The chunked
-    // copy above stays for the other levels, the multiplicative sweep and
-    // the batched form.
+    // copy (lev.inv) serves the other levels, the multiplicative sweep and
+    // the batched form; on a symmetric level it holds the interior boxes'
+    // shared inverse alone.
     lev.use_sym = d_.smoother == IBMG_RAS && !defer_coarse_ && lev.n_ib > 0 && g.nown % 64 == 0 &&
                   lev.n_ib * g.nch >= 256 && ras_ib_ksplit(g, lev.n_ib) <= (sizeof(T) == 8 ? 4 : 2) &&
                   std::getenv("IBMG_NO_SYM") == nullptr;
@@ -1085,9 +1086,16 @@ class Solver final : public SolverBase {
       lev.inv_sym.alloc((size_t)lev.n_ib * sym_box_stride(g));
       lev.sym_part.alloc((size_t)lev.n_ib * sym_part_len(g, lev.n_ib));
     }
+    lev.inv.alloc((size_t)(lev.n_unique - inv_base(lev)) * box_stride(lev));
   }
 
   SymIB sym_of(Level<T>& lev) { return SymIB{lev.inv_sym.p, lev.d_perm.p, lev.sym_part.p}; }
+
+  // first unique box whose owned rows lev.inv holds in chunks (the IB boxes
+  // of a symmetric level live in inv_sym only)
+  static int inv_base(const Level<T>& lev) { return lev.use_sym ? lev.n_ib : 0; }
+  // the interior boxes' shared inverse
+  T* shared_inv(Level<T>& lev) { return lev.inv.p + (size_t)(lev.n_ib - inv_base(lev)) * box_stride(lev); }
 
   // The unique box inverses of every Schwarz level: assembled per level,
   // inverted in batches that mix levels whose boxes have the same number of
@@ -1136,8 +1144,11 @@ class Solver final : public SolverBase {
         launch_gj_invert(mats.p, n, cnt, work.p, dinv.p, s);
         for_runs([&](int l, int u0, int count, size_t slot) {
           Level<T>& lev = levels_[l];
-          launch_extract_owned<T>(mats.p + slot * n * n, count, lev.g, lev.inv.p + (size_t)u0 * box_stride(lev), s,
-                                  lev.sum_mode);
+          const int skip = std::min(count, std::max(0, inv_base(lev) - u0));
+          if (count > skip)
+            launch_extract_owned<T>(mats.p + (slot + skip) * n * n, count - skip, lev.g,
+                                    lev.inv.p + (size_t)(u0 + skip - inv_base(lev)) * box_stride(lev), s,
+                                    lev.sum_mode);
           // unique indices below n_ib are the IB boxes
           const int nsym = lev.use_sym ? std::min(count, std::max(0, lev.n_ib - u0)) : 0;
           if (nsym > 0)
