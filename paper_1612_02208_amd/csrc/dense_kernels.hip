@@ -907,9 +907,19 @@ __global__ void k_ras_sum(const T* __restrict__ pa, const int* __restrict__ ba, 
       const int cr = row >> 6;
       const T* pp = ps + (size_t)b * sym_part_off(g.nch, kss);
       const T* pr = pp + sym_part_off(cr, kss) + (row & 63);
+      // the row's kss slice sums, then the later chunks' column sums: read
+      // eight at a time, added one by one in that order
+      const int m = kss + (g.nch - cr - 1);
+      auto val = [&](int i) { return i < kss ? pr[64 * i] : pp[sym_part_off(cr + 1 + i - kss, kss) + 64 * kss + row]; };
       T a = pr[0];
-      for (int sl = 1; sl < kss; ++sl) a += pr[64 * sl];
-      for (int c = cr + 1; c < g.nch; ++c) a += pp[sym_part_off(c, kss) + 64 * kss + row];
+      for (int i0 = 1; i0 < m; i0 += 8) {
+        T v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = i0 + j < m ? val(i0 + j) : T(0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (i0 + j < m) a += v[j];
+      }
       const size_t o = own_glob(g, ba[b], row);
       z[o] = acc ? z[o] + a : a;
       continue;
@@ -920,7 +930,14 @@ __global__ void k_ras_sum(const T* __restrict__ pa, const int* __restrict__ ba, 
     const T* p = first ? pa : pb;
     const int n = first ? na : nb, ks = first ? ksa : ksb;
     T a = 0;
-    for (int sl = 0; sl < ks; ++sl) a += p[((size_t)sl * n + b) * nown_pad + row];
+    for (int s0 = 0; s0 < ks; s0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = s0 + j < ks ? p[((size_t)(s0 + j) * n + b) * nown_pad + row] : T(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (s0 + j < ks) a += v[j];
+    }
     const size_t o = own_glob(g, (first ? ba : bb)[b], row);
     z[o] = acc ? z[o] + a : a;
   }
