@@ -44,17 +44,21 @@ __device__ __forceinline__ T aib_row(const T* __restrict__ x, int r, int N, cons
 }
 
 // (-M^ p)_ij = (1/h^2) sum over the 4 faces of (p_ij - p_nb) / diag(A_IB)_face
-template <typename T>
-__device__ __forceinline__ T mhat_row(const T* __restrict__ p, int q, int N, T ih2,
-                                      const T* __restrict__ dinv) {
+template <typename T, typename Ld>
+__device__ __forceinline__ T mhat_row_l(Ld pv, int q, int N, T ih2, const T* __restrict__ dinv) {
   const int NN = N * N;
   const int i = q % N, j = q / N;
   const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
   const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-  const T pc = p[q];
-  const T a = dinv[q] * (pc - p[j * N + im]) + dinv[j * N + ip] * (pc - p[j * N + ip]) +
-              dinv[NN + q] * (pc - p[jm * N + i]) + dinv[NN + jp * N + i] * (pc - p[jp * N + i]);
+  const T pc = pv(q);
+  const T a = dinv[q] * (pc - pv(j * N + im)) + dinv[j * N + ip] * (pc - pv(j * N + ip)) +
+              dinv[NN + q] * (pc - pv(jm * N + i)) + dinv[NN + jp * N + i] * (pc - pv(jp * N + i));
   return ih2 * a;
+}
+template <typename T>
+__device__ __forceinline__ T mhat_row(const T* __restrict__ p, int q, int N, T ih2,
+                                      const T* __restrict__ dinv) {
+  return mhat_row_l<T>([p](int k) { return p[k]; }, q, N, ih2, dinv);
 }
 
 // x_r += (b_r - (A x)_r) / diag_r for the rows of one colour
@@ -130,30 +134,38 @@ __global__ void __launch_bounds__(1024) k_gs_band_p(T* x, const T* __restrict__ 
 // wave calls this (live = false for lanes without a row).
 constexpr int kGsGroup = 16;
 
-template <typename T>
-__device__ __forceinline__ void gs_row_group(T* x, const T* __restrict__ b, int r, bool live, int sub, int N,
-                                             const StokesCoef<T>& c, const CsrT<T>& tu, const CsrT<T>& tv,
-                                             const T* __restrict__ diag) {
+// xv(k): entry k of the iterate [u | v]; bv(r): the right-hand side
+template <typename T, typename Ld, typename Bv>
+__device__ __forceinline__ void gs_row_group_l(Ld xv, Bv bv, T* x, int r, bool live, int sub, int N,
+                                               const StokesCoef<T>& c, const CsrT<T>& tu, const CsrT<T>& tv,
+                                               const T* __restrict__ diag) {
   constexpr int G = kGsGroup;
   const int NN = N * N;
   const int comp = r >= NN ? 1 : 0;
   const int q = r - comp * NN;
-  const T* f = x + (size_t)comp * NN;
+  const int o = comp * NN;
   const CsrT<T>& tm = comp ? tv : tu;
   T a = 0;
   if (live)
-    for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * x[tm.col[k]];
+    for (int k = tm.ptr[q] + sub; k < tm.ptr[q + 1]; k += G) a += tm.val[k] * xv(tm.col[k]);
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
   if (live && sub == 0) {
     const int i = q % N, j = q / N;
     const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
     const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-    const T xc = f[q];
-    const T ax = c.alpha * xc - c.beta * (f[j * N + im] + f[j * N + ip] + f[jm * N + i] + f[jp * N + i] -
-                                          T(4) * xc) + a;
-    x[r] += (b[r] - ax) / diag[r];
+    const T xc = xv(o + q);
+    const T ax = c.alpha * xc -
+                 c.beta * (xv(o + j * N + im) + xv(o + j * N + ip) + xv(o + jm * N + i) + xv(o + jp * N + i) -
+                           T(4) * xc) + a;
+    x[r] = xv(r) + (bv(r) - ax) / diag[r];
   }
+}
+template <typename T>
+__device__ __forceinline__ void gs_row_group(T* x, const T* __restrict__ b, int r, bool live, int sub, int N,
+                                             const StokesCoef<T>& c, const CsrT<T>& tu, const CsrT<T>& tv,
+                                             const T* __restrict__ diag) {
+  gs_row_group_l<T>([x](int k) { return x[k]; }, [b](int k) { return b[k]; }, x, r, live, sub, N, c, tu, tv, diag);
 }
 
 // One large colour over the grid: its nlong long rows (listed first) with a
@@ -173,6 +185,68 @@ __global__ void k_gs_colour_split(T* x, const T* __restrict__ b, const int* __re
   if (t >= count) return;
   const int r = rows[t];
   x[r] += (b[r] - aib_row<T>(x, r, N, c, tu, tv)) / diag[r];
+}
+
+// The sweep's first two colours in one launch, when colour 1 is a large
+// colour: from x = 0, colour 0's rows take b / diag and colour 1's rows
+// solve against those values, each formed where it is read (as the first
+// launch would store it); every other row is zeroed.  The grid holds colour
+// 1's long rows (lane groups, nbl blocks), then its other rows (nsb
+// blocks), then every row for the fill.  GRAD (velocity sweeps): b = G p,
+// formed on the fly and stored for the later colours.
+template <typename T, bool GRAD>
+__global__ void k_gs_init_c1(T* __restrict__ x, T* __restrict__ b, const T* __restrict__ p,
+                             const int* __restrict__ colour, const int* __restrict__ rows, int nlong, int cnt,
+                             int nbl, int nsb, int N, StokesCoef<T> c, CsrT<T> tu, CsrT<T> tv,
+                             const T* __restrict__ diag) {
+  const int NN = N * N;
+  auto bv = [&](int r) -> T {
+    if (!GRAD) return b[r];
+    const int comp = r >= NN ? 1 : 0, q = r - comp * NN;
+    const int i = q % N, j = q / N;
+    const int im = i == 0 ? N - 1 : i - 1, jm = j == 0 ? N - 1 : j - 1;
+    return c.gi * (p[q] - p[comp ? jm * N + i : j * N + im]);
+  };
+  auto xv = [&](int k) -> T { return colour[k] == 0 ? (bv(k) - T(0)) / diag[k] : T(0); };
+  const int blk = blockIdx.x;
+  if (blk < nbl) {
+    const int gidx = (int)((blk * (size_t)blockDim.x + threadIdx.x) / kGsGroup);
+    const bool live = gidx < nlong;
+    gs_row_group_l<T>(xv, bv, x, live ? rows[gidx] : 0, live, threadIdx.x % kGsGroup, N, c, tu, tv, diag);
+    return;
+  }
+  if (blk < nbl + nsb) {
+    const int t = nlong + (int)((blk - nbl) * (size_t)blockDim.x + threadIdx.x);
+    if (t >= cnt) return;
+    const int r = rows[t];
+    x[r] = xv(r) + (bv(r) - aib_row_l<T>(xv, r, N, c, tu, tv)) / diag[r];
+    return;
+  }
+  const int r = (int)((blk - nbl - nsb) * (size_t)blockDim.x + threadIdx.x);
+  if (r >= 2 * NN) return;
+  const int cr = colour[r];
+  if (GRAD) b[r] = bv(r);
+  if (cr != 1) x[r] = cr == 0 ? (bv(r) - T(0)) / diag[r] : T(0);
+}
+
+// The same for a sweep on -M^ (cells; colour 1's rows one thread each).
+template <typename T>
+__global__ void k_gs_init_c1_m(T* __restrict__ x, const T* __restrict__ b, const int* __restrict__ colour,
+                               const int* __restrict__ rows, int cnt, int nsb, int N, const T* __restrict__ diag,
+                               const T* __restrict__ dinv, T ih2) {
+  auto xv = [&](int k) -> T { return colour[k] == 0 ? (b[k] - T(0)) / diag[k] : T(0); };
+  const int blk = blockIdx.x;
+  if (blk < nsb) {
+    const int t = (int)(blk * (size_t)blockDim.x + threadIdx.x);
+    if (t >= cnt) return;
+    const int r = rows[t];
+    x[r] = xv(r) + (b[r] - mhat_row_l<T>(xv, r, N, ih2, dinv)) / diag[r];
+    return;
+  }
+  const int r = (int)((blk - nsb) * (size_t)blockDim.x + threadIdx.x);
+  if (r >= N * N) return;
+  const int cr = colour[r];
+  if (cr != 1) x[r] = cr == 0 ? (b[r] - T(0)) / diag[r] : T(0);
 }
 
 // a span of small velocity colours inside one work-group, lane groups per row
@@ -404,7 +478,30 @@ void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s) {
   const int C = cl.ncol;
   const size_t n = cl.colour.size();
   if (!C) return;
-  {
+  // colour 1 large: the first two colours in one launch
+  const bool fuse1 = C >= 2 && cl.big(1);
+  if (fuse1) {
+    const int cnt = cl.ptr[2] - cl.ptr[1];
+    const int* rows = cl.d_rows.p + cl.ptr[1];
+    if (g.grad_p && (g.mhat || n != 2 * (size_t)g.N * g.N || g.grad_out != b))
+      throw Error(IBMG_ERR_ARG, "the fused gradient start is for velocity sweeps on b = G p");
+    if (g.mhat) {
+      const int nsb = cdiv(cnt, 256);
+      IBMG_KLAUNCH((k_gs_init_c1_m<T>), dim3(nsb + cdiv(n, 256)), dim3(256), 0, s, x, b, cl.d_colour.p, rows, cnt,
+                   nsb, g.N, g.diag, g.dinv, g.ih2);
+    } else {
+      const int nl = cl.nlong[1];
+      const int nbl = cdiv((size_t)nl * kGsGroup, 256), nsb = cdiv(cnt - nl, 256);
+      const dim3 grid(nbl + nsb + cdiv(n, 256));
+      if (g.grad_p)
+        IBMG_KLAUNCH((k_gs_init_c1<T, true>), grid, dim3(256), 0, s, x, g.grad_out, g.grad_p, cl.d_colour.p, rows,
+                     nl, cnt, nbl, nsb, g.N, g.c, g.tu, g.tv, g.diag);
+      else
+        IBMG_KLAUNCH((k_gs_init_c1<T, false>), grid, dim3(256), 0, s, x, const_cast<T*>(b), nullptr,
+                     cl.d_colour.p, rows, nl, cnt, nbl, nsb, g.N, g.c, g.tu, g.tv, g.diag);
+    }
+    IBMG_LAUNCH_CHECK();
+  } else {
     int grid = cdiv(n, 256);
     if (grid > 4096) grid = 4096;
     if (g.grad_p) {
@@ -420,7 +517,7 @@ void launch_gs_sweep(T* x, const T* b, const GsSweep<T>& g, hipStream_t s) {
   std::vector<int> seq;
   for (int c = 1; c < C; ++c) seq.push_back(c);
   for (int c = C - 2; c >= 0; --c) seq.push_back(c);
-  for (size_t a = 0; a < seq.size();) {
+  for (size_t a = fuse1 ? 1 : 0; a < seq.size();) {
     const int col = seq[a];
     if (cl.big(col)) {
       const int cnt = cl.ptr[col + 1] - cl.ptr[col];
