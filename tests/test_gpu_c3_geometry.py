@@ -133,3 +133,27 @@ def test_solves_both_precisions(c3):
         e12 = assert_classes(host(x12), xo12, lc(P), SOLVE_TOL, f"{prec} at 1e-12 vs oracle at 1e-12")
         print(f"[c3-128 {prec}] 1e-8: {i8['iters']} its (oracle {io8['iters']}), true {true:.2e}, "
               f"vs oracle {e8}; 1e-12: {i12['iters']} its (oracle {io12['iters']}), vs oracle {e12}")
+
+
+def test_symmetric_and_chunked_ib_storage_agree(c3, monkeypatch):
+    """The IB boxes' owned rows in symmetric storage (lower owned tiles,
+    transposed column sums; the default where the level has enough IB boxes)
+    against the chunked storage of every owned row (IBMG_NO_SYM=1): the
+    Schwarz sweep of every level and a V-cycle agree to rounding."""
+    from paper_1612_02208_amd import StokesIB
+    wl, P, H = c3
+    monkeypatch.setenv("IBMG_NO_SYM", "1")
+    G2 = StokesIB(wl, precision="fp64")
+    monkeypatch.delenv("IBMG_NO_SYM")
+    try:
+        rng = np.random.default_rng(12)
+        for l in range(1, len(P.levels)):
+            r = rng.uniform(-1, 1, P.levels[l].n)
+            a = host(H["fp64"].smoother_apply(l, dev(r)))
+            b = host(G2.smoother_apply(l, dev(r)))
+            assert_classes(a, b, lc(P, l), OPS_TOL, f"symmetric vs chunked sweep, level {l}")
+        r = P.project(W.rhs(wl.N, 13))
+        assert_classes(host(H["fp64"].vcycle(dev(r))), host(G2.vcycle(dev(r))), lc(P), OPS_TOL,
+                       "symmetric vs chunked V-cycle")
+    finally:
+        G2.close()
