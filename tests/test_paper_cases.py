@@ -10,13 +10,23 @@ thin membrane) and of the parameter-study driver's host logic.
   alpha = gamma 3.93/0.005 (thick) and 7 gamma 3.93/0.005 (thin);
 * the background flow is discretely divergence-free (the oracle's MAC
   divergence) and samples the unit-speed cell flow to O(h^2);
-* dt = 0.32 h and an 8 x 8 coarsest grid.
+* dt = 0.32 h and an 8 x 8 coarsest grid;
+* the stiffness reading against the paper's explicit-stability statements
+  (Sec. 5.1: alpha = 3.93/0.005 is about the largest stable stiffness of an
+  explicit solver for the shell at h = 1/64, dt = 0.005, and this limit is
+  insensitive to refinement; Sec. 5.2: for the membrane the limit falls in
+  proportion to h, and gamma = 5 is about 100 times it).  The limit of
+  forward Euler in Stokes flow is 2 / (dt lambda_max(J L^-1 S (-K))), with
+  the Stokes solve done by FFT on the periodic MAC grid.
 """
 import numpy as np
 import pytest
 
+import scipy.sparse.linalg as sla
+
 import workloads as W
-from oracle.mac import divergence
+from oracle.ib import interp_matrix, spread_matrix, stiffness_matrix
+from oracle.mac import divergence, gradient, scalar_laplacian
 from oracle.timestep import fibre_force_periodic
 from paper_1612_02208_amd import sweep
 
@@ -92,6 +102,96 @@ def test_background_flow_is_divergence_free(N):
     u = b[:n].reshape(N, N)
     exact = np.outer(np.cos(2 * np.pi * yc), np.sin(2 * np.pi * x))   # u[j, i] at (i h, (j+1/2) h)
     assert np.abs(u - exact).max() < (2 * np.pi * h) ** 2 / 24 * 1.01
+
+
+def _stokes_periodic(f, N, mu=1.0):
+    """Steady Stokes -mu Lap u + G p = f, D u = 0 on the periodic MAC grid,
+    diagonal in Fourier space: with d = (e^{i theta} - 1) / h per direction
+    (the symbol of D; G's is -conj(d) and -Lap's is |d|^2),
+    p^ = -(d . f^) / |d|^2 and u^ = (f^ - conj(d) (d . f^) / |d|^2) / (mu |d|^2);
+    the mean mode is set to zero.  f = [fx, fy] on the faces (2 N^2)."""
+    n = N * N
+    h = 1.0 / N
+    th = 2 * np.pi * np.fft.fftfreq(N)
+    dx = np.broadcast_to((np.exp(1j * th) - 1)[None, :] / h, (N, N))   # along i (axis 1)
+    dy = np.broadcast_to((np.exp(1j * th) - 1)[:, None] / h, (N, N))   # along j (axis 0)
+    d2 = np.abs(dx) ** 2 + np.abs(dy) ** 2
+    zero = d2 == 0
+    d2 = np.where(zero, 1.0, d2)
+    fx = np.fft.fft2(f[:n].reshape(N, N))
+    fy = np.fft.fft2(f[n:].reshape(N, N))
+    div = (dx * fx + dy * fy) / d2
+    out = []
+    for c in ((fx - np.conj(dx) * div) / (mu * d2), (fy - np.conj(dy) * div) / (mu * d2), -div):
+        c = np.where(zero, 0.0, c)
+        out.append(np.real(np.fft.ifft2(c)).ravel())
+    return np.concatenate(out[:2]), out[2]
+
+
+def test_fft_stokes_solves_the_mac_system():
+    N, mu = 32, 0.7
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(2 * N * N)
+    f[:N * N] -= f[:N * N].mean()
+    f[N * N:] -= f[N * N:].mean()
+    u, p = _stokes_periodic(f, N, mu)
+    L = scalar_laplacian(N)
+    n = N * N
+    mom = np.concatenate([-mu * (L @ u[:n]), -mu * (L @ u[n:])]) + gradient(N) @ p - f
+    assert np.abs(mom).max() < 1e-10 * np.abs(f).max()
+    assert np.abs(divergence(N) @ u).max() < 1e-10 * np.abs(u).max() * N
+
+
+def _explicit_alpha(X, springs, kappa_per_alpha, N, dt=0.005):
+    """Largest alpha for which forward Euler X += dt J u(F(X)), with u the
+    Stokes flow of the spread force F = alpha K1 X, is linearly stable:
+    2 / (dt lambda_max(J L^-1 S (-K1)))."""
+    M = X.shape[0]
+    K = stiffness_matrix(M, springs, kappa_per_alpha)
+    S = [spread_matrix(X, N, c) for c in (0, 1)]
+    J = [interp_matrix(X, N, c) for c in (0, 1)]
+    n = N * N
+
+    def mv(z):
+        Z = z.reshape(2, M)
+        f = np.concatenate([S[c] @ -(K @ Z[c]) for c in (0, 1)])
+        u, _ = _stokes_periodic(f, N)
+        return np.concatenate([J[0] @ u[:n], J[1] @ u[n:]])
+
+    op = sla.LinearOperator((2 * M, 2 * M), matvec=mv, dtype=np.float64)
+    v0 = np.random.default_rng(0).standard_normal(2 * M)
+    lam = sla.eigs(op, k=1, which="LM", v0=v0, tol=1e-8, return_eigenvectors=False)
+    return 2.0 / (dt * float(np.real(lam[0])))
+
+
+def test_stiffness_reading_matches_the_explicit_limits():
+    """The nodal-weight reading puts the membrane's gamma = 5 at about 100
+    times its explicit limit (135 here), with a limit that halves with h, and
+    gives the shell a limit within a factor 5 of 3.93/0.005 that changes
+    little under refinement.  Two other readings fail these statements: shell
+    springs without the ds2 weight (limit 24 times too small at h = 1/64 and
+    falling about 2.5 times per refinement), and a membrane alpha scaled to
+    the shell's total force (gamma = 5 only about 1.2 times its limit)."""
+    a_exp = 3.93 / 0.005
+    lim = {}
+    for N in (64, 128):
+        X, S, kap, (ds1, ds2) = W.thick_shell(N, 1.0)
+        lim["shell", N] = _explicit_alpha(X, S, kap / a_exp, N)
+        lim["fibre", N] = _explicit_alpha(X, S, kap / a_exp / ds2, N)
+        Xm, Sm, km, _ = W.thin_membrane(N, 1.0)
+        lim["membrane", N] = _explicit_alpha(Xm, Sm, km / (7 * a_exp), N)
+    # thin: gamma = 5 is about 100 x the limit, which falls in proportion to h
+    ratio = 7 * 5 * a_exp / lim["membrane", 64]
+    assert 50 < ratio < 200
+    assert abs(lim["membrane", 64] / lim["membrane", 128] - 2) < 0.1
+    # the same membrane scaled to the shell's total force (alpha w instead of 7 alpha)
+    assert 7 * 5 * a_exp * (W.SHELL_WIDTH / 7) / lim["membrane", 64] < 2
+    # thick: near 3.93/0.005 and insensitive to refinement
+    assert 1 / 5 < lim["shell", 64] / a_exp < 5
+    assert lim["shell", 64] / lim["shell", 128] < 1.5
+    # springs without the ds2 weight miss both statements
+    assert lim["fibre", 64] / a_exp < 1 / 20
+    assert lim["fibre", 64] / lim["fibre", 128] > 2
 
 
 def test_paper_case_parameters():
