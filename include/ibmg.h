@@ -150,7 +150,12 @@ typedef struct {
   double rel_res_est;   /* Arnoldi residual estimate / ||b||                 */
   double rel_res_true;  /* ||P b - L x|| / ||P b|| recomputed at the end      */
   double rhs_null_norm; /* ||b - P b||, the null-space part removed from b    */
-  double solve_ms;      /* wall time of the call                             */
+  double setup_ms;      /* wall time of the handle's latest set-up, device
+                           work included: ibmg_create / ibmg_batch_create,
+                           ibmg_set_kappa, or the rebuild at X^{n+1} that
+                           ibmg_time_step ends with (then that step's)       */
+  double solve_ms;      /* wall time of the call (for ibmg_time_step: its
+                           solve, without the rebuild)                       */
   double* history;      /* optional host array of residual estimates         */
   int32_t history_cap;  /* its capacity (0 if history is NULL)               */
   int32_t vcycles;      /* V-cycles applied                                  */

@@ -47,7 +47,8 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double),
-                ("rhs_null_norm", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("rhs_null_norm", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double),
                 ("history", _dp), ("history_cap", ctypes.c_int32), ("vcycles", ctypes.c_int32)]
 
 

@@ -48,6 +48,7 @@ template <typename T>
 class BatchSolver final : public BatchBase {
  public:
   BatchSolver(int nsys, const ibmg_desc* d, hipStream_t s) : ns_(nsys) {
+    const auto t_begin = std::chrono::steady_clock::now();
     validate_batch(nsys, d);
     const ibmg_desc& d0 = d[0];
     nu1_ = d0.nu1;
@@ -101,6 +102,7 @@ class BatchSolver final : public BatchBase {
     alloc_outer(max_restart_);
     tune(s);
     IBMG_HIP(hipStreamSynchronize(s));
+    setup_ms_ = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
   }
 
   ~BatchSolver() override {
@@ -659,6 +661,7 @@ class BatchSolver final : public BatchBase {
       inf.rel_res_est = bnorm[p] > 0 ? est[p] / bnorm[p] : 0.0;
       inf.rel_res_true = bnorm[p] > 0 ? tr[p] / bnorm[p] : 0.0;
       inf.rhs_null_norm = null[p];
+      inf.setup_ms = setup_ms_;
       inf.solve_ms = ms;
       inf.vcycles = vcyc[p];
     }
@@ -707,6 +710,7 @@ class BatchSolver final : public BatchBase {
 
  private:
   int ns_ = 0, Lmax_ = 0, nu1_ = 2, nu2_ = 2, n0_ = 0, max_restart_ = 30;
+  double setup_ms_ = 0.0;   // wall time of the constructor's set-up (device work included)
   bool rho_zero_ = false;
   std::vector<int> order_, nact_;
   std::vector<std::unique_ptr<Solver<T>>> sys_;

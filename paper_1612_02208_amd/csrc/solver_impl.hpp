@@ -180,6 +180,7 @@ class Solver final : public SolverBase {
   void build_all(hipStream_t s) {
     const bool timed = std::getenv("IBMG_SETUP_TIMES") != nullptr;
     auto t = std::chrono::steady_clock::now();
+    const auto t_begin = t;
     auto mark = [&](const char* what) {
       if (!timed) return;
       IBMG_HIP(hipStreamSynchronize(s));
@@ -197,6 +198,7 @@ class Solver final : public SolverBase {
     if (!defer_coarse_) tune_interior(s);
     mark("interior tuning");
     IBMG_HIP(hipStreamSynchronize(s));
+    setup_ms_ = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
   }
 
   // Release everything alloc_fixed did not place (the whole hierarchy, the
@@ -1566,6 +1568,7 @@ class Solver final : public SolverBase {
       info->iters = 0;
       info->restarts = 0;
       info->rhs_null_norm = std::sqrt(null2);
+      info->setup_ms = setup_ms_;
       info->vcycles = 0;
     }
     if (!std::isfinite(bnorm) || !std::isfinite(null2)) throw Error(IBMG_ERR_NONFINITE, "right-hand side holds NaN/Inf");
@@ -1704,6 +1707,7 @@ class Solver final : public SolverBase {
     for (double x : X_)
       if (!std::isfinite(x) || x < 0.0 || x >= 1.0) throw Error(IBMG_ERR_NONFINITE, "updated positions are invalid");
     rebuild(s);
+    if (info) info->setup_ms = setup_ms_;
     return st;
   }
 
@@ -1924,6 +1928,7 @@ class Solver final : public SolverBase {
   DBuf<double> coarse_aug_;       // its work matrix until the join
   bool defer_coarse_ = false;   // a member of a batch: the batch inverts the coarsest system
   bool valid_ = true;
+  double setup_ms_ = 0.0;   // wall time of the latest build_all (device work included)
   int nn0_ = 0;          // size of the bordered coarsest system
   DBuf<double> aug0_;    // its assembled [A | I] while the inversion is deferred
 

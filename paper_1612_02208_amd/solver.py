@@ -248,7 +248,8 @@ class StokesIB:
         return x, dict(status=_STATUS[st], converged=st == 0, iters=info.iters,
                        restarts=info.restarts, rel_res_est=info.rel_res_est,
                        rel_res_true=info.rel_res_true, rhs_null_norm=info.rhs_null_norm,
-                       solve_ms=info.solve_ms, vcycles=info.vcycles, history=list(hist[:k]))
+                       setup_ms=info.setup_ms, solve_ms=info.solve_ms, vcycles=info.vcycles,
+                       history=list(hist[:k]))
 
     # ---- semi-implicit time step (Sec. 2.2) --------------------------------
     def step_rhs(self, w):
@@ -271,7 +272,7 @@ class StokesIB:
         st = self._check(self.lib.ibmg_time_step(self.h, _ptr(x), ctypes.byref(o), ctypes.byref(info), _stream()),
                          ok=(0, 1))
         return x, dict(status=_STATUS[st], converged=st == 0, iters=info.iters, rel_res_true=info.rel_res_true,
-                       rhs_null_norm=info.rhs_null_norm, solve_ms=info.solve_ms)
+                       rhs_null_norm=info.rhs_null_norm, solve_ms=info.solve_ms, rebuild_ms=info.setup_ms)
 
     def positions(self):
         X = np.empty((self.M, 2), dtype=np.float64)
@@ -422,7 +423,8 @@ class StokesIBBatch:
             k = min(inf.iters, history)
             out.append(dict(converged=inf.rel_res_est <= rtol, iters=inf.iters, restarts=inf.restarts,
                             rel_res_est=inf.rel_res_est, rel_res_true=inf.rel_res_true,
-                            rhs_null_norm=inf.rhs_null_norm, solve_ms=inf.solve_ms, vcycles=inf.vcycles,
+                            rhs_null_norm=inf.rhs_null_norm, setup_ms=inf.setup_ms, solve_ms=inf.solve_ms,
+                            vcycles=inf.vcycles,
                             history=list(hists[i][:k])))
         return xs, dict(status=_STATUS[st], converged=st == 0, systems=out)
 

@@ -7,6 +7,8 @@
 * Rebuilds (ibmg_set_kappa) lay the hierarchy out again in the same place:
   repeated on an exactly sized workspace they need no more.
 * The batched form takes its workspace the same way.
+* The solve info carries the latest set-up's wall time: the handle's
+  creation, a set_kappa rebuild, or the rebuild a time step ends with.
 * Errors: a NaN right-hand side gives IBMG_ERR_NONFINITE (single and batch);
   a restart beyond max_restart gives IBMG_ERR_ARG; stiffness so large that
   the IB rows overflow makes the set-up report IBMG_ERR_BREAKDOWN.
@@ -105,6 +107,31 @@ def test_batch_exact_workspace():
     assert B.workspace_used()[1] == B.workspace_bytes
     xs, info = B.solve([dev(W.rhs(s.N, s.rhs_seed)) for s in systems], rtol=1e-8)
     assert info["converged"]
+    B.close()
+
+
+def test_setup_time_is_reported():
+    from paper_1612_02208_amd import StokesIB, StokesIBBatch
+    wl = W.plain_32()
+    G = StokesIB(wl)
+    b = dev(W.rhs(32, 0))
+    _, i1 = G.solve(b, rtol=1e-8)
+    assert np.isfinite(i1["setup_ms"]) and i1["setup_ms"] > 0
+    _, i2 = G.solve(b, rtol=1e-8)
+    assert i2["setup_ms"] == i1["setup_ms"]          # no set-up between the solves
+    G.set_kappa(2.0 * wl.kappa)
+    _, i3 = G.solve(b, rtol=1e-8)
+    assert i3["setup_ms"] > 0 and i3["setup_ms"] != i1["setup_ms"]
+    _, st = G.time_step(torch.zeros_like(b), rtol=1e-8)
+    assert st["rebuild_ms"] > 0
+    _, i4 = G.solve(b, rtol=1e-8)
+    assert i4["setup_ms"] == st["rebuild_ms"]        # the step's rebuild is the latest set-up
+    G.close()
+    systems = W.batch_systems(3, sizes=(32, 64))
+    B = StokesIBBatch(systems)
+    _, info = B.solve([dev(W.rhs(s.N, s.rhs_seed)) for s in systems], rtol=1e-8)
+    ms = [s["setup_ms"] for s in info["systems"]]
+    assert ms[0] > 0 and all(m == ms[0] for m in ms)
     B.close()
 
 
